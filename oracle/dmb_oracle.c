@@ -1,0 +1,587 @@
+/*
+ * dmb_oracle.c -- plain, slow FP64 CPU oracle for the DM-gas pair interaction
+ * step of Hainje & Farrar, "A New Method to Simulate Dark Matter-Baryon
+ * Interactions and Application to an Isolated Disk Galaxy" (arXiv 2603.24688).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or constant with
+ * the HIP path.
+ *
+ * Everything is IEEE double.  Neighbours are found by brute force.  Each
+ * function cites the passage of the paper it writes out.
+ *
+ * Units: kpc, km/s, Msun; time in kpc/(km/s); sigma0 in cm^2; m_chi, mu in g;
+ * gas specific internal energy u in (km/s)^2, 1-D velocity variance
+ * varsigma^2 = 2u/3 (= T/mu with k_B absorbed).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+#define ORC_MSUN_G 1.988409870698051e33
+#define ORC_KPC_CM 3.0856775814913673e21
+#define ORC_C_KMS 299792.458
+#define ORC_MP_G 1.67262192369e-24
+
+/* ------------------------------------------------------------------------- */
+/* Cubic-spline softening kernel (Sec. 2.4, "GIZMO implementation"):
+ * W(r,h) = w(r/h)/h^3 with w(q) = 8/pi * {1-6q^2+6q^3, q<=1/2; 2(1-q)^3,
+ * 1/2<q<=1; 0, q>1}.                                                        */
+double orc_w(double q)
+{
+    if (q < 0.0) q = -q;
+    if (q <= 0.5) return (8.0 / ORC_PI) * (1.0 - 6.0 * q * q + 6.0 * q * q * q);
+    if (q <= 1.0) { double p = 1.0 - q; return (8.0 / ORC_PI) * 2.0 * p * p * p; }
+    return 0.0;
+}
+
+double orc_W(double r, double h) { return orc_w(r / h) / (h * h * h); }
+
+/* ------------------------------------------------------------------------- */
+/* Overlap integral g_ij (eq. dm-update-prob; Appendix D).
+ *
+ * g = int d^3x W(|x-x_i|,h_i) W(|x-x_j|,h_j).  Appendix D reduces it, with
+ * the outer radial integral over the kernel with the larger h (h_b) and the
+ * ratio eta = h_s/h_b <= 1, delta = d/h_b, to
+ *     g = (2 pi / h_s^3) int_0^1 ds s^2 w(s) F(s),
+ *     F(s) = int_{-1}^{1} dc w( sqrt(s^2 + delta^2 - 2 delta s c) / eta ).
+ * Substituting t = sqrt(s^2+delta^2-2 delta s c) gives
+ *     F(s) = eta^2/(delta s) [psi((s+delta)/eta) - psi(|s-delta|/eta)],
+ *     psi(Q) = int_0^Q q w(q) dq,
+ * a piecewise polynomial.  The s-integrand is therefore a polynomial of
+ * degree <= 9 between the breakpoints {1/2, delta, delta +- eta/2,
+ * delta +- eta, eta/2 - delta, eta - delta}, so 6-point Gauss-Legendre on each
+ * piece is exact up to rounding.  No table.                                  */
+
+/* psi on each branch; branch 0: Q<=1/2, 1: 1/2<Q<=1, 2: Q>1.                */
+static int psi_branch(double Q) { return Q <= 0.5 ? 0 : (Q <= 1.0 ? 1 : 2); }
+
+/* psi(b) - psi(a) for a, b inside one branch, in a factored form that keeps
+ * relative accuracy when b - a is small; bma = b - a supplied by the caller. */
+static double psi_diff_same_branch(int br, double a, double b, double bma)
+{
+    const double c = 8.0 / ORC_PI;
+    if (br == 0) {
+        /* psi = c [Q^2/2 - 3 Q^4/2 + 6 Q^5/5] */
+        double s1 = a + b;
+        double s3 = (a * a + b * b) * s1;                  /* b^4-a^4 = (b-a) s3 */
+        double s4 = b * b * b * b + b * b * b * a + b * b * a * a + b * a * a * a + a * a * a * a;
+        return c * bma * (0.5 * s1 - 1.5 * s3 + 1.2 * s4);
+    }
+    if (br == 1) {
+        /* psi = const + c [ -(1-Q)^4/2 + 2 (1-Q)^5/5 ];  with p = 1-Q,
+         * p_a - p_b = b - a.                                                */
+        double pa = 1.0 - a, pb = 1.0 - b;
+        double t3 = (pa * pa + pb * pb) * (pa + pb);       /* pa^4-pb^4 = (pa-pb) t3 */
+        double t4 = pa * pa * pa * pa + pa * pa * pa * pb + pa * pa * pb * pb + pa * pb * pb * pb + pb * pb * pb * pb;
+        return c * bma * (0.5 * t3 - 0.4 * t4);
+    }
+    return 0.0;
+}
+
+/* psi at the branch edges: psi(1/2) = c*11/160, psi(1) = c*7/80.           */
+static double psi_edge(int k) { return (8.0 / ORC_PI) * (k == 0 ? 11.0 / 160.0 : 7.0 / 80.0); }
+
+/* psi(b) - psi(a), 0 <= a <= b, with bma = b - a given.                      */
+static double psi_diff(double a, double b, double bma)
+{
+    int ba = psi_branch(a), bb = psi_branch(b);
+    if (ba == bb) return psi_diff_same_branch(ba, a, b, bma);
+    double acc = 0.0, lo = a;
+    int br = ba;
+    while (br < bb) {
+        double edge = (br == 0) ? 0.5 : 1.0;
+        acc += psi_diff_same_branch(br, lo, edge, edge - lo);
+        lo = edge;
+        br++;
+    }
+    acc += psi_diff_same_branch(bb, lo, b, b - lo);
+    return acc;
+}
+
+static const double GL6_X[6] = {-0.9324695142031521, -0.6612093864662645, -0.2386191860831969,
+                                 0.2386191860831969, 0.6612093864662645, 0.9324695142031521};
+static const double GL6_W[6] = {0.1713244923791704, 0.3607615730481386, 0.4679139345726910,
+                                 0.4679139345726910, 0.3607615730481386, 0.1713244923791704};
+
+/* Integrand s^2 w(s) F(s) of Appendix D (without the 2 pi/h_s^3 prefactor). */
+static double overlap_integrand(double s, double delta, double eta)
+{
+    double ws = orc_w(s);
+    if (ws == 0.0) return 0.0;
+    double F;
+    if (delta == 0.0) {
+        F = 2.0 * orc_w(s / eta);                       /* limit delta -> 0 */
+    } else {
+        double a = fabs(s - delta) / eta, b = (s + delta) / eta;
+        double bma = 2.0 * (s < delta ? s : delta) / eta;
+        F = eta * eta / (delta * s) * psi_diff(a, b, bma);
+    }
+    return s * s * ws * F;
+}
+
+static int cmp_double(const void *x, const void *y)
+{
+    double a = *(const double *)x, b = *(const double *)y;
+    return (a > b) - (a < b);
+}
+
+/* Dimensionless G(delta, eta) = int_0^1 ds s^2 w(s) F(s); g = 2 pi G / h_s^3. */
+double orc_overlap_G(double delta, double eta)
+{
+    if (delta >= 1.0 + eta) return 0.0;
+    double bp[16];
+    int nb = 0;
+    double cand[9] = {0.0, 1.0, 0.5, delta, delta - 0.5 * eta, delta + 0.5 * eta,
+                      delta - eta, delta + eta, 0.5 * eta - delta};
+    for (int k = 0; k < 9; k++) {
+        double v = cand[k];
+        if (v >= 0.0 && v <= 1.0) bp[nb++] = v;
+    }
+    if (eta - delta > 0.0 && eta - delta < 1.0) bp[nb++] = eta - delta;
+    qsort(bp, (size_t)nb, sizeof(double), cmp_double);
+    double acc = 0.0;
+    for (int k = 0; k + 1 < nb; k++) {
+        double lo = bp[k], hi = bp[k + 1];
+        if (hi <= lo) continue;
+        double half = 0.5 * (hi - lo), mid = 0.5 * (hi + lo);
+        double piece = 0.0;
+        for (int q = 0; q < 6; q++) piece += GL6_W[q] * overlap_integrand(mid + half * GL6_X[q], delta, eta);
+        acc += half * piece;
+    }
+    return acc;
+}
+
+double orc_overlap(double d, double h1, double h2)
+{
+    double hb = h1 > h2 ? h1 : h2, hs = h1 > h2 ? h2 : h1;
+    double delta = d / hb, eta = hs / hb;
+    return 2.0 * ORC_PI * orc_overlap_G(delta, eta) / (hs * hs * hs);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Confluent hypergeometric 1F1(a, b; -x), x >= 0 (Sec. 2.4 and Appendix B).
+ * x < 50: Kummer's transformation 1F1(a,b;-x) = e^{-x} 1F1(b-a,b;x) and the
+ * defining power series (all terms positive when b-a > 0 and b > 0).
+ * x >= 50: the paper's expansion Gamma(b) x^{-a} / Gamma(b-a) *
+ * sum_{k=0}^{4} (a)_k (1+a-b)_k / (k! x^k), truncated at five terms.         */
+double orc_hyp1f1_negx(double a, double b, double x)
+{
+    if (x < 50.0) {
+        double c = b - a, term = 1.0, sum = 1.0;
+        for (int k = 0; k < 2000; k++) {
+            term *= (c + k) / (b + k) * x / (k + 1.0);
+            sum += term;
+            if (term < 1e-18 * sum) break;
+        }
+        return exp(-x) * sum;
+    }
+    double pre = exp(lgamma(b) - lgamma(b - a)) * pow(x, -a);
+    /* Gamma(b-a) may be negative for b-a<0; not reached for the (a,b) used here. */
+    double term = 1.0, sum = 1.0;
+    for (int k = 0; k < 4; k++) {
+        term *= (a + k) * (1.0 + a - b + k) / ((k + 1.0) * x);
+        sum += term;
+    }
+    return pre * sum;
+}
+
+/* alpha_n = 2^{(n+5)/2} Gamma(3+n/2) / sqrt(pi)  (Appendix B).               */
+double orc_alpha_n(int n) { return pow(2.0, 0.5 * (n + 5)) * tgamma(3.0 + 0.5 * n) / sqrt(ORC_PI); }
+
+/* Rate integrals (eq. scrA, scrB) for sigma-bar = sigma0 (v/c)^n, written
+ * without the factor sigma0 c^{-n}:
+ *   Ahat = alpha_n/3 vs^{n+1} 1F1(-(n+1)/2, 5/2, -w^2/(2 vs^2)),
+ *   Bhat = alpha_n   vs^{n+3} 1F1(-(n+3)/2, 3/2, -w^2/(2 vs^2)).
+ * vs = varsigma (km/s), w = |w| (km/s).  vs = 0 (cold gas) takes the limit
+ * Ahat = w^{n+1}, Bhat = w^{n+3}.                                            */
+void orc_rates(int n, double w, double vs, double *A, double *B)
+{
+    if (vs <= 0.0) {
+        *A = pow(w, n + 1);
+        *B = pow(w, n + 3);
+        return;
+    }
+    double x = w * w / (2.0 * vs * vs);
+    double al = orc_alpha_n(n);
+    *A = al / 3.0 * pow(vs, n + 1) * orc_hyp1f1_negx(-0.5 * (n + 1), 2.5, x);
+    *B = al * pow(vs, n + 3) * orc_hyp1f1_negx(-0.5 * (n + 3), 1.5, x);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 counter-based generator (Salmon, Moraes, Dror & Shaw, SC'11,
+ * "Parallel Random Numbers: As Easy as 1, 2, 3"), written from the published
+ * description: each round takes the two 32x32->64 products of (M0, x0) and
+ * (M1, x2), outputs (hi1^x1^k0, lo1, hi0^x3^k1, lo0); the key is bumped by the
+ * Weyl constants between rounds.  A 64-bit-word instance of the same round
+ * structure is provided for checking against an independent library.        */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr_in[0], x1 = ctr_in[1], x2 = ctr_in[2], x3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+void orc_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4])
+{
+    uint64_t x0 = ctr_in[0], x1 = ctr_in[1], x2 = ctr_in[2], x3 = ctr_in[3];
+    uint64_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) { k0 += 0x9E3779B97F4A7C15ull; k1 += 0xBB67AE8584CAA73Bull; }
+        unsigned __int128 p0 = (unsigned __int128)0xD2E7470EE14C6C93ull * x0;
+        unsigned __int128 p1 = (unsigned __int128)0xCA5A826395121157ull * x2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        uint64_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* 24-bit centred uniform in (0,1): ((r >> 8) + 1/2) 2^-24, exact in binary32. */
+double orc_u24(uint32_t r) { return ((double)(r >> 8) + 0.5) * (1.0 / 16777216.0); }
+
+/* Stream layout: key = (seed lo32, seed hi32); counter = (dm index, gas index,
+ * step, tag | box << 8).  Tag 0: gas-velocity sample of pair (i,j); tag 1:
+ * scattering direction of pair (i,j); tag 2: per-DM decision uniform (gas
+ * index 0xFFFFFFFF).                                                         */
+static void orc_block(uint64_t seed, uint32_t i, uint32_t j, uint32_t step, uint32_t tag, uint32_t box,
+                      double u[4])
+{
+    uint32_t ctr[4] = {i, j, step, tag | (box << 8)};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    for (int k = 0; k < 4; k++) u[k] = orc_u24(r[k]);
+}
+
+/* Box-Muller: three standard normals from one block.                        */
+void orc_normals3(const double u[4], double z[3])
+{
+    double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+    z[0] = r0 * cos(2.0 * ORC_PI * u[1]);
+    z[1] = r0 * sin(2.0 * ORC_PI * u[1]);
+    z[2] = r1 * cos(2.0 * ORC_PI * u[3]);
+}
+
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int64_t n;
+    const double *pos;        /* [n][3] kpc */
+    const double *vel;        /* [n][3] km/s */
+    const double *mass;       /* [n] Msun */
+    const double *h;          /* [n] kpc (kernel support radius) */
+    const double *u;          /* gas: [n] (km/s)^2; ignored for DM */
+    const double *mu;         /* gas: [n] g, NULL => proton mass */
+    const uint8_t *active;    /* NULL => all active */
+    const double *dt;         /* NULL => params dt */
+} orc_particles;
+
+typedef struct {
+    double sigma0_cm2;
+    int n_pow;
+    double m_chi_g;
+    double dt;
+    uint64_t seed;
+    uint32_t step;
+    uint32_t box_id;
+    double box[3];            /* periodic side lengths; 0 => open */
+} orc_params;
+
+enum { ORC_C_PAIRS_GAS = 0, ORC_C_PAIRS_DM, ORC_C_SCATTERS, ORC_C_NEAR_BOUNDARY, ORC_C_NEAR_DECISION,
+       ORC_C_CRIT_VIOL, ORC_C_P_GE_1, ORC_C_NONFINITE, ORC_NCOUNTERS };
+
+typedef struct {
+    double *dv_dm;            /* [n_dm][3] km/s */
+    double *dp_gas;           /* [n_gas][3] Msun km/s */
+    double *de_gas;           /* [n_gas] Msun (km/s)^2, internal energy */
+    double *dp_abs;           /* [n_gas][3] sum of |terms| (nullable) */
+    double *de_abs;           /* [n_gas] (nullable) */
+    int32_t *partner;         /* [n_dm] gas index or -1 */
+    double *p_sum;            /* [n_dm] (nullable) */
+    double *p_max;            /* [n_dm] (nullable) */
+    uint8_t *flags;           /* [n_dm] bit0 near decision, bit1 near-boundary pair (nullable) */
+    uint64_t counters[ORC_NCOUNTERS];
+} orc_out;
+
+static void min_image(const orc_params *par, double dx[3])
+{
+    for (int k = 0; k < 3; k++)
+        if (par->box[k] > 0.0) dx[k] -= par->box[k] * nearbyint(dx[k] / par->box[k]);
+}
+
+/* Pair membership (Appendix D: overlap vanishes iff d >= h_i + h_j).         */
+static int pair_test(const orc_particles *gas, const orc_particles *dm, const orc_params *par, int64_t j,
+                     int64_t i, double *d_out, int *near)
+{
+    double dx[3];
+    for (int k = 0; k < 3; k++) dx[k] = dm->pos[3 * i + k] - gas->pos[3 * j + k];
+    min_image(par, dx);
+    double d2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
+    double hs = dm->h[i] + gas->h[j];
+    double r = d2 / (hs * hs);
+    if (near) *near = fabs(r - 1.0) <= 1e-6;
+    *d_out = sqrt(d2);
+    return d2 < hs * hs;
+}
+
+static double gas_mu(const orc_particles *gas, int64_t j) { return gas->mu ? gas->mu[j] : ORC_MP_G; }
+static double gas_vs(const orc_particles *gas, int64_t j) { return sqrt(2.0 * gas->u[j] / 3.0); }
+static double p_dt(const orc_particles *p, const orc_params *par, int64_t k) { return p->dt ? p->dt[k] : par->dt; }
+
+/* Neumaier-compensated accumulator. */
+typedef struct { double s, c; } orc_sum;
+static void nsum_add(orc_sum *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x; else a->c += (x - t) + a->s;
+    a->s = t;
+}
+static double nsum_get(const orc_sum *a) { return a->s + a->c; }
+
+/* Gas mean field for gas j (eq. gas-dVdt and gas-dTdt):
+ *   dV_j/dt = sum_i M_i/(m_chi+mu_j) g_ij A(w) w,
+ *   (3/(2 mu_j)) dT_j/dt = sum_i M_i/(m_chi+mu_j) g_ij [w^2 A - mu_j/(m_chi+mu_j) B],
+ * w = v_i - V_j.  Output dp = M_j dt_j dV/dt and dE = M_j dt_j (3/(2mu)) dT/dt
+ * (the internal-energy change; the bulk-kinetic part is V_j . dp).  Sums run
+ * over DM in index order, compensated.                                      */
+static void gas_one(const orc_particles *gas, const orc_particles *dm, const orc_params *par, int64_t j,
+                    orc_out *out, uint64_t *npairs)
+{
+    orc_sum sp[3] = {{0, 0}, {0, 0}, {0, 0}}, se = {0, 0};
+    double ap[3] = {0, 0, 0}, ae = 0;
+    uint64_t np = 0;
+    int gas_act = gas->active ? gas->active[j] : 1;
+    if (gas_act) {
+        double mu = gas_mu(gas, j), vs = gas_vs(gas, j);
+        double sig_kpc2 = par->sigma0_cm2 / (ORC_KPC_CM * ORC_KPC_CM);
+        double cfac = sig_kpc2 * pow(ORC_C_KMS, -par->n_pow);
+        double redm = mu / (par->m_chi_g + mu);
+        for (int64_t i = 0; i < dm->n; i++) {
+            double d;
+            if (!pair_test(gas, dm, par, j, i, &d, NULL)) continue;
+            np++;
+            double g = orc_overlap(d, dm->h[i], gas->h[j]);
+            double w[3], w2 = 0;
+            for (int k = 0; k < 3; k++) { w[k] = dm->vel[3 * i + k] - gas->vel[3 * j + k]; w2 += w[k] * w[k]; }
+            double A, B;
+            orc_rates(par->n_pow, sqrt(w2), vs, &A, &B);
+            double num = dm->mass[i] * ORC_MSUN_G / (par->m_chi_g + mu);
+            double fac = num * g * cfac;
+            for (int k = 0; k < 3; k++) { double t = fac * A * w[k]; nsum_add(&sp[k], t); ap[k] += fabs(t); }
+            double tE1 = fac * w2 * A, tE2 = -fac * redm * B;
+            nsum_add(&se, tE1);
+            nsum_add(&se, tE2);
+            ae += fabs(tE1) + fabs(tE2);
+        }
+    }
+    double sc = gas_act ? gas->mass[j] * p_dt(gas, par, j) : 0.0;
+    for (int k = 0; k < 3; k++) {
+        out->dp_gas[3 * j + k] = sc * nsum_get(&sp[k]);
+        if (out->dp_abs) out->dp_abs[3 * j + k] = sc * ap[k];
+    }
+    out->de_gas[j] = sc * nsum_get(&se);
+    if (out->de_abs) out->de_abs[j] = sc * ae;
+    *npairs += np;
+}
+
+/* Relative velocity v_i - v^B_ij with v^B_ij = V_j + varsigma_j z, z from the
+ * tag-0 block of pair (i,j) (one Maxwellian sample per pair, Sec. 2.2).      */
+static void pair_urel(const orc_particles *gas, const orc_particles *dm, const orc_params *par, int64_t j,
+                      int64_t i, double urel[3])
+{
+    double u[4], z[3];
+    orc_block(par->seed, (uint32_t)i, (uint32_t)j, par->step, 0u, par->box_id, u);
+    orc_normals3(u, z);
+    double vs = gas_vs(gas, j);
+    for (int k = 0; k < 3; k++) urel[k] = dm->vel[3 * i + k] - (gas->vel[3 * j + k] + vs * z[k]);
+}
+
+/* Scattering probability P_ij = (M_j/mu_j) g_ij sigma(v_rel) v_rel dt_i
+ * (eq. dm-update-prob), sigma = sigma0 (v/c)^n.                              */
+static double pair_P(const orc_particles *gas, const orc_particles *dm, const orc_params *par, int64_t j,
+                     int64_t i, double d, double urel[3])
+{
+    pair_urel(gas, dm, par, j, i, urel);
+    double vrel = sqrt(urel[0] * urel[0] + urel[1] * urel[1] + urel[2] * urel[2]);
+    double g = orc_overlap(d, dm->h[i], gas->h[j]);
+    double ncount = gas->mass[j] * ORC_MSUN_G / gas_mu(gas, j);
+    double sig = par->sigma0_cm2 / (ORC_KPC_CM * ORC_KPC_CM) * pow(vrel / ORC_C_KMS, par->n_pow);
+    return ncount * g * sig * vrel * p_dt(dm, par, i);
+}
+
+typedef struct { int64_t j; double P; double urel[3]; } orc_pair;
+
+static int cmp_pair(const void *x, const void *y)
+{
+    int64_t a = ((const orc_pair *)x)->j, b = ((const orc_pair *)y)->j;
+    return (a > b) - (a < b);
+}
+
+/* DM Monte Carlo for DM i (eq. dm-update-vels, dm-update-prob; Sec. 2.4):
+ * one categorical draw from nu'_i: U_i from the tag-2 block; if U_i < P_i =
+ * sum_j P_ij the partner is the first gas index (ascending) whose running sum
+ * exceeds U_i; the new direction is isotropic (tag-1 block of the chosen
+ * pair, cos theta = 2u0-1, phi = 2 pi u1) and the kick follows eq. scatter_chi
+ * with the same gas-velocity sample that set P_ij.  Criterion of eq.
+ * prob_criterion is counted, not enforced.                                   */
+static void dm_one(const orc_particles *gas, const orc_particles *dm, const orc_params *par, int64_t i,
+                   orc_out *out, uint64_t cnt[ORC_NCOUNTERS])
+{
+    for (int k = 0; k < 3; k++) out->dv_dm[3 * i + k] = 0.0;
+    out->partner[i] = -1;
+    if (out->p_sum) out->p_sum[i] = 0.0;
+    if (out->p_max) out->p_max[i] = 0.0;
+    if (out->flags) out->flags[i] = 0;
+    if (dm->active && !dm->active[i]) return;
+
+    size_t cap = 64, np = 0;
+    orc_pair *pairs = (orc_pair *)malloc(cap * sizeof(orc_pair));
+    int near_b = 0;
+    for (int64_t j = 0; j < gas->n; j++) {
+        double d;
+        int near;
+        int in = pair_test(gas, dm, par, j, i, &d, &near);
+        if (near) near_b = 1;
+        if (!in) continue;
+        if (np == cap) { cap *= 2; pairs = (orc_pair *)realloc(pairs, cap * sizeof(orc_pair)); }
+        pairs[np].j = j;
+        pairs[np].P = pair_P(gas, dm, par, j, i, d, pairs[np].urel);
+        np++;
+    }
+    qsort(pairs, np, sizeof(orc_pair), cmp_pair); /* already ascending; kept explicit */
+    double S = 0.0, pmax = 0.0;
+    int nonfinite = 0;
+    for (size_t k = 0; k < np; k++) {
+        double P = pairs[k].P;
+        if (!isfinite(P)) nonfinite = 1;
+        S += P;
+        if (P > pmax) pmax = P;
+        double mu = gas_mu(gas, pairs[k].j);
+        double q = (par->m_chi_g + mu) / mu;
+        double crit = fmin(0.1, 1e-4 * q * q);
+        if (P >= crit) cnt[ORC_C_CRIT_VIOL]++;
+    }
+    cnt[ORC_C_PAIRS_DM] += np;
+    if (nonfinite) cnt[ORC_C_NONFINITE]++;
+    if (S >= 1.0) cnt[ORC_C_P_GE_1]++;
+    if (near_b) cnt[ORC_C_NEAR_BOUNDARY]++;
+    if (out->p_sum) out->p_sum[i] = S;
+    if (out->p_max) out->p_max[i] = pmax;
+
+    double ud[4];
+    orc_block(par->seed, (uint32_t)i, 0xFFFFFFFFu, par->step, 2u, par->box_id, ud);
+    double U = ud[0];
+    int near_d = fabs(S - U) <= 1e-6 * U;
+    int64_t jstar = -1;
+    size_t kstar = 0;
+    if (U < S) {
+        double run = 0.0;
+        for (size_t k = 0; k < np; k++) {
+            run += pairs[k].P;
+            if (fabs(run - U) <= 1e-6 * U) near_d = 1;
+            if (jstar < 0 && run > U) { jstar = pairs[k].j; kstar = k; }
+        }
+        if (jstar < 0 && np > 0) { jstar = pairs[np - 1].j; kstar = np - 1; }
+    }
+    if (near_d) cnt[ORC_C_NEAR_DECISION]++;
+    if (out->flags) out->flags[i] = (uint8_t)((near_d ? 1 : 0) | (near_b ? 2 : 0));
+    if (jstar >= 0) {
+        cnt[ORC_C_SCATTERS]++;
+        out->partner[i] = (int32_t)jstar;
+        double *ur = pairs[kstar].urel;
+        double vrel = sqrt(ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2]);
+        if (vrel > 0.0) {
+            double ua[4];
+            orc_block(par->seed, (uint32_t)i, (uint32_t)jstar, par->step, 1u, par->box_id, ua);
+            double ct = 2.0 * ua[0] - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
+            double ph = 2.0 * ORC_PI * ua[1];
+            double nn[3] = {st * cos(ph), st * sin(ph), ct};
+            double mu = gas_mu(gas, jstar);
+            double fr = mu / (par->m_chi_g + mu);
+            for (int k = 0; k < 3; k++) out->dv_dm[3 * i + k] = fr * vrel * (nn[k] - ur[k] / vrel);
+        }
+    }
+    free(pairs);
+}
+
+/* Full step for selected owners.  gas_sel/dm_sel list the owner indices to
+ * evaluate (NULL => all).  Outputs of unselected owners are left untouched. */
+int orc_step_sel(const orc_particles *gas, const orc_particles *dm, const orc_params *par, orc_out *out,
+                 const int64_t *gas_sel, int64_t n_gas_sel, const int64_t *dm_sel, int64_t n_dm_sel)
+{
+    if (!gas || !dm || !par || !out) return -1;
+    memset(out->counters, 0, sizeof(out->counters));
+    int64_t ng = gas_sel ? n_gas_sel : gas->n;
+    int64_t nd = dm_sel ? n_dm_sel : dm->n;
+    uint64_t pg = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : pg)
+    for (int64_t t = 0; t < ng; t++) {
+        int64_t j = gas_sel ? gas_sel[t] : t;
+        gas_one(gas, dm, par, j, out, &pg);
+    }
+    out->counters[ORC_C_PAIRS_GAS] = pg;
+    uint64_t c[ORC_NCOUNTERS];
+    memset(c, 0, sizeof(c));
+    uint64_t c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0, c7 = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : c1, c2, c3, c4, c5, c6, c7)
+    for (int64_t t = 0; t < nd; t++) {
+        int64_t i = dm_sel ? dm_sel[t] : t;
+        uint64_t cl[ORC_NCOUNTERS];
+        memset(cl, 0, sizeof(cl));
+        dm_one(gas, dm, par, i, out, cl);
+        c1 += cl[ORC_C_PAIRS_DM]; c2 += cl[ORC_C_SCATTERS]; c3 += cl[ORC_C_NEAR_BOUNDARY];
+        c4 += cl[ORC_C_NEAR_DECISION]; c5 += cl[ORC_C_CRIT_VIOL]; c6 += cl[ORC_C_P_GE_1];
+        c7 += cl[ORC_C_NONFINITE];
+    }
+    out->counters[ORC_C_PAIRS_DM] = c1; out->counters[ORC_C_SCATTERS] = c2;
+    out->counters[ORC_C_NEAR_BOUNDARY] = c3; out->counters[ORC_C_NEAR_DECISION] = c4;
+    out->counters[ORC_C_CRIT_VIOL] = c5; out->counters[ORC_C_P_GE_1] = c6; out->counters[ORC_C_NONFINITE] = c7;
+    (void)c;
+    return 0;
+}
+
+int orc_step(const orc_particles *gas, const orc_particles *dm, const orc_params *par, orc_out *out)
+{
+    return orc_step_sel(gas, dm, par, out, NULL, 0, NULL, 0);
+}
+
+/* Brute-force pair set (Appendix D support; each unordered pair once):
+ * writes up to cap (dm index, gas index) pairs in (dm, gas) order and
+ * returns the total count.                                                   */
+int64_t orc_pairs(const orc_particles *gas, const orc_particles *dm, const orc_params *par, int64_t *out_i,
+                  int64_t *out_j, int64_t cap)
+{
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < dm->n; i++)
+        for (int64_t j = 0; j < gas->n; j++) {
+            double d;
+            if (pair_test(gas, dm, par, j, i, &d, NULL)) {
+                if (cnt < cap) { out_i[cnt] = i; out_j[cnt] = j; }
+                cnt++;
+            }
+        }
+    return cnt;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
