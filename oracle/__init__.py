@@ -49,7 +49,7 @@ class Params(C.Structure):
 
 class Out(C.Structure):
     _fields_ = [("dv_dm", C.c_void_p), ("dp_gas", C.c_void_p), ("de_gas", C.c_void_p),
-                ("dp_abs", C.c_void_p), ("de_abs", C.c_void_p), ("partner", C.c_void_p),
+                ("dp_abs", C.c_void_p), ("de_abs", C.c_void_p), ("pk_abs", C.c_void_p), ("partner", C.c_void_p),
                 ("p_sum", C.c_void_p), ("p_max", C.c_void_p), ("flags", C.c_void_p),
                 ("counters", C.c_uint64 * N_COUNTERS)]
 
@@ -180,10 +180,12 @@ def _params(p: dict) -> Params:
                   int(p.get("box_id", 0)), (C.c_double * 3)(*[float(b) for b in box]))
 
 
-def step(gas: dict, dm: dict, params: dict, gas_sel=None, dm_sel=None) -> dict:
+def step(gas: dict, dm: dict, params: dict, gas_sel=None, dm_sel=None, peak_scale=False) -> dict:
     """Run the oracle step.  gas/dm: dicts of numpy arrays (pos, vel, mass, h,
     u, mu, active, dt); params: sigma0_cm2, n_pow, m_chi_g, dt, seed, step,
-    box_id, box.  gas_sel / dm_sel: optional owner index subsets."""
+    box_id, box.  gas_sel / dm_sel: optional owner index subsets.  peak_scale
+    also returns pk_abs: per gas, the sum of |terms| with each overlap
+    replaced by its value at zero separation."""
     keep: list = []
     G = _particles(gas, keep)
     D = _particles(dm, keep)
@@ -191,11 +193,15 @@ def step(gas: dict, dm: dict, params: dict, gas_sel=None, dm_sel=None) -> dict:
     ng, nd = G.n, D.n
     res = {
         "dv_dm": np.zeros((nd, 3)), "dp_gas": np.zeros((ng, 3)), "de_gas": np.zeros(ng),
-        "dp_abs": np.zeros((ng, 3)), "de_abs": np.zeros(ng), "partner": np.full(nd, -1, np.int32),
+        "dp_abs": np.zeros((ng, 3)), "de_abs": np.zeros(ng), "pk_abs": np.zeros(ng),
+        "partner": np.full(nd, -1, np.int32),
         "p_sum": np.zeros(nd), "p_max": np.zeros(nd), "flags": np.zeros(nd, np.uint8),
     }
-    O = Out(*(res[k].ctypes.data for k in ["dv_dm", "dp_gas", "de_gas", "dp_abs", "de_abs", "partner",
-                                            "p_sum", "p_max", "flags"]))
+    if not peak_scale:
+        res["pk_abs"] = None
+    O = Out(*(None if res[k] is None else res[k].ctypes.data
+              for k in ["dv_dm", "dp_gas", "de_gas", "dp_abs", "de_abs", "pk_abs", "partner", "p_sum", "p_max",
+                        "flags"]))
     gs = None if gas_sel is None else np.ascontiguousarray(gas_sel, dtype=np.int64)
     ds = None if dm_sel is None else np.ascontiguousarray(dm_sel, dtype=np.int64)
     keep.extend(a for a in (gs, ds) if a is not None)

@@ -309,6 +309,7 @@ typedef struct {
     double *de_gas;           /* [n_gas] Msun (km/s)^2, internal energy */
     double *dp_abs;           /* [n_gas][3] sum of |terms| (nullable) */
     double *de_abs;           /* [n_gas] (nullable) */
+    double *pk_abs;           /* [n_gas] sum over pairs and components of |term| g(0)/g (nullable) */
     int32_t *partner;         /* [n_dm] gas index or -1 */
     double *p_sum;            /* [n_dm] (nullable) */
     double *p_max;            /* [n_dm] (nullable) */
@@ -361,7 +362,7 @@ static void gas_one(const orc_particles *gas, const orc_particles *dm, const orc
                     orc_out *out, uint64_t *npairs)
 {
     orc_sum sp[3] = {{0, 0}, {0, 0}, {0, 0}}, se = {0, 0};
-    double ap[3] = {0, 0, 0}, ae = 0;
+    double ap[3] = {0, 0, 0}, ae = 0, apk = 0;
     uint64_t np = 0;
     int gas_act = gas->active ? gas->active[j] : 1;
     if (gas_act) {
@@ -385,6 +386,10 @@ static void gas_one(const orc_particles *gas, const orc_particles *dm, const orc
             nsum_add(&se, tE1);
             nsum_add(&se, tE2);
             ae += fabs(tE1) + fabs(tE2);
+            if (out->pk_abs && g > 0.0) {
+                double gpk = orc_overlap(0.0, dm->h[i], gas->h[j]);
+                apk += (fabs(fac * A) * (fabs(w[0]) + fabs(w[1]) + fabs(w[2])) + fabs(tE1) + fabs(tE2)) * gpk / g;
+            }
         }
     }
     double sc = gas_act ? gas->mass[j] * p_dt(gas, par, j) : 0.0;
@@ -394,6 +399,7 @@ static void gas_one(const orc_particles *gas, const orc_particles *dm, const orc
     }
     out->de_gas[j] = sc * nsum_get(&se);
     if (out->de_abs) out->de_abs[j] = sc * ae;
+    if (out->pk_abs) out->pk_abs[j] = sc * apk;
     *npairs += np;
 }
 

@@ -1,0 +1,217 @@
+"""MI355X (gfx950) DM-gas pair interaction step of Hainje & Farrar (arXiv 2603.24688).
+
+Thin ctypes binding over the C ABI of ``libdmb.so`` (declared in
+``include/dmb.h``).  Every step of the computation runs in the HIP kernels of
+the library; this module only marshals torch device tensors into the C
+structs.  Importing works without a GPU; calling needs the built library and a
+HIP device and raises otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libdmb.so")
+
+DMB_FP64, DMB_FP32 = 0, 1
+DMB_RATES_EXACT = 0
+COUNTER_NAMES = ["pairs_gas", "pairs_dm", "scatters", "near_boundary", "near_decision",
+                 "crit_viol", "p_ge_1", "nonfinite"]
+N_COUNTERS = len(COUNTER_NAMES)
+STATUS = {0: "DMB_OK", -1: "DMB_EINVAL", -2: "DMB_ENOMEM", -3: "DMB_EHIP", -4: "DMB_ERANGE", -5: "DMB_ESTALE"}
+
+# Symbols declared in include/dmb.h.
+EXPORTS = ["dmb_create", "dmb_destroy", "dmb_set_stream", "dmb_build_cells", "dmb_interact_step",
+           "dmb_overlap_eval", "dmb_rates_eval", "dmb_philox_eval", "dmb_profile_enable", "dmb_profile_read",
+           "dmb_last_error"]
+PHASES = ["build", "gather", "pass_gas", "combine_gas", "pass_dm", "combine_dm", "resolve"]
+
+
+class DmbError(RuntimeError):
+    pass
+
+
+class Particles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("vel", C.c_void_p), ("mass", C.c_void_p),
+                ("h", C.c_void_p), ("u", C.c_void_p), ("mu", C.c_void_p), ("active", C.c_void_p),
+                ("dt", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("sigma0_cm2", C.c_double), ("n_pow", C.c_int32), ("m_chi_g", C.c_double), ("dt", C.c_double),
+                ("seed", C.c_uint64), ("step", C.c_uint32), ("box_id", C.c_uint32), ("box", C.c_double * 3),
+                ("precision", C.c_int32), ("rates", C.c_int32)]
+
+
+class Out(C.Structure):
+    _fields_ = [("dv_dm", C.c_void_p), ("dp_gas", C.c_void_p), ("de_gas", C.c_void_p), ("partner", C.c_void_p),
+                ("p_sum", C.c_void_p), ("p_max", C.c_void_p), ("counters", C.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libdmb.so and declare the C signatures.  Raises if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise DmbError(f"{path} is not built; run paper_2603_24688_amd.build.build()")
+    L = C.CDLL(path)
+    vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+    L.dmb_create.restype = C.c_int; L.dmb_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+    L.dmb_destroy.restype = C.c_int; L.dmb_destroy.argtypes = [vp]
+    L.dmb_set_stream.restype = C.c_int; L.dmb_set_stream.argtypes = [vp, vp]
+    L.dmb_build_cells.restype = C.c_int
+    L.dmb_build_cells.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params)]
+    L.dmb_interact_step.restype = C.c_int
+    L.dmb_interact_step.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params), C.POINTER(Out)]
+    L.dmb_overlap_eval.restype = C.c_int; L.dmb_overlap_eval.argtypes = [vp, i64, vp, vp, vp, i32, vp]
+    L.dmb_rates_eval.restype = C.c_int; L.dmb_rates_eval.argtypes = [vp, i64, vp, vp, i32, i32, vp, vp]
+    L.dmb_philox_eval.restype = C.c_int; L.dmb_philox_eval.argtypes = [vp, i64, vp, u64, vp]
+    L.dmb_profile_enable.restype = C.c_int; L.dmb_profile_enable.argtypes = [vp, i32]
+    L.dmb_profile_read.restype = C.c_int; L.dmb_profile_read.argtypes = [vp, vp, vp, i32]
+    L.dmb_last_error.restype = C.c_char_p; L.dmb_last_error.argtypes = [vp]
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise DmbError("tensors passed to the HIP library must live on the GPU")
+    if not t.is_contiguous():
+        raise DmbError("tensors passed to the HIP library must be contiguous")
+    return t.data_ptr()
+
+
+def _particles(d: dict) -> Particles:
+    return Particles(int(d["mass"].shape[0]), _ptr(d["pos"]), _ptr(d.get("vel")), _ptr(d.get("mass")),
+                     _ptr(d["h"]), _ptr(d.get("u")), _ptr(d.get("mu")), _ptr(d.get("active")), _ptr(d.get("dt")))
+
+
+def _params(p: dict, precision: int) -> Params:
+    box = p.get("box") or (0.0, 0.0, 0.0)
+    return Params(float(p["sigma0_cm2"]), int(p.get("n_pow", 0)), float(p["m_chi_g"]), float(p["dt"]),
+                  int(p["seed"]) & 0xFFFFFFFFFFFFFFFF, int(p.get("step", 0)) & 0xFFFFFFFF, int(p.get("box_id", 0)),
+                  (C.c_double * 3)(*[float(b) for b in box]), int(precision), int(p.get("rates", DMB_RATES_EXACT)))
+
+
+class Context:
+    """One library context bound to a HIP device and stream (torch's current
+    stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise DmbError("no HIP device visible")
+        self.device = device
+        s = torch.cuda.current_stream(device) if stream is None else stream
+        self.stream = s
+        h = C.c_void_p()
+        rc = self.lib.dmb_create(C.byref(h), int(device), C.c_void_p(s.cuda_stream))
+        if rc != 0:
+            raise DmbError(f"dmb_create failed: {STATUS.get(rc, rc)}")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dmb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, what: str):
+        if rc != 0:
+            msg = self.lib.dmb_last_error(self.h).decode(errors="replace")
+            raise DmbError(f"{what}: {STATUS.get(rc, rc)}: {msg}")
+
+    # -- the two calls of the hot path ---------------------------------------------------------
+    def build_cells(self, gas: dict, dm: dict, params: dict, precision: int = DMB_FP32):
+        G, D, P = _particles(gas), _particles(dm), _params(params, precision)
+        self._check(self.lib.dmb_build_cells(self.h, C.byref(G), C.byref(D), C.byref(P)), "dmb_build_cells")
+
+    def interact_step(self, gas: dict, dm: dict, params: dict, out: dict, precision: int = DMB_FP32):
+        G, D, P = _particles(gas), _particles(dm), _params(params, precision)
+        O = Out(_ptr(out["dv_dm"]), _ptr(out["dp_gas"]), _ptr(out["de_gas"]), _ptr(out["partner"]),
+                _ptr(out.get("p_sum")), _ptr(out.get("p_max")), _ptr(out.get("counters")))
+        self._check(self.lib.dmb_interact_step(self.h, C.byref(G), C.byref(D), C.byref(P), C.byref(O)),
+                    "dmb_interact_step")
+
+    # -- phase timing ---------------------------------------------------------------------------
+    def profile_enable(self, on: bool = True):
+        self._check(self.lib.dmb_profile_enable(self.h, int(bool(on))), "dmb_profile_enable")
+
+    def profile_read(self, reset: bool = True) -> dict:
+        ms = (C.c_double * len(PHASES))()
+        calls = (C.c_int64 * len(PHASES))()
+        self._check(self.lib.dmb_profile_read(self.h, ms, calls, int(bool(reset))), "dmb_profile_read")
+        return {p: (ms[k], int(calls[k])) for k, p in enumerate(PHASES)}
+
+    # -- evaluation helpers -------------------------------------------------------------------
+    def overlap_eval(self, d, h1, h2, precision: int = DMB_FP32):
+        import torch
+        g = torch.empty_like(d)
+        self._check(self.lib.dmb_overlap_eval(self.h, d.numel(), _ptr(d), _ptr(h1), _ptr(h2), precision, _ptr(g)),
+                    "dmb_overlap_eval")
+        return g
+
+    def rates_eval(self, w, vs, n_pow: int, precision: int = DMB_FP32):
+        import torch
+        A, B = torch.empty_like(w), torch.empty_like(w)
+        self._check(self.lib.dmb_rates_eval(self.h, w.numel(), _ptr(w), _ptr(vs), int(n_pow), precision, _ptr(A),
+                                            _ptr(B)), "dmb_rates_eval")
+        return A, B
+
+    def philox_eval(self, ctr, seed: int):
+        import torch
+        out = torch.empty_like(ctr)
+        self._check(self.lib.dmb_philox_eval(self.h, ctr.shape[0], _ptr(ctr), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                             _ptr(out)), "dmb_philox_eval")
+        return out
+
+
+def alloc_out(n_gas: int, n_dm: int, device="cuda"):
+    """Output buffers for interact_step (torch tensors on `device`)."""
+    import torch
+    return {
+        "dv_dm": torch.empty((n_dm, 3), dtype=torch.float64, device=device),
+        "dp_gas": torch.empty((n_gas, 3), dtype=torch.float64, device=device),
+        "de_gas": torch.empty((n_gas,), dtype=torch.float64, device=device),
+        "partner": torch.empty((n_dm,), dtype=torch.int32, device=device),
+        "p_sum": torch.empty((n_dm,), dtype=torch.float64, device=device),
+        "p_max": torch.empty((n_dm,), dtype=torch.float64, device=device),
+        "counters": torch.zeros((N_COUNTERS,), dtype=torch.int64, device=device),
+    }
+
+
+def to_device(species: dict, device="cuda") -> dict:
+    """numpy particle dict -> contiguous torch tensors on `device`."""
+    import numpy as np
+    import torch
+    out = {}
+    for k, v in species.items():
+        if v is None:
+            continue
+        a = np.ascontiguousarray(v)
+        t = torch.from_numpy(a)
+        if k == "active":
+            t = t.to(torch.uint8)
+        out[k] = t.to(device).contiguous()
+    return out
+
+
+def counters_dict(t) -> dict:
+    vals = t.cpu().tolist()
+    return {k: int(v) for k, v in zip(COUNTER_NAMES, vals)}

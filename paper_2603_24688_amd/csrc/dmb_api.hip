@@ -1,0 +1,733 @@
+// dmb_api.hip -- host side of the C ABI declared in include/dmb.h.
+//
+// Owns the device buffers (grow-only), validates arguments before enqueuing
+// anything, and launches the kernels of dmb_kernels.h on the context stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/dmb.h"
+#include "dmb_kernels.h"
+#include "dmb_sort.h"
+
+using namespace dmb;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+struct Species {
+    int64_t n = 0, n_own = 0, ntile = 0, nsuper = 0, nown_tile = 0;
+    DevBuf keys, keys2, vals, vals2;       // sort
+    DevBuf sx, sy, sz, sh;                 // sorted position, h
+    DevBuf flag, flag_off, own;            // active owners (sorted positions)
+    DevBuf tbox, th, sbox, shh, obox, oh;  // tiles, super-tiles, owner tiles
+    DevBuf cube;                           // Morton cube
+    // per-step gathers (sorted order)
+    DevBuf v0, v1, v2;                     // velocity components (double)
+    DevBuf r0, r1, r2, r3, r4, r5, r6;     // Real-typed per-particle factors
+    const uint32_t* perm = nullptr;        // = vals after the sort
+};
+
+struct Pairs {                             // candidate lists: owner tiles of A x tiles of B
+    DevBuf cnt, off, cand, icnt, ioff, it_tile, it_cb, it_ce;
+    int64_t total = 0, nitems = 0;
+};
+
+}  // namespace
+
+struct dmb_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 256;
+    DevBuf gtab;
+    Species gas, dm;
+    Pairs gp, dp;                          // gas owners x DM tiles; DM owners x gas tiles
+    DevBuf scan_tmp[4];
+    DevBuf sort_table;
+    DevBuf bbox_part, boxL;
+    DevBuf part_gas, part_p, part_pm, psum_own;
+    DevBuf qctr, slist;
+    DevBuf counters_local;
+    int64_t built_ngas = -1, built_ndm = -1;
+    const double* built_gas_pos = nullptr;
+    const double* built_dm_pos = nullptr;
+    double built_L[3] = {0, 0, 0};
+    int split = 16;
+    // phase timing
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct Pending { int phase; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    double ph_ms[DMB_NPHASES] = {0};
+    int64_t ph_calls[DMB_NPHASES] = {0};
+    char err[512] = {0};
+};
+
+namespace {
+
+dmb_status fail(dmb_ctx* c, dmb_status st, const char* fmt, ...)
+{
+    if (c) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(c->err, sizeof(c->err), fmt, ap);
+        va_end(ap);
+    }
+    return st;
+}
+
+#define HIPCHK(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return fail(ctx, DMB_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+dmb_status ensure(dmb_ctx* c, DevBuf& b, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (bytes <= b.cap) return DMB_OK;
+    if (b.p) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return fail(c, DMB_EHIP, "sync before realloc: %s", hipGetErrorString(e));
+        hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t nb = bytes + bytes / 4 + 256;
+    if (hipMalloc(&b.p, nb) != hipSuccess) {
+        b.p = nullptr;
+        return fail(c, DMB_ENOMEM, "hipMalloc(%zu) failed", nb);
+    }
+    b.cap = nb;
+    return DMB_OK;
+}
+
+#define ENSURE(ctx, buf, bytes)                          \
+    do {                                                 \
+        dmb_status s_ = ensure(ctx, buf, (bytes));       \
+        if (s_ != DMB_OK) return s_;                     \
+    } while (0)
+
+hipEvent_t ev_get(dmb_ctx* c)
+{
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// RAII phase marker: records a start event now and a stop event on scope exit.
+struct Phase {
+    dmb_ctx* c;
+    int ph;
+    hipEvent_t a = nullptr;
+    Phase(dmb_ctx* c_, int ph_) : c(c_), ph(ph_)
+    {
+        if (c->prof && (a = ev_get(c))) hipEventRecord(a, c->stream);
+    }
+    ~Phase()
+    {
+        if (!a) return;
+        hipEvent_t b = ev_get(c);
+        if (!b) { c->ev_pool.push_back(a); return; }
+        hipEventRecord(b, c->stream);
+        c->pending.push_back({ph, a, b});
+    }
+};
+
+inline unsigned blocks_for(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
+
+// Exclusive scan of n u32 values in place into out (out may equal in).
+dmb_status scan_excl(dmb_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, int level = 0)
+{
+    if (n <= 0) return DMB_OK;
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (level >= 4) return fail(c, DMB_EINVAL, "scan too large");
+    ENSURE(c, c->scan_tmp[level], size_t(nb + 1) * sizeof(uint32_t));
+    uint32_t* sums = c->scan_tmp[level].as<uint32_t>();
+    hipLaunchKernelGGL(k_scan_block, dim3(unsigned(nb)), dim3(kScanBlock), 0, c->stream, in, out, sums, n);
+    if (nb > 1) {
+        dmb_status s = scan_excl(c, sums, sums, nb, level + 1);
+        if (s != DMB_OK) return s;
+        hipLaunchKernelGGL(k_scan_add, dim3(unsigned(nb)), dim3(kScanBlock), 0, c->stream, out, sums, n);
+    }
+    HIPCHK(c, hipGetLastError());
+    return DMB_OK;
+}
+
+int bits_for(int64_t n)
+{
+    int b = 1;
+    while ((int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+dmb_status check_particles(dmb_ctx* c, const dmb_particles* p, const char* name, bool gas)
+{
+    if (!p) return fail(c, DMB_EINVAL, "%s: null particle struct", name);
+    if (p->n < 0) return fail(c, DMB_EINVAL, "%s: n < 0", name);
+    if (p->n >= (int64_t(1) << 31)) return fail(c, DMB_ERANGE, "%s: n >= 2^31", name);
+    if (p->n > 0 && (!p->pos || !p->h)) return fail(c, DMB_EINVAL, "%s: null pos or h", name);
+    (void)gas;
+    return DMB_OK;
+}
+
+// Morton sort + tiles + owner tiles + super tiles for one species.
+dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
+{
+    S.n = p->n;
+    if (S.n == 0) {
+        S.n_own = S.ntile = S.nsuper = S.nown_tile = 0;
+        return DMB_OK;
+    }
+    const int64_t n = S.n;
+    ENSURE(c, S.keys, n * 8); ENSURE(c, S.keys2, n * 8);
+    ENSURE(c, S.vals, n * 4); ENSURE(c, S.vals2, n * 4);
+    ENSURE(c, S.cube, 8 * sizeof(double));
+    const int nparts = 256;
+    ENSURE(c, c->bbox_part, nparts * 6 * sizeof(double));
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nparts), dim3(256), 0, c->stream, p->pos, n, c->bbox_part.as<double>());
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, c->stream, c->bbox_part.as<const double>(), nparts,
+                       c->boxL.as<const double>(), S.cube.as<double>());
+    hipLaunchKernelGGL(k_morton, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, p->pos, n,
+                       S.cube.as<const double>(), c->boxL.as<const double>(), S.keys.as<uint64_t>(),
+                       S.vals.as<uint32_t>());
+    // radix sort on the top bits that resolve ~2^6 particles per cell
+    int need = std::min(63, std::max(24, 3 * ((bits_for(n) + 6 + 2) / 3)));
+    int passes = (need + 7) / 8;
+    int nblk = int((n + kSortTile - 1) / kSortTile);
+    int64_t tsz = int64_t(256) * nblk;
+    ENSURE(c, c->sort_table, size_t(tsz + 1) * 4);
+    uint64_t *ka = S.keys.as<uint64_t>(), *kb = S.keys2.as<uint64_t>();
+    uint32_t *va = S.vals.as<uint32_t>(), *vb = S.vals2.as<uint32_t>();
+    for (int ps = 0; ps < passes; ++ps) {
+        int shift = 63 - 8 * (passes - ps);
+        if (shift < 0) shift = 0;
+        hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(kSortBlock), 0, c->stream, ka, n, shift,
+                           c->sort_table.as<uint32_t>(), nblk);
+        dmb_status s = scan_excl(c, c->sort_table.as<uint32_t>(), c->sort_table.as<uint32_t>(), tsz);
+        if (s != DMB_OK) return s;
+        hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(kSortBlock), 0, c->stream, ka, va, kb, vb, n, shift,
+                           c->sort_table.as<const uint32_t>(), nblk);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    // keep the sorted permutation in S.vals
+    if (va != S.vals.as<uint32_t>()) {
+        std::swap(S.vals, S.vals2);
+        std::swap(S.keys, S.keys2);
+    }
+    S.perm = S.vals.as<const uint32_t>();
+    ENSURE(c, S.sx, n * 8); ENSURE(c, S.sy, n * 8); ENSURE(c, S.sz, n * 8); ENSURE(c, S.sh, n * 8);
+    hipLaunchKernelGGL(k_gather_pos, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, S.perm, n, p->pos, p->h,
+                       c->boxL.as<const double>(), S.sx.as<double>(), S.sy.as<double>(), S.sz.as<double>(),
+                       S.sh.as<double>());
+    // owners (active subset, Morton order)
+    ENSURE(c, S.flag, (n + 1) * 4); ENSURE(c, S.flag_off, (n + 1) * 4); ENSURE(c, S.own, n * 4);
+    hipLaunchKernelGGL(k_active_flags, dim3(blocks_for(n + 1, 256)), dim3(256), 0, c->stream, S.perm, n, p->active,
+                       S.flag.as<uint32_t>());
+    dmb_status s = scan_excl(c, S.flag.as<const uint32_t>(), S.flag_off.as<uint32_t>(), n + 1);
+    if (s != DMB_OK) return s;
+    hipLaunchKernelGGL(k_compact, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, S.flag.as<const uint32_t>(),
+                       S.flag_off.as<const uint32_t>(), n, S.own.as<uint32_t>());
+    // tiles over all particles (other role) and super-tiles
+    S.ntile = (n + kTile - 1) / kTile;
+    S.nsuper = (S.ntile + kTile - 1) / kTile;
+    ENSURE(c, S.tbox, S.ntile * 48); ENSURE(c, S.th, S.ntile * 8);
+    ENSURE(c, S.sbox, S.nsuper * 48); ENSURE(c, S.shh, S.nsuper * 8);
+    hipLaunchKernelGGL(k_tile_bounds, dim3(unsigned(S.ntile)), dim3(64), 0, c->stream, (const uint32_t*)nullptr, n,
+                       S.sx.as<const double>(), S.sy.as<const double>(), S.sz.as<const double>(),
+                       S.sh.as<const double>(), S.tbox.as<double>(), S.th.as<double>());
+    hipLaunchKernelGGL(k_super_bounds, dim3(unsigned(S.nsuper)), dim3(64), 0, c->stream, S.ntile,
+                       S.tbox.as<const double>(), S.th.as<const double>(), S.sbox.as<double>(), S.shh.as<double>());
+    HIPCHK(c, hipGetLastError());
+    return DMB_OK;
+}
+
+// Owner tiles need n_own, known after a read-back.
+dmb_status build_owner_tiles(dmb_ctx* c, Species& S)
+{
+    S.nown_tile = (S.n_own + kTile - 1) / kTile;
+    if (S.nown_tile == 0) return DMB_OK;
+    ENSURE(c, S.obox, S.nown_tile * 48); ENSURE(c, S.oh, S.nown_tile * 8);
+    hipLaunchKernelGGL(k_tile_bounds, dim3(unsigned(S.nown_tile)), dim3(64), 0, c->stream, S.own.as<const uint32_t>(),
+                       S.n_own, S.sx.as<const double>(), S.sy.as<const double>(), S.sz.as<const double>(),
+                       S.sh.as<const double>(), S.obox.as<double>(), S.oh.as<double>());
+    HIPCHK(c, hipGetLastError());
+    return DMB_OK;
+}
+
+CandArgs cand_args(dmb_ctx* c, Species& A, Species& B, Pairs& P)
+{
+    CandArgs a;
+    a.nown_tile = A.nown_tile; a.ntile = B.ntile; a.nsuper = B.nsuper;
+    a.obox = A.obox.as<const double>(); a.oh = A.oh.as<const double>();
+    a.tbox = B.tbox.as<const double>(); a.th = B.th.as<const double>();
+    a.sbox = B.sbox.as<const double>(); a.shh = B.shh.as<const double>();
+    for (int k = 0; k < 3; ++k) a.L[k] = c->built_L[k];
+    a.cnt = P.cnt.as<uint32_t>(); a.off = P.off.as<const uint32_t>(); a.cand = P.cand.as<uint32_t>();
+    return a;
+}
+
+dmb_status cand_count(dmb_ctx* c, Species& A, Species& B, Pairs& P)
+{
+    int64_t nt = A.nown_tile;
+    ENSURE(c, P.cnt, (nt + 1) * 4); ENSURE(c, P.off, (nt + 1) * 4);
+    ENSURE(c, P.icnt, (nt + 1) * 4); ENSURE(c, P.ioff, (nt + 1) * 4);
+    if (nt == 0 || B.ntile == 0) {
+        HIPCHK(c, hipMemsetAsync(P.off.p, 0, (nt + 1) * 4, c->stream));
+        HIPCHK(c, hipMemsetAsync(P.ioff.p, 0, (nt + 1) * 4, c->stream));
+        return DMB_OK;
+    }
+    CandArgs a = cand_args(c, A, B, P);
+    hipLaunchKernelGGL(k_cand<false>, dim3(unsigned(nt)), dim3(64), 0, c->stream, a);
+    HIPCHK(c, hipMemsetAsync(P.cnt.as<uint32_t>() + nt, 0, 4, c->stream));
+    dmb_status s = scan_excl(c, P.cnt.as<const uint32_t>(), P.off.as<uint32_t>(), nt + 1);
+    if (s != DMB_OK) return s;
+    hipLaunchKernelGGL(k_item_count, dim3(blocks_for(nt + 1, 256)), dim3(256), 0, c->stream,
+                       P.cnt.as<const uint32_t>(), nt, uint32_t(c->split), P.icnt.as<uint32_t>());
+    s = scan_excl(c, P.icnt.as<const uint32_t>(), P.ioff.as<uint32_t>(), nt + 1);
+    if (s != DMB_OK) return s;
+    HIPCHK(c, hipGetLastError());
+    return DMB_OK;
+}
+
+dmb_status cand_write(dmb_ctx* c, Species& A, Species& B, Pairs& P)
+{
+    int64_t nt = A.nown_tile;
+    ENSURE(c, P.cand, std::max<int64_t>(P.total, 1) * 4);
+    ENSURE(c, P.it_tile, std::max<int64_t>(P.nitems, 1) * 4);
+    ENSURE(c, P.it_cb, std::max<int64_t>(P.nitems, 1) * 4);
+    ENSURE(c, P.it_ce, std::max<int64_t>(P.nitems, 1) * 4);
+    if (nt == 0 || B.ntile == 0 || P.total == 0) return DMB_OK;
+    CandArgs a = cand_args(c, A, B, P);
+    hipLaunchKernelGGL(k_cand<true>, dim3(unsigned(nt)), dim3(64), 0, c->stream, a);
+    hipLaunchKernelGGL(k_item_write, dim3(blocks_for(nt, 256)), dim3(256), 0, c->stream, P.off.as<const uint32_t>(),
+                       P.ioff.as<const uint32_t>(), nt, uint32_t(c->split), P.it_tile.as<uint32_t>(),
+                       P.it_cb.as<uint32_t>(), P.it_ce.as<uint32_t>());
+    HIPCHK(c, hipGetLastError());
+    return DMB_OK;
+}
+
+double alpha_n(int n) { return std::pow(2.0, 0.5 * (n + 5)) * std::tgamma(3.0 + 0.5 * n) / std::sqrt(kPi); }
+
+bool n_supported(int n) { return n == -4 || n == -2 || n == 0 || n == 2; }
+
+PassGeom geom(dmb_ctx* c, Species& A, Species& B, Pairs& P, uint64_t* counters)
+{
+    PassGeom g;
+    g.own = A.own.as<const uint32_t>(); g.n_own = A.n_own;
+    g.ox = A.sx.as<const double>(); g.oy = A.sy.as<const double>(); g.oz = A.sz.as<const double>();
+    g.oh = A.sh.as<const double>(); g.obox = A.obox.as<const double>();
+    g.tx = B.sx.as<const double>(); g.ty = B.sy.as<const double>(); g.tz = B.sz.as<const double>();
+    g.th = B.sh.as<const double>(); g.n_other = B.n; g.tbox = B.tbox.as<const double>();
+    g.cand = P.cand.as<const uint32_t>();
+    g.it_tile = P.it_tile.as<const uint32_t>(); g.it_cb = P.it_cb.as<const uint32_t>();
+    g.it_ce = P.it_ce.as<const uint32_t>(); g.n_items = P.nitems;
+    g.queue_ctr = c->qctr.as<uint32_t>();
+    for (int k = 0; k < 3; ++k) g.L[k] = c->built_L[k];
+    g.counters = counters;
+    return g;
+}
+
+template <typename Real, int N>
+dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
+                       dmb_out* out, uint64_t* counters)
+{
+    constexpr bool kExact = sizeof(Real) == 8;
+    const int nb_persist = std::max(8, (c->num_cu * 8 / 8) * 8);
+    const uint32_t k0 = uint32_t(par->seed), k1 = uint32_t(par->seed >> 32);
+    const double sig_kpc2_cn = par->sigma0_cm2 / (kKpcCm * kKpcCm) * std::pow(kCKms, -double(par->n_pow));
+    Species& G = c->gas;
+    Species& D = c->dm;
+    const int rs = int(sizeof(Real));
+    // gathers
+    Phase* ph_g = new Phase(c, DMB_PH_GATHER);
+    if (G.n > 0) {
+        ENSURE(c, G.v0, G.n * 8); ENSURE(c, G.v1, G.n * 8); ENSURE(c, G.v2, G.n * 8);
+        DevBuf* rb[7] = {&G.r0, &G.r1, &G.r2, &G.r3, &G.r4, &G.r5, &G.r6};
+        for (DevBuf* b : rb) ENSURE(c, *b, G.n * rs);
+        GasGatherArgs ga;
+        ga.n = G.n; ga.perm = G.perm; ga.vel = gas->vel; ga.mass = gas->mass; ga.u = gas->u; ga.mu = gas->mu;
+        ga.m_chi = par->m_chi_g; ga.sig_kpc2_cn = sig_kpc2_cn; ga.alpha_n = alpha_n(par->n_pow); ga.n_pow = par->n_pow;
+        ga.Vx = G.v0.as<double>(); ga.Vy = G.v1.as<double>(); ga.Vz = G.v2.as<double>();
+        ga.vs = G.r0.p; ga.inv2s2 = G.r1.p; ga.ra = G.r2.p; ga.rb = G.r3.p; ga.rr = G.r4.p; ga.K = G.r5.p;
+        ga.crit = G.r6.p;
+        hipLaunchKernelGGL(k_gather_gas<Real>, dim3(blocks_for(G.n, 256)), dim3(256), 0, c->stream, ga);
+    }
+    if (D.n > 0) {
+        ENSURE(c, D.v0, D.n * 8); ENSURE(c, D.v1, D.n * 8); ENSURE(c, D.v2, D.n * 8);
+        ENSURE(c, D.r0, D.n * rs); ENSURE(c, D.r1, D.n * rs);
+        DmGatherArgs da;
+        da.n = D.n; da.perm = D.perm; da.vel = dm->vel; da.mass = dm->mass; da.dt = dm->dt;
+        da.dt_default = par->dt;
+        da.vx = D.v0.as<double>(); da.vy = D.v1.as<double>(); da.vz = D.v2.as<double>();
+        da.m = D.r0.p; da.dtr = D.r1.p;
+        hipLaunchKernelGGL(k_gather_dm<Real>, dim3(blocks_for(D.n, 256)), dim3(256), 0, c->stream, da);
+    }
+    // outputs, counters, work-queue counters
+    // qctr: [0, 8) gas work queue, [8, 16) DM work queue, [16] scatter count
+    ENSURE(c, c->qctr, (2 * kXcd + 4) * 4);
+    uint32_t* scount = c->qctr.as<uint32_t>() + 2 * kXcd;
+    int64_t nfill = std::max<int64_t>(std::max<int64_t>(G.n, D.n), 2 * kXcd + 4);
+    hipLaunchKernelGGL(k_fill_out, dim3(blocks_for(nfill, 256)), dim3(256), 0, c->stream, G.n, D.n, out->dp_gas,
+                       out->de_gas, out->dv_dm, out->partner, out->p_sum, out->p_max, counters,
+                       c->qctr.as<uint32_t>(), 2 * kXcd + 4);
+    delete ph_g;
+    // gas pass
+    if (c->gp.nitems > 0) {
+        ENSURE(c, c->part_gas, size_t(c->gp.nitems) * kTile * 4 * 8);
+        GasPassArgs a;
+        a.g = geom(c, G, D, c->gp, counters);
+        a.Vx = G.v0.as<const double>(); a.Vy = G.v1.as<const double>(); a.Vz = G.v2.as<const double>();
+        a.inv2s2 = G.r1.p; a.ra = G.r2.p; a.rb = G.r3.p; a.rr = G.r4.p;
+        a.dvx = D.v0.as<const double>(); a.dvy = D.v1.as<const double>(); a.dvz = D.v2.as<const double>();
+        a.dm_m = D.r0.p;
+        a.gtab = c->gtab.as<const float4>();
+        a.part = c->part_gas.as<double>();
+        int nb = int(std::min<int64_t>(nb_persist, ((c->gp.nitems + 7) / 8) * 8));
+        {
+            Phase ph(c, DMB_PH_PASS_GAS);
+            hipLaunchKernelGGL((k_pass_gas<Real, N, kExact>), dim3(nb), dim3(64), 0, c->stream, a);
+        }
+        GasCombineArgs cb;
+        cb.n_own = G.n_own; cb.own = G.own.as<const uint32_t>(); cb.perm = G.perm;
+        cb.item_off = c->gp.ioff.as<const uint32_t>(); cb.part = c->part_gas.as<const double>();
+        cb.mass = gas->mass; cb.mu = gas->mu; cb.dt = gas->dt; cb.dt_default = par->dt; cb.m_chi = par->m_chi_g;
+        cb.sig_kpc2_cn = sig_kpc2_cn; cb.dp = out->dp_gas; cb.de = out->de_gas;
+        Phase ph(c, DMB_PH_COMBINE_GAS);
+        hipLaunchKernelGGL(k_combine_gas, dim3(blocks_for(G.n_own, 256)), dim3(256), 0, c->stream, cb);
+    }
+    // DM pass, decision, resolve
+    if (c->dp.nitems > 0) {
+        ENSURE(c, c->part_p, size_t(c->dp.nitems) * kTile * 8);
+        ENSURE(c, c->part_pm, size_t(c->dp.nitems) * kTile * 4);
+        ENSURE(c, c->psum_own, size_t(D.n_own) * 8);
+        ENSURE(c, c->slist, size_t(D.n_own) * 4);
+        DmPassArgs a;
+        a.g = geom(c, D, G, c->dp, counters);
+        a.g.queue_ctr = c->qctr.as<uint32_t>() + kXcd;
+        a.vx = D.v0.as<const double>(); a.vy = D.v1.as<const double>(); a.vz = D.v2.as<const double>();
+        a.dtr = D.r1.p; a.dm_perm = D.perm;
+        a.Vx = G.v0.as<const double>(); a.Vy = G.v1.as<const double>(); a.Vz = G.v2.as<const double>();
+        a.vs = G.r0.p; a.K = G.r5.p; a.crit = G.r6.p; a.gas_perm = G.perm;
+        a.gtab = c->gtab.as<const float4>();
+        a.k0 = k0; a.k1 = k1; a.step = par->step; a.box = par->box_id;
+        a.part_p = c->part_p.as<double>(); a.part_pm = c->part_pm.as<float>();
+        int nb = int(std::min<int64_t>(nb_persist, ((c->dp.nitems + 7) / 8) * 8));
+        {
+            Phase ph(c, DMB_PH_PASS_DM);
+            hipLaunchKernelGGL((k_pass_dm<Real, N, kExact>), dim3(nb), dim3(64), 0, c->stream, a);
+        }
+        DmCombineArgs cb;
+        cb.n_own = D.n_own; cb.own = D.own.as<const uint32_t>(); cb.perm = D.perm;
+        cb.item_off = c->dp.ioff.as<const uint32_t>(); cb.part_p = c->part_p.as<const double>();
+        cb.part_pm = c->part_pm.as<const float>(); cb.k0 = k0; cb.k1 = k1; cb.step = par->step; cb.box = par->box_id;
+        cb.psum_own = c->psum_own.as<double>(); cb.psum = out->p_sum; cb.pmax = out->p_max;
+        cb.scount = scount; cb.slist = c->slist.as<uint32_t>(); cb.counters = counters;
+        {
+            Phase ph(c, DMB_PH_COMBINE_DM);
+            hipLaunchKernelGGL(k_combine_dm, dim3(blocks_for(D.n_own, 256)), dim3(256), 0, c->stream, cb);
+        }
+        ResolveArgs r;
+        r.g = a.g;
+        r.cand_off = c->dp.off.as<const uint32_t>();
+        r.vx = a.vx; r.vy = a.vy; r.vz = a.vz; r.dtr = a.dtr; r.dm_perm = a.dm_perm;
+        r.Vx = a.Vx; r.Vy = a.Vy; r.Vz = a.Vz; r.vs = a.vs; r.K = a.K; r.gas_perm = a.gas_perm;
+        r.gas_vel = gas->vel; r.gas_u = gas->u; r.gas_mu = gas->mu; r.m_chi = par->m_chi_g;
+        r.gtab = a.gtab; r.k0 = k0; r.k1 = k1; r.step = par->step; r.box = par->box_id;
+        r.n_gas_bits = bits_for(std::max<int64_t>(G.n, 2));
+        r.n_gas = uint32_t(G.n);
+        r.scount = scount; r.slist = c->slist.as<const uint32_t>();
+        r.dv = out->dv_dm; r.partner = out->partner; r.counters = counters;
+        Phase ph(c, DMB_PH_RESOLVE);
+        hipLaunchKernelGGL((k_resolve<Real, N, kExact>), dim3(std::max(8, c->num_cu * 4)), dim3(64), 0, c->stream, r);
+    }
+    HIPCHK(c, hipGetLastError());
+    return DMB_OK;
+}
+
+template <typename Real>
+dmb_status dispatch_n(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
+                      dmb_out* out, uint64_t* counters)
+{
+    switch (par->n_pow) {
+        case -4: return launch_step<Real, -4>(c, gas, dm, par, out, counters);
+        case -2: return launch_step<Real, -2>(c, gas, dm, par, out, counters);
+        case 0: return launch_step<Real, 0>(c, gas, dm, par, out, counters);
+        case 2: return launch_step<Real, 2>(c, gas, dm, par, out, counters);
+    }
+    return fail(c, DMB_EINVAL, "n_pow %d not supported", par->n_pow);
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+dmb_status dmb_create(dmb_ctx** out, int device, void* hip_stream)
+{
+    if (!out) return DMB_EINVAL;
+    *out = nullptr;
+    dmb_ctx* c = new (std::nothrow) dmb_ctx();
+    if (!c) return DMB_ENOMEM;
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return DMB_EHIP;
+    }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+        c->num_cu = ncu;
+    size_t tb = size_t(kTabND + 1) * (kTabNE + 1) * sizeof(float4);
+    if (ensure(c, c->gtab, tb) != DMB_OK || ensure(c, c->boxL, 4 * sizeof(double)) != DMB_OK) {
+        dmb_destroy(c);
+        return DMB_ENOMEM;
+    }
+    hipLaunchKernelGGL(k_gtab_build, dim3(blocks_for(int64_t(kTabND + 1) * (kTabNE + 1), 256)), dim3(256), 0,
+                       c->stream, c->gtab.as<float4>());
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+        dmb_destroy(c);
+        return DMB_EHIP;
+    }
+    *out = c;
+    return DMB_OK;
+}
+
+dmb_status dmb_destroy(dmb_ctx* c)
+{
+    if (!c) return DMB_EINVAL;
+    hipSetDevice(c->device);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    auto fr = [](DevBuf& b) { if (b.p) hipFree(b.p); b.p = nullptr; b.cap = 0; };
+    for (Species* S : {&c->gas, &c->dm}) {
+        DevBuf* all[] = {&S->keys, &S->keys2, &S->vals, &S->vals2, &S->sx, &S->sy, &S->sz, &S->sh, &S->flag,
+                         &S->flag_off, &S->own, &S->tbox, &S->th, &S->sbox, &S->shh, &S->obox, &S->oh, &S->cube,
+                         &S->v0, &S->v1, &S->v2, &S->r0, &S->r1, &S->r2, &S->r3, &S->r4, &S->r5, &S->r6};
+        for (DevBuf* b : all) fr(*b);
+    }
+    for (Pairs* P : {&c->gp, &c->dp}) {
+        DevBuf* all[] = {&P->cnt, &P->off, &P->cand, &P->icnt, &P->ioff, &P->it_tile, &P->it_cb, &P->it_ce};
+        for (DevBuf* b : all) fr(*b);
+    }
+    for (auto& b : c->scan_tmp) fr(b);
+    for (auto& p : c->pending) { c->ev_pool.push_back(p.a); c->ev_pool.push_back(p.b); }
+    for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+    DevBuf* rest[] = {&c->gtab, &c->sort_table, &c->bbox_part, &c->boxL, &c->part_gas, &c->part_p, &c->part_pm,
+                      &c->psum_own, &c->qctr, &c->slist, &c->counters_local};
+    for (DevBuf* b : rest) fr(*b);
+    delete c;
+    return DMB_OK;
+}
+
+dmb_status dmb_set_stream(dmb_ctx* c, void* hip_stream)
+{
+    if (!c) return DMB_EINVAL;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return DMB_OK;
+}
+
+const char* dmb_last_error(const dmb_ctx* c) { return c ? c->err : "null context"; }
+
+dmb_status dmb_profile_enable(dmb_ctx* c, int32_t on)
+{
+    if (!c) return DMB_EINVAL;
+    c->prof = on != 0;
+    return DMB_OK;
+}
+
+dmb_status dmb_profile_read(dmb_ctx* c, double* ms, int64_t* calls, int32_t reset)
+{
+    if (!c) return DMB_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    for (auto& p : c->pending) {
+        HIPCHK(c, hipEventSynchronize(p.b));
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, p.a, p.b));
+        c->ph_ms[p.phase] += double(t);
+        c->ph_calls[p.phase] += 1;
+        c->ev_pool.push_back(p.a);
+        c->ev_pool.push_back(p.b);
+    }
+    c->pending.clear();
+    for (int k = 0; k < DMB_NPHASES; ++k) {
+        if (ms) ms[k] = c->ph_ms[k];
+        if (calls) calls[k] = c->ph_calls[k];
+        if (reset) { c->ph_ms[k] = 0.0; c->ph_calls[k] = 0; }
+    }
+    return DMB_OK;
+}
+
+dmb_status dmb_build_cells(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par)
+{
+    if (!c) return DMB_EINVAL;
+    if (!par) return fail(c, DMB_EINVAL, "null params");
+    dmb_status s;
+    if ((s = check_particles(c, gas, "gas", true)) != DMB_OK) return s;
+    if ((s = check_particles(c, dm, "dm", false)) != DMB_OK) return s;
+    bool periodic = par->box[0] > 0.0 || par->box[1] > 0.0 || par->box[2] > 0.0;
+    if (periodic && !(par->box[0] > 0.0 && par->box[1] > 0.0 && par->box[2] > 0.0))
+        return fail(c, DMB_EINVAL, "periodic box needs three positive sides");
+    HIPCHK(c, hipSetDevice(c->device));
+    Phase ph(c, DMB_PH_BUILD);
+    for (int k = 0; k < 3; ++k) c->built_L[k] = periodic ? par->box[k] : 0.0;
+    double Lh[4] = {c->built_L[0], c->built_L[1], c->built_L[2], 0.0};
+    HIPCHK(c, hipMemcpyAsync(c->boxL.p, Lh, sizeof(Lh), hipMemcpyHostToDevice, c->stream));
+    if ((s = build_species(c, c->gas, gas)) != DMB_OK) return s;
+    if ((s = build_species(c, c->dm, dm)) != DMB_OK) return s;
+    // read back owner counts and the largest h (for the periodic range check)
+    uint32_t nown[2] = {0, 0};
+    if (c->gas.n > 0)
+        HIPCHK(c, hipMemcpyAsync(&nown[0], c->gas.flag_off.as<uint32_t>() + c->gas.n, 4, hipMemcpyDeviceToHost, c->stream));
+    if (c->dm.n > 0)
+        HIPCHK(c, hipMemcpyAsync(&nown[1], c->dm.flag_off.as<uint32_t>() + c->dm.n, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->gas.n_own = nown[0];
+    c->dm.n_own = nown[1];
+    if ((s = build_owner_tiles(c, c->gas)) != DMB_OK) return s;
+    if ((s = build_owner_tiles(c, c->dm)) != DMB_OK) return s;
+    if ((s = cand_count(c, c->gas, c->dm, c->gp)) != DMB_OK) return s;
+    if ((s = cand_count(c, c->dm, c->gas, c->dp)) != DMB_OK) return s;
+    uint32_t tot[4] = {0, 0, 0, 0};
+    double hmax[2] = {0, 0};
+    if (c->gas.nown_tile > 0) {
+        HIPCHK(c, hipMemcpyAsync(&tot[0], c->gp.off.as<uint32_t>() + c->gas.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(&tot[1], c->gp.ioff.as<uint32_t>() + c->gas.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
+    }
+    if (c->dm.nown_tile > 0) {
+        HIPCHK(c, hipMemcpyAsync(&tot[2], c->dp.off.as<uint32_t>() + c->dm.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(&tot[3], c->dp.ioff.as<uint32_t>() + c->dm.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
+    }
+    if (periodic) {
+        // largest h of each species from the super-tile maxima
+        for (int sp = 0; sp < 2; ++sp) {
+            Species& S = sp == 0 ? c->gas : c->dm;
+            if (S.nsuper == 0) continue;
+            double* tmp = new double[S.nsuper];
+            HIPCHK(c, hipMemcpyAsync(tmp, S.shh.p, S.nsuper * 8, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            for (int64_t k = 0; k < S.nsuper; ++k) hmax[sp] = std::max(hmax[sp], tmp[k]);
+            delete[] tmp;
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (periodic) {
+        double Lmin = std::min(par->box[0], std::min(par->box[1], par->box[2]));
+        if (hmax[0] + hmax[1] >= 0.5 * Lmin) {
+            c->built_ngas = c->built_ndm = -1;
+            return fail(c, DMB_ERANGE, "max h_gas + max h_dm = %g >= L/2 = %g", hmax[0] + hmax[1], 0.5 * Lmin);
+        }
+    }
+    c->gp.total = tot[0]; c->gp.nitems = tot[1];
+    c->dp.total = tot[2]; c->dp.nitems = tot[3];
+    if ((s = cand_write(c, c->gas, c->dm, c->gp)) != DMB_OK) return s;
+    if ((s = cand_write(c, c->dm, c->gas, c->dp)) != DMB_OK) return s;
+    c->built_ngas = gas->n;
+    c->built_ndm = dm->n;
+    c->built_gas_pos = gas->pos;
+    c->built_dm_pos = dm->pos;
+    return DMB_OK;
+}
+
+dmb_status dmb_interact_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
+                             dmb_out* out)
+{
+    if (!c) return DMB_EINVAL;
+    if (!par || !out) return fail(c, DMB_EINVAL, "null params or out");
+    dmb_status s;
+    if ((s = check_particles(c, gas, "gas", true)) != DMB_OK) return s;
+    if ((s = check_particles(c, dm, "dm", false)) != DMB_OK) return s;
+    if (gas->n != c->built_ngas || dm->n != c->built_ndm)
+        return fail(c, DMB_ESTALE, "interact_step: sizes differ from the last build_cells");
+    if (gas->n > 0 && (!gas->vel || !gas->mass || !gas->u))
+        return fail(c, DMB_EINVAL, "gas: null vel, mass or u");
+    if (dm->n > 0 && (!dm->vel || !dm->mass)) return fail(c, DMB_EINVAL, "dm: null vel or mass");
+    if ((gas->n > 0 && (!out->dp_gas || !out->de_gas)) || (dm->n > 0 && (!out->dv_dm || !out->partner)))
+        return fail(c, DMB_EINVAL, "null output array");
+    if (!n_supported(par->n_pow)) return fail(c, DMB_EINVAL, "n_pow %d not supported", par->n_pow);
+    if (par->rates != DMB_RATES_EXACT) return fail(c, DMB_EINVAL, "rates mode %d not supported", par->rates);
+    if (!(par->m_chi_g > 0.0) || !(par->sigma0_cm2 >= 0.0)) return fail(c, DMB_EINVAL, "bad m_chi or sigma0");
+    HIPCHK(c, hipSetDevice(c->device));
+    uint64_t* counters = out->counters;
+    if (!counters) {
+        ENSURE(c, c->counters_local, DMB_NCOUNTERS * 8);
+        counters = c->counters_local.as<uint64_t>();
+    }
+    if (par->precision == DMB_FP64) return dispatch_n<double>(c, gas, dm, par, out, counters);
+    if (par->precision == DMB_FP32) return dispatch_n<float>(c, gas, dm, par, out, counters);
+    return fail(c, DMB_EINVAL, "precision %d not supported", par->precision);
+}
+
+dmb_status dmb_overlap_eval(dmb_ctx* c, int64_t n, const double* d, const double* h1, const double* h2,
+                            int32_t precision, double* g_out)
+{
+    if (!c) return DMB_EINVAL;
+    if (n < 0 || (n > 0 && (!d || !h1 || !h2 || !g_out))) return fail(c, DMB_EINVAL, "overlap_eval: bad args");
+    if (n == 0) return DMB_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    if (precision == DMB_FP64)
+        hipLaunchKernelGGL(k_overlap_eval<double>, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, n, d, h1, h2,
+                           c->gtab.as<const float4>(), true, g_out);
+    else
+        hipLaunchKernelGGL(k_overlap_eval<float>, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, n, d, h1, h2,
+                           c->gtab.as<const float4>(), false, g_out);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DMB_OK;
+}
+
+dmb_status dmb_rates_eval(dmb_ctx* c, int64_t n, const double* w, const double* vs, int32_t n_pow, int32_t precision,
+                          double* A_out, double* B_out)
+{
+    if (!c) return DMB_EINVAL;
+    if (n < 0 || (n > 0 && (!w || !vs || !A_out || !B_out))) return fail(c, DMB_EINVAL, "rates_eval: bad args");
+    if (!n_supported(n_pow)) return fail(c, DMB_EINVAL, "n_pow %d not supported", n_pow);
+    if (n == 0) return DMB_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    double al = alpha_n(n_pow);
+    dim3 gr(blocks_for(n, 256)), bl(256);
+#define RATES_CASE(NN)                                                                                              \
+    case NN:                                                                                                        \
+        if (precision == DMB_FP64)                                                                                  \
+            hipLaunchKernelGGL((k_rates_eval<double, NN>), gr, bl, 0, c->stream, n, w, vs, al, A_out, B_out);       \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_rates_eval<float, NN>), gr, bl, 0, c->stream, n, w, vs, al, A_out, B_out);        \
+        break;
+    switch (n_pow) { RATES_CASE(-4) RATES_CASE(-2) RATES_CASE(0) RATES_CASE(2) }
+#undef RATES_CASE
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DMB_OK;
+}
+
+dmb_status dmb_philox_eval(dmb_ctx* c, int64_t n, const uint32_t* ctr, uint64_t seed, uint32_t* out)
+{
+    if (!c) return DMB_EINVAL;
+    if (n < 0 || (n > 0 && (!ctr || !out))) return fail(c, DMB_EINVAL, "philox_eval: bad args");
+    if (n == 0) return DMB_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_philox_eval, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, n, ctr, uint32_t(seed),
+                       uint32_t(seed >> 32), out);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DMB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,297 @@
+// dmb_device.h -- device-side math of the DM-gas pair step for gfx950.
+//
+// Paper: Hainje & Farrar, arXiv 2603.24688.  Each function names the passage
+// it implements.  Templates over float/double are one code path: the pair
+// math runs in `Real`, positions and sums in double.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dmb {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrtPi = 1.7724538509055160273;
+
+// ---------------------------------------------------------------------------
+// Cubic-spline kernel (Sec. 2.4): w(q) = 8/pi {1-6q^2+6q^3; 2(1-q)^3; 0}.
+template <typename T>
+__device__ __forceinline__ T kernel_w(T q)
+{
+    const T c = T(8.0 / kPi);
+    if (q <= T(0.5)) return c * (T(1) + q * q * (T(6) * q - T(6)));
+    if (q < T(1)) { T p = T(1) - q; return c * T(2) * p * p * p; }
+    return T(0);
+}
+
+// psi(Q) = int_0^Q q w(q) dq differences on one polynomial branch, factored so
+// that a small b - a keeps relative accuracy (Appendix D inner integral).
+__device__ __forceinline__ double psi_piece(int br, double a, double b, double bma)
+{
+    const double c = 8.0 / kPi;
+    if (br == 0) {
+        double a2 = a * a, b2 = b * b;
+        double s1 = a + b;
+        double s3 = (a2 + b2) * s1;
+        double s4 = b2 * b2 + b2 * b * a + b2 * a2 + b * a2 * a + a2 * a2;
+        return c * bma * (0.5 * s1 - 1.5 * s3 + 1.2 * s4);
+    }
+    if (br == 1) {
+        double pa = 1.0 - a, pb = 1.0 - b;
+        double pa2 = pa * pa, pb2 = pb * pb;
+        double t3 = (pa2 + pb2) * (pa + pb);
+        double t4 = pa2 * pa2 + pa2 * pa * pb + pa2 * pb2 + pa * pb2 * pb + pb2 * pb2;
+        return c * bma * (0.5 * t3 - 0.4 * t4);
+    }
+    return 0.0;
+}
+
+__device__ __forceinline__ int psi_branch(double q) { return q <= 0.5 ? 0 : (q <= 1.0 ? 1 : 2); }
+
+__device__ __forceinline__ double psi_range(double a, double b, double bma)
+{
+    int ba = psi_branch(a), bb = psi_branch(b);
+    if (ba == bb) return psi_piece(ba, a, b, bma);
+    double acc = 0.0, lo = a;
+    for (int br = ba; br < bb; ++br) {
+        double edge = br == 0 ? 0.5 : 1.0;
+        acc += psi_piece(br, lo, edge, edge - lo);
+        lo = edge;
+    }
+    return acc + psi_piece(bb, lo, b, b - lo);
+}
+
+// Overlap H(delta, eta) = h_b^3 g for the cubic spline (Appendix D):
+//   H = (2 pi / eta^3) int_0^1 ds s^2 w(s) F(s),
+//   F(s) = eta^2/(delta s) [psi((s+delta)/eta) - psi(|s-delta|/eta)],
+// exact up to rounding with 6-point Gauss-Legendre on each polynomial piece.
+__device__ double overlap_H_exact(double delta, double eta)
+{
+    if (delta >= 1.0 + eta) return 0.0;
+    const double gx[3] = {0.2386191860831969086, 0.6612093864662645137, 0.9324695142031520278};
+    const double gw[3] = {0.4679139345726910473, 0.3607615730481386076, 0.1713244923791703450};
+    double bp[10];
+    int nb = 0;
+    bp[nb++] = 0.0;
+    bp[nb++] = 1.0;
+    const double cand[8] = {0.5, delta, delta - 0.5 * eta, delta + 0.5 * eta, delta - eta, delta + eta,
+                            0.5 * eta - delta, eta - delta};
+    for (int k = 0; k < 8; ++k)
+        if (cand[k] > 0.0 && cand[k] < 1.0) bp[nb++] = cand[k];
+    for (int i = 1; i < nb; ++i) {  // insertion sort, nb <= 10
+        double v = bp[i];
+        int j = i - 1;
+        while (j >= 0 && bp[j] > v) { bp[j + 1] = bp[j]; --j; }
+        bp[j + 1] = v;
+    }
+    double acc = 0.0;
+    for (int k = 0; k + 1 < nb; ++k) {
+        double lo = bp[k], hi = bp[k + 1];
+        if (!(hi > lo)) continue;
+        double half = 0.5 * (hi - lo), mid = 0.5 * (hi + lo), piece = 0.0;
+        for (int q = 0; q < 6; ++q) {
+            double s = mid + half * (q < 3 ? -gx[2 - q] : gx[q - 3]);
+            double wq = q < 3 ? gw[2 - q] : gw[q - 3];
+            double ws = kernel_w(s);
+            double F;
+            if (delta == 0.0) {
+                F = 2.0 * kernel_w(s / eta);
+            } else {
+                double a = fabs(s - delta) / eta, b = (s + delta) / eta;
+                double bma = 2.0 * fmin(s, delta) / eta;
+                F = eta * eta / (delta * s) * psi_range(a, b, bma);
+            }
+            piece += wq * s * s * ws * F;
+        }
+        acc += half * piece;
+    }
+    return 2.0 * kPi * acc / (eta * eta * eta);
+}
+
+// ---------------------------------------------------------------------------
+// Overlap table for the FP32 path (Appendix D tabulates the overlap over the
+// distance ratio and the softening ratio).  Nodes delta_i = i*2/ND (i <= ND),
+// eta_j = j/NE (j <= NE); each node holds float4(H, dH/ddelta * ddelta,
+// dH/deta * deta, 0); lookup is cubic Hermite in both directions with the
+// eta-derivative interpolated linearly along delta.
+constexpr int kTabND = 512;
+constexpr int kTabNE = 128;
+
+
+template <typename T>
+__device__ __forceinline__ T overlap_g_table(const float4* __restrict__ tab, T d, T hi, T hj)
+{
+    // Nodes are stored in binary32; the interpolation runs in binary64 (same
+    // FMA rate as binary32 on gfx950 vector ALUs) so that the result carries
+    // only the node rounding (~1e-7 of the peak), not float arithmetic error.
+    double hb = double(hi > hj ? hi : hj), hs = double(hi > hj ? hj : hi);
+    double ib = 1.0 / hb;
+    double fd = double(d) * ib * (kTabND * 0.5), fe = hs * ib * double(kTabNE);
+    int i = min(int(fd), kTabND - 1), j = min(int(fe), kTabNE - 1);
+    double a = fd - double(i), b = fe - double(j);
+    float4 c00 = tab[j * (kTabND + 1) + i], c10 = tab[j * (kTabND + 1) + i + 1];
+    float4 c01 = tab[(j + 1) * (kTabND + 1) + i], c11 = tab[(j + 1) * (kTabND + 1) + i + 1];
+    double a2 = a * a, a3 = a2 * a;
+    double h0 = 2.0 * a3 - 3.0 * a2 + 1.0, h1 = a3 - 2.0 * a2 + a, h2 = 3.0 * a2 - 2.0 * a3, h3 = a3 - a2;
+    double r0 = h0 * double(c00.x) + h1 * double(c00.y) + h2 * double(c10.x) + h3 * double(c10.y);
+    double r1 = h0 * double(c01.x) + h1 * double(c01.y) + h2 * double(c11.x) + h3 * double(c11.y);
+    double e0 = double(c00.z) + a * double(c10.z - c00.z), e1 = double(c01.z) + a * double(c11.z - c01.z);
+    double b2 = b * b, b3 = b2 * b;
+    double H = (2.0 * b3 - 3.0 * b2 + 1.0) * r0 + (b3 - 2.0 * b2 + b) * e0 + (3.0 * b2 - 2.0 * b3) * r1 +
+               (b3 - b2) * e1;
+    H = fmax(H, 0.0);
+    return T(H * ib * ib * ib);
+}
+
+template <typename T>
+__device__ __forceinline__ T overlap_g_exact(T d, T hi, T hj)
+{
+    double hb = double(hi > hj ? hi : hj), hs = double(hi > hj ? hj : hi);
+    return T(overlap_H_exact(double(d) / hb, hs / hb) / (hb * hb * hb));
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): per round the products M0*x0 and
+// M1*x2 give (hi1^x1^k0, lo1, hi0^x3^k1, lo0); key bumped by the Weyl
+// constants between rounds.
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        U4 n;
+        n.x = hi1 ^ c.y ^ k0;
+        n.y = lo1;
+        n.z = hi0 ^ c.w ^ k1;
+        n.w = lo0;
+        c = n;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// 24-bit centred uniform ((r >> 8) + 1/2) 2^-24, exactly representable.
+template <typename T>
+__device__ __forceinline__ T u24(uint32_t r) { return (T(r >> 8) + T(0.5)) * T(1.0 / 16777216.0); }
+
+// Stream layout shared with every consumer of the random numbers:
+// counter = (dm index, gas index, step, tag | box << 8), key = seed.
+enum : uint32_t { kTagGasVel = 0u, kTagDir = 1u, kTagDecision = 2u };
+
+__device__ __forceinline__ U4 philox_block(uint32_t i, uint32_t j, uint32_t step, uint32_t tag, uint32_t box,
+                                           uint32_t k0, uint32_t k1)
+{
+    U4 c{i, j, step, tag | (box << 8)};
+    return philox4x32_10(c, k0, k1);
+}
+
+// cos(2 pi u), sin(2 pi u): the gfx950 transcendental unit takes turns.
+__device__ __forceinline__ void sincos_turns(float u, float* s, float* c)
+{
+    *s = __builtin_amdgcn_sinf(u);
+    *c = __builtin_amdgcn_cosf(u);
+}
+__device__ __forceinline__ void sincos_turns(double u, double* s, double* c) { sincospi(2.0 * u, s, c); }
+
+__device__ __forceinline__ float log_real(float x) { return __logf(x); }
+__device__ __forceinline__ double log_real(double x) { return log(x); }
+__device__ __forceinline__ float sqrt_real(float x) { return __fsqrt_rn(x); }
+__device__ __forceinline__ double sqrt_real(double x) { return sqrt(x); }
+
+// Three standard normals by Box-Muller from one Philox block.
+template <typename T>
+__device__ __forceinline__ void normals3(U4 r, T z[3])
+{
+    T u0 = u24<T>(r.x), u1 = u24<T>(r.y), u2 = u24<T>(r.z), u3 = u24<T>(r.w);
+    T r0 = sqrt_real(T(-2) * log_real(u0)), r1 = sqrt_real(T(-2) * log_real(u2));
+    T s, c, s2, c2;
+    sincos_turns(u1, &s, &c);
+    sincos_turns(u3, &s2, &c2);
+    z[0] = r0 * c;
+    z[1] = r0 * s;
+    z[2] = r1 * c2;
+}
+
+// ---------------------------------------------------------------------------
+// Rate functions (Appendix B): for sigma-bar = sigma0 (v/c)^n,
+//   A = alpha_n/3 vs^{n+1} 1F1(-(n+1)/2, 5/2, -x),
+//   B = alpha_n   vs^{n+3} 1F1(-(n+3)/2, 3/2, -x),  x = w^2/(2 vs^2).
+// Here FA, FB are the two 1F1 values.  Large x: erf/exp closed forms of the
+// 1F1 for integer n; x < 1: their Taylor series (the closed forms cancel).
+template <int N>
+struct RateCoef {
+    static constexpr int kTerms = 24;
+    double ca[kTerms], cb[kTerms];
+    constexpr RateCoef() : ca(), cb()
+    {
+        double a1 = -(N + 1) * 0.5, b1 = 2.5, a2 = -(N + 3) * 0.5, b2 = 1.5;
+        double t1 = 1.0, t2 = 1.0;
+        for (int k = 0; k < kTerms; ++k) {
+            ca[k] = t1;
+            cb[k] = t2;
+            t1 *= -(a1 + k) / ((b1 + k) * (k + 1));
+            t2 *= -(a2 + k) / ((b2 + k) * (k + 1));
+        }
+    }
+};
+
+template <typename T> struct RealTraits;
+template <> struct RealTraits<float> { static constexpr int kTaylor = 12; };
+template <> struct RealTraits<double> { static constexpr int kTaylor = 22; };
+
+__device__ __forceinline__ float erf_real(float x) { return erff(x); }
+__device__ __forceinline__ double erf_real(double x) { return erf(x); }
+__device__ __forceinline__ float exp_neg(float x) { return __expf(-x); }
+__device__ __forceinline__ double exp_neg(double x) { return exp(-x); }
+
+template <int N, typename T>
+__device__ __forceinline__ void rate_1f1(T x, T* FA, T* FB)
+{
+    constexpr RateCoef<N> C{};
+    if (x < T(1)) {
+        constexpr int K = RealTraits<T>::kTaylor;
+        T fa = T(C.ca[K - 1]), fb = T(C.cb[K - 1]);
+#pragma unroll
+        for (int k = K - 2; k >= 0; --k) {
+            fa = fa * x + T(C.ca[k]);
+            fb = fb * x + T(C.cb[k]);
+        }
+        *FA = fa;
+        *FB = fb;
+        return;
+    }
+    T t = sqrt_real(x), r = T(1) / x, it = T(1) / t;
+    T E = erf_real(t), ex = exp_neg(x);
+    T spE = T(kSqrtPi) * E;
+    if constexpr (N == 0) {
+        *FA = T(3.0 / 32.0) * (spE * (T(4) * x + T(4) - r) * it + T(2) * (T(2) + r) * ex);
+        *FB = (spE * ((T(4) * x + T(12)) * x + T(3)) * it + T(2) * (T(2) * x + T(5)) * ex) * T(1.0 / 16.0);
+    } else if constexpr (N == -2) {
+        *FA = T(0.75) * ex * r + T(0.75) * spE * it - T(0.375) * spE * r * it;
+        *FB = T(0.5) * spE * t + T(0.5) * ex + T(0.25) * spE * it;
+    } else if constexpr (N == -4) {
+        *FA = T(-1.5) * ex * r + T(0.75) * spE * r * it;
+        *FB = T(0.5) * spE * it;
+    } else if constexpr (N == 2) {
+        *FA = (spE * (((T(8) * x + T(36)) * x + T(18)) * x - T(3)) * it + T(2) * ((T(4) * x + T(16)) * x + T(3)) * ex) *
+              (r * T(1.0 / 64.0));
+        *FB = (spE * (((T(8) * x + T(60)) * x + T(90)) * x + T(15)) * it + T(2) * ((T(4) * x + T(28)) * x + T(33)) * ex) *
+              T(1.0 / 96.0);
+    }
+}
+
+// v^{n+1} for the scattering probability P = K g v^{n+1} dt.
+template <int N, typename T>
+__device__ __forceinline__ T pow_np1(T v)
+{
+    if constexpr (N == 0) return v;
+    else if constexpr (N == -2) return T(1) / v;
+    else if constexpr (N == -4) { T iv = T(1) / v; return iv * iv * iv; }
+    else if constexpr (N == 2) return v * v * v;
+    else return T(0);
+}
+
+}  // namespace dmb

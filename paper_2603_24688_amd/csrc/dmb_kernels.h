@@ -1,0 +1,1111 @@
+// dmb_kernels.h -- gfx950 kernels of the DM-gas pair step: Morton cells,
+// tiles and candidate lists, the gas mean-field pass, the DM Monte Carlo pass
+// and the partner resolve.  See dmb.h for the operation each entry computes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dmb_device.h"
+
+namespace dmb {
+
+constexpr int kTile = 64;        // particles per tile (one wavefront)
+constexpr int kXcd = 8;          // XCDs per MI355X; blockIdx round-robins over them
+constexpr double kMsunG = 1.988409870698051e33;
+constexpr double kKpcCm = 3.0856775814913673e21;
+constexpr double kCKms = 299792.458;
+constexpr double kMpG = 1.67262192369e-24;
+
+__device__ __forceinline__ int lane_id() { return int(threadIdx.x & 63); }
+
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(v, d);
+        if (lane_id() >= d) v += y;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Bounding cube for Morton keys.
+__global__ __launch_bounds__(256) void k_bbox_partial(const double* __restrict__ pos, int64_t n,
+                                                      double* __restrict__ part)
+{
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        for (int a = 0; a < 3; ++a) {
+            double v = pos[3 * i + a];
+            lo[a] = fmin(lo[a], v);
+            hi[a] = fmax(hi[a], v);
+        }
+    __shared__ double s[6][4];
+    for (int a = 0; a < 3; ++a) {
+        for (int d = 32; d >= 1; d >>= 1) {
+            lo[a] = fmin(lo[a], __shfl_xor(lo[a], d));
+            hi[a] = fmax(hi[a], __shfl_xor(hi[a], d));
+        }
+    }
+    int w = threadIdx.x >> 6;
+    if (lane_id() == 0)
+        for (int a = 0; a < 3; ++a) { s[a][w] = lo[a]; s[3 + a][w] = hi[a]; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) {
+            double l = s[a][0], h = s[3 + a][0];
+            for (int k = 1; k < 4; ++k) { l = fmin(l, s[a][k]); h = fmax(h, s[3 + a][k]); }
+            part[6 * blockIdx.x + a] = l;
+            part[6 * blockIdx.x + 3 + a] = h;
+        }
+    }
+}
+
+// cube[0..2] = origin, cube[3] = 2^21 / side (quantisation scale).
+__global__ void k_bbox_final(const double* __restrict__ part, int nparts, const double* __restrict__ boxL,
+                             double* __restrict__ cube)
+{
+    if (threadIdx.x != 0) return;
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) { lo[a] = 1e300; hi[a] = -1e300; }
+    for (int k = 0; k < nparts; ++k)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], part[6 * k + a]);
+            hi[a] = fmax(hi[a], part[6 * k + 3 + a]);
+        }
+    bool periodic = boxL[0] > 0.0;
+    double side = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        if (periodic) { lo[a] = 0.0; hi[a] = boxL[a]; }
+        side = fmax(side, hi[a] - lo[a]);
+    }
+    side = side > 0.0 ? side * (1.0 + 1e-9) + 1e-300 : 1.0;
+    for (int a = 0; a < 3; ++a) cube[a] = lo[a];
+    cube[3] = 2097152.0 / side;
+}
+
+__device__ __forceinline__ uint64_t spread21(uint64_t x)
+{
+    x &= 0x1fffffull;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__global__ __launch_bounds__(256) void k_morton(const double* __restrict__ pos, int64_t n,
+                                                const double* __restrict__ cube, const double* __restrict__ boxL,
+                                                uint64_t* __restrict__ keys, uint32_t* __restrict__ vals)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t q[3];
+    for (int a = 0; a < 3; ++a) {
+        double x = pos[3 * i + a];
+        if (boxL[a] > 0.0) x -= boxL[a] * floor(x / boxL[a]);
+        double f = (x - cube[a]) * cube[3];
+        f = fmin(fmax(f, 0.0), 2097151.0);
+        q[a] = uint64_t(f);
+    }
+    keys[i] = spread21(q[0]) | (spread21(q[1]) << 1) | (spread21(q[2]) << 2);
+    vals[i] = uint32_t(i);
+}
+
+// Sorted SoA copies of position and h (positions wrapped into [0, L) when
+// periodic so that tile boxes are compact).
+__global__ __launch_bounds__(256) void k_gather_pos(const uint32_t* __restrict__ perm, int64_t n,
+                                                    const double* __restrict__ pos, const double* __restrict__ h,
+                                                    const double* __restrict__ boxL, double* __restrict__ sx,
+                                                    double* __restrict__ sy, double* __restrict__ sz,
+                                                    double* __restrict__ sh)
+{
+    int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t o = perm[k];
+    double p[3];
+    for (int a = 0; a < 3; ++a) {
+        double x = pos[3 * int64_t(o) + a];
+        if (boxL[a] > 0.0) x -= boxL[a] * floor(x / boxL[a]);
+        p[a] = x;
+    }
+    sx[k] = p[0];
+    sy[k] = p[1];
+    sz[k] = p[2];
+    sh[k] = h[o];
+}
+
+__global__ __launch_bounds__(256) void k_active_flags(const uint32_t* __restrict__ perm, int64_t n,
+                                                      const uint8_t* __restrict__ active, uint32_t* __restrict__ flag)
+{
+    int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k > n) return;
+    flag[k] = (k < n) ? (active ? (active[perm[k]] != 0 ? 1u : 0u) : 1u) : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ off,
+                                                 int64_t n, uint32_t* __restrict__ own)
+{
+    int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k < n && flag[k]) own[off[k]] = uint32_t(k);
+}
+
+// Tile bounds: one wave per tile of 64 consecutive entries of `list`
+// (identity when list == nullptr).  box = {lo xyz, hi xyz}, hmax.
+__global__ __launch_bounds__(64) void k_tile_bounds(const uint32_t* __restrict__ list, int64_t n,
+                                                    const double* __restrict__ sx, const double* __restrict__ sy,
+                                                    const double* __restrict__ sz, const double* __restrict__ sh,
+                                                    double* __restrict__ box, double* __restrict__ hmax)
+{
+    int64_t t = blockIdx.x;
+    int64_t k = t * kTile + lane_id();
+    bool v = k < n;
+    int64_t p = v ? (list ? int64_t(list[k]) : k) : 0;
+    double x = v ? sx[p] : 1e300, y = v ? sy[p] : 1e300, z = v ? sz[p] : 1e300;
+    double X = v ? sx[p] : -1e300, Y = v ? sy[p] : -1e300, Z = v ? sz[p] : -1e300;
+    double hh = v ? sh[p] : 0.0;
+    for (int d = 32; d >= 1; d >>= 1) {
+        x = fmin(x, __shfl_xor(x, d)); y = fmin(y, __shfl_xor(y, d)); z = fmin(z, __shfl_xor(z, d));
+        X = fmax(X, __shfl_xor(X, d)); Y = fmax(Y, __shfl_xor(Y, d)); Z = fmax(Z, __shfl_xor(Z, d));
+        hh = fmax(hh, __shfl_xor(hh, d));
+    }
+    if (lane_id() == 0) {
+        box[6 * t + 0] = x; box[6 * t + 1] = y; box[6 * t + 2] = z;
+        box[6 * t + 3] = X; box[6 * t + 4] = Y; box[6 * t + 5] = Z;
+        hmax[t] = hh;
+    }
+}
+
+// Super-tile bounds over 64 consecutive tiles.
+__global__ __launch_bounds__(64) void k_super_bounds(int64_t ntile, const double* __restrict__ tbox,
+                                                     const double* __restrict__ th, double* __restrict__ box,
+                                                     double* __restrict__ hmax)
+{
+    int64_t s = blockIdx.x;
+    int64_t t = s * kTile + lane_id();
+    bool v = t < ntile;
+    double b[6];
+    for (int a = 0; a < 3; ++a) {
+        b[a] = v ? tbox[6 * t + a] : 1e300;
+        b[3 + a] = v ? tbox[6 * t + 3 + a] : -1e300;
+    }
+    double hh = v ? th[t] : 0.0;
+    for (int d = 32; d >= 1; d >>= 1) {
+        for (int a = 0; a < 3; ++a) {
+            b[a] = fmin(b[a], __shfl_xor(b[a], d));
+            b[3 + a] = fmax(b[3 + a], __shfl_xor(b[3 + a], d));
+        }
+        hh = fmax(hh, __shfl_xor(hh, d));
+    }
+    if (lane_id() == 0) {
+        for (int a = 0; a < 6; ++a) box[6 * s + a] = b[a];
+        hmax[s] = hh;
+    }
+}
+
+// Squared gap between two boxes (minimum over periodic images).
+__device__ __forceinline__ double box_gap2(const double* A, const double* B, const double* L)
+{
+    double g2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double gap = fmax(0.0, fmax(B[a] - A[3 + a], A[a] - B[3 + a]));
+        if (L[a] > 0.0) {
+            double gp = fmax(0.0, fmax(B[a] + L[a] - A[3 + a], A[a] - B[3 + a] - L[a]));
+            double gm = fmax(0.0, fmax(B[a] - L[a] - A[3 + a], A[a] - B[3 + a] + L[a]));
+            gap = fmin(gap, fmin(gp, gm));
+        }
+        g2 += gap * gap;
+    }
+    return g2;
+}
+
+__device__ __forceinline__ bool boxes_near(const double* A, double ha, const double* B, double hb, const double* L)
+{
+    double reach = (ha + hb) * (1.0 + 1e-12);
+    return box_gap2(A, B, L) < reach * reach;
+}
+
+// Candidate other-tiles of each owner tile (two-level culling through the
+// super-tiles).  count mode: cnt[t] = number of candidates; write mode:
+// cand[off[t] + k] in super-tile then tile order.
+struct CandArgs {
+    int64_t nown_tile, ntile, nsuper;
+    const double* obox; const double* oh;
+    const double* tbox; const double* th;
+    const double* sbox; const double* shh;
+    double L[3];
+    uint32_t* cnt;
+    const uint32_t* off;
+    uint32_t* cand;
+};
+
+template <bool WRITE>
+__global__ __launch_bounds__(64) void k_cand(CandArgs a)
+{
+    int64_t t = blockIdx.x;
+    int lane = lane_id();
+    double A[6];
+    for (int k = 0; k < 6; ++k) A[k] = a.obox[6 * t + k];
+    double ha = a.oh[t];
+    uint32_t count = 0;
+    uint32_t base = WRITE ? a.off[t] : 0u;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t s0 = 0; s0 < a.nsuper; s0 += 64) {
+        int64_t s = s0 + lane;
+        bool hit = false;
+        if (s < a.nsuper) hit = boxes_near(A, ha, a.sbox + 6 * s, a.shh[s], a.L);
+        uint64_t bal = __ballot(hit);
+        while (bal) {
+            int b = __ffsll((unsigned long long)bal) - 1;
+            bal &= bal - 1;
+            int64_t tt = (s0 + b) * kTile + lane;
+            bool h2 = false;
+            if (tt < a.ntile) h2 = boxes_near(A, ha, a.tbox + 6 * tt, a.th[tt], a.L);
+            uint64_t b2 = __ballot(h2);
+            if (WRITE && h2) a.cand[base + count + uint32_t(__popcll(b2 & lt))] = uint32_t(tt);
+            count += uint32_t(__popcll(b2));
+        }
+    }
+    if (!WRITE && lane == 0) a.cnt[t] = count;
+}
+
+// Work items: candidate lists split into pieces of at most `split` tiles.
+__global__ __launch_bounds__(256) void k_item_count(const uint32_t* __restrict__ cnt, int64_t nt, uint32_t split,
+                                                    uint32_t* __restrict__ icnt)
+{
+    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t > nt) return;
+    icnt[t] = t < nt ? (cnt[t] + split - 1) / split : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_item_write(const uint32_t* __restrict__ cand_off,
+                                                    const uint32_t* __restrict__ item_off, int64_t nt, uint32_t split,
+                                                    uint32_t* __restrict__ it_tile, uint32_t* __restrict__ it_cb,
+                                                    uint32_t* __restrict__ it_ce)
+{
+    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    uint32_t cb = cand_off[t], ce = cand_off[t + 1];
+    uint32_t it = item_off[t];
+    for (uint32_t c = cb; c < ce; c += split, ++it) {
+        it_tile[it] = uint32_t(t);
+        it_cb[it] = c;
+        it_ce[it] = min(ce, c + split);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-step gathers into sorted order.
+struct GasGatherArgs {
+    int64_t n;
+    const uint32_t* perm;
+    const double* vel; const double* mass; const double* u; const double* mu;
+    double m_chi, sig_kpc2_cn, alpha_n;
+    int n_pow;
+    double* Vx; double* Vy; double* Vz;
+    void* vs; void* inv2s2; void* ra; void* rb; void* rr; void* K; void* crit;
+};
+
+template <typename Real>
+__device__ __forceinline__ void gas_derived(double u, double mu, double m_chi, double alpha_n, int n_pow,
+                                            Real* vs, Real* inv2s2, Real* ra, Real* rb, Real* rr, Real* crit)
+{
+    double s2 = 2.0 * u / 3.0;
+    double s = sqrt(s2);
+    *vs = Real(s);
+    *inv2s2 = Real(s2 > 0.0 ? 1.0 / (2.0 * s2) : INFINITY);
+    *ra = Real(alpha_n / 3.0 * pow(s, double(n_pow + 1)));
+    *rb = Real(alpha_n * pow(s, double(n_pow + 3)));
+    *rr = Real(mu / (m_chi + mu));
+    double q = (m_chi + mu) / mu;
+    *crit = Real(fmin(0.1, 1e-4 * q * q));
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_gather_gas(GasGatherArgs a)
+{
+    int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    uint32_t o = a.perm[k];
+    a.Vx[k] = a.vel[3 * int64_t(o)];
+    a.Vy[k] = a.vel[3 * int64_t(o) + 1];
+    a.Vz[k] = a.vel[3 * int64_t(o) + 2];
+    double mu = a.mu ? a.mu[o] : kMpG;
+    Real vs, i2, ra, rb, rr, cr;
+    gas_derived<Real>(a.u[o], mu, a.m_chi, a.alpha_n, a.n_pow, &vs, &i2, &ra, &rb, &rr, &cr);
+    reinterpret_cast<Real*>(a.vs)[k] = vs;
+    reinterpret_cast<Real*>(a.inv2s2)[k] = i2;
+    reinterpret_cast<Real*>(a.ra)[k] = ra;
+    reinterpret_cast<Real*>(a.rb)[k] = rb;
+    reinterpret_cast<Real*>(a.rr)[k] = rr;
+    reinterpret_cast<Real*>(a.crit)[k] = cr;
+    reinterpret_cast<Real*>(a.K)[k] = Real(a.mass[o] * kMsunG / mu * a.sig_kpc2_cn);
+}
+
+struct DmGatherArgs {
+    int64_t n;
+    const uint32_t* perm;
+    const double* vel; const double* mass; const double* dt;
+    double dt_default;
+    double* vx; double* vy; double* vz;
+    void* m; void* dtr;
+};
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_gather_dm(DmGatherArgs a)
+{
+    int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    uint32_t o = a.perm[k];
+    a.vx[k] = a.vel[3 * int64_t(o)];
+    a.vy[k] = a.vel[3 * int64_t(o) + 1];
+    a.vz[k] = a.vel[3 * int64_t(o) + 2];
+    reinterpret_cast<Real*>(a.m)[k] = Real(a.mass[o]);
+    reinterpret_cast<Real*>(a.dtr)[k] = Real(a.dt ? a.dt[o] : a.dt_default);
+}
+
+__global__ __launch_bounds__(256) void k_fill_out(int64_t n_gas, int64_t n_dm, double* dp, double* de, double* dv,
+                                                  int32_t* partner, double* psum, double* pmax, uint64_t* counters,
+                                                  uint32_t* queues, int nqueues)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n_gas) {
+        dp[3 * i] = 0.0; dp[3 * i + 1] = 0.0; dp[3 * i + 2] = 0.0;
+        de[i] = 0.0;
+    }
+    if (i < n_dm) {
+        dv[3 * i] = 0.0; dv[3 * i + 1] = 0.0; dv[3 * i + 2] = 0.0;
+        partner[i] = -1;
+        if (psum) psum[i] = 0.0;
+        if (pmax) pmax[i] = 0.0;
+    }
+    if (i < 8 && counters) counters[i] = 0ull;
+    if (i < nqueues) queues[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Pair passes.  One wavefront per block owns a tile of 64 owners (lane = owner)
+// and walks its candidate tiles.  For each candidate tile the owners test the
+// 64 others from LDS, push hits into an owner-major queue, and the wave then
+// evaluates the queue 64 pairs at a time (lane = pair).  Each owner's terms
+// form a contiguous segment of the queue; a segmented suffix sum over lanes
+// (wavefront shuffles) leaves the segment total on its first lane, which the
+// owner lane pulls.  No atomics touch physical quantities.
+struct PassGeom {
+    const uint32_t* own;          // owner slot -> sorted position (owner species)
+    int64_t n_own;
+    const double* ox; const double* oy; const double* oz; const double* oh;   // owner sorted pos/h
+    const double* obox;           // owner tile boxes
+    const double* tx; const double* ty; const double* tz; const double* th;   // other sorted pos/h
+    int64_t n_other;
+    const double* tbox;           // other tile boxes
+    const uint32_t* cand;         // candidate other tiles
+    const uint32_t* it_tile; const uint32_t* it_cb; const uint32_t* it_ce;
+    int64_t n_items;
+    uint32_t* queue_ctr;          // [kXcd] work counters
+    double L[3];
+    uint64_t* counters;
+};
+
+// Per tile pair: image shift of the other tile and whether every pair of
+// particles is then at its minimum image (else per-pair minimum image).
+__device__ __forceinline__ void tile_pair_shift(const double* A, const double* B, const double* L, double sh[3],
+                                                bool* clean)
+{
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+        sh[a] = 0.0;
+        if (L[a] > 0.0) {
+            double ca = 0.5 * (A[a] + A[3 + a]), cb = 0.5 * (B[a] + B[3 + a]);
+            sh[a] = L[a] * rint((ca - cb) / L[a]);
+            double lo = A[a] - (B[3 + a] + sh[a]), hi = A[3 + a] - (B[a] + sh[a]);
+            if (!(lo > -0.5 * L[a] && hi < 0.5 * L[a])) ok = false;
+        }
+    }
+    *clean = ok;
+}
+
+__device__ __forceinline__ double min_image(double d, double L) { return L > 0.0 ? d - L * rint(d / L) : d; }
+
+// d^2 of owner (x) and other (p, already shifted); explicit evaluation order
+// shared by every pass.
+__device__ __forceinline__ double pair_d2(double ax, double ay, double az, double bx, double by, double bz,
+                                          bool clean, const double* L)
+{
+    double dx = ax - bx, dy = ay - by, dz = az - bz;
+    if (!clean) { dx = min_image(dx, L[0]); dy = min_image(dy, L[1]); dz = min_image(dz, L[2]); }
+    return fma(dx, dx, fma(dy, dy, dz * dz));
+}
+
+__device__ __forceinline__ bool item_next(uint32_t* queue_ctr, int64_t n_items, int64_t* it)
+{
+    // XCD-aware: blocks of XCD x take items from the x-th contiguous range.
+    __shared__ int64_t s_it;
+    int x = blockIdx.x % kXcd;
+    int64_t lo = n_items * x / kXcd, hi = n_items * (x + 1) / kXcd;
+    if (threadIdx.x == 0) s_it = lo + int64_t(atomicAdd(&queue_ctr[x], 1u));
+    __syncthreads();
+    *it = s_it;
+    __syncthreads();
+    return *it < hi;
+}
+
+template <typename T>
+__device__ __forceinline__ T seg_sum(T v, int lane, int seg_end)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T t = __shfl_down(v, d);
+        if (lane + d <= seg_end) v += t;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T seg_max(T v, int lane, int seg_end)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T t = __shfl_down(v, d);
+        if (lane + d <= seg_end) v = v > t ? v : t;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Gas (mean-field) pass: owners = active gas, others = DM.
+struct GasPassArgs {
+    PassGeom g;
+    const double* Vx; const double* Vy; const double* Vz;     // gas, sorted
+    const void* inv2s2; const void* ra; const void* rb; const void* rr;
+    const double* dvx; const double* dvy; const double* dvz;  // DM velocities, sorted
+    const void* dm_m;
+    const float4* gtab;
+    double* part;                 // [n_items][64][4]
+};
+
+template <typename Real, int N, bool EXACT_G>
+__global__ __launch_bounds__(64) void k_pass_gas(GasPassArgs a)
+{
+    __shared__ double s_x[64], s_y[64], s_z[64], s_h[64], s_vx[64], s_vy[64], s_vz[64];
+    __shared__ Real s_m[64];
+    __shared__ double o_x[64], o_y[64], o_z[64], o_h[64], o_Vx[64], o_Vy[64], o_Vz[64];
+    __shared__ Real o_i2[64], o_a[64], o_b[64], o_r[64];
+    __shared__ uint16_t q[64 * 32];
+    __shared__ int offs[65];
+    const PassGeom& G = a.g;
+    const int lane = lane_id();
+    const Real* inv2s2 = reinterpret_cast<const Real*>(a.inv2s2);
+    const Real* ra = reinterpret_cast<const Real*>(a.ra);
+    const Real* rb = reinterpret_cast<const Real*>(a.rb);
+    const Real* rr = reinterpret_cast<const Real*>(a.rr);
+    const Real* dm_m = reinterpret_cast<const Real*>(a.dm_m);
+    int64_t it;
+    uint64_t npairs = 0;
+    while (item_next(G.queue_ctr, G.n_items, &it)) {
+        const int64_t t = a.g.it_tile[it];
+        const uint32_t cb = G.it_cb[it], ce = G.it_ce[it];
+        const int64_t slot = t * kTile + lane;
+        const bool ov = slot < G.n_own;
+        const int64_t sp = ov ? int64_t(G.own[slot]) : 0;
+        double mx = ov ? G.ox[sp] : 0.0, my = ov ? G.oy[sp] : 0.0, mz = ov ? G.oz[sp] : 0.0;
+        double mh = ov ? G.oh[sp] : 0.0;
+        o_x[lane] = mx; o_y[lane] = my; o_z[lane] = mz; o_h[lane] = mh;
+        o_Vx[lane] = ov ? a.Vx[sp] : 0.0; o_Vy[lane] = ov ? a.Vy[sp] : 0.0; o_Vz[lane] = ov ? a.Vz[sp] : 0.0;
+        o_i2[lane] = ov ? inv2s2[sp] : Real(0);
+        o_a[lane] = ov ? ra[sp] : Real(0);
+        o_b[lane] = ov ? rb[sp] : Real(0);
+        o_r[lane] = ov ? rr[sp] : Real(0);
+        double A[6];
+        for (int k = 0; k < 6; ++k) A[k] = G.obox[6 * t + k];
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        for (uint32_t c = cb; c < ce; ++c) {
+            const int64_t ot = G.cand[c];
+            const int64_t obase = ot * kTile;
+            const int ocnt = int(min<int64_t>(kTile, G.n_other - obase));
+            double sh[3];
+            bool clean;
+            tile_pair_shift(A, G.tbox + 6 * ot, G.L, sh, &clean);
+            __syncthreads();
+            if (lane < ocnt) {
+                int64_t k = obase + lane;
+                s_x[lane] = G.tx[k] + sh[0]; s_y[lane] = G.ty[k] + sh[1]; s_z[lane] = G.tz[k] + sh[2];
+                s_h[lane] = G.th[k];
+                s_vx[lane] = a.dvx[k]; s_vy[lane] = a.dvy[k]; s_vz[lane] = a.dvz[k];
+                s_m[lane] = dm_m[k];
+            }
+            __syncthreads();
+            for (int kb = 0; kb < ocnt; kb += 32) {
+                const int kn = min(32, ocnt - kb);
+                uint32_t mask = 0u;
+                if (ov) {
+                    for (int k = 0; k < kn; ++k) {
+                        double d2 = pair_d2(mx, my, mz, s_x[kb + k], s_y[kb + k], s_z[kb + k], clean, G.L);
+                        double hs = mh + s_h[kb + k];
+                        if (d2 < hs * hs) mask |= 1u << k;
+                    }
+                }
+                const int cnt = __popc(mask);
+                const int incl = wave_incl_scan(cnt);
+                const int H = __shfl(incl, 63);
+                int p = incl - cnt;
+                offs[lane] = p;
+                if (lane == 63) offs[64] = H;
+                while (mask) {
+                    int k = __ffs(mask) - 1;
+                    mask &= mask - 1u;
+                    q[p++] = uint16_t((lane << 8) | (kb + k));
+                }
+                npairs += uint64_t(cnt);
+                __syncthreads();
+                const int my_lo = offs[lane], my_hi = offs[lane + 1];
+                for (int base = 0; base < H; base += 64) {
+                    const int pp = base + lane;
+                    const bool pv = pp < H;
+                    Real c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+                    int seg_end = -1;
+                    if (pv) {
+                        const uint16_t e = q[pp];
+                        const int o = e >> 8, k = e & 255;
+                        seg_end = min(offs[o + 1], base + 64) - 1 - base;
+                        double d2 = pair_d2(o_x[o], o_y[o], o_z[o], s_x[k], s_y[k], s_z[k], clean, G.L);
+                        Real d = Real(sqrt(d2));
+                        Real g = EXACT_G ? overlap_g_exact<Real>(d, Real(s_h[k]), Real(o_h[o]))
+                                         : overlap_g_table<Real>(a.gtab, d, Real(s_h[k]), Real(o_h[o]));
+                        Real wx = Real(s_vx[k] - o_Vx[o]), wy = Real(s_vy[k] - o_Vy[o]), wz = Real(s_vz[k] - o_Vz[o]);
+                        Real w2 = wx * wx + wy * wy + wz * wz;
+                        Real FA, FB, Ar, Br;
+                        const Real i2 = o_i2[o];
+                        if (isinf(i2)) {  // cold gas: A = w^{n+1}, B = w^{n+3}
+                            Real wn = sqrt_real(w2);
+                            Ar = pow_np1<N>(wn);
+                            Br = Ar * w2;
+                        } else {
+                            rate_1f1<N, Real>(w2 * i2, &FA, &FB);
+                            Ar = o_a[o] * FA;
+                            Br = o_b[o] * FB;
+                        }
+                        const Real mg = s_m[k] * g;
+                        const Real mgA = mg * Ar;
+                        c0 = mgA * wx; c1 = mgA * wy; c2 = mgA * wz;
+                        c3 = mg * (w2 * Ar - o_r[o] * Br);
+                    }
+                    c0 = seg_sum(c0, lane, seg_end);
+                    c1 = seg_sum(c1, lane, seg_end);
+                    c2 = seg_sum(c2, lane, seg_end);
+                    c3 = seg_sum(c3, lane, seg_end);
+                    const int s0 = max(my_lo, base);
+                    const bool has = s0 < my_hi && s0 < base + 64;
+                    const int src = has ? s0 - base : 0;
+                    const Real v0 = __shfl(c0, src), v1 = __shfl(c1, src), v2 = __shfl(c2, src), v3 = __shfl(c3, src);
+                    if (has) { acc0 += double(v0); acc1 += double(v1); acc2 += double(v2); acc3 += double(v3); }
+                }
+                __syncthreads();
+            }
+        }
+        double* P = a.part + (it * kTile + lane) * 4;
+        P[0] = acc0; P[1] = acc1; P[2] = acc2; P[3] = acc3;
+    }
+    // wave-total pair count
+    for (int d = 32; d >= 1; d >>= 1) npairs += __shfl_xor(npairs, d);
+    if (lane == 0 && npairs) atomicAdd((unsigned long long*)&G.counters[0], (unsigned long long)npairs);
+}
+
+// ---------------------------------------------------------------------------
+// DM (Monte Carlo) pass: owners = active DM, others = gas.
+struct DmPassArgs {
+    PassGeom g;
+    const double* vx; const double* vy; const double* vz;    // DM velocities, sorted
+    const void* dtr;                                          // DM dt (Real), sorted
+    const uint32_t* dm_perm;                                  // DM sorted pos -> index
+    const double* Vx; const double* Vy; const double* Vz;     // gas, sorted
+    const void* vs; const void* K; const void* crit;          // gas (Real), sorted
+    const uint32_t* gas_perm;                                 // gas sorted pos -> index
+    const float4* gtab;
+    uint32_t k0, k1, step, box;
+    double* part_p;               // [n_items][64]
+    float* part_pm;               // [n_items][64]
+};
+
+// P_ij for one (DM, gas) pair: one Maxwellian gas-velocity sample (Philox tag
+// 0) and P = K_j g v_rel^{n+1} dt_i (eq. dm-update-prob).  `urel` returns
+// v_i - v^B_ij.  Shared by the DM pass and the partner resolve so both see
+// identical values.
+template <typename Real, int N, bool EXACT_G>
+__device__ __forceinline__ Real pair_P(double d2, double dh, double gh, double vx, double vy, double vz, double Vx,
+                                       double Vy, double Vz, Real vs, Real K, Real dt, uint32_t i, uint32_t j,
+                                       uint32_t step, uint32_t box, uint32_t k0, uint32_t k1, const float4* gtab,
+                                       Real urel[3])
+{
+    Real d = Real(sqrt(d2));
+    Real g = EXACT_G ? overlap_g_exact<Real>(d, Real(dh), Real(gh)) : overlap_g_table<Real>(gtab, d, Real(dh), Real(gh));
+    U4 r = philox_block(i, j, step, kTagGasVel, box, k0, k1);
+    Real z[3];
+    normals3<Real>(r, z);
+    urel[0] = Real(vx - Vx) - vs * z[0];
+    urel[1] = Real(vy - Vy) - vs * z[1];
+    urel[2] = Real(vz - Vz) - vs * z[2];
+    Real vrel = sqrt_real(urel[0] * urel[0] + urel[1] * urel[1] + urel[2] * urel[2]);
+    return K * g * pow_np1<N>(vrel) * dt;
+}
+
+template <typename Real, int N, bool EXACT_G>
+__global__ __launch_bounds__(64) void k_pass_dm(DmPassArgs a)
+{
+    __shared__ double s_x[64], s_y[64], s_z[64], s_h[64], s_Vx[64], s_Vy[64], s_Vz[64];
+    __shared__ Real s_vs[64], s_K[64], s_cr[64];
+    __shared__ uint32_t s_id[64];
+    __shared__ double o_x[64], o_y[64], o_z[64], o_h[64], o_vx[64], o_vy[64], o_vz[64];
+    __shared__ Real o_dt[64];
+    __shared__ uint32_t o_id[64];
+    __shared__ uint16_t q[64 * 32];
+    __shared__ int offs[65];
+    const PassGeom& G = a.g;
+    const int lane = lane_id();
+    const Real* dtr = reinterpret_cast<const Real*>(a.dtr);
+    const Real* vs = reinterpret_cast<const Real*>(a.vs);
+    const Real* Kp = reinterpret_cast<const Real*>(a.K);
+    const Real* cr = reinterpret_cast<const Real*>(a.crit);
+    int64_t it;
+    uint64_t npairs = 0, ncrit = 0, nnear = 0;
+    while (item_next(G.queue_ctr, G.n_items, &it)) {
+        const int64_t t = G.it_tile[it];
+        const uint32_t cb = G.it_cb[it], ce = G.it_ce[it];
+        const int64_t slot = t * kTile + lane;
+        const bool ov = slot < G.n_own;
+        const int64_t sp = ov ? int64_t(G.own[slot]) : 0;
+        double mx = ov ? G.ox[sp] : 0.0, my = ov ? G.oy[sp] : 0.0, mz = ov ? G.oz[sp] : 0.0;
+        double mh = ov ? G.oh[sp] : 0.0;
+        o_x[lane] = mx; o_y[lane] = my; o_z[lane] = mz; o_h[lane] = mh;
+        o_vx[lane] = ov ? a.vx[sp] : 0.0; o_vy[lane] = ov ? a.vy[sp] : 0.0; o_vz[lane] = ov ? a.vz[sp] : 0.0;
+        o_dt[lane] = ov ? dtr[sp] : Real(0);
+        o_id[lane] = ov ? a.dm_perm[sp] : 0u;
+        double A[6];
+        for (int k = 0; k < 6; ++k) A[k] = G.obox[6 * t + k];
+        double accP = 0.0;
+        Real accM = 0;
+        bool near_b = false;
+        for (uint32_t c = cb; c < ce; ++c) {
+            const int64_t ot = G.cand[c];
+            const int64_t obase = ot * kTile;
+            const int ocnt = int(min<int64_t>(kTile, G.n_other - obase));
+            double sh[3];
+            bool clean;
+            tile_pair_shift(A, G.tbox + 6 * ot, G.L, sh, &clean);
+            __syncthreads();
+            if (lane < ocnt) {
+                int64_t k = obase + lane;
+                s_x[lane] = G.tx[k] + sh[0]; s_y[lane] = G.ty[k] + sh[1]; s_z[lane] = G.tz[k] + sh[2];
+                s_h[lane] = G.th[k];
+                s_Vx[lane] = a.Vx[k]; s_Vy[lane] = a.Vy[k]; s_Vz[lane] = a.Vz[k];
+                s_vs[lane] = vs[k]; s_K[lane] = Kp[k]; s_cr[lane] = cr[k];
+                s_id[lane] = a.gas_perm[k];
+            }
+            __syncthreads();
+            for (int kb = 0; kb < ocnt; kb += 32) {
+                const int kn = min(32, ocnt - kb);
+                uint32_t mask = 0u;
+                if (ov) {
+                    for (int k = 0; k < kn; ++k) {
+                        double d2 = pair_d2(mx, my, mz, s_x[kb + k], s_y[kb + k], s_z[kb + k], clean, G.L);
+                        double hs = mh + s_h[kb + k];
+                        double hs2 = hs * hs;
+                        if (d2 < hs2) mask |= 1u << k;
+                        if (fabs(d2 - hs2) <= 1e-6 * hs2) near_b = true;
+                    }
+                }
+                const int cnt = __popc(mask);
+                const int incl = wave_incl_scan(cnt);
+                const int H = __shfl(incl, 63);
+                int p = incl - cnt;
+                offs[lane] = p;
+                if (lane == 63) offs[64] = H;
+                while (mask) {
+                    int k = __ffs(mask) - 1;
+                    mask &= mask - 1u;
+                    q[p++] = uint16_t((lane << 8) | (kb + k));
+                }
+                npairs += uint64_t(cnt);
+                __syncthreads();
+                const int my_lo = offs[lane], my_hi = offs[lane + 1];
+                for (int base = 0; base < H; base += 64) {
+                    const int pp = base + lane;
+                    const bool pv = pp < H;
+                    double cP = 0.0;
+                    Real cM = 0;
+                    int seg_end = -1;
+                    if (pv) {
+                        const uint16_t e = q[pp];
+                        const int o = e >> 8, k = e & 255;
+                        seg_end = min(offs[o + 1], base + 64) - 1 - base;
+                        double d2 = pair_d2(o_x[o], o_y[o], o_z[o], s_x[k], s_y[k], s_z[k], clean, G.L);
+                        Real urel[3];
+                        Real P = pair_P<Real, N, EXACT_G>(d2, o_h[o], s_h[k], o_vx[o], o_vy[o], o_vz[o], s_Vx[k],
+                                                          s_Vy[k], s_Vz[k], s_vs[k], s_K[k], o_dt[o], o_id[o],
+                                                          s_id[k], a.step, a.box, a.k0, a.k1, a.gtab, urel);
+                        cP = double(P);
+                        cM = P;
+                        if (P >= s_cr[k]) ncrit++;
+                    }
+                    cP = seg_sum(cP, lane, seg_end);
+                    cM = seg_max(cM, lane, seg_end);
+                    const int s0 = max(my_lo, base);
+                    const bool has = s0 < my_hi && s0 < base + 64;
+                    const int src = has ? s0 - base : 0;
+                    const double vP = __shfl(cP, src);
+                    const Real vM = __shfl(cM, src);
+                    if (has) { accP += vP; accM = accM > vM ? accM : vM; }
+                }
+                __syncthreads();
+            }
+        }
+        if (ov && near_b) nnear++;
+        a.part_p[it * kTile + lane] = accP;
+        a.part_pm[it * kTile + lane] = float(accM);
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        npairs += __shfl_xor(npairs, d);
+        ncrit += __shfl_xor(ncrit, d);
+        nnear += __shfl_xor(nnear, d);
+    }
+    if (lane == 0) {
+        if (npairs) atomicAdd((unsigned long long*)&G.counters[1], (unsigned long long)npairs);
+        if (nnear) atomicAdd((unsigned long long*)&G.counters[3], (unsigned long long)nnear);
+        if (ncrit) atomicAdd((unsigned long long*)&G.counters[5], (unsigned long long)ncrit);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Combine partials of each owner (fixed item order) and apply owner factors.
+struct GasCombineArgs {
+    int64_t n_own;
+    const uint32_t* own; const uint32_t* perm;
+    const uint32_t* item_off;     // [nown_tile + 1]
+    const double* part;
+    const double* mass; const double* mu; const double* dt;
+    double dt_default, m_chi, sig_kpc2_cn;
+    double* dp; double* de;
+};
+
+__global__ __launch_bounds__(256) void k_combine_gas(GasCombineArgs a)
+{
+    int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= a.n_own) return;
+    int64_t t = s / kTile, l = s % kTile;
+    double acc[4] = {0, 0, 0, 0};
+    for (uint32_t it = a.item_off[t]; it < a.item_off[t + 1]; ++it)
+        for (int c = 0; c < 4; ++c) acc[c] += a.part[(int64_t(it) * kTile + l) * 4 + c];
+    uint32_t o = a.perm[a.own[s]];
+    double mu = a.mu ? a.mu[o] : kMpG;
+    double dtj = a.dt ? a.dt[o] : a.dt_default;
+    double sc = a.mass[o] * dtj * kMsunG / (a.m_chi + mu) * a.sig_kpc2_cn;
+    a.dp[3 * int64_t(o)] = sc * acc[0];
+    a.dp[3 * int64_t(o) + 1] = sc * acc[1];
+    a.dp[3 * int64_t(o) + 2] = sc * acc[2];
+    a.de[o] = sc * acc[3];
+}
+
+struct DmCombineArgs {
+    int64_t n_own;
+    const uint32_t* own; const uint32_t* perm;
+    const uint32_t* item_off;
+    const double* part_p; const float* part_pm;
+    uint32_t k0, k1, step, box;
+    double* psum_own;             // [n_own] P_i in owner-slot order
+    double* psum; double* pmax;   // outputs (nullable)
+    uint32_t* scount; uint32_t* slist;
+    uint64_t* counters;
+};
+
+__global__ __launch_bounds__(256) void k_combine_dm(DmCombineArgs a)
+{
+    int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    bool v = s < a.n_own;
+    uint32_t scat = 0, pge1 = 0, nonf = 0, nearD = 0;
+    if (v) {
+        int64_t t = s / kTile, l = s % kTile;
+        double P = 0.0;
+        float Pm = 0.f;
+        for (uint32_t it = a.item_off[t]; it < a.item_off[t + 1]; ++it) {
+            P += a.part_p[int64_t(it) * kTile + l];
+            Pm = fmaxf(Pm, a.part_pm[int64_t(it) * kTile + l]);
+        }
+        uint32_t o = a.perm[a.own[s]];
+        a.psum_own[s] = P;
+        if (a.psum) a.psum[o] = P;
+        if (a.pmax) a.pmax[o] = double(Pm);
+        U4 r = philox_block(o, 0xFFFFFFFFu, a.step, kTagDecision, a.box, a.k0, a.k1);
+        double U = u24<double>(r.x);
+        if (!isfinite(P)) nonf = 1;
+        if (P >= 1.0) pge1 = 1;
+        if (U < P) {
+            uint32_t idx = atomicAdd(a.scount, 1u);
+            a.slist[idx] = uint32_t(s);
+            scat = 1;
+        } else if (fabs(P - U) <= 1e-6 * U) {
+            nearD = 1;
+        }
+    }
+    uint64_t b0 = __ballot(scat), b1 = __ballot(pge1), b2 = __ballot(nonf), b3 = __ballot(nearD);
+    if (lane_id() == 0) {
+        if (b0) atomicAdd((unsigned long long*)&a.counters[2], (unsigned long long)__popcll(b0));
+        if (b1) atomicAdd((unsigned long long*)&a.counters[6], (unsigned long long)__popcll(b1));
+        if (b2) atomicAdd((unsigned long long*)&a.counters[7], (unsigned long long)__popcll(b2));
+        if (b3) atomicAdd((unsigned long long*)&a.counters[4], (unsigned long long)__popcll(b3));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Partner resolve for the DM that scatter (eq. dm-update-vels: one draw from
+// the mixture): the partner is the smallest gas index whose running sum of
+// P_ij exceeds U_i.  Radix select over the gas index, 8 bits per pass; each
+// pass recomputes the DM's pair probabilities (same arithmetic as the DM
+// pass) and accumulates them per digit as exact fixed-point integers
+// (P * 2^64 split into two u64 halves), so the running sums are exact sums
+// of the per-pair values and independent of accumulation order.
+struct ResolveArgs {
+    PassGeom g;                   // owners = DM, others = gas (same as the DM pass)
+    const uint32_t* cand_off;     // [nown_tile + 1]
+    const double* vx; const double* vy; const double* vz; const void* dtr; const uint32_t* dm_perm;
+    const double* Vx; const double* Vy; const double* Vz; const void* vs; const void* K; const uint32_t* gas_perm;
+    const double* gas_vel; const double* gas_u; const double* gas_mu;   // raw gas inputs (partner kick)
+    double m_chi;
+    const float4* gtab;
+    uint32_t k0, k1, step, box;
+    int n_gas_bits;
+    uint32_t n_gas;
+    const uint32_t* scount; const uint32_t* slist;
+    double* dv; int32_t* partner;
+    uint64_t* counters;
+};
+
+__device__ __forceinline__ void fixed_split(double P, unsigned long long* hi, unsigned long long* lo)
+{
+    if (!(P >= 0.0)) { *hi = 0ull; *lo = 0ull; return; }
+    if (!(P < 2147483648.0)) { *hi = 1ull << 63; *lo = 0ull; return; }
+    double pd = P * 4294967296.0;
+    double fl = floor(pd);
+    *hi = (unsigned long long)fl;
+    *lo = (unsigned long long)((pd - fl) * 4294967296.0);
+}
+
+constexpr int kResolveList = 2048;   // candidate tiles kept per scattering DM after the point test
+
+template <typename Real, int N, bool EXACT_G>
+__global__ __launch_bounds__(64) void k_resolve(ResolveArgs a)
+{
+    __shared__ unsigned long long hhi[256], hlo[256];
+    __shared__ uint32_t s_list[kResolveList];
+    __shared__ uint32_t s_sel;
+    __shared__ int s_near;
+    const PassGeom& G = a.g;
+    const int lane = lane_id();
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const Real* dtr = reinterpret_cast<const Real*>(a.dtr);
+    const Real* vs = reinterpret_cast<const Real*>(a.vs);
+    const Real* Kp = reinterpret_cast<const Real*>(a.K);
+    const uint32_t nsc = *a.scount;
+    uint32_t nnearD = 0;
+    for (uint32_t e = blockIdx.x; e < nsc; e += gridDim.x) {
+        const int64_t s = a.slist[e];
+        const int64_t sp = G.own[s];
+        const int64_t t = s / kTile;
+        const double mx = G.ox[sp], my = G.oy[sp], mz = G.oz[sp], mh = G.oh[sp];
+        const double mvx = a.vx[sp], mvy = a.vy[sp], mvz = a.vz[sp];
+        const Real mdt = dtr[sp];
+        const uint32_t oid = a.dm_perm[sp];
+        U4 rd = philox_block(oid, 0xFFFFFFFFu, a.step, kTagDecision, a.box, a.k0, a.k1);
+        const unsigned __int128 Ufix = (unsigned __int128)(2ull * (rd.x >> 8) + 1ull) << 39;
+        double A[6];
+        for (int k = 0; k < 6; ++k) A[k] = G.obox[6 * t + k];
+        const uint32_t cb = a.cand_off[t], ce = a.cand_off[t + 1];
+        // Keep only the candidate tiles of the owner tile that this DM can
+        // reach (point-to-box gap < h_i + h_max of the tile); lanes test 64
+        // candidates at a time.  Falls back to the full list if it overflows.
+        const double P6[6] = {mx, my, mz, mx, my, mz};
+        uint32_t nrel = 0;
+        for (uint32_t c0 = cb; c0 < ce; c0 += 64) {
+            const uint32_t c = c0 + lane;
+            bool hit = false;
+            uint32_t ot = 0;
+            if (c < ce) {
+                ot = G.cand[c];
+                hit = boxes_near(P6, mh, G.tbox + 6 * int64_t(ot), G.th[ot], G.L);
+            }
+            const uint64_t bal = __ballot(hit);
+            const uint32_t pos = nrel + uint32_t(__popcll(bal & lt));
+            if (hit && pos < kResolveList) s_list[pos] = c;
+            nrel += uint32_t(__popcll(bal));
+        }
+        const bool use_list = nrel <= uint32_t(kResolveList);
+        const uint32_t nl = use_list ? nrel : ce - cb;
+        __syncthreads();
+        const int npass = (a.n_gas_bits + 7) / 8;
+        uint32_t prefix = 0;
+        unsigned __int128 below = 0;
+        for (int ps = 0; ps < npass; ++ps) {
+            const int shft = 8 * (npass - 1 - ps);
+            for (int b = lane; b < 256; b += 64) { hhi[b] = 0ull; hlo[b] = 0ull; }
+            __syncthreads();
+            for (uint32_t q = 0; q < nl; ++q) {
+                const uint32_t c = use_list ? s_list[q] : cb + q;
+                const int64_t ot = G.cand[c];
+                const int64_t k = ot * kTile + lane;
+                double sh[3];
+                bool clean;
+                tile_pair_shift(A, G.tbox + 6 * ot, G.L, sh, &clean);
+                if (k < G.n_other) {
+                    const uint32_t gid = a.gas_perm[k];
+                    if (uint64_t(gid) >> (shft + 8) == uint64_t(prefix)) {
+                        double px = G.tx[k] + sh[0], py = G.ty[k] + sh[1], pz = G.tz[k] + sh[2];
+                        double d2 = pair_d2(mx, my, mz, px, py, pz, clean, G.L);
+                        double hs = mh + G.th[k];
+                        if (d2 < hs * hs) {
+                            Real urel[3];
+                            Real P = pair_P<Real, N, EXACT_G>(d2, mh, G.th[k], mvx, mvy, mvz, a.Vx[k], a.Vy[k], a.Vz[k],
+                                                              vs[k], Kp[k], mdt, oid, gid, a.step, a.box, a.k0, a.k1,
+                                                              a.gtab, urel);
+                            unsigned long long hi, lo;
+                            fixed_split(double(P), &hi, &lo);
+                            const int dg = (gid >> shft) & 255u;
+                            atomicAdd(&hhi[dg], hi);
+                            atomicAdd(&hlo[dg], lo);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (lane == 0) {
+                unsigned __int128 cum = below;
+                int sel = -1, last_nz = -1;
+                unsigned __int128 sel_below = below, sel_after = below;
+                for (int b = 0; b < 256; ++b) {
+                    unsigned __int128 v = ((unsigned __int128)hhi[b] << 32) + (unsigned __int128)hlo[b];
+                    if (v != 0) last_nz = b;
+                    unsigned __int128 nx = cum + v;
+                    if (sel < 0 && nx > Ufix) { sel = b; sel_below = cum; sel_after = nx; }
+                    cum = nx;
+                }
+                if (sel < 0) {  // rounding guard: keep the largest index with P > 0
+                    sel = last_nz < 0 ? 0 : last_nz;
+                    sel_below = below;
+                    sel_after = cum;
+                }
+                below = sel_below;
+                s_sel = uint32_t(sel);
+                if (ps == npass - 1) {
+                    // running sums adjacent to U_i (relative 1e-6 band)
+                    double Ud = double(Ufix) * 0x1p-64, Sb = double(sel_below) * 0x1p-64, Sa = double(sel_after) * 0x1p-64;
+                    s_near = (fabs(Sb - Ud) <= 1e-6 * Ud || fabs(Sa - Ud) <= 1e-6 * Ud) ? 1 : 0;
+                }
+            }
+            __syncthreads();
+            prefix = (prefix << 8) | s_sel;
+            __syncthreads();
+        }
+        if (lane == 0) {
+            const uint32_t j = prefix < a.n_gas ? prefix : a.n_gas - 1u;
+            nnearD += uint32_t(s_near);
+            const double muj = a.gas_mu ? a.gas_mu[j] : kMpG;
+            Real vsj, i2, ra, rb, rr, cr;
+            gas_derived<Real>(a.gas_u[j], muj, a.m_chi, 1.0, 0, &vsj, &i2, &ra, &rb, &rr, &cr);
+            U4 r = philox_block(oid, j, a.step, kTagGasVel, a.box, a.k0, a.k1);
+            Real z[3];
+            normals3<Real>(r, z);
+            Real ux = Real(mvx - a.gas_vel[3 * int64_t(j)]) - vsj * z[0];
+            Real uy = Real(mvy - a.gas_vel[3 * int64_t(j) + 1]) - vsj * z[1];
+            Real uz = Real(mvz - a.gas_vel[3 * int64_t(j) + 2]) - vsj * z[2];
+            Real vrel = sqrt_real(ux * ux + uy * uy + uz * uz);
+            double dvx = 0.0, dvy = 0.0, dvz = 0.0;
+            if (vrel > Real(0)) {
+                U4 r2 = philox_block(oid, j, a.step, kTagDir, a.box, a.k0, a.k1);
+                Real ct = Real(2) * u24<Real>(r2.x) - Real(1);
+                Real st = sqrt_real(fmax(Real(0), Real(1) - ct * ct));
+                Real sp_, cp_;
+                sincos_turns(u24<Real>(r2.y), &sp_, &cp_);
+                Real iv = Real(1) / vrel;
+                Real f = rr * vrel;
+                dvx = double(f * (st * cp_ - ux * iv));
+                dvy = double(f * (st * sp_ - uy * iv));
+                dvz = double(f * (ct - uz * iv));
+            }
+            a.dv[3 * int64_t(oid)] = dvx;
+            a.dv[3 * int64_t(oid) + 1] = dvy;
+            a.dv[3 * int64_t(oid) + 2] = dvz;
+            a.partner[oid] = int32_t(j);
+        }
+        __syncthreads();
+    }
+    if (lane == 0 && nnearD) atomicAdd((unsigned long long*)&a.counters[4], (unsigned long long)nnearD);
+}
+
+// ---------------------------------------------------------------------------
+// Overlap table (Appendix D), built on the device from the exact overlap.
+__global__ __launch_bounds__(256) void k_gtab_build(float4* __restrict__ tab)
+{
+    int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int nx = kTabND + 1, ny = kTabNE + 1;
+    if (id >= int64_t(nx) * ny) return;
+    int i = int(id % nx), j = int(id / nx);
+    double dd = 2.0 / kTabND, de = 1.0 / kTabNE;
+    double delta = i * dd, eta = j * de;
+    auto H = [](double dl, double et) -> double {
+        if (et <= 0.0) return kernel_w(dl);
+        return overlap_H_exact(dl, et);
+    };
+    double h0 = H(delta, eta);
+    const double st = 1e-5;
+    double dHd = delta == 0.0 ? 0.0 : (H(delta + st, eta) - H(fmax(delta - st, 0.0), eta)) / (delta + st - fmax(delta - st, 0.0));
+    double el = fmax(eta - st, 0.0), eh = fmin(eta + st, 1.0);
+    double dHe = (H(delta, eh) - H(delta, el)) / (eh - el);
+    tab[id] = make_float4(float(h0), float(dHd * dd), float(dHe * de), 0.f);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_overlap_eval(int64_t n, const double* d, const double* h1, const double* h2,
+                                                      const float4* tab, bool exact, double* out)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Real dd = Real(d[i]), a = Real(h1[i]), b = Real(h2[i]);
+    Real g;
+    if (d[i] >= h1[i] + h2[i]) g = Real(0);
+    else g = exact ? overlap_g_exact<Real>(dd, a, b) : overlap_g_table<Real>(tab, dd, a, b);
+    out[i] = double(g);
+}
+
+template <typename Real, int N>
+__global__ __launch_bounds__(256) void k_rates_eval(int64_t n, const double* w, const double* vs, double alpha_n,
+                                                    double* A, double* B)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = vs[i];
+    Real w2 = Real(w[i] * w[i]);
+    if (s <= 0.0) {
+        Real wn = sqrt_real(w2);
+        Real Ar = pow_np1<N>(wn);
+        A[i] = double(Ar);
+        B[i] = double(Ar * w2);
+        return;
+    }
+    Real i2 = Real(1.0 / (2.0 * s * s));
+    Real ra = Real(alpha_n / 3.0 * pow(s, double(N + 1))), rb = Real(alpha_n * pow(s, double(N + 3)));
+    Real FA, FB;
+    rate_1f1<N, Real>(w2 * i2, &FA, &FB);
+    A[i] = double(ra * FA);
+    B[i] = double(rb * FB);
+}
+
+__global__ __launch_bounds__(256) void k_philox_eval(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k1,
+                                                     uint32_t* out)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    U4 c{ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]};
+    U4 r = philox4x32_10(c, k0, k1);
+    out[4 * i] = r.x; out[4 * i + 1] = r.y; out[4 * i + 2] = r.z; out[4 * i + 3] = r.w;
+}
+
+}  // namespace dmb
