@@ -162,6 +162,8 @@ def main():
     ph = ctx.profile_read(reset=True)
     ctx.profile_enable(False)
     cnt = dmb.counters_dict(out["counters"])
+    bst = ctx.build_stats()
+    log(f"bench: build stats {bst}")
     log(f"bench: timed {args.steps} steps in {t1 - t0:.3f} s; counters {cnt}")
     log("bench: phases (ms per step) " + ", ".join(f"{k}={v[0] / max(v[1], 1):.3f}" for k, v in ph.items()))
     if args.copy_probe_mb > 0:
@@ -204,6 +206,9 @@ def main():
         "interact_only_pairs_per_s": pairs / (sum(v for k, v in per_kernel.items() if k != "build") * 1e-3),
         "hbm_algorithmic_GBps": bytes_step / (ms_step * 1e-3) / 1e9,
         "roofline": roof,
+        "build_stats": bst,
+        "hit_fraction": {"gas": pairs / max(1, bst["cand_pairs_gas"] * 4096),
+                         "dm": pairs / max(1, bst["cand_pairs_dm"] * 4096)},
     }
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")

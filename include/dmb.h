@@ -169,6 +169,12 @@ dmb_status dmb_profile_enable(dmb_ctx *ctx, int32_t on);
  * counts per phase (host arrays of DMB_NPHASES); reset != 0 clears them. */
 dmb_status dmb_profile_read(dmb_ctx *ctx, double *ms, int64_t *calls, int32_t reset);
 
+/* Structure of the last dmb_build_cells (host array of 10 int64):
+ * [active gas, active DM, gas tiles, DM tiles, gas owner tiles, DM owner
+ *  tiles, candidate tile pairs of the gas pass, of the DM pass, work items of
+ *  the gas pass, of the DM pass]. */
+dmb_status dmb_build_stats(const dmb_ctx *ctx, int64_t *out10);
+
 /* Message for the last failure on this context (never NULL). */
 const char *dmb_last_error(const dmb_ctx *ctx);
 

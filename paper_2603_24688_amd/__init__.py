@@ -24,7 +24,9 @@ STATUS = {0: "DMB_OK", -1: "DMB_EINVAL", -2: "DMB_ENOMEM", -3: "DMB_EHIP", -4: "
 # Symbols declared in include/dmb.h.
 EXPORTS = ["dmb_create", "dmb_destroy", "dmb_set_stream", "dmb_build_cells", "dmb_interact_step",
            "dmb_overlap_eval", "dmb_rates_eval", "dmb_philox_eval", "dmb_profile_enable", "dmb_profile_read",
-           "dmb_last_error"]
+           "dmb_build_stats", "dmb_last_error"]
+BUILD_STATS = ["active_gas", "active_dm", "gas_tiles", "dm_tiles", "gas_owner_tiles", "dm_owner_tiles",
+               "cand_pairs_gas", "cand_pairs_dm", "items_gas", "items_dm"]
 PHASES = ["build", "gather", "pass_gas", "combine_gas", "pass_dm", "combine_dm", "resolve"]
 
 
@@ -73,6 +75,7 @@ def load_library(path: str = LIB_PATH):
     L.dmb_philox_eval.restype = C.c_int; L.dmb_philox_eval.argtypes = [vp, i64, vp, u64, vp]
     L.dmb_profile_enable.restype = C.c_int; L.dmb_profile_enable.argtypes = [vp, i32]
     L.dmb_profile_read.restype = C.c_int; L.dmb_profile_read.argtypes = [vp, vp, vp, i32]
+    L.dmb_build_stats.restype = C.c_int; L.dmb_build_stats.argtypes = [vp, vp]
     L.dmb_last_error.restype = C.c_char_p; L.dmb_last_error.argtypes = [vp]
     _lib = L
     return L
@@ -148,6 +151,11 @@ class Context:
                 _ptr(out.get("p_sum")), _ptr(out.get("p_max")), _ptr(out.get("counters")))
         self._check(self.lib.dmb_interact_step(self.h, C.byref(G), C.byref(D), C.byref(P), C.byref(O)),
                     "dmb_interact_step")
+
+    def build_stats(self) -> dict:
+        v = (C.c_int64 * len(BUILD_STATS))()
+        self._check(self.lib.dmb_build_stats(self.h, v), "dmb_build_stats")
+        return dict(zip(BUILD_STATS, [int(x) for x in v]))
 
     # -- phase timing ---------------------------------------------------------------------------
     def profile_enable(self, on: bool = True):

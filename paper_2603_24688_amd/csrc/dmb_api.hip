@@ -546,6 +546,15 @@ dmb_status dmb_set_stream(dmb_ctx* c, void* hip_stream)
 
 const char* dmb_last_error(const dmb_ctx* c) { return c ? c->err : "null context"; }
 
+dmb_status dmb_build_stats(const dmb_ctx* c, int64_t* o)
+{
+    if (!c || !o) return DMB_EINVAL;
+    const int64_t v[10] = {c->gas.n_own, c->dm.n_own, c->gas.ntile, c->dm.ntile, c->gas.nown_tile, c->dm.nown_tile,
+                           c->gp.total, c->dp.total, c->gp.nitems, c->dp.nitems};
+    for (int k = 0; k < 10; ++k) o[k] = v[k];
+    return DMB_OK;
+}
+
 dmb_status dmb_profile_enable(dmb_ctx* c, int32_t on)
 {
     if (!c) return DMB_EINVAL;
