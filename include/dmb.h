@@ -175,7 +175,8 @@ dmb_status dmb_profile_read(dmb_ctx *ctx, double *ms, int64_t *calls, int32_t re
  *  the gas pass, of the DM pass]. */
 dmb_status dmb_build_stats(const dmb_ctx *ctx, int64_t *out10);
 
-/* Message for the last failure on this context (never NULL). */
+/* Message for the last failure on this context; with ctx == NULL, the
+ * message of the last failed dmb_create (never NULL). */
 const char *dmb_last_error(const dmb_ctx *ctx);
 
 #ifdef __cplusplus

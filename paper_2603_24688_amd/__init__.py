@@ -61,6 +61,12 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise DmbError(f"{path} is not built; run paper_2603_24688_amd.build.build()")
+    # torch ships its own HIP runtime; load it first so that libdmb.so binds to
+    # the same runtime instance (one device context per process).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
     L.dmb_create.restype = C.c_int; L.dmb_create.argtypes = [C.POINTER(vp), C.c_int, vp]
@@ -121,7 +127,8 @@ class Context:
         h = C.c_void_p()
         rc = self.lib.dmb_create(C.byref(h), int(device), C.c_void_p(s.cuda_stream))
         if rc != 0:
-            raise DmbError(f"dmb_create failed: {STATUS.get(rc, rc)}")
+            msg = self.lib.dmb_last_error(None).decode(errors="replace")
+            raise DmbError(f"dmb_create failed: {STATUS.get(rc, rc)}: {msg}")
         self.h = h
 
     def close(self):

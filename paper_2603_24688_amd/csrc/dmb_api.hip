@@ -27,11 +27,13 @@ struct DevBuf {
 };
 
 struct Species {
-    int64_t n = 0, n_own = 0, ntile = 0, nsuper = 0, nown_tile = 0;
+    int64_t n = 0, n_own = 0, ntile = 0, nsuper = 0, nmega = 0, nown_tile = 0, nchunk = 0;
+    int sort_lo_bit = 0;
+    DevBuf sub_ccnt, sub_coff, sub_start, sub_cnt;   // sub-tiles (other role): per-chunk counts/offsets, ranges
     DevBuf keys, keys2, vals, vals2;       // sort
     DevBuf sx, sy, sz, sh;                 // sorted position, h
     DevBuf flag, flag_off, own;            // active owners (sorted positions)
-    DevBuf tbox, th, sbox, shh, obox, oh;  // tiles, super-tiles, owner tiles
+    DevBuf tbox, th, sbox, shh, mbox, mhh, obox, oh;  // sub-tiles, super-, mega-tiles, owner tiles
     DevBuf cube;                           // Morton cube
     // per-step gathers (sorted order)
     DevBuf v0, v1, v2;                     // velocity components (double)
@@ -56,14 +58,14 @@ struct dmb_ctx {
     DevBuf scan_tmp[4];
     DevBuf sort_table;
     DevBuf bbox_part, boxL;
-    DevBuf part_gas, part_p, part_pm, psum_own;
+    DevBuf part_gas, part_p, part_pm, part_nb, psum_own;
     DevBuf qctr, slist;
     DevBuf counters_local;
     int64_t built_ngas = -1, built_ndm = -1;
     const double* built_gas_pos = nullptr;
     const double* built_dm_pos = nullptr;
     double built_L[3] = {0, 0, 0};
-    int split = 16;
+    int split = 64;
     // phase timing
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -192,7 +194,7 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
 {
     S.n = p->n;
     if (S.n == 0) {
-        S.n_own = S.ntile = S.nsuper = S.nown_tile = 0;
+        S.n_own = S.ntile = S.nsuper = S.nmega = S.nown_tile = S.nchunk = 0;
         return DMB_OK;
     }
     const int64_t n = S.n;
@@ -227,6 +229,7 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
         std::swap(ka, kb);
         std::swap(va, vb);
     }
+    S.sort_lo_bit = std::max(0, 63 - 8 * passes);
     // keep the sorted permutation in S.vals
     if (va != S.vals.as<uint32_t>()) {
         std::swap(S.vals, S.vals2);
@@ -245,16 +248,40 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
     if (s != DMB_OK) return s;
     hipLaunchKernelGGL(k_compact, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, S.flag.as<const uint32_t>(),
                        S.flag_off.as<const uint32_t>(), n, S.own.as<uint32_t>());
-    // tiles over all particles (other role) and super-tiles
-    S.ntile = (n + kTile - 1) / kTile;
+    // sub-tile counts per 64-chunk (other role); totals are read back by the caller
+    S.nchunk = (n + kTile - 1) / kTile;
+    ENSURE(c, S.sub_ccnt, (S.nchunk + 1) * 4); ENSURE(c, S.sub_coff, (S.nchunk + 1) * 4);
+    hipLaunchKernelGGL(k_subtile_split<false>, dim3(unsigned(S.nchunk)), dim3(64), 0, c->stream,
+                       S.keys.as<const uint64_t>(), n, S.sort_lo_bit, S.sub_ccnt.as<uint32_t>(),
+                       (const uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr);
+    HIPCHK(c, hipMemsetAsync(S.sub_ccnt.as<uint32_t>() + S.nchunk, 0, 4, c->stream));
+    s = scan_excl(c, S.sub_ccnt.as<const uint32_t>(), S.sub_coff.as<uint32_t>(), S.nchunk + 1);
+    if (s != DMB_OK) return s;
+    HIPCHK(c, hipGetLastError());
+    return DMB_OK;
+}
+
+// Sub-tile ranges and bounds, super-tiles (needs the sub-tile count).
+dmb_status build_subtiles(dmb_ctx* c, Species& S)
+{
+    if (S.n == 0) return DMB_OK;
+    ENSURE(c, S.sub_start, S.ntile * 4); ENSURE(c, S.sub_cnt, S.ntile * 4);
+    hipLaunchKernelGGL(k_subtile_split<true>, dim3(unsigned(S.nchunk)), dim3(64), 0, c->stream,
+                       S.keys.as<const uint64_t>(), S.n, S.sort_lo_bit, (uint32_t*)nullptr,
+                       S.sub_coff.as<const uint32_t>(), S.sub_start.as<uint32_t>(), S.sub_cnt.as<uint32_t>());
     S.nsuper = (S.ntile + kTile - 1) / kTile;
     ENSURE(c, S.tbox, S.ntile * 48); ENSURE(c, S.th, S.ntile * 8);
     ENSURE(c, S.sbox, S.nsuper * 48); ENSURE(c, S.shh, S.nsuper * 8);
-    hipLaunchKernelGGL(k_tile_bounds, dim3(unsigned(S.ntile)), dim3(64), 0, c->stream, (const uint32_t*)nullptr, n,
-                       S.sx.as<const double>(), S.sy.as<const double>(), S.sz.as<const double>(),
-                       S.sh.as<const double>(), S.tbox.as<double>(), S.th.as<double>());
+    hipLaunchKernelGGL(k_range_bounds, dim3(unsigned(S.ntile)), dim3(64), 0, c->stream,
+                       S.sub_start.as<const uint32_t>(), S.sub_cnt.as<const uint32_t>(), S.sx.as<const double>(),
+                       S.sy.as<const double>(), S.sz.as<const double>(), S.sh.as<const double>(),
+                       S.tbox.as<double>(), S.th.as<double>());
     hipLaunchKernelGGL(k_super_bounds, dim3(unsigned(S.nsuper)), dim3(64), 0, c->stream, S.ntile,
                        S.tbox.as<const double>(), S.th.as<const double>(), S.sbox.as<double>(), S.shh.as<double>());
+    S.nmega = (S.nsuper + kTile - 1) / kTile;
+    ENSURE(c, S.mbox, S.nmega * 48); ENSURE(c, S.mhh, S.nmega * 8);
+    hipLaunchKernelGGL(k_super_bounds, dim3(unsigned(S.nmega)), dim3(64), 0, c->stream, S.nsuper,
+                       S.sbox.as<const double>(), S.shh.as<const double>(), S.mbox.as<double>(), S.mhh.as<double>());
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
 }
@@ -275,7 +302,8 @@ dmb_status build_owner_tiles(dmb_ctx* c, Species& S)
 CandArgs cand_args(dmb_ctx* c, Species& A, Species& B, Pairs& P)
 {
     CandArgs a;
-    a.nown_tile = A.nown_tile; a.ntile = B.ntile; a.nsuper = B.nsuper;
+    a.nown_tile = A.nown_tile; a.ntile = B.ntile; a.nsuper = B.nsuper; a.nmega = B.nmega;
+    a.mbox = B.mbox.as<const double>(); a.mhh = B.mhh.as<const double>();
     a.obox = A.obox.as<const double>(); a.oh = A.oh.as<const double>();
     a.tbox = B.tbox.as<const double>(); a.th = B.th.as<const double>();
     a.sbox = B.sbox.as<const double>(); a.shh = B.shh.as<const double>();
@@ -336,7 +364,9 @@ PassGeom geom(dmb_ctx* c, Species& A, Species& B, Pairs& P, uint64_t* counters)
     g.oh = A.sh.as<const double>(); g.obox = A.obox.as<const double>();
     g.tx = B.sx.as<const double>(); g.ty = B.sy.as<const double>(); g.tz = B.sz.as<const double>();
     g.th = B.sh.as<const double>(); g.n_other = B.n; g.tbox = B.tbox.as<const double>();
+    g.sub_start = B.sub_start.as<const uint32_t>(); g.sub_cnt = B.sub_cnt.as<const uint32_t>();
     g.cand = P.cand.as<const uint32_t>();
+    g.item_off = P.ioff.as<const uint32_t>();
     g.it_tile = P.it_tile.as<const uint32_t>(); g.it_cb = P.it_cb.as<const uint32_t>();
     g.it_ce = P.it_ce.as<const uint32_t>(); g.n_items = P.nitems;
     g.queue_ctr = c->qctr.as<uint32_t>();
@@ -350,7 +380,12 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
                        dmb_out* out, uint64_t* counters)
 {
     constexpr bool kExact = sizeof(Real) == 8;
-    const int nb_persist = std::max(8, (c->num_cu * 8 / 8) * 8);
+    // persistent grids: as many single-wave blocks as can be resident
+    auto persist = [&](const void* fn) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, 0) != hipSuccess || per_cu < 1) per_cu = 8;
+        return std::max(8, (c->num_cu * per_cu / 8) * 8);
+    };
     const uint32_t k0 = uint32_t(par->seed), k1 = uint32_t(par->seed >> 32);
     const double sig_kpc2_cn = par->sigma0_cm2 / (kKpcCm * kKpcCm) * std::pow(kCKms, -double(par->n_pow));
     Species& G = c->gas;
@@ -400,7 +435,9 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
         a.dm_m = D.r0.p;
         a.gtab = c->gtab.as<const float4>();
         a.part = c->part_gas.as<double>();
-        int nb = int(std::min<int64_t>(nb_persist, ((c->gp.nitems + 7) / 8) * 8));
+        a.perm = G.perm; a.mass = gas->mass; a.mu = gas->mu; a.dt = gas->dt; a.dt_default = par->dt;
+        a.m_chi = par->m_chi_g; a.sig_kpc2_cn = sig_kpc2_cn; a.dp = out->dp_gas; a.de = out->de_gas;
+        int nb = int(std::min<int64_t>(persist((const void*)k_pass_gas<Real, N, kExact>), ((c->gp.nitems + 7) / 8) * 8));
         {
             Phase ph(c, DMB_PH_PASS_GAS);
             hipLaunchKernelGGL((k_pass_gas<Real, N, kExact>), dim3(nb), dim3(64), 0, c->stream, a);
@@ -417,6 +454,7 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
     if (c->dp.nitems > 0) {
         ENSURE(c, c->part_p, size_t(c->dp.nitems) * kTile * 8);
         ENSURE(c, c->part_pm, size_t(c->dp.nitems) * kTile * 4);
+        ENSURE(c, c->part_nb, size_t(c->dp.nitems) * kTile);
         ENSURE(c, c->psum_own, size_t(D.n_own) * 8);
         ENSURE(c, c->slist, size_t(D.n_own) * 4);
         DmPassArgs a;
@@ -428,8 +466,10 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
         a.vs = G.r0.p; a.K = G.r5.p; a.crit = G.r6.p; a.gas_perm = G.perm;
         a.gtab = c->gtab.as<const float4>();
         a.k0 = k0; a.k1 = k1; a.step = par->step; a.box = par->box_id;
-        a.part_p = c->part_p.as<double>(); a.part_pm = c->part_pm.as<float>();
-        int nb = int(std::min<int64_t>(nb_persist, ((c->dp.nitems + 7) / 8) * 8));
+        a.part_p = c->part_p.as<double>(); a.part_pm = c->part_pm.as<float>(); a.part_nb = c->part_nb.as<uint8_t>();
+        a.psum_own = c->psum_own.as<double>(); a.psum = out->p_sum; a.pmax = out->p_max;
+        a.scount = scount; a.slist = c->slist.as<uint32_t>();
+        int nb = int(std::min<int64_t>(persist((const void*)k_pass_dm<Real, N, kExact>), ((c->dp.nitems + 7) / 8) * 8));
         {
             Phase ph(c, DMB_PH_PASS_DM);
             hipLaunchKernelGGL((k_pass_dm<Real, N, kExact>), dim3(nb), dim3(64), 0, c->stream, a);
@@ -437,7 +477,7 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
         DmCombineArgs cb;
         cb.n_own = D.n_own; cb.own = D.own.as<const uint32_t>(); cb.perm = D.perm;
         cb.item_off = c->dp.ioff.as<const uint32_t>(); cb.part_p = c->part_p.as<const double>();
-        cb.part_pm = c->part_pm.as<const float>(); cb.k0 = k0; cb.k1 = k1; cb.step = par->step; cb.box = par->box_id;
+        cb.part_pm = c->part_pm.as<const float>(); cb.part_nb = c->part_nb.as<const uint8_t>(); cb.k0 = k0; cb.k1 = k1; cb.step = par->step; cb.box = par->box_id;
         cb.psum_own = c->psum_own.as<double>(); cb.psum = out->p_sum; cb.pmax = out->p_max;
         cb.scount = scount; cb.slist = c->slist.as<uint32_t>(); cb.counters = counters;
         {
@@ -456,7 +496,7 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
         r.scount = scount; r.slist = c->slist.as<const uint32_t>();
         r.dv = out->dv_dm; r.partner = out->partner; r.counters = counters;
         Phase ph(c, DMB_PH_RESOLVE);
-        hipLaunchKernelGGL((k_resolve<Real, N, kExact>), dim3(std::max(8, c->num_cu * 4)), dim3(64), 0, c->stream, r);
+        hipLaunchKernelGGL((k_resolve<Real, N, kExact>), dim3(std::max(8, c->num_cu * 2)), dim3(kResolveThreads), 0, c->stream, r);
     }
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
@@ -478,6 +518,10 @@ dmb_status dispatch_n(dmb_ctx* c, const dmb_particles* gas, const dmb_particles*
 }  // namespace
 
 // ===========================================================================
+namespace {
+char g_create_err[256] = "no error";   // message of the last failed dmb_create (no context exists then)
+}
+
 extern "C" {
 
 dmb_status dmb_create(dmb_ctx** out, int device, void* hip_stream)
@@ -488,7 +532,9 @@ dmb_status dmb_create(dmb_ctx** out, int device, void* hip_stream)
     if (!c) return DMB_ENOMEM;
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    if (hipSetDevice(device) != hipSuccess) {
+    hipError_t he = hipSetDevice(device);
+    if (he != hipSuccess) {
+        snprintf(g_create_err, sizeof(g_create_err), "hipSetDevice(%d): %s", device, hipGetErrorString(he));
         delete c;
         return DMB_EHIP;
     }
@@ -497,12 +543,16 @@ dmb_status dmb_create(dmb_ctx** out, int device, void* hip_stream)
         c->num_cu = ncu;
     size_t tb = size_t(kTabND + 1) * (kTabNE + 1) * sizeof(float4);
     if (ensure(c, c->gtab, tb) != DMB_OK || ensure(c, c->boxL, 4 * sizeof(double)) != DMB_OK) {
+        snprintf(g_create_err, sizeof(g_create_err), "%s", c->err);
         dmb_destroy(c);
         return DMB_ENOMEM;
     }
     hipLaunchKernelGGL(k_gtab_build, dim3(blocks_for(int64_t(kTabND + 1) * (kTabNE + 1), 256)), dim3(256), 0,
                        c->stream, c->gtab.as<float4>());
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+    he = hipGetLastError();
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) {
+        snprintf(g_create_err, sizeof(g_create_err), "overlap table build: %s", hipGetErrorString(he));
         dmb_destroy(c);
         return DMB_EHIP;
     }
@@ -519,8 +569,9 @@ dmb_status dmb_destroy(dmb_ctx* c)
     auto fr = [](DevBuf& b) { if (b.p) hipFree(b.p); b.p = nullptr; b.cap = 0; };
     for (Species* S : {&c->gas, &c->dm}) {
         DevBuf* all[] = {&S->keys, &S->keys2, &S->vals, &S->vals2, &S->sx, &S->sy, &S->sz, &S->sh, &S->flag,
-                         &S->flag_off, &S->own, &S->tbox, &S->th, &S->sbox, &S->shh, &S->obox, &S->oh, &S->cube,
-                         &S->v0, &S->v1, &S->v2, &S->r0, &S->r1, &S->r2, &S->r3, &S->r4, &S->r5, &S->r6};
+                         &S->flag_off, &S->own, &S->tbox, &S->th, &S->sbox, &S->shh, &S->mbox, &S->mhh, &S->obox, &S->oh, &S->cube,
+                         &S->v0, &S->v1, &S->v2, &S->r0, &S->r1, &S->r2, &S->r3, &S->r4, &S->r5, &S->r6,
+                         &S->sub_ccnt, &S->sub_coff, &S->sub_start, &S->sub_cnt};
         for (DevBuf* b : all) fr(*b);
     }
     for (Pairs* P : {&c->gp, &c->dp}) {
@@ -530,7 +581,7 @@ dmb_status dmb_destroy(dmb_ctx* c)
     for (auto& b : c->scan_tmp) fr(b);
     for (auto& p : c->pending) { c->ev_pool.push_back(p.a); c->ev_pool.push_back(p.b); }
     for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
-    DevBuf* rest[] = {&c->gtab, &c->sort_table, &c->bbox_part, &c->boxL, &c->part_gas, &c->part_p, &c->part_pm,
+    DevBuf* rest[] = {&c->gtab, &c->sort_table, &c->bbox_part, &c->boxL, &c->part_gas, &c->part_p, &c->part_pm, &c->part_nb,
                       &c->psum_own, &c->qctr, &c->slist, &c->counters_local};
     for (DevBuf* b : rest) fr(*b);
     delete c;
@@ -544,7 +595,7 @@ dmb_status dmb_set_stream(dmb_ctx* c, void* hip_stream)
     return DMB_OK;
 }
 
-const char* dmb_last_error(const dmb_ctx* c) { return c ? c->err : "null context"; }
+const char* dmb_last_error(const dmb_ctx* c) { return c ? c->err : g_create_err; }
 
 dmb_status dmb_build_stats(const dmb_ctx* c, int64_t* o)
 {
@@ -601,15 +652,21 @@ dmb_status dmb_build_cells(dmb_ctx* c, const dmb_particles* gas, const dmb_parti
     HIPCHK(c, hipMemcpyAsync(c->boxL.p, Lh, sizeof(Lh), hipMemcpyHostToDevice, c->stream));
     if ((s = build_species(c, c->gas, gas)) != DMB_OK) return s;
     if ((s = build_species(c, c->dm, dm)) != DMB_OK) return s;
-    // read back owner counts and the largest h (for the periodic range check)
-    uint32_t nown[2] = {0, 0};
-    if (c->gas.n > 0)
-        HIPCHK(c, hipMemcpyAsync(&nown[0], c->gas.flag_off.as<uint32_t>() + c->gas.n, 4, hipMemcpyDeviceToHost, c->stream));
-    if (c->dm.n > 0)
-        HIPCHK(c, hipMemcpyAsync(&nown[1], c->dm.flag_off.as<uint32_t>() + c->dm.n, 4, hipMemcpyDeviceToHost, c->stream));
+    // read back owner and sub-tile counts
+    uint32_t nown[2] = {0, 0}, nsub[2] = {0, 0};
+    for (int sp = 0; sp < 2; ++sp) {
+        Species& S = sp == 0 ? c->gas : c->dm;
+        if (S.n == 0) continue;
+        HIPCHK(c, hipMemcpyAsync(&nown[sp], S.flag_off.as<uint32_t>() + S.n, 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(&nsub[sp], S.sub_coff.as<uint32_t>() + S.nchunk, 4, hipMemcpyDeviceToHost, c->stream));
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->gas.n_own = nown[0];
     c->dm.n_own = nown[1];
+    c->gas.ntile = nsub[0];
+    c->dm.ntile = nsub[1];
+    if ((s = build_subtiles(c, c->gas)) != DMB_OK) return s;
+    if ((s = build_subtiles(c, c->dm)) != DMB_OK) return s;
     if ((s = build_owner_tiles(c, c->gas)) != DMB_OK) return s;
     if ((s = build_owner_tiles(c, c->dm)) != DMB_OK) return s;
     if ((s = cand_count(c, c->gas, c->dm, c->gp)) != DMB_OK) return s;

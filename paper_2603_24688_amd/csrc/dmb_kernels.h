@@ -204,6 +204,78 @@ __global__ __launch_bounds__(64) void k_super_bounds(int64_t ntile, const double
     }
 }
 
+// Sub-tiles of the "other" role: each chunk of 64 Morton-consecutive
+// particles is cut wherever two neighbours in the order differ at a Morton
+// level coarser than the chunk's median neighbour level minus one, so that a
+// chunk straddling a coarse cell boundary becomes several compact boxes.
+// count mode: cnt[c] = number of sub-tiles of chunk c; write mode: starts and
+// counts of the sub-tiles at off[c]...  `lo_bit` masks key bits the sort did
+// not order.
+template <bool WRITE>
+__global__ __launch_bounds__(64) void k_subtile_split(const uint64_t* __restrict__ keys, int64_t n, int lo_bit,
+                                                      uint32_t* __restrict__ cnt, const uint32_t* __restrict__ off,
+                                                      uint32_t* __restrict__ sub_start, uint32_t* __restrict__ sub_cnt)
+{
+    const int lane = lane_id();
+    const int64_t c = blockIdx.x;
+    const int64_t k = c * kTile + lane;
+    const bool valid = k < n;
+    const int m = int(min<int64_t>(kTile, n - c * kTile));
+    const uint64_t key = valid ? (keys[k] >> lo_bit) : 0ull;
+    const uint64_t prev = __shfl_up(key, 1);
+    int lvl = 22;
+    if (valid && lane > 0) {
+        uint64_t x = (prev ^ key) << lo_bit;       // differing sorted bits, in place
+        lvl = x == 0ull ? 21 : (__clzll((long long)x) - 1) / 3;
+    }
+    // median neighbour level over lanes 1..m-1
+    int med = 0;
+    const int need = m / 2;
+    for (int t = 21; t >= 0; --t) {
+        int cntt = __popcll(__ballot(valid && lane > 0 && lvl >= t));
+        if (cntt >= need) { med = t; break; }
+    }
+    const bool cut = valid && (lane == 0 || lvl < med - 1);
+    const uint64_t cm = __ballot(cut);
+    if (!WRITE) {
+        if (lane == 0) cnt[c] = uint32_t(__popcll(cm));
+        return;
+    }
+    if (cut) {
+        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        const uint32_t idx = off[c] + uint32_t(__popcll(cm & lt));
+        const uint64_t above = lane == 63 ? 0ull : (cm >> (lane + 1));
+        const int next = above ? lane + __ffsll((unsigned long long)above) : m;
+        sub_start[idx] = uint32_t(k);
+        sub_cnt[idx] = uint32_t(next - lane);
+    }
+}
+
+// Bounds of ranges [start, start + count) of the sorted arrays (count <= 64).
+__global__ __launch_bounds__(64) void k_range_bounds(const uint32_t* __restrict__ start, const uint32_t* __restrict__ count,
+                                                     const double* __restrict__ sx, const double* __restrict__ sy,
+                                                     const double* __restrict__ sz, const double* __restrict__ sh,
+                                                     double* __restrict__ box, double* __restrict__ hmax)
+{
+    const int64_t t = blockIdx.x;
+    const int lane = lane_id();
+    const bool v = lane < int(count[t]);
+    const int64_t p = int64_t(start[t]) + lane;
+    double x = v ? sx[p] : 1e300, y = v ? sy[p] : 1e300, z = v ? sz[p] : 1e300;
+    double X = v ? sx[p] : -1e300, Y = v ? sy[p] : -1e300, Z = v ? sz[p] : -1e300;
+    double hh = v ? sh[p] : 0.0;
+    for (int d = 32; d >= 1; d >>= 1) {
+        x = fmin(x, __shfl_xor(x, d)); y = fmin(y, __shfl_xor(y, d)); z = fmin(z, __shfl_xor(z, d));
+        X = fmax(X, __shfl_xor(X, d)); Y = fmax(Y, __shfl_xor(Y, d)); Z = fmax(Z, __shfl_xor(Z, d));
+        hh = fmax(hh, __shfl_xor(hh, d));
+    }
+    if (lane == 0) {
+        box[6 * t + 0] = x; box[6 * t + 1] = y; box[6 * t + 2] = z;
+        box[6 * t + 3] = X; box[6 * t + 4] = Y; box[6 * t + 5] = Z;
+        hmax[t] = hh;
+    }
+}
+
 // Squared gap between two boxes (minimum over periodic images).
 __device__ __forceinline__ double box_gap2(const double* A, const double* B, const double* L)
 {
@@ -226,14 +298,16 @@ __device__ __forceinline__ bool boxes_near(const double* A, double ha, const dou
     return box_gap2(A, B, L) < reach * reach;
 }
 
-// Candidate other-tiles of each owner tile (two-level culling through the
-// super-tiles).  count mode: cnt[t] = number of candidates; write mode:
-// cand[off[t] + k] in super-tile then tile order.
+// Candidate other sub-tiles of each owner tile, culled through three levels
+// of boxes (64 super-tiles per mega-tile, 64 sub-tiles per super-tile).
+// count mode: cnt[t] = number of candidates; write mode: cand[off[t] + k] in
+// mega, super, sub-tile order.
 struct CandArgs {
-    int64_t nown_tile, ntile, nsuper;
+    int64_t nown_tile, ntile, nsuper, nmega;
     const double* obox; const double* oh;
     const double* tbox; const double* th;
     const double* sbox; const double* shh;
+    const double* mbox; const double* mhh;
     double L[3];
     uint32_t* cnt;
     const uint32_t* off;
@@ -243,28 +317,33 @@ struct CandArgs {
 template <bool WRITE>
 __global__ __launch_bounds__(64) void k_cand(CandArgs a)
 {
-    int64_t t = blockIdx.x;
-    int lane = lane_id();
+    const int64_t t = blockIdx.x;
+    const int lane = lane_id();
     double A[6];
     for (int k = 0; k < 6; ++k) A[k] = a.obox[6 * t + k];
-    double ha = a.oh[t];
+    const double ha = a.oh[t];
     uint32_t count = 0;
-    uint32_t base = WRITE ? a.off[t] : 0u;
+    const uint32_t base = WRITE ? a.off[t] : 0u;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    for (int64_t s0 = 0; s0 < a.nsuper; s0 += 64) {
-        int64_t s = s0 + lane;
-        bool hit = false;
-        if (s < a.nsuper) hit = boxes_near(A, ha, a.sbox + 6 * s, a.shh[s], a.L);
-        uint64_t bal = __ballot(hit);
-        while (bal) {
-            int b = __ffsll((unsigned long long)bal) - 1;
-            bal &= bal - 1;
-            int64_t tt = (s0 + b) * kTile + lane;
-            bool h2 = false;
-            if (tt < a.ntile) h2 = boxes_near(A, ha, a.tbox + 6 * tt, a.th[tt], a.L);
-            uint64_t b2 = __ballot(h2);
-            if (WRITE && h2) a.cand[base + count + uint32_t(__popcll(b2 & lt))] = uint32_t(tt);
-            count += uint32_t(__popcll(b2));
+    for (int64_t m0 = 0; m0 < a.nmega; m0 += 64) {
+        const int64_t mg = m0 + lane;
+        const bool hm = mg < a.nmega && boxes_near(A, ha, a.mbox + 6 * mg, a.mhh[mg], a.L);
+        uint64_t bm = __ballot(hm);
+        while (bm) {
+            const int64_t mi = m0 + __ffsll((unsigned long long)bm) - 1;
+            bm &= bm - 1;
+            const int64_t sg = mi * kTile + lane;
+            const bool hs = sg < a.nsuper && boxes_near(A, ha, a.sbox + 6 * sg, a.shh[sg], a.L);
+            uint64_t bs = __ballot(hs);
+            while (bs) {
+                const int64_t si = mi * kTile + __ffsll((unsigned long long)bs) - 1;
+                bs &= bs - 1;
+                const int64_t tt = si * kTile + lane;
+                const bool h2 = tt < a.ntile && boxes_near(A, ha, a.tbox + 6 * tt, a.th[tt], a.L);
+                const uint64_t b2 = __ballot(h2);
+                if (WRITE && h2) a.cand[base + count + uint32_t(__popcll(b2 & lt))] = uint32_t(tt);
+                count += uint32_t(__popcll(b2));
+            }
         }
     }
     if (!WRITE && lane == 0) a.cnt[t] = count;
@@ -385,13 +464,25 @@ __global__ __launch_bounds__(256) void k_fill_out(int64_t n_gas, int64_t n_dm, d
 }
 
 // ---------------------------------------------------------------------------
-// Pair passes.  One wavefront per block owns a tile of 64 owners (lane = owner)
-// and walks its candidate tiles.  For each candidate tile the owners test the
-// 64 others from LDS, push hits into an owner-major queue, and the wave then
-// evaluates the queue 64 pairs at a time (lane = pair).  Each owner's terms
-// form a contiguous segment of the queue; a segmented suffix sum over lanes
-// (wavefront shuffles) leaves the segment total on its first lane, which the
-// owner lane pulls.  No atomics touch physical quantities.
+// Pair passes.  One wavefront per block owns a tile of 64 owners (lane =
+// owner) and walks its candidate sub-tiles of the other species in groups of
+// kGroup.  Test phase: the group's positions and h are staged in LDS as
+// binary32 offsets from the owner tile's centre, and every owner lane tests
+// them with a conservative binary32 test (margin kTestMargin), building one
+// 64-bit hit mask per sub-tile.  Evaluate phase: the group's hits, ordered
+// owner-major, are decoded 64 at a time (lane = pair); each lane repeats the
+// test exactly in binary64, evaluates the pair and the owner's terms form a
+// contiguous run of lanes, so a segmented suffix sum over lanes (wavefront
+// shuffles) leaves each run's total on its first lane, which the owner lane
+// pulls.  No atomics touch physical quantities.
+constexpr int kGroup = 4;
+constexpr float kTestMargin = 1.0f + 4e-6f;
+// Slack of the expanded binary32 test |a-b|^2 - (ha+hb)^2 = A + B - 2 (a.b + ha hb)
+// with A = |a|^2 - ha^2, B = |b|^2 - hb^2: its rounding error is below
+// 8 eps32 (|a|^2 + ha^2 + |b|^2 + hb^2); subtracting kTestSlack times that sum
+// makes the test accept every pair that is inside in exact arithmetic.
+constexpr float kTestSlack = 2e-6f;
+
 struct PassGeom {
     const uint32_t* own;          // owner slot -> sorted position (owner species)
     int64_t n_own;
@@ -399,9 +490,11 @@ struct PassGeom {
     const double* obox;           // owner tile boxes
     const double* tx; const double* ty; const double* tz; const double* th;   // other sorted pos/h
     int64_t n_other;
-    const double* tbox;           // other tile boxes
-    const uint32_t* cand;         // candidate other tiles
+    const double* tbox;           // other sub-tile boxes
+    const uint32_t* sub_start; const uint32_t* sub_cnt;                       // other sub-tiles
+    const uint32_t* cand;         // candidate other sub-tiles
     const uint32_t* it_tile; const uint32_t* it_cb; const uint32_t* it_ce;
+    const uint32_t* item_off;     // [owner tiles + 1] item ranges per owner tile
     int64_t n_items;
     uint32_t* queue_ctr;          // [kXcd] work counters
     double L[3];
@@ -427,9 +520,10 @@ __device__ __forceinline__ void tile_pair_shift(const double* A, const double* B
 }
 
 __device__ __forceinline__ double min_image(double d, double L) { return L > 0.0 ? d - L * rint(d / L) : d; }
+__device__ __forceinline__ float min_image_f(float d, float L) { return L > 0.f ? d - L * rintf(d / L) : d; }
 
-// d^2 of owner (x) and other (p, already shifted); explicit evaluation order
-// shared by every pass.
+// d^2 of owner (a) and other (b, already shifted); explicit evaluation order
+// shared by every pass and by the resolve.
 __device__ __forceinline__ double pair_d2(double ax, double ay, double az, double bx, double by, double bz,
                                           bool clean, const double* L)
 {
@@ -438,17 +532,24 @@ __device__ __forceinline__ double pair_d2(double ax, double ay, double az, doubl
     return fma(dx, dx, fma(dy, dy, dz * dz));
 }
 
+// Work items are dealt to the 8 XCDs in chunks of kXcdChunk consecutive
+// items (XCD x takes chunks x, x+8, ...), so neighbouring items share an L2
+// while every XCD samples the whole domain; within an XCD, blocks take the
+// next item from an atomic counter.
+constexpr int kXcdChunk = 32;
+
 __device__ __forceinline__ bool item_next(uint32_t* queue_ctr, int64_t n_items, int64_t* it)
 {
-    // XCD-aware: blocks of XCD x take items from the x-th contiguous range.
     __shared__ int64_t s_it;
-    int x = blockIdx.x % kXcd;
-    int64_t lo = n_items * x / kXcd, hi = n_items * (x + 1) / kXcd;
-    if (threadIdx.x == 0) s_it = lo + int64_t(atomicAdd(&queue_ctr[x], 1u));
+    const int x = blockIdx.x % kXcd;
+    if (threadIdx.x == 0) {
+        const int64_t k = int64_t(atomicAdd(&queue_ctr[x], 1u));
+        s_it = (k / kXcdChunk) * (int64_t(kXcd) * kXcdChunk) + int64_t(x) * kXcdChunk + (k % kXcdChunk);
+    }
     __syncthreads();
     *it = s_it;
     __syncthreads();
-    return *it < hi;
+    return *it < n_items;
 }
 
 template <typename T>
@@ -473,6 +574,119 @@ __device__ __forceinline__ T seg_max(T v, int lane, int seg_end)
     return v;
 }
 
+// Index of the r-th set bit (r < popcount(m)).
+__device__ __forceinline__ int select_bit(uint64_t m, int r)
+{
+    uint32_t w = uint32_t(m);
+    int base = 0;
+    int c = __popc(w);
+    if (r >= c) { r -= c; w = uint32_t(m >> 32); base = 32; }
+    c = __popc(w & 0xFFFFu); if (r >= c) { r -= c; w >>= 16; base += 16; }
+    c = __popc(w & 0xFFu);   if (r >= c) { r -= c; w >>= 8; base += 8; }
+    c = __popc(w & 0xFu);    if (r >= c) { r -= c; w >>= 4; base += 4; }
+    c = __popc(w & 0x3u);    if (r >= c) { r -= c; w >>= 2; base += 2; }
+    c = int(w & 1u);         if (r >= c) { base += 1; }
+    return base;
+}
+
+// LDS state of one group of candidate sub-tiles.
+struct GroupLds {
+    float4 t[kGroup][64];         // binary32 offsets from the owner-tile centre (x, y, z) and h
+    float tb[kGroup][64];         // |p|^2 - h^2 - kTestSlack (|p|^2 + h^2)
+    double sh[kGroup][3];         // periodic image shift of each sub-tile
+    int base[kGroup], cnt[kGroup], clean[kGroup];
+    uint64_t mask[64][kGroup];    // hit masks per owner lane
+    int pref[64][kGroup + 1];     // owner's running hit count before each sub-tile
+    int offs[65];                 // owner-major offsets of the group's hits
+    int ng;
+};
+
+// Stage up to kGroup candidate sub-tiles [c, c+ng) and build the owner-major
+// hit layout.  Returns the group's hit count (wave-uniform).
+__device__ __forceinline__ int group_test(GroupLds& S, const PassGeom& G, const double* A, const double cen[3],
+                                          uint32_t c, int ng, bool ov, float fx, float fy, float fz, float fh,
+                                          const float Lf[3])
+{
+    const int lane = lane_id();
+    __syncthreads();
+    for (int g = 0; g < ng; ++g) {
+        const uint32_t ot = G.cand[c + g];
+        const int base = int(G.sub_start[ot]), cnt = int(G.sub_cnt[ot]);
+        double sh[3];
+        bool clean;
+        tile_pair_shift(A, G.tbox + 6 * int64_t(ot), G.L, sh, &clean);
+        if (lane < cnt) {
+            const int64_t k = int64_t(base) + lane;
+            const float4 q = make_float4(float(G.tx[k] + sh[0] - cen[0]), float(G.ty[k] + sh[1] - cen[1]),
+                                         float(G.tz[k] + sh[2] - cen[2]), float(G.th[k]));
+            const float p2 = q.x * q.x + q.y * q.y + q.z * q.z, h2 = q.w * q.w;
+            S.t[g][lane] = q;
+            S.tb[g][lane] = (p2 - h2) - kTestSlack * (p2 + h2);
+        }
+        if (lane == 0) {
+            S.base[g] = base; S.cnt[g] = cnt; S.clean[g] = clean ? 1 : 0;
+            S.sh[g][0] = sh[0]; S.sh[g][1] = sh[1]; S.sh[g][2] = sh[2];
+        }
+    }
+    if (lane == 0) S.ng = ng;
+    __syncthreads();
+    int tot = 0;
+    S.pref[lane][0] = 0;
+    const float ap2 = fx * fx + fy * fy + fz * fz, ah2 = fh * fh;
+    const float A2 = (ap2 - ah2) - kTestSlack * (ap2 + ah2);
+    const float mx2 = -2.f * fx, my2 = -2.f * fy, mz2 = -2.f * fz, mh2 = -2.f * fh;
+    for (int g = 0; g < ng; ++g) {
+        uint64_t m = 0ull;
+        const int cnt = S.cnt[g];
+        if (ov) {
+            if (S.clean[g]) {
+                uint32_t mlo = 0u, mhi = 0u;
+                for (int k = 0; k < cnt; ++k) {
+                    const float4 q = S.t[g][k];
+                    const float e = fmaf(mx2, q.x, fmaf(my2, q.y, fmaf(mz2, q.z, fmaf(mh2, q.w, A2 + S.tb[g][k]))));
+                    if (k < 32) mlo |= (e < 0.f ? 1u : 0u) << k;
+                    else mhi |= (e < 0.f ? 1u : 0u) << (k - 32);
+                }
+                m = (uint64_t(mhi) << 32) | mlo;
+            } else {
+                for (int k = 0; k < cnt; ++k) {
+                    const float4 q = S.t[g][k];
+                    const float dx = min_image_f(fx - q.x, Lf[0]), dy = min_image_f(fy - q.y, Lf[1]),
+                                dz = min_image_f(fz - q.z, Lf[2]), hs = fh + q.w;
+                    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    if (d2 < hs * hs * kTestMargin) m |= 1ull << k;
+                }
+            }
+        }
+        S.mask[lane][g] = m;
+        tot += __popcll(m);
+        S.pref[lane][g + 1] = tot;
+    }
+    const int incl = wave_incl_scan(tot);
+    S.offs[lane] = incl - tot;
+    const int H = __shfl(incl, 63);
+    if (lane == 63) S.offs[64] = H;
+    __syncthreads();
+    return H;
+}
+
+// Decode hit `pos` of the group: owner lane o, sub-tile g, particle k.
+__device__ __forceinline__ void group_decode(const GroupLds& S, int pos, int* o_out, int* g_out, int* k_out)
+{
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1)
+        if (S.offs[lo + step] <= pos) lo += step;
+    const int o = lo;
+    int r = pos - S.offs[o];
+    int g = 0;
+    while (g + 1 < S.ng && S.pref[o][g + 1] <= r) ++g;
+    r -= S.pref[o][g];
+    *o_out = o;
+    *g_out = g;
+    *k_out = select_bit(S.mask[o][g], r);
+}
+
 // ---------------------------------------------------------------------------
 // Gas (mean-field) pass: owners = active gas, others = DM.
 struct GasPassArgs {
@@ -483,17 +697,30 @@ struct GasPassArgs {
     const void* dm_m;
     const float4* gtab;
     double* part;                 // [n_items][64][4]
+    // direct output for owner tiles with a single work item
+    const uint32_t* perm;         // gas sorted pos -> index
+    const double* mass; const double* mu; const double* dt;
+    double dt_default, m_chi, sig_kpc2_cn;
+    double* dp; double* de;
 };
+
+__device__ __forceinline__ void gas_write_out(const GasPassArgs& a, uint32_t o, const double acc[4])
+{
+    double mu = a.mu ? a.mu[o] : kMpG;
+    double dtj = a.dt ? a.dt[o] : a.dt_default;
+    double sc = a.mass[o] * dtj * kMsunG / (a.m_chi + mu) * a.sig_kpc2_cn;
+    a.dp[3 * int64_t(o)] = sc * acc[0];
+    a.dp[3 * int64_t(o) + 1] = sc * acc[1];
+    a.dp[3 * int64_t(o) + 2] = sc * acc[2];
+    a.de[o] = sc * acc[3];
+}
 
 template <typename Real, int N, bool EXACT_G>
 __global__ __launch_bounds__(64) void k_pass_gas(GasPassArgs a)
 {
-    __shared__ double s_x[64], s_y[64], s_z[64], s_h[64], s_vx[64], s_vy[64], s_vz[64];
-    __shared__ Real s_m[64];
+    __shared__ GroupLds S;
     __shared__ double o_x[64], o_y[64], o_z[64], o_h[64], o_Vx[64], o_Vy[64], o_Vz[64];
     __shared__ Real o_i2[64], o_a[64], o_b[64], o_r[64];
-    __shared__ uint16_t q[64 * 32];
-    __shared__ int offs[65];
     const PassGeom& G = a.g;
     const int lane = lane_id();
     const Real* inv2s2 = reinterpret_cast<const Real*>(a.inv2s2);
@@ -501,16 +728,18 @@ __global__ __launch_bounds__(64) void k_pass_gas(GasPassArgs a)
     const Real* rb = reinterpret_cast<const Real*>(a.rb);
     const Real* rr = reinterpret_cast<const Real*>(a.rr);
     const Real* dm_m = reinterpret_cast<const Real*>(a.dm_m);
+    const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
     int64_t it;
     uint64_t npairs = 0;
     while (item_next(G.queue_ctr, G.n_items, &it)) {
-        const int64_t t = a.g.it_tile[it];
+        const int64_t t = G.it_tile[it];
         const uint32_t cb = G.it_cb[it], ce = G.it_ce[it];
         const int64_t slot = t * kTile + lane;
         const bool ov = slot < G.n_own;
         const int64_t sp = ov ? int64_t(G.own[slot]) : 0;
-        double mx = ov ? G.ox[sp] : 0.0, my = ov ? G.oy[sp] : 0.0, mz = ov ? G.oz[sp] : 0.0;
-        double mh = ov ? G.oh[sp] : 0.0;
+        const double mx = ov ? G.ox[sp] : 0.0, my = ov ? G.oy[sp] : 0.0, mz = ov ? G.oz[sp] : 0.0;
+        const double mh = ov ? G.oh[sp] : 0.0;
+        __syncthreads();
         o_x[lane] = mx; o_y[lane] = my; o_z[lane] = mz; o_h[lane] = mh;
         o_Vx[lane] = ov ? a.Vx[sp] : 0.0; o_Vy[lane] = ov ? a.Vy[sp] : 0.0; o_Vz[lane] = ov ? a.Vz[sp] : 0.0;
         o_i2[lane] = ov ? inv2s2[sp] : Real(0);
@@ -519,66 +748,38 @@ __global__ __launch_bounds__(64) void k_pass_gas(GasPassArgs a)
         o_r[lane] = ov ? rr[sp] : Real(0);
         double A[6];
         for (int k = 0; k < 6; ++k) A[k] = G.obox[6 * t + k];
+        const double cen[3] = {0.5 * (A[0] + A[3]), 0.5 * (A[1] + A[4]), 0.5 * (A[2] + A[5])};
+        const float fx = float(mx - cen[0]), fy = float(my - cen[1]), fz = float(mz - cen[2]), fh = float(mh);
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-        for (uint32_t c = cb; c < ce; ++c) {
-            const int64_t ot = G.cand[c];
-            const int64_t obase = ot * kTile;
-            const int ocnt = int(min<int64_t>(kTile, G.n_other - obase));
-            double sh[3];
-            bool clean;
-            tile_pair_shift(A, G.tbox + 6 * ot, G.L, sh, &clean);
-            __syncthreads();
-            if (lane < ocnt) {
-                int64_t k = obase + lane;
-                s_x[lane] = G.tx[k] + sh[0]; s_y[lane] = G.ty[k] + sh[1]; s_z[lane] = G.tz[k] + sh[2];
-                s_h[lane] = G.th[k];
-                s_vx[lane] = a.dvx[k]; s_vy[lane] = a.dvy[k]; s_vz[lane] = a.dvz[k];
-                s_m[lane] = dm_m[k];
-            }
-            __syncthreads();
-            for (int kb = 0; kb < ocnt; kb += 32) {
-                const int kn = min(32, ocnt - kb);
-                uint32_t mask = 0u;
-                if (ov) {
-                    for (int k = 0; k < kn; ++k) {
-                        double d2 = pair_d2(mx, my, mz, s_x[kb + k], s_y[kb + k], s_z[kb + k], clean, G.L);
-                        double hs = mh + s_h[kb + k];
-                        if (d2 < hs * hs) mask |= 1u << k;
-                    }
-                }
-                const int cnt = __popc(mask);
-                const int incl = wave_incl_scan(cnt);
-                const int H = __shfl(incl, 63);
-                int p = incl - cnt;
-                offs[lane] = p;
-                if (lane == 63) offs[64] = H;
-                while (mask) {
-                    int k = __ffs(mask) - 1;
-                    mask &= mask - 1u;
-                    q[p++] = uint16_t((lane << 8) | (kb + k));
-                }
-                npairs += uint64_t(cnt);
-                __syncthreads();
-                const int my_lo = offs[lane], my_hi = offs[lane + 1];
-                for (int base = 0; base < H; base += 64) {
-                    const int pp = base + lane;
-                    const bool pv = pp < H;
-                    Real c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-                    int seg_end = -1;
-                    if (pv) {
-                        const uint16_t e = q[pp];
-                        const int o = e >> 8, k = e & 255;
-                        seg_end = min(offs[o + 1], base + 64) - 1 - base;
-                        double d2 = pair_d2(o_x[o], o_y[o], o_z[o], s_x[k], s_y[k], s_z[k], clean, G.L);
-                        Real d = Real(sqrt(d2));
-                        Real g = EXACT_G ? overlap_g_exact<Real>(d, Real(s_h[k]), Real(o_h[o]))
-                                         : overlap_g_table<Real>(a.gtab, d, Real(s_h[k]), Real(o_h[o]));
-                        Real wx = Real(s_vx[k] - o_Vx[o]), wy = Real(s_vy[k] - o_Vy[o]), wz = Real(s_vz[k] - o_Vz[o]);
-                        Real w2 = wx * wx + wy * wy + wz * wz;
+        for (uint32_t c = cb; c < ce; c += kGroup) {
+            const int ng = int(min<uint32_t>(kGroup, ce - c));
+            const int H = group_test(S, G, A, cen, c, ng, ov, fx, fy, fz, fh, Lf);
+            const int my_lo = S.offs[lane], my_hi = S.offs[lane + 1];
+            for (int base = 0; base < H; base += 64) {
+                const int pp = base + lane;
+                Real c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+                int seg_end = -1;
+                if (pp < H) {
+                    int o, g, k;
+                    group_decode(S, pp, &o, &g, &k);
+                    seg_end = min(S.offs[o + 1], base + 64) - 1 - base;
+                    const int64_t q = int64_t(S.base[g]) + k;
+                    const double qx = G.tx[q] + S.sh[g][0], qy = G.ty[q] + S.sh[g][1], qz = G.tz[q] + S.sh[g][2];
+                    const double qh = G.th[q];
+                    const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.clean[g] != 0, G.L);
+                    const double hs = o_h[o] + qh;
+                    if (d2 < hs * hs) {
+                        npairs++;
+                        const Real d = Real(sqrt(d2));
+                        const Real gg = EXACT_G ? overlap_g_exact<Real>(d, Real(qh), Real(o_h[o]))
+                                                : overlap_g_table<Real>(a.gtab, d, Real(qh), Real(o_h[o]));
+                        const Real wx = Real(a.dvx[q] - o_Vx[o]), wy = Real(a.dvy[q] - o_Vy[o]),
+                                   wz = Real(a.dvz[q] - o_Vz[o]);
+                        const Real w2 = wx * wx + wy * wy + wz * wz;
                         Real FA, FB, Ar, Br;
                         const Real i2 = o_i2[o];
                         if (isinf(i2)) {  // cold gas: A = w^{n+1}, B = w^{n+3}
-                            Real wn = sqrt_real(w2);
+                            const Real wn = sqrt_real(w2);
                             Ar = pow_np1<N>(wn);
                             Br = Ar * w2;
                         } else {
@@ -586,28 +787,31 @@ __global__ __launch_bounds__(64) void k_pass_gas(GasPassArgs a)
                             Ar = o_a[o] * FA;
                             Br = o_b[o] * FB;
                         }
-                        const Real mg = s_m[k] * g;
+                        const Real mg = dm_m[q] * gg;
                         const Real mgA = mg * Ar;
                         c0 = mgA * wx; c1 = mgA * wy; c2 = mgA * wz;
                         c3 = mg * (w2 * Ar - o_r[o] * Br);
                     }
-                    c0 = seg_sum(c0, lane, seg_end);
-                    c1 = seg_sum(c1, lane, seg_end);
-                    c2 = seg_sum(c2, lane, seg_end);
-                    c3 = seg_sum(c3, lane, seg_end);
-                    const int s0 = max(my_lo, base);
-                    const bool has = s0 < my_hi && s0 < base + 64;
-                    const int src = has ? s0 - base : 0;
-                    const Real v0 = __shfl(c0, src), v1 = __shfl(c1, src), v2 = __shfl(c2, src), v3 = __shfl(c3, src);
-                    if (has) { acc0 += double(v0); acc1 += double(v1); acc2 += double(v2); acc3 += double(v3); }
                 }
-                __syncthreads();
+                c0 = seg_sum(c0, lane, seg_end);
+                c1 = seg_sum(c1, lane, seg_end);
+                c2 = seg_sum(c2, lane, seg_end);
+                c3 = seg_sum(c3, lane, seg_end);
+                const int s0 = max(my_lo, base);
+                const bool has = s0 < my_hi && s0 < base + 64;
+                const int src = has ? s0 - base : 0;
+                const Real v0 = __shfl(c0, src), v1 = __shfl(c1, src), v2 = __shfl(c2, src), v3 = __shfl(c3, src);
+                if (has) { acc0 += double(v0); acc1 += double(v1); acc2 += double(v2); acc3 += double(v3); }
             }
         }
-        double* P = a.part + (it * kTile + lane) * 4;
-        P[0] = acc0; P[1] = acc1; P[2] = acc2; P[3] = acc3;
+        const double acc[4] = {acc0, acc1, acc2, acc3};
+        if (G.item_off[t + 1] - G.item_off[t] == 1u) {
+            if (ov) gas_write_out(a, a.perm[sp], acc);
+        } else {
+            double* P = a.part + (it * kTile + lane) * 4;
+            P[0] = acc0; P[1] = acc1; P[2] = acc2; P[3] = acc3;
+        }
     }
-    // wave-total pair count
     for (int d = 32; d >= 1; d >>= 1) npairs += __shfl_xor(npairs, d);
     if (lane == 0 && npairs) atomicAdd((unsigned long long*)&G.counters[0], (unsigned long long)npairs);
 }
@@ -626,6 +830,10 @@ struct DmPassArgs {
     uint32_t k0, k1, step, box;
     double* part_p;               // [n_items][64]
     float* part_pm;               // [n_items][64]
+    uint8_t* part_nb;             // [n_items][64] near-boundary flags
+    // direct decision for owner tiles with a single work item
+    double* psum_own; double* psum; double* pmax;
+    uint32_t* scount; uint32_t* slist;
 };
 
 // P_ij for one (DM, gas) pair: one Maxwellian gas-velocity sample (Philox tag
@@ -650,134 +858,148 @@ __device__ __forceinline__ Real pair_P(double d2, double dh, double gh, double v
     return K * g * pow_np1<N>(vrel) * dt;
 }
 
-template <typename Real, int N, bool EXACT_G>
-__global__ __launch_bounds__(64) void k_pass_dm(DmPassArgs a)
+// Decision of eq. dm-update-vels for one DM owner: U_i (tag 2) against P_i;
+// scattering DM go to the resolve list.  Returns flags (scatter, P>=1,
+// non-finite, near-decision) as bits 0..3.
+__device__ __forceinline__ uint32_t dm_decide(uint32_t o, int64_t s, double P, float Pm, uint32_t step, uint32_t box,
+                                              uint32_t k0, uint32_t k1, double* psum_own, double* psum, double* pmax,
+                                              uint32_t* scount, uint32_t* slist)
 {
-    __shared__ double s_x[64], s_y[64], s_z[64], s_h[64], s_Vx[64], s_Vy[64], s_Vz[64];
-    __shared__ Real s_vs[64], s_K[64], s_cr[64];
-    __shared__ uint32_t s_id[64];
+    psum_own[s] = P;
+    if (psum) psum[o] = P;
+    if (pmax) pmax[o] = double(Pm);
+    U4 r = philox_block(o, 0xFFFFFFFFu, step, kTagDecision, box, k0, k1);
+    double U = u24<double>(r.x);
+    uint32_t f = 0;
+    if (!isfinite(P)) f |= 4u;
+    if (P >= 1.0) f |= 2u;
+    if (U < P) {
+        uint32_t idx = atomicAdd(scount, 1u);
+        slist[idx] = uint32_t(s);
+        f |= 1u;
+    } else if (fabs(P - U) <= 1e-6 * U) {
+        f |= 8u;
+    }
+    return f;
+}
+
+template <typename Real, int N, bool EXACT_G>
+__global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a)
+{
+    __shared__ GroupLds S;
     __shared__ double o_x[64], o_y[64], o_z[64], o_h[64], o_vx[64], o_vy[64], o_vz[64];
     __shared__ Real o_dt[64];
     __shared__ uint32_t o_id[64];
-    __shared__ uint16_t q[64 * 32];
-    __shared__ int offs[65];
     const PassGeom& G = a.g;
     const int lane = lane_id();
     const Real* dtr = reinterpret_cast<const Real*>(a.dtr);
     const Real* vs = reinterpret_cast<const Real*>(a.vs);
     const Real* Kp = reinterpret_cast<const Real*>(a.K);
     const Real* cr = reinterpret_cast<const Real*>(a.crit);
+    const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
     int64_t it;
-    uint64_t npairs = 0, ncrit = 0, nnear = 0;
+    uint64_t npairs = 0, ncrit = 0, nnear = 0, nscat = 0, npge1 = 0, nnonf = 0, nneard = 0;
     while (item_next(G.queue_ctr, G.n_items, &it)) {
         const int64_t t = G.it_tile[it];
         const uint32_t cb = G.it_cb[it], ce = G.it_ce[it];
         const int64_t slot = t * kTile + lane;
         const bool ov = slot < G.n_own;
         const int64_t sp = ov ? int64_t(G.own[slot]) : 0;
-        double mx = ov ? G.ox[sp] : 0.0, my = ov ? G.oy[sp] : 0.0, mz = ov ? G.oz[sp] : 0.0;
-        double mh = ov ? G.oh[sp] : 0.0;
+        const double mx = ov ? G.ox[sp] : 0.0, my = ov ? G.oy[sp] : 0.0, mz = ov ? G.oz[sp] : 0.0;
+        const double mh = ov ? G.oh[sp] : 0.0;
+        __syncthreads();
         o_x[lane] = mx; o_y[lane] = my; o_z[lane] = mz; o_h[lane] = mh;
         o_vx[lane] = ov ? a.vx[sp] : 0.0; o_vy[lane] = ov ? a.vy[sp] : 0.0; o_vz[lane] = ov ? a.vz[sp] : 0.0;
         o_dt[lane] = ov ? dtr[sp] : Real(0);
         o_id[lane] = ov ? a.dm_perm[sp] : 0u;
         double A[6];
         for (int k = 0; k < 6; ++k) A[k] = G.obox[6 * t + k];
+        const double cen[3] = {0.5 * (A[0] + A[3]), 0.5 * (A[1] + A[4]), 0.5 * (A[2] + A[5])};
+        const float fx = float(mx - cen[0]), fy = float(my - cen[1]), fz = float(mz - cen[2]), fh = float(mh);
         double accP = 0.0;
         Real accM = 0;
-        bool near_b = false;
-        for (uint32_t c = cb; c < ce; ++c) {
-            const int64_t ot = G.cand[c];
-            const int64_t obase = ot * kTile;
-            const int ocnt = int(min<int64_t>(kTile, G.n_other - obase));
-            double sh[3];
-            bool clean;
-            tile_pair_shift(A, G.tbox + 6 * ot, G.L, sh, &clean);
-            __syncthreads();
-            if (lane < ocnt) {
-                int64_t k = obase + lane;
-                s_x[lane] = G.tx[k] + sh[0]; s_y[lane] = G.ty[k] + sh[1]; s_z[lane] = G.tz[k] + sh[2];
-                s_h[lane] = G.th[k];
-                s_Vx[lane] = a.Vx[k]; s_Vy[lane] = a.Vy[k]; s_Vz[lane] = a.Vz[k];
-                s_vs[lane] = vs[k]; s_K[lane] = Kp[k]; s_cr[lane] = cr[k];
-                s_id[lane] = a.gas_perm[k];
-            }
-            __syncthreads();
-            for (int kb = 0; kb < ocnt; kb += 32) {
-                const int kn = min(32, ocnt - kb);
-                uint32_t mask = 0u;
-                if (ov) {
-                    for (int k = 0; k < kn; ++k) {
-                        double d2 = pair_d2(mx, my, mz, s_x[kb + k], s_y[kb + k], s_z[kb + k], clean, G.L);
-                        double hs = mh + s_h[kb + k];
-                        double hs2 = hs * hs;
-                        if (d2 < hs2) mask |= 1u << k;
-                        if (fabs(d2 - hs2) <= 1e-6 * hs2) near_b = true;
-                    }
-                }
-                const int cnt = __popc(mask);
-                const int incl = wave_incl_scan(cnt);
-                const int H = __shfl(incl, 63);
-                int p = incl - cnt;
-                offs[lane] = p;
-                if (lane == 63) offs[64] = H;
-                while (mask) {
-                    int k = __ffs(mask) - 1;
-                    mask &= mask - 1u;
-                    q[p++] = uint16_t((lane << 8) | (kb + k));
-                }
-                npairs += uint64_t(cnt);
-                __syncthreads();
-                const int my_lo = offs[lane], my_hi = offs[lane + 1];
-                for (int base = 0; base < H; base += 64) {
-                    const int pp = base + lane;
-                    const bool pv = pp < H;
-                    double cP = 0.0;
-                    Real cM = 0;
-                    int seg_end = -1;
-                    if (pv) {
-                        const uint16_t e = q[pp];
-                        const int o = e >> 8, k = e & 255;
-                        seg_end = min(offs[o + 1], base + 64) - 1 - base;
-                        double d2 = pair_d2(o_x[o], o_y[o], o_z[o], s_x[k], s_y[k], s_z[k], clean, G.L);
+        int accNB = 0;
+        for (uint32_t c = cb; c < ce; c += kGroup) {
+            const int ng = int(min<uint32_t>(kGroup, ce - c));
+            const int H = group_test(S, G, A, cen, c, ng, ov, fx, fy, fz, fh, Lf);
+            const int my_lo = S.offs[lane], my_hi = S.offs[lane + 1];
+            for (int base = 0; base < H; base += 64) {
+                const int pp = base + lane;
+                double cP = 0.0;
+                Real cM = 0;
+                int cNB = 0;
+                int seg_end = -1;
+                if (pp < H) {
+                    int o, g, k;
+                    group_decode(S, pp, &o, &g, &k);
+                    seg_end = min(S.offs[o + 1], base + 64) - 1 - base;
+                    const int64_t q = int64_t(S.base[g]) + k;
+                    const double qx = G.tx[q] + S.sh[g][0], qy = G.ty[q] + S.sh[g][1], qz = G.tz[q] + S.sh[g][2];
+                    const double qh = G.th[q];
+                    const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.clean[g] != 0, G.L);
+                    const double hs = o_h[o] + qh;
+                    const double hs2 = hs * hs;
+                    if (fabs(d2 - hs2) <= 1e-6 * hs2) cNB = 1;
+                    if (d2 < hs2) {
+                        npairs++;
                         Real urel[3];
-                        Real P = pair_P<Real, N, EXACT_G>(d2, o_h[o], s_h[k], o_vx[o], o_vy[o], o_vz[o], s_Vx[k],
-                                                          s_Vy[k], s_Vz[k], s_vs[k], s_K[k], o_dt[o], o_id[o],
-                                                          s_id[k], a.step, a.box, a.k0, a.k1, a.gtab, urel);
+                        const Real P = pair_P<Real, N, EXACT_G>(d2, o_h[o], qh, o_vx[o], o_vy[o], o_vz[o], a.Vx[q],
+                                                                a.Vy[q], a.Vz[q], vs[q], Kp[q], o_dt[o], o_id[o],
+                                                                a.gas_perm[q], a.step, a.box, a.k0, a.k1, a.gtab, urel);
                         cP = double(P);
                         cM = P;
-                        if (P >= s_cr[k]) ncrit++;
+                        if (P >= cr[q]) ncrit++;
                     }
-                    cP = seg_sum(cP, lane, seg_end);
-                    cM = seg_max(cM, lane, seg_end);
-                    const int s0 = max(my_lo, base);
-                    const bool has = s0 < my_hi && s0 < base + 64;
-                    const int src = has ? s0 - base : 0;
-                    const double vP = __shfl(cP, src);
-                    const Real vM = __shfl(cM, src);
-                    if (has) { accP += vP; accM = accM > vM ? accM : vM; }
                 }
-                __syncthreads();
+                cP = seg_sum(cP, lane, seg_end);
+                cM = seg_max(cM, lane, seg_end);
+                cNB = seg_max(cNB, lane, seg_end);
+                const int s0 = max(my_lo, base);
+                const bool has = s0 < my_hi && s0 < base + 64;
+                const int src = has ? s0 - base : 0;
+                const double vP = __shfl(cP, src);
+                const Real vM = __shfl(cM, src);
+                const int vNB = __shfl(cNB, src);
+                if (has) { accP += vP; accM = accM > vM ? accM : vM; accNB |= vNB; }
             }
         }
-        if (ov && near_b) nnear++;
-        a.part_p[it * kTile + lane] = accP;
-        a.part_pm[it * kTile + lane] = float(accM);
+        if (G.item_off[t + 1] - G.item_off[t] == 1u) {
+            if (ov) {
+                if (accNB) nnear++;
+                uint32_t f = dm_decide(o_id[lane], slot, accP, float(accM), a.step, a.box, a.k0, a.k1, a.psum_own,
+                                       a.psum, a.pmax, a.scount, a.slist);
+                nscat += f & 1u; npge1 += (f >> 1) & 1u; nnonf += (f >> 2) & 1u; nneard += (f >> 3) & 1u;
+            }
+        } else {
+            a.part_p[it * kTile + lane] = accP;
+            a.part_pm[it * kTile + lane] = float(accM);
+            a.part_nb[it * kTile + lane] = uint8_t(accNB);
+        }
     }
     for (int d = 32; d >= 1; d >>= 1) {
         npairs += __shfl_xor(npairs, d);
         ncrit += __shfl_xor(ncrit, d);
         nnear += __shfl_xor(nnear, d);
+        nscat += __shfl_xor(nscat, d);
+        npge1 += __shfl_xor(npge1, d);
+        nnonf += __shfl_xor(nnonf, d);
+        nneard += __shfl_xor(nneard, d);
     }
     if (lane == 0) {
         if (npairs) atomicAdd((unsigned long long*)&G.counters[1], (unsigned long long)npairs);
+        if (nscat) atomicAdd((unsigned long long*)&G.counters[2], (unsigned long long)nscat);
         if (nnear) atomicAdd((unsigned long long*)&G.counters[3], (unsigned long long)nnear);
+        if (nneard) atomicAdd((unsigned long long*)&G.counters[4], (unsigned long long)nneard);
         if (ncrit) atomicAdd((unsigned long long*)&G.counters[5], (unsigned long long)ncrit);
+        if (npge1) atomicAdd((unsigned long long*)&G.counters[6], (unsigned long long)npge1);
+        if (nnonf) atomicAdd((unsigned long long*)&G.counters[7], (unsigned long long)nnonf);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Combine partials of each owner (fixed item order) and apply owner factors.
+// Combine partials of owners whose tile was split into several work items
+// (fixed item order) and apply owner factors; single-item tiles were written
+// by the pass itself.
 struct GasCombineArgs {
     int64_t n_own;
     const uint32_t* own; const uint32_t* perm;
@@ -793,8 +1015,10 @@ __global__ __launch_bounds__(256) void k_combine_gas(GasCombineArgs a)
     int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (s >= a.n_own) return;
     int64_t t = s / kTile, l = s % kTile;
+    const uint32_t i0 = a.item_off[t], i1 = a.item_off[t + 1];
+    if (i1 - i0 <= 1u) return;
     double acc[4] = {0, 0, 0, 0};
-    for (uint32_t it = a.item_off[t]; it < a.item_off[t + 1]; ++it)
+    for (uint32_t it = i0; it < i1; ++it)
         for (int c = 0; c < 4; ++c) acc[c] += a.part[(int64_t(it) * kTile + l) * 4 + c];
     uint32_t o = a.perm[a.own[s]];
     double mu = a.mu ? a.mu[o] : kMpG;
@@ -810,7 +1034,7 @@ struct DmCombineArgs {
     int64_t n_own;
     const uint32_t* own; const uint32_t* perm;
     const uint32_t* item_off;
-    const double* part_p; const float* part_pm;
+    const double* part_p; const float* part_pm; const uint8_t* part_nb;
     uint32_t k0, k1, step, box;
     double* psum_own;             // [n_own] P_i in owner-slot order
     double* psum; double* pmax;   // outputs (nullable)
@@ -821,51 +1045,45 @@ struct DmCombineArgs {
 __global__ __launch_bounds__(256) void k_combine_dm(DmCombineArgs a)
 {
     int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    bool v = s < a.n_own;
-    uint32_t scat = 0, pge1 = 0, nonf = 0, nearD = 0;
-    if (v) {
+    uint32_t f = 0, nb = 0;
+    if (s < a.n_own) {
         int64_t t = s / kTile, l = s % kTile;
-        double P = 0.0;
-        float Pm = 0.f;
-        for (uint32_t it = a.item_off[t]; it < a.item_off[t + 1]; ++it) {
-            P += a.part_p[int64_t(it) * kTile + l];
-            Pm = fmaxf(Pm, a.part_pm[int64_t(it) * kTile + l]);
-        }
-        uint32_t o = a.perm[a.own[s]];
-        a.psum_own[s] = P;
-        if (a.psum) a.psum[o] = P;
-        if (a.pmax) a.pmax[o] = double(Pm);
-        U4 r = philox_block(o, 0xFFFFFFFFu, a.step, kTagDecision, a.box, a.k0, a.k1);
-        double U = u24<double>(r.x);
-        if (!isfinite(P)) nonf = 1;
-        if (P >= 1.0) pge1 = 1;
-        if (U < P) {
-            uint32_t idx = atomicAdd(a.scount, 1u);
-            a.slist[idx] = uint32_t(s);
-            scat = 1;
-        } else if (fabs(P - U) <= 1e-6 * U) {
-            nearD = 1;
+        const uint32_t i0 = a.item_off[t], i1 = a.item_off[t + 1];
+        if (i1 - i0 > 1u) {
+            double P = 0.0;
+            float Pm = 0.f;
+            for (uint32_t it = i0; it < i1; ++it) {
+                P += a.part_p[int64_t(it) * kTile + l];
+                Pm = fmaxf(Pm, a.part_pm[int64_t(it) * kTile + l]);
+                nb |= a.part_nb[int64_t(it) * kTile + l];
+            }
+            uint32_t o = a.perm[a.own[s]];
+            f = dm_decide(o, s, P, Pm, a.step, a.box, a.k0, a.k1, a.psum_own, a.psum, a.pmax, a.scount, a.slist);
         }
     }
-    uint64_t b0 = __ballot(scat), b1 = __ballot(pge1), b2 = __ballot(nonf), b3 = __ballot(nearD);
+    uint64_t b0 = __ballot(f & 1u), b1 = __ballot(f & 2u), b2 = __ballot(f & 4u), b3 = __ballot(f & 8u);
+    uint64_t b4 = __ballot(nb != 0);
     if (lane_id() == 0) {
         if (b0) atomicAdd((unsigned long long*)&a.counters[2], (unsigned long long)__popcll(b0));
+        if (b4) atomicAdd((unsigned long long*)&a.counters[3], (unsigned long long)__popcll(b4));
+        if (b3) atomicAdd((unsigned long long*)&a.counters[4], (unsigned long long)__popcll(b3));
         if (b1) atomicAdd((unsigned long long*)&a.counters[6], (unsigned long long)__popcll(b1));
         if (b2) atomicAdd((unsigned long long*)&a.counters[7], (unsigned long long)__popcll(b2));
-        if (b3) atomicAdd((unsigned long long*)&a.counters[4], (unsigned long long)__popcll(b3));
     }
 }
 
 // ---------------------------------------------------------------------------
 // Partner resolve for the DM that scatter (eq. dm-update-vels: one draw from
 // the mixture): the partner is the smallest gas index whose running sum of
-// P_ij exceeds U_i.  Radix select over the gas index, 8 bits per pass; each
-// pass recomputes the DM's pair probabilities (same arithmetic as the DM
-// pass) and accumulates them per digit as exact fixed-point integers
-// (P * 2^64 split into two u64 halves), so the running sums are exact sums
-// of the per-pair values and independent of accumulation order.
+// P_ij exceeds U_i.  The DM's pairs are enumerated once (candidate sub-tiles
+// first filtered by a point-to-box test) with the same arithmetic as the DM
+// pass and cached in LDS as (gas index, P_ij); a radix select over the gas
+// index, 8 bits per pass, accumulates P_ij per digit as exact fixed-point
+// integers (P * 2^64 split into two u64 halves), so the running sums are exact
+// sums of the per-pair values and do not depend on accumulation order.  DM
+// with more pairs than the cache recompute their pairs in every pass.
 struct ResolveArgs {
-    PassGeom g;                   // owners = DM, others = gas (same as the DM pass)
+    PassGeom g;                   // owners = DM, others = gas sub-tiles (as in the DM pass)
     const uint32_t* cand_off;     // [nown_tile + 1]
     const double* vx; const double* vy; const double* vz; const void* dtr; const uint32_t* dm_perm;
     const double* Vx; const double* Vy; const double* Vz; const void* vs; const void* K; const uint32_t* gas_perm;
@@ -890,18 +1108,22 @@ __device__ __forceinline__ void fixed_split(double P, unsigned long long* hi, un
     *lo = (unsigned long long)((pd - fl) * 4294967296.0);
 }
 
-constexpr int kResolveList = 2048;   // candidate tiles kept per scattering DM after the point test
+constexpr int kResolveThreads = 256;  // four wavefronts per scattering DM
+constexpr int kResolveList = 2048;    // candidate sub-tiles kept per scattering DM after the point test
+constexpr int kResolvePairs = 2048;   // pairs cached per scattering DM
 
 template <typename Real, int N, bool EXACT_G>
-__global__ __launch_bounds__(64) void k_resolve(ResolveArgs a)
+__global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
 {
     __shared__ unsigned long long hhi[256], hlo[256];
     __shared__ uint32_t s_list[kResolveList];
-    __shared__ uint32_t s_sel;
+    __shared__ uint32_t s_pre[kResolveList + 1];
+    __shared__ uint32_t s_gid[kResolvePairs];
+    __shared__ double s_P[kResolvePairs];
+    __shared__ uint32_t s_nrel, s_npairs, s_sel;
     __shared__ int s_near;
     const PassGeom& G = a.g;
-    const int lane = lane_id();
-    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int tid = threadIdx.x;
     const Real* dtr = reinterpret_cast<const Real*>(a.dtr);
     const Real* vs = reinterpret_cast<const Real*>(a.vs);
     const Real* Kp = reinterpret_cast<const Real*>(a.K);
@@ -920,63 +1142,101 @@ __global__ __launch_bounds__(64) void k_resolve(ResolveArgs a)
         double A[6];
         for (int k = 0; k < 6; ++k) A[k] = G.obox[6 * t + k];
         const uint32_t cb = a.cand_off[t], ce = a.cand_off[t + 1];
-        // Keep only the candidate tiles of the owner tile that this DM can
-        // reach (point-to-box gap < h_i + h_max of the tile); lanes test 64
-        // candidates at a time.  Falls back to the full list if it overflows.
+        if (tid == 0) { s_nrel = 0; s_npairs = 0; }
+        __syncthreads();
+        // candidate sub-tiles this DM can reach (point-to-box gap < h_i + h_max)
         const double P6[6] = {mx, my, mz, mx, my, mz};
-        uint32_t nrel = 0;
-        for (uint32_t c0 = cb; c0 < ce; c0 += 64) {
-            const uint32_t c = c0 + lane;
-            bool hit = false;
-            uint32_t ot = 0;
-            if (c < ce) {
-                ot = G.cand[c];
-                hit = boxes_near(P6, mh, G.tbox + 6 * int64_t(ot), G.th[ot], G.L);
+        for (uint32_t c = cb + tid; c < ce; c += kResolveThreads) {
+            const uint32_t ot = G.cand[c];
+            if (boxes_near(P6, mh, G.tbox + 6 * int64_t(ot), G.th[ot], G.L)) {
+                const uint32_t pos = atomicAdd(&s_nrel, 1u);
+                if (pos < uint32_t(kResolveList)) s_list[pos] = c;
             }
-            const uint64_t bal = __ballot(hit);
-            const uint32_t pos = nrel + uint32_t(__popcll(bal & lt));
-            if (hit && pos < kResolveList) s_list[pos] = c;
-            nrel += uint32_t(__popcll(bal));
         }
+        __syncthreads();
+        const uint32_t nrel = s_nrel;
         const bool use_list = nrel <= uint32_t(kResolveList);
         const uint32_t nl = use_list ? nrel : ce - cb;
+        // prefix sums of particle counts over the kept sub-tiles (one thread; nl <= kResolveList)
+        if (tid == 0 && use_list) {
+            uint32_t acc = 0;
+            for (uint32_t q = 0; q < nl; ++q) {
+                s_pre[q] = acc;
+                acc += G.sub_cnt[G.cand[s_list[q]]];
+            }
+            s_pre[nl] = acc;
+        }
         __syncthreads();
+        // Pairs of this DM, enumerated over the flattened particles of the kept
+        // sub-tiles (four wavefronts in parallel).  Without a list (too many
+        // candidates) every candidate sub-tile is walked by one wavefront.
+        auto for_pairs = [&](auto&& fn) {
+            auto visit = [&](uint32_t c, int kk) {
+                const uint32_t ot = G.cand[c];
+                double sh[3];
+                bool clean;
+                tile_pair_shift(A, G.tbox + 6 * int64_t(ot), G.L, sh, &clean);
+                if (kk < int(G.sub_cnt[ot])) {
+                    const int64_t k = int64_t(G.sub_start[ot]) + kk;
+                    const double px = G.tx[k] + sh[0], py = G.ty[k] + sh[1], pz = G.tz[k] + sh[2];
+                    const double d2 = pair_d2(mx, my, mz, px, py, pz, clean, G.L);
+                    const double hs = mh + G.th[k];
+                    if (d2 < hs * hs) {
+                        const uint32_t gid = a.gas_perm[k];
+                        Real urel[3];
+                        const double P = double(pair_P<Real, N, EXACT_G>(d2, mh, G.th[k], mvx, mvy, mvz, a.Vx[k],
+                                                                         a.Vy[k], a.Vz[k], vs[k], Kp[k], mdt, oid, gid,
+                                                                         a.step, a.box, a.k0, a.k1, a.gtab, urel));
+                        fn(gid, P);
+                    }
+                }
+            };
+            if (use_list) {
+                const uint32_t np = s_pre[nl];
+                for (uint32_t pos = tid; pos < np; pos += kResolveThreads) {
+                    uint32_t lo = 0, hi = nl;  // largest q with s_pre[q] <= pos
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (s_pre[mid] <= pos) lo = mid; else hi = mid;
+                    }
+                    visit(s_list[lo], int(pos - s_pre[lo]));
+                }
+            } else {
+                const int w = tid >> 6, lane = tid & 63;
+                for (uint32_t q = w; q < nl; q += kResolveThreads / 64) visit(cb + q, lane);
+            }
+        };
+        for_pairs([&](uint32_t gid, double P) {
+            const uint32_t pos = atomicAdd(&s_npairs, 1u);
+            if (pos < uint32_t(kResolvePairs)) { s_gid[pos] = gid; s_P[pos] = P; }
+        });
+        __syncthreads();
+        const uint32_t npairs = s_npairs;
+        const bool cached = npairs <= uint32_t(kResolvePairs);
         const int npass = (a.n_gas_bits + 7) / 8;
         uint32_t prefix = 0;
         unsigned __int128 below = 0;
         for (int ps = 0; ps < npass; ++ps) {
             const int shft = 8 * (npass - 1 - ps);
-            for (int b = lane; b < 256; b += 64) { hhi[b] = 0ull; hlo[b] = 0ull; }
+            hhi[tid & 255] = 0ull;
+            hlo[tid & 255] = 0ull;
             __syncthreads();
-            for (uint32_t q = 0; q < nl; ++q) {
-                const uint32_t c = use_list ? s_list[q] : cb + q;
-                const int64_t ot = G.cand[c];
-                const int64_t k = ot * kTile + lane;
-                double sh[3];
-                bool clean;
-                tile_pair_shift(A, G.tbox + 6 * ot, G.L, sh, &clean);
-                if (k < G.n_other) {
-                    const uint32_t gid = a.gas_perm[k];
-                    if (uint64_t(gid) >> (shft + 8) == uint64_t(prefix)) {
-                        double px = G.tx[k] + sh[0], py = G.ty[k] + sh[1], pz = G.tz[k] + sh[2];
-                        double d2 = pair_d2(mx, my, mz, px, py, pz, clean, G.L);
-                        double hs = mh + G.th[k];
-                        if (d2 < hs * hs) {
-                            Real urel[3];
-                            Real P = pair_P<Real, N, EXACT_G>(d2, mh, G.th[k], mvx, mvy, mvz, a.Vx[k], a.Vy[k], a.Vz[k],
-                                                              vs[k], Kp[k], mdt, oid, gid, a.step, a.box, a.k0, a.k1,
-                                                              a.gtab, urel);
-                            unsigned long long hi, lo;
-                            fixed_split(double(P), &hi, &lo);
-                            const int dg = (gid >> shft) & 255u;
-                            atomicAdd(&hhi[dg], hi);
-                            atomicAdd(&hlo[dg], lo);
-                        }
-                    }
+            auto add = [&](uint32_t gid, double P) {
+                if ((uint64_t(gid) >> (shft + 8)) == uint64_t(prefix)) {
+                    unsigned long long hi, lo;
+                    fixed_split(P, &hi, &lo);
+                    const int dg = (gid >> shft) & 255u;
+                    atomicAdd(&hhi[dg], hi);
+                    atomicAdd(&hlo[dg], lo);
                 }
+            };
+            if (cached) {
+                for (uint32_t q = tid; q < npairs; q += kResolveThreads) add(s_gid[q], s_P[q]);
+            } else {
+                for_pairs(add);
             }
             __syncthreads();
-            if (lane == 0) {
+            if (tid == 0) {
                 unsigned __int128 cum = below;
                 int sel = -1, last_nz = -1;
                 unsigned __int128 sel_below = below, sel_after = below;
@@ -1004,7 +1264,7 @@ __global__ __launch_bounds__(64) void k_resolve(ResolveArgs a)
             prefix = (prefix << 8) | s_sel;
             __syncthreads();
         }
-        if (lane == 0) {
+        if (tid == 0) {
             const uint32_t j = prefix < a.n_gas ? prefix : a.n_gas - 1u;
             nnearD += uint32_t(s_near);
             const double muj = a.gas_mu ? a.gas_mu[j] : kMpG;
@@ -1037,7 +1297,7 @@ __global__ __launch_bounds__(64) void k_resolve(ResolveArgs a)
         }
         __syncthreads();
     }
-    if (lane == 0 && nnearD) atomicAdd((unsigned long long*)&a.counters[4], (unsigned long long)nnearD);
+    if (tid == 0 && nnearD) atomicAdd((unsigned long long*)&a.counters[4], (unsigned long long)nnearD);
 }
 
 // ---------------------------------------------------------------------------
