@@ -51,7 +51,8 @@ typedef enum { DMB_FP64 = 0, DMB_FP32 = 1 } dmb_precision;
 
 /* How the rate integrals A, B (eq. scrA, scrB) are evaluated in the gas pass. */
 typedef enum {
-    DMB_RATES_EXACT = 0   /* closed forms of the 1F1 expressions of Appendix B (integer n) */
+    DMB_RATES_EXACT = 0,  /* closed forms of the 1F1 expressions of Appendix B (integer n) */
+    DMB_RATES_QUAD = 1    /* K-node Gauss-Legendre quadrature of the radial form of eq. scrA/scrB */
 } dmb_rates;
 
 enum {
@@ -92,6 +93,7 @@ typedef struct {
     double box[3];          /* periodic side lengths in kpc; all 0 => open boundaries */
     int32_t precision;      /* dmb_precision */
     int32_t rates;          /* dmb_rates */
+    int32_t quad_nodes;     /* K for DMB_RATES_QUAD, 4..64; 0 => 32 */
 } dmb_params;
 
 typedef struct {
@@ -141,14 +143,15 @@ dmb_status dmb_interact_step(dmb_ctx *ctx, const dmb_particles *gas, const dmb_p
 /* Device-side evaluation helpers (synchronous; device arrays of length n).
  * dmb_overlap_eval: g(d; h1, h2) of eq. dm-update-prob / Appendix D, table
  *   (DMB_FP32) or exact (DMB_FP64).
- * dmb_rates_eval: A/(sigma0 c^-n), B/(sigma0 c^-n) of Appendix B at speeds w
- *   and dispersions vs for power n.
+ * dmb_rates_eval: A/(sigma0 c^-n), B/(sigma0 c^-n) of eq. scrA/scrB at speeds
+ *   w and dispersions vs for power n, by the closed forms of Appendix B
+ *   (rates = DMB_RATES_EXACT) or by quad_nodes-point quadrature (DMB_RATES_QUAD).
  * dmb_philox_eval: Philox4x32-10 blocks for counters ctr[n][4] under key
  *   (seed lo, seed hi), written to out[n][4]. */
 dmb_status dmb_overlap_eval(dmb_ctx *ctx, int64_t n, const double *d, const double *h1, const double *h2,
                             int32_t precision, double *g_out);
 dmb_status dmb_rates_eval(dmb_ctx *ctx, int64_t n, const double *w, const double *vs, int32_t n_pow,
-                          int32_t precision, double *A_out, double *B_out);
+                          int32_t precision, int32_t rates, int32_t quad_nodes, double *A_out, double *B_out);
 dmb_status dmb_philox_eval(dmb_ctx *ctx, int64_t n, const uint32_t *ctr, uint64_t seed, uint32_t *out);
 
 /* Phase timing with HIP events recorded on the context stream around each

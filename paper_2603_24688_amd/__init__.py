@@ -15,7 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libdmb.so")
 
 DMB_FP64, DMB_FP32 = 0, 1
-DMB_RATES_EXACT = 0
+DMB_RATES_EXACT, DMB_RATES_QUAD = 0, 1
 COUNTER_NAMES = ["pairs_gas", "pairs_dm", "scatters", "near_boundary", "near_decision",
                  "crit_viol", "p_ge_1", "nonfinite"]
 N_COUNTERS = len(COUNTER_NAMES)
@@ -43,7 +43,7 @@ class Particles(C.Structure):
 class Params(C.Structure):
     _fields_ = [("sigma0_cm2", C.c_double), ("n_pow", C.c_int32), ("m_chi_g", C.c_double), ("dt", C.c_double),
                 ("seed", C.c_uint64), ("step", C.c_uint32), ("box_id", C.c_uint32), ("box", C.c_double * 3),
-                ("precision", C.c_int32), ("rates", C.c_int32)]
+                ("precision", C.c_int32), ("rates", C.c_int32), ("quad_nodes", C.c_int32)]
 
 
 class Out(C.Structure):
@@ -77,7 +77,7 @@ def load_library(path: str = LIB_PATH):
     L.dmb_interact_step.restype = C.c_int
     L.dmb_interact_step.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params), C.POINTER(Out)]
     L.dmb_overlap_eval.restype = C.c_int; L.dmb_overlap_eval.argtypes = [vp, i64, vp, vp, vp, i32, vp]
-    L.dmb_rates_eval.restype = C.c_int; L.dmb_rates_eval.argtypes = [vp, i64, vp, vp, i32, i32, vp, vp]
+    L.dmb_rates_eval.restype = C.c_int; L.dmb_rates_eval.argtypes = [vp, i64, vp, vp, i32, i32, i32, i32, vp, vp]
     L.dmb_philox_eval.restype = C.c_int; L.dmb_philox_eval.argtypes = [vp, i64, vp, u64, vp]
     L.dmb_profile_enable.restype = C.c_int; L.dmb_profile_enable.argtypes = [vp, i32]
     L.dmb_profile_read.restype = C.c_int; L.dmb_profile_read.argtypes = [vp, vp, vp, i32]
@@ -109,7 +109,8 @@ def _params(p: dict, precision: int) -> Params:
     box = p.get("box") or (0.0, 0.0, 0.0)
     return Params(float(p["sigma0_cm2"]), int(p.get("n_pow", 0)), float(p["m_chi_g"]), float(p["dt"]),
                   int(p["seed"]) & 0xFFFFFFFFFFFFFFFF, int(p.get("step", 0)) & 0xFFFFFFFF, int(p.get("box_id", 0)),
-                  (C.c_double * 3)(*[float(b) for b in box]), int(precision), int(p.get("rates", DMB_RATES_EXACT)))
+                  (C.c_double * 3)(*[float(b) for b in box]), int(precision), int(p.get("rates", DMB_RATES_EXACT)),
+                  int(p.get("quad_nodes", 0)))
 
 
 class Context:
@@ -182,11 +183,12 @@ class Context:
                     "dmb_overlap_eval")
         return g
 
-    def rates_eval(self, w, vs, n_pow: int, precision: int = DMB_FP32):
+    def rates_eval(self, w, vs, n_pow: int, precision: int = DMB_FP32, rates: int = DMB_RATES_EXACT,
+                   quad_nodes: int = 0):
         import torch
         A, B = torch.empty_like(w), torch.empty_like(w)
-        self._check(self.lib.dmb_rates_eval(self.h, w.numel(), _ptr(w), _ptr(vs), int(n_pow), precision, _ptr(A),
-                                            _ptr(B)), "dmb_rates_eval")
+        self._check(self.lib.dmb_rates_eval(self.h, w.numel(), _ptr(w), _ptr(vs), int(n_pow), precision, int(rates),
+                                            int(quad_nodes), _ptr(A), _ptr(B)), "dmb_rates_eval")
         return A, B
 
     def philox_eval(self, ctr, seed: int):

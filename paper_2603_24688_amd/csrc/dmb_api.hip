@@ -66,6 +66,8 @@ struct dmb_ctx {
     const double* built_dm_pos = nullptr;
     double built_L[3] = {0, 0, 0};
     int split = 64;
+    DevBuf gl64, gl32;                     // Gauss-Legendre nodes [x | w] for the quadrature rates
+    int gl_k = 0;
     // phase timing
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -356,6 +358,55 @@ double alpha_n(int n) { return std::pow(2.0, 0.5 * (n + 5)) * std::tgamma(3.0 + 
 
 bool n_supported(int n) { return n == -4 || n == -2 || n == 0 || n == 2; }
 
+// K-point Gauss-Legendre nodes and weights on [-1, 1]: Newton iteration on the
+// Legendre recurrence from the asymptotic initial guess.
+void gauss_legendre(int K, double* x, double* w)
+{
+    for (int i = 0; i < K; ++i) {
+        double z = std::cos(kPi * (i + 0.75) / (K + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int j = 2; j <= K; ++j) {
+                double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (K == 1) p0 = 1.0;
+            dp = K * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int j = 2; j <= K; ++j) {
+            double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = K * (z * p1 - p0) / (z * z - 1.0);
+        x[K - 1 - i] = z;
+        w[K - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+dmb_status ensure_quad_nodes(dmb_ctx* c, int K)
+{
+    if (K == c->gl_k) return DMB_OK;
+    ENSURE(c, c->gl64, 2 * kMaxQuadNodes * sizeof(double));
+    ENSURE(c, c->gl32, 2 * kMaxQuadNodes * sizeof(float));
+    double h64[2 * kMaxQuadNodes] = {0};
+    float h32[2 * kMaxQuadNodes] = {0};
+    gauss_legendre(K, h64, h64 + kMaxQuadNodes);
+    for (int k = 0; k < 2 * kMaxQuadNodes; ++k) h32[k] = float(h64[k]);
+    HIPCHK(c, hipMemcpyAsync(c->gl64.p, h64, sizeof(h64), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->gl32.p, h32, sizeof(h32), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->gl_k = K;
+    return DMB_OK;
+}
+
+int quad_k(const dmb_params* p) { return p->quad_nodes == 0 ? 32 : p->quad_nodes; }
+
 PassGeom geom(dmb_ctx* c, Species& A, Species& B, Pairs& P, uint64_t* counters)
 {
     PassGeom g;
@@ -375,7 +426,7 @@ PassGeom geom(dmb_ctx* c, Species& A, Species& B, Pairs& P, uint64_t* counters)
     return g;
 }
 
-template <typename Real, int N>
+template <typename Real, int N, int RM>
 dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
                        dmb_out* out, uint64_t* counters)
 {
@@ -434,13 +485,18 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
         a.dvx = D.v0.as<const double>(); a.dvy = D.v1.as<const double>(); a.dvz = D.v2.as<const double>();
         a.dm_m = D.r0.p;
         a.gtab = c->gtab.as<const float4>();
+        const DevBuf& glb = sizeof(Real) == 8 ? c->gl64 : c->gl32;
+        a.gl_x = glb.p;
+        a.gl_w = glb.p ? static_cast<const char*>(glb.p) + kMaxQuadNodes * sizeof(Real) : nullptr;
+        a.gl_k = c->gl_k;
+        a.inv_alpha = 1.0 / alpha_n(par->n_pow);
         a.part = c->part_gas.as<double>();
         a.perm = G.perm; a.mass = gas->mass; a.mu = gas->mu; a.dt = gas->dt; a.dt_default = par->dt;
         a.m_chi = par->m_chi_g; a.sig_kpc2_cn = sig_kpc2_cn; a.dp = out->dp_gas; a.de = out->de_gas;
-        int nb = int(std::min<int64_t>(persist((const void*)k_pass_gas<Real, N, kExact>), ((c->gp.nitems + 7) / 8) * 8));
+        int nb = int(std::min<int64_t>(persist((const void*)k_pass_gas<Real, N, kExact, RM>), ((c->gp.nitems + 7) / 8) * 8));
         {
             Phase ph(c, DMB_PH_PASS_GAS);
-            hipLaunchKernelGGL((k_pass_gas<Real, N, kExact>), dim3(nb), dim3(64), 0, c->stream, a);
+            hipLaunchKernelGGL((k_pass_gas<Real, N, kExact, RM>), dim3(nb), dim3(64), 0, c->stream, a);
         }
         GasCombineArgs cb;
         cb.n_own = G.n_own; cb.own = G.own.as<const uint32_t>(); cb.perm = G.perm;
@@ -502,17 +558,29 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
     return DMB_OK;
 }
 
-template <typename Real>
+template <typename Real, int RM>
 dmb_status dispatch_n(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
                       dmb_out* out, uint64_t* counters)
 {
     switch (par->n_pow) {
-        case -4: return launch_step<Real, -4>(c, gas, dm, par, out, counters);
-        case -2: return launch_step<Real, -2>(c, gas, dm, par, out, counters);
-        case 0: return launch_step<Real, 0>(c, gas, dm, par, out, counters);
-        case 2: return launch_step<Real, 2>(c, gas, dm, par, out, counters);
+        case -4: return launch_step<Real, -4, RM>(c, gas, dm, par, out, counters);
+        case -2: return launch_step<Real, -2, RM>(c, gas, dm, par, out, counters);
+        case 0: return launch_step<Real, 0, RM>(c, gas, dm, par, out, counters);
+        case 2: return launch_step<Real, 2, RM>(c, gas, dm, par, out, counters);
     }
     return fail(c, DMB_EINVAL, "n_pow %d not supported", par->n_pow);
+}
+
+template <typename Real>
+dmb_status dispatch_rates(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
+                          dmb_out* out, uint64_t* counters)
+{
+    if (par->rates == DMB_RATES_QUAD) {
+        dmb_status s = ensure_quad_nodes(c, quad_k(par));
+        if (s != DMB_OK) return s;
+        return dispatch_n<Real, kRatesQuad>(c, gas, dm, par, out, counters);
+    }
+    return dispatch_n<Real, kRatesExact>(c, gas, dm, par, out, counters);
 }
 
 }  // namespace
@@ -581,7 +649,7 @@ dmb_status dmb_destroy(dmb_ctx* c)
     for (auto& b : c->scan_tmp) fr(b);
     for (auto& p : c->pending) { c->ev_pool.push_back(p.a); c->ev_pool.push_back(p.b); }
     for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
-    DevBuf* rest[] = {&c->gtab, &c->sort_table, &c->bbox_part, &c->boxL, &c->part_gas, &c->part_p, &c->part_pm, &c->part_nb,
+    DevBuf* rest[] = {&c->gl64, &c->gl32, &c->gtab, &c->sort_table, &c->bbox_part, &c->boxL, &c->part_gas, &c->part_p, &c->part_pm, &c->part_nb,
                       &c->psum_own, &c->qctr, &c->slist, &c->counters_local};
     for (DevBuf* b : rest) fr(*b);
     delete c;
@@ -728,7 +796,10 @@ dmb_status dmb_interact_step(dmb_ctx* c, const dmb_particles* gas, const dmb_par
     if ((gas->n > 0 && (!out->dp_gas || !out->de_gas)) || (dm->n > 0 && (!out->dv_dm || !out->partner)))
         return fail(c, DMB_EINVAL, "null output array");
     if (!n_supported(par->n_pow)) return fail(c, DMB_EINVAL, "n_pow %d not supported", par->n_pow);
-    if (par->rates != DMB_RATES_EXACT) return fail(c, DMB_EINVAL, "rates mode %d not supported", par->rates);
+    if (par->rates != DMB_RATES_EXACT && par->rates != DMB_RATES_QUAD)
+        return fail(c, DMB_EINVAL, "rates mode %d not supported", par->rates);
+    if (par->rates == DMB_RATES_QUAD && (quad_k(par) < 4 || quad_k(par) > kMaxQuadNodes))
+        return fail(c, DMB_EINVAL, "quad_nodes %d outside 4..%d", par->quad_nodes, kMaxQuadNodes);
     if (!(par->m_chi_g > 0.0) || !(par->sigma0_cm2 >= 0.0)) return fail(c, DMB_EINVAL, "bad m_chi or sigma0");
     HIPCHK(c, hipSetDevice(c->device));
     uint64_t* counters = out->counters;
@@ -736,8 +807,8 @@ dmb_status dmb_interact_step(dmb_ctx* c, const dmb_particles* gas, const dmb_par
         ENSURE(c, c->counters_local, DMB_NCOUNTERS * 8);
         counters = c->counters_local.as<uint64_t>();
     }
-    if (par->precision == DMB_FP64) return dispatch_n<double>(c, gas, dm, par, out, counters);
-    if (par->precision == DMB_FP32) return dispatch_n<float>(c, gas, dm, par, out, counters);
+    if (par->precision == DMB_FP64) return dispatch_rates<double>(c, gas, dm, par, out, counters);
+    if (par->precision == DMB_FP32) return dispatch_rates<float>(c, gas, dm, par, out, counters);
     return fail(c, DMB_EINVAL, "precision %d not supported", par->precision);
 }
 
@@ -760,21 +831,39 @@ dmb_status dmb_overlap_eval(dmb_ctx* c, int64_t n, const double* d, const double
 }
 
 dmb_status dmb_rates_eval(dmb_ctx* c, int64_t n, const double* w, const double* vs, int32_t n_pow, int32_t precision,
-                          double* A_out, double* B_out)
+                          int32_t rates, int32_t quad_nodes, double* A_out, double* B_out)
 {
     if (!c) return DMB_EINVAL;
     if (n < 0 || (n > 0 && (!w || !vs || !A_out || !B_out))) return fail(c, DMB_EINVAL, "rates_eval: bad args");
     if (!n_supported(n_pow)) return fail(c, DMB_EINVAL, "n_pow %d not supported", n_pow);
+    if (rates != DMB_RATES_EXACT && rates != DMB_RATES_QUAD) return fail(c, DMB_EINVAL, "rates mode %d", rates);
+    const int K = quad_nodes == 0 ? 32 : quad_nodes;
+    if (rates == DMB_RATES_QUAD && (K < 4 || K > kMaxQuadNodes)) return fail(c, DMB_EINVAL, "quad_nodes %d", quad_nodes);
     if (n == 0) return DMB_OK;
     HIPCHK(c, hipSetDevice(c->device));
+    if (rates == DMB_RATES_QUAD) {
+        dmb_status s = ensure_quad_nodes(c, K);
+        if (s != DMB_OK) return s;
+    }
     double al = alpha_n(n_pow);
     dim3 gr(blocks_for(n, 256)), bl(256);
+    const void* x64 = c->gl64.p;
+    const void* w64 = c->gl64.p ? static_cast<const char*>(c->gl64.p) + kMaxQuadNodes * 8 : nullptr;
+    const void* x32 = c->gl32.p;
+    const void* w32 = c->gl32.p ? static_cast<const char*>(c->gl32.p) + kMaxQuadNodes * 4 : nullptr;
 #define RATES_CASE(NN)                                                                                              \
     case NN:                                                                                                        \
-        if (precision == DMB_FP64)                                                                                  \
-            hipLaunchKernelGGL((k_rates_eval<double, NN>), gr, bl, 0, c->stream, n, w, vs, al, A_out, B_out);       \
-        else                                                                                                        \
-            hipLaunchKernelGGL((k_rates_eval<float, NN>), gr, bl, 0, c->stream, n, w, vs, al, A_out, B_out);        \
+        if (rates == DMB_RATES_QUAD) {                                                                              \
+            if (precision == DMB_FP64)                                                                              \
+                hipLaunchKernelGGL((k_rates_eval<double, NN, kRatesQuad>), gr, bl, 0, c->stream, n, w, vs, al, x64, w64, K, A_out, B_out); \
+            else                                                                                                    \
+                hipLaunchKernelGGL((k_rates_eval<float, NN, kRatesQuad>), gr, bl, 0, c->stream, n, w, vs, al, x32, w32, K, A_out, B_out); \
+        } else {                                                                                                    \
+            if (precision == DMB_FP64)                                                                              \
+                hipLaunchKernelGGL((k_rates_eval<double, NN, kRatesExact>), gr, bl, 0, c->stream, n, w, vs, al, x64, w64, K, A_out, B_out); \
+            else                                                                                                    \
+                hipLaunchKernelGGL((k_rates_eval<float, NN, kRatesExact>), gr, bl, 0, c->stream, n, w, vs, al, x32, w32, K, A_out, B_out); \
+        }                                                                                                           \
         break;
     switch (n_pow) { RATES_CASE(-4) RATES_CASE(-2) RATES_CASE(0) RATES_CASE(2) }
 #undef RATES_CASE

@@ -283,6 +283,60 @@ __device__ __forceinline__ void rate_1f1(T x, T* FA, T* FB)
     }
 }
 
+// Rate integrals by quadrature (for any momentum-transfer cross section;
+// used here for sigma-bar = sigma0 (v/c)^n).  With s = u/vs and x = w/vs,
+// integrating eq. scrA / scrB over directions of u about w gives
+//   A / vs^{n+1} = sqrt(2/pi) (1/x) int_0^inf s^{4+n} e^{-(s^2+x^2)/2} j(s x) ds,
+//   B / vs^{n+3} = sqrt(2/pi)       int_0^inf s^{5+n} e^{-(s^2+x^2)/2} sinh(s x)/(s x) ds,
+// j(k) = cosh k / k - sinh k / k^2.  The Gaussian factors are formed as
+// e^{-(s -+ x)^2/2} (no overflow) and small k uses the Taylor series of j(k)/k
+// and sinh(k)/k.  K-node Gauss-Legendre on [max(0, x - 8.5), max(x + 8.5, 11)].
+// Returns the values divided by alpha_n/3 and alpha_n, i.e. in the same
+// normalisation as the 1F1 forms of rate_1f1.
+template <int N> struct Pow {
+    template <typename T> __device__ static __forceinline__ T of(T s)
+    {
+        if constexpr (N == 0) return T(1);
+        else if constexpr (N > 0) return s * Pow<N - 1>::of(s);
+        else return T(1) / Pow<-N>::of(s);
+    }
+};
+
+template <typename T> struct QuadTraits;
+template <> struct QuadTraits<float> { static constexpr float kSmall = 0.5f; };
+template <> struct QuadTraits<double> { static constexpr double kSmall = 0.1; };
+
+template <int N, typename Real>
+__device__ __forceinline__ void rate_quad(Real x, const Real* __restrict__ gx, const Real* __restrict__ gw, int K,
+                                          Real inv_alpha, Real* FA, Real* FB)
+{
+    const Real a = x > Real(8.5) ? x - Real(8.5) : Real(0);
+    const Real b = x + Real(8.5) > Real(11) ? x + Real(8.5) : Real(11);
+    const Real mid = Real(0.5) * (a + b), half = Real(0.5) * (b - a);
+    Real accA = 0, accB = 0;
+    for (int q = 0; q < K; ++q) {
+        const Real s = mid + half * gx[q];
+        const Real k = s * x, k2 = k * k;
+        Real jx, es;
+        if (k < QuadTraits<Real>::kSmall) {
+            const Real e0 = exp_neg(Real(0.5) * (s * s + x * x));
+            jx = e0 * s * (Real(1.0 / 3.0) + k2 * (Real(1.0 / 30.0) + k2 * (Real(1.0 / 840.0) + k2 * Real(1.0 / 45360.0))));
+            es = e0 * (Real(1) + k2 * (Real(1.0 / 6.0) + k2 * (Real(1.0 / 120.0) + k2 * (Real(1.0 / 5040.0) + k2 * Real(1.0 / 362880.0)))));
+        } else {
+            const Real g1 = exp_neg(Real(0.5) * (s - x) * (s - x)), g2 = exp_neg(Real(0.5) * (s + x) * (s + x));
+            const Real c = Real(0.5) * (g1 + g2), sh = Real(0.5) * (g1 - g2), ik = Real(1) / k;
+            jx = (c - sh * ik) * ik / x;
+            es = sh * ik;
+        }
+        const Real p4 = Pow<4 + N>::of(s);
+        accA += gw[q] * p4 * jx;
+        accB += gw[q] * p4 * s * es;
+    }
+    const Real c0 = Real(0.79788456080286535588) * half;   // sqrt(2/pi)
+    *FA = c0 * accA * Real(3) * inv_alpha;
+    *FB = c0 * accB * inv_alpha;
+}
+
 // v^{n+1} for the scattering probability P = K g v^{n+1} dt.
 template <int N, typename T>
 __device__ __forceinline__ T pow_np1(T v)

@@ -15,6 +15,8 @@ constexpr double kMsunG = 1.988409870698051e33;
 constexpr double kKpcCm = 3.0856775814913673e21;
 constexpr double kCKms = 299792.458;
 constexpr double kMpG = 1.67262192369e-24;
+enum { kRatesExact = 0, kRatesQuad = 1, kRatesMlp = 2 };
+constexpr int kMaxQuadNodes = 64;
 
 __device__ __forceinline__ int lane_id() { return int(threadIdx.x & 63); }
 
@@ -696,6 +698,7 @@ struct GasPassArgs {
     const double* dvx; const double* dvy; const double* dvz;  // DM velocities, sorted
     const void* dm_m;
     const float4* gtab;
+    const void* gl_x; const void* gl_w; int gl_k; double inv_alpha;   // quadrature rates (Real)
     double* part;                 // [n_items][64][4]
     // direct output for owner tiles with a single work item
     const uint32_t* perm;         // gas sorted pos -> index
@@ -715,10 +718,11 @@ __device__ __forceinline__ void gas_write_out(const GasPassArgs& a, uint32_t o, 
     a.de[o] = sc * acc[3];
 }
 
-template <typename Real, int N, bool EXACT_G>
+template <typename Real, int N, bool EXACT_G, int RM>
 __global__ __launch_bounds__(64) void k_pass_gas(GasPassArgs a)
 {
     __shared__ GroupLds S;
+    __shared__ Real s_gx[kMaxQuadNodes], s_gw[kMaxQuadNodes];
     __shared__ double o_x[64], o_y[64], o_z[64], o_h[64], o_Vx[64], o_Vy[64], o_Vz[64];
     __shared__ Real o_i2[64], o_a[64], o_b[64], o_r[64];
     const PassGeom& G = a.g;
@@ -729,6 +733,13 @@ __global__ __launch_bounds__(64) void k_pass_gas(GasPassArgs a)
     const Real* rr = reinterpret_cast<const Real*>(a.rr);
     const Real* dm_m = reinterpret_cast<const Real*>(a.dm_m);
     const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
+    if constexpr (RM == kRatesQuad) {
+        if (lane < a.gl_k) {
+            s_gx[lane] = reinterpret_cast<const Real*>(a.gl_x)[lane];
+            s_gw[lane] = reinterpret_cast<const Real*>(a.gl_w)[lane];
+        }
+    }
+    const Real inv_alpha = Real(a.inv_alpha);
     int64_t it;
     uint64_t npairs = 0;
     while (item_next(G.queue_ctr, G.n_items, &it)) {
@@ -783,7 +794,10 @@ __global__ __launch_bounds__(64) void k_pass_gas(GasPassArgs a)
                             Ar = pow_np1<N>(wn);
                             Br = Ar * w2;
                         } else {
-                            rate_1f1<N, Real>(w2 * i2, &FA, &FB);
+                            if constexpr (RM == kRatesQuad)
+                                rate_quad<N, Real>(sqrt_real(Real(2) * w2 * i2), s_gx, s_gw, a.gl_k, inv_alpha, &FA, &FB);
+                            else
+                                rate_1f1<N, Real>(w2 * i2, &FA, &FB);
                             Ar = o_a[o] * FA;
                             Br = o_b[o] * FB;
                         }
@@ -1335,10 +1349,18 @@ __global__ __launch_bounds__(256) void k_overlap_eval(int64_t n, const double* d
     out[i] = double(g);
 }
 
-template <typename Real, int N>
+template <typename Real, int N, int RM>
 __global__ __launch_bounds__(256) void k_rates_eval(int64_t n, const double* w, const double* vs, double alpha_n,
-                                                    double* A, double* B)
+                                                    const void* gl_x, const void* gl_w, int gl_k, double* A, double* B)
 {
+    __shared__ Real s_gx[kMaxQuadNodes], s_gw[kMaxQuadNodes];
+    if constexpr (RM == kRatesQuad) {
+        if (int(threadIdx.x) < gl_k) {
+            s_gx[threadIdx.x] = reinterpret_cast<const Real*>(gl_x)[threadIdx.x];
+            s_gw[threadIdx.x] = reinterpret_cast<const Real*>(gl_w)[threadIdx.x];
+        }
+        __syncthreads();
+    }
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double s = vs[i];
@@ -1353,7 +1375,10 @@ __global__ __launch_bounds__(256) void k_rates_eval(int64_t n, const double* w, 
     Real i2 = Real(1.0 / (2.0 * s * s));
     Real ra = Real(alpha_n / 3.0 * pow(s, double(N + 1))), rb = Real(alpha_n * pow(s, double(N + 3)));
     Real FA, FB;
-    rate_1f1<N, Real>(w2 * i2, &FA, &FB);
+    if constexpr (RM == kRatesQuad)
+        rate_quad<N, Real>(sqrt_real(Real(2) * w2 * i2), s_gx, s_gw, gl_k, Real(1.0 / alpha_n), &FA, &FB);
+    else
+        rate_1f1<N, Real>(w2 * i2, &FA, &FB);
     A[i] = double(ra * FA);
     B[i] = double(rb * FB);
 }

@@ -90,6 +90,26 @@ def test_rates(ctx, orc, n_pow):
         assert eA < tol and eB < tol
 
 
+@pytest.mark.parametrize("n_pow", [-4, -2, 0, 2])
+def test_rates_quadrature(ctx, orc, n_pow):
+    """DMB_RATES_QUAD: Gauss-Legendre quadrature of the radial form of
+    eq. scrA/scrB against the oracle's 1F1 values."""
+    import torch
+    import paper_2603_24688_amd as dmb
+    r = np.random.default_rng(8)
+    vs = r.uniform(0.5, 30.0, 3000)
+    w = vs * np.concatenate([r.uniform(0, 2.0, 1000), r.uniform(0, 10.0, 1500), 10 ** r.uniform(-4, 0, 500)])
+    w[:3] = 0.0
+    ref = np.array([orc.rates(n_pow, a, b) for a, b in zip(w, vs)])
+    tw, tv = torch.from_numpy(w).cuda(), torch.from_numpy(vs).cuda()
+    for prec, K, tol in ((0, 48, 1e-12), (1, 32, 3e-6)):
+        A, B = ctx.rates_eval(tw, tv, n_pow, precision=prec, rates=dmb.DMB_RATES_QUAD, quad_nodes=K)
+        eA = np.max(np.abs(A.cpu().numpy() / ref[:, 0] - 1))
+        eB = np.max(np.abs(B.cpu().numpy() / ref[:, 1] - 1))
+        _log(f"quad rates n={n_pow} prec={prec} K={K}: A {eA:.2e} B {eB:.2e}")
+        assert eA < tol and eB < tol
+
+
 # --------------------------------------------------------------------------- full step
 def _check_step(ctx, orc, cfg, precision, label, dm_sel=None, gas_sel=None, ref=None, edge_only=False):
     """edge_only: the configuration puts gas particles whose whole neighbour
@@ -147,6 +167,17 @@ def test_box_velocity_dependent(ctx, orc, n_pow):
                         sigma0_cm2=workloads.sigma0_for_npow(n_pow, 30.0, 3e-23))
     _check_step(ctx, orc, cfg, 1, f"box-n{n_pow}")
     _check_step(ctx, orc, cfg, 0, f"box-n{n_pow}")
+
+
+@pytest.mark.parametrize("precision,K", [(0, 48), (1, 32)])
+def test_box_quadrature_rates(ctx, orc, precision, K):
+    """Gas pass with DMB_RATES_QUAD (n = -2) against the oracle's 1F1 rates."""
+    import paper_2603_24688_amd as dmb
+    cfg = workloads.box(n_gas=1200, n_dm=1000, seed=(4, 21), n_pow=-2,
+                        sigma0_cm2=workloads.sigma0_for_npow(-2, 30.0, 3e-23))
+    cfg["params"]["rates"] = dmb.DMB_RATES_QUAD
+    cfg["params"]["quad_nodes"] = K
+    _check_step(ctx, orc, cfg, precision, f"box-quad-K{K}")
 
 
 @pytest.mark.parametrize("precision", [0, 1])
