@@ -52,7 +52,9 @@ typedef enum { DMB_FP64 = 0, DMB_FP32 = 1 } dmb_precision;
 /* How the rate integrals A, B (eq. scrA, scrB) are evaluated in the gas pass. */
 typedef enum {
     DMB_RATES_EXACT = 0,  /* closed forms of the 1F1 expressions of Appendix B (integer n) */
-    DMB_RATES_QUAD = 1    /* K-node Gauss-Legendre quadrature of the radial form of eq. scrA/scrB */
+    DMB_RATES_QUAD = 1,   /* K-node Gauss-Legendre quadrature of the radial form of eq. scrA/scrB */
+    DMB_RATES_MLP = 2     /* learned closure (dmb_mlp_*), binary32 only; K-node quadrature where the
+                             similarity variable u = w/varsigma exceeds the trained range (u > 1000) */
 } dmb_rates;
 
 enum {
@@ -93,7 +95,8 @@ typedef struct {
     double box[3];          /* periodic side lengths in kpc; all 0 => open boundaries */
     int32_t precision;      /* dmb_precision */
     int32_t rates;          /* dmb_rates */
-    int32_t quad_nodes;     /* K for DMB_RATES_QUAD, 4..64; 0 => 32 */
+    int32_t quad_nodes;     /* K for DMB_RATES_QUAD (and the DMB_RATES_MLP fallback), 4..64; 0 => 32.
+                               K >= 24 integrates over w/vs +- 8.5, smaller K over +- 5.5 */
 } dmb_params;
 
 typedef struct {
@@ -145,7 +148,9 @@ dmb_status dmb_interact_step(dmb_ctx *ctx, const dmb_particles *gas, const dmb_p
  *   (DMB_FP32) or exact (DMB_FP64).
  * dmb_rates_eval: A/(sigma0 c^-n), B/(sigma0 c^-n) of eq. scrA/scrB at speeds
  *   w and dispersions vs for power n, by the closed forms of Appendix B
- *   (rates = DMB_RATES_EXACT) or by quad_nodes-point quadrature (DMB_RATES_QUAD).
+ *   (rates = DMB_RATES_EXACT), by quad_nodes-point quadrature (DMB_RATES_QUAD)
+ *   or by the loaded network (DMB_RATES_MLP, binary32 whatever precision says,
+ *   with the arithmetic of the interaction step).
  * dmb_philox_eval: Philox4x32-10 blocks for counters ctr[n][4] under key
  *   (seed lo, seed hi), written to out[n][4]. */
 dmb_status dmb_overlap_eval(dmb_ctx *ctx, int64_t n, const double *d, const double *h1, const double *h2,
@@ -153,6 +158,65 @@ dmb_status dmb_overlap_eval(dmb_ctx *ctx, int64_t n, const double *d, const doub
 dmb_status dmb_rates_eval(dmb_ctx *ctx, int64_t n, const double *w, const double *vs, int32_t n_pow,
                           int32_t precision, int32_t rates, int32_t quad_nodes, double *A_out, double *B_out);
 dmb_status dmb_philox_eval(dmb_ctx *ctx, int64_t n, const uint32_t *ctr, uint64_t seed, uint32_t *out);
+
+/* ------------------------------------------------------------------------
+ * Learned closure for the rate integrals (an extension of the method: the
+ * paper evaluates eq. scrA / scrB through 1F1; here a small network may stand
+ * in for them, with quadrature as its judge and fallback).
+ *
+ * Inputs per sample, x[k][4] (device, binary64): x1 = w / varsigma_gas,
+ * x2 = T_DM / T_gas, x3 = log10(m_chi / mu), x4 = n in {-4, -2, 0, 2}.
+ * A Maxwellian DM population makes the relative velocity Gaussian with
+ * dispersion vth = varsigma_gas r, r = sqrt(1 + x2 10^{-x3}) (x2 = 0 in the
+ * interaction step, where each DM particle has one velocity), so with
+ * u = x1 / r (Appendix B):
+ *   Ahat / vs^{n+1} = r^{n+1} (alpha_n/3) 1F1(-(n+1)/2, 5/2, -u^2/2),
+ *   Bhat / vs^{n+3} = r^{n+3}  alpha_n    1F1(-(n+3)/2, 3/2, -u^2/2).
+ * The network (inputs s = 2u/(u+2) - 1 and one-hot n; three 64-unit ReLU
+ * layers; two outputs) predicts y = (ln of the two 1F1 terms) minus
+ * (ln a_A(u), ln a_B(u)), a = (c0 + c1 u^2 + u^4)^{p/4} with p = n+1 (A),
+ * n+3 (B), c0 = (u = 0 value)^{4/p} (values alpha_n/3 and alpha_n), and
+ * c1 = (0.833, 0.694), (4.327, 4.114), (8.061, 7.967), (11.981, 12.089) for
+ * n = -4, -2, 0, 2 (A, B).  bfloat16 weights and
+ * activations, binary32 accumulation (MFMA); binary32 master weights.
+ * Parameter vector (binary32, DMB_MLP_PARAMS values, row-major W[out][in]):
+ *   W1[64][5] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[2][64] b4[2].
+ * The context owns the weights; all calls below are synchronous.
+ */
+#define DMB_MLP_PARAMS 8834
+
+typedef struct {
+    int32_t epochs;         /* passes over the training set */
+    int32_t batch;          /* samples per Adam step: a positive multiple of 64, <= n */
+    double lr0, lr_min;     /* cosine learning rate from lr0 (first step) towards lr_min */
+    double beta1, beta2, eps;  /* Adam (Kingma & Ba 2015) */
+    uint64_t seed;          /* epoch shuffles; and the initial weights when init != 0 */
+    int32_t init;           /* nonzero: draw fresh He-uniform weights from seed first */
+    int32_t use_graph;      /* nonzero: capture one epoch as a hipGraph and replay it */
+} dmb_mlp_train_cfg;
+
+/* Residual targets y[n][2] (device, binary64) for inputs x[n][4] by
+ * quad_nodes-point (0 => 48) binary64 quadrature of the rate integrals.
+ * Errors: DMB_EINVAL (bad pointers, n < 0, quad_nodes outside 4..64). */
+dmb_status dmb_mlp_labels(dmb_ctx *ctx, int64_t n, const double *x, int32_t quad_nodes, double *y);
+/* Fresh weights from Philox (counter = (parameter, 0, 0, 4), key = seed). */
+dmb_status dmb_mlp_init(dmb_ctx *ctx, uint64_t seed);
+/* Copy the parameter vector from / to HOST memory (count == DMB_MLP_PARAMS). */
+dmb_status dmb_mlp_set_params(dmb_ctx *ctx, const float *params, int64_t count);
+dmb_status dmb_mlp_get_params(dmb_ctx *ctx, float *params, int64_t count);
+/* Loss L = 100 sum_{k,o} (out_ko - y_ko)^2 / (2n) over the n samples as one
+ * batch and its gradient (straight-through bfloat16 rounding) with respect to
+ * the parameters.  x, y device; grad a HOST array of DMB_MLP_PARAMS floats;
+ * loss a HOST double (nullable).  Errors: DMB_EINVAL (n < 1, no weights). */
+dmb_status dmb_mlp_grad(dmb_ctx *ctx, int64_t n, const double *x, const double *y, float *grad, double *loss);
+/* Train on n samples (x, y device) with Adam: epochs x floor(n / batch)
+ * steps; forward and backward on MFMA.  epoch_loss: HOST array of cfg->epochs
+ * mean training losses (nullable).  Errors: DMB_EINVAL, DMB_EHIP. */
+dmb_status dmb_mlp_train(dmb_ctx *ctx, int64_t n, const double *x, const double *y, const dmb_mlp_train_cfg *cfg,
+                         double *epoch_loss);
+/* Network estimate of (ln Ahat/vs^{n+1}, ln Bhat/vs^{n+3}) into out[n][2]
+ * (device, binary64); u > 1000 by binary64 quadrature.  Errors: DMB_EINVAL. */
+dmb_status dmb_mlp_eval(dmb_ctx *ctx, int64_t n, const double *x, double *out);
 
 /* Phase timing with HIP events recorded on the context stream around each
  * kernel group of dmb_build_cells / dmb_interact_step. */

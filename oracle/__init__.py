@@ -69,6 +69,7 @@ def lib():
         L.orc_overlap.restype = d; L.orc_overlap.argtypes = [d, d, d]
         L.orc_overlap_G.restype = d; L.orc_overlap_G.argtypes = [d, d]
         L.orc_hyp1f1_negx.restype = d; L.orc_hyp1f1_negx.argtypes = [d, d, d]
+        L.orc_hyp1f1_negx_v.restype = None; L.orc_hyp1f1_negx_v.argtypes = [C.c_long, d, d, p, p]
         L.orc_alpha_n.restype = d; L.orc_alpha_n.argtypes = [i]
         L.orc_rates.restype = None; L.orc_rates.argtypes = [i, d, d, C.POINTER(d), C.POINTER(d)]
         L.orc_philox4x32_10.restype = None; L.orc_philox4x32_10.argtypes = [p, p, p]
@@ -106,6 +107,13 @@ def overlap_G(delta: float, eta: float) -> float:
 
 def hyp1f1_negx(a: float, b: float, x: float) -> float:
     return lib().orc_hyp1f1_negx(float(a), float(b), float(x))
+
+
+def hyp1f1_negx_v(a: float, b: float, x) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    lib().orc_hyp1f1_negx_v(x.size, float(a), float(b), x.ctypes.data, out.ctypes.data)
+    return out
 
 
 def alpha_n(n: int) -> float:

@@ -189,6 +189,12 @@ double orc_hyp1f1_negx(double a, double b, double x)
     return pre * sum;
 }
 
+/* orc_hyp1f1_negx over an array (labels for the learned closure).          */
+void orc_hyp1f1_negx_v(long n, double a, double b, const double *x, double *out)
+{
+    for (long k = 0; k < n; k++) out[k] = orc_hyp1f1_negx(a, b, x[k]);
+}
+
 /* alpha_n = 2^{(n+5)/2} Gamma(3+n/2) / sqrt(pi)  (Appendix B).               */
 double orc_alpha_n(int n) { return pow(2.0, 0.5 * (n + 5)) * tgamma(3.0 + 0.5 * n) / sqrt(ORC_PI); }
 

@@ -15,7 +15,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libdmb.so")
 
 DMB_FP64, DMB_FP32 = 0, 1
-DMB_RATES_EXACT, DMB_RATES_QUAD = 0, 1
+DMB_RATES_EXACT, DMB_RATES_QUAD, DMB_RATES_MLP = 0, 1, 2
+MLP_PARAMS = 8834
 COUNTER_NAMES = ["pairs_gas", "pairs_dm", "scatters", "near_boundary", "near_decision",
                  "crit_viol", "p_ge_1", "nonfinite"]
 N_COUNTERS = len(COUNTER_NAMES)
@@ -24,7 +25,8 @@ STATUS = {0: "DMB_OK", -1: "DMB_EINVAL", -2: "DMB_ENOMEM", -3: "DMB_EHIP", -4: "
 # Symbols declared in include/dmb.h.
 EXPORTS = ["dmb_create", "dmb_destroy", "dmb_set_stream", "dmb_build_cells", "dmb_interact_step",
            "dmb_overlap_eval", "dmb_rates_eval", "dmb_philox_eval", "dmb_profile_enable", "dmb_profile_read",
-           "dmb_build_stats", "dmb_last_error"]
+           "dmb_build_stats", "dmb_last_error", "dmb_mlp_labels", "dmb_mlp_init", "dmb_mlp_set_params",
+           "dmb_mlp_get_params", "dmb_mlp_grad", "dmb_mlp_train", "dmb_mlp_eval"]
 BUILD_STATS = ["active_gas", "active_dm", "gas_tiles", "dm_tiles", "gas_owner_tiles", "dm_owner_tiles",
                "cand_pairs_gas", "cand_pairs_dm", "items_gas", "items_dm"]
 PHASES = ["build", "gather", "pass_gas", "combine_gas", "pass_dm", "combine_dm", "resolve"]
@@ -49,6 +51,12 @@ class Params(C.Structure):
 class Out(C.Structure):
     _fields_ = [("dv_dm", C.c_void_p), ("dp_gas", C.c_void_p), ("de_gas", C.c_void_p), ("partner", C.c_void_p),
                 ("p_sum", C.c_void_p), ("p_max", C.c_void_p), ("counters", C.c_void_p)]
+
+
+class MlpTrainCfg(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr0", C.c_double), ("lr_min", C.c_double),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64),
+                ("init", C.c_int32), ("use_graph", C.c_int32)]
 
 
 _lib = None
@@ -83,6 +91,14 @@ def load_library(path: str = LIB_PATH):
     L.dmb_profile_read.restype = C.c_int; L.dmb_profile_read.argtypes = [vp, vp, vp, i32]
     L.dmb_build_stats.restype = C.c_int; L.dmb_build_stats.argtypes = [vp, vp]
     L.dmb_last_error.restype = C.c_char_p; L.dmb_last_error.argtypes = [vp]
+    L.dmb_mlp_labels.restype = C.c_int; L.dmb_mlp_labels.argtypes = [vp, i64, vp, i32, vp]
+    L.dmb_mlp_init.restype = C.c_int; L.dmb_mlp_init.argtypes = [vp, u64]
+    L.dmb_mlp_set_params.restype = C.c_int; L.dmb_mlp_set_params.argtypes = [vp, vp, i64]
+    L.dmb_mlp_get_params.restype = C.c_int; L.dmb_mlp_get_params.argtypes = [vp, vp, i64]
+    L.dmb_mlp_grad.restype = C.c_int; L.dmb_mlp_grad.argtypes = [vp, i64, vp, vp, vp, vp]
+    L.dmb_mlp_train.restype = C.c_int
+    L.dmb_mlp_train.argtypes = [vp, i64, vp, vp, C.POINTER(MlpTrainCfg), vp]
+    L.dmb_mlp_eval.restype = C.c_int; L.dmb_mlp_eval.argtypes = [vp, i64, vp, vp]
     _lib = L
     return L
 
@@ -190,6 +206,56 @@ class Context:
         self._check(self.lib.dmb_rates_eval(self.h, w.numel(), _ptr(w), _ptr(vs), int(n_pow), precision, int(rates),
                                             int(quad_nodes), _ptr(A), _ptr(B)), "dmb_rates_eval")
         return A, B
+
+    # -- learned rate closure ----------------------------------------------------------------
+    def mlp_labels(self, x, quad_nodes: int = 0):
+        """Residual targets [n, 2] (float64, device) for inputs x [n, 4] (float64, device)."""
+        import torch
+        y = torch.empty((x.shape[0], 2), dtype=torch.float64, device=x.device)
+        self._check(self.lib.dmb_mlp_labels(self.h, x.shape[0], _ptr(x), int(quad_nodes), _ptr(y)), "dmb_mlp_labels")
+        return y
+
+    def mlp_init(self, seed: int):
+        self._check(self.lib.dmb_mlp_init(self.h, int(seed) & 0xFFFFFFFFFFFFFFFF), "dmb_mlp_init")
+
+    def mlp_set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self.lib.dmb_mlp_set_params(self.h, p.ctypes.data, p.size), "dmb_mlp_set_params")
+
+    def mlp_get_params(self):
+        import numpy as np
+        p = np.empty(MLP_PARAMS, dtype=np.float32)
+        self._check(self.lib.dmb_mlp_get_params(self.h, p.ctypes.data, p.size), "dmb_mlp_get_params")
+        return p
+
+    def mlp_grad(self, x, y):
+        """(gradient [MLP_PARAMS] float32 numpy, loss) of the n samples as one batch."""
+        import numpy as np
+        g = np.empty(MLP_PARAMS, dtype=np.float32)
+        loss = C.c_double()
+        self._check(self.lib.dmb_mlp_grad(self.h, x.shape[0], _ptr(x), _ptr(y), g.ctypes.data, C.byref(loss)),
+                    "dmb_mlp_grad")
+        return g, loss.value
+
+    def mlp_train(self, x, y, epochs: int, batch: int = 4096, lr0: float = 2e-3, lr_min: float = 1e-5,
+                  beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, seed: int = 1, init: bool = True,
+                  use_graph: bool = True):
+        """Train on (x, y) (device tensors); returns the mean loss of each epoch."""
+        import numpy as np
+        cfg = MlpTrainCfg(int(epochs), int(batch), float(lr0), float(lr_min), float(beta1), float(beta2), float(eps),
+                          int(seed) & 0xFFFFFFFFFFFFFFFF, int(bool(init)), int(bool(use_graph)))
+        losses = np.zeros(int(epochs), dtype=np.float64)
+        self._check(self.lib.dmb_mlp_train(self.h, x.shape[0], _ptr(x), _ptr(y), C.byref(cfg), losses.ctypes.data),
+                    "dmb_mlp_train")
+        return losses
+
+    def mlp_eval(self, x):
+        """Network (ln Ahat/vs^{n+1}, ln Bhat/vs^{n+3}) [n, 2] for inputs x [n, 4]."""
+        import torch
+        out = torch.empty((x.shape[0], 2), dtype=torch.float64, device=x.device)
+        self._check(self.lib.dmb_mlp_eval(self.h, x.shape[0], _ptr(x), _ptr(out)), "dmb_mlp_eval")
+        return out
 
     def philox_eval(self, ctr, seed: int):
         import torch

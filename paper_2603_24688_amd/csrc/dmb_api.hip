@@ -68,6 +68,12 @@ struct dmb_ctx {
     int split = 64;
     DevBuf gl64, gl32;                     // Gauss-Legendre nodes [x | w] for the quadrature rates
     int gl_k = 0;
+    // learned rate closure
+    DevBuf mlp_p, mlp_m, mlp_v;            // binary32 master weights, Adam moments
+    DevBuf mlp_blob;                       // packed bfloat16 weights (MlpBlob)
+    DevBuf mlp_part, mlp_red, mlp_ts, mlp_loss, mlp_epoch, mlp_shuf;
+    bool mlp_ready = false;
+    hipStream_t train_stream = nullptr;
     // phase timing
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -432,9 +438,10 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
 {
     constexpr bool kExact = sizeof(Real) == 8;
     // persistent grids: as many single-wave blocks as can be resident
-    auto persist = [&](const void* fn) {
+    auto persist = [&](const void* fn, int threads) {
         int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, 0) != hipSuccess || per_cu < 1) per_cu = 8;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess || per_cu < 1)
+            per_cu = 8;
         return std::max(8, (c->num_cu * per_cu / 8) * 8);
     };
     const uint32_t k0 = uint32_t(par->seed), k1 = uint32_t(par->seed >> 32);
@@ -490,13 +497,29 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
         a.gl_w = glb.p ? static_cast<const char*>(glb.p) + kMaxQuadNodes * sizeof(Real) : nullptr;
         a.gl_k = c->gl_k;
         a.inv_alpha = 1.0 / alpha_n(par->n_pow);
+        quad_window(c->gl_k, &a.gl_hw, &a.gl_bmin);
+        if constexpr (RM == kRatesMlp) {
+            const double al = alpha_n(N);
+            a.mlp = c->mlp_blob.as<const MlpBlob>();
+            a.mlp_nidx = mlp_n_index(N);
+            a.mlp_c0A = float(std::pow(al / 3.0, 4.0 / (N + 1)));
+            a.mlp_c0B = float(std::pow(al, 4.0 / (N + 3)));
+            a.mlp_c1A = float(kMlpC1[mlp_n_index(N)][0]);
+            a.mlp_c1B = float(kMlpC1[mlp_n_index(N)][1]);
+            a.mlp_kA = float(3.0 / al);
+            a.mlp_kB = float(1.0 / al);
+        } else {
+            a.mlp = nullptr;
+        }
         a.part = c->part_gas.as<double>();
         a.perm = G.perm; a.mass = gas->mass; a.mu = gas->mu; a.dt = gas->dt; a.dt_default = par->dt;
         a.m_chi = par->m_chi_g; a.sig_kpc2_cn = sig_kpc2_cn; a.dp = out->dp_gas; a.de = out->de_gas;
-        int nb = int(std::min<int64_t>(persist((const void*)k_pass_gas<Real, N, kExact, RM>), ((c->gp.nitems + 7) / 8) * 8));
+        constexpr int kW = RM == kRatesMlp ? kMlpPassWaves : 1;
+        const int64_t want = (((c->gp.nitems + kW - 1) / kW + 7) / 8) * 8;
+        int nb = int(std::min<int64_t>(persist((const void*)k_pass_gas<Real, N, kExact, RM>, 64 * kW), want));
         {
             Phase ph(c, DMB_PH_PASS_GAS);
-            hipLaunchKernelGGL((k_pass_gas<Real, N, kExact, RM>), dim3(nb), dim3(64), 0, c->stream, a);
+            hipLaunchKernelGGL((k_pass_gas<Real, N, kExact, RM>), dim3(nb), dim3(64 * kW), 0, c->stream, a);
         }
         GasCombineArgs cb;
         cb.n_own = G.n_own; cb.own = G.own.as<const uint32_t>(); cb.perm = G.perm;
@@ -525,7 +548,7 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
         a.part_p = c->part_p.as<double>(); a.part_pm = c->part_pm.as<float>(); a.part_nb = c->part_nb.as<uint8_t>();
         a.psum_own = c->psum_own.as<double>(); a.psum = out->p_sum; a.pmax = out->p_max;
         a.scount = scount; a.slist = c->slist.as<uint32_t>();
-        int nb = int(std::min<int64_t>(persist((const void*)k_pass_dm<Real, N, kExact>), ((c->dp.nitems + 7) / 8) * 8));
+        int nb = int(std::min<int64_t>(persist((const void*)k_pass_dm<Real, N, kExact>, 64), ((c->dp.nitems + 7) / 8) * 8));
         {
             Phase ph(c, DMB_PH_PASS_DM);
             hipLaunchKernelGGL((k_pass_dm<Real, N, kExact>), dim3(nb), dim3(64), 0, c->stream, a);
@@ -580,7 +603,76 @@ dmb_status dispatch_rates(dmb_ctx* c, const dmb_particles* gas, const dmb_partic
         if (s != DMB_OK) return s;
         return dispatch_n<Real, kRatesQuad>(c, gas, dm, par, out, counters);
     }
+    if (par->rates == DMB_RATES_MLP) {
+        if constexpr (sizeof(Real) == 4) {
+            dmb_status s = ensure_quad_nodes(c, quad_k(par));
+            if (s != DMB_OK) return s;
+            return dispatch_n<float, kRatesMlp>(c, gas, dm, par, out, counters);
+        } else {
+            return fail(c, DMB_EINVAL, "network rates need DMB_FP32");
+        }
+    }
     return dispatch_n<Real, kRatesExact>(c, gas, dm, par, out, counters);
+}
+
+// ---------------------------------------------------------------------------
+// learned rate closure: host helpers
+MlpConst mlp_const()
+{
+    MlpConst K;
+    const int nv[4] = {-4, -2, 0, 2};
+    for (int j = 0; j < 4; ++j) {
+        const double al = alpha_n(nv[j]);
+        K.lnA[j] = std::log(al / 3.0);
+        K.lnB[j] = std::log(al);
+        K.c0A[j] = std::pow(al / 3.0, 4.0 / (nv[j] + 1));
+        K.c0B[j] = std::pow(al, 4.0 / (nv[j] + 3));
+        K.inv_alpha[j] = 1.0 / al;
+    }
+    return K;
+}
+
+dmb_status mlp_alloc(dmb_ctx* c)
+{
+    ENSURE(c, c->mlp_p, kMlpParams * sizeof(float));
+    ENSURE(c, c->mlp_m, kMlpParams * sizeof(float));
+    ENSURE(c, c->mlp_v, kMlpParams * sizeof(float));
+    ENSURE(c, c->mlp_blob, sizeof(MlpBlob));
+    ENSURE(c, c->mlp_red, (kMlpParams + 1) * sizeof(float));
+    return DMB_OK;
+}
+
+// Rebuild the packed weights from the binary32 master copy.
+dmb_status mlp_repack(dmb_ctx* c, hipStream_t st)
+{
+    HIPCHK(c, hipMemsetAsync(c->mlp_blob.p, 0, sizeof(MlpBlob), st));
+    hipLaunchKernelGGL(k_mlp_pack, dim3(blocks_for(kMlpParams, 256)), dim3(256), 0, st, c->mlp_p.as<const float>(),
+                       c->mlp_blob.as<MlpBlob>());
+    HIPCHK(c, hipGetLastError());
+    return DMB_OK;
+}
+
+// Training samples (s, n index, targets) for n inputs x[n][4] and targets y[n][2].
+dmb_status mlp_prep(dmb_ctx* c, int64_t n, const double* x, const double* y)
+{
+    ENSURE(c, c->mlp_ts, size_t(n) * sizeof(float4));
+    hipLaunchKernelGGL(k_mlp_prep, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, n, x, y, c->mlp_ts.as<float4>());
+    HIPCHK(c, hipGetLastError());
+    return DMB_OK;
+}
+
+uint64_t splitmix64(uint64_t* s)
+{
+    uint64_t z = (*s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t gcd64(uint64_t a, uint64_t b)
+{
+    while (b) { uint64_t t = a % b; a = b; b = t; }
+    return a;
 }
 
 }  // namespace
@@ -649,6 +741,10 @@ dmb_status dmb_destroy(dmb_ctx* c)
     for (auto& b : c->scan_tmp) fr(b);
     for (auto& p : c->pending) { c->ev_pool.push_back(p.a); c->ev_pool.push_back(p.b); }
     for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+    DevBuf* mlp[] = {&c->mlp_p, &c->mlp_m, &c->mlp_v, &c->mlp_blob, &c->mlp_part, &c->mlp_red, &c->mlp_ts,
+                     &c->mlp_loss, &c->mlp_epoch, &c->mlp_shuf};
+    for (DevBuf* b : mlp) fr(*b);
+    if (c->train_stream) hipStreamDestroy(c->train_stream);
     DevBuf* rest[] = {&c->gl64, &c->gl32, &c->gtab, &c->sort_table, &c->bbox_part, &c->boxL, &c->part_gas, &c->part_p, &c->part_pm, &c->part_nb,
                       &c->psum_own, &c->qctr, &c->slist, &c->counters_local};
     for (DevBuf* b : rest) fr(*b);
@@ -796,9 +892,13 @@ dmb_status dmb_interact_step(dmb_ctx* c, const dmb_particles* gas, const dmb_par
     if ((gas->n > 0 && (!out->dp_gas || !out->de_gas)) || (dm->n > 0 && (!out->dv_dm || !out->partner)))
         return fail(c, DMB_EINVAL, "null output array");
     if (!n_supported(par->n_pow)) return fail(c, DMB_EINVAL, "n_pow %d not supported", par->n_pow);
-    if (par->rates != DMB_RATES_EXACT && par->rates != DMB_RATES_QUAD)
+    if (par->rates != DMB_RATES_EXACT && par->rates != DMB_RATES_QUAD && par->rates != DMB_RATES_MLP)
         return fail(c, DMB_EINVAL, "rates mode %d not supported", par->rates);
-    if (par->rates == DMB_RATES_QUAD && (quad_k(par) < 4 || quad_k(par) > kMaxQuadNodes))
+    if (par->rates == DMB_RATES_MLP && !c->mlp_ready)
+        return fail(c, DMB_EINVAL, "network rates requested but no weights are loaded (dmb_mlp_init/set_params/train)");
+    if (par->rates == DMB_RATES_MLP && par->precision != DMB_FP32)
+        return fail(c, DMB_EINVAL, "network rates need DMB_FP32");
+    if (par->rates != DMB_RATES_EXACT && (quad_k(par) < 4 || quad_k(par) > kMaxQuadNodes))
         return fail(c, DMB_EINVAL, "quad_nodes %d outside 4..%d", par->quad_nodes, kMaxQuadNodes);
     if (!(par->m_chi_g > 0.0) || !(par->sigma0_cm2 >= 0.0)) return fail(c, DMB_EINVAL, "bad m_chi or sigma0");
     HIPCHK(c, hipSetDevice(c->device));
@@ -836,16 +936,42 @@ dmb_status dmb_rates_eval(dmb_ctx* c, int64_t n, const double* w, const double* 
     if (!c) return DMB_EINVAL;
     if (n < 0 || (n > 0 && (!w || !vs || !A_out || !B_out))) return fail(c, DMB_EINVAL, "rates_eval: bad args");
     if (!n_supported(n_pow)) return fail(c, DMB_EINVAL, "n_pow %d not supported", n_pow);
-    if (rates != DMB_RATES_EXACT && rates != DMB_RATES_QUAD) return fail(c, DMB_EINVAL, "rates mode %d", rates);
+    if (rates != DMB_RATES_EXACT && rates != DMB_RATES_QUAD && rates != DMB_RATES_MLP)
+        return fail(c, DMB_EINVAL, "rates mode %d", rates);
+    if (rates == DMB_RATES_MLP && !c->mlp_ready) return fail(c, DMB_EINVAL, "network rates: no weights loaded");
     const int K = quad_nodes == 0 ? 32 : quad_nodes;
-    if (rates == DMB_RATES_QUAD && (K < 4 || K > kMaxQuadNodes)) return fail(c, DMB_EINVAL, "quad_nodes %d", quad_nodes);
+    if (rates != DMB_RATES_EXACT && (K < 4 || K > kMaxQuadNodes)) return fail(c, DMB_EINVAL, "quad_nodes %d", quad_nodes);
     if (n == 0) return DMB_OK;
     HIPCHK(c, hipSetDevice(c->device));
-    if (rates == DMB_RATES_QUAD) {
+    if (rates != DMB_RATES_EXACT) {
         dmb_status s = ensure_quad_nodes(c, K);
         if (s != DMB_OK) return s;
     }
     double al = alpha_n(n_pow);
+    double hw = 0.0, bmin = 0.0;
+    quad_window(K, &hw, &bmin);
+    if (rates == DMB_RATES_MLP) {
+        MlpRatesArgs m;
+        m.n = n; m.w = w; m.vs = vs; m.alpha_n = al; m.mlp = c->mlp_blob.as<const MlpBlob>();
+        m.nidx = mlp_n_index(n_pow);
+        m.c0A = float(std::pow(al / 3.0, 4.0 / (n_pow + 1)));
+        m.c0B = float(std::pow(al, 4.0 / (n_pow + 3)));
+        m.c1A = float(kMlpC1[mlp_n_index(n_pow)][0]);
+        m.c1B = float(kMlpC1[mlp_n_index(n_pow)][1]);
+        m.kA = float(3.0 / al); m.kB = float(1.0 / al);
+        m.gl_x = c->gl32.as<const float>(); m.gl_w = c->gl32.as<const float>() + kMaxQuadNodes; m.gl_k = K;
+        m.hw = hw; m.bmin = bmin; m.A = A_out; m.B = B_out;
+        dim3 g2(blocks_for(n, 256)), b2(256);
+        switch (n_pow) {
+            case -4: hipLaunchKernelGGL(k_rates_eval_mlp<-4>, g2, b2, 0, c->stream, m); break;
+            case -2: hipLaunchKernelGGL(k_rates_eval_mlp<-2>, g2, b2, 0, c->stream, m); break;
+            case 0: hipLaunchKernelGGL(k_rates_eval_mlp<0>, g2, b2, 0, c->stream, m); break;
+            case 2: hipLaunchKernelGGL(k_rates_eval_mlp<2>, g2, b2, 0, c->stream, m); break;
+        }
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return DMB_OK;
+    }
     dim3 gr(blocks_for(n, 256)), bl(256);
     const void* x64 = c->gl64.p;
     const void* w64 = c->gl64.p ? static_cast<const char*>(c->gl64.p) + kMaxQuadNodes * 8 : nullptr;
@@ -855,14 +981,14 @@ dmb_status dmb_rates_eval(dmb_ctx* c, int64_t n, const double* w, const double* 
     case NN:                                                                                                        \
         if (rates == DMB_RATES_QUAD) {                                                                              \
             if (precision == DMB_FP64)                                                                              \
-                hipLaunchKernelGGL((k_rates_eval<double, NN, kRatesQuad>), gr, bl, 0, c->stream, n, w, vs, al, x64, w64, K, A_out, B_out); \
+                hipLaunchKernelGGL((k_rates_eval<double, NN, kRatesQuad>), gr, bl, 0, c->stream, n, w, vs, al, x64, w64, K, hw, bmin, A_out, B_out); \
             else                                                                                                    \
-                hipLaunchKernelGGL((k_rates_eval<float, NN, kRatesQuad>), gr, bl, 0, c->stream, n, w, vs, al, x32, w32, K, A_out, B_out); \
+                hipLaunchKernelGGL((k_rates_eval<float, NN, kRatesQuad>), gr, bl, 0, c->stream, n, w, vs, al, x32, w32, K, hw, bmin, A_out, B_out); \
         } else {                                                                                                    \
             if (precision == DMB_FP64)                                                                              \
-                hipLaunchKernelGGL((k_rates_eval<double, NN, kRatesExact>), gr, bl, 0, c->stream, n, w, vs, al, x64, w64, K, A_out, B_out); \
+                hipLaunchKernelGGL((k_rates_eval<double, NN, kRatesExact>), gr, bl, 0, c->stream, n, w, vs, al, x64, w64, K, hw, bmin, A_out, B_out); \
             else                                                                                                    \
-                hipLaunchKernelGGL((k_rates_eval<float, NN, kRatesExact>), gr, bl, 0, c->stream, n, w, vs, al, x32, w32, K, A_out, B_out); \
+                hipLaunchKernelGGL((k_rates_eval<float, NN, kRatesExact>), gr, bl, 0, c->stream, n, w, vs, al, x32, w32, K, hw, bmin, A_out, B_out); \
         }                                                                                                           \
         break;
     switch (n_pow) { RATES_CASE(-4) RATES_CASE(-2) RATES_CASE(0) RATES_CASE(2) }
@@ -880,6 +1006,208 @@ dmb_status dmb_philox_eval(dmb_ctx* c, int64_t n, const uint32_t* ctr, uint64_t 
     HIPCHK(c, hipSetDevice(c->device));
     hipLaunchKernelGGL(k_philox_eval, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, n, ctr, uint32_t(seed),
                        uint32_t(seed >> 32), out);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DMB_OK;
+}
+
+dmb_status dmb_mlp_labels(dmb_ctx* c, int64_t n, const double* x, int32_t quad_nodes, double* y)
+{
+    if (!c) return DMB_EINVAL;
+    if (n < 0 || (n > 0 && (!x || !y))) return fail(c, DMB_EINVAL, "mlp_labels: bad args");
+    const int K = quad_nodes == 0 ? 48 : quad_nodes;
+    if (K < 4 || K > kMaxQuadNodes) return fail(c, DMB_EINVAL, "quad_nodes %d outside 4..%d", quad_nodes, kMaxQuadNodes);
+    if (n == 0) return DMB_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    dmb_status s = ensure_quad_nodes(c, K);
+    if (s != DMB_OK) return s;
+    double hw, bmin;
+    quad_window(K, &hw, &bmin);
+    hipLaunchKernelGGL(k_mlp_labels, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, n, x, mlp_const(),
+                       c->gl64.as<const double>(), c->gl64.as<const double>() + kMaxQuadNodes, K, hw, bmin, y);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DMB_OK;
+}
+
+dmb_status dmb_mlp_init(dmb_ctx* c, uint64_t seed)
+{
+    if (!c) return DMB_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    dmb_status s = mlp_alloc(c);
+    if (s != DMB_OK) return s;
+    hipLaunchKernelGGL(k_mlp_init, dim3(blocks_for(kMlpParams, 256)), dim3(256), 0, c->stream, c->mlp_p.as<float>(),
+                       uint32_t(seed), uint32_t(seed >> 32));
+    HIPCHK(c, hipGetLastError());
+    if ((s = mlp_repack(c, c->stream)) != DMB_OK) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->mlp_ready = true;
+    return DMB_OK;
+}
+
+dmb_status dmb_mlp_set_params(dmb_ctx* c, const float* params, int64_t count)
+{
+    if (!c) return DMB_EINVAL;
+    if (!params || count != kMlpParams) return fail(c, DMB_EINVAL, "mlp_set_params: need %d values", kMlpParams);
+    HIPCHK(c, hipSetDevice(c->device));
+    dmb_status s = mlp_alloc(c);
+    if (s != DMB_OK) return s;
+    HIPCHK(c, hipMemcpyAsync(c->mlp_p.p, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    if ((s = mlp_repack(c, c->stream)) != DMB_OK) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->mlp_ready = true;
+    return DMB_OK;
+}
+
+dmb_status dmb_mlp_get_params(dmb_ctx* c, float* params, int64_t count)
+{
+    if (!c) return DMB_EINVAL;
+    if (!params || count != kMlpParams) return fail(c, DMB_EINVAL, "mlp_get_params: need %d values", kMlpParams);
+    if (!c->mlp_ready) return fail(c, DMB_EINVAL, "mlp_get_params: no weights loaded");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(params, c->mlp_p.p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DMB_OK;
+}
+
+dmb_status dmb_mlp_grad(dmb_ctx* c, int64_t n, const double* x, const double* y, float* grad, double* loss)
+{
+    if (!c) return DMB_EINVAL;
+    if (n < 1 || !x || !y || !grad) return fail(c, DMB_EINVAL, "mlp_grad: bad args");
+    if (!c->mlp_ready) return fail(c, DMB_EINVAL, "mlp_grad: no weights loaded");
+    HIPCHK(c, hipSetDevice(c->device));
+    dmb_status s = mlp_prep(c, n, x, y);
+    if (s != DMB_OK) return s;
+    const int64_t nblk = (n + kMlpWave - 1) / kMlpWave;
+    ENSURE(c, c->mlp_part, size_t(nblk) * (kMlpParams + 1) * sizeof(float));
+    MlpGradArgs g;
+    g.ts = c->mlp_ts.as<const float4>(); g.n_total = n; g.batch = n; g.epoch = nullptr; g.shuffle = nullptr;
+    g.step = 0; g.W = c->mlp_blob.as<const MlpBlob>(); g.part = c->mlp_part.as<float>();
+    hipLaunchKernelGGL(k_mlp_grad, dim3(unsigned(nblk)), dim3(64), 0, c->stream, g);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3(blocks_for(kMlpParams + 1, 256)), dim3(256), 0, c->stream,
+                       c->mlp_part.as<const float>(), int(nblk), c->mlp_red.as<float>());
+    HIPCHK(c, hipGetLastError());
+    std::vector<float> h(kMlpParams + 1);
+    HIPCHK(c, hipMemcpyAsync(h.data(), c->mlp_red.p, h.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::memcpy(grad, h.data(), kMlpParams * sizeof(float));
+    if (loss) *loss = double(h[kMlpParams]);
+    return DMB_OK;
+}
+
+dmb_status dmb_mlp_train(dmb_ctx* c, int64_t n, const double* x, const double* y, const dmb_mlp_train_cfg* cfg,
+                         double* epoch_loss)
+{
+    if (!c) return DMB_EINVAL;
+    if (!cfg || !x || !y) return fail(c, DMB_EINVAL, "mlp_train: null argument");
+    if (cfg->epochs < 1 || cfg->batch < kMlpWave || cfg->batch % kMlpWave != 0 || n < cfg->batch)
+        return fail(c, DMB_EINVAL, "mlp_train: need epochs >= 1, batch a positive multiple of 64, n >= batch");
+    if (!(cfg->lr0 > 0.0) || !(cfg->lr_min >= 0.0) || !(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0) ||
+        !(cfg->beta2 >= 0.0 && cfg->beta2 < 1.0) || !(cfg->eps > 0.0))
+        return fail(c, DMB_EINVAL, "mlp_train: bad optimiser settings");
+    HIPCHK(c, hipSetDevice(c->device));
+    dmb_status s;
+    if (cfg->init) {
+        if ((s = dmb_mlp_init(c, cfg->seed)) != DMB_OK) return s;
+    } else if (!c->mlp_ready) {
+        return fail(c, DMB_EINVAL, "mlp_train: no weights loaded and init == 0");
+    }
+    const int64_t S = n / cfg->batch, total = S * cfg->epochs, nblk = cfg->batch / kMlpWave;
+    if ((s = mlp_prep(c, n, x, y)) != DMB_OK) return s;
+    ENSURE(c, c->mlp_part, size_t(nblk) * (kMlpParams + 1) * sizeof(float));
+    ENSURE(c, c->mlp_loss, size_t(total) * sizeof(float));
+    ENSURE(c, c->mlp_epoch, sizeof(uint32_t));
+    ENSURE(c, c->mlp_shuf, size_t(cfg->epochs) * 2 * sizeof(uint64_t));
+    // one shuffle (an affine permutation of 0..n-1) per epoch
+    std::vector<uint64_t> shuf(2 * size_t(cfg->epochs));
+    uint64_t st = cfg->seed ^ 0x5DEECE66Dull;
+    for (int e = 0; e < cfg->epochs; ++e) {
+        uint64_t m = 1;
+        if (n > 1) {
+            do { m = 1 + splitmix64(&st) % uint64_t(n - 1); } while (gcd64(m, uint64_t(n)) != 1);
+        }
+        shuf[2 * e] = e == 0 && n == 1 ? 1 : m;
+        shuf[2 * e + 1] = splitmix64(&st) % uint64_t(n);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->mlp_shuf.p, shuf.data(), shuf.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!c->train_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->train_stream, hipStreamNonBlocking));
+    hipStream_t ts = c->train_stream;
+    HIPCHK(c, hipMemsetAsync(c->mlp_m.p, 0, kMlpParams * sizeof(float), ts));
+    HIPCHK(c, hipMemsetAsync(c->mlp_v.p, 0, kMlpParams * sizeof(float), ts));
+    HIPCHK(c, hipMemsetAsync(c->mlp_epoch.p, 0, sizeof(uint32_t), ts));
+    MlpGradArgs g;
+    g.ts = c->mlp_ts.as<const float4>(); g.n_total = n; g.batch = cfg->batch;
+    g.epoch = c->mlp_epoch.as<const uint32_t>(); g.shuffle = c->mlp_shuf.as<const uint64_t>();
+    g.W = c->mlp_blob.as<const MlpBlob>(); g.part = c->mlp_part.as<float>();
+    MlpAdamArgs a;
+    a.p = c->mlp_p.as<float>(); a.m = c->mlp_m.as<float>(); a.v = c->mlp_v.as<float>();
+    a.part = c->mlp_part.as<const float>(); a.nblk = int(nblk); a.epoch = c->mlp_epoch.as<const uint32_t>();
+    a.steps_per_epoch = S; a.total_steps = total;
+    a.lr0 = float(cfg->lr0); a.lr_min = float(cfg->lr_min); a.beta1 = float(cfg->beta1); a.beta2 = float(cfg->beta2);
+    a.eps = float(cfg->eps); a.W = c->mlp_blob.as<MlpBlob>(); a.loss = c->mlp_loss.as<float>();
+    auto enqueue_epoch = [&]() {
+        for (int64_t k = 0; k < S; ++k) {
+            g.step = k;
+            a.step = k;
+            hipLaunchKernelGGL(k_mlp_grad, dim3(unsigned(nblk)), dim3(64), 0, ts, g);
+            hipLaunchKernelGGL(k_mlp_adam, dim3(blocks_for(kMlpParams + 1, 256)), dim3(256), 0, ts, a);
+        }
+        hipLaunchKernelGGL(k_mlp_tick, dim3(1), dim3(1), 0, ts, c->mlp_epoch.as<uint32_t>());
+    };
+    if (cfg->use_graph) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(ts, hipStreamCaptureModeThreadLocal));
+        enqueue_epoch();
+        hipError_t e1 = hipStreamEndCapture(ts, &graph);
+        if (e1 != hipSuccess) return fail(c, DMB_EHIP, "epoch capture: %s", hipGetErrorString(e1));
+        e1 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e1 != hipSuccess) {
+            hipGraphDestroy(graph);
+            return fail(c, DMB_EHIP, "epoch graph: %s", hipGetErrorString(e1));
+        }
+        // one replay per epoch, each waited for before the next is launched
+        hipError_t e2 = hipSuccess;
+        for (int e = 0; e < cfg->epochs && e1 == hipSuccess && e2 == hipSuccess; ++e) {
+            e1 = hipGraphLaunch(exec, ts);
+            if (e1 == hipSuccess) e2 = hipStreamSynchronize(ts);
+        }
+        hipGraphExecDestroy(exec);
+        hipGraphDestroy(graph);
+        if (e1 != hipSuccess || e2 != hipSuccess)
+            return fail(c, DMB_EHIP, "epoch replay: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    } else {
+        for (int e = 0; e < cfg->epochs; ++e) enqueue_epoch();
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipStreamSynchronize(ts));
+    }
+    if (epoch_loss) {
+        std::vector<float> L(static_cast<size_t>(total));
+        HIPCHK(c, hipMemcpy(L.data(), c->mlp_loss.p, L.size() * sizeof(float), hipMemcpyDeviceToHost));
+        for (int e = 0; e < cfg->epochs; ++e) {
+            double acc = 0.0;
+            for (int64_t k = 0; k < S; ++k) acc += L[size_t(e) * S + k];
+            epoch_loss[e] = acc / double(S);
+        }
+    }
+    return DMB_OK;
+}
+
+dmb_status dmb_mlp_eval(dmb_ctx* c, int64_t n, const double* x, double* out)
+{
+    if (!c) return DMB_EINVAL;
+    if (n < 0 || (n > 0 && (!x || !out))) return fail(c, DMB_EINVAL, "mlp_eval: bad args");
+    if (!c->mlp_ready) return fail(c, DMB_EINVAL, "mlp_eval: no weights loaded");
+    if (n == 0) return DMB_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    dmb_status s = ensure_quad_nodes(c, 48);
+    if (s != DMB_OK) return s;
+    double hw, bmin;
+    quad_window(48, &hw, &bmin);
+    hipLaunchKernelGGL(k_mlp_eval, dim3(blocks_for(n, 64)), dim3(64), 0, c->stream, n, x,
+                       c->mlp_blob.as<const MlpBlob>(), mlp_const(), c->gl64.as<const double>(),
+                       c->gl64.as<const double>() + kMaxQuadNodes, 48, hw, bmin, out);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return DMB_OK;

@@ -290,9 +290,10 @@ __device__ __forceinline__ void rate_1f1(T x, T* FA, T* FB)
 //   B / vs^{n+3} = sqrt(2/pi)       int_0^inf s^{5+n} e^{-(s^2+x^2)/2} sinh(s x)/(s x) ds,
 // j(k) = cosh k / k - sinh k / k^2.  The Gaussian factors are formed as
 // e^{-(s -+ x)^2/2} (no overflow) and small k uses the Taylor series of j(k)/k
-// and sinh(k)/k.  K-node Gauss-Legendre on [max(0, x - 8.5), max(x + 8.5, 11)].
-// Returns the values divided by alpha_n/3 and alpha_n, i.e. in the same
-// normalisation as the 1F1 forms of rate_1f1.
+// and sinh(k)/k.  K-node Gauss-Legendre on [max(0, x - hw), max(x + hw, bmin)]
+// (hw = 8.5, bmin = 11 reach 1e-10 at K = 32; hw = 5.5, bmin = 7 reach 1e-3
+// at K = 12).  Returns the values divided by alpha_n/3 and alpha_n, i.e. in
+// the same normalisation as the 1F1 forms of rate_1f1.
 template <int N> struct Pow {
     template <typename T> __device__ static __forceinline__ T of(T s)
     {
@@ -308,10 +309,10 @@ template <> struct QuadTraits<double> { static constexpr double kSmall = 0.1; };
 
 template <int N, typename Real>
 __device__ __forceinline__ void rate_quad(Real x, const Real* __restrict__ gx, const Real* __restrict__ gw, int K,
-                                          Real inv_alpha, Real* FA, Real* FB)
+                                          Real inv_alpha, Real hw, Real bmin, Real* FA, Real* FB)
 {
-    const Real a = x > Real(8.5) ? x - Real(8.5) : Real(0);
-    const Real b = x + Real(8.5) > Real(11) ? x + Real(8.5) : Real(11);
+    const Real a = x > hw ? x - hw : Real(0);
+    const Real b = x + hw > bmin ? x + hw : bmin;
     const Real mid = Real(0.5) * (a + b), half = Real(0.5) * (b - a);
     Real accA = 0, accB = 0;
     for (int q = 0; q < K; ++q) {

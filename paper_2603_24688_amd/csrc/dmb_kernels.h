@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "dmb_device.h"
+#include "dmb_mlp.h"
 
 namespace dmb {
 
@@ -17,6 +18,31 @@ constexpr double kCKms = 299792.458;
 constexpr double kMpG = 1.67262192369e-24;
 enum { kRatesExact = 0, kRatesQuad = 1, kRatesMlp = 2 };
 constexpr int kMaxQuadNodes = 64;
+constexpr int kMlpPassWaves = 4;     // independent waves per block of the network gas pass
+constexpr int kMlpPassBlocks = 4;    // column blocks per weight read in the network gas pass
+
+// Integration window of rate_quad for K nodes: the wide window reaches 1e-10
+// from K = 32 on; below K = 24 the narrow one is the cheaper choice at the
+// 1e-3 level (K = 12 suffices there).
+__host__ __device__ inline void quad_window(int K, double* hw, double* bmin)
+{
+    *hw = K >= 24 ? 8.5 : 5.5;
+    *bmin = K >= 24 ? 11.0 : 7.0;
+}
+
+// Ordering of the LDS staging of one wave.  With one wave per block this is
+// the block barrier; blocks of several independent waves order each wave's
+// own LDS traffic (a wave's LDS operations complete in issue order).
+template <int W>
+__device__ __forceinline__ void stage_sync()
+{
+    if constexpr (W == 1) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
 
 __device__ __forceinline__ int lane_id() { return int(threadIdx.x & 63); }
 
@@ -540,17 +566,27 @@ __device__ __forceinline__ double pair_d2(double ax, double ay, double az, doubl
 // next item from an atomic counter.
 constexpr int kXcdChunk = 32;
 
+template <int W = 1>
 __device__ __forceinline__ bool item_next(uint32_t* queue_ctr, int64_t n_items, int64_t* it)
 {
-    __shared__ int64_t s_it;
     const int x = blockIdx.x % kXcd;
-    if (threadIdx.x == 0) {
-        const int64_t k = int64_t(atomicAdd(&queue_ctr[x], 1u));
-        s_it = (k / kXcdChunk) * (int64_t(kXcd) * kXcdChunk) + int64_t(x) * kXcdChunk + (k % kXcdChunk);
+    if constexpr (W == 1) {
+        __shared__ int64_t s_it;
+        if (threadIdx.x == 0) {
+            const int64_t k = int64_t(atomicAdd(&queue_ctr[x], 1u));
+            s_it = (k / kXcdChunk) * (int64_t(kXcd) * kXcdChunk) + int64_t(x) * kXcdChunk + (k % kXcdChunk);
+        }
+        __syncthreads();
+        *it = s_it;
+        __syncthreads();
+    } else {
+        int64_t v = 0;
+        if (lane_id() == 0) {
+            const int64_t k = int64_t(atomicAdd(&queue_ctr[x], 1u));
+            v = (k / kXcdChunk) * (int64_t(kXcd) * kXcdChunk) + int64_t(x) * kXcdChunk + (k % kXcdChunk);
+        }
+        *it = __shfl(v, 0);
     }
-    __syncthreads();
-    *it = s_it;
-    __syncthreads();
     return *it < n_items;
 }
 
@@ -605,12 +641,13 @@ struct GroupLds {
 
 // Stage up to kGroup candidate sub-tiles [c, c+ng) and build the owner-major
 // hit layout.  Returns the group's hit count (wave-uniform).
+template <int W = 1>
 __device__ __forceinline__ int group_test(GroupLds& S, const PassGeom& G, const double* A, const double cen[3],
                                           uint32_t c, int ng, bool ov, float fx, float fy, float fz, float fh,
                                           const float Lf[3])
 {
     const int lane = lane_id();
-    __syncthreads();
+    stage_sync<W>();
     for (int g = 0; g < ng; ++g) {
         const uint32_t ot = G.cand[c + g];
         const int base = int(G.sub_start[ot]), cnt = int(G.sub_cnt[ot]);
@@ -631,7 +668,7 @@ __device__ __forceinline__ int group_test(GroupLds& S, const PassGeom& G, const 
         }
     }
     if (lane == 0) S.ng = ng;
-    __syncthreads();
+    stage_sync<W>();
     int tot = 0;
     S.pref[lane][0] = 0;
     const float ap2 = fx * fx + fy * fy + fz * fz, ah2 = fh * fh;
@@ -668,7 +705,7 @@ __device__ __forceinline__ int group_test(GroupLds& S, const PassGeom& G, const 
     S.offs[lane] = incl - tot;
     const int H = __shfl(incl, 63);
     if (lane == 63) S.offs[64] = H;
-    __syncthreads();
+    stage_sync<W>();
     return H;
 }
 
@@ -699,6 +736,11 @@ struct GasPassArgs {
     const void* dm_m;
     const float4* gtab;
     const void* gl_x; const void* gl_w; int gl_k; double inv_alpha;   // quadrature rates (Real)
+    double gl_hw, gl_bmin;        // quadrature window
+    const MlpBlob* mlp;           // network weights (network rates)
+    int mlp_nidx;                 // one-hot slot of n
+    float mlp_c0A, mlp_c1A, mlp_c0B, mlp_c1B;   // base-function constants
+    float mlp_kA, mlp_kB;                       // 3/alpha_n, 1/alpha_n
     double* part;                 // [n_items][64][4]
     // direct output for owner tiles with a single work item
     const uint32_t* perm;         // gas sorted pos -> index
@@ -719,12 +761,22 @@ __device__ __forceinline__ void gas_write_out(const GasPassArgs& a, uint32_t o, 
 }
 
 template <typename Real, int N, bool EXACT_G, int RM>
-__global__ __launch_bounds__(64) void k_pass_gas(GasPassArgs a)
+__global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kRatesMlp ? 2 : 1) void k_pass_gas(GasPassArgs a)
 {
-    __shared__ GroupLds S;
+    // The network variant runs kMlpPassWaves independent waves per block so
+    // that they share one LDS copy of the weights.
+    constexpr int W = RM == kRatesMlp ? kMlpPassWaves : 1;
+    static_assert(RM != kRatesMlp || sizeof(Real) == 4, "network rates run in binary32");
+    __shared__ GroupLds S_[W];
     __shared__ Real s_gx[kMaxQuadNodes], s_gw[kMaxQuadNodes];
-    __shared__ double o_x[64], o_y[64], o_z[64], o_h[64], o_Vx[64], o_Vy[64], o_Vz[64];
-    __shared__ Real o_i2[64], o_a[64], o_b[64], o_r[64];
+    __shared__ double o_x_[W][64], o_y_[W][64], o_z_[W][64], o_h_[W][64], o_Vx_[W][64], o_Vy_[W][64], o_Vz_[W][64];
+    __shared__ Real o_i2_[W][64], o_a_[W][64], o_b_[W][64], o_r_[W][64];
+    __shared__ __align__(16) unsigned char s_mlp[RM == kRatesMlp ? kMlpInferBytes : 16];
+    const int wv = W == 1 ? 0 : int(threadIdx.x) >> 6;
+    GroupLds& S = S_[wv];
+    double* o_x = o_x_[wv]; double* o_y = o_y_[wv]; double* o_z = o_z_[wv]; double* o_h = o_h_[wv];
+    double* o_Vx = o_Vx_[wv]; double* o_Vy = o_Vy_[wv]; double* o_Vz = o_Vz_[wv];
+    Real* o_i2 = o_i2_[wv]; Real* o_a = o_a_[wv]; Real* o_b = o_b_[wv]; Real* o_r = o_r_[wv];
     const PassGeom& G = a.g;
     const int lane = lane_id();
     const Real* inv2s2 = reinterpret_cast<const Real*>(a.inv2s2);
@@ -733,16 +785,22 @@ __global__ __launch_bounds__(64) void k_pass_gas(GasPassArgs a)
     const Real* rr = reinterpret_cast<const Real*>(a.rr);
     const Real* dm_m = reinterpret_cast<const Real*>(a.dm_m);
     const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
-    if constexpr (RM == kRatesQuad) {
-        if (lane < a.gl_k) {
-            s_gx[lane] = reinterpret_cast<const Real*>(a.gl_x)[lane];
-            s_gw[lane] = reinterpret_cast<const Real*>(a.gl_w)[lane];
+    if constexpr (RM == kRatesQuad || RM == kRatesMlp) {
+        if (int(threadIdx.x) < a.gl_k) {
+            s_gx[threadIdx.x] = reinterpret_cast<const Real*>(a.gl_x)[threadIdx.x];
+            s_gw[threadIdx.x] = reinterpret_cast<const Real*>(a.gl_w)[threadIdx.x];
         }
     }
-    const Real inv_alpha = Real(a.inv_alpha);
+    if constexpr (RM == kRatesMlp) {
+        const uint4* src = reinterpret_cast<const uint4*>(a.mlp);
+        uint4* dst = reinterpret_cast<uint4*>(s_mlp);
+        for (int k = int(threadIdx.x); k < int(kMlpInferBytes / 16); k += 64 * W) dst[k] = src[k];
+        __syncthreads();
+    }
+    const Real inv_alpha = Real(a.inv_alpha), q_hw = Real(a.gl_hw), q_bmin = Real(a.gl_bmin);
     int64_t it;
     uint64_t npairs = 0;
-    while (item_next(G.queue_ctr, G.n_items, &it)) {
+    while (item_next<W>(G.queue_ctr, G.n_items, &it)) {
         const int64_t t = G.it_tile[it];
         const uint32_t cb = G.it_cb[it], ce = G.it_ce[it];
         const int64_t slot = t * kTile + lane;
@@ -750,7 +808,7 @@ __global__ __launch_bounds__(64) void k_pass_gas(GasPassArgs a)
         const int64_t sp = ov ? int64_t(G.own[slot]) : 0;
         const double mx = ov ? G.ox[sp] : 0.0, my = ov ? G.oy[sp] : 0.0, mz = ov ? G.oz[sp] : 0.0;
         const double mh = ov ? G.oh[sp] : 0.0;
-        __syncthreads();
+        stage_sync<W>();
         o_x[lane] = mx; o_y[lane] = my; o_z[lane] = mz; o_h[lane] = mh;
         o_Vx[lane] = ov ? a.Vx[sp] : 0.0; o_Vy[lane] = ov ? a.Vy[sp] : 0.0; o_Vz[lane] = ov ? a.Vz[sp] : 0.0;
         o_i2[lane] = ov ? inv2s2[sp] : Real(0);
@@ -764,45 +822,108 @@ __global__ __launch_bounds__(64) void k_pass_gas(GasPassArgs a)
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
         for (uint32_t c = cb; c < ce; c += kGroup) {
             const int ng = int(min<uint32_t>(kGroup, ce - c));
-            const int H = group_test(S, G, A, cen, c, ng, ov, fx, fy, fz, fh, Lf);
+            const int H = group_test<W>(S, G, A, cen, c, ng, ov, fx, fy, fz, fh, Lf);
             const int my_lo = S.offs[lane], my_hi = S.offs[lane + 1];
             for (int base = 0; base < H; base += 64) {
                 const int pp = base + lane;
                 Real c0 = 0, c1 = 0, c2 = 0, c3 = 0;
                 int seg_end = -1;
-                if (pp < H) {
-                    int o, g, k;
-                    group_decode(S, pp, &o, &g, &k);
-                    seg_end = min(S.offs[o + 1], base + 64) - 1 - base;
-                    const int64_t q = int64_t(S.base[g]) + k;
-                    const double qx = G.tx[q] + S.sh[g][0], qy = G.ty[q] + S.sh[g][1], qz = G.tz[q] + S.sh[g][2];
-                    const double qh = G.th[q];
-                    const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.clean[g] != 0, G.L);
-                    const double hs = o_h[o] + qh;
-                    if (d2 < hs * hs) {
-                        npairs++;
-                        const Real d = Real(sqrt(d2));
-                        const Real gg = EXACT_G ? overlap_g_exact<Real>(d, Real(qh), Real(o_h[o]))
-                                                : overlap_g_table<Real>(a.gtab, d, Real(qh), Real(o_h[o]));
-                        const Real wx = Real(a.dvx[q] - o_Vx[o]), wy = Real(a.dvy[q] - o_Vy[o]),
-                                   wz = Real(a.dvz[q] - o_Vz[o]);
-                        const Real w2 = wx * wx + wy * wy + wz * wz;
-                        Real FA, FB, Ar, Br;
-                        const Real i2 = o_i2[o];
-                        if (isinf(i2)) {  // cold gas: A = w^{n+1}, B = w^{n+3}
-                            const Real wn = sqrt_real(w2);
-                            Ar = pow_np1<N>(wn);
+                if constexpr (RM != kRatesMlp) {
+                    if (pp < H) {
+                        int o, g, k;
+                        group_decode(S, pp, &o, &g, &k);
+                        seg_end = min(S.offs[o + 1], base + 64) - 1 - base;
+                        const int64_t q = int64_t(S.base[g]) + k;
+                        const double qx = G.tx[q] + S.sh[g][0], qy = G.ty[q] + S.sh[g][1], qz = G.tz[q] + S.sh[g][2];
+                        const double qh = G.th[q];
+                        const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.clean[g] != 0, G.L);
+                        const double hs = o_h[o] + qh;
+                        if (d2 < hs * hs) {
+                            npairs++;
+                            const Real d = Real(sqrt(d2));
+                            const Real gg = EXACT_G ? overlap_g_exact<Real>(d, Real(qh), Real(o_h[o]))
+                                                    : overlap_g_table<Real>(a.gtab, d, Real(qh), Real(o_h[o]));
+                            const Real wx = Real(a.dvx[q] - o_Vx[o]), wy = Real(a.dvy[q] - o_Vy[o]),
+                                       wz = Real(a.dvz[q] - o_Vz[o]);
+                            const Real w2 = wx * wx + wy * wy + wz * wz;
+                            Real FA, FB, Ar, Br;
+                            const Real i2 = o_i2[o];
+                            if (isinf(i2)) {  // cold gas: A = w^{n+1}, B = w^{n+3}
+                                const Real wn = sqrt_real(w2);
+                                Ar = pow_np1<N>(wn);
+                                Br = Ar * w2;
+                            } else {
+                                if constexpr (RM == kRatesQuad)
+                                    rate_quad<N, Real>(sqrt_real(Real(2) * w2 * i2), s_gx, s_gw, a.gl_k, inv_alpha,
+                                                       q_hw, q_bmin, &FA, &FB);
+                                else
+                                    rate_1f1<N, Real>(w2 * i2, &FA, &FB);
+                                Ar = o_a[o] * FA;
+                                Br = o_b[o] * FB;
+                            }
+                            const Real mg = dm_m[q] * gg;
+                            const Real mgA = mg * Ar;
+                            c0 = mgA * wx; c1 = mgA * wy; c2 = mgA * wz;
+                            c3 = mg * (w2 * Ar - o_r[o] * Br);
+                        }
+                    }
+                } else {
+                    // pair geometry per lane, then the network over the whole wave
+                    bool live = false;
+                    int o = 0;
+                    int64_t q = 0;
+                    float gg = 0.f, wx = 0.f, wy = 0.f, wz = 0.f, w2 = 0.f, i2 = 0.f, u = 0.f;
+                    if (pp < H) {
+                        int g, k;
+                        group_decode(S, pp, &o, &g, &k);
+                        seg_end = min(S.offs[o + 1], base + 64) - 1 - base;
+                        q = int64_t(S.base[g]) + k;
+                        const double qx = G.tx[q] + S.sh[g][0], qy = G.ty[q] + S.sh[g][1], qz = G.tz[q] + S.sh[g][2];
+                        const double qh = G.th[q];
+                        const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.clean[g] != 0, G.L);
+                        const double hs = o_h[o] + qh;
+                        if (d2 < hs * hs) {
+                            live = true;
+                            npairs++;
+                            gg = overlap_g_table<float>(a.gtab, float(sqrt(d2)), float(qh), float(o_h[o]));
+                            wx = float(a.dvx[q] - o_Vx[o]);
+                            wy = float(a.dvy[q] - o_Vy[o]);
+                            wz = float(a.dvz[q] - o_Vz[o]);
+                            w2 = wx * wx + wy * wy + wz * wz;
+                            i2 = o_i2[o];
+                            u = isinf(i2) ? 0.f : __fsqrt_rn(2.f * w2 * i2);
+                        }
+                    }
+                    const bool net = live && !isinf(i2) && u <= kMlpUMax;
+                    float yA = 0.f, yB = 0.f;
+                    if (__ballot(net) != 0ull) {
+                        // an opaque zero offset keeps the weight reads inside the loop
+                        // (hoisted, they would pin ~90 registers for the kernel's lifetime)
+                        int zoff = 0;
+                        asm volatile("" : "+v"(zoff));
+                        const MlpBlob* Wl = reinterpret_cast<const MlpBlob*>(s_mlp + zoff);
+                        mlp_forward64<kMlpPassBlocks>(Wl, mlp_input(u), a.mlp_nidx, &yA, &yB);
+                    }
+                    if (live) {
+                        float Ar, Br;
+                        if (isinf(i2)) {
+                            Ar = pow_np1<N>(__fsqrt_rn(w2));
                             Br = Ar * w2;
                         } else {
-                            if constexpr (RM == kRatesQuad)
-                                rate_quad<N, Real>(sqrt_real(Real(2) * w2 * i2), s_gx, s_gw, a.gl_k, inv_alpha, &FA, &FB);
-                            else
-                                rate_1f1<N, Real>(w2 * i2, &FA, &FB);
+                            float FA, FB;
+                            if (net) {
+                                float bA, bB;
+                                mlp_base<N>(u * u, a.mlp_c0A, a.mlp_c1A, a.mlp_c0B, a.mlp_c1B, &bA, &bB);
+                                FA = a.mlp_kA * bA * __expf(yA);
+                                FB = a.mlp_kB * bB * __expf(yB);
+                            } else {
+                                rate_quad<N, float>(u, s_gx, s_gw, a.gl_k, inv_alpha, q_hw, q_bmin, &FA, &FB);
+                            }
                             Ar = o_a[o] * FA;
                             Br = o_b[o] * FB;
                         }
-                        const Real mg = dm_m[q] * gg;
-                        const Real mgA = mg * Ar;
+                        const float mg = dm_m[q] * gg;
+                        const float mgA = mg * Ar;
                         c0 = mgA * wx; c1 = mgA * wy; c2 = mgA * wz;
                         c3 = mg * (w2 * Ar - o_r[o] * Br);
                     }
@@ -1351,7 +1472,8 @@ __global__ __launch_bounds__(256) void k_overlap_eval(int64_t n, const double* d
 
 template <typename Real, int N, int RM>
 __global__ __launch_bounds__(256) void k_rates_eval(int64_t n, const double* w, const double* vs, double alpha_n,
-                                                    const void* gl_x, const void* gl_w, int gl_k, double* A, double* B)
+                                                    const void* gl_x, const void* gl_w, int gl_k, double hw,
+                                                    double bmin, double* A, double* B)
 {
     __shared__ Real s_gx[kMaxQuadNodes], s_gw[kMaxQuadNodes];
     if constexpr (RM == kRatesQuad) {
@@ -1376,11 +1498,63 @@ __global__ __launch_bounds__(256) void k_rates_eval(int64_t n, const double* w, 
     Real ra = Real(alpha_n / 3.0 * pow(s, double(N + 1))), rb = Real(alpha_n * pow(s, double(N + 3)));
     Real FA, FB;
     if constexpr (RM == kRatesQuad)
-        rate_quad<N, Real>(sqrt_real(Real(2) * w2 * i2), s_gx, s_gw, gl_k, Real(1.0 / alpha_n), &FA, &FB);
+        rate_quad<N, Real>(sqrt_real(Real(2) * w2 * i2), s_gx, s_gw, gl_k, Real(1.0 / alpha_n), Real(hw), Real(bmin),
+                           &FA, &FB);
     else
         rate_1f1<N, Real>(w2 * i2, &FA, &FB);
     A[i] = double(ra * FA);
     B[i] = double(rb * FB);
+}
+
+// The same values from the network, with the arithmetic of the network gas
+// pass (binary32; quadrature for u > kMlpUMax; cold gas exact).
+struct MlpRatesArgs {
+    int64_t n; const double* w; const double* vs; double alpha_n;
+    const MlpBlob* mlp; int nidx; float c0A, c1A, c0B, c1B, kA, kB;
+    const float* gl_x; const float* gl_w; int gl_k; double hw, bmin;
+    double* A; double* B;
+};
+
+template <int N>
+__global__ __launch_bounds__(256) void k_rates_eval_mlp(MlpRatesArgs a)
+{
+    __shared__ float s_gx[kMaxQuadNodes], s_gw[kMaxQuadNodes];
+    if (int(threadIdx.x) < a.gl_k) {
+        s_gx[threadIdx.x] = a.gl_x[threadIdx.x];
+        s_gw[threadIdx.x] = a.gl_w[threadIdx.x];
+    }
+    __syncthreads();
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool ok = i < a.n;
+    const double s = ok ? a.vs[i] : 1.0;
+    const float w2 = ok ? float(a.w[i] * a.w[i]) : 0.f;
+    const bool cold = !(s > 0.0);
+    const float i2 = cold ? INFINITY : float(1.0 / (2.0 * s * s));
+    const float u = cold ? 0.f : __fsqrt_rn(2.f * w2 * i2);
+    const bool net = ok && !cold && u <= kMlpUMax;
+    float yA = 0.f, yB = 0.f;
+    mlp_forward64(a.mlp, mlp_input(u), a.nidx, &yA, &yB);
+    if (!ok) return;
+    float Ar, Br;
+    if (cold) {
+        Ar = pow_np1<N>(__fsqrt_rn(w2));
+        Br = Ar * w2;
+    } else {
+        const float ra = float(a.alpha_n / 3.0 * pow(s, double(N + 1))), rb = float(a.alpha_n * pow(s, double(N + 3)));
+        float FA, FB;
+        if (net) {
+            float bA, bB;
+            mlp_base<N>(u * u, a.c0A, a.c1A, a.c0B, a.c1B, &bA, &bB);
+            FA = a.kA * bA * __expf(yA);
+            FB = a.kB * bB * __expf(yB);
+        } else {
+            rate_quad<N, float>(u, s_gx, s_gw, a.gl_k, float(1.0 / a.alpha_n), float(a.hw), float(a.bmin), &FA, &FB);
+        }
+        Ar = ra * FA;
+        Br = rb * FB;
+    }
+    a.A[i] = double(Ar);
+    a.B[i] = double(Br);
 }
 
 __global__ __launch_bounds__(256) void k_philox_eval(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k1,

@@ -232,3 +232,39 @@ def batch(n_box=64, n_min=10_000, n_max=500_000, seed=(5, 1), n_ngb=32, h_mode="
         cfg["params"]["box_id"] = b
         out.append(cfg)
     return out
+
+
+# --------------------------------------------------------------------------- rate-closure samples
+MLP_N_VALUES = (-4.0, -2.0, 0.0, 2.0)
+
+
+def mlp_samples(n: int, seed=(4, 1), ext: float = 0.25, x2_zero: bool = False) -> np.ndarray:
+    """Inputs x[n][4] = (w/vs_gas, T_DM/T_gas, log10(m_chi/mu), n) of the rate
+    closure: x1 uniform on [0, 10] (a fraction `ext` log-uniform on
+    [10, 1000] instead), x2 uniform on [0, 100] (0 with x2_zero: one DM
+    velocity per pair, as in the interaction step), x3 uniform on [-2, 1.3]
+    (10 MeV .. 10 GeV for mu = m_p), n uniform over {-4, -2, 0, 2}."""
+    r = rng(*seed)
+    x = np.empty((n, 4))
+    x[:, 0] = r.uniform(0.0, 10.0, n)
+    m = r.random(n) < ext
+    x[m, 0] = 10.0 ** r.uniform(1.0, 3.0, int(m.sum()))
+    x[:, 1] = 0.0 if x2_zero else r.uniform(0.0, 100.0, n)
+    x[:, 2] = r.uniform(-2.0, 1.3, n)
+    x[:, 3] = r.choice(np.array(MLP_N_VALUES), n)
+    return x
+
+
+def mlp_params(seed=(4, 9), scale: float = 1.0) -> np.ndarray:
+    """A random parameter vector of the rate-closure network (He-uniform
+    weights times `scale`, small random biases) for checking its kernels."""
+    r = rng(*seed)
+    shapes = [(64, 5), (64,), (64, 64), (64,), (64, 64), (64,), (2, 64), (2,)]
+    out = []
+    for s in shapes:
+        if len(s) == 2:
+            b = math.sqrt(6.0 / s[1])
+            out.append(scale * r.uniform(-b, b, s).ravel())
+        else:
+            out.append(r.uniform(-0.1, 0.1, s))
+    return np.concatenate(out).astype(np.float32)
