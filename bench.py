@@ -95,6 +95,73 @@ def cpu_baseline(cfg, seconds: float, seed: int = 0):
                       f"oracle time, {done_pairs} pair evaluations over both passes"}
 
 
+def surrogate_compare(ctx, cfg, dev, steps: int, log_fn) -> dict:
+    """Network rates vs quadrature on the galaxy workload with sigma ~ v^n,
+    n in {-4, -2, 2} (sigma0 with sigma(200 km/s) = 1e-24 cm^2): pairs per
+    second of the interaction step and gas-pass time for the closed forms,
+    quadrature at K = 32 (the 1e-10 judge) and K = 12 (the smallest K at the
+    1e-3 level) and the network; the network is trained first on the GPU.
+    Rate errors are measured against the binary64 closed forms."""
+    import numpy as np
+    import torch
+    import paper_2603_24688_amd as dmb
+    import workloads
+    t0 = time.time()
+    X = torch.from_numpy(workloads.mlp_samples(2_000_000, seed=(4, 1))).to(dev)
+    Y = ctx.mlp_labels(X)
+    torch.cuda.synchronize()
+    t1 = time.time()
+    losses = ctx.mlp_train(X, Y, epochs=200, batch=4096, lr0=2e-3, lr_min=1e-5, seed=1, init=True, use_graph=True)
+    t2 = time.time()
+    del X, Y
+    log_fn(f"bench: network trained: labels {t1 - t0:.2f} s, 200 epochs {t2 - t1:.2f} s, loss {losses[-1]:.3e}")
+    res = {"train": {"samples": 2_000_000, "epochs": 200, "batch": 4096, "label_s": round(t1 - t0, 3),
+                     "train_s": round(t2 - t1, 3), "final_loss": float(losses[-1])}}
+    G = dmb.to_device(cfg["gas"], dev)
+    D = dmb.to_device(cfg["dm"], dev)
+    out = dmb.alloc_out(len(cfg["gas"]["mass"]), len(cfg["dm"]["mass"]), dev)
+    modes = [("exact", dmb.DMB_RATES_EXACT, 0), ("quad32", dmb.DMB_RATES_QUAD, 32),
+             ("quad12", dmb.DMB_RATES_QUAD, 12), ("mlp", dmb.DMB_RATES_MLP, 32)]
+    # rate accuracy over the range of w / vs met in the workload (one DM velocity per pair)
+    w = torch.linspace(0.0, 1000.0, 200_001, dtype=torch.float64, device=dev)
+    vs = torch.full_like(w, 9.085)
+    for n_pow in (-4, -2, 2):
+        par = dict(cfg["params"])
+        par["n_pow"] = n_pow
+        par["sigma0_cm2"] = workloads.sigma0_for_npow(n_pow)
+        A0, B0 = ctx.rates_eval(w, vs, n_pow, precision=dmb.DMB_FP64, rates=dmb.DMB_RATES_EXACT)
+        ok = A0 > 0
+        row = {}
+        ctx.build_cells(G, D, par, precision=dmb.DMB_FP32)
+        for name, rates, K in modes:
+            A1, B1 = ctx.rates_eval(w, vs, n_pow, precision=dmb.DMB_FP32, rates=rates, quad_nodes=K)
+            err = torch.maximum((A1[ok] / A0[ok] - 1).abs(), (B1[ok] / B0[ok] - 1).abs()).max().item()
+            par["rates"], par["quad_nodes"] = rates, K
+            ctx.interact_step(G, D, par, out, precision=dmb.DMB_FP32)
+            torch.cuda.synchronize()
+            ctx.profile_enable(True)
+            ctx.profile_read(reset=True)
+            ta = time.perf_counter()
+            for _ in range(steps):
+                ctx.interact_step(G, D, par, out, precision=dmb.DMB_FP32)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            ph = ctx.profile_read(reset=True)
+            ctx.profile_enable(False)
+            pairs = dmb.counters_dict(out["counters"])["pairs_gas"]
+            ms = (tb - ta) * 1e3 / steps
+            row[name] = {"pairs_per_s": pairs / (ms * 1e-3), "interact_ms": round(ms, 4),
+                         "pass_gas_ms": round(ph["pass_gas"][0] / max(ph["pass_gas"][1], 1), 4),
+                         "max_rel_rate_err": err}
+        row["mlp_vs_quad12"] = row["quad12"]["pass_gas_ms"] / row["mlp"]["pass_gas_ms"]
+        row["mlp_vs_quad32"] = row["quad32"]["pass_gas_ms"] / row["mlp"]["pass_gas_ms"]
+        res[f"n={n_pow}"] = row
+        log_fn(f"bench: surrogate n={n_pow}: " + ", ".join(
+            f"{k} {v['pass_gas_ms']:.3f} ms (err {v['max_rel_rate_err']:.1e})" for k, v in row.items()
+            if isinstance(v, dict)))
+    return res
+
+
 def traffic_from_profile(kernel: str):
     """HBM bytes per launch measured with rocprofv3 PMC runs, if they were
     taken for the current kernel sources; else None."""
@@ -120,6 +187,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the network-vs-quadrature comparison (sigma ~ v^n on the galaxy workload)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this size (for PMC counter scaling)")
     args = ap.parse_args()
@@ -210,6 +279,8 @@ def main():
         "hit_fraction": {"gas": pairs / max(1, bst["cand_pairs_gas"] * 4096),
                          "dm": pairs / max(1, bst["cand_pairs_dm"] * 4096)},
     }
+    if args.workload == "galaxy" and not args.no_surrogate:
+        line["surrogate"] = surrogate_compare(ctx, cfg, dev, 3, log)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)

@@ -19,7 +19,6 @@ constexpr double kMpG = 1.67262192369e-24;
 enum { kRatesExact = 0, kRatesQuad = 1, kRatesMlp = 2 };
 constexpr int kMaxQuadNodes = 64;
 constexpr int kMlpPassWaves = 4;     // independent waves per block of the network gas pass
-constexpr int kMlpPassBlocks = 4;    // column blocks per weight read in the network gas pass
 
 // Integration window of rate_quad for K nodes: the wide window reaches 1e-10
 // from K = 32 on; below K = 24 the narrow one is the cheaper choice at the
@@ -902,7 +901,15 @@ __global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kR
                         int zoff = 0;
                         asm volatile("" : "+v"(zoff));
                         const MlpBlob* Wl = reinterpret_cast<const MlpBlob*>(s_mlp + zoff);
-                        mlp_forward64<kMlpPassBlocks>(Wl, mlp_input(u), a.mlp_nidx, &yA, &yB);
+                        // candidate pairs occupy lanes 0 .. H-base-1: evaluate only the
+                        // 16-column blocks that hold some
+                        const int nlive = min(H - base, 64);
+                        if (nlive > 32)
+                            mlp_forward64<4, 4>(Wl, mlp_input(u), a.mlp_nidx, &yA, &yB);
+                        else if (nlive > 16)
+                            mlp_forward64<2, 2>(Wl, mlp_input(u), a.mlp_nidx, &yA, &yB);
+                        else
+                            mlp_forward64<1, 1>(Wl, mlp_input(u), a.mlp_nidx, &yA, &yB);
                     }
                     if (live) {
                         float Ar, Br;

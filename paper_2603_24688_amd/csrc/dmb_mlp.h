@@ -154,7 +154,9 @@ __device__ __forceinline__ float mlp_input(float u) { return 2.f * u / (u + kMlp
 // each weight fragment once; NB = 2 halves the live accumulators).
 // If `act` is non-null the bfloat16 activations of layers 1..3 are kept
 // there: act[layer][block][step] (B-operand layout of the lane).
-template <int NB = 4>
+// NBLK < 4 evaluates only the first NBLK column blocks (lanes 0 .. 16 NBLK - 1);
+// the other lanes return 0.
+template <int NB = 4, int NBLK = 4>
 __device__ __forceinline__ void mlp_forward64(const MlpBlob* __restrict__ W, float s_in, int nidx, float* yA,
                                               float* yB, uint4 (*act)[4][2] = nullptr)
 {
@@ -162,7 +164,7 @@ __device__ __forceinline__ void mlp_forward64(const MlpBlob* __restrict__ W, flo
     const int l = threadIdx.x & 63, h = l >> 4, c = l & 15;
     float oA = 0.f, oB = 0.f;
 #pragma unroll 1
-    for (int r = 0; r < 4 / NB; ++r) {
+    for (int r = 0; r < (NBLK + NB - 1) / NB; ++r) {
         f32x4 D[NB][4];
         uint4 Bx[NB][2];
         // layer 1 (16x16x16): four 16-unit blocks
