@@ -160,6 +160,38 @@ dmb_status dmb_rates_eval(dmb_ctx *ctx, int64_t n, const double *w, const double
 dmb_status dmb_philox_eval(dmb_ctx *ctx, int64_t n, const uint32_t *ctr, uint64_t seed, uint32_t *out);
 
 /* ------------------------------------------------------------------------
+ * Batched boxes: parameter sweeps over many independent volumes (each with
+ * its own sigma0, m_chi, periodic box, particle counts) run as one step.
+ * Each box keeps its own Morton cell structure; each of the two pair passes
+ * is one persistent launch over the work items of all boxes.  gas, dm, par
+ * and out are HOST arrays of nbox structs pointing at device data; every
+ * box's out.counters must be set.  n_pow, precision, rates and quad_nodes
+ * must agree across boxes.  Results per box are those of dmb_build_cells +
+ * dmb_interact_step on that box with the same tuning.
+ */
+/* Cell structures of all boxes (as dmb_build_cells, box by box).
+ * Errors: as dmb_build_cells, the message naming the box. */
+dmb_status dmb_batch_build(dmb_ctx *ctx, int32_t nbox, const dmb_particles *gas, const dmb_particles *dm,
+                           const dmb_params *par);
+/* nsteps interaction steps of every box; step k uses Philox step
+ * par[b].step + k; outputs hold the last step.  use_graph != 0 captures one
+ * step as a hipGraph (on the context stream, or on a private non-blocking
+ * stream when the context uses the default stream) and replays it nsteps
+ * times; the call then waits for the GPU.  Errors: DMB_EINVAL, DMB_ESTALE
+ * (sizes differ from the last dmb_batch_build), DMB_EHIP. */
+dmb_status dmb_batch_step(dmb_ctx *ctx, int32_t nbox, const dmb_particles *gas, const dmb_particles *dm,
+                          const dmb_params *par, dmb_out *out, int32_t nsteps, int32_t use_graph);
+/* Autotuner: times the batched step over work-item sizes {32, 64, 128}
+ * candidate sub-tiles, sub-tile granularities (cut at Morton level median -
+ * {0, 1, 2}) and persistent grids of {50, 100} % of the resident maximum,
+ * keeps the fastest setting in the context (it applies to every later build
+ * and step) and rebuilds the boxes with it.  choice (HOST, 4 int64, nullable)
+ * receives {work-item size, granularity, grid %, microseconds per step}.
+ * Overwrites the outputs.  Errors: as dmb_batch_step. */
+dmb_status dmb_batch_tune(dmb_ctx *ctx, int32_t nbox, const dmb_particles *gas, const dmb_particles *dm,
+                          const dmb_params *par, dmb_out *out, int64_t *choice);
+
+/* ------------------------------------------------------------------------
  * Learned closure for the rate integrals (an extension of the method: the
  * paper evaluates eq. scrA / scrB through 1F1; here a small network may stand
  * in for them, with quadrature as its judge and fallback).

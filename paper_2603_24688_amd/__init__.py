@@ -26,7 +26,8 @@ STATUS = {0: "DMB_OK", -1: "DMB_EINVAL", -2: "DMB_ENOMEM", -3: "DMB_EHIP", -4: "
 EXPORTS = ["dmb_create", "dmb_destroy", "dmb_set_stream", "dmb_build_cells", "dmb_interact_step",
            "dmb_overlap_eval", "dmb_rates_eval", "dmb_philox_eval", "dmb_profile_enable", "dmb_profile_read",
            "dmb_build_stats", "dmb_last_error", "dmb_mlp_labels", "dmb_mlp_init", "dmb_mlp_set_params",
-           "dmb_mlp_get_params", "dmb_mlp_grad", "dmb_mlp_train", "dmb_mlp_eval"]
+           "dmb_mlp_get_params", "dmb_mlp_grad", "dmb_mlp_train", "dmb_mlp_eval", "dmb_batch_build",
+           "dmb_batch_step", "dmb_batch_tune"]
 BUILD_STATS = ["active_gas", "active_dm", "gas_tiles", "dm_tiles", "gas_owner_tiles", "dm_owner_tiles",
                "cand_pairs_gas", "cand_pairs_dm", "items_gas", "items_dm"]
 PHASES = ["build", "gather", "pass_gas", "combine_gas", "pass_dm", "combine_dm", "resolve"]
@@ -99,6 +100,14 @@ def load_library(path: str = LIB_PATH):
     L.dmb_mlp_train.restype = C.c_int
     L.dmb_mlp_train.argtypes = [vp, i64, vp, vp, C.POINTER(MlpTrainCfg), vp]
     L.dmb_mlp_eval.restype = C.c_int; L.dmb_mlp_eval.argtypes = [vp, i64, vp, vp]
+    L.dmb_batch_build.restype = C.c_int
+    L.dmb_batch_build.argtypes = [vp, i32, C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params)]
+    L.dmb_batch_step.restype = C.c_int
+    L.dmb_batch_step.argtypes = [vp, i32, C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params),
+                                 C.POINTER(Out), i32, i32]
+    L.dmb_batch_tune.restype = C.c_int
+    L.dmb_batch_tune.argtypes = [vp, i32, C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params),
+                                 C.POINTER(Out), vp]
     _lib = L
     return L
 
@@ -206,6 +215,37 @@ class Context:
         self._check(self.lib.dmb_rates_eval(self.h, w.numel(), _ptr(w), _ptr(vs), int(n_pow), precision, int(rates),
                                             int(quad_nodes), _ptr(A), _ptr(B)), "dmb_rates_eval")
         return A, B
+
+    # -- batched boxes -------------------------------------------------------------------------
+    @staticmethod
+    def _batch_structs(gas_list, dm_list, par_list, precision, out_list=None):
+        nb = len(gas_list)
+        if not (len(dm_list) == nb and len(par_list) == nb and (out_list is None or len(out_list) == nb)):
+            raise ValueError("batch lists differ in length")
+        G = (Particles * nb)(*[_particles(g) for g in gas_list])
+        D = (Particles * nb)(*[_particles(d) for d in dm_list])
+        P = (Params * nb)(*[_params(p, precision) for p in par_list])
+        O = None
+        if out_list is not None:
+            O = (Out * nb)(*[Out(_ptr(o["dv_dm"]), _ptr(o["dp_gas"]), _ptr(o["de_gas"]), _ptr(o["partner"]),
+                                 _ptr(o.get("p_sum")), _ptr(o.get("p_max")), _ptr(o["counters"])) for o in out_list])
+        return nb, G, D, P, O
+
+    def batch_build(self, gas_list, dm_list, par_list, precision: int = DMB_FP32):
+        nb, G, D, P, _ = self._batch_structs(gas_list, dm_list, par_list, precision)
+        self._check(self.lib.dmb_batch_build(self.h, nb, G, D, P), "dmb_batch_build")
+
+    def batch_step(self, gas_list, dm_list, par_list, out_list, precision: int = DMB_FP32, nsteps: int = 1,
+                   graph: bool = False):
+        nb, G, D, P, O = self._batch_structs(gas_list, dm_list, par_list, precision, out_list)
+        self._check(self.lib.dmb_batch_step(self.h, nb, G, D, P, O, int(nsteps), int(bool(graph))), "dmb_batch_step")
+
+    def batch_tune(self, gas_list, dm_list, par_list, out_list, precision: int = DMB_FP32) -> dict:
+        nb, G, D, P, O = self._batch_structs(gas_list, dm_list, par_list, precision, out_list)
+        ch = (C.c_int64 * 4)()
+        self._check(self.lib.dmb_batch_tune(self.h, nb, G, D, P, O, ch), "dmb_batch_tune")
+        return {"work_item": int(ch[0]), "subtile_delta": int(ch[1]), "grid_pct": int(ch[2]),
+                "us_per_step": int(ch[3])}
 
     # -- learned rate closure ----------------------------------------------------------------
     def mlp_labels(self, x, quad_nodes: int = 0):

@@ -46,6 +46,21 @@ struct Pairs {                             // candidate lists: owner tiles of A 
     int64_t total = 0, nitems = 0;
 };
 
+// Cell structure and per-step buffers of one box (one periodic volume or
+// open region).  The context keeps one for dmb_build_cells / dmb_interact_step
+// and one per box of the batched calls.
+struct Cells {
+    Species gas, dm;
+    Pairs gp, dp;                          // gas owners x DM tiles; DM owners x gas tiles
+    DevBuf boxL;                           // periodic side lengths (device, 4 doubles)
+    DevBuf part_gas, part_p, part_pm, part_nb, psum_own;
+    DevBuf qctr, slist;
+    int64_t built_ngas = -1, built_ndm = -1;
+    const double* built_gas_pos = nullptr;
+    const double* built_dm_pos = nullptr;
+    double built_L[3] = {0, 0, 0};
+};
+
 }  // namespace
 
 struct dmb_ctx {
@@ -53,19 +68,18 @@ struct dmb_ctx {
     hipStream_t stream = nullptr;
     int num_cu = 256;
     DevBuf gtab;
-    Species gas, dm;
-    Pairs gp, dp;                          // gas owners x DM tiles; DM owners x gas tiles
+    Cells cells;                           // single-box structure
+    Cells* X = &cells;                     // structure the internal build / step functions act on
+    std::vector<Cells*> boxes;             // batched boxes
+    DevBuf bstep, bgeom, bitem;            // batched step: Philox step offset, per-box pass arguments, item offsets
     DevBuf scan_tmp[4];
     DevBuf sort_table;
-    DevBuf bbox_part, boxL;
-    DevBuf part_gas, part_p, part_pm, part_nb, psum_own;
-    DevBuf qctr, slist;
+    DevBuf bbox_part;
     DevBuf counters_local;
-    int64_t built_ngas = -1, built_ndm = -1;
-    const double* built_gas_pos = nullptr;
-    const double* built_dm_pos = nullptr;
-    double built_L[3] = {0, 0, 0};
     int split = 64;
+    int subtile_delta = 1;                 // (tunable) sub-tile cut: Morton level below (median - delta)
+    int grid_pct = 100;                    // (tunable) persistent grid size, % of the resident maximum
+    int batch_n = 0;                       // boxes of the last batch build
     DevBuf gl64, gl32;                     // Gauss-Legendre nodes [x | w] for the quadrature rates
     int gl_k = 0;
     // learned rate closure
@@ -213,9 +227,9 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
     ENSURE(c, c->bbox_part, nparts * 6 * sizeof(double));
     hipLaunchKernelGGL(k_bbox_partial, dim3(nparts), dim3(256), 0, c->stream, p->pos, n, c->bbox_part.as<double>());
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, c->stream, c->bbox_part.as<const double>(), nparts,
-                       c->boxL.as<const double>(), S.cube.as<double>());
+                       c->X->boxL.as<const double>(), S.cube.as<double>());
     hipLaunchKernelGGL(k_morton, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, p->pos, n,
-                       S.cube.as<const double>(), c->boxL.as<const double>(), S.keys.as<uint64_t>(),
+                       S.cube.as<const double>(), c->X->boxL.as<const double>(), S.keys.as<uint64_t>(),
                        S.vals.as<uint32_t>());
     // radix sort on the top bits that resolve ~2^6 particles per cell
     int need = std::min(63, std::max(24, 3 * ((bits_for(n) + 6 + 2) / 3)));
@@ -246,7 +260,7 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
     S.perm = S.vals.as<const uint32_t>();
     ENSURE(c, S.sx, n * 8); ENSURE(c, S.sy, n * 8); ENSURE(c, S.sz, n * 8); ENSURE(c, S.sh, n * 8);
     hipLaunchKernelGGL(k_gather_pos, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, S.perm, n, p->pos, p->h,
-                       c->boxL.as<const double>(), S.sx.as<double>(), S.sy.as<double>(), S.sz.as<double>(),
+                       c->X->boxL.as<const double>(), S.sx.as<double>(), S.sy.as<double>(), S.sz.as<double>(),
                        S.sh.as<double>());
     // owners (active subset, Morton order)
     ENSURE(c, S.flag, (n + 1) * 4); ENSURE(c, S.flag_off, (n + 1) * 4); ENSURE(c, S.own, n * 4);
@@ -260,7 +274,7 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
     S.nchunk = (n + kTile - 1) / kTile;
     ENSURE(c, S.sub_ccnt, (S.nchunk + 1) * 4); ENSURE(c, S.sub_coff, (S.nchunk + 1) * 4);
     hipLaunchKernelGGL(k_subtile_split<false>, dim3(unsigned(S.nchunk)), dim3(64), 0, c->stream,
-                       S.keys.as<const uint64_t>(), n, S.sort_lo_bit, S.sub_ccnt.as<uint32_t>(),
+                       S.keys.as<const uint64_t>(), n, S.sort_lo_bit, c->subtile_delta, S.sub_ccnt.as<uint32_t>(),
                        (const uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr);
     HIPCHK(c, hipMemsetAsync(S.sub_ccnt.as<uint32_t>() + S.nchunk, 0, 4, c->stream));
     s = scan_excl(c, S.sub_ccnt.as<const uint32_t>(), S.sub_coff.as<uint32_t>(), S.nchunk + 1);
@@ -275,7 +289,7 @@ dmb_status build_subtiles(dmb_ctx* c, Species& S)
     if (S.n == 0) return DMB_OK;
     ENSURE(c, S.sub_start, S.ntile * 4); ENSURE(c, S.sub_cnt, S.ntile * 4);
     hipLaunchKernelGGL(k_subtile_split<true>, dim3(unsigned(S.nchunk)), dim3(64), 0, c->stream,
-                       S.keys.as<const uint64_t>(), S.n, S.sort_lo_bit, (uint32_t*)nullptr,
+                       S.keys.as<const uint64_t>(), S.n, S.sort_lo_bit, c->subtile_delta, (uint32_t*)nullptr,
                        S.sub_coff.as<const uint32_t>(), S.sub_start.as<uint32_t>(), S.sub_cnt.as<uint32_t>());
     S.nsuper = (S.ntile + kTile - 1) / kTile;
     ENSURE(c, S.tbox, S.ntile * 48); ENSURE(c, S.th, S.ntile * 8);
@@ -315,7 +329,7 @@ CandArgs cand_args(dmb_ctx* c, Species& A, Species& B, Pairs& P)
     a.obox = A.obox.as<const double>(); a.oh = A.oh.as<const double>();
     a.tbox = B.tbox.as<const double>(); a.th = B.th.as<const double>();
     a.sbox = B.sbox.as<const double>(); a.shh = B.shh.as<const double>();
-    for (int k = 0; k < 3; ++k) a.L[k] = c->built_L[k];
+    for (int k = 0; k < 3; ++k) a.L[k] = c->X->built_L[k];
     a.cnt = P.cnt.as<uint32_t>(); a.off = P.off.as<const uint32_t>(); a.cand = P.cand.as<uint32_t>();
     return a;
 }
@@ -413,7 +427,7 @@ dmb_status ensure_quad_nodes(dmb_ctx* c, int K)
 
 int quad_k(const dmb_params* p) { return p->quad_nodes == 0 ? 32 : p->quad_nodes; }
 
-PassGeom geom(dmb_ctx* c, Species& A, Species& B, Pairs& P, uint64_t* counters)
+PassGeom geom(Cells& X, Species& A, Species& B, Pairs& P, uint64_t* counters)
 {
     PassGeom g;
     g.own = A.own.as<const uint32_t>(); g.n_own = A.n_own;
@@ -426,38 +440,44 @@ PassGeom geom(dmb_ctx* c, Species& A, Species& B, Pairs& P, uint64_t* counters)
     g.item_off = P.ioff.as<const uint32_t>();
     g.it_tile = P.it_tile.as<const uint32_t>(); g.it_cb = P.it_cb.as<const uint32_t>();
     g.it_ce = P.it_ce.as<const uint32_t>(); g.n_items = P.nitems;
-    g.queue_ctr = c->qctr.as<uint32_t>();
-    for (int k = 0; k < 3; ++k) g.L[k] = c->built_L[k];
+    g.queue_ctr = X.qctr.as<uint32_t>();
+    for (int k = 0; k < 3; ++k) g.L[k] = X.built_L[k];
     g.counters = counters;
     return g;
 }
 
-template <typename Real, int N, int RM>
-dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
-                       dmb_out* out, uint64_t* counters)
+// Persistent grid: as many blocks of `threads` as can be resident, capped by need.
+int persist_blocks(dmb_ctx* c, const void* fn, int threads, int64_t want)
 {
-    constexpr bool kExact = sizeof(Real) == 8;
-    // persistent grids: as many single-wave blocks as can be resident
-    auto persist = [&](const void* fn, int threads) {
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess || per_cu < 1)
-            per_cu = 8;
-        return std::max(8, (c->num_cu * per_cu / 8) * 8);
-    };
-    const uint32_t k0 = uint32_t(par->seed), k1 = uint32_t(par->seed >> 32);
-    const double sig_kpc2_cn = par->sigma0_cm2 / (kKpcCm * kKpcCm) * std::pow(kCKms, -double(par->n_pow));
-    Species& G = c->gas;
-    Species& D = c->dm;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess || per_cu < 1) per_cu = 8;
+    const int64_t full = std::max<int64_t>(8, (int64_t(c->num_cu) * per_cu * c->grid_pct / 100 / 8) * 8);
+    return int(std::max<int64_t>(8, std::min<int64_t>(full, ((want + 7) / 8) * 8)));
+}
+
+double sig_kpc2_cn_of(const dmb_params* par)
+{
+    return par->sigma0_cm2 / (kKpcCm * kKpcCm) * std::pow(kCKms, -double(par->n_pow));
+}
+
+// Per-step gathers into Morton order and the clearing of outputs, counters
+// and the box's queue counters (qctr: [0, 8) gas queue, [8, 16) DM queue,
+// [16] scatter count).
+template <typename Real>
+dmb_status gather_and_fill(dmb_ctx* c, Cells& X, const dmb_particles* gas, const dmb_particles* dm,
+                           const dmb_params* par, dmb_out* out, uint64_t* counters)
+{
+    Species& G = X.gas;
+    Species& D = X.dm;
     const int rs = int(sizeof(Real));
-    // gathers
-    Phase* ph_g = new Phase(c, DMB_PH_GATHER);
     if (G.n > 0) {
         ENSURE(c, G.v0, G.n * 8); ENSURE(c, G.v1, G.n * 8); ENSURE(c, G.v2, G.n * 8);
         DevBuf* rb[7] = {&G.r0, &G.r1, &G.r2, &G.r3, &G.r4, &G.r5, &G.r6};
         for (DevBuf* b : rb) ENSURE(c, *b, G.n * rs);
         GasGatherArgs ga;
         ga.n = G.n; ga.perm = G.perm; ga.vel = gas->vel; ga.mass = gas->mass; ga.u = gas->u; ga.mu = gas->mu;
-        ga.m_chi = par->m_chi_g; ga.sig_kpc2_cn = sig_kpc2_cn; ga.alpha_n = alpha_n(par->n_pow); ga.n_pow = par->n_pow;
+        ga.m_chi = par->m_chi_g; ga.sig_kpc2_cn = sig_kpc2_cn_of(par); ga.alpha_n = alpha_n(par->n_pow);
+        ga.n_pow = par->n_pow;
         ga.Vx = G.v0.as<double>(); ga.Vy = G.v1.as<double>(); ga.Vz = G.v2.as<double>();
         ga.vs = G.r0.p; ga.inv2s2 = G.r1.p; ga.ra = G.r2.p; ga.rb = G.r3.p; ga.rr = G.r4.p; ga.K = G.r5.p;
         ga.crit = G.r6.p;
@@ -473,111 +493,341 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
         da.m = D.r0.p; da.dtr = D.r1.p;
         hipLaunchKernelGGL(k_gather_dm<Real>, dim3(blocks_for(D.n, 256)), dim3(256), 0, c->stream, da);
     }
-    // outputs, counters, work-queue counters
-    // qctr: [0, 8) gas work queue, [8, 16) DM work queue, [16] scatter count
-    ENSURE(c, c->qctr, (2 * kXcd + 4) * 4);
-    uint32_t* scount = c->qctr.as<uint32_t>() + 2 * kXcd;
+    ENSURE(c, X.qctr, (2 * kXcd + 4) * 4);
     int64_t nfill = std::max<int64_t>(std::max<int64_t>(G.n, D.n), 2 * kXcd + 4);
     hipLaunchKernelGGL(k_fill_out, dim3(blocks_for(nfill, 256)), dim3(256), 0, c->stream, G.n, D.n, out->dp_gas,
                        out->de_gas, out->dv_dm, out->partner, out->p_sum, out->p_max, counters,
-                       c->qctr.as<uint32_t>(), 2 * kXcd + 4);
-    delete ph_g;
-    // gas pass
-    if (c->gp.nitems > 0) {
-        ENSURE(c, c->part_gas, size_t(c->gp.nitems) * kTile * 4 * 8);
-        GasPassArgs a;
-        a.g = geom(c, G, D, c->gp, counters);
-        a.Vx = G.v0.as<const double>(); a.Vy = G.v1.as<const double>(); a.Vz = G.v2.as<const double>();
-        a.inv2s2 = G.r1.p; a.ra = G.r2.p; a.rb = G.r3.p; a.rr = G.r4.p;
-        a.dvx = D.v0.as<const double>(); a.dvy = D.v1.as<const double>(); a.dvz = D.v2.as<const double>();
-        a.dm_m = D.r0.p;
-        a.gtab = c->gtab.as<const float4>();
-        const DevBuf& glb = sizeof(Real) == 8 ? c->gl64 : c->gl32;
-        a.gl_x = glb.p;
-        a.gl_w = glb.p ? static_cast<const char*>(glb.p) + kMaxQuadNodes * sizeof(Real) : nullptr;
-        a.gl_k = c->gl_k;
-        a.inv_alpha = 1.0 / alpha_n(par->n_pow);
-        quad_window(c->gl_k, &a.gl_hw, &a.gl_bmin);
-        if constexpr (RM == kRatesMlp) {
-            const double al = alpha_n(N);
-            a.mlp = c->mlp_blob.as<const MlpBlob>();
-            a.mlp_nidx = mlp_n_index(N);
-            a.mlp_c0A = float(std::pow(al / 3.0, 4.0 / (N + 1)));
-            a.mlp_c0B = float(std::pow(al, 4.0 / (N + 3)));
-            a.mlp_c1A = float(kMlpC1[mlp_n_index(N)][0]);
-            a.mlp_c1B = float(kMlpC1[mlp_n_index(N)][1]);
-            a.mlp_kA = float(3.0 / al);
-            a.mlp_kB = float(1.0 / al);
-        } else {
-            a.mlp = nullptr;
-        }
-        a.part = c->part_gas.as<double>();
-        a.perm = G.perm; a.mass = gas->mass; a.mu = gas->mu; a.dt = gas->dt; a.dt_default = par->dt;
-        a.m_chi = par->m_chi_g; a.sig_kpc2_cn = sig_kpc2_cn; a.dp = out->dp_gas; a.de = out->de_gas;
-        constexpr int kW = RM == kRatesMlp ? kMlpPassWaves : 1;
-        const int64_t want = (((c->gp.nitems + kW - 1) / kW + 7) / 8) * 8;
-        int nb = int(std::min<int64_t>(persist((const void*)k_pass_gas<Real, N, kExact, RM>, 64 * kW), want));
-        {
-            Phase ph(c, DMB_PH_PASS_GAS);
-            hipLaunchKernelGGL((k_pass_gas<Real, N, kExact, RM>), dim3(nb), dim3(64 * kW), 0, c->stream, a);
-        }
-        GasCombineArgs cb;
-        cb.n_own = G.n_own; cb.own = G.own.as<const uint32_t>(); cb.perm = G.perm;
-        cb.item_off = c->gp.ioff.as<const uint32_t>(); cb.part = c->part_gas.as<const double>();
-        cb.mass = gas->mass; cb.mu = gas->mu; cb.dt = gas->dt; cb.dt_default = par->dt; cb.m_chi = par->m_chi_g;
-        cb.sig_kpc2_cn = sig_kpc2_cn; cb.dp = out->dp_gas; cb.de = out->de_gas;
-        Phase ph(c, DMB_PH_COMBINE_GAS);
-        hipLaunchKernelGGL(k_combine_gas, dim3(blocks_for(G.n_own, 256)), dim3(256), 0, c->stream, cb);
-    }
-    // DM pass, decision, resolve
-    if (c->dp.nitems > 0) {
-        ENSURE(c, c->part_p, size_t(c->dp.nitems) * kTile * 8);
-        ENSURE(c, c->part_pm, size_t(c->dp.nitems) * kTile * 4);
-        ENSURE(c, c->part_nb, size_t(c->dp.nitems) * kTile);
-        ENSURE(c, c->psum_own, size_t(D.n_own) * 8);
-        ENSURE(c, c->slist, size_t(D.n_own) * 4);
-        DmPassArgs a;
-        a.g = geom(c, D, G, c->dp, counters);
-        a.g.queue_ctr = c->qctr.as<uint32_t>() + kXcd;
-        a.vx = D.v0.as<const double>(); a.vy = D.v1.as<const double>(); a.vz = D.v2.as<const double>();
-        a.dtr = D.r1.p; a.dm_perm = D.perm;
-        a.Vx = G.v0.as<const double>(); a.Vy = G.v1.as<const double>(); a.Vz = G.v2.as<const double>();
-        a.vs = G.r0.p; a.K = G.r5.p; a.crit = G.r6.p; a.gas_perm = G.perm;
-        a.gtab = c->gtab.as<const float4>();
-        a.k0 = k0; a.k1 = k1; a.step = par->step; a.box = par->box_id;
-        a.part_p = c->part_p.as<double>(); a.part_pm = c->part_pm.as<float>(); a.part_nb = c->part_nb.as<uint8_t>();
-        a.psum_own = c->psum_own.as<double>(); a.psum = out->p_sum; a.pmax = out->p_max;
-        a.scount = scount; a.slist = c->slist.as<uint32_t>();
-        int nb = int(std::min<int64_t>(persist((const void*)k_pass_dm<Real, N, kExact>, 64), ((c->dp.nitems + 7) / 8) * 8));
-        {
-            Phase ph(c, DMB_PH_PASS_DM);
-            hipLaunchKernelGGL((k_pass_dm<Real, N, kExact>), dim3(nb), dim3(64), 0, c->stream, a);
-        }
-        DmCombineArgs cb;
-        cb.n_own = D.n_own; cb.own = D.own.as<const uint32_t>(); cb.perm = D.perm;
-        cb.item_off = c->dp.ioff.as<const uint32_t>(); cb.part_p = c->part_p.as<const double>();
-        cb.part_pm = c->part_pm.as<const float>(); cb.part_nb = c->part_nb.as<const uint8_t>(); cb.k0 = k0; cb.k1 = k1; cb.step = par->step; cb.box = par->box_id;
-        cb.psum_own = c->psum_own.as<double>(); cb.psum = out->p_sum; cb.pmax = out->p_max;
-        cb.scount = scount; cb.slist = c->slist.as<uint32_t>(); cb.counters = counters;
-        {
-            Phase ph(c, DMB_PH_COMBINE_DM);
-            hipLaunchKernelGGL(k_combine_dm, dim3(blocks_for(D.n_own, 256)), dim3(256), 0, c->stream, cb);
-        }
-        ResolveArgs r;
-        r.g = a.g;
-        r.cand_off = c->dp.off.as<const uint32_t>();
-        r.vx = a.vx; r.vy = a.vy; r.vz = a.vz; r.dtr = a.dtr; r.dm_perm = a.dm_perm;
-        r.Vx = a.Vx; r.Vy = a.Vy; r.Vz = a.Vz; r.vs = a.vs; r.K = a.K; r.gas_perm = a.gas_perm;
-        r.gas_vel = gas->vel; r.gas_u = gas->u; r.gas_mu = gas->mu; r.m_chi = par->m_chi_g;
-        r.gtab = a.gtab; r.k0 = k0; r.k1 = k1; r.step = par->step; r.box = par->box_id;
-        r.n_gas_bits = bits_for(std::max<int64_t>(G.n, 2));
-        r.n_gas = uint32_t(G.n);
-        r.scount = scount; r.slist = c->slist.as<const uint32_t>();
-        r.dv = out->dv_dm; r.partner = out->partner; r.counters = counters;
-        Phase ph(c, DMB_PH_RESOLVE);
-        hipLaunchKernelGGL((k_resolve<Real, N, kExact>), dim3(std::max(8, c->num_cu * 2)), dim3(kResolveThreads), 0, c->stream, r);
+                       X.qctr.as<uint32_t>(), 2 * kXcd + 4);
+    if (X.gp.nitems > 0) ENSURE(c, X.part_gas, size_t(X.gp.nitems) * kTile * 4 * 8);
+    if (X.dp.nitems > 0) {
+        ENSURE(c, X.part_p, size_t(X.dp.nitems) * kTile * 8);
+        ENSURE(c, X.part_pm, size_t(X.dp.nitems) * kTile * 4);
+        ENSURE(c, X.part_nb, size_t(X.dp.nitems) * kTile);
+        ENSURE(c, X.psum_own, size_t(D.n_own) * 8);
+        ENSURE(c, X.slist, size_t(D.n_own) * 4);
     }
     HIPCHK(c, hipGetLastError());
+    return DMB_OK;
+}
+
+template <typename Real, int N, int RM>
+GasPassArgs gas_pass_args(dmb_ctx* c, Cells& X, const dmb_particles* gas, const dmb_params* par, dmb_out* out,
+                          uint64_t* counters)
+{
+    Species& G = X.gas;
+    Species& D = X.dm;
+    GasPassArgs a;
+    a.g = geom(X, G, D, X.gp, counters);
+    a.Vx = G.v0.as<const double>(); a.Vy = G.v1.as<const double>(); a.Vz = G.v2.as<const double>();
+    a.inv2s2 = G.r1.p; a.ra = G.r2.p; a.rb = G.r3.p; a.rr = G.r4.p;
+    a.dvx = D.v0.as<const double>(); a.dvy = D.v1.as<const double>(); a.dvz = D.v2.as<const double>();
+    a.dm_m = D.r0.p;
+    a.gtab = c->gtab.as<const float4>();
+    const DevBuf& glb = sizeof(Real) == 8 ? c->gl64 : c->gl32;
+    a.gl_x = glb.p;
+    a.gl_w = glb.p ? static_cast<const char*>(glb.p) + kMaxQuadNodes * sizeof(Real) : nullptr;
+    a.gl_k = c->gl_k;
+    a.inv_alpha = 1.0 / alpha_n(par->n_pow);
+    quad_window(c->gl_k, &a.gl_hw, &a.gl_bmin);
+    a.mlp = nullptr;
+    if constexpr (RM == kRatesMlp) {
+        const double al = alpha_n(N);
+        a.mlp = c->mlp_blob.as<const MlpBlob>();
+        a.mlp_nidx = mlp_n_index(N);
+        a.mlp_c0A = float(std::pow(al / 3.0, 4.0 / (N + 1)));
+        a.mlp_c0B = float(std::pow(al, 4.0 / (N + 3)));
+        a.mlp_c1A = float(kMlpC1[mlp_n_index(N)][0]);
+        a.mlp_c1B = float(kMlpC1[mlp_n_index(N)][1]);
+        a.mlp_kA = float(3.0 / al);
+        a.mlp_kB = float(1.0 / al);
+    }
+    a.part = X.part_gas.as<double>();
+    a.perm = G.perm; a.mass = gas->mass; a.mu = gas->mu; a.dt = gas->dt; a.dt_default = par->dt;
+    a.m_chi = par->m_chi_g; a.sig_kpc2_cn = sig_kpc2_cn_of(par); a.dp = out->dp_gas; a.de = out->de_gas;
+    return a;
+}
+
+void combine_gas(dmb_ctx* c, Cells& X, const dmb_particles* gas, const dmb_params* par, dmb_out* out)
+{
+    Species& G = X.gas;
+    GasCombineArgs cb;
+    cb.n_own = G.n_own; cb.own = G.own.as<const uint32_t>(); cb.perm = G.perm;
+    cb.item_off = X.gp.ioff.as<const uint32_t>(); cb.part = X.part_gas.as<const double>();
+    cb.mass = gas->mass; cb.mu = gas->mu; cb.dt = gas->dt; cb.dt_default = par->dt; cb.m_chi = par->m_chi_g;
+    cb.sig_kpc2_cn = sig_kpc2_cn_of(par); cb.dp = out->dp_gas; cb.de = out->de_gas;
+    hipLaunchKernelGGL(k_combine_gas, dim3(blocks_for(G.n_own, 256)), dim3(256), 0, c->stream, cb);
+}
+
+DmPassArgs dm_pass_args(dmb_ctx* c, Cells& X, const dmb_params* par, dmb_out* out, uint64_t* counters,
+                        const uint32_t* step_off)
+{
+    Species& G = X.gas;
+    Species& D = X.dm;
+    DmPassArgs a;
+    a.g = geom(X, D, G, X.dp, counters);
+    a.g.queue_ctr = X.qctr.as<uint32_t>() + kXcd;
+    a.vx = D.v0.as<const double>(); a.vy = D.v1.as<const double>(); a.vz = D.v2.as<const double>();
+    a.dtr = D.r1.p; a.dm_perm = D.perm;
+    a.Vx = G.v0.as<const double>(); a.Vy = G.v1.as<const double>(); a.Vz = G.v2.as<const double>();
+    a.vs = G.r0.p; a.K = G.r5.p; a.crit = G.r6.p; a.gas_perm = G.perm;
+    a.gtab = c->gtab.as<const float4>();
+    a.k0 = uint32_t(par->seed); a.k1 = uint32_t(par->seed >> 32); a.step = par->step; a.box = par->box_id;
+    a.step_off = step_off;
+    a.part_p = X.part_p.as<double>(); a.part_pm = X.part_pm.as<float>(); a.part_nb = X.part_nb.as<uint8_t>();
+    a.psum_own = X.psum_own.as<double>(); a.psum = out->p_sum; a.pmax = out->p_max;
+    a.scount = X.qctr.as<uint32_t>() + 2 * kXcd; a.slist = X.slist.as<uint32_t>();
+    return a;
+}
+
+template <typename Real, int N>
+void combine_dm_and_resolve(dmb_ctx* c, Cells& X, const DmPassArgs& a, const dmb_particles* gas,
+                            const dmb_params* par, dmb_out* out, uint64_t* counters)
+{
+    constexpr bool kExact = sizeof(Real) == 8;
+    Species& G = X.gas;
+    Species& D = X.dm;
+    DmCombineArgs cb;
+    cb.n_own = D.n_own; cb.own = D.own.as<const uint32_t>(); cb.perm = D.perm;
+    cb.item_off = X.dp.ioff.as<const uint32_t>(); cb.part_p = X.part_p.as<const double>();
+    cb.part_pm = X.part_pm.as<const float>(); cb.part_nb = X.part_nb.as<const uint8_t>();
+    cb.k0 = a.k0; cb.k1 = a.k1; cb.step = a.step; cb.box = a.box; cb.step_off = a.step_off;
+    cb.psum_own = X.psum_own.as<double>(); cb.psum = out->p_sum; cb.pmax = out->p_max;
+    cb.scount = a.scount; cb.slist = X.slist.as<uint32_t>(); cb.counters = counters;
+    {
+        Phase ph(c, DMB_PH_COMBINE_DM);
+        hipLaunchKernelGGL(k_combine_dm, dim3(blocks_for(D.n_own, 256)), dim3(256), 0, c->stream, cb);
+    }
+    ResolveArgs r;
+    r.g = a.g;
+    r.cand_off = X.dp.off.as<const uint32_t>();
+    r.vx = a.vx; r.vy = a.vy; r.vz = a.vz; r.dtr = a.dtr; r.dm_perm = a.dm_perm;
+    r.Vx = a.Vx; r.Vy = a.Vy; r.Vz = a.Vz; r.vs = a.vs; r.K = a.K; r.gas_perm = a.gas_perm;
+    r.gas_vel = gas->vel; r.gas_u = gas->u; r.gas_mu = gas->mu; r.m_chi = par->m_chi_g;
+    r.gtab = a.gtab; r.k0 = a.k0; r.k1 = a.k1; r.step = a.step; r.box = a.box; r.step_off = a.step_off;
+    r.n_gas_bits = bits_for(std::max<int64_t>(G.n, 2));
+    r.n_gas = uint32_t(G.n);
+    r.scount = a.scount; r.slist = X.slist.as<const uint32_t>();
+    r.dv = out->dv_dm; r.partner = out->partner; r.counters = counters;
+    Phase ph(c, DMB_PH_RESOLVE);
+    hipLaunchKernelGGL((k_resolve<Real, N, kExact>), dim3(std::max(8, c->num_cu * 2)), dim3(kResolveThreads), 0,
+                       c->stream, r);
+}
+
+template <typename Real, int N, int RM>
+dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
+                       dmb_out* out, uint64_t* counters)
+{
+    constexpr bool kExact = sizeof(Real) == 8;
+    constexpr int kW = RM == kRatesMlp ? kMlpPassWaves : 1;
+    Cells& X = *c->X;
+    {
+        Phase ph(c, DMB_PH_GATHER);
+        dmb_status s = gather_and_fill<Real>(c, X, gas, dm, par, out, counters);
+        if (s != DMB_OK) return s;
+    }
+    if (X.gp.nitems > 0) {
+        GasPassArgs a = gas_pass_args<Real, N, RM>(c, X, gas, par, out, counters);
+        const int nb = persist_blocks(c, (const void*)k_pass_gas<Real, N, kExact, RM>, 64 * kW,
+                                      (X.gp.nitems + kW - 1) / kW);
+        {
+            Phase ph(c, DMB_PH_PASS_GAS);
+            hipLaunchKernelGGL((k_pass_gas<Real, N, kExact, RM>), dim3(nb), dim3(64 * kW), 0, c->stream, a,
+                               (const GasPassArgs*)nullptr, (const int64_t*)nullptr, 0);
+        }
+        Phase ph(c, DMB_PH_COMBINE_GAS);
+        combine_gas(c, X, gas, par, out);
+    }
+    if (X.dp.nitems > 0) {
+        DmPassArgs a = dm_pass_args(c, X, par, out, counters, nullptr);
+        const int nb = persist_blocks(c, (const void*)k_pass_dm<Real, N, kExact>, 64, X.dp.nitems);
+        {
+            Phase ph(c, DMB_PH_PASS_DM);
+            hipLaunchKernelGGL((k_pass_dm<Real, N, kExact>), dim3(nb), dim3(64), 0, c->stream, a,
+                               (const DmPassArgs*)nullptr, (const int64_t*)nullptr, 0);
+        }
+        combine_dm_and_resolve<Real, N>(c, X, a, gas, par, out, counters);
+    }
+    HIPCHK(c, hipGetLastError());
+    return DMB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched boxes: per-box gathers, combines and resolves; each pair pass is one
+// persistent launch over the work items of all boxes.  Arguments live in
+// device arrays prepared by batch_prepare, so batch_enqueue launches kernels
+// only (it can be captured in a graph).
+struct BatchPlan {
+    int nbox = 0;
+    int64_t gas_items = 0, dm_items = 0;
+    std::vector<GasPassArgs> ga;
+    std::vector<DmPassArgs> da;
+    int nb_gas = 0, nb_dm = 0;
+};
+
+template <typename Real, int N, int RM>
+dmb_status batch_prepare(dmb_ctx* c, int nbox, const dmb_particles* gas, const dmb_particles* dm,
+                         const dmb_params* par, dmb_out* out, BatchPlan& P)
+{
+    constexpr bool kExact = sizeof(Real) == 8;
+    constexpr int kW = RM == kRatesMlp ? kMlpPassWaves : 1;
+    P.nbox = nbox;
+    P.ga.resize(nbox);
+    P.da.resize(nbox);
+    std::vector<int64_t> gi(nbox + 1, 0), di(nbox + 1, 0);
+    // global queues [0, 16) and the Philox step offset [16]
+    ENSURE(c, c->bstep, 32 * sizeof(uint32_t));
+    const uint32_t* step_off = c->bstep.as<const uint32_t>() + 2 * kXcd;
+    for (int b = 0; b < nbox; ++b) {
+        Cells& X = *c->boxes[b];
+        // buffers the step writes (sized here so that enqueueing allocates nothing)
+        if (X.gp.nitems > 0) ENSURE(c, X.part_gas, size_t(X.gp.nitems) * kTile * 4 * 8);
+        if (X.dp.nitems > 0) {
+            ENSURE(c, X.part_p, size_t(X.dp.nitems) * kTile * 8);
+            ENSURE(c, X.part_pm, size_t(X.dp.nitems) * kTile * 4);
+            ENSURE(c, X.part_nb, size_t(X.dp.nitems) * kTile);
+            ENSURE(c, X.psum_own, size_t(X.dm.n_own) * 8);
+            ENSURE(c, X.slist, size_t(X.dm.n_own) * 4);
+        }
+        ENSURE(c, X.qctr, (2 * kXcd + 4) * 4);
+        const int rs = int(sizeof(Real));
+        Species& G = X.gas;
+        Species& D = X.dm;
+        if (G.n > 0) {
+            ENSURE(c, G.v0, G.n * 8); ENSURE(c, G.v1, G.n * 8); ENSURE(c, G.v2, G.n * 8);
+            DevBuf* rb[7] = {&G.r0, &G.r1, &G.r2, &G.r3, &G.r4, &G.r5, &G.r6};
+            for (DevBuf* bb : rb) ENSURE(c, *bb, G.n * rs);
+        }
+        if (D.n > 0) {
+            ENSURE(c, D.v0, D.n * 8); ENSURE(c, D.v1, D.n * 8); ENSURE(c, D.v2, D.n * 8);
+            ENSURE(c, D.r0, D.n * rs); ENSURE(c, D.r1, D.n * rs);
+        }
+        uint64_t* counters = out[b].counters;
+        P.ga[b] = gas_pass_args<Real, N, RM>(c, X, gas + b, par + b, out + b, counters);
+        P.da[b] = dm_pass_args(c, X, par + b, out + b, counters, step_off);
+        gi[b + 1] = gi[b] + X.gp.nitems;
+        di[b + 1] = di[b] + X.dp.nitems;
+    }
+    P.gas_items = gi[nbox];
+    P.dm_items = di[nbox];
+    const size_t argb = sizeof(GasPassArgs) + sizeof(DmPassArgs);
+    ENSURE(c, c->bgeom, size_t(nbox) * argb + 256);
+    ENSURE(c, c->bitem, size_t(2 * (nbox + 1)) * sizeof(int64_t));
+    char* gdev = c->bgeom.as<char>();
+    HIPCHK(c, hipMemcpyAsync(gdev, P.ga.data(), nbox * sizeof(GasPassArgs), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(gdev + size_t(nbox) * sizeof(GasPassArgs), P.da.data(), nbox * sizeof(DmPassArgs),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->bitem.p, gi.data(), (nbox + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->bitem.as<int64_t>() + nbox + 1, di.data(), (nbox + 1) * sizeof(int64_t),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    P.nb_gas = persist_blocks(c, (const void*)k_pass_gas<Real, N, kExact, RM, true>, 64 * kW,
+                              (P.gas_items + kW - 1) / kW);
+    P.nb_dm = persist_blocks(c, (const void*)k_pass_dm<Real, N, kExact, true>, 64, P.dm_items);
+    return DMB_OK;
+}
+
+template <typename Real, int N, int RM>
+dmb_status batch_enqueue(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
+                         dmb_out* out, const BatchPlan& P)
+{
+    constexpr bool kExact = sizeof(Real) == 8;
+    constexpr int kW = RM == kRatesMlp ? kMlpPassWaves : 1;
+    const int nbox = P.nbox;
+    const GasPassArgs* gdev = reinterpret_cast<const GasPassArgs*>(c->bgeom.p);
+    const DmPassArgs* ddev = reinterpret_cast<const DmPassArgs*>(c->bgeom.as<char>() + size_t(nbox) * sizeof(GasPassArgs));
+    const int64_t* gitems = c->bitem.as<const int64_t>();
+    const int64_t* ditems = gitems + nbox + 1;
+    for (int b = 0; b < nbox; ++b) {
+        dmb_status s = gather_and_fill<Real>(c, *c->boxes[b], gas + b, dm + b, par + b, out + b, out[b].counters);
+        if (s != DMB_OK) return s;
+    }
+    hipLaunchKernelGGL(k_fill_out, dim3(1), dim3(256), 0, c->stream, int64_t(0), int64_t(0), (double*)nullptr,
+                       (double*)nullptr, (double*)nullptr, (int32_t*)nullptr, (double*)nullptr, (double*)nullptr,
+                       (uint64_t*)nullptr, c->bstep.as<uint32_t>(), 2 * kXcd);
+    if (P.gas_items > 0) {
+        GasPassArgs a0 = P.ga[0];
+        a0.g.queue_ctr = c->bstep.as<uint32_t>();
+        a0.g.n_items = P.gas_items;
+        {
+            Phase ph(c, DMB_PH_PASS_GAS);
+            hipLaunchKernelGGL((k_pass_gas<Real, N, kExact, RM, true>), dim3(P.nb_gas), dim3(64 * kW), 0, c->stream,
+                               a0, gdev, gitems, nbox);
+        }
+        Phase ph(c, DMB_PH_COMBINE_GAS);
+        for (int b = 0; b < nbox; ++b)
+            if (c->boxes[b]->gp.nitems > 0) combine_gas(c, *c->boxes[b], gas + b, par + b, out + b);
+    }
+    if (P.dm_items > 0) {
+        DmPassArgs a0 = P.da[0];
+        a0.g.queue_ctr = c->bstep.as<uint32_t>() + kXcd;
+        a0.g.n_items = P.dm_items;
+        {
+            Phase ph(c, DMB_PH_PASS_DM);
+            hipLaunchKernelGGL((k_pass_dm<Real, N, kExact, true>), dim3(P.nb_dm), dim3(64), 0, c->stream, a0, ddev,
+                               ditems, nbox);
+        }
+        for (int b = 0; b < nbox; ++b)
+            if (c->boxes[b]->dp.nitems > 0)
+                combine_dm_and_resolve<Real, N>(c, *c->boxes[b], P.da[b], gas + b, par + b, out + b, out[b].counters);
+    }
+    HIPCHK(c, hipGetLastError());
+    return DMB_OK;
+}
+
+// nsteps steps of all boxes (Philox step = params.step + k), eagerly or as
+// replays of one captured step.
+template <typename Real, int N, int RM>
+dmb_status batch_run(dmb_ctx* c, int nbox, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
+                     dmb_out* out, int nsteps, bool graph)
+{
+    BatchPlan P;
+    dmb_status s = batch_prepare<Real, N, RM>(c, nbox, gas, dm, par, out, P);
+    if (s != DMB_OK) return s;
+    uint32_t* step_off = c->bstep.as<uint32_t>() + 2 * kXcd;
+    HIPCHK(c, hipMemsetAsync(step_off, 0, sizeof(uint32_t), c->stream));
+    if (!graph) {
+        for (int k = 0; k < nsteps; ++k) {
+            if ((s = batch_enqueue<Real, N, RM>(c, gas, dm, par, out, P)) != DMB_OK) return s;
+            hipLaunchKernelGGL(k_mlp_tick, dim3(1), dim3(1), 0, c->stream, step_off);
+        }
+        HIPCHK(c, hipGetLastError());
+        return DMB_OK;
+    }
+    // capture needs a stream other than the legacy default one: use the
+    // context's own non-blocking stream for the captured work when needed
+    hipStream_t user = c->stream;
+    HIPCHK(c, hipStreamSynchronize(user));
+    if (!user) {
+        if (!c->train_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->train_stream, hipStreamNonBlocking));
+        c->stream = c->train_stream;
+    }
+    struct StreamRestore { dmb_ctx* c; hipStream_t s; ~StreamRestore() { c->stream = s; } } restore{c, user};
+    const bool prof = c->prof;
+    c->prof = false;                       // no event records inside the captured step
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    s = batch_enqueue<Real, N, RM>(c, gas, dm, par, out, P);
+    hipLaunchKernelGGL(k_mlp_tick, dim3(1), dim3(1), 0, c->stream, step_off);
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->prof = prof;
+    if (s != DMB_OK) { if (g) (void)hipGraphDestroy(g); return s; }
+    if (e != hipSuccess) return fail(c, DMB_EHIP, "step capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(c, DMB_EHIP, "step graph: %s", hipGetErrorString(e));
+    }
+    hipError_t e2 = hipSuccess;
+    {
+        Phase ph(c, DMB_PH_PASS_GAS);     // whole replays are timed under the gas-pass slot when profiling
+        for (int k = 0; k < nsteps && e == hipSuccess; ++k) e = hipGraphLaunch(ge, c->stream);
+    }
+    e2 = hipStreamSynchronize(c->stream);
+    (void)hipGraphExecDestroy(ge);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess || e2 != hipSuccess)
+        return fail(c, DMB_EHIP, "step replay: %s", hipGetErrorString(e != hipSuccess ? e : e2));
     return DMB_OK;
 }
 
@@ -613,6 +863,40 @@ dmb_status dispatch_rates(dmb_ctx* c, const dmb_particles* gas, const dmb_partic
         }
     }
     return dispatch_n<Real, kRatesExact>(c, gas, dm, par, out, counters);
+}
+
+template <typename Real, int RM>
+dmb_status batch_dispatch_n(dmb_ctx* c, int nbox, const dmb_particles* gas, const dmb_particles* dm,
+                            const dmb_params* par, dmb_out* out, int nsteps, bool graph)
+{
+    switch (par->n_pow) {
+        case -4: return batch_run<Real, -4, RM>(c, nbox, gas, dm, par, out, nsteps, graph);
+        case -2: return batch_run<Real, -2, RM>(c, nbox, gas, dm, par, out, nsteps, graph);
+        case 0: return batch_run<Real, 0, RM>(c, nbox, gas, dm, par, out, nsteps, graph);
+        case 2: return batch_run<Real, 2, RM>(c, nbox, gas, dm, par, out, nsteps, graph);
+    }
+    return fail(c, DMB_EINVAL, "n_pow %d not supported", par->n_pow);
+}
+
+template <typename Real>
+dmb_status batch_dispatch_rates(dmb_ctx* c, int nbox, const dmb_particles* gas, const dmb_particles* dm,
+                                const dmb_params* par, dmb_out* out, int nsteps, bool graph)
+{
+    if (par->rates == DMB_RATES_QUAD) {
+        dmb_status s = ensure_quad_nodes(c, quad_k(par));
+        if (s != DMB_OK) return s;
+        return batch_dispatch_n<Real, kRatesQuad>(c, nbox, gas, dm, par, out, nsteps, graph);
+    }
+    if (par->rates == DMB_RATES_MLP) {
+        if constexpr (sizeof(Real) == 4) {
+            dmb_status s = ensure_quad_nodes(c, quad_k(par));
+            if (s != DMB_OK) return s;
+            return batch_dispatch_n<float, kRatesMlp>(c, nbox, gas, dm, par, out, nsteps, graph);
+        } else {
+            return fail(c, DMB_EINVAL, "network rates need DMB_FP32");
+        }
+    }
+    return batch_dispatch_n<Real, kRatesExact>(c, nbox, gas, dm, par, out, nsteps, graph);
 }
 
 // ---------------------------------------------------------------------------
@@ -675,7 +959,30 @@ uint64_t gcd64(uint64_t a, uint64_t b)
     return a;
 }
 
+// Release the device buffers of one box.
+void free_cells(Cells& X)
+{
+    auto fr = [](DevBuf& b) { if (b.p) (void)hipFree(b.p); b.p = nullptr; b.cap = 0; };
+    for (Species* S : {&X.gas, &X.dm}) {
+        DevBuf* all[] = {&S->keys, &S->keys2, &S->vals, &S->vals2, &S->sx, &S->sy, &S->sz, &S->sh, &S->flag,
+                         &S->flag_off, &S->own, &S->tbox, &S->th, &S->sbox, &S->shh, &S->mbox, &S->mhh, &S->obox,
+                         &S->oh, &S->cube, &S->v0, &S->v1, &S->v2, &S->r0, &S->r1, &S->r2, &S->r3, &S->r4, &S->r5,
+                         &S->r6, &S->sub_ccnt, &S->sub_coff, &S->sub_start, &S->sub_cnt};
+        for (DevBuf* b : all) fr(*b);
+    }
+    for (Pairs* P : {&X.gp, &X.dp}) {
+        DevBuf* all[] = {&P->cnt, &P->off, &P->cand, &P->icnt, &P->ioff, &P->it_tile, &P->it_cb, &P->it_ce};
+        for (DevBuf* b : all) fr(*b);
+    }
+    DevBuf* rest[] = {&X.boxL, &X.part_gas, &X.part_p, &X.part_pm, &X.part_nb, &X.psum_own, &X.qctr, &X.slist};
+    for (DevBuf* b : rest) fr(*b);
+}
+
 }  // namespace
+
+namespace {
+dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par);
+}
 
 // ===========================================================================
 namespace {
@@ -702,7 +1009,7 @@ dmb_status dmb_create(dmb_ctx** out, int device, void* hip_stream)
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         c->num_cu = ncu;
     size_t tb = size_t(kTabND + 1) * (kTabNE + 1) * sizeof(float4);
-    if (ensure(c, c->gtab, tb) != DMB_OK || ensure(c, c->boxL, 4 * sizeof(double)) != DMB_OK) {
+    if (ensure(c, c->gtab, tb) != DMB_OK || ensure(c, c->X->boxL, 4 * sizeof(double)) != DMB_OK) {
         snprintf(g_create_err, sizeof(g_create_err), "%s", c->err);
         dmb_destroy(c);
         return DMB_ENOMEM;
@@ -726,18 +1033,13 @@ dmb_status dmb_destroy(dmb_ctx* c)
     hipSetDevice(c->device);
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
+    free_cells(c->cells);
+    for (Cells* X : c->boxes) {
+        free_cells(*X);
+        delete X;
+    }
+    c->boxes.clear();
     auto fr = [](DevBuf& b) { if (b.p) hipFree(b.p); b.p = nullptr; b.cap = 0; };
-    for (Species* S : {&c->gas, &c->dm}) {
-        DevBuf* all[] = {&S->keys, &S->keys2, &S->vals, &S->vals2, &S->sx, &S->sy, &S->sz, &S->sh, &S->flag,
-                         &S->flag_off, &S->own, &S->tbox, &S->th, &S->sbox, &S->shh, &S->mbox, &S->mhh, &S->obox, &S->oh, &S->cube,
-                         &S->v0, &S->v1, &S->v2, &S->r0, &S->r1, &S->r2, &S->r3, &S->r4, &S->r5, &S->r6,
-                         &S->sub_ccnt, &S->sub_coff, &S->sub_start, &S->sub_cnt};
-        for (DevBuf* b : all) fr(*b);
-    }
-    for (Pairs* P : {&c->gp, &c->dp}) {
-        DevBuf* all[] = {&P->cnt, &P->off, &P->cand, &P->icnt, &P->ioff, &P->it_tile, &P->it_cb, &P->it_ce};
-        for (DevBuf* b : all) fr(*b);
-    }
     for (auto& b : c->scan_tmp) fr(b);
     for (auto& p : c->pending) { c->ev_pool.push_back(p.a); c->ev_pool.push_back(p.b); }
     for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
@@ -745,8 +1047,8 @@ dmb_status dmb_destroy(dmb_ctx* c)
                      &c->mlp_loss, &c->mlp_epoch, &c->mlp_shuf};
     for (DevBuf* b : mlp) fr(*b);
     if (c->train_stream) hipStreamDestroy(c->train_stream);
-    DevBuf* rest[] = {&c->gl64, &c->gl32, &c->gtab, &c->sort_table, &c->bbox_part, &c->boxL, &c->part_gas, &c->part_p, &c->part_pm, &c->part_nb,
-                      &c->psum_own, &c->qctr, &c->slist, &c->counters_local};
+    DevBuf* rest[] = {&c->gl64, &c->gl32, &c->gtab, &c->sort_table, &c->bbox_part, &c->counters_local,
+                      &c->bstep, &c->bgeom, &c->bitem};
     for (DevBuf* b : rest) fr(*b);
     delete c;
     return DMB_OK;
@@ -764,8 +1066,8 @@ const char* dmb_last_error(const dmb_ctx* c) { return c ? c->err : g_create_err;
 dmb_status dmb_build_stats(const dmb_ctx* c, int64_t* o)
 {
     if (!c || !o) return DMB_EINVAL;
-    const int64_t v[10] = {c->gas.n_own, c->dm.n_own, c->gas.ntile, c->dm.ntile, c->gas.nown_tile, c->dm.nown_tile,
-                           c->gp.total, c->dp.total, c->gp.nitems, c->dp.nitems};
+    const int64_t v[10] = {c->X->gas.n_own, c->X->dm.n_own, c->X->gas.ntile, c->X->dm.ntile, c->X->gas.nown_tile, c->X->dm.nown_tile,
+                           c->X->gp.total, c->X->dp.total, c->X->gp.nitems, c->X->dp.nitems};
     for (int k = 0; k < 10; ++k) o[k] = v[k];
     return DMB_OK;
 }
@@ -810,45 +1112,58 @@ dmb_status dmb_build_cells(dmb_ctx* c, const dmb_particles* gas, const dmb_parti
     if (periodic && !(par->box[0] > 0.0 && par->box[1] > 0.0 && par->box[2] > 0.0))
         return fail(c, DMB_EINVAL, "periodic box needs three positive sides");
     HIPCHK(c, hipSetDevice(c->device));
+    c->X = &c->cells;
+    return build_cells_impl(c, gas, dm, par);
+}
+
+}  // extern "C"
+
+namespace {
+// Cell structure of one box into c->X (arguments already checked).
+dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par)
+{
+    dmb_status s;
+    const bool periodic = par->box[0] > 0.0 || par->box[1] > 0.0 || par->box[2] > 0.0;
+    ENSURE(c, c->X->boxL, 4 * sizeof(double));
     Phase ph(c, DMB_PH_BUILD);
-    for (int k = 0; k < 3; ++k) c->built_L[k] = periodic ? par->box[k] : 0.0;
-    double Lh[4] = {c->built_L[0], c->built_L[1], c->built_L[2], 0.0};
-    HIPCHK(c, hipMemcpyAsync(c->boxL.p, Lh, sizeof(Lh), hipMemcpyHostToDevice, c->stream));
-    if ((s = build_species(c, c->gas, gas)) != DMB_OK) return s;
-    if ((s = build_species(c, c->dm, dm)) != DMB_OK) return s;
+    for (int k = 0; k < 3; ++k) c->X->built_L[k] = periodic ? par->box[k] : 0.0;
+    double Lh[4] = {c->X->built_L[0], c->X->built_L[1], c->X->built_L[2], 0.0};
+    HIPCHK(c, hipMemcpyAsync(c->X->boxL.p, Lh, sizeof(Lh), hipMemcpyHostToDevice, c->stream));
+    if ((s = build_species(c, c->X->gas, gas)) != DMB_OK) return s;
+    if ((s = build_species(c, c->X->dm, dm)) != DMB_OK) return s;
     // read back owner and sub-tile counts
     uint32_t nown[2] = {0, 0}, nsub[2] = {0, 0};
     for (int sp = 0; sp < 2; ++sp) {
-        Species& S = sp == 0 ? c->gas : c->dm;
+        Species& S = sp == 0 ? c->X->gas : c->X->dm;
         if (S.n == 0) continue;
         HIPCHK(c, hipMemcpyAsync(&nown[sp], S.flag_off.as<uint32_t>() + S.n, 4, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipMemcpyAsync(&nsub[sp], S.sub_coff.as<uint32_t>() + S.nchunk, 4, hipMemcpyDeviceToHost, c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->gas.n_own = nown[0];
-    c->dm.n_own = nown[1];
-    c->gas.ntile = nsub[0];
-    c->dm.ntile = nsub[1];
-    if ((s = build_subtiles(c, c->gas)) != DMB_OK) return s;
-    if ((s = build_subtiles(c, c->dm)) != DMB_OK) return s;
-    if ((s = build_owner_tiles(c, c->gas)) != DMB_OK) return s;
-    if ((s = build_owner_tiles(c, c->dm)) != DMB_OK) return s;
-    if ((s = cand_count(c, c->gas, c->dm, c->gp)) != DMB_OK) return s;
-    if ((s = cand_count(c, c->dm, c->gas, c->dp)) != DMB_OK) return s;
+    c->X->gas.n_own = nown[0];
+    c->X->dm.n_own = nown[1];
+    c->X->gas.ntile = nsub[0];
+    c->X->dm.ntile = nsub[1];
+    if ((s = build_subtiles(c, c->X->gas)) != DMB_OK) return s;
+    if ((s = build_subtiles(c, c->X->dm)) != DMB_OK) return s;
+    if ((s = build_owner_tiles(c, c->X->gas)) != DMB_OK) return s;
+    if ((s = build_owner_tiles(c, c->X->dm)) != DMB_OK) return s;
+    if ((s = cand_count(c, c->X->gas, c->X->dm, c->X->gp)) != DMB_OK) return s;
+    if ((s = cand_count(c, c->X->dm, c->X->gas, c->X->dp)) != DMB_OK) return s;
     uint32_t tot[4] = {0, 0, 0, 0};
     double hmax[2] = {0, 0};
-    if (c->gas.nown_tile > 0) {
-        HIPCHK(c, hipMemcpyAsync(&tot[0], c->gp.off.as<uint32_t>() + c->gas.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipMemcpyAsync(&tot[1], c->gp.ioff.as<uint32_t>() + c->gas.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
+    if (c->X->gas.nown_tile > 0) {
+        HIPCHK(c, hipMemcpyAsync(&tot[0], c->X->gp.off.as<uint32_t>() + c->X->gas.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(&tot[1], c->X->gp.ioff.as<uint32_t>() + c->X->gas.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
     }
-    if (c->dm.nown_tile > 0) {
-        HIPCHK(c, hipMemcpyAsync(&tot[2], c->dp.off.as<uint32_t>() + c->dm.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipMemcpyAsync(&tot[3], c->dp.ioff.as<uint32_t>() + c->dm.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
+    if (c->X->dm.nown_tile > 0) {
+        HIPCHK(c, hipMemcpyAsync(&tot[2], c->X->dp.off.as<uint32_t>() + c->X->dm.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(&tot[3], c->X->dp.ioff.as<uint32_t>() + c->X->dm.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
     }
     if (periodic) {
         // largest h of each species from the super-tile maxima
         for (int sp = 0; sp < 2; ++sp) {
-            Species& S = sp == 0 ? c->gas : c->dm;
+            Species& S = sp == 0 ? c->X->gas : c->X->dm;
             if (S.nsuper == 0) continue;
             double* tmp = new double[S.nsuper];
             HIPCHK(c, hipMemcpyAsync(tmp, S.shh.p, S.nsuper * 8, hipMemcpyDeviceToHost, c->stream));
@@ -861,20 +1176,23 @@ dmb_status dmb_build_cells(dmb_ctx* c, const dmb_particles* gas, const dmb_parti
     if (periodic) {
         double Lmin = std::min(par->box[0], std::min(par->box[1], par->box[2]));
         if (hmax[0] + hmax[1] >= 0.5 * Lmin) {
-            c->built_ngas = c->built_ndm = -1;
+            c->X->built_ngas = c->X->built_ndm = -1;
             return fail(c, DMB_ERANGE, "max h_gas + max h_dm = %g >= L/2 = %g", hmax[0] + hmax[1], 0.5 * Lmin);
         }
     }
-    c->gp.total = tot[0]; c->gp.nitems = tot[1];
-    c->dp.total = tot[2]; c->dp.nitems = tot[3];
-    if ((s = cand_write(c, c->gas, c->dm, c->gp)) != DMB_OK) return s;
-    if ((s = cand_write(c, c->dm, c->gas, c->dp)) != DMB_OK) return s;
-    c->built_ngas = gas->n;
-    c->built_ndm = dm->n;
-    c->built_gas_pos = gas->pos;
-    c->built_dm_pos = dm->pos;
+    c->X->gp.total = tot[0]; c->X->gp.nitems = tot[1];
+    c->X->dp.total = tot[2]; c->X->dp.nitems = tot[3];
+    if ((s = cand_write(c, c->X->gas, c->X->dm, c->X->gp)) != DMB_OK) return s;
+    if ((s = cand_write(c, c->X->dm, c->X->gas, c->X->dp)) != DMB_OK) return s;
+    c->X->built_ngas = gas->n;
+    c->X->built_ndm = dm->n;
+    c->X->built_gas_pos = gas->pos;
+    c->X->built_dm_pos = dm->pos;
     return DMB_OK;
 }
+}  // namespace
+
+extern "C" {
 
 dmb_status dmb_interact_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
                              dmb_out* out)
@@ -884,7 +1202,8 @@ dmb_status dmb_interact_step(dmb_ctx* c, const dmb_particles* gas, const dmb_par
     dmb_status s;
     if ((s = check_particles(c, gas, "gas", true)) != DMB_OK) return s;
     if ((s = check_particles(c, dm, "dm", false)) != DMB_OK) return s;
-    if (gas->n != c->built_ngas || dm->n != c->built_ndm)
+    c->X = &c->cells;
+    if (gas->n != c->X->built_ngas || dm->n != c->X->built_ndm)
         return fail(c, DMB_ESTALE, "interact_step: sizes differ from the last build_cells");
     if (gas->n > 0 && (!gas->vel || !gas->mass || !gas->u))
         return fail(c, DMB_EINVAL, "gas: null vel, mass or u");
@@ -1210,6 +1529,164 @@ dmb_status dmb_mlp_eval(dmb_ctx* c, int64_t n, const double* x, double* out)
                        c->gl64.as<const double>() + kMaxQuadNodes, 48, hw, bmin, out);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DMB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched boxes
+namespace {
+struct CellsGuard {          // restores the single-box structure as current
+    dmb_ctx* c;
+    ~CellsGuard() { c->X = &c->cells; }
+};
+
+dmb_status check_batch(dmb_ctx* c, int32_t nbox, const dmb_particles* gas, const dmb_particles* dm,
+                       const dmb_params* par)
+{
+    if (nbox < 1 || nbox > 65536) return fail(c, DMB_EINVAL, "nbox %d outside 1..65536", nbox);
+    if (!gas || !dm || !par) return fail(c, DMB_EINVAL, "null batch arrays");
+    dmb_status s;
+    for (int b = 0; b < nbox; ++b) {
+        if ((s = check_particles(c, gas + b, "gas", true)) != DMB_OK) return s;
+        if ((s = check_particles(c, dm + b, "dm", false)) != DMB_OK) return s;
+        const dmb_params* p = par + b;
+        const bool periodic = p->box[0] > 0.0 || p->box[1] > 0.0 || p->box[2] > 0.0;
+        if (periodic && !(p->box[0] > 0.0 && p->box[1] > 0.0 && p->box[2] > 0.0))
+            return fail(c, DMB_EINVAL, "box %d: periodic box needs three positive sides", b);
+    }
+    return DMB_OK;
+}
+
+dmb_status batch_build_all(dmb_ctx* c, int32_t nbox, const dmb_particles* gas, const dmb_particles* dm,
+                           const dmb_params* par)
+{
+    CellsGuard guard{c};
+    while (int(c->boxes.size()) < nbox) c->boxes.push_back(new Cells());
+    for (int b = 0; b < nbox; ++b) {
+        c->X = c->boxes[b];
+        dmb_status s = build_cells_impl(c, gas + b, dm + b, par + b);
+        if (s != DMB_OK) {
+            c->batch_n = 0;
+            char msg[512];
+            snprintf(msg, sizeof(msg), "box %d: %s", b, c->err);
+            return fail(c, s, "%s", msg);
+        }
+    }
+    c->batch_n = nbox;
+    return DMB_OK;
+}
+
+dmb_status batch_step_checked(dmb_ctx* c, int32_t nbox, const dmb_particles* gas, const dmb_particles* dm,
+                              const dmb_params* par, dmb_out* out, int32_t nsteps, int32_t use_graph)
+{
+    if (nbox != c->batch_n) return fail(c, DMB_ESTALE, "batch_step: %d boxes, %d built", nbox, c->batch_n);
+    if (!out) return fail(c, DMB_EINVAL, "null outputs");
+    if (nsteps < 1) return fail(c, DMB_EINVAL, "nsteps < 1");
+    const dmb_params& p0 = par[0];
+    if (!n_supported(p0.n_pow)) return fail(c, DMB_EINVAL, "n_pow %d not supported", p0.n_pow);
+    if (p0.rates != DMB_RATES_EXACT && p0.rates != DMB_RATES_QUAD && p0.rates != DMB_RATES_MLP)
+        return fail(c, DMB_EINVAL, "rates mode %d not supported", p0.rates);
+    if (p0.rates == DMB_RATES_MLP && (!c->mlp_ready || p0.precision != DMB_FP32))
+        return fail(c, DMB_EINVAL, "network rates need loaded weights and DMB_FP32");
+    if (p0.rates != DMB_RATES_EXACT && (quad_k(&p0) < 4 || quad_k(&p0) > kMaxQuadNodes))
+        return fail(c, DMB_EINVAL, "quad_nodes %d outside 4..%d", p0.quad_nodes, kMaxQuadNodes);
+    for (int b = 0; b < nbox; ++b) {
+        const dmb_params& p = par[b];
+        if (p.n_pow != p0.n_pow || p.precision != p0.precision || p.rates != p0.rates ||
+            quad_k(&p) != quad_k(&p0))
+            return fail(c, DMB_EINVAL, "box %d: n_pow, precision, rates and quad_nodes must agree across boxes", b);
+        if (!(p.m_chi_g > 0.0) || !(p.sigma0_cm2 >= 0.0)) return fail(c, DMB_EINVAL, "box %d: bad m_chi or sigma0", b);
+        const Cells& X = *c->boxes[b];
+        if (gas[b].n != X.built_ngas || dm[b].n != X.built_ndm)
+            return fail(c, DMB_ESTALE, "box %d: sizes differ from the last batch build", b);
+        if (gas[b].n > 0 && (!gas[b].vel || !gas[b].mass || !gas[b].u))
+            return fail(c, DMB_EINVAL, "box %d: gas: null vel, mass or u", b);
+        if (dm[b].n > 0 && (!dm[b].vel || !dm[b].mass)) return fail(c, DMB_EINVAL, "box %d: dm: null vel or mass", b);
+        if ((gas[b].n > 0 && (!out[b].dp_gas || !out[b].de_gas)) ||
+            (dm[b].n > 0 && (!out[b].dv_dm || !out[b].partner)) || !out[b].counters)
+            return fail(c, DMB_EINVAL, "box %d: null output array or counters", b);
+    }
+    if (p0.precision == DMB_FP64) return batch_dispatch_rates<double>(c, nbox, gas, dm, par, out, nsteps, use_graph != 0);
+    if (p0.precision == DMB_FP32) return batch_dispatch_rates<float>(c, nbox, gas, dm, par, out, nsteps, use_graph != 0);
+    return fail(c, DMB_EINVAL, "precision %d not supported", p0.precision);
+}
+}  // namespace
+
+extern "C" {
+
+dmb_status dmb_batch_build(dmb_ctx* c, int32_t nbox, const dmb_particles* gas, const dmb_particles* dm,
+                           const dmb_params* par)
+{
+    if (!c) return DMB_EINVAL;
+    dmb_status s = check_batch(c, nbox, gas, dm, par);
+    if (s != DMB_OK) return s;
+    HIPCHK(c, hipSetDevice(c->device));
+    return batch_build_all(c, nbox, gas, dm, par);
+}
+
+dmb_status dmb_batch_step(dmb_ctx* c, int32_t nbox, const dmb_particles* gas, const dmb_particles* dm,
+                          const dmb_params* par, dmb_out* out, int32_t nsteps, int32_t use_graph)
+{
+    if (!c) return DMB_EINVAL;
+    dmb_status s = check_batch(c, nbox, gas, dm, par);
+    if (s != DMB_OK) return s;
+    HIPCHK(c, hipSetDevice(c->device));
+    CellsGuard guard{c};
+    return batch_step_checked(c, nbox, gas, dm, par, out, nsteps, use_graph);
+}
+
+dmb_status dmb_batch_tune(dmb_ctx* c, int32_t nbox, const dmb_particles* gas, const dmb_particles* dm,
+                          const dmb_params* par, dmb_out* out, int64_t* choice)
+{
+    if (!c) return DMB_EINVAL;
+    dmb_status s = check_batch(c, nbox, gas, dm, par);
+    if (s != DMB_OK) return s;
+    HIPCHK(c, hipSetDevice(c->device));
+    CellsGuard guard{c};
+    const int splits[3] = {32, 64, 128};
+    const int deltas[3] = {0, 1, 2};
+    const int grids[2] = {50, 100};
+    const bool prof = c->prof;
+    c->prof = false;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    double best = 1e300;
+    int bs = c->split, bd = c->subtile_delta, bg = c->grid_pct;
+    for (int sp : splits)
+        for (int dl : deltas) {
+            c->split = sp;
+            c->subtile_delta = dl;
+            if ((s = batch_build_all(c, nbox, gas, dm, par)) != DMB_OK) break;
+            for (int gp : grids) {
+                c->grid_pct = gp;
+                if ((s = batch_step_checked(c, nbox, gas, dm, par, out, 1, 0)) != DMB_OK) break;   // warm-up
+                (void)hipEventRecord(e0, c->stream);
+                if ((s = batch_step_checked(c, nbox, gas, dm, par, out, 2, 0)) != DMB_OK) break;
+                (void)hipEventRecord(e1, c->stream);
+                (void)hipEventSynchronize(e1);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best) { best = ms; bs = sp; bd = dl; bg = gp; }
+            }
+            if (s != DMB_OK) break;
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->prof = prof;
+    c->split = bs;
+    c->subtile_delta = bd;
+    c->grid_pct = bg;
+    if (s != DMB_OK) return s;
+    if ((s = batch_build_all(c, nbox, gas, dm, par)) != DMB_OK) return s;
+    if (choice) {
+        choice[0] = bs;
+        choice[1] = bd;
+        choice[2] = bg;
+        choice[3] = int64_t(best * 1000.0 / 2.0);   // microseconds per step
+    }
     return DMB_OK;
 }
 

@@ -240,7 +240,8 @@ __global__ __launch_bounds__(64) void k_super_bounds(int64_t ntile, const double
 // not order.
 template <bool WRITE>
 __global__ __launch_bounds__(64) void k_subtile_split(const uint64_t* __restrict__ keys, int64_t n, int lo_bit,
-                                                      uint32_t* __restrict__ cnt, const uint32_t* __restrict__ off,
+                                                      int cut_delta, uint32_t* __restrict__ cnt,
+                                                      const uint32_t* __restrict__ off,
                                                       uint32_t* __restrict__ sub_start, uint32_t* __restrict__ sub_cnt)
 {
     const int lane = lane_id();
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(64) void k_subtile_split(const uint64_t* __restrict
         int cntt = __popcll(__ballot(valid && lane > 0 && lvl >= t));
         if (cntt >= need) { med = t; break; }
     }
-    const bool cut = valid && (lane == 0 || lvl < med - 1);
+    const bool cut = valid && (lane == 0 || lvl < med - cut_delta);
     const uint64_t cm = __ballot(cut);
     if (!WRITE) {
         if (lane == 0) cnt[c] = uint32_t(__popcll(cm));
@@ -727,6 +728,19 @@ __device__ __forceinline__ void group_decode(const GroupLds& S, int pos, int* o_
 
 // ---------------------------------------------------------------------------
 // Gas (mean-field) pass: owners = active gas, others = DM.
+// Box of global work item `it` in a batched pass: box_items[b] is the first
+// item of box b (box_items[nbox] = total).
+__device__ __forceinline__ int box_of_item(const int64_t* __restrict__ box_items, int nbox, int64_t it)
+{
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (box_items[mid] <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 struct GasPassArgs {
     PassGeom g;
     const double* Vx; const double* Vy; const double* Vz;     // gas, sorted
@@ -759,9 +773,12 @@ __device__ __forceinline__ void gas_write_out(const GasPassArgs& a, uint32_t o, 
     a.de[o] = sc * acc[3];
 }
 
-template <typename Real, int N, bool EXACT_G, int RM>
-__global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kRatesMlp ? 2 : 1) void k_pass_gas(GasPassArgs a)
+template <typename Real, int N, bool EXACT_G, int RM, bool BATCH = false>
+__global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kRatesMlp ? 2 : 1) void k_pass_gas(
+    GasPassArgs a0, const GasPassArgs* __restrict__ boxes, const int64_t* __restrict__ box_items, int nbox)
 {
+    // BATCH: one launch over the work items of all boxes; a0 holds the
+    // shared queue and item total, boxes[b] the arguments of box b.
     // The network variant runs kMlpPassWaves independent waves per block so
     // that they share one LDS copy of the weights.
     constexpr int W = RM == kRatesMlp ? kMlpPassWaves : 1;
@@ -776,30 +793,44 @@ __global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kR
     double* o_x = o_x_[wv]; double* o_y = o_y_[wv]; double* o_z = o_z_[wv]; double* o_h = o_h_[wv];
     double* o_Vx = o_Vx_[wv]; double* o_Vy = o_Vy_[wv]; double* o_Vz = o_Vz_[wv];
     Real* o_i2 = o_i2_[wv]; Real* o_a = o_a_[wv]; Real* o_b = o_b_[wv]; Real* o_r = o_r_[wv];
-    const PassGeom& G = a.g;
     const int lane = lane_id();
-    const Real* inv2s2 = reinterpret_cast<const Real*>(a.inv2s2);
-    const Real* ra = reinterpret_cast<const Real*>(a.ra);
-    const Real* rb = reinterpret_cast<const Real*>(a.rb);
-    const Real* rr = reinterpret_cast<const Real*>(a.rr);
-    const Real* dm_m = reinterpret_cast<const Real*>(a.dm_m);
-    const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
     if constexpr (RM == kRatesQuad || RM == kRatesMlp) {
-        if (int(threadIdx.x) < a.gl_k) {
-            s_gx[threadIdx.x] = reinterpret_cast<const Real*>(a.gl_x)[threadIdx.x];
-            s_gw[threadIdx.x] = reinterpret_cast<const Real*>(a.gl_w)[threadIdx.x];
+        if (int(threadIdx.x) < a0.gl_k) {
+            s_gx[threadIdx.x] = reinterpret_cast<const Real*>(a0.gl_x)[threadIdx.x];
+            s_gw[threadIdx.x] = reinterpret_cast<const Real*>(a0.gl_w)[threadIdx.x];
         }
     }
     if constexpr (RM == kRatesMlp) {
-        const uint4* src = reinterpret_cast<const uint4*>(a.mlp);
+        const uint4* src = reinterpret_cast<const uint4*>(a0.mlp);
         uint4* dst = reinterpret_cast<uint4*>(s_mlp);
         for (int k = int(threadIdx.x); k < int(kMlpInferBytes / 16); k += 64 * W) dst[k] = src[k];
         __syncthreads();
     }
-    const Real inv_alpha = Real(a.inv_alpha), q_hw = Real(a.gl_hw), q_bmin = Real(a.gl_bmin);
+    const Real inv_alpha = Real(a0.inv_alpha), q_hw = Real(a0.gl_hw), q_bmin = Real(a0.gl_bmin);
     int64_t it;
     uint64_t npairs = 0;
-    while (item_next<W>(G.queue_ctr, G.n_items, &it)) {
+    int cur_b = 0;
+    while (item_next<W>(a0.g.queue_ctr, a0.g.n_items, &it)) {
+        int b = 0;
+        if constexpr (BATCH) {
+            b = box_of_item(box_items, nbox, it);
+            it -= box_items[b];
+            if (b != cur_b) {   // counters belong to the box: flush when the box changes
+                for (int d = 32; d >= 1; d >>= 1) npairs += __shfl_xor(npairs, d);
+                if (lane == 0 && npairs)
+                    atomicAdd((unsigned long long*)&boxes[cur_b].g.counters[0], (unsigned long long)npairs);
+                npairs = 0;
+                cur_b = b;
+            }
+        }
+        const GasPassArgs& a = BATCH ? boxes[b] : a0;
+        const PassGeom& G = a.g;
+        const Real* inv2s2 = reinterpret_cast<const Real*>(a.inv2s2);
+        const Real* ra = reinterpret_cast<const Real*>(a.ra);
+        const Real* rb = reinterpret_cast<const Real*>(a.rb);
+        const Real* rr = reinterpret_cast<const Real*>(a.rr);
+        const Real* dm_m = reinterpret_cast<const Real*>(a.dm_m);
+        const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
         const int64_t t = G.it_tile[it];
         const uint32_t cb = G.it_cb[it], ce = G.it_ce[it];
         const int64_t slot = t * kTile + lane;
@@ -853,7 +884,7 @@ __global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kR
                                 Br = Ar * w2;
                             } else {
                                 if constexpr (RM == kRatesQuad)
-                                    rate_quad<N, Real>(sqrt_real(Real(2) * w2 * i2), s_gx, s_gw, a.gl_k, inv_alpha,
+                                    rate_quad<N, Real>(sqrt_real(Real(2) * w2 * i2), s_gx, s_gw, a0.gl_k, inv_alpha,
                                                        q_hw, q_bmin, &FA, &FB);
                                 else
                                     rate_1f1<N, Real>(w2 * i2, &FA, &FB);
@@ -905,11 +936,11 @@ __global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kR
                         // 16-column blocks that hold some
                         const int nlive = min(H - base, 64);
                         if (nlive > 32)
-                            mlp_forward64<4, 4>(Wl, mlp_input(u), a.mlp_nidx, &yA, &yB);
+                            mlp_forward64<4, 4>(Wl, mlp_input(u), a0.mlp_nidx, &yA, &yB);
                         else if (nlive > 16)
-                            mlp_forward64<2, 2>(Wl, mlp_input(u), a.mlp_nidx, &yA, &yB);
+                            mlp_forward64<2, 2>(Wl, mlp_input(u), a0.mlp_nidx, &yA, &yB);
                         else
-                            mlp_forward64<1, 1>(Wl, mlp_input(u), a.mlp_nidx, &yA, &yB);
+                            mlp_forward64<1, 1>(Wl, mlp_input(u), a0.mlp_nidx, &yA, &yB);
                     }
                     if (live) {
                         float Ar, Br;
@@ -920,11 +951,11 @@ __global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kR
                             float FA, FB;
                             if (net) {
                                 float bA, bB;
-                                mlp_base<N>(u * u, a.mlp_c0A, a.mlp_c1A, a.mlp_c0B, a.mlp_c1B, &bA, &bB);
-                                FA = a.mlp_kA * bA * __expf(yA);
-                                FB = a.mlp_kB * bB * __expf(yB);
+                                mlp_base<N>(u * u, a0.mlp_c0A, a0.mlp_c1A, a0.mlp_c0B, a0.mlp_c1B, &bA, &bB);
+                                FA = a0.mlp_kA * bA * __expf(yA);
+                                FB = a0.mlp_kB * bB * __expf(yB);
                             } else {
-                                rate_quad<N, float>(u, s_gx, s_gw, a.gl_k, inv_alpha, q_hw, q_bmin, &FA, &FB);
+                                rate_quad<N, float>(u, s_gx, s_gw, a0.gl_k, inv_alpha, q_hw, q_bmin, &FA, &FB);
                             }
                             Ar = o_a[o] * FA;
                             Br = o_b[o] * FB;
@@ -955,7 +986,8 @@ __global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kR
         }
     }
     for (int d = 32; d >= 1; d >>= 1) npairs += __shfl_xor(npairs, d);
-    if (lane == 0 && npairs) atomicAdd((unsigned long long*)&G.counters[0], (unsigned long long)npairs);
+    uint64_t* cnt = BATCH ? boxes[cur_b].g.counters : a0.g.counters;
+    if (lane == 0 && npairs) atomicAdd((unsigned long long*)&cnt[0], (unsigned long long)npairs);
 }
 
 // ---------------------------------------------------------------------------
@@ -970,6 +1002,7 @@ struct DmPassArgs {
     const uint32_t* gas_perm;                                 // gas sorted pos -> index
     const float4* gtab;
     uint32_t k0, k1, step, box;
+    const uint32_t* step_off;     // nullable: device offset added to step (graph replays)
     double* part_p;               // [n_items][64]
     float* part_pm;               // [n_items][64]
     uint8_t* part_nb;             // [n_items][64] near-boundary flags
@@ -1025,23 +1058,58 @@ __device__ __forceinline__ uint32_t dm_decide(uint32_t o, int64_t s, double P, f
     return f;
 }
 
-template <typename Real, int N, bool EXACT_G>
-__global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a)
+template <typename Real, int N, bool EXACT_G, bool BATCH = false>
+__global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a0, const DmPassArgs* __restrict__ boxes,
+                                                   const int64_t* __restrict__ box_items, int nbox)
 {
     __shared__ GroupLds S;
     __shared__ double o_x[64], o_y[64], o_z[64], o_h[64], o_vx[64], o_vy[64], o_vz[64];
     __shared__ Real o_dt[64];
     __shared__ uint32_t o_id[64];
-    const PassGeom& G = a.g;
     const int lane = lane_id();
-    const Real* dtr = reinterpret_cast<const Real*>(a.dtr);
-    const Real* vs = reinterpret_cast<const Real*>(a.vs);
-    const Real* Kp = reinterpret_cast<const Real*>(a.K);
-    const Real* cr = reinterpret_cast<const Real*>(a.crit);
-    const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
     int64_t it;
     uint64_t npairs = 0, ncrit = 0, nnear = 0, nscat = 0, npge1 = 0, nnonf = 0, nneard = 0;
-    while (item_next(G.queue_ctr, G.n_items, &it)) {
+    int cur_b = 0;
+    // counters belong to the box: flushed when the box changes and at the end
+    auto flush = [&](uint64_t* counters) {
+        for (int d = 32; d >= 1; d >>= 1) {
+            npairs += __shfl_xor(npairs, d);
+            ncrit += __shfl_xor(ncrit, d);
+            nnear += __shfl_xor(nnear, d);
+            nscat += __shfl_xor(nscat, d);
+            npge1 += __shfl_xor(npge1, d);
+            nnonf += __shfl_xor(nnonf, d);
+            nneard += __shfl_xor(nneard, d);
+        }
+        if (lane == 0) {
+            if (npairs) atomicAdd((unsigned long long*)&counters[1], (unsigned long long)npairs);
+            if (nscat) atomicAdd((unsigned long long*)&counters[2], (unsigned long long)nscat);
+            if (nnear) atomicAdd((unsigned long long*)&counters[3], (unsigned long long)nnear);
+            if (nneard) atomicAdd((unsigned long long*)&counters[4], (unsigned long long)nneard);
+            if (ncrit) atomicAdd((unsigned long long*)&counters[5], (unsigned long long)ncrit);
+            if (npge1) atomicAdd((unsigned long long*)&counters[6], (unsigned long long)npge1);
+            if (nnonf) atomicAdd((unsigned long long*)&counters[7], (unsigned long long)nnonf);
+        }
+        npairs = ncrit = nnear = nscat = npge1 = nnonf = nneard = 0;
+    };
+    while (item_next(a0.g.queue_ctr, a0.g.n_items, &it)) {
+        int b = 0;
+        if constexpr (BATCH) {
+            b = box_of_item(box_items, nbox, it);
+            it -= box_items[b];
+            if (b != cur_b) {
+                flush(boxes[cur_b].g.counters);
+                cur_b = b;
+            }
+        }
+        const DmPassArgs& a = BATCH ? boxes[b] : a0;
+        const PassGeom& G = a.g;
+        const Real* dtr = reinterpret_cast<const Real*>(a.dtr);
+        const Real* vs = reinterpret_cast<const Real*>(a.vs);
+        const Real* Kp = reinterpret_cast<const Real*>(a.K);
+        const Real* cr = reinterpret_cast<const Real*>(a.crit);
+        const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
+        const uint32_t step = a.step + (a.step_off ? *a.step_off : 0u);
         const int64_t t = G.it_tile[it];
         const uint32_t cb = G.it_cb[it], ce = G.it_ce[it];
         const int64_t slot = t * kTile + lane;
@@ -1087,7 +1155,7 @@ __global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a)
                         Real urel[3];
                         const Real P = pair_P<Real, N, EXACT_G>(d2, o_h[o], qh, o_vx[o], o_vy[o], o_vz[o], a.Vx[q],
                                                                 a.Vy[q], a.Vz[q], vs[q], Kp[q], o_dt[o], o_id[o],
-                                                                a.gas_perm[q], a.step, a.box, a.k0, a.k1, a.gtab, urel);
+                                                                a.gas_perm[q], step, a.box, a.k0, a.k1, a.gtab, urel);
                         cP = double(P);
                         cM = P;
                         if (P >= cr[q]) ncrit++;
@@ -1108,7 +1176,7 @@ __global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a)
         if (G.item_off[t + 1] - G.item_off[t] == 1u) {
             if (ov) {
                 if (accNB) nnear++;
-                uint32_t f = dm_decide(o_id[lane], slot, accP, float(accM), a.step, a.box, a.k0, a.k1, a.psum_own,
+                uint32_t f = dm_decide(o_id[lane], slot, accP, float(accM), step, a.box, a.k0, a.k1, a.psum_own,
                                        a.psum, a.pmax, a.scount, a.slist);
                 nscat += f & 1u; npge1 += (f >> 1) & 1u; nnonf += (f >> 2) & 1u; nneard += (f >> 3) & 1u;
             }
@@ -1118,24 +1186,7 @@ __global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a)
             a.part_nb[it * kTile + lane] = uint8_t(accNB);
         }
     }
-    for (int d = 32; d >= 1; d >>= 1) {
-        npairs += __shfl_xor(npairs, d);
-        ncrit += __shfl_xor(ncrit, d);
-        nnear += __shfl_xor(nnear, d);
-        nscat += __shfl_xor(nscat, d);
-        npge1 += __shfl_xor(npge1, d);
-        nnonf += __shfl_xor(nnonf, d);
-        nneard += __shfl_xor(nneard, d);
-    }
-    if (lane == 0) {
-        if (npairs) atomicAdd((unsigned long long*)&G.counters[1], (unsigned long long)npairs);
-        if (nscat) atomicAdd((unsigned long long*)&G.counters[2], (unsigned long long)nscat);
-        if (nnear) atomicAdd((unsigned long long*)&G.counters[3], (unsigned long long)nnear);
-        if (nneard) atomicAdd((unsigned long long*)&G.counters[4], (unsigned long long)nneard);
-        if (ncrit) atomicAdd((unsigned long long*)&G.counters[5], (unsigned long long)ncrit);
-        if (npge1) atomicAdd((unsigned long long*)&G.counters[6], (unsigned long long)npge1);
-        if (nnonf) atomicAdd((unsigned long long*)&G.counters[7], (unsigned long long)nnonf);
-    }
+    flush(BATCH ? boxes[cur_b].g.counters : a0.g.counters);
 }
 
 // ---------------------------------------------------------------------------
@@ -1178,6 +1229,7 @@ struct DmCombineArgs {
     const uint32_t* item_off;
     const double* part_p; const float* part_pm; const uint8_t* part_nb;
     uint32_t k0, k1, step, box;
+    const uint32_t* step_off;     // nullable: device offset added to step
     double* psum_own;             // [n_own] P_i in owner-slot order
     double* psum; double* pmax;   // outputs (nullable)
     uint32_t* scount; uint32_t* slist;
@@ -1200,7 +1252,8 @@ __global__ __launch_bounds__(256) void k_combine_dm(DmCombineArgs a)
                 nb |= a.part_nb[int64_t(it) * kTile + l];
             }
             uint32_t o = a.perm[a.own[s]];
-            f = dm_decide(o, s, P, Pm, a.step, a.box, a.k0, a.k1, a.psum_own, a.psum, a.pmax, a.scount, a.slist);
+            f = dm_decide(o, s, P, Pm, a.step + (a.step_off ? *a.step_off : 0u), a.box, a.k0, a.k1, a.psum_own,
+                          a.psum, a.pmax, a.scount, a.slist);
         }
     }
     uint64_t b0 = __ballot(f & 1u), b1 = __ballot(f & 2u), b2 = __ballot(f & 4u), b3 = __ballot(f & 8u);
@@ -1233,6 +1286,7 @@ struct ResolveArgs {
     double m_chi;
     const float4* gtab;
     uint32_t k0, k1, step, box;
+    const uint32_t* step_off;     // nullable: device offset added to step
     int n_gas_bits;
     uint32_t n_gas;
     const uint32_t* scount; const uint32_t* slist;
@@ -1266,6 +1320,7 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
     __shared__ int s_near;
     const PassGeom& G = a.g;
     const int tid = threadIdx.x;
+    const uint32_t step = a.step + (a.step_off ? *a.step_off : 0u);
     const Real* dtr = reinterpret_cast<const Real*>(a.dtr);
     const Real* vs = reinterpret_cast<const Real*>(a.vs);
     const Real* Kp = reinterpret_cast<const Real*>(a.K);
@@ -1279,7 +1334,7 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
         const double mvx = a.vx[sp], mvy = a.vy[sp], mvz = a.vz[sp];
         const Real mdt = dtr[sp];
         const uint32_t oid = a.dm_perm[sp];
-        U4 rd = philox_block(oid, 0xFFFFFFFFu, a.step, kTagDecision, a.box, a.k0, a.k1);
+        U4 rd = philox_block(oid, 0xFFFFFFFFu, step, kTagDecision, a.box, a.k0, a.k1);
         const unsigned __int128 Ufix = (unsigned __int128)(2ull * (rd.x >> 8) + 1ull) << 39;
         double A[6];
         for (int k = 0; k < 6; ++k) A[k] = G.obox[6 * t + k];
@@ -1328,7 +1383,7 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
                         Real urel[3];
                         const double P = double(pair_P<Real, N, EXACT_G>(d2, mh, G.th[k], mvx, mvy, mvz, a.Vx[k],
                                                                          a.Vy[k], a.Vz[k], vs[k], Kp[k], mdt, oid, gid,
-                                                                         a.step, a.box, a.k0, a.k1, a.gtab, urel));
+                                                                         step, a.box, a.k0, a.k1, a.gtab, urel));
                         fn(gid, P);
                     }
                 }
@@ -1412,7 +1467,7 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
             const double muj = a.gas_mu ? a.gas_mu[j] : kMpG;
             Real vsj, i2, ra, rb, rr, cr;
             gas_derived<Real>(a.gas_u[j], muj, a.m_chi, 1.0, 0, &vsj, &i2, &ra, &rb, &rr, &cr);
-            U4 r = philox_block(oid, j, a.step, kTagGasVel, a.box, a.k0, a.k1);
+            U4 r = philox_block(oid, j, step, kTagGasVel, a.box, a.k0, a.k1);
             Real z[3];
             normals3<Real>(r, z);
             Real ux = Real(mvx - a.gas_vel[3 * int64_t(j)]) - vsj * z[0];
@@ -1421,7 +1476,7 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
             Real vrel = sqrt_real(ux * ux + uy * uy + uz * uz);
             double dvx = 0.0, dvy = 0.0, dvz = 0.0;
             if (vrel > Real(0)) {
-                U4 r2 = philox_block(oid, j, a.step, kTagDir, a.box, a.k0, a.k1);
+                U4 r2 = philox_block(oid, j, step, kTagDir, a.box, a.k0, a.k1);
                 Real ct = Real(2) * u24<Real>(r2.x) - Real(1);
                 Real st = sqrt_real(fmax(Real(0), Real(1) - ct * ct));
                 Real sp_, cp_;
