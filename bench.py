@@ -28,9 +28,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Vector ALU: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz lane-instructions per second.
 VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
-# VALU instructions per pair in the pair-body basic blocks of the built
-# kernels (binary32 path, n = 0), counted from the gfx950 assembly.
-PAIR_BODY_VALU = {"pass_dm": 281, "pass_gas": 207}
+# VALU instructions per visited pair in the built kernels (binary32 pair
+# math, n = 0, closed-form rates), counted from their gfx950 assembly: the
+# hit decode with the exact distance recheck, plus the pair body (DM pass:
+# overlap table, Philox4x32-10, Box-Muller, P_ij, running sums; gas pass:
+# overlap table, relative velocity, erf/exp rate terms, the four sums).
+PAIR_BODY_VALU = {"pass_dm": 90 + 333, "pass_gas": 89 + 120 + 49}
 
 
 def log(msg):
@@ -45,22 +48,49 @@ def src_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def make_workload(name: str, scale: float, seed: int):
+def make_workload(name: str, scale: float, seed: int, n_pow: int = 0):
     import workloads
+    sig = workloads.sigma0_for_npow(n_pow)
     if name == "galaxy":
-        cfg = workloads.galaxy(n_gas=int(1_000_000 * scale), n_dm=int(4_000_000 * scale), seed=(2, seed))
+        cfg = workloads.galaxy(n_gas=int(1_000_000 * scale), n_dm=int(4_000_000 * scale), seed=(2, seed),
+                               n_pow=n_pow, sigma0_cm2=sig)
         desc = {"workload": "isolated galaxy: exponential gas disk + NFW halo",
                 "n_gas": len(cfg["gas"]["mass"]), "n_dm": len(cfg["dm"]["mass"]), "n_ngb": 64,
-                "sigma0_cm2": cfg["params"]["sigma0_cm2"], "m_chi_over_mp": 2.0, "n_pow": 0, "dt_myr": 1.0,
+                "sigma0_cm2": sig, "m_chi_over_mp": 2.0, "n_pow": n_pow, "dt_myr": 1.0,
+                "pair_math": "binary32", "accumulation": "binary64"}
+    elif name == "milky_way":
+        cfg = workloads.milky_way(n_gas=int(8_000_000 * scale), n_dm=int(32_000_000 * scale), seed=(3, seed),
+                                  n_pow=n_pow, sigma0_cm2=sig)
+        desc = {"workload": "Milky-Way-scale disk + halo, h over 3 decades, 10% active per species",
+                "n_gas": len(cfg["gas"]["mass"]), "n_dm": len(cfg["dm"]["mass"]), "n_ngb": 64,
+                "sigma0_cm2": sig, "m_chi_over_mp": 2.0, "n_pow": n_pow, "dt_myr": 0.1,
                 "pair_math": "binary32", "accumulation": "binary64"}
     elif name == "box":
-        cfg = workloads.box(seed=(1, seed))
+        cfg = workloads.box(seed=(1, seed), n_pow=n_pow, sigma0_cm2=sig)
         desc = {"workload": "periodic test box", "n_gas": 4096, "n_dm": 4096, "n_ngb": 32,
-                "sigma0_cm2": 1e-24, "m_chi_over_mp": 2.0, "n_pow": 0, "dt_myr": 0.05,
+                "sigma0_cm2": sig, "m_chi_over_mp": 2.0, "n_pow": n_pow, "dt_myr": 0.05,
                 "pair_math": "binary64", "accumulation": "binary64"}
     else:
         raise SystemExit(f"unknown workload {name}")
     return cfg, desc
+
+
+def train_network(ctx, dev, log_fn) -> dict:
+    """The rate-closure network trained on the GPU (2 000 000 samples labelled
+    by binary64 quadrature, 200 epochs of Adam)."""
+    import torch
+    import workloads
+    t0 = time.time()
+    X = torch.from_numpy(workloads.mlp_samples(2_000_000, seed=(4, 1))).to(dev)
+    Y = ctx.mlp_labels(X)
+    torch.cuda.synchronize()
+    t1 = time.time()
+    losses = ctx.mlp_train(X, Y, epochs=200, batch=4096, lr0=2e-3, lr_min=1e-5, seed=1, init=True, use_graph=True)
+    t2 = time.time()
+    del X, Y
+    log_fn(f"bench: network trained: labels {t1 - t0:.2f} s, 200 epochs {t2 - t1:.2f} s, loss {losses[-1]:.3e}")
+    return {"samples": 2_000_000, "epochs": 200, "batch": 4096, "label_s": round(t1 - t0, 3),
+            "train_s": round(t2 - t1, 3), "final_loss": float(losses[-1])}
 
 
 def cpu_baseline(cfg, seconds: float, seed: int = 0):
@@ -106,17 +136,7 @@ def surrogate_compare(ctx, cfg, dev, steps: int, log_fn) -> dict:
     import torch
     import paper_2603_24688_amd as dmb
     import workloads
-    t0 = time.time()
-    X = torch.from_numpy(workloads.mlp_samples(2_000_000, seed=(4, 1))).to(dev)
-    Y = ctx.mlp_labels(X)
-    torch.cuda.synchronize()
-    t1 = time.time()
-    losses = ctx.mlp_train(X, Y, epochs=200, batch=4096, lr0=2e-3, lr_min=1e-5, seed=1, init=True, use_graph=True)
-    t2 = time.time()
-    del X, Y
-    log_fn(f"bench: network trained: labels {t1 - t0:.2f} s, 200 epochs {t2 - t1:.2f} s, loss {losses[-1]:.3e}")
-    res = {"train": {"samples": 2_000_000, "epochs": 200, "batch": 4096, "label_s": round(t1 - t0, 3),
-                     "train_s": round(t2 - t1, 3), "final_loss": float(losses[-1])}}
+    res = {"train": train_network(ctx, dev, log_fn)}
     G = dmb.to_device(cfg["gas"], dev)
     D = dmb.to_device(cfg["dm"], dev)
     out = dmb.alloc_out(len(cfg["gas"]["mass"]), len(cfg["dm"]["mass"]), dev)
@@ -162,6 +182,49 @@ def surrogate_compare(ctx, cfg, dev, steps: int, log_fn) -> dict:
     return res
 
 
+def batch_sweep(dev, steps: int, log_fn) -> dict:
+    """Parameter sweep of 64 periodic boxes of uneven size (10^4 .. 5 10^5
+    particles per species, sigma0 1e-28 .. 1e-24 cm^2, m_chi/m_p in
+    {0.5, 1, 2, 5}; the test box's densities and temperatures): autotune,
+    then `steps` replays of one captured step of all boxes."""
+    import torch
+    import paper_2603_24688_amd as dmb
+    import workloads
+    t0 = time.time()
+    bx = workloads.batch(n_box=64, n_min=10_000, n_max=500_000, seed=(5, 1))
+    G = [dmb.to_device(b["gas"], dev) for b in bx]
+    D = [dmb.to_device(b["dm"], dev) for b in bx]
+    P = [dict(b["params"]) for b in bx]
+    O = [dmb.alloc_out(len(b["gas"]["mass"]), len(b["dm"]["mass"]), dev) for b in bx]
+    ng = sum(len(b["gas"]["mass"]) for b in bx)
+    nd = sum(len(b["dm"]["mass"]) for b in bx)
+    del bx
+    log_fn(f"bench: batch of 64 boxes generated in {time.time() - t0:.1f} s: {ng} gas, {nd} DM")
+    ctx = dmb.Context(0)
+    try:
+        t1 = time.time()
+        choice = ctx.batch_tune(G, D, P, O, precision=dmb.DMB_FP32)
+        t2 = time.time()
+        log_fn(f"bench: batch autotune {t2 - t1:.1f} s -> {choice}")
+        ctx.batch_step(G, D, P, O, precision=dmb.DMB_FP32, nsteps=1, graph=True)   # warm-up replay
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        ctx.batch_step(G, D, P, O, precision=dmb.DMB_FP32, nsteps=steps, graph=True)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        pairs = sum(dmb.counters_dict(o["counters"])["pairs_gas"] for o in O)
+        scat = sum(dmb.counters_dict(o["counters"])["scatters"] for o in O)
+        ms = (tb - ta) * 1e3 / steps
+        log_fn(f"bench: batch {steps} graph replays: {ms:.3f} ms per step, {pairs} pairs per step")
+        return {"workload": "64 periodic boxes, 1e4..5e5 particles per species each, sigma0 1e-28..1e-24 cm^2, "
+                            "m_chi/m_p in {0.5,1,2,5}", "n_gas": ng, "n_dm": nd, "pairs_per_step": pairs,
+                "scatters_per_step": scat, "ms_per_step": ms, "pairs_per_s": pairs / (ms * 1e-3),
+                "graph_replays": steps, "tuned": choice, "tune_s": round(t2 - t1, 2),
+                "pair_math": "binary32", "accumulation": "binary64"}
+    finally:
+        ctx.close()
+
+
 def traffic_from_profile(kernel: str):
     """HBM bytes per launch measured with rocprofv3 PMC runs, if they were
     taken for the current kernel sources; else None."""
@@ -182,11 +245,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="galaxy", choices=["galaxy", "box"])
+    ap.add_argument("--workload", default="galaxy", choices=["galaxy", "box", "milky_way", "batch"])
+    ap.add_argument("--rates", default="exact", choices=["exact", "quad", "mlp"],
+                    help="rate integrals: closed forms, quadrature (--quad-nodes) or the trained network")
+    ap.add_argument("--quad-nodes", type=int, default=12)
+    ap.add_argument("--n-pow", type=int, default=0, choices=[-4, -2, 0, 2])
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the workload's particle counts")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-box batched sweep")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the network-vs-quadrature comparison (sigma ~ v^n on the galaxy workload)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -200,16 +268,31 @@ def main():
     import torch
     import paper_2603_24688_amd as dmb
 
+    dev = torch.device("cuda:0")
+    if args.workload == "batch":
+        b = batch_sweep(dev, args.steps, log)
+        line = {"metric": "DM-gas pair interactions/sec per step", "value": b["pairs_per_s"],
+                "unit": "pair interactions/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+                "ms_per_step": b["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f32", "data": "synthetic", "config": b}
+        print(json.dumps(line), flush=True)
+        return
     t0 = time.time()
-    cfg, desc = make_workload(args.workload, args.scale, args.seed)
+    cfg, desc = make_workload(args.workload, args.scale, args.seed, args.n_pow)
     log(f"bench: workload generated in {time.time() - t0:.1f} s: {desc['n_gas']} gas, {desc['n_dm']} DM")
     precision = dmb.DMB_FP32 if desc["pair_math"] == "binary32" else dmb.DMB_FP64
-    dev = torch.device("cuda:0")
     G = dmb.to_device(cfg["gas"], dev)
     D = dmb.to_device(cfg["dm"], dev)
     out = dmb.alloc_out(desc["n_gas"], desc["n_dm"], dev)
     ctx = dmb.Context(0)
     par = dict(cfg["params"])
+    rates = {"exact": dmb.DMB_RATES_EXACT, "quad": dmb.DMB_RATES_QUAD, "mlp": dmb.DMB_RATES_MLP}[args.rates]
+    par["rates"], par["quad_nodes"] = rates, args.quad_nodes
+    desc["rates"] = args.rates if args.rates != "quad" else f"quad{args.quad_nodes}"
+    if args.rates == "mlp":
+        precision = dmb.DMB_FP32
+        desc["pair_math"] = "binary32"
+        desc["network"] = train_network(ctx, dev, log)
 
     def one_step(s):
         par["step"] = s
@@ -251,9 +334,9 @@ def main():
     dom = "pass_dm" if per_kernel["pass_dm"] >= per_kernel["pass_gas"] else "pass_gas"
     t_dom = per_kernel[dom] * 1e-3
     units = cnt["pairs_dm"] if dom == "pass_dm" else cnt["pairs_gas"]
-    ops = units * PAIR_BODY_VALU[dom] if precision == dmb.DMB_FP32 else None
-    if ops is not None:
-        achieved = ops / t_dom / 1e9
+    counted = precision == dmb.DMB_FP32 and args.n_pow == 0 and (dom == "pass_dm" or args.rates == "exact")
+    if counted:
+        achieved = units * PAIR_BODY_VALU[dom] / t_dom / 1e9
         roof = {"bound": "alu", "kernel": "k_pass_dm" if dom == "pass_dm" else "k_pass_gas",
                 "achieved": achieved, "peak": VALU_PEAK_GOPS, "unit": "Gop/s (VALU lane-instructions)",
                 "frac": achieved / VALU_PEAK_GOPS, "traffic": traffic_from_profile(dom),
@@ -261,7 +344,8 @@ def main():
                 "ops_per_pair": PAIR_BODY_VALU[dom], "pairs_per_launch": units}
     else:
         roof = {"bound": "alu", "kernel": dom, "achieved": None, "peak": VALU_PEAK_GOPS, "unit": "Gop/s",
-                "frac": None, "traffic": None, "kernel_ms": per_kernel[dom]}
+                "frac": None, "traffic": None, "kernel_ms": per_kernel[dom],
+                "note": "instruction counts are taken for binary32 closed-form rates with n = 0"}
     # algorithmic HBM bytes of the step: each particle read once (sorted copies),
     # outputs written once (see the design doc for the per-particle byte counts)
     bytes_step = desc["n_gas"] * (40 + 32) + desc["n_dm"] * (32 + 36)
@@ -279,8 +363,11 @@ def main():
         "hit_fraction": {"gas": pairs / max(1, bst["cand_pairs_gas"] * 4096),
                          "dm": pairs / max(1, bst["cand_pairs_dm"] * 4096)},
     }
-    if args.workload == "galaxy" and not args.no_surrogate:
+    default_run = args.workload == "galaxy" and args.rates == "exact" and args.n_pow == 0
+    if default_run and not args.no_surrogate:
         line["surrogate"] = surrogate_compare(ctx, cfg, dev, 3, log)
+    if default_run and not args.no_batch:
+        line["batch"] = batch_sweep(dev, 10, log)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)

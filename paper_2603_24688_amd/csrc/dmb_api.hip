@@ -176,19 +176,21 @@ struct Phase {
 
 inline unsigned blocks_for(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
 
-// Exclusive scan of n u32 values in place into out (out may equal in).
-dmb_status scan_excl(dmb_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, int level = 0)
+// Exclusive scan of n values (TI in, TO out and partial sums) into out (out
+// may equal in when the types agree).
+template <typename TI = uint32_t, typename TO = uint32_t>
+dmb_status scan_excl(dmb_ctx* c, const TI* in, TO* out, int64_t n, int level = 0)
 {
     if (n <= 0) return DMB_OK;
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (level >= 4) return fail(c, DMB_EINVAL, "scan too large");
-    ENSURE(c, c->scan_tmp[level], size_t(nb + 1) * sizeof(uint32_t));
-    uint32_t* sums = c->scan_tmp[level].as<uint32_t>();
-    hipLaunchKernelGGL(k_scan_block, dim3(unsigned(nb)), dim3(kScanBlock), 0, c->stream, in, out, sums, n);
+    ENSURE(c, c->scan_tmp[level], size_t(nb + 1) * sizeof(TO));
+    TO* sums = c->scan_tmp[level].as<TO>();
+    hipLaunchKernelGGL((k_scan_block<TI, TO>), dim3(unsigned(nb)), dim3(kScanBlock), 0, c->stream, in, out, sums, n);
     if (nb > 1) {
-        dmb_status s = scan_excl(c, sums, sums, nb, level + 1);
+        dmb_status s = scan_excl<TO, TO>(c, sums, sums, nb, level + 1);
         if (s != DMB_OK) return s;
-        hipLaunchKernelGGL(k_scan_add, dim3(unsigned(nb)), dim3(kScanBlock), 0, c->stream, out, sums, n);
+        hipLaunchKernelGGL(k_scan_add<TO>, dim3(unsigned(nb)), dim3(kScanBlock), 0, c->stream, out, sums, n);
     }
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
@@ -330,24 +332,25 @@ CandArgs cand_args(dmb_ctx* c, Species& A, Species& B, Pairs& P)
     a.tbox = B.tbox.as<const double>(); a.th = B.th.as<const double>();
     a.sbox = B.sbox.as<const double>(); a.shh = B.shh.as<const double>();
     for (int k = 0; k < 3; ++k) a.L[k] = c->X->built_L[k];
-    a.cnt = P.cnt.as<uint32_t>(); a.off = P.off.as<const uint32_t>(); a.cand = P.cand.as<uint32_t>();
+    a.cnt = P.cnt.as<uint32_t>(); a.off = P.off.as<const uint64_t>(); a.cand = P.cand.as<uint32_t>();
     return a;
 }
 
 dmb_status cand_count(dmb_ctx* c, Species& A, Species& B, Pairs& P)
 {
     int64_t nt = A.nown_tile;
-    ENSURE(c, P.cnt, (nt + 1) * 4); ENSURE(c, P.off, (nt + 1) * 4);
+    ENSURE(c, P.cnt, (nt + 1) * 4); ENSURE(c, P.off, (nt + 1) * 8);
     ENSURE(c, P.icnt, (nt + 1) * 4); ENSURE(c, P.ioff, (nt + 1) * 4);
     if (nt == 0 || B.ntile == 0) {
-        HIPCHK(c, hipMemsetAsync(P.off.p, 0, (nt + 1) * 4, c->stream));
+        HIPCHK(c, hipMemsetAsync(P.off.p, 0, (nt + 1) * 8, c->stream));
         HIPCHK(c, hipMemsetAsync(P.ioff.p, 0, (nt + 1) * 4, c->stream));
         return DMB_OK;
     }
     CandArgs a = cand_args(c, A, B, P);
     hipLaunchKernelGGL(k_cand<false>, dim3(unsigned(nt)), dim3(64), 0, c->stream, a);
     HIPCHK(c, hipMemsetAsync(P.cnt.as<uint32_t>() + nt, 0, 4, c->stream));
-    dmb_status s = scan_excl(c, P.cnt.as<const uint32_t>(), P.off.as<uint32_t>(), nt + 1);
+    // candidate offsets in 64 bits (totals pass 2^32 at Milky-Way sizes)
+    dmb_status s = scan_excl<uint32_t, uint64_t>(c, P.cnt.as<const uint32_t>(), P.off.as<uint64_t>(), nt + 1);
     if (s != DMB_OK) return s;
     hipLaunchKernelGGL(k_item_count, dim3(blocks_for(nt + 1, 256)), dim3(256), 0, c->stream,
                        P.cnt.as<const uint32_t>(), nt, uint32_t(c->split), P.icnt.as<uint32_t>());
@@ -362,14 +365,14 @@ dmb_status cand_write(dmb_ctx* c, Species& A, Species& B, Pairs& P)
     int64_t nt = A.nown_tile;
     ENSURE(c, P.cand, std::max<int64_t>(P.total, 1) * 4);
     ENSURE(c, P.it_tile, std::max<int64_t>(P.nitems, 1) * 4);
-    ENSURE(c, P.it_cb, std::max<int64_t>(P.nitems, 1) * 4);
-    ENSURE(c, P.it_ce, std::max<int64_t>(P.nitems, 1) * 4);
+    ENSURE(c, P.it_cb, std::max<int64_t>(P.nitems, 1) * 8);
+    ENSURE(c, P.it_ce, std::max<int64_t>(P.nitems, 1) * 8);
     if (nt == 0 || B.ntile == 0 || P.total == 0) return DMB_OK;
     CandArgs a = cand_args(c, A, B, P);
     hipLaunchKernelGGL(k_cand<true>, dim3(unsigned(nt)), dim3(64), 0, c->stream, a);
-    hipLaunchKernelGGL(k_item_write, dim3(blocks_for(nt, 256)), dim3(256), 0, c->stream, P.off.as<const uint32_t>(),
+    hipLaunchKernelGGL(k_item_write, dim3(blocks_for(nt, 256)), dim3(256), 0, c->stream, P.off.as<const uint64_t>(),
                        P.ioff.as<const uint32_t>(), nt, uint32_t(c->split), P.it_tile.as<uint32_t>(),
-                       P.it_cb.as<uint32_t>(), P.it_ce.as<uint32_t>());
+                       P.it_cb.as<uint64_t>(), P.it_ce.as<uint64_t>());
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
 }
@@ -438,8 +441,8 @@ PassGeom geom(Cells& X, Species& A, Species& B, Pairs& P, uint64_t* counters)
     g.sub_start = B.sub_start.as<const uint32_t>(); g.sub_cnt = B.sub_cnt.as<const uint32_t>();
     g.cand = P.cand.as<const uint32_t>();
     g.item_off = P.ioff.as<const uint32_t>();
-    g.it_tile = P.it_tile.as<const uint32_t>(); g.it_cb = P.it_cb.as<const uint32_t>();
-    g.it_ce = P.it_ce.as<const uint32_t>(); g.n_items = P.nitems;
+    g.it_tile = P.it_tile.as<const uint32_t>(); g.it_cb = P.it_cb.as<const uint64_t>();
+    g.it_ce = P.it_ce.as<const uint64_t>(); g.n_items = P.nitems;
     g.queue_ctr = X.qctr.as<uint32_t>();
     for (int k = 0; k < 3; ++k) g.L[k] = X.built_L[k];
     g.counters = counters;
@@ -599,7 +602,7 @@ void combine_dm_and_resolve(dmb_ctx* c, Cells& X, const DmPassArgs& a, const dmb
     }
     ResolveArgs r;
     r.g = a.g;
-    r.cand_off = X.dp.off.as<const uint32_t>();
+    r.cand_off = X.dp.off.as<const uint64_t>();
     r.vx = a.vx; r.vy = a.vy; r.vz = a.vz; r.dtr = a.dtr; r.dm_perm = a.dm_perm;
     r.Vx = a.Vx; r.Vy = a.Vy; r.Vz = a.Vz; r.vs = a.vs; r.K = a.K; r.gas_perm = a.gas_perm;
     r.gas_vel = gas->vel; r.gas_u = gas->u; r.gas_mu = gas->mu; r.m_chi = par->m_chi_g;
@@ -1150,14 +1153,14 @@ dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_part
     if ((s = build_owner_tiles(c, c->X->dm)) != DMB_OK) return s;
     if ((s = cand_count(c, c->X->gas, c->X->dm, c->X->gp)) != DMB_OK) return s;
     if ((s = cand_count(c, c->X->dm, c->X->gas, c->X->dp)) != DMB_OK) return s;
-    uint32_t tot[4] = {0, 0, 0, 0};
+    uint64_t tot[4] = {0, 0, 0, 0};
     double hmax[2] = {0, 0};
     if (c->X->gas.nown_tile > 0) {
-        HIPCHK(c, hipMemcpyAsync(&tot[0], c->X->gp.off.as<uint32_t>() + c->X->gas.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(&tot[0], c->X->gp.off.as<uint64_t>() + c->X->gas.nown_tile, 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipMemcpyAsync(&tot[1], c->X->gp.ioff.as<uint32_t>() + c->X->gas.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
     }
     if (c->X->dm.nown_tile > 0) {
-        HIPCHK(c, hipMemcpyAsync(&tot[2], c->X->dp.off.as<uint32_t>() + c->X->dm.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(&tot[2], c->X->dp.off.as<uint64_t>() + c->X->dm.nown_tile, 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipMemcpyAsync(&tot[3], c->X->dp.ioff.as<uint32_t>() + c->X->dm.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
     }
     if (periodic) {

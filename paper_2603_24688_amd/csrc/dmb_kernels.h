@@ -338,7 +338,7 @@ struct CandArgs {
     const double* mbox; const double* mhh;
     double L[3];
     uint32_t* cnt;
-    const uint32_t* off;
+    const uint64_t* off;          // candidate offsets can pass 2^32 at Milky-Way sizes
     uint32_t* cand;
 };
 
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(64) void k_cand(CandArgs a)
     for (int k = 0; k < 6; ++k) A[k] = a.obox[6 * t + k];
     const double ha = a.oh[t];
     uint32_t count = 0;
-    const uint32_t base = WRITE ? a.off[t] : 0u;
+    const uint64_t base = WRITE ? a.off[t] : 0ull;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     for (int64_t m0 = 0; m0 < a.nmega; m0 += 64) {
         const int64_t mg = m0 + lane;
@@ -386,19 +386,19 @@ __global__ __launch_bounds__(256) void k_item_count(const uint32_t* __restrict__
     icnt[t] = t < nt ? (cnt[t] + split - 1) / split : 0u;
 }
 
-__global__ __launch_bounds__(256) void k_item_write(const uint32_t* __restrict__ cand_off,
+__global__ __launch_bounds__(256) void k_item_write(const uint64_t* __restrict__ cand_off,
                                                     const uint32_t* __restrict__ item_off, int64_t nt, uint32_t split,
-                                                    uint32_t* __restrict__ it_tile, uint32_t* __restrict__ it_cb,
-                                                    uint32_t* __restrict__ it_ce)
+                                                    uint32_t* __restrict__ it_tile, uint64_t* __restrict__ it_cb,
+                                                    uint64_t* __restrict__ it_ce)
 {
     int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= nt) return;
-    uint32_t cb = cand_off[t], ce = cand_off[t + 1];
+    const uint64_t cb = cand_off[t], ce = cand_off[t + 1];
     uint32_t it = item_off[t];
-    for (uint32_t c = cb; c < ce; c += split, ++it) {
+    for (uint64_t c = cb; c < ce; c += split, ++it) {
         it_tile[it] = uint32_t(t);
         it_cb[it] = c;
-        it_ce[it] = min(ce, c + split);
+        it_ce[it] = min(ce, c + uint64_t(split));
     }
 }
 
@@ -521,7 +521,7 @@ struct PassGeom {
     const double* tbox;           // other sub-tile boxes
     const uint32_t* sub_start; const uint32_t* sub_cnt;                       // other sub-tiles
     const uint32_t* cand;         // candidate other sub-tiles
-    const uint32_t* it_tile; const uint32_t* it_cb; const uint32_t* it_ce;
+    const uint32_t* it_tile; const uint64_t* it_cb; const uint64_t* it_ce;
     const uint32_t* item_off;     // [owner tiles + 1] item ranges per owner tile
     int64_t n_items;
     uint32_t* queue_ctr;          // [kXcd] work counters
@@ -643,7 +643,7 @@ struct GroupLds {
 // hit layout.  Returns the group's hit count (wave-uniform).
 template <int W = 1>
 __device__ __forceinline__ int group_test(GroupLds& S, const PassGeom& G, const double* A, const double cen[3],
-                                          uint32_t c, int ng, bool ov, float fx, float fy, float fz, float fh,
+                                          uint64_t c, int ng, bool ov, float fx, float fy, float fz, float fh,
                                           const float Lf[3])
 {
     const int lane = lane_id();
@@ -832,7 +832,7 @@ __global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kR
         const Real* dm_m = reinterpret_cast<const Real*>(a.dm_m);
         const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
         const int64_t t = G.it_tile[it];
-        const uint32_t cb = G.it_cb[it], ce = G.it_ce[it];
+        const uint64_t cb = G.it_cb[it], ce = G.it_ce[it];
         const int64_t slot = t * kTile + lane;
         const bool ov = slot < G.n_own;
         const int64_t sp = ov ? int64_t(G.own[slot]) : 0;
@@ -850,8 +850,8 @@ __global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kR
         const double cen[3] = {0.5 * (A[0] + A[3]), 0.5 * (A[1] + A[4]), 0.5 * (A[2] + A[5])};
         const float fx = float(mx - cen[0]), fy = float(my - cen[1]), fz = float(mz - cen[2]), fh = float(mh);
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-        for (uint32_t c = cb; c < ce; c += kGroup) {
-            const int ng = int(min<uint32_t>(kGroup, ce - c));
+        for (uint64_t c = cb; c < ce; c += kGroup) {
+            const int ng = int(min<uint64_t>(kGroup, ce - c));
             const int H = group_test<W>(S, G, A, cen, c, ng, ov, fx, fy, fz, fh, Lf);
             const int my_lo = S.offs[lane], my_hi = S.offs[lane + 1];
             for (int base = 0; base < H; base += 64) {
@@ -1111,7 +1111,7 @@ __global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a0, const DmPassAr
         const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
         const uint32_t step = a.step + (a.step_off ? *a.step_off : 0u);
         const int64_t t = G.it_tile[it];
-        const uint32_t cb = G.it_cb[it], ce = G.it_ce[it];
+        const uint64_t cb = G.it_cb[it], ce = G.it_ce[it];
         const int64_t slot = t * kTile + lane;
         const bool ov = slot < G.n_own;
         const int64_t sp = ov ? int64_t(G.own[slot]) : 0;
@@ -1129,8 +1129,8 @@ __global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a0, const DmPassAr
         double accP = 0.0;
         Real accM = 0;
         int accNB = 0;
-        for (uint32_t c = cb; c < ce; c += kGroup) {
-            const int ng = int(min<uint32_t>(kGroup, ce - c));
+        for (uint64_t c = cb; c < ce; c += kGroup) {
+            const int ng = int(min<uint64_t>(kGroup, ce - c));
             const int H = group_test(S, G, A, cen, c, ng, ov, fx, fy, fz, fh, Lf);
             const int my_lo = S.offs[lane], my_hi = S.offs[lane + 1];
             for (int base = 0; base < H; base += 64) {
@@ -1279,7 +1279,7 @@ __global__ __launch_bounds__(256) void k_combine_dm(DmCombineArgs a)
 // with more pairs than the cache recompute their pairs in every pass.
 struct ResolveArgs {
     PassGeom g;                   // owners = DM, others = gas sub-tiles (as in the DM pass)
-    const uint32_t* cand_off;     // [nown_tile + 1]
+    const uint64_t* cand_off;     // [nown_tile + 1]
     const double* vx; const double* vy; const double* vz; const void* dtr; const uint32_t* dm_perm;
     const double* Vx; const double* Vy; const double* Vz; const void* vs; const void* K; const uint32_t* gas_perm;
     const double* gas_vel; const double* gas_u; const double* gas_mu;   // raw gas inputs (partner kick)
@@ -1338,28 +1338,28 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
         const unsigned __int128 Ufix = (unsigned __int128)(2ull * (rd.x >> 8) + 1ull) << 39;
         double A[6];
         for (int k = 0; k < 6; ++k) A[k] = G.obox[6 * t + k];
-        const uint32_t cb = a.cand_off[t], ce = a.cand_off[t + 1];
+        const uint64_t cb = a.cand_off[t], ce = a.cand_off[t + 1];
         if (tid == 0) { s_nrel = 0; s_npairs = 0; }
         __syncthreads();
         // candidate sub-tiles this DM can reach (point-to-box gap < h_i + h_max)
         const double P6[6] = {mx, my, mz, mx, my, mz};
-        for (uint32_t c = cb + tid; c < ce; c += kResolveThreads) {
+        for (uint64_t c = cb + tid; c < ce; c += kResolveThreads) {
             const uint32_t ot = G.cand[c];
             if (boxes_near(P6, mh, G.tbox + 6 * int64_t(ot), G.th[ot], G.L)) {
                 const uint32_t pos = atomicAdd(&s_nrel, 1u);
-                if (pos < uint32_t(kResolveList)) s_list[pos] = c;
+                if (pos < uint32_t(kResolveList)) s_list[pos] = uint32_t(c - cb);   // offset in the tile's list
             }
         }
         __syncthreads();
         const uint32_t nrel = s_nrel;
         const bool use_list = nrel <= uint32_t(kResolveList);
-        const uint32_t nl = use_list ? nrel : ce - cb;
+        const uint32_t nl = use_list ? nrel : uint32_t(ce - cb);
         // prefix sums of particle counts over the kept sub-tiles (one thread; nl <= kResolveList)
         if (tid == 0 && use_list) {
             uint32_t acc = 0;
             for (uint32_t q = 0; q < nl; ++q) {
                 s_pre[q] = acc;
-                acc += G.sub_cnt[G.cand[s_list[q]]];
+                acc += G.sub_cnt[G.cand[cb + s_list[q]]];
             }
             s_pre[nl] = acc;
         }
@@ -1368,8 +1368,8 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
         // sub-tiles (four wavefronts in parallel).  Without a list (too many
         // candidates) every candidate sub-tile is walked by one wavefront.
         auto for_pairs = [&](auto&& fn) {
-            auto visit = [&](uint32_t c, int kk) {
-                const uint32_t ot = G.cand[c];
+            auto visit = [&](uint32_t lc, int kk) {
+                const uint32_t ot = G.cand[cb + lc];
                 double sh[3];
                 bool clean;
                 tile_pair_shift(A, G.tbox + 6 * int64_t(ot), G.L, sh, &clean);
@@ -1400,7 +1400,7 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
                 }
             } else {
                 const int w = tid >> 6, lane = tid & 63;
-                for (uint32_t q = w; q < nl; q += kResolveThreads / 64) visit(cb + q, lane);
+                for (uint32_t q = w; q < nl; q += kResolveThreads / 64) visit(q, lane);
             }
         };
         for_pairs([&](uint32_t gid, double P) {

@@ -45,6 +45,24 @@ def mean_field_peak_error(gpu, ref, gas_sel=None):
     return float(np.max(e, initial=0.0))
 
 
+def mean_field_errors(gpu, ref, gas_sel=None):
+    """Per gas owner: (condition-aware error, peak-scaled error), each the
+    larger over the momentum components and the energy (see the two
+    functions above)."""
+    sel = slice(None) if gas_sel is None else gas_sel
+    dp_err = np.abs(gpu["dp_gas"][sel] - ref["dp_gas"][sel])                 # [n, 3]
+    de_err = np.abs(gpu["de_gas"][sel] - ref["de_gas"][sel])
+    dp_scale = np.maximum(np.abs(ref["dp_gas"][sel]), ref["dp_abs"][sel])    # per component
+    de_scale = np.maximum(np.abs(ref["de_gas"][sel]), ref["de_abs"][sel])
+    with np.errstate(invalid="ignore", divide="ignore"):
+        cond = np.maximum(np.where(dp_scale > 0, dp_err / dp_scale, dp_err).max(axis=1),
+                          np.where(de_scale > 0, de_err / de_scale, de_err))
+        worst = np.maximum(dp_err.max(axis=1), de_err)
+        pk = ref["pk_abs"][sel]
+        peak = np.where(pk > 0, worst / pk, worst)
+    return cond, peak
+
+
 def decision_report(gpu, ref, dm_sel=None):
     """Partner choices on DM not flagged near-threshold by the oracle."""
     sel = np.arange(len(ref["partner"])) if dm_sel is None else np.asarray(dm_sel)

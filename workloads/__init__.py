@@ -268,3 +268,21 @@ def mlp_params(seed=(4, 9), scale: float = 1.0) -> np.ndarray:
         else:
             out.append(r.uniform(-0.1, 0.1, s))
     return np.concatenate(out).astype(np.float32)
+
+
+# --------------------------------------------------------------------------- Milky-Way-scale step
+def milky_way(n_gas=8_000_000, n_dm=32_000_000, seed=(3, 1), active_frac=0.1, step=0, decades=3.0,
+              dt_myr=0.1, n_pow=0, sigma0_cm2=1e-24) -> dict:
+    """Disk + halo with the galaxy profiles at Milky-Way particle counts, for
+    one step of a hierarchical-timestep run: h spread log-uniformly over
+    `decades` decades per species (rank-matched to the density estimate,
+    top-anchored at its maximum) and an independent `active_frac` of each
+    species active (drawn per step)."""
+    cfg = galaxy(n_gas=n_gas, n_dm=n_dm, n_ngb=64, seed=seed, sigma0_cm2=sigma0_cm2, n_pow=n_pow, dt_myr=dt_myr)
+    for sp in ("gas", "dm"):
+        cfg[sp]["h"] = spread_h_log(cfg[sp]["h"], decades)
+    r = rng(seed[0], seed[1], 100 + int(step))
+    cfg["gas"]["active"] = (r.random(n_gas) < active_frac).astype(np.uint8)
+    cfg["dm"]["active"] = (r.random(n_dm) < active_frac).astype(np.uint8)
+    cfg["params"]["step"] = int(step)
+    return cfg
