@@ -438,3 +438,43 @@ def test_step_outputs_structure(orc):
     assert np.all(np.isfinite(res["dp_gas"])) and np.all(np.isfinite(res["de_gas"]))
     none = res["partner"] < 0
     assert np.all(res["dv_dm"][none] == 0.0)
+
+
+# --------------------------------------------------------------------------- two-population relaxation
+@pytest.mark.parametrize("n", [-2, 0, 2])
+def test_relaxation_rhs_is_the_maxwellian_average(orc, n):
+    """The relaxation rates of oracle/relax.py equal the average, over a
+    Maxwellian DM population, of the per-pair mean-field terms of eq.
+    gas-dVdt / gas-dTdt (rates at the gas dispersion, relative velocity
+    w = v - V_B), and conserve momentum and total energy."""
+    from oracle import relax
+    rho_b, rho_x, sig, m_x, mu = 1e10, 2e10, 1e-24 * (299792.458 / 200.0) ** n, 2 * 1.67262192369e-24, 1.67262192369e-24
+    VX, VB, sx, sb = 50.0, 3.0, 20.0, 9.0
+    d = relax.rhs([VX, VB, sx * sx, sb * sb], rho_b, rho_x, sig, n, m_x, mu)
+    k = relax.coupling(sig, n, m_x, mu)
+
+    def fp(vx, vp):
+        A, _ = orc.rates(n, math.hypot(vx - VB, vp), sb)
+        return A * (vx - VB)
+
+    def fe(vx, vp):
+        w = math.hypot(vx - VB, vp)
+        A, B = orc.rates(n, w, sb)
+        return w * w * A - mu / (m_x + mu) * B
+    dVB = k * rho_x * _gauss_expect(fp, VX, sx)
+    duB = k * rho_x * _gauss_expect(fe, VX, sx)
+    assert d[1] == pytest.approx(dVB, rel=1e-9)
+    assert 1.5 * d[3] == pytest.approx(duB, rel=1e-9)
+    # conservation of momentum and of internal + bulk kinetic energy per volume
+    assert abs(rho_x * d[0] + rho_b * d[1]) <= 1e-12 * rho_b * abs(d[1])
+    dE = rho_x * (1.5 * d[2] + VX * d[0]) + rho_b * (1.5 * d[3] + VB * d[1])
+    assert abs(dE) <= 1e-10 * rho_b * abs(1.5 * d[3])
+
+
+def test_relaxation_equilibrium_is_stationary(orc):
+    from oracle import relax
+    m_x, mu = 2 * 1.67262192369e-24, 1.67262192369e-24
+    sb2 = 80.0
+    sx2 = sb2 * mu / m_x          # equal temperatures, no drift
+    d = relax.rhs([7.0, 7.0, sx2, sb2], 1e10, 1e10, 1e-24, 0, m_x, mu)
+    assert np.max(np.abs(d)) < 1e-12 * sb2
