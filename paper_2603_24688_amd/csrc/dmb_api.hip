@@ -438,6 +438,7 @@ PassGeom geom(Cells& X, Species& A, Species& B, Pairs& P, uint64_t* counters)
     g.oh = A.sh.as<const double>(); g.obox = A.obox.as<const double>();
     g.tx = B.sx.as<const double>(); g.ty = B.sy.as<const double>(); g.tz = B.sz.as<const double>();
     g.th = B.sh.as<const double>(); g.n_other = B.n; g.tbox = B.tbox.as<const double>();
+    g.thmax = B.th.as<const double>();
     g.sub_start = B.sub_start.as<const uint32_t>(); g.sub_cnt = B.sub_cnt.as<const uint32_t>();
     g.cand = P.cand.as<const uint32_t>();
     g.item_off = P.ioff.as<const uint32_t>();

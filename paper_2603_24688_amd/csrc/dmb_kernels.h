@@ -493,22 +493,24 @@ __global__ __launch_bounds__(256) void k_fill_out(int64_t n_gas, int64_t n_dm, d
 
 // ---------------------------------------------------------------------------
 // Pair passes.  One wavefront per block owns a tile of 64 owners (lane =
-// owner) and walks its candidate sub-tiles of the other species in groups of
-// kGroup.  Test phase: the group's positions and h are staged in LDS as
-// binary32 offsets from the owner tile's centre, and every owner lane tests
-// them with a conservative binary32 test (margin kTestMargin), building one
-// 64-bit hit mask per sub-tile.  Evaluate phase: the group's hits, ordered
-// owner-major, are decoded 64 at a time (lane = pair); each lane repeats the
-// test exactly in binary64, evaluates the pair and the owner's terms form a
-// contiguous run of lanes, so a segmented suffix sum over lanes (wavefront
-// shuffles) leaves each run's total on its first lane, which the owner lane
-// pulls.  No atomics touch physical quantities.
-constexpr int kGroup = 4;
+// owner) and walks its candidate sub-tiles of the other species in chunks of
+// up to 64.  Test phase: each owner is checked against every sub-tile box of
+// the chunk; the sub-tiles some owner reaches are packed into groups of at
+// most 64 particles ("slots"), and one group is tested against all 64 owners
+// at once as a dense binary32 product on the matrix cores (below), giving
+// one 64-bit hit mask over the slots per owner.  Evaluate phase: the group's
+// hits, ordered owner-major, are decoded 64 at a time (lane = pair); each
+// lane repeats the test exactly in binary64, evaluates the pair and the
+// owner's terms form a contiguous run of lanes, so a segmented suffix sum
+// over lanes (wavefront shuffles) leaves each run's total on its first lane,
+// which the owner lane pulls.  No atomics touch physical quantities.
 constexpr float kTestMargin = 1.0f + 4e-6f;
 // Slack of the expanded binary32 test |a-b|^2 - (ha+hb)^2 = A + B - 2 (a.b + ha hb)
-// with A = |a|^2 - ha^2, B = |b|^2 - hb^2: its rounding error is below
-// 8 eps32 (|a|^2 + ha^2 + |b|^2 + hb^2); subtracting kTestSlack times that sum
-// makes the test accept every pair that is inside in exact arithmetic.
+// with A = |a|^2 - ha^2, B = |b|^2 - hb^2, in offsets from the owner tile's
+// centre: evaluated as a six-term dot product (any summation order) its
+// rounding error stays below 20 eps32 (|a|^2 + ha^2 + |b|^2 + hb^2) ~ 1.2e-6 (...);
+// subtracting kTestSlack times that sum makes the test accept every pair that
+// is inside in exact arithmetic.
 constexpr float kTestSlack = 2e-6f;
 
 struct PassGeom {
@@ -519,6 +521,7 @@ struct PassGeom {
     const double* tx; const double* ty; const double* tz; const double* th;   // other sorted pos/h
     int64_t n_other;
     const double* tbox;           // other sub-tile boxes
+    const double* thmax;          // other sub-tile max h
     const uint32_t* sub_start; const uint32_t* sub_cnt;                       // other sub-tiles
     const uint32_t* cand;         // candidate other sub-tiles
     const uint32_t* it_tile; const uint64_t* it_cb; const uint64_t* it_ce;
@@ -627,103 +630,275 @@ __device__ __forceinline__ int select_bit(uint64_t m, int r)
     return base;
 }
 
-// LDS state of one group of candidate sub-tiles.
-struct GroupLds {
-    float4 t[kGroup][64];         // binary32 offsets from the owner-tile centre (x, y, z) and h
-    float tb[kGroup][64];         // |p|^2 - h^2 - kTestSlack (|p|^2 + h^2)
-    double sh[kGroup][3];         // periodic image shift of each sub-tile
-    int base[kGroup], cnt[kGroup], clean[kGroup];
-    uint64_t mask[64][kGroup];    // hit masks per owner lane
-    int pref[64][kGroup + 1];     // owner's running hit count before each sub-tile
+// Per-wave LDS of the test phase.
+struct TestLds {
+    float4 dlo[64];               // chunk sub-tiles: box lo (offsets from the owner-tile centre), max h
+    float4 dhi[64];               // box hi; w = 1 when every pair of the sub-tile is at its tile-level image
+    double dsh[64][3];            // periodic image shift of each chunk sub-tile
+    int dbase[64];                // first sorted index of each chunk sub-tile
+    int dpre[64], dincl[64];      // exclusive / inclusive slot prefix over the reached sub-tiles
+    int sj[64];                   // slot -> chunk sub-tile (prefix-max scratch)
+    double px[64], py[64], pz[64], ph[64];   // slot particles: shifted position and h
+    uint32_t pq[64];              // slot -> sorted index of the other particle
+    int pclean[64];               // slot's sub-tile is clean
+    float4 pf[64];                // slot offsets from the owner-tile centre and h (binary32)
+    uint64_t mask[64];            // per owner lane: hit mask over the group's slots
     int offs[65];                 // owner-major offsets of the group's hits
-    int ng;
 };
 
-// Stage up to kGroup candidate sub-tiles [c, c+ng) and build the owner-major
-// hit layout.  Returns the group's hit count (wave-uniform).
-template <int W = 1>
-__device__ __forceinline__ int group_test(GroupLds& S, const PassGeom& G, const double* A, const double cen[3],
-                                          uint64_t c, int ng, bool ov, float fx, float fy, float fz, float fh,
-                                          const float Lf[3])
+// Test-phase state of one wave (owner lane values and the chunk/group cursor).
+struct PairTest {
+    bool ov;
+    float fx, fy, fz, fh;         // owner offset from the tile centre and h (binary32)
+    uint64_t c0, ce;              // next chunk start, end of the item's candidate list
+    uint64_t actA, actB;          // chunk sub-tiles reached by some owner of lanes 0-31 / 32-63
+    int total, Ps;                // slots of the chunk, start of the next group
+};
+
+__device__ __forceinline__ int wave_incl_max(int v)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(v, d);
+        if (lane_id() >= d) v = v > y ? v : y;
+    }
+    return v;
+}
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Slot loaded by lane L.  In v_mfma_f32_32x32x2_f32 lane L supplies row L%32
+// of A for K index L/32, and receives column L%32, rows 8(r/4) + 4(L/32) + r%4
+// (r = 0..15) of D.  Rows of the slot tile st are slots
+// 32 st + 16 ((i/4)%2) + 4 (i/8) + i%4, so lane L loads the slot of row L%32
+// in tile L/32 and its 16 results of tile st are slots 32 st + 16 (L/32) + r.
+__device__ __forceinline__ int slot_of_lane(int L)
+{
+    const int i = L & 31;
+    return (L & 32) | (((i >> 2) & 1) << 4) | ((i >> 3) << 2) | (i & 3);
+}
+
+// e = A^T B over the three K steps; sign bits of the 16 results shifted into m
+// (first result ends in the lowest of the 16 new bits).
+__device__ __forceinline__ uint32_t mfma_signs(const float a[3], const float b[3], uint32_t m)
+{
+    f32x16 d = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    d = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], b[0], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], b[1], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2], b[2], d, 0, 0, 0);
+#pragma unroll
+    for (int r = 15; r >= 0; --r) m = __builtin_amdgcn_alignbit(m, __float_as_uint(d[r]), 31);
+    __builtin_amdgcn_sched_barrier(0);    // one 16-register accumulator live at a time
+    return m;
+}
+
+// Operands of the product for K components (2 step + half) of two 32-lane
+// halves: `own` is this lane's component set, the other half's arrives from
+// the partner lane L^32.  out[t][step] = operand for tile t.
+__device__ __forceinline__ void half_operands(const float c[6], float out[2][3])
+{
+    const bool h = lane_id() >= 32;
+#pragma unroll
+    for (int step = 0; step < 3; ++step) {
+        const float mine = h ? c[2 * step + 1] : c[2 * step];
+        const float send = h ? c[2 * step] : c[2 * step + 1];
+        const float recv = __shfl_xor(send, 32);
+        out[0][step] = h ? recv : mine;
+        out[1][step] = h ? mine : recv;
+    }
+}
+
+__device__ __forceinline__ void test_begin(PairTest& T, bool ov, float fx, float fy, float fz, float fh, uint64_t cb,
+                                           uint64_t ce)
+{
+    T.ov = ov; T.fx = fx; T.fy = fy; T.fz = fz; T.fh = fh;
+    T.c0 = cb; T.ce = ce;
+    T.actA = T.actB = 0ull;
+    T.total = 0; T.Ps = 0;
+}
+
+// Next chunk of up to 64 candidate sub-tiles: descriptors to LDS (lane = sub-tile),
+// per-owner reach check against each box, slot prefix over the reached ones.
+// Every owner/sub-tile pair the per-pair test can accept passes the reach check:
+// each candidate offset q lies in the binary32 box [lo, hi] (same rounding,
+// monotone), so gap <= |p - q|, and an accepted pair has
+// gap^2 < (fh + hb)^2 + (kTestSlack + 20 eps32) (|p|^2 + fh^2 + Q2 + hb^2), Q2 >= |q|^2.
+template <int W>
+__device__ __forceinline__ void test_chunk(PairTest& T, TestLds& S, const PassGeom& G, const double* A,
+                                           const double cen[3])
 {
     const int lane = lane_id();
-    stage_sync<W>();
-    for (int g = 0; g < ng; ++g) {
-        const uint32_t ot = G.cand[c + g];
-        const int base = int(G.sub_start[ot]), cnt = int(G.sub_cnt[ot]);
+    const int nch = int(min<uint64_t>(64, T.ce - T.c0));
+    stage_sync<W>();    // the previous chunk's groups are done with the descriptors
+    int cnt = 0;
+    if (lane < nch) {
+        const uint32_t ot = G.cand[T.c0 + lane];
+        const double* B = G.tbox + 6 * int64_t(ot);
+        double Bx[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Bx[k] = B[k];
         double sh[3];
         bool clean;
-        tile_pair_shift(A, G.tbox + 6 * int64_t(ot), G.L, sh, &clean);
-        if (lane < cnt) {
-            const int64_t k = int64_t(base) + lane;
-            const float4 q = make_float4(float(G.tx[k] + sh[0] - cen[0]), float(G.ty[k] + sh[1] - cen[1]),
-                                         float(G.tz[k] + sh[2] - cen[2]), float(G.th[k]));
-            const float p2 = q.x * q.x + q.y * q.y + q.z * q.z, h2 = q.w * q.w;
-            S.t[g][lane] = q;
-            S.tb[g][lane] = (p2 - h2) - kTestSlack * (p2 + h2);
-        }
-        if (lane == 0) {
-            S.base[g] = base; S.cnt[g] = cnt; S.clean[g] = clean ? 1 : 0;
-            S.sh[g][0] = sh[0]; S.sh[g][1] = sh[1]; S.sh[g][2] = sh[2];
-        }
+        tile_pair_shift(A, Bx, G.L, sh, &clean);
+        S.dlo[lane] = make_float4(float(Bx[0] + sh[0] - cen[0]), float(Bx[1] + sh[1] - cen[1]),
+                                  float(Bx[2] + sh[2] - cen[2]), float(G.thmax[ot]));
+        S.dhi[lane] = make_float4(float(Bx[3] + sh[0] - cen[0]), float(Bx[4] + sh[1] - cen[1]),
+                                  float(Bx[5] + sh[2] - cen[2]), clean ? 1.f : 0.f);
+        S.dsh[lane][0] = sh[0]; S.dsh[lane][1] = sh[1]; S.dsh[lane][2] = sh[2];
+        S.dbase[lane] = int(G.sub_start[ot]);
+        cnt = int(G.sub_cnt[ot]);
     }
-    if (lane == 0) S.ng = ng;
+    T.c0 += uint64_t(nch);
     stage_sync<W>();
-    int tot = 0;
-    S.pref[lane][0] = 0;
+    float fx = T.fx, fy = T.fy, fz = T.fz, fh = T.fh;     // opaque copies: not hoisted out of the item loop
+    asm volatile("" : "+v"(fx), "+v"(fy), "+v"(fz), "+v"(fh));
     const float ap2 = fx * fx + fy * fy + fz * fz, ah2 = fh * fh;
-    const float A2 = (ap2 - ah2) - kTestSlack * (ap2 + ah2);
-    const float mx2 = -2.f * fx, my2 = -2.f * fy, mz2 = -2.f * fz, mh2 = -2.f * fh;
-    for (int g = 0; g < ng; ++g) {
-        uint64_t m = 0ull;
-        const int cnt = S.cnt[g];
-        if (ov) {
-            if (S.clean[g]) {
-                uint32_t mlo = 0u, mhi = 0u;
-                for (int k = 0; k < cnt; ++k) {
-                    const float4 q = S.t[g][k];
-                    const float e = fmaf(mx2, q.x, fmaf(my2, q.y, fmaf(mz2, q.z, fmaf(mh2, q.w, A2 + S.tb[g][k]))));
-                    if (k < 32) mlo |= (e < 0.f ? 1u : 0u) << k;
-                    else mhi |= (e < 0.f ? 1u : 0u) << (k - 32);
-                }
-                m = (uint64_t(mhi) << 32) | mlo;
-            } else {
-                for (int k = 0; k < cnt; ++k) {
-                    const float4 q = S.t[g][k];
-                    const float dx = min_image_f(fx - q.x, Lf[0]), dy = min_image_f(fy - q.y, Lf[1]),
-                                dz = min_image_f(fz - q.z, Lf[2]), hs = fh + q.w;
-                    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    if (d2 < hs * hs * kTestMargin) m |= 1ull << k;
-                }
-            }
+    uint64_t actA = 0ull, actB = 0ull;
+    for (int j = 0; j < nch; ++j) {
+        const float4 lo = S.dlo[j], hi = S.dhi[j];
+        bool near = T.ov;
+        if (hi.w != 0.f) {
+            const float gx = fmaxf(0.f, fmaxf(lo.x - fx, fx - hi.x));
+            const float gy = fmaxf(0.f, fmaxf(lo.y - fy, fy - hi.y));
+            const float gz = fmaxf(0.f, fmaxf(lo.z - fz, fz - hi.z));
+            const float gap2 = fmaf(gx, gx, fmaf(gy, gy, gz * gz));
+            const float Q2 = fmaxf(lo.x * lo.x, hi.x * hi.x) + fmaxf(lo.y * lo.y, hi.y * hi.y) +
+                             fmaxf(lo.z * lo.z, hi.z * hi.z);
+            const float hs = fh + lo.w;
+            const float reach2 = fmaf(hs, hs, 4e-6f * (ap2 + ah2 + Q2 + lo.w * lo.w)) * (1.f + 1e-5f);
+            near = T.ov && gap2 < reach2;
         }
-        S.mask[lane][g] = m;
-        tot += __popcll(m);
-        S.pref[lane][g + 1] = tot;
+        const uint64_t om = __ballot(near);
+        if (uint32_t(om)) actA |= 1ull << j;
+        if (om >> 32) actB |= 1ull << j;
     }
+    T.actA = actA; T.actB = actB;
+    const bool act = ((actA | actB) >> lane) & 1ull;
+    const int ca = act ? cnt : 0;
+    const int incl = wave_incl_scan(ca);
+    S.dpre[lane] = incl - ca;
+    S.dincl[lane] = incl;
+    T.total = __shfl(incl, 63);
+    T.Ps = 0;
+}
+
+// Test the next group of slots against the tile's owners.  Returns the group's
+// hit count (wave-uniform), -1 when the item's candidates are exhausted.
+template <int W>
+__device__ __forceinline__ int test_next(PairTest& T, TestLds& S, const PassGeom& G, const double* A,
+                                         const double cen[3], const float Lf[3])
+{
+    const int lane = lane_id();
+    while (T.Ps >= T.total) {
+        if (T.c0 >= T.ce) return -1;
+        test_chunk<W>(T, S, G, A, cen);
+    }
+    stage_sync<W>();    // the previous group's decode is done with the slot table
+    // reached sub-tiles whose slots fall in [Ps, Ps + 64): a contiguous run
+    const bool act = ((T.actA | T.actB) >> lane) & 1ull;
+    const int pre = S.dpre[lane], inc = S.dincl[lane];
+    const bool mem = act && pre >= T.Ps && inc <= T.Ps + 64;
+    const uint64_t gm = __ballot(mem);
+    const int end = S.dincl[63 - __clzll(gm)];
+    const int ns = end - T.Ps;
+    const bool tileA = (T.actA & gm) != 0ull, tileB = (T.actB & gm) != 0ull;
+    S.sj[lane] = -1;
+    stage_sync<W>();
+    if (mem) S.sj[pre - T.Ps] = lane;
+    stage_sync<W>();
+    const int jm = wave_incl_max(S.sj[lane]);
+    // lane L loads slot s
+    const int s = slot_of_lane(lane);
+    const int j = __shfl(jm, s);
+    const bool sv = s < ns;
+    int cl = 1;
+    float c[6] = {0.f, 0.f, 0.f, 0.f, 1.f, __builtin_inff()};
+    if (sv) {
+        const int64_t q = int64_t(S.dbase[j]) + (s - (S.dpre[j] - T.Ps));
+        cl = S.dhi[j].w != 0.f;
+        const double X = G.tx[q] + S.dsh[j][0], Y = G.ty[q] + S.dsh[j][1], Z = G.tz[q] + S.dsh[j][2];
+        const double Hh = G.th[q];
+        S.px[s] = X; S.py[s] = Y; S.pz[s] = Z; S.ph[s] = Hh;
+        S.pq[s] = uint32_t(q);
+        S.pclean[s] = cl;
+        const float qx = float(X - cen[0]), qy = float(Y - cen[1]), qz = float(Z - cen[2]), qh = float(Hh);
+        S.pf[s] = make_float4(qx, qy, qz, qh);
+        const float p2 = qx * qx + qy * qy + qz * qz, h2 = qh * qh;
+        c[0] = -2.f * qx; c[1] = -2.f * qy; c[2] = -2.f * qz; c[3] = -2.f * qh;
+        c[5] = (p2 - h2) - kTestSlack * (p2 + h2);
+    }
+    // owner terms are rebuilt per group: opaque copies keep the compiler from
+    // hoisting them (they would stay live through the evaluate phase)
+    float fx = T.fx, fy = T.fy, fz = T.fz, fh = T.fh;
+    asm volatile("" : "+v"(fx), "+v"(fy), "+v"(fz), "+v"(fh));
+    const float ap2 = fx * fx + fy * fy + fz * fz, ah2 = fh * fh;
+    uint64_t m = 0ull;
+    if (__ballot(!cl) == 0ull) {
+        // e(slot, owner) = [-2q, -2qh, 1, B] . [p, ph, A, 1] on the matrix cores
+        const float oc[6] = {T.ov ? fx : 0.f, T.ov ? fy : 0.f, T.ov ? fz : 0.f, T.ov ? fh : 0.f,
+                             T.ov ? (ap2 - ah2) - kTestSlack * (ap2 + ah2) : __builtin_inff(), 1.f};
+        float a[2][3], b[2][3];
+        half_operands(c, a);
+        half_operands(oc, b);
+        uint32_t w0 = 0u, w1 = 0u;
+        if (tileA) {
+            if (ns > 32) w0 = mfma_signs(a[1], b[0], w0);
+            w0 = mfma_signs(a[0], b[0], w0);
+        }
+        if (tileB) {
+            if (ns > 32) w1 = mfma_signs(a[1], b[1], w1);
+            w1 = mfma_signs(a[0], b[1], w1);
+        }
+        // w_t: owner 32 t + L%32 against slots 16 (L/32) + r (low half) and
+        // 32 + 16 (L/32) + r (high half); owner L keeps w_{L/32}, the partner
+        // supplies the other 32 slots
+        const bool h = lane >= 32;
+        const uint32_t mine = h ? w1 : w0, send = h ? w0 : w1;
+        const uint32_t recv = uint32_t(__shfl_xor(int(send), 32));
+        const uint32_t lo16 = h ? recv : mine, hi16 = h ? mine : recv;
+        const uint32_t mlo = (lo16 & 0xffffu) | (hi16 << 16), mhi = (lo16 >> 16) | (hi16 & 0xffff0000u);
+        m = (uint64_t(mhi) << 32) | mlo;
+    } else {
+        // some sub-tile needs the per-pair minimum image: owner lanes walk the slots
+        stage_sync<W>();
+        const float A2 = (ap2 - ah2) - kTestSlack * (ap2 + ah2);
+        const float mx2 = -2.f * fx, my2 = -2.f * fy, mz2 = -2.f * fz, mh2 = -2.f * fh;
+#pragma unroll 1
+        for (int t = 0; t < ns; ++t) {
+            const float4 q = S.pf[t];
+            bool hit;
+            if (S.pclean[t]) {
+                const float p2 = q.x * q.x + q.y * q.y + q.z * q.z, h2 = q.w * q.w;
+                const float tb = (p2 - h2) - kTestSlack * (p2 + h2);
+                hit = fmaf(mx2, q.x, fmaf(my2, q.y, fmaf(mz2, q.z, fmaf(mh2, q.w, A2 + tb)))) < 0.f;
+            } else {
+                const float dx = min_image_f(fx - q.x, Lf[0]), dy = min_image_f(fy - q.y, Lf[1]),
+                            dz = min_image_f(fz - q.z, Lf[2]), hs = fh + q.w;
+                hit = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < hs * hs * kTestMargin;
+            }
+            if (T.ov && hit) m |= 1ull << t;
+        }
+    }
+    S.mask[lane] = m;
+    const int tot = __popcll(m);
     const int incl = wave_incl_scan(tot);
     S.offs[lane] = incl - tot;
     const int H = __shfl(incl, 63);
     if (lane == 63) S.offs[64] = H;
+    T.Ps = end;
     stage_sync<W>();
     return H;
 }
 
-// Decode hit `pos` of the group: owner lane o, sub-tile g, particle k.
-__device__ __forceinline__ void group_decode(const GroupLds& S, int pos, int* o_out, int* g_out, int* k_out)
+// Hit `pos` of the group: owner lane o and slot s.
+__device__ __forceinline__ void test_decode(const TestLds& S, int pos, int* o_out, int* s_out)
 {
     int lo = 0;
 #pragma unroll
     for (int step = 32; step >= 1; step >>= 1)
         if (S.offs[lo + step] <= pos) lo += step;
-    const int o = lo;
-    int r = pos - S.offs[o];
-    int g = 0;
-    while (g + 1 < S.ng && S.pref[o][g + 1] <= r) ++g;
-    r -= S.pref[o][g];
-    *o_out = o;
-    *g_out = g;
-    *k_out = select_bit(S.mask[o][g], r);
+    *o_out = lo;
+    *s_out = select_bit(S.mask[lo], pos - S.offs[lo]);
 }
 
 // ---------------------------------------------------------------------------
@@ -774,7 +949,8 @@ __device__ __forceinline__ void gas_write_out(const GasPassArgs& a, uint32_t o, 
 }
 
 template <typename Real, int N, bool EXACT_G, int RM, bool BATCH = false>
-__global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kRatesMlp ? 2 : 1) void k_pass_gas(
+__global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kRatesMlp ? 2 : (sizeof(Real) == 4 ? 3 : (RM == kRatesExact ? 1 : 2)))
+void k_pass_gas(
     GasPassArgs a0, const GasPassArgs* __restrict__ boxes, const int64_t* __restrict__ box_items, int nbox)
 {
     // BATCH: one launch over the work items of all boxes; a0 holds the
@@ -783,13 +959,13 @@ __global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kR
     // that they share one LDS copy of the weights.
     constexpr int W = RM == kRatesMlp ? kMlpPassWaves : 1;
     static_assert(RM != kRatesMlp || sizeof(Real) == 4, "network rates run in binary32");
-    __shared__ GroupLds S_[W];
+    __shared__ TestLds S_[W];
     __shared__ Real s_gx[kMaxQuadNodes], s_gw[kMaxQuadNodes];
     __shared__ double o_x_[W][64], o_y_[W][64], o_z_[W][64], o_h_[W][64], o_Vx_[W][64], o_Vy_[W][64], o_Vz_[W][64];
     __shared__ Real o_i2_[W][64], o_a_[W][64], o_b_[W][64], o_r_[W][64];
     __shared__ __align__(16) unsigned char s_mlp[RM == kRatesMlp ? kMlpInferBytes : 16];
     const int wv = W == 1 ? 0 : int(threadIdx.x) >> 6;
-    GroupLds& S = S_[wv];
+    TestLds& S = S_[wv];
     double* o_x = o_x_[wv]; double* o_y = o_y_[wv]; double* o_z = o_z_[wv]; double* o_h = o_h_[wv];
     double* o_Vx = o_Vx_[wv]; double* o_Vy = o_Vy_[wv]; double* o_Vz = o_Vz_[wv];
     Real* o_i2 = o_i2_[wv]; Real* o_a = o_a_[wv]; Real* o_b = o_b_[wv]; Real* o_r = o_r_[wv];
@@ -850,9 +1026,11 @@ __global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kR
         const double cen[3] = {0.5 * (A[0] + A[3]), 0.5 * (A[1] + A[4]), 0.5 * (A[2] + A[5])};
         const float fx = float(mx - cen[0]), fy = float(my - cen[1]), fz = float(mz - cen[2]), fh = float(mh);
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-        for (uint64_t c = cb; c < ce; c += kGroup) {
-            const int ng = int(min<uint64_t>(kGroup, ce - c));
-            const int H = group_test<W>(S, G, A, cen, c, ng, ov, fx, fy, fz, fh, Lf);
+        PairTest T;
+        test_begin(T, ov, fx, fy, fz, fh, cb, ce);
+        for (;;) {
+            const int H = test_next<W>(T, S, G, A, cen, Lf);
+            if (H < 0) break;
             const int my_lo = S.offs[lane], my_hi = S.offs[lane + 1];
             for (int base = 0; base < H; base += 64) {
                 const int pp = base + lane;
@@ -860,13 +1038,12 @@ __global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kR
                 int seg_end = -1;
                 if constexpr (RM != kRatesMlp) {
                     if (pp < H) {
-                        int o, g, k;
-                        group_decode(S, pp, &o, &g, &k);
+                        int o, sl;
+                        test_decode(S, pp, &o, &sl);
                         seg_end = min(S.offs[o + 1], base + 64) - 1 - base;
-                        const int64_t q = int64_t(S.base[g]) + k;
-                        const double qx = G.tx[q] + S.sh[g][0], qy = G.ty[q] + S.sh[g][1], qz = G.tz[q] + S.sh[g][2];
-                        const double qh = G.th[q];
-                        const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.clean[g] != 0, G.L);
+                        const int64_t q = int64_t(S.pq[sl]);
+                        const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
+                        const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.pclean[sl] != 0, G.L);
                         const double hs = o_h[o] + qh;
                         if (d2 < hs * hs) {
                             npairs++;
@@ -904,13 +1081,12 @@ __global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kR
                     int64_t q = 0;
                     float gg = 0.f, wx = 0.f, wy = 0.f, wz = 0.f, w2 = 0.f, i2 = 0.f, u = 0.f;
                     if (pp < H) {
-                        int g, k;
-                        group_decode(S, pp, &o, &g, &k);
+                        int sl;
+                        test_decode(S, pp, &o, &sl);
                         seg_end = min(S.offs[o + 1], base + 64) - 1 - base;
-                        q = int64_t(S.base[g]) + k;
-                        const double qx = G.tx[q] + S.sh[g][0], qy = G.ty[q] + S.sh[g][1], qz = G.tz[q] + S.sh[g][2];
-                        const double qh = G.th[q];
-                        const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.clean[g] != 0, G.L);
+                        q = int64_t(S.pq[sl]);
+                        const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
+                        const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.pclean[sl] != 0, G.L);
                         const double hs = o_h[o] + qh;
                         if (d2 < hs * hs) {
                             live = true;
@@ -1062,7 +1238,7 @@ template <typename Real, int N, bool EXACT_G, bool BATCH = false>
 __global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a0, const DmPassArgs* __restrict__ boxes,
                                                    const int64_t* __restrict__ box_items, int nbox)
 {
-    __shared__ GroupLds S;
+    __shared__ TestLds S;
     __shared__ double o_x[64], o_y[64], o_z[64], o_h[64], o_vx[64], o_vy[64], o_vz[64];
     __shared__ Real o_dt[64];
     __shared__ uint32_t o_id[64];
@@ -1129,9 +1305,11 @@ __global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a0, const DmPassAr
         double accP = 0.0;
         Real accM = 0;
         int accNB = 0;
-        for (uint64_t c = cb; c < ce; c += kGroup) {
-            const int ng = int(min<uint64_t>(kGroup, ce - c));
-            const int H = group_test(S, G, A, cen, c, ng, ov, fx, fy, fz, fh, Lf);
+        PairTest T;
+        test_begin(T, ov, fx, fy, fz, fh, cb, ce);
+        for (;;) {
+            const int H = test_next<1>(T, S, G, A, cen, Lf);
+            if (H < 0) break;
             const int my_lo = S.offs[lane], my_hi = S.offs[lane + 1];
             for (int base = 0; base < H; base += 64) {
                 const int pp = base + lane;
@@ -1140,13 +1318,12 @@ __global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a0, const DmPassAr
                 int cNB = 0;
                 int seg_end = -1;
                 if (pp < H) {
-                    int o, g, k;
-                    group_decode(S, pp, &o, &g, &k);
+                    int o, sl;
+                    test_decode(S, pp, &o, &sl);
                     seg_end = min(S.offs[o + 1], base + 64) - 1 - base;
-                    const int64_t q = int64_t(S.base[g]) + k;
-                    const double qx = G.tx[q] + S.sh[g][0], qy = G.ty[q] + S.sh[g][1], qz = G.tz[q] + S.sh[g][2];
-                    const double qh = G.th[q];
-                    const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.clean[g] != 0, G.L);
+                    const int64_t q = int64_t(S.pq[sl]);
+                    const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
+                    const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.pclean[sl] != 0, G.L);
                     const double hs = o_h[o] + qh;
                     const double hs2 = hs * hs;
                     if (fabs(d2 - hs2) <= 1e-6 * hs2) cNB = 1;
