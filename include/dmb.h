@@ -270,8 +270,8 @@ dmb_status dmb_profile_read(dmb_ctx *ctx, double *ms, int64_t *calls, int32_t re
 
 /* Structure of the last dmb_build_cells (host array of 10 int64):
  * [active gas, active DM, gas tiles, DM tiles, gas owner tiles, DM owner
- *  tiles, candidate tile pairs of the gas pass, of the DM pass, work items of
- *  the gas pass, of the DM pass]. */
+ *  tiles, candidate (owner tile, sub-tile) pairs of the gas pass, of the DM
+ *  pass, work items of the gas pass, of the DM pass]. */
 dmb_status dmb_build_stats(const dmb_ctx *ctx, int64_t *out10);
 
 /* Message for the last failure on this context; with ctx == NULL, the

@@ -34,6 +34,8 @@ struct Species {
     DevBuf sx, sy, sz, sh;                 // sorted position, h
     DevBuf flag, flag_off, own;            // active owners (sorted positions)
     DevBuf tbox, th, sbox, shh, mbox, mhh, obox, oh;  // sub-tiles, super-, mega-tiles, owner tiles
+    DevBuf tsup, ssup, msup;               // support boxes (union of [x - h, x + h]) of sub-, super-, mega-tiles
+    DevBuf tq, sq, mq;                     // binary32 candidate-search nodes of sub-, super-, mega-tiles
     DevBuf cube;                           // Morton cube
     // per-step gathers (sorted order)
     DevBuf v0, v1, v2;                     // velocity components (double)
@@ -41,9 +43,14 @@ struct Species {
     const uint32_t* perm = nullptr;        // = vals after the sort
 };
 
-struct Pairs {                             // candidate lists: owner tiles of A x tiles of B
-    DevBuf cnt, off, cand, icnt, ioff, it_tile, it_cb, it_ce;
-    int64_t total = 0, nitems = 0;
+struct Pairs {                             // candidate lists: owner tiles of A x sub-tiles of B
+    // (owner tile, candidate super-tile) pairs: per-tile counts and offsets, the pairs, their sub-tile masks
+    DevBuf cnt, off, psup, ptile, mask, pcnt, soff;
+    DevBuf pad, maxcnt;                    // count-pass copy of the first pad_cap super-tiles per tile; largest count
+    // candidate sub-tiles: per-tile counts and starts, the lists, work items
+    DevBuf scnt, beg, cand, icnt, ioff, it_tile, it_cb, it_ce;
+    int pad_cap = 128;                     // grown from the largest count seen
+    int64_t npairs = 0, total = 0, nitems = 0;
 };
 
 // Cell structure and per-step buffers of one box (one periodic volume or
@@ -275,9 +282,8 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
     // sub-tile counts per 64-chunk (other role); totals are read back by the caller
     S.nchunk = (n + kTile - 1) / kTile;
     ENSURE(c, S.sub_ccnt, (S.nchunk + 1) * 4); ENSURE(c, S.sub_coff, (S.nchunk + 1) * 4);
-    hipLaunchKernelGGL(k_subtile_split<false>, dim3(unsigned(S.nchunk)), dim3(64), 0, c->stream,
-                       S.keys.as<const uint64_t>(), n, S.sort_lo_bit, c->subtile_delta, S.sub_ccnt.as<uint32_t>(),
-                       (const uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr);
+    hipLaunchKernelGGL(k_subtile_count, dim3(unsigned(S.nchunk)), dim3(64), 0, c->stream,
+                       S.keys.as<const uint64_t>(), n, S.sort_lo_bit, c->subtile_delta, S.sub_ccnt.as<uint32_t>());
     HIPCHK(c, hipMemsetAsync(S.sub_ccnt.as<uint32_t>() + S.nchunk, 0, 4, c->stream));
     s = scan_excl(c, S.sub_ccnt.as<const uint32_t>(), S.sub_coff.as<uint32_t>(), S.nchunk + 1);
     if (s != DMB_OK) return s;
@@ -290,22 +296,25 @@ dmb_status build_subtiles(dmb_ctx* c, Species& S)
 {
     if (S.n == 0) return DMB_OK;
     ENSURE(c, S.sub_start, S.ntile * 4); ENSURE(c, S.sub_cnt, S.ntile * 4);
-    hipLaunchKernelGGL(k_subtile_split<true>, dim3(unsigned(S.nchunk)), dim3(64), 0, c->stream,
-                       S.keys.as<const uint64_t>(), S.n, S.sort_lo_bit, c->subtile_delta, (uint32_t*)nullptr,
-                       S.sub_coff.as<const uint32_t>(), S.sub_start.as<uint32_t>(), S.sub_cnt.as<uint32_t>());
     S.nsuper = (S.ntile + kTile - 1) / kTile;
-    ENSURE(c, S.tbox, S.ntile * 48); ENSURE(c, S.th, S.ntile * 8);
-    ENSURE(c, S.sbox, S.nsuper * 48); ENSURE(c, S.shh, S.nsuper * 8);
-    hipLaunchKernelGGL(k_range_bounds, dim3(unsigned(S.ntile)), dim3(64), 0, c->stream,
-                       S.sub_start.as<const uint32_t>(), S.sub_cnt.as<const uint32_t>(), S.sx.as<const double>(),
-                       S.sy.as<const double>(), S.sz.as<const double>(), S.sh.as<const double>(),
-                       S.tbox.as<double>(), S.th.as<double>());
+    ENSURE(c, S.tbox, S.ntile * 48); ENSURE(c, S.th, S.ntile * 8); ENSURE(c, S.tsup, S.ntile * 48);
+    ENSURE(c, S.sbox, S.nsuper * 48); ENSURE(c, S.shh, S.nsuper * 8); ENSURE(c, S.ssup, S.nsuper * 48);
+    ENSURE(c, S.tq, S.ntile * 64); ENSURE(c, S.sq, S.nsuper * 64);
+    hipLaunchKernelGGL(k_subtile_write, dim3(unsigned(S.nchunk)), dim3(64), 0, c->stream,
+                       S.keys.as<const uint64_t>(), S.n, S.sort_lo_bit, c->subtile_delta,
+                       S.sub_coff.as<const uint32_t>(), S.sub_start.as<uint32_t>(), S.sub_cnt.as<uint32_t>(),
+                       S.sx.as<const double>(), S.sy.as<const double>(), S.sz.as<const double>(),
+                       S.sh.as<const double>(), S.tbox.as<double>(), S.th.as<double>(), S.tsup.as<double>(),
+                       S.tq.as<float4>());
     hipLaunchKernelGGL(k_super_bounds, dim3(unsigned(S.nsuper)), dim3(64), 0, c->stream, S.ntile,
-                       S.tbox.as<const double>(), S.th.as<const double>(), S.sbox.as<double>(), S.shh.as<double>());
+                       S.tbox.as<const double>(), S.th.as<const double>(), S.tsup.as<const double>(),
+                       S.sbox.as<double>(), S.shh.as<double>(), S.ssup.as<double>(), S.sq.as<float4>());
     S.nmega = (S.nsuper + kTile - 1) / kTile;
-    ENSURE(c, S.mbox, S.nmega * 48); ENSURE(c, S.mhh, S.nmega * 8);
+    ENSURE(c, S.mbox, S.nmega * 48); ENSURE(c, S.mhh, S.nmega * 8); ENSURE(c, S.msup, S.nmega * 48);
+    ENSURE(c, S.mq, S.nmega * 64);
     hipLaunchKernelGGL(k_super_bounds, dim3(unsigned(S.nmega)), dim3(64), 0, c->stream, S.nsuper,
-                       S.sbox.as<const double>(), S.shh.as<const double>(), S.mbox.as<double>(), S.mhh.as<double>());
+                       S.sbox.as<const double>(), S.shh.as<const double>(), S.ssup.as<const double>(),
+                       S.mbox.as<double>(), S.mhh.as<double>(), S.msup.as<double>(), S.mq.as<float4>());
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
 }
@@ -327,12 +336,12 @@ CandArgs cand_args(dmb_ctx* c, Species& A, Species& B, Pairs& P)
 {
     CandArgs a;
     a.nown_tile = A.nown_tile; a.ntile = B.ntile; a.nsuper = B.nsuper; a.nmega = B.nmega;
-    a.mbox = B.mbox.as<const double>(); a.mhh = B.mhh.as<const double>();
     a.obox = A.obox.as<const double>(); a.oh = A.oh.as<const double>();
-    a.tbox = B.tbox.as<const double>(); a.th = B.th.as<const double>();
-    a.sbox = B.sbox.as<const double>(); a.shh = B.shh.as<const double>();
+    a.sq = B.sq.as<const float4>(); a.mq = B.mq.as<const float4>();
     for (int k = 0; k < 3; ++k) a.L[k] = c->X->built_L[k];
     a.cnt = P.cnt.as<uint32_t>(); a.off = P.off.as<const uint64_t>(); a.cand = P.cand.as<uint32_t>();
+    a.pad = P.pad.as<uint32_t>(); a.pad_cap = P.pad_cap; a.maxcnt = P.maxcnt.as<uint32_t>();
+    a.cand = P.psup.as<uint32_t>(); a.ptile = P.ptile.as<uint32_t>();
     return a;
 }
 
@@ -341,25 +350,68 @@ dmb_status cand_count(dmb_ctx* c, Species& A, Species& B, Pairs& P)
     int64_t nt = A.nown_tile;
     ENSURE(c, P.cnt, (nt + 1) * 4); ENSURE(c, P.off, (nt + 1) * 8);
     ENSURE(c, P.icnt, (nt + 1) * 4); ENSURE(c, P.ioff, (nt + 1) * 4);
+    ENSURE(c, P.scnt, (nt + 1) * 4); ENSURE(c, P.beg, (nt + 1) * 8);
     if (nt == 0 || B.ntile == 0) {
         HIPCHK(c, hipMemsetAsync(P.off.p, 0, (nt + 1) * 8, c->stream));
         HIPCHK(c, hipMemsetAsync(P.ioff.p, 0, (nt + 1) * 4, c->stream));
         return DMB_OK;
     }
+    // the candidate copy kept by the count pass: at most kPadBytes in all
+    constexpr int64_t kPadBytes = int64_t(3) << 30;
+    P.pad_cap = int(std::max<int64_t>(0, std::min<int64_t>(P.pad_cap, kPadBytes / (4 * nt))));
+    ENSURE(c, P.pad, std::max<int64_t>(1, nt * P.pad_cap) * 4);
+    ENSURE(c, P.maxcnt, 4);
+    HIPCHK(c, hipMemsetAsync(P.maxcnt.p, 0, 4, c->stream));
     CandArgs a = cand_args(c, A, B, P);
-    hipLaunchKernelGGL(k_cand<false>, dim3(unsigned(nt)), dim3(64), 0, c->stream, a);
+    const unsigned grid = unsigned((nt + kXcd - 1) / kXcd * kXcd);
+    hipLaunchKernelGGL(k_cand<false>, dim3(grid), dim3(64), 0, c->stream, a);
     HIPCHK(c, hipMemsetAsync(P.cnt.as<uint32_t>() + nt, 0, 4, c->stream));
-    // candidate offsets in 64 bits (totals pass 2^32 at Milky-Way sizes)
     dmb_status s = scan_excl<uint32_t, uint64_t>(c, P.cnt.as<const uint32_t>(), P.off.as<uint64_t>(), nt + 1);
     if (s != DMB_OK) return s;
+    HIPCHK(c, hipGetLastError());
+    return DMB_OK;
+}
+
+// Pair list, sub-tile masks and counts, work-item counts (needs P.npairs).
+dmb_status cand_subs(dmb_ctx* c, Species& A, Species& B, Pairs& P)
+{
+    int64_t nt = A.nown_tile;
+    if (nt == 0 || B.ntile == 0 || P.npairs == 0) {
+        if (nt > 0) {
+            HIPCHK(c, hipMemsetAsync(P.scnt.p, 0, (nt + 1) * 4, c->stream));
+            HIPCHK(c, hipMemsetAsync(P.ioff.p, 0, (nt + 1) * 4, c->stream));
+        }
+        return DMB_OK;
+    }
+    const int64_t np = P.npairs;
+    ENSURE(c, P.psup, np * 4); ENSURE(c, P.ptile, np * 4);
+    ENSURE(c, P.mask, np * 8); ENSURE(c, P.pcnt, (np + 1) * 4); ENSURE(c, P.soff, (np + 1) * 8);
+    CandArgs a = cand_args(c, A, B, P);
+    hipLaunchKernelGGL(k_cand<true>, dim3(unsigned((nt + kXcd - 1) / kXcd * kXcd)), dim3(64), 0, c->stream, a);
+    SubMaskArgs m;
+    m.npairs = np; m.ntile = B.ntile;
+    m.ptile = P.ptile.as<const uint32_t>(); m.psup = P.psup.as<const uint32_t>();
+    m.obox = A.obox.as<const double>(); m.oh = A.oh.as<const double>();
+    m.tq = B.tq.as<const float4>();
+    for (int k = 0; k < 3; ++k) m.L[k] = c->X->built_L[k];
+    m.mask = P.mask.as<uint64_t>(); m.pcnt = P.pcnt.as<uint32_t>();
+    hipLaunchKernelGGL(k_sub_masks, dim3(unsigned((np + kSubPairs - 1) / kSubPairs)), dim3(64), 0, c->stream, m);
+    HIPCHK(c, hipMemsetAsync(P.pcnt.as<uint32_t>() + np, 0, 4, c->stream));
+    // candidate offsets in 64 bits (totals pass 2^32 at Milky-Way sizes)
+    dmb_status s = scan_excl<uint32_t, uint64_t>(c, P.pcnt.as<const uint32_t>(), P.soff.as<uint64_t>(), np + 1);
+    if (s != DMB_OK) return s;
+    hipLaunchKernelGGL(k_tile_subs, dim3(blocks_for(nt + 1, 256)), dim3(256), 0, c->stream, nt,
+                       P.off.as<const uint64_t>(), P.soff.as<const uint64_t>(), P.scnt.as<uint32_t>(),
+                       P.beg.as<uint64_t>());
     hipLaunchKernelGGL(k_item_count, dim3(blocks_for(nt + 1, 256)), dim3(256), 0, c->stream,
-                       P.cnt.as<const uint32_t>(), nt, uint32_t(c->split), P.icnt.as<uint32_t>());
+                       P.scnt.as<const uint32_t>(), nt, uint32_t(c->split), P.icnt.as<uint32_t>());
     s = scan_excl(c, P.icnt.as<const uint32_t>(), P.ioff.as<uint32_t>(), nt + 1);
     if (s != DMB_OK) return s;
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
 }
 
+// Candidate sub-tile lists and work items (needs P.total, P.nitems).
 dmb_status cand_write(dmb_ctx* c, Species& A, Species& B, Pairs& P)
 {
     int64_t nt = A.nown_tile;
@@ -368,11 +420,12 @@ dmb_status cand_write(dmb_ctx* c, Species& A, Species& B, Pairs& P)
     ENSURE(c, P.it_cb, std::max<int64_t>(P.nitems, 1) * 8);
     ENSURE(c, P.it_ce, std::max<int64_t>(P.nitems, 1) * 8);
     if (nt == 0 || B.ntile == 0 || P.total == 0) return DMB_OK;
-    CandArgs a = cand_args(c, A, B, P);
-    hipLaunchKernelGGL(k_cand<true>, dim3(unsigned(nt)), dim3(64), 0, c->stream, a);
-    hipLaunchKernelGGL(k_item_write, dim3(blocks_for(nt, 256)), dim3(256), 0, c->stream, P.off.as<const uint64_t>(),
-                       P.ioff.as<const uint32_t>(), nt, uint32_t(c->split), P.it_tile.as<uint32_t>(),
-                       P.it_cb.as<uint64_t>(), P.it_ce.as<uint64_t>());
+    hipLaunchKernelGGL(k_expand, dim3(blocks_for(P.npairs, 256)), dim3(256), 0, c->stream, P.npairs,
+                       P.psup.as<const uint32_t>(), P.mask.as<const uint64_t>(), P.soff.as<const uint64_t>(),
+                       P.cand.as<uint32_t>());
+    hipLaunchKernelGGL(k_item_write, dim3(blocks_for(nt, 256)), dim3(256), 0, c->stream, P.beg.as<const uint64_t>(),
+                       P.scnt.as<const uint32_t>(), P.ioff.as<const uint32_t>(), nt, uint32_t(c->split),
+                       P.it_tile.as<uint32_t>(), P.it_cb.as<uint64_t>(), P.it_ce.as<uint64_t>());
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
 }
@@ -603,7 +656,7 @@ void combine_dm_and_resolve(dmb_ctx* c, Cells& X, const DmPassArgs& a, const dmb
     }
     ResolveArgs r;
     r.g = a.g;
-    r.cand_off = X.dp.off.as<const uint64_t>();
+    r.cand_beg = X.dp.beg.as<const uint64_t>(); r.cand_cnt = X.dp.scnt.as<const uint32_t>();
     r.vx = a.vx; r.vy = a.vy; r.vz = a.vz; r.dtr = a.dtr; r.dm_perm = a.dm_perm;
     r.Vx = a.Vx; r.Vy = a.Vy; r.Vz = a.Vz; r.vs = a.vs; r.K = a.K; r.gas_perm = a.gas_perm;
     r.gas_vel = gas->vel; r.gas_u = gas->u; r.gas_mu = gas->mu; r.m_chi = par->m_chi_g;
@@ -971,11 +1024,14 @@ void free_cells(Cells& X)
         DevBuf* all[] = {&S->keys, &S->keys2, &S->vals, &S->vals2, &S->sx, &S->sy, &S->sz, &S->sh, &S->flag,
                          &S->flag_off, &S->own, &S->tbox, &S->th, &S->sbox, &S->shh, &S->mbox, &S->mhh, &S->obox,
                          &S->oh, &S->cube, &S->v0, &S->v1, &S->v2, &S->r0, &S->r1, &S->r2, &S->r3, &S->r4, &S->r5,
-                         &S->r6, &S->sub_ccnt, &S->sub_coff, &S->sub_start, &S->sub_cnt};
+                         &S->r6, &S->sub_ccnt, &S->sub_coff, &S->sub_start, &S->sub_cnt, &S->tsup, &S->ssup,
+                         &S->msup, &S->tq, &S->sq, &S->mq};
         for (DevBuf* b : all) fr(*b);
     }
     for (Pairs* P : {&X.gp, &X.dp}) {
-        DevBuf* all[] = {&P->cnt, &P->off, &P->cand, &P->icnt, &P->ioff, &P->it_tile, &P->it_cb, &P->it_ce};
+        DevBuf* all[] = {&P->cnt, &P->off, &P->cand, &P->icnt, &P->ioff, &P->it_tile, &P->it_cb, &P->it_ce,
+                         &P->pad, &P->maxcnt, &P->beg, &P->psup, &P->ptile, &P->mask, &P->pcnt, &P->soff,
+                         &P->scnt};
         for (DevBuf* b : all) fr(*b);
     }
     DevBuf* rest[] = {&X.boxL, &X.part_gas, &X.part_p, &X.part_pm, &X.part_nb, &X.psum_own, &X.qctr, &X.slist};
@@ -1154,15 +1210,16 @@ dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_part
     if ((s = build_owner_tiles(c, c->X->dm)) != DMB_OK) return s;
     if ((s = cand_count(c, c->X->gas, c->X->dm, c->X->gp)) != DMB_OK) return s;
     if ((s = cand_count(c, c->X->dm, c->X->gas, c->X->dp)) != DMB_OK) return s;
-    uint64_t tot[4] = {0, 0, 0, 0};
+    uint64_t npairs[2] = {0, 0};
+    uint32_t maxcnt[2] = {0, 0};
     double hmax[2] = {0, 0};
-    if (c->X->gas.nown_tile > 0) {
-        HIPCHK(c, hipMemcpyAsync(&tot[0], c->X->gp.off.as<uint64_t>() + c->X->gas.nown_tile, 8, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipMemcpyAsync(&tot[1], c->X->gp.ioff.as<uint32_t>() + c->X->gas.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
-    }
-    if (c->X->dm.nown_tile > 0) {
-        HIPCHK(c, hipMemcpyAsync(&tot[2], c->X->dp.off.as<uint64_t>() + c->X->dm.nown_tile, 8, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipMemcpyAsync(&tot[3], c->X->dp.ioff.as<uint32_t>() + c->X->dm.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
+    for (int k = 0; k < 2; ++k) {
+        Species& A = k == 0 ? c->X->gas : c->X->dm;
+        Species& B = k == 0 ? c->X->dm : c->X->gas;
+        Pairs& P = k == 0 ? c->X->gp : c->X->dp;
+        if (A.nown_tile == 0) continue;
+        HIPCHK(c, hipMemcpyAsync(&npairs[k], P.off.as<uint64_t>() + A.nown_tile, 8, hipMemcpyDeviceToHost, c->stream));
+        if (B.ntile > 0) HIPCHK(c, hipMemcpyAsync(&maxcnt[k], P.maxcnt.p, 4, hipMemcpyDeviceToHost, c->stream));
     }
     if (periodic) {
         // largest h of each species from the super-tile maxima
@@ -1184,10 +1241,29 @@ dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_part
             return fail(c, DMB_ERANGE, "max h_gas + max h_dm = %g >= L/2 = %g", hmax[0] + hmax[1], 0.5 * Lmin);
         }
     }
-    c->X->gp.total = tot[0]; c->X->gp.nitems = tot[1];
-    c->X->dp.total = tot[2]; c->X->dp.nitems = tot[3];
+    c->X->gp.npairs = int64_t(npairs[0]);
+    c->X->dp.npairs = int64_t(npairs[1]);
+    if ((s = cand_subs(c, c->X->gas, c->X->dm, c->X->gp)) != DMB_OK) return s;
+    if ((s = cand_subs(c, c->X->dm, c->X->gas, c->X->dp)) != DMB_OK) return s;
+    uint64_t tot[2] = {0, 0};
+    uint32_t nit[2] = {0, 0};
+    for (int k = 0; k < 2; ++k) {
+        Species& A = k == 0 ? c->X->gas : c->X->dm;
+        Pairs& P = k == 0 ? c->X->gp : c->X->dp;
+        if (A.nown_tile == 0) continue;
+        if (P.npairs > 0) HIPCHK(c, hipMemcpyAsync(&tot[k], P.soff.as<uint64_t>() + P.npairs, 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(&nit[k], P.ioff.as<uint32_t>() + A.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->X->gp.total = int64_t(tot[0]); c->X->gp.nitems = nit[0];
+    c->X->dp.total = int64_t(tot[1]); c->X->dp.nitems = nit[1];
     if ((s = cand_write(c, c->X->gas, c->X->dm, c->X->gp)) != DMB_OK) return s;
     if ((s = cand_write(c, c->X->dm, c->X->gas, c->X->dp)) != DMB_OK) return s;
+    // later builds keep every candidate of (almost) every tile in the count pass
+    for (int k = 0; k < 2; ++k) {
+        Pairs& P = k == 0 ? c->X->gp : c->X->dp;
+        if (int64_t(maxcnt[k]) > P.pad_cap) P.pad_cap = int(std::min<int64_t>(1 << 20, (int64_t(maxcnt[k]) * 5 / 4 + 63) / 64 * 64));
+    }
     c->X->built_ngas = gas->n;
     c->X->built_ndm = dm->n;
     c->X->built_gas_pos = gas->pos;

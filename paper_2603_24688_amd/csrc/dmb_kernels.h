@@ -204,30 +204,47 @@ __global__ __launch_bounds__(64) void k_tile_bounds(const uint32_t* __restrict__
     }
 }
 
-// Super-tile bounds over 64 consecutive tiles.
+// Binary32 copy of a node's bounds for the candidate search, rounded
+// outward: q[0] = (box lo, max h), q[1] = (box hi, 0), q[2] = (support lo, 0),
+// q[3] = (support hi, 0).
+__device__ __forceinline__ void write_node_q(float4* q, const double b[6], double hm, const double u[6])
+{
+    q[0] = make_float4(__double2float_rd(b[0]), __double2float_rd(b[1]), __double2float_rd(b[2]), __double2float_ru(hm));
+    q[1] = make_float4(__double2float_ru(b[3]), __double2float_ru(b[4]), __double2float_ru(b[5]), 0.f);
+    q[2] = make_float4(__double2float_rd(u[0]), __double2float_rd(u[1]), __double2float_rd(u[2]), 0.f);
+    q[3] = make_float4(__double2float_ru(u[3]), __double2float_ru(u[4]), __double2float_ru(u[5]), 0.f);
+}
+
+// Super-tile bounds over 64 consecutive tiles: box, max h, support box.
 __global__ __launch_bounds__(64) void k_super_bounds(int64_t ntile, const double* __restrict__ tbox,
-                                                     const double* __restrict__ th, double* __restrict__ box,
-                                                     double* __restrict__ hmax)
+                                                     const double* __restrict__ th, const double* __restrict__ tsup,
+                                                     double* __restrict__ box, double* __restrict__ hmax,
+                                                     double* __restrict__ sup, float4* __restrict__ q)
 {
     int64_t s = blockIdx.x;
     int64_t t = s * kTile + lane_id();
     bool v = t < ntile;
-    double b[6];
+    double b[6], u[6];
     for (int a = 0; a < 3; ++a) {
         b[a] = v ? tbox[6 * t + a] : 1e300;
         b[3 + a] = v ? tbox[6 * t + 3 + a] : -1e300;
+        u[a] = v ? tsup[6 * t + a] : 1e300;
+        u[3 + a] = v ? tsup[6 * t + 3 + a] : -1e300;
     }
     double hh = v ? th[t] : 0.0;
     for (int d = 32; d >= 1; d >>= 1) {
         for (int a = 0; a < 3; ++a) {
             b[a] = fmin(b[a], __shfl_xor(b[a], d));
             b[3 + a] = fmax(b[3 + a], __shfl_xor(b[3 + a], d));
+            u[a] = fmin(u[a], __shfl_xor(u[a], d));
+            u[3 + a] = fmax(u[3 + a], __shfl_xor(u[3 + a], d));
         }
         hh = fmax(hh, __shfl_xor(hh, d));
     }
     if (lane_id() == 0) {
-        for (int a = 0; a < 6; ++a) box[6 * s + a] = b[a];
+        for (int a = 0; a < 6; ++a) { box[6 * s + a] = b[a]; sup[6 * s + a] = u[a]; }
         hmax[s] = hh;
+        write_node_q(q + 4 * s, b, hh, u);
     }
 }
 
@@ -235,17 +252,12 @@ __global__ __launch_bounds__(64) void k_super_bounds(int64_t ntile, const double
 // particles is cut wherever two neighbours in the order differ at a Morton
 // level coarser than the chunk's median neighbour level minus one, so that a
 // chunk straddling a coarse cell boundary becomes several compact boxes.
-// count mode: cnt[c] = number of sub-tiles of chunk c; write mode: starts and
-// counts of the sub-tiles at off[c]...  `lo_bit` masks key bits the sort did
-// not order.
-template <bool WRITE>
-__global__ __launch_bounds__(64) void k_subtile_split(const uint64_t* __restrict__ keys, int64_t n, int lo_bit,
-                                                      int cut_delta, uint32_t* __restrict__ cnt,
-                                                      const uint32_t* __restrict__ off,
-                                                      uint32_t* __restrict__ sub_start, uint32_t* __restrict__ sub_cnt)
+// Returns the mask of lanes that start a sub-tile.  `lo_bit` masks key bits
+// the sort did not order.
+__device__ __forceinline__ uint64_t subtile_cuts(const uint64_t* __restrict__ keys, int64_t n, int lo_bit,
+                                                 int cut_delta, int64_t c)
 {
     const int lane = lane_id();
-    const int64_t c = blockIdx.x;
     const int64_t k = c * kTile + lane;
     const bool valid = k < n;
     const int m = int(min<int64_t>(kTile, n - c * kTile));
@@ -263,44 +275,84 @@ __global__ __launch_bounds__(64) void k_subtile_split(const uint64_t* __restrict
         int cntt = __popcll(__ballot(valid && lane > 0 && lvl >= t));
         if (cntt >= need) { med = t; break; }
     }
-    const bool cut = valid && (lane == 0 || lvl < med - cut_delta);
-    const uint64_t cm = __ballot(cut);
-    if (!WRITE) {
-        if (lane == 0) cnt[c] = uint32_t(__popcll(cm));
-        return;
-    }
-    if (cut) {
-        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-        const uint32_t idx = off[c] + uint32_t(__popcll(cm & lt));
-        const uint64_t above = lane == 63 ? 0ull : (cm >> (lane + 1));
-        const int next = above ? lane + __ffsll((unsigned long long)above) : m;
-        sub_start[idx] = uint32_t(k);
-        sub_cnt[idx] = uint32_t(next - lane);
-    }
+    return __ballot(valid && (lane == 0 || lvl < med - cut_delta));
 }
 
-// Bounds of ranges [start, start + count) of the sorted arrays (count <= 64).
-__global__ __launch_bounds__(64) void k_range_bounds(const uint32_t* __restrict__ start, const uint32_t* __restrict__ count,
-                                                     const double* __restrict__ sx, const double* __restrict__ sy,
-                                                     const double* __restrict__ sz, const double* __restrict__ sh,
-                                                     double* __restrict__ box, double* __restrict__ hmax)
+// cnt[c] = number of sub-tiles of chunk c.
+__global__ __launch_bounds__(64) void k_subtile_count(const uint64_t* __restrict__ keys, int64_t n, int lo_bit,
+                                                      int cut_delta, uint32_t* __restrict__ cnt)
 {
-    const int64_t t = blockIdx.x;
-    const int lane = lane_id();
-    const bool v = lane < int(count[t]);
-    const int64_t p = int64_t(start[t]) + lane;
-    double x = v ? sx[p] : 1e300, y = v ? sy[p] : 1e300, z = v ? sz[p] : 1e300;
-    double X = v ? sx[p] : -1e300, Y = v ? sy[p] : -1e300, Z = v ? sz[p] : -1e300;
-    double hh = v ? sh[p] : 0.0;
-    for (int d = 32; d >= 1; d >>= 1) {
-        x = fmin(x, __shfl_xor(x, d)); y = fmin(y, __shfl_xor(y, d)); z = fmin(z, __shfl_xor(z, d));
-        X = fmax(X, __shfl_xor(X, d)); Y = fmax(Y, __shfl_xor(Y, d)); Z = fmax(Z, __shfl_xor(Z, d));
-        hh = fmax(hh, __shfl_xor(hh, d));
+    const uint64_t cm = subtile_cuts(keys, n, lo_bit, cut_delta, blockIdx.x);
+    if (lane_id() == 0) cnt[blockIdx.x] = uint32_t(__popcll(cm));
+}
+
+// Segmented reductions over runs of lanes: lane l ends with the min / max over
+// lanes [l, seg_end] (seg_end is shared by the lanes of a run).
+__device__ __forceinline__ double seg_min_d(double v, int lane, int seg_end)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double t = __shfl_down(v, d);
+        if (lane + d <= seg_end) v = fmin(v, t);
     }
-    if (lane == 0) {
-        box[6 * t + 0] = x; box[6 * t + 1] = y; box[6 * t + 2] = z;
-        box[6 * t + 3] = X; box[6 * t + 4] = Y; box[6 * t + 5] = Z;
-        hmax[t] = hh;
+    return v;
+}
+__device__ __forceinline__ double seg_max_d(double v, int lane, int seg_end)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double t = __shfl_down(v, d);
+        if (lane + d <= seg_end) v = fmax(v, t);
+    }
+    return v;
+}
+
+// Support box of one particle coordinate: [x - h, x + h] widened by a few
+// units in the last place, so that it holds the exact interval.
+__device__ __forceinline__ double sup_lo(double x, double h) { const double v = x - h; return v - 4e-16 * fabs(v); }
+__device__ __forceinline__ double sup_hi(double x, double h) { const double v = x + h; return v + 4e-16 * fabs(v); }
+
+// Starts, counts and bounds of the sub-tiles of chunk c at off[c]...: box,
+// max h and support box (union of the particles' [x - h, x + h]), each a
+// segmented reduction over the sub-tile's run of lanes.
+__global__ __launch_bounds__(64) void k_subtile_write(const uint64_t* __restrict__ keys, int64_t n, int lo_bit,
+                                                      int cut_delta, const uint32_t* __restrict__ off,
+                                                      uint32_t* __restrict__ sub_start, uint32_t* __restrict__ sub_cnt,
+                                                      const double* __restrict__ sx, const double* __restrict__ sy,
+                                                      const double* __restrict__ sz, const double* __restrict__ sh,
+                                                      double* __restrict__ box, double* __restrict__ hmax,
+                                                      double* __restrict__ sup, float4* __restrict__ q)
+{
+    const int lane = lane_id();
+    const int64_t c = blockIdx.x;
+    const int64_t k = c * kTile + lane;
+    const int m = int(min<int64_t>(kTile, n - c * kTile));
+    const uint64_t cm = subtile_cuts(keys, n, lo_bit, cut_delta, c);
+    const uint64_t above = lane == 63 ? 0ull : (cm >> (lane + 1));
+    const int next = above ? lane + __ffsll((unsigned long long)above) : m;
+    const int seg_end = next - 1;
+    const bool valid = lane < m;
+    const int64_t kk = valid ? k : c * kTile;
+    const double x3[3] = {sx[kk], sy[kk], sz[kk]};
+    const double hh = sh[kk];
+    double b[6], u[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        b[a] = seg_min_d(x3[a], lane, seg_end);
+        b[3 + a] = seg_max_d(x3[a], lane, seg_end);
+        u[a] = seg_min_d(sup_lo(x3[a], hh), lane, seg_end);
+        u[3 + a] = seg_max_d(sup_hi(x3[a], hh), lane, seg_end);
+    }
+    const double hm = seg_max_d(hh, lane, seg_end);
+    if (valid && ((cm >> lane) & 1ull)) {
+        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        const int64_t idx = int64_t(off[c]) + __popcll(cm & lt);
+        sub_start[idx] = uint32_t(k);
+        sub_cnt[idx] = uint32_t(next - lane);
+#pragma unroll
+        for (int a = 0; a < 6; ++a) { box[6 * idx + a] = b[a]; sup[6 * idx + a] = u[a]; }
+        hmax[idx] = hm;
+        write_node_q(q + 4 * idx, b, hm, u);
     }
 }
 
@@ -326,58 +378,227 @@ __device__ __forceinline__ bool boxes_near(const double* A, double ha, const dou
     return box_gap2(A, B, L) < reach * reach;
 }
 
-// Candidate other sub-tiles of each owner tile, culled through three levels
-// of boxes (64 super-tiles per mega-tile, 64 sub-tiles per super-tile).
-// count mode: cnt[t] = number of candidates; write mode: cand[off[t] + k] in
-// mega, super, sub-tile order.
+// Owner box A (max h ha) against the support box Bs of some other particles:
+// a pair can interact (|a - b| < h_a + h_b) only if a lies within h_a of b's
+// support, so only if the gap is below ha.
+__device__ __forceinline__ bool reach_near(const double* A, double ha, const double* Bs, const double* L)
+{
+    const double r = ha * (1.0 + 1e-12);
+    return box_gap2(A, Bs, L) < r * r;
+}
+
+// Gap along one axis between [alo, ahi] and [blo, bhi] (minimum over the
+// periodic images when L > 0).
+__device__ __forceinline__ float axis_gap(float alo, float ahi, float blo, float bhi, float L)
+{
+    float g = fmaxf(0.f, fmaxf(blo - ahi, alo - bhi));
+    if (L > 0.f) {
+        const float gp = fmaxf(0.f, fmaxf(blo + L - ahi, alo - bhi - L));
+        const float gm = fmaxf(0.f, fmaxf(blo - L - ahi, alo - bhi + L));
+        g = fminf(g, fminf(gp, gm));
+    }
+    return g;
+}
+
+// Owner box (alo, ahi; ah = max h) against node q (write_node_q layout): both
+// necessary conditions of some pair being within h_a + h_b, the Euclidean
+// box gap below ah + max h of the node and the gap to the node's support box
+// below ah.  Binary32 on outward-rounded bounds: the gaps' rounding is below
+// 1e-5 of the reach, and `dL` (a few units in the last place of the box side)
+// covers the rounding of the periodic image shifts.
+__device__ __forceinline__ bool node_near(float4 alo, float4 ahi, float ah, const float4* __restrict__ q,
+                                          const float L[3], float dL)
+{
+    const float4 lo = q[0], hi = q[1], slo = q[2], shi = q[3];
+    const float g1x = axis_gap(alo.x, ahi.x, lo.x, hi.x, L[0]), g1y = axis_gap(alo.y, ahi.y, lo.y, hi.y, L[1]),
+                g1z = axis_gap(alo.z, ahi.z, lo.z, hi.z, L[2]);
+    const float g2x = axis_gap(alo.x, ahi.x, slo.x, shi.x, L[0]), g2y = axis_gap(alo.y, ahi.y, slo.y, shi.y, L[1]),
+                g2z = axis_gap(alo.z, ahi.z, slo.z, shi.z, L[2]);
+    const float r1 = fmaf(ah + lo.w, 1e-5f, ah + lo.w) + dL, r2 = fmaf(ah, 1e-5f, ah) + dL;
+    return fmaf(g1x, g1x, fmaf(g1y, g1y, g1z * g1z)) < r1 * r1 && fmaf(g2x, g2x, fmaf(g2y, g2y, g2z * g2z)) < r2 * r2;
+}
+
+// Candidate search, in three steps.  (1) k_cand: candidate other super-tiles
+// (64 consecutive sub-tiles) of each owner tile, culled through two levels of
+// binary32 nodes (64 super-tiles per mega-tile).  count mode: cnt[t] = number
+// of candidates; write mode: the flat list of (owner tile, super-tile) pairs,
+// tile t's at off[t]..., in mega, super-tile order.  (2) k_sub_masks: for
+// every pair, the super-tile's sub-tiles that pass the same node check
+// against the owner tile, as a 64-bit mask.  (3) k_expand: the masks' set
+// bits become each tile's candidate sub-tile list (ascending within a pair).
+// Splitting the levels keeps the per-tile work short: one owner tile whose
+// box spans much of the domain no longer holds up a whole launch.
 struct CandArgs {
     int64_t nown_tile, ntile, nsuper, nmega;
     const double* obox; const double* oh;
-    const double* tbox; const double* th;
-    const double* sbox; const double* shh;
-    const double* mbox; const double* mhh;
+    const float4* sq; const float4* mq;   // binary32 nodes (write_node_q): super-, mega-tiles
     double L[3];
     uint32_t* cnt;
     const uint64_t* off;          // candidate offsets can pass 2^32 at Milky-Way sizes
     uint32_t* cand;
+    uint32_t* pad;                // [owner tiles][pad_cap]: the count pass keeps the first pad_cap candidates
+    int pad_cap;
+    uint32_t* maxcnt;             // largest count (count pass)
+    uint32_t* ptile;              // write mode: owner tile of each pair
 };
 
+constexpr int kCandUnroll = 4;     // independent node tests in flight per lane
+
+// Owner tile of block b in a grid of 8 ceil(n / 8) blocks: XCD b % 8 takes a
+// contiguous range of tiles, so neighbouring tiles (which share most of their
+// candidates) meet in one L2.  Returns -1 for the padding blocks.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n)
+{
+    const int64_t per = (n + kXcd - 1) / kXcd;
+    const int64_t t = (b % kXcd) * per + b / kXcd;
+    return t < n ? t : -1;
+}
+
+// The near megas' super-tiles are tested kCandUnroll megas at a time (their
+// node loads overlap).  The count pass also stores the first pad_cap
+// candidates of each tile; the lists stay there when all fit, else the write
+// pass copies the fitting ones and traverses again for the others.
 template <bool WRITE>
 __global__ __launch_bounds__(64) void k_cand(CandArgs a)
 {
-    const int64_t t = blockIdx.x;
+    const int64_t t = xcd_tile(blockIdx.x, a.nown_tile);
+    if (t < 0) return;
     const int lane = lane_id();
-    double A[6];
-    for (int k = 0; k < 6; ++k) A[k] = a.obox[6 * t + k];
-    const double ha = a.oh[t];
+    if (WRITE && a.cnt[t] <= uint32_t(a.pad_cap)) {
+        const uint32_t n = a.cnt[t];
+        const uint32_t* src = a.pad + t * int64_t(a.pad_cap);
+        uint32_t* dst = a.cand + a.off[t];
+        uint32_t* dt = a.ptile + a.off[t];
+        for (uint32_t k = uint32_t(lane); k < n; k += 64) { dst[k] = src[k]; dt[k] = uint32_t(t); }
+        return;
+    }
+    uint32_t* pad = a.pad + t * int64_t(a.pad_cap);
+    const float4 alo = make_float4(__double2float_rd(a.obox[6 * t + 0]), __double2float_rd(a.obox[6 * t + 1]),
+                                   __double2float_rd(a.obox[6 * t + 2]), 0.f);
+    const float4 ahi = make_float4(__double2float_ru(a.obox[6 * t + 3]), __double2float_ru(a.obox[6 * t + 4]),
+                                   __double2float_ru(a.obox[6 * t + 5]), 0.f);
+    const float ah = __double2float_ru(a.oh[t]);
+    const float Lf[3] = {__double2float_ru(a.L[0]), __double2float_ru(a.L[1]), __double2float_ru(a.L[2])};
+    const float dL = 1e-6f * fmaxf(Lf[0], fmaxf(Lf[1], Lf[2]));
     uint32_t count = 0;
     const uint64_t base = WRITE ? a.off[t] : 0ull;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     for (int64_t m0 = 0; m0 < a.nmega; m0 += 64) {
         const int64_t mg = m0 + lane;
-        const bool hm = mg < a.nmega && boxes_near(A, ha, a.mbox + 6 * mg, a.mhh[mg], a.L);
+        const bool hm = mg < a.nmega && node_near(alo, ahi, ah, a.mq + 4 * mg, Lf, dL);
         uint64_t bm = __ballot(hm);
         while (bm) {
-            const int64_t mi = m0 + __ffsll((unsigned long long)bm) - 1;
-            bm &= bm - 1;
-            const int64_t sg = mi * kTile + lane;
-            const bool hs = sg < a.nsuper && boxes_near(A, ha, a.sbox + 6 * sg, a.shh[sg], a.L);
-            uint64_t bs = __ballot(hs);
-            while (bs) {
-                const int64_t si = mi * kTile + __ffsll((unsigned long long)bs) - 1;
-                bs &= bs - 1;
-                const int64_t tt = si * kTile + lane;
-                const bool h2 = tt < a.ntile && boxes_near(A, ha, a.tbox + 6 * tt, a.th[tt], a.L);
-                const uint64_t b2 = __ballot(h2);
-                if (WRITE && h2) a.cand[base + count + uint32_t(__popcll(b2 & lt))] = uint32_t(tt);
-                count += uint32_t(__popcll(b2));
+            int64_t mi[kCandUnroll];
+            bool mv[kCandUnroll];
+#pragma unroll
+            for (int u = 0; u < kCandUnroll; ++u) {
+                mv[u] = bm != 0ull;
+                mi[u] = mv[u] ? m0 + __ffsll((unsigned long long)bm) - 1 : m0;
+                bm &= bm - 1;
+            }
+            bool hit[kCandUnroll];
+            int64_t sg[kCandUnroll];
+            float4 nq[kCandUnroll][4];
+#pragma unroll
+            for (int u = 0; u < kCandUnroll; ++u) {     // loads first, all in flight
+                sg[u] = mi[u] * kTile + lane;
+                const int64_t si = sg[u] < a.nsuper ? sg[u] : 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) nq[u][k] = a.sq[4 * si + k];
+            }
+#pragma unroll
+            for (int u = 0; u < kCandUnroll; ++u)
+                hit[u] = mv[u] && sg[u] < a.nsuper && node_near(alo, ahi, ah, nq[u], Lf, dL);
+#pragma unroll
+            for (int u = 0; u < kCandUnroll; ++u) {
+                const uint64_t b = __ballot(hit[u]);
+                const uint32_t k = count + uint32_t(__popcll(b & lt));
+                if (WRITE && hit[u]) { a.cand[base + k] = uint32_t(sg[u]); a.ptile[base + k] = uint32_t(t); }
+                if (!WRITE && hit[u] && k < uint32_t(a.pad_cap)) pad[k] = uint32_t(sg[u]);
+                count += uint32_t(__popcll(b));
             }
         }
     }
-    if (!WRITE && lane == 0) a.cnt[t] = count;
+    if (!WRITE && lane == 0) {
+        a.cnt[t] = count;
+        // one word shared by every tile: skip the atomic unless it can raise it
+        if (count > __hip_atomic_load(a.maxcnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(a.maxcnt, count);
+    }
 }
 
-// Work items: candidate lists split into pieces of at most `split` tiles.
+struct SubMaskArgs {
+    int64_t npairs, ntile;
+    const uint32_t* ptile; const uint32_t* psup;   // pairs: owner tile, candidate super-tile
+    const double* obox; const double* oh;          // owner tiles
+    const float4* tq;                              // sub-tile nodes (write_node_q layout)
+    double L[3];
+    uint64_t* mask; uint32_t* pcnt;                // per pair
+};
+
+constexpr int kSubPairs = 4;       // pairs per wave, their node loads in flight together
+
+__global__ __launch_bounds__(64) void k_sub_masks(SubMaskArgs a)
+{
+    const int lane = lane_id();
+    const int64_t p0 = int64_t(blockIdx.x) * kSubPairs;
+    const float Lf[3] = {__double2float_ru(a.L[0]), __double2float_ru(a.L[1]), __double2float_ru(a.L[2])};
+    const float dL = 1e-6f * fmaxf(Lf[0], fmaxf(Lf[1], Lf[2]));
+    float4 nq[kSubPairs][4];
+    int64_t st[kSubPairs], tl[kSubPairs];
+#pragma unroll
+    for (int u = 0; u < kSubPairs; ++u) {     // loads first, all in flight
+        const int64_t p = p0 + u < a.npairs ? p0 + u : 0;
+        tl[u] = a.ptile[p];
+        st[u] = int64_t(a.psup[p]) * kTile + lane;
+        const int64_t si = st[u] < a.ntile ? st[u] : 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) nq[u][k] = a.tq[4 * si + k];
+    }
+#pragma unroll
+    for (int u = 0; u < kSubPairs; ++u) {
+        const int64_t t = tl[u];
+        const float4 alo = make_float4(__double2float_rd(a.obox[6 * t + 0]), __double2float_rd(a.obox[6 * t + 1]),
+                                       __double2float_rd(a.obox[6 * t + 2]), 0.f);
+        const float4 ahi = make_float4(__double2float_ru(a.obox[6 * t + 3]), __double2float_ru(a.obox[6 * t + 4]),
+                                       __double2float_ru(a.obox[6 * t + 5]), 0.f);
+        const bool hit = p0 + u < a.npairs && st[u] < a.ntile &&
+                         node_near(alo, ahi, __double2float_ru(a.oh[t]), nq[u], Lf, dL);
+        const uint64_t m = __ballot(hit);
+        if (lane == 0 && p0 + u < a.npairs) {
+            a.mask[p0 + u] = m;
+            a.pcnt[p0 + u] = uint32_t(__popcll(m));
+        }
+    }
+}
+
+// Candidate sub-tiles of pair p at soff[p]... (ascending).
+__global__ __launch_bounds__(256) void k_expand(int64_t npairs, const uint32_t* __restrict__ psup,
+                                                const uint64_t* __restrict__ mask, const uint64_t* __restrict__ soff,
+                                                uint32_t* __restrict__ cand)
+{
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    uint64_t m = mask[p];
+    const uint32_t s0 = psup[p] * uint32_t(kTile);
+    uint32_t* dst = cand + soff[p];
+    for (int k = 0; m; ++k, m &= m - 1) dst[k] = s0 + uint32_t(__ffsll((unsigned long long)m) - 1);
+}
+
+// Per owner tile: its candidate sub-tile count and where its list starts
+// (poff: pair offsets per tile, soff: sub-tile offsets per pair).
+__global__ __launch_bounds__(256) void k_tile_subs(int64_t nt, const uint64_t* __restrict__ poff,
+                                                   const uint64_t* __restrict__ soff, uint32_t* __restrict__ scnt,
+                                                   uint64_t* __restrict__ sbeg)
+{
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t > nt) return;
+    if (t == nt) { scnt[t] = 0u; return; }
+    const uint64_t b = soff[poff[t]], e = soff[poff[t + 1]];
+    sbeg[t] = b;
+    scnt[t] = uint32_t(e - b);
+}
+
+// Work items: candidate lists split into pieces of at most `split` sub-tiles.
 __global__ __launch_bounds__(256) void k_item_count(const uint32_t* __restrict__ cnt, int64_t nt, uint32_t split,
                                                     uint32_t* __restrict__ icnt)
 {
@@ -386,14 +607,15 @@ __global__ __launch_bounds__(256) void k_item_count(const uint32_t* __restrict__
     icnt[t] = t < nt ? (cnt[t] + split - 1) / split : 0u;
 }
 
-__global__ __launch_bounds__(256) void k_item_write(const uint64_t* __restrict__ cand_off,
+// Tile t's list: cnt[t] sub-tiles from beg[t].
+__global__ __launch_bounds__(256) void k_item_write(const uint64_t* __restrict__ beg, const uint32_t* __restrict__ cnt,
                                                     const uint32_t* __restrict__ item_off, int64_t nt, uint32_t split,
                                                     uint32_t* __restrict__ it_tile, uint64_t* __restrict__ it_cb,
                                                     uint64_t* __restrict__ it_ce)
 {
     int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= nt) return;
-    const uint64_t cb = cand_off[t], ce = cand_off[t + 1];
+    const uint64_t cb = beg[t], ce = cb + cnt[t];
     uint32_t it = item_off[t];
     for (uint64_t c = cb; c < ce; c += split, ++it) {
         it_tile[it] = uint32_t(t);
@@ -641,7 +863,6 @@ struct TestLds {
     double px[64], py[64], pz[64], ph[64];   // slot particles: shifted position and h
     uint32_t pq[64];              // slot -> sorted index of the other particle
     int pclean[64];               // slot's sub-tile is clean
-    float4 pf[64];                // slot offsets from the owner-tile centre and h (binary32)
     uint64_t mask[64];            // per owner lane: hit mask over the group's slots
     int offs[65];                 // owner-major offsets of the group's hits
 };
@@ -822,7 +1043,6 @@ __device__ __forceinline__ int test_next(PairTest& T, TestLds& S, const PassGeom
         S.pq[s] = uint32_t(q);
         S.pclean[s] = cl;
         const float qx = float(X - cen[0]), qy = float(Y - cen[1]), qz = float(Z - cen[2]), qh = float(Hh);
-        S.pf[s] = make_float4(qx, qy, qz, qh);
         const float p2 = qx * qx + qy * qy + qz * qz, h2 = qh * qh;
         c[0] = -2.f * qx; c[1] = -2.f * qy; c[2] = -2.f * qz; c[3] = -2.f * qh;
         c[5] = (p2 - h2) - kTestSlack * (p2 + h2);
@@ -865,7 +1085,8 @@ __device__ __forceinline__ int test_next(PairTest& T, TestLds& S, const PassGeom
         const float mx2 = -2.f * fx, my2 = -2.f * fy, mz2 = -2.f * fz, mh2 = -2.f * fh;
 #pragma unroll 1
         for (int t = 0; t < ns; ++t) {
-            const float4 q = S.pf[t];
+            const float4 q = make_float4(float(S.px[t] - cen[0]), float(S.py[t] - cen[1]), float(S.pz[t] - cen[2]),
+                                         float(S.ph[t]));
             bool hit;
             if (S.pclean[t]) {
                 const float p2 = q.x * q.x + q.y * q.y + q.z * q.z, h2 = q.w * q.w;
@@ -1456,7 +1677,7 @@ __global__ __launch_bounds__(256) void k_combine_dm(DmCombineArgs a)
 // with more pairs than the cache recompute their pairs in every pass.
 struct ResolveArgs {
     PassGeom g;                   // owners = DM, others = gas sub-tiles (as in the DM pass)
-    const uint64_t* cand_off;     // [nown_tile + 1]
+    const uint64_t* cand_beg; const uint32_t* cand_cnt;   // each owner tile's candidate list
     const double* vx; const double* vy; const double* vz; const void* dtr; const uint32_t* dm_perm;
     const double* Vx; const double* Vy; const double* Vz; const void* vs; const void* K; const uint32_t* gas_perm;
     const double* gas_vel; const double* gas_u; const double* gas_mu;   // raw gas inputs (partner kick)
@@ -1515,38 +1736,54 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
         const unsigned __int128 Ufix = (unsigned __int128)(2ull * (rd.x >> 8) + 1ull) << 39;
         double A[6];
         for (int k = 0; k < 6; ++k) A[k] = G.obox[6 * t + k];
-        const uint64_t cb = a.cand_off[t], ce = a.cand_off[t + 1];
+        const uint64_t cb = a.cand_beg[t], ce = cb + a.cand_cnt[t];
         if (tid == 0) { s_nrel = 0; s_npairs = 0; }
         __syncthreads();
-        // candidate sub-tiles this DM can reach (point-to-box gap < h_i + h_max)
+        // candidate sub-tiles this DM can reach (point-to-box gap < h_i + max h of the sub-tile)
         const double P6[6] = {mx, my, mz, mx, my, mz};
         for (uint64_t c = cb + tid; c < ce; c += kResolveThreads) {
             const uint32_t ot = G.cand[c];
-            if (boxes_near(P6, mh, G.tbox + 6 * int64_t(ot), G.th[ot], G.L)) {
+            if (boxes_near(P6, mh, G.tbox + 6 * int64_t(ot), G.thmax[ot], G.L)) {
                 const uint32_t pos = atomicAdd(&s_nrel, 1u);
-                if (pos < uint32_t(kResolveList)) s_list[pos] = uint32_t(c - cb);   // offset in the tile's list
+                if (pos < uint32_t(kResolveList)) s_list[pos] = ot;
             }
         }
         __syncthreads();
         const uint32_t nrel = s_nrel;
         const bool use_list = nrel <= uint32_t(kResolveList);
         const uint32_t nl = use_list ? nrel : uint32_t(ce - cb);
-        // prefix sums of particle counts over the kept sub-tiles (one thread; nl <= kResolveList)
-        if (tid == 0 && use_list) {
-            uint32_t acc = 0;
-            for (uint32_t q = 0; q < nl; ++q) {
-                s_pre[q] = acc;
-                acc += G.sub_cnt[G.cand[cb + s_list[q]]];
+        // prefix sums of particle counts over the kept sub-tiles (nl <= kResolveList):
+        // counts loaded in parallel, each thread sums a contiguous run, the
+        // run totals are scanned in LDS
+        if (use_list) {
+            for (uint32_t q = tid; q < nl; q += kResolveThreads) s_pre[q] = G.sub_cnt[s_list[q]];
+            __syncthreads();
+            const uint32_t per = (nl + kResolveThreads - 1) / kResolveThreads;
+            const uint32_t q0 = min(nl, uint32_t(tid) * per), q1 = min(nl, q0 + per);
+            uint32_t run = 0;
+            for (uint32_t q = q0; q < q1; ++q) run += s_pre[q];
+            hhi[tid] = run;
+            __syncthreads();
+            for (int d = 1; d < kResolveThreads; d <<= 1) {
+                const unsigned long long y = tid >= d ? hhi[tid - d] : 0ull;
+                __syncthreads();
+                hhi[tid] += y;
+                __syncthreads();
             }
-            s_pre[nl] = acc;
+            uint32_t acc = uint32_t(hhi[tid]) - run;
+            for (uint32_t q = q0; q < q1; ++q) {
+                const uint32_t v = s_pre[q];
+                s_pre[q] = acc;
+                acc += v;
+            }
+            if (tid == kResolveThreads - 1) s_pre[nl] = uint32_t(hhi[tid]);
         }
         __syncthreads();
         // Pairs of this DM, enumerated over the flattened particles of the kept
         // sub-tiles (four wavefronts in parallel).  Without a list (too many
         // candidates) every candidate sub-tile is walked by one wavefront.
         auto for_pairs = [&](auto&& fn) {
-            auto visit = [&](uint32_t lc, int kk) {
-                const uint32_t ot = G.cand[cb + lc];
+            auto visit = [&](uint32_t ot, int kk) {
                 double sh[3];
                 bool clean;
                 tile_pair_shift(A, G.tbox + 6 * int64_t(ot), G.L, sh, &clean);
@@ -1577,7 +1814,7 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
                 }
             } else {
                 const int w = tid >> 6, lane = tid & 63;
-                for (uint32_t q = w; q < nl; q += kResolveThreads / 64) visit(q, lane);
+                for (uint32_t q = w; q < nl; q += kResolveThreads / 64) visit(G.cand[cb + q], lane);
             }
         };
         for_pairs([&](uint32_t gid, double P) {
