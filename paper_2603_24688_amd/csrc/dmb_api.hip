@@ -423,8 +423,8 @@ dmb_status cand_write(dmb_ctx* c, Species& A, Species& B, Pairs& P)
     hipLaunchKernelGGL(k_expand, dim3(blocks_for(P.npairs, 256)), dim3(256), 0, c->stream, P.npairs,
                        P.psup.as<const uint32_t>(), P.mask.as<const uint64_t>(), P.soff.as<const uint64_t>(),
                        P.cand.as<uint32_t>());
-    hipLaunchKernelGGL(k_item_write, dim3(blocks_for(nt, 256)), dim3(256), 0, c->stream, P.beg.as<const uint64_t>(),
-                       P.scnt.as<const uint32_t>(), P.ioff.as<const uint32_t>(), nt, uint32_t(c->split),
+    hipLaunchKernelGGL(k_item_write, dim3(blocks_for(P.nitems, 256)), dim3(256), 0, c->stream, P.beg.as<const uint64_t>(),
+                       P.scnt.as<const uint32_t>(), P.ioff.as<const uint32_t>(), nt, P.nitems, uint32_t(c->split),
                        P.it_tile.as<uint32_t>(), P.it_cb.as<uint64_t>(), P.it_ce.as<uint64_t>());
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
@@ -612,7 +612,8 @@ void combine_gas(dmb_ctx* c, Cells& X, const dmb_particles* gas, const dmb_param
     cb.item_off = X.gp.ioff.as<const uint32_t>(); cb.part = X.part_gas.as<const double>();
     cb.mass = gas->mass; cb.mu = gas->mu; cb.dt = gas->dt; cb.dt_default = par->dt; cb.m_chi = par->m_chi_g;
     cb.sig_kpc2_cn = sig_kpc2_cn_of(par); cb.dp = out->dp_gas; cb.de = out->de_gas;
-    hipLaunchKernelGGL(k_combine_gas, dim3(blocks_for(G.n_own, 256)), dim3(256), 0, c->stream, cb);
+    hipLaunchKernelGGL(k_combine_gas, dim3(unsigned((G.n_own + kTile - 1) / kTile)), dim3(64 * kCombineWaves), 0,
+                       c->stream, cb);
 }
 
 DmPassArgs dm_pass_args(dmb_ctx* c, Cells& X, const dmb_params* par, dmb_out* out, uint64_t* counters,
@@ -652,7 +653,8 @@ void combine_dm_and_resolve(dmb_ctx* c, Cells& X, const DmPassArgs& a, const dmb
     cb.scount = a.scount; cb.slist = X.slist.as<uint32_t>(); cb.counters = counters;
     {
         Phase ph(c, DMB_PH_COMBINE_DM);
-        hipLaunchKernelGGL(k_combine_dm, dim3(blocks_for(D.n_own, 256)), dim3(256), 0, c->stream, cb);
+        hipLaunchKernelGGL(k_combine_dm, dim3(unsigned((D.n_own + kTile - 1) / kTile)), dim3(64 * kCombineWaves), 0,
+                           c->stream, cb);
     }
     ResolveArgs r;
     r.g = a.g;

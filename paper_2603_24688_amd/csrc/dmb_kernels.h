@@ -607,21 +607,24 @@ __global__ __launch_bounds__(256) void k_item_count(const uint32_t* __restrict__
     icnt[t] = t < nt ? (cnt[t] + split - 1) / split : 0u;
 }
 
-// Tile t's list: cnt[t] sub-tiles from beg[t].
+// Item it: its tile t (binary search over item_off), and the piece of t's
+// list (cnt[t] sub-tiles from beg[t]) it covers.
 __global__ __launch_bounds__(256) void k_item_write(const uint64_t* __restrict__ beg, const uint32_t* __restrict__ cnt,
-                                                    const uint32_t* __restrict__ item_off, int64_t nt, uint32_t split,
-                                                    uint32_t* __restrict__ it_tile, uint64_t* __restrict__ it_cb,
-                                                    uint64_t* __restrict__ it_ce)
+                                                    const uint32_t* __restrict__ item_off, int64_t nt, int64_t nitems,
+                                                    uint32_t split, uint32_t* __restrict__ it_tile,
+                                                    uint64_t* __restrict__ it_cb, uint64_t* __restrict__ it_ce)
 {
-    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= nt) return;
-    const uint64_t cb = beg[t], ce = cb + cnt[t];
-    uint32_t it = item_off[t];
-    for (uint64_t c = cb; c < ce; c += split, ++it) {
-        it_tile[it] = uint32_t(t);
-        it_cb[it] = c;
-        it_ce[it] = min(ce, c + uint64_t(split));
+    const int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (it >= nitems) return;
+    int64_t lo = 0, hi = nt;      // largest t with item_off[t] <= it
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (int64_t(item_off[mid]) <= it) lo = mid; else hi = mid;
     }
+    const uint64_t cb = beg[lo] + uint64_t(it - int64_t(item_off[lo])) * split, ce = beg[lo] + cnt[lo];
+    it_tile[it] = uint32_t(lo);
+    it_cb[it] = cb;
+    it_ce[it] = min(ce, cb + uint64_t(split));
 }
 
 // ---------------------------------------------------------------------------
@@ -1601,16 +1604,30 @@ struct GasCombineArgs {
     double* dp; double* de;
 };
 
-__global__ __launch_bounds__(256) void k_combine_gas(GasCombineArgs a)
+// One block per owner tile with several items; wave w sums the tile's items
+// w, w + kCombineWaves, ... (lane = owner slot) and the wave sums are added in
+// wave order, so the result does not depend on scheduling.
+constexpr int kCombineWaves = 8;
+
+__global__ __launch_bounds__(64 * kCombineWaves) void k_combine_gas(GasCombineArgs a)
 {
-    int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= a.n_own) return;
-    int64_t t = s / kTile, l = s % kTile;
+    __shared__ double s_acc[kCombineWaves][64][4];
+    const int64_t t = blockIdx.x;
     const uint32_t i0 = a.item_off[t], i1 = a.item_off[t + 1];
     if (i1 - i0 <= 1u) return;
+    const int w = int(threadIdx.x) >> 6, l = lane_id();
     double acc[4] = {0, 0, 0, 0};
-    for (uint32_t it = i0; it < i1; ++it)
-        for (int c = 0; c < 4; ++c) acc[c] += a.part[(int64_t(it) * kTile + l) * 4 + c];
+#pragma unroll 4
+    for (uint32_t it = i0 + uint32_t(w); it < i1; it += kCombineWaves) {
+        const double* P = a.part + (int64_t(it) * kTile + l) * 4;
+        for (int c = 0; c < 4; ++c) acc[c] += P[c];
+    }
+    for (int c = 0; c < 4; ++c) s_acc[w][l][c] = acc[c];
+    __syncthreads();
+    const int64_t s = t * kTile + l;
+    if (w != 0 || s >= a.n_own) return;
+    for (int v = 1; v < kCombineWaves; ++v)
+        for (int c = 0; c < 4; ++c) acc[c] += s_acc[v][l][c];
     uint32_t o = a.perm[a.own[s]];
     double mu = a.mu ? a.mu[o] : kMpG;
     double dtj = a.dt ? a.dt[o] : a.dt_default;
@@ -1634,29 +1651,41 @@ struct DmCombineArgs {
     uint64_t* counters;
 };
 
-__global__ __launch_bounds__(256) void k_combine_dm(DmCombineArgs a)
+__global__ __launch_bounds__(64 * kCombineWaves) void k_combine_dm(DmCombineArgs a)
 {
-    int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    uint32_t f = 0, nb = 0;
+    __shared__ double s_p[kCombineWaves][64];
+    __shared__ float s_m[kCombineWaves][64];
+    __shared__ uint32_t s_nb[kCombineWaves][64];
+    const int64_t t = blockIdx.x;
+    const uint32_t i0 = a.item_off[t], i1 = a.item_off[t + 1];
+    if (i1 - i0 <= 1u) return;
+    const int w = int(threadIdx.x) >> 6, l = lane_id();
+    double P = 0.0;
+    float Pm = 0.f;
+    uint32_t nb = 0;
+#pragma unroll 4
+    for (uint32_t it = i0 + uint32_t(w); it < i1; it += kCombineWaves) {
+        P += a.part_p[int64_t(it) * kTile + l];
+        Pm = fmaxf(Pm, a.part_pm[int64_t(it) * kTile + l]);
+        nb |= a.part_nb[int64_t(it) * kTile + l];
+    }
+    s_p[w][l] = P; s_m[w][l] = Pm; s_nb[w][l] = nb;
+    __syncthreads();
+    if (w != 0) return;
+    const int64_t s = t * kTile + l;
+    uint32_t f = 0;
+    nb = 0;
     if (s < a.n_own) {
-        int64_t t = s / kTile, l = s % kTile;
-        const uint32_t i0 = a.item_off[t], i1 = a.item_off[t + 1];
-        if (i1 - i0 > 1u) {
-            double P = 0.0;
-            float Pm = 0.f;
-            for (uint32_t it = i0; it < i1; ++it) {
-                P += a.part_p[int64_t(it) * kTile + l];
-                Pm = fmaxf(Pm, a.part_pm[int64_t(it) * kTile + l]);
-                nb |= a.part_nb[int64_t(it) * kTile + l];
-            }
-            uint32_t o = a.perm[a.own[s]];
-            f = dm_decide(o, s, P, Pm, a.step + (a.step_off ? *a.step_off : 0u), a.box, a.k0, a.k1, a.psum_own,
-                          a.psum, a.pmax, a.scount, a.slist);
-        }
+        P = 0.0;
+        Pm = 0.f;
+        for (int v = 0; v < kCombineWaves; ++v) { P += s_p[v][l]; Pm = fmaxf(Pm, s_m[v][l]); nb |= s_nb[v][l]; }
+        uint32_t o = a.perm[a.own[s]];
+        f = dm_decide(o, s, P, Pm, a.step + (a.step_off ? *a.step_off : 0u), a.box, a.k0, a.k1, a.psum_own, a.psum,
+                      a.pmax, a.scount, a.slist);
     }
     uint64_t b0 = __ballot(f & 1u), b1 = __ballot(f & 2u), b2 = __ballot(f & 4u), b3 = __ballot(f & 8u);
     uint64_t b4 = __ballot(nb != 0);
-    if (lane_id() == 0) {
+    if (l == 0) {
         if (b0) atomicAdd((unsigned long long*)&a.counters[2], (unsigned long long)__popcll(b0));
         if (b4) atomicAdd((unsigned long long*)&a.counters[3], (unsigned long long)__popcll(b4));
         if (b3) atomicAdd((unsigned long long*)&a.counters[4], (unsigned long long)__popcll(b3));
