@@ -1733,7 +1733,7 @@ __device__ __forceinline__ void fixed_split(double P, unsigned long long* hi, un
 
 constexpr int kResolveThreads = 256;  // four wavefronts per scattering DM
 constexpr int kResolveList = 2048;    // candidate sub-tiles kept per scattering DM after the point test
-constexpr int kResolvePairs = 2048;   // pairs cached per scattering DM
+constexpr int kResolvePairs = 8192;   // pairs cached per scattering DM (LDS)
 
 template <typename Real, int N, bool EXACT_G>
 __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
@@ -1744,7 +1744,9 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
     __shared__ uint32_t s_gid[kResolvePairs];
     __shared__ double s_P[kResolvePairs];
     __shared__ uint32_t s_nrel, s_npairs, s_sel;
-    __shared__ int s_near;
+    __shared__ int s_near, s_found, s_lastnz;
+    __shared__ unsigned __int128 s_cum[256], s_selb, s_sela;
+    static_assert(kResolveThreads == 256, "one thread per histogram bin");
     const PassGeom& G = a.g;
     const int tid = threadIdx.x;
     const uint32_t step = a.step + (a.step_off ? *a.step_off : 0u);
@@ -1875,30 +1877,39 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
             } else {
                 for_pairs(add);
             }
+            // the selected bin: the first whose running sum (from `below`) passes
+            // U_i, by an inclusive scan over the 256 bins (thread = bin)
+            if (tid == 0) { s_found = 0; s_lastnz = -1; }
             __syncthreads();
-            if (tid == 0) {
-                unsigned __int128 cum = below;
-                int sel = -1, last_nz = -1;
-                unsigned __int128 sel_below = below, sel_after = below;
-                for (int b = 0; b < 256; ++b) {
-                    unsigned __int128 v = ((unsigned __int128)hhi[b] << 32) + (unsigned __int128)hlo[b];
-                    if (v != 0) last_nz = b;
-                    unsigned __int128 nx = cum + v;
-                    if (sel < 0 && nx > Ufix) { sel = b; sel_below = cum; sel_after = nx; }
-                    cum = nx;
-                }
-                if (sel < 0) {  // rounding guard: keep the largest index with P > 0
-                    sel = last_nz < 0 ? 0 : last_nz;
-                    sel_below = below;
-                    sel_after = cum;
-                }
-                below = sel_below;
-                s_sel = uint32_t(sel);
-                if (ps == npass - 1) {
-                    // running sums adjacent to U_i (relative 1e-6 band)
-                    double Ud = double(Ufix) * 0x1p-64, Sb = double(sel_below) * 0x1p-64, Sa = double(sel_after) * 0x1p-64;
-                    s_near = (fabs(Sb - Ud) <= 1e-6 * Ud || fabs(Sa - Ud) <= 1e-6 * Ud) ? 1 : 0;
-                }
+            const unsigned __int128 v = ((unsigned __int128)hhi[tid] << 32) + (unsigned __int128)hlo[tid];
+            s_cum[tid] = v;
+            if (v != 0) atomicMax(&s_lastnz, tid);
+            __syncthreads();
+            for (int d = 1; d < 256; d <<= 1) {
+                const unsigned __int128 y = tid >= d ? s_cum[tid - d] : (unsigned __int128)0;
+                __syncthreads();
+                s_cum[tid] += y;
+                __syncthreads();
+            }
+            const unsigned __int128 incl = below + s_cum[tid], excl = incl - v;
+            if (excl <= Ufix && incl > Ufix) {      // unique: running sums increase, empty bins cannot pass
+                s_found = 1;
+                s_sel = uint32_t(tid);
+                s_selb = excl;
+                s_sela = incl;
+            }
+            __syncthreads();
+            if (tid == 0 && !s_found) {   // rounding guard: keep the largest index with P > 0
+                s_sel = uint32_t(s_lastnz < 0 ? 0 : s_lastnz);
+                s_selb = below;
+                s_sela = below + s_cum[255];
+            }
+            __syncthreads();
+            below = s_selb;
+            if (tid == 0 && ps == npass - 1) {
+                // running sums adjacent to U_i (relative 1e-6 band)
+                double Ud = double(Ufix) * 0x1p-64, Sb = double(s_selb) * 0x1p-64, Sa = double(s_sela) * 0x1p-64;
+                s_near = (fabs(Sb - Ud) <= 1e-6 * Ud || fabs(Sa - Ud) <= 1e-6 * Ud) ? 1 : 0;
             }
             __syncthreads();
             prefix = (prefix << 8) | s_sel;
