@@ -40,6 +40,7 @@ struct Species {
     // per-step gathers (sorted order)
     DevBuf v0, v1, v2;                     // velocity components (double)
     DevBuf r0, r1, r2, r3, r4, r5, r6;     // Real-typed per-particle factors
+    DevBuf rec;                            // per-pair records of this species as the other one (GasRec / DmRec)
     const uint32_t* perm = nullptr;        // = vals after the sort
 };
 
@@ -536,8 +537,9 @@ dmb_status gather_and_fill(dmb_ctx* c, Cells& X, const dmb_particles* gas, const
         ga.m_chi = par->m_chi_g; ga.sig_kpc2_cn = sig_kpc2_cn_of(par); ga.alpha_n = alpha_n(par->n_pow);
         ga.n_pow = par->n_pow;
         ga.Vx = G.v0.as<double>(); ga.Vy = G.v1.as<double>(); ga.Vz = G.v2.as<double>();
-        ga.vs = G.r0.p; ga.inv2s2 = G.r1.p; ga.ra = G.r2.p; ga.rb = G.r3.p; ga.rr = G.r4.p; ga.K = G.r5.p;
-        ga.crit = G.r6.p;
+        ga.inv2s2 = G.r1.p; ga.ra = G.r2.p; ga.rb = G.r3.p; ga.rr = G.r4.p;
+        ENSURE(c, G.rec, G.n * (sizeof(Real) == 4 ? sizeof(GasRec<float>) : sizeof(GasRec<double>)));
+        ga.rec = G.rec.p;
         hipLaunchKernelGGL(k_gather_gas<Real>, dim3(blocks_for(G.n, 256)), dim3(256), 0, c->stream, ga);
     }
     if (D.n > 0) {
@@ -547,7 +549,9 @@ dmb_status gather_and_fill(dmb_ctx* c, Cells& X, const dmb_particles* gas, const
         da.n = D.n; da.perm = D.perm; da.vel = dm->vel; da.mass = dm->mass; da.dt = dm->dt;
         da.dt_default = par->dt;
         da.vx = D.v0.as<double>(); da.vy = D.v1.as<double>(); da.vz = D.v2.as<double>();
-        da.m = D.r0.p; da.dtr = D.r1.p;
+        da.dtr = D.r1.p;
+        ENSURE(c, D.rec, D.n * (sizeof(Real) == 4 ? sizeof(DmRec<float>) : sizeof(DmRec<double>)));
+        da.rec = D.rec.p;
         hipLaunchKernelGGL(k_gather_dm<Real>, dim3(blocks_for(D.n, 256)), dim3(256), 0, c->stream, da);
     }
     ENSURE(c, X.qctr, (2 * kXcd + 4) * 4);
@@ -577,8 +581,7 @@ GasPassArgs gas_pass_args(dmb_ctx* c, Cells& X, const dmb_particles* gas, const 
     a.g = geom(X, G, D, X.gp, counters);
     a.Vx = G.v0.as<const double>(); a.Vy = G.v1.as<const double>(); a.Vz = G.v2.as<const double>();
     a.inv2s2 = G.r1.p; a.ra = G.r2.p; a.rb = G.r3.p; a.rr = G.r4.p;
-    a.dvx = D.v0.as<const double>(); a.dvy = D.v1.as<const double>(); a.dvz = D.v2.as<const double>();
-    a.dm_m = D.r0.p;
+    a.drec = D.rec.p;
     a.gtab = c->gtab.as<const float4>();
     const DevBuf& glb = sizeof(Real) == 8 ? c->gl64 : c->gl32;
     a.gl_x = glb.p;
@@ -627,7 +630,7 @@ DmPassArgs dm_pass_args(dmb_ctx* c, Cells& X, const dmb_params* par, dmb_out* ou
     a.vx = D.v0.as<const double>(); a.vy = D.v1.as<const double>(); a.vz = D.v2.as<const double>();
     a.dtr = D.r1.p; a.dm_perm = D.perm;
     a.Vx = G.v0.as<const double>(); a.Vy = G.v1.as<const double>(); a.Vz = G.v2.as<const double>();
-    a.vs = G.r0.p; a.K = G.r5.p; a.crit = G.r6.p; a.gas_perm = G.perm;
+    a.grec = G.rec.p;
     a.gtab = c->gtab.as<const float4>();
     a.k0 = uint32_t(par->seed); a.k1 = uint32_t(par->seed >> 32); a.step = par->step; a.box = par->box_id;
     a.step_off = step_off;
@@ -660,7 +663,7 @@ void combine_dm_and_resolve(dmb_ctx* c, Cells& X, const DmPassArgs& a, const dmb
     r.g = a.g;
     r.cand_beg = X.dp.beg.as<const uint64_t>(); r.cand_cnt = X.dp.scnt.as<const uint32_t>();
     r.vx = a.vx; r.vy = a.vy; r.vz = a.vz; r.dtr = a.dtr; r.dm_perm = a.dm_perm;
-    r.Vx = a.Vx; r.Vy = a.Vy; r.Vz = a.Vz; r.vs = a.vs; r.K = a.K; r.gas_perm = a.gas_perm;
+    r.grec = a.grec;
     r.gas_vel = gas->vel; r.gas_u = gas->u; r.gas_mu = gas->mu; r.m_chi = par->m_chi_g;
     r.gtab = a.gtab; r.k0 = a.k0; r.k1 = a.k1; r.step = a.step; r.box = a.box; r.step_off = a.step_off;
     r.n_gas_bits = bits_for(std::max<int64_t>(G.n, 2));
@@ -755,10 +758,12 @@ dmb_status batch_prepare(dmb_ctx* c, int nbox, const dmb_particles* gas, const d
             ENSURE(c, G.v0, G.n * 8); ENSURE(c, G.v1, G.n * 8); ENSURE(c, G.v2, G.n * 8);
             DevBuf* rb[7] = {&G.r0, &G.r1, &G.r2, &G.r3, &G.r4, &G.r5, &G.r6};
             for (DevBuf* bb : rb) ENSURE(c, *bb, G.n * rs);
+            ENSURE(c, G.rec, G.n * (sizeof(Real) == 4 ? sizeof(GasRec<float>) : sizeof(GasRec<double>)));
         }
         if (D.n > 0) {
             ENSURE(c, D.v0, D.n * 8); ENSURE(c, D.v1, D.n * 8); ENSURE(c, D.v2, D.n * 8);
             ENSURE(c, D.r0, D.n * rs); ENSURE(c, D.r1, D.n * rs);
+            ENSURE(c, D.rec, D.n * (sizeof(Real) == 4 ? sizeof(DmRec<float>) : sizeof(DmRec<double>)));
         }
         uint64_t* counters = out[b].counters;
         P.ga[b] = gas_pass_args<Real, N, RM>(c, X, gas + b, par + b, out + b, counters);
@@ -1026,7 +1031,7 @@ void free_cells(Cells& X)
         DevBuf* all[] = {&S->keys, &S->keys2, &S->vals, &S->vals2, &S->sx, &S->sy, &S->sz, &S->sh, &S->flag,
                          &S->flag_off, &S->own, &S->tbox, &S->th, &S->sbox, &S->shh, &S->mbox, &S->mhh, &S->obox,
                          &S->oh, &S->cube, &S->v0, &S->v1, &S->v2, &S->r0, &S->r1, &S->r2, &S->r3, &S->r4, &S->r5,
-                         &S->r6, &S->sub_ccnt, &S->sub_coff, &S->sub_start, &S->sub_cnt, &S->tsup, &S->ssup,
+                         &S->r6, &S->rec, &S->sub_ccnt, &S->sub_coff, &S->sub_start, &S->sub_cnt, &S->tsup, &S->ssup,
                          &S->msup, &S->tq, &S->sq, &S->mq};
         for (DevBuf* b : all) fr(*b);
     }

@@ -124,7 +124,10 @@ __device__ __forceinline__ T overlap_g_table(const float4* __restrict__ tab, T d
     // FMA rate as binary32 on gfx950 vector ALUs) so that the result carries
     // only the node rounding (~1e-7 of the peak), not float arithmetic error.
     double hb = double(hi > hj ? hi : hj), hs = double(hi > hj ? hj : hi);
-    double ib = 1.0 / hb;
+    // 1/hb: binary32 reciprocal and one Newton step in binary64 (relative
+    // error ~1e-14, far below the node rounding; no binary64 division)
+    double ib = double(__builtin_amdgcn_rcpf(float(hb)));
+    ib = ib * fma(-hb, ib, 2.0);
     double fd = double(d) * ib * (kTabND * 0.5), fe = hs * ib * double(kTabNE);
     int i = min(int(fd), kTabND - 1), j = min(int(fe), kTabNE - 1);
     double a = fd - double(i), b = fe - double(j);
@@ -157,6 +160,9 @@ struct U4 { uint32_t x, y, z, w; };
 
 __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
 {
+    // the key schedule is rebuilt per call (scalar adds): hoisted, its 20 words
+    // would occupy scalar registers for a whole pass.  Keys are wave-uniform.
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);

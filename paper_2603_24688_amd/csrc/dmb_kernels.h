@@ -88,18 +88,23 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const double* __restrict__
     }
 }
 
-// cube[0..2] = origin, cube[3] = 2^21 / side (quantisation scale).
-__global__ void k_bbox_final(const double* __restrict__ part, int nparts, const double* __restrict__ boxL,
-                             double* __restrict__ cube)
+// cube[0..2] = origin, cube[3] = 2^21 / side (quantisation scale).  One wave.
+__global__ __launch_bounds__(64) void k_bbox_final(const double* __restrict__ part, int nparts,
+                                                   const double* __restrict__ boxL, double* __restrict__ cube)
 {
-    if (threadIdx.x != 0) return;
     double lo[3], hi[3];
     for (int a = 0; a < 3; ++a) { lo[a] = 1e300; hi[a] = -1e300; }
-    for (int k = 0; k < nparts; ++k)
+    for (int k = lane_id(); k < nparts; k += 64)
         for (int a = 0; a < 3; ++a) {
             lo[a] = fmin(lo[a], part[6 * k + a]);
             hi[a] = fmax(hi[a], part[6 * k + 3 + a]);
         }
+    for (int a = 0; a < 3; ++a)
+        for (int d = 32; d >= 1; d >>= 1) {
+            lo[a] = fmin(lo[a], __shfl_xor(lo[a], d));
+            hi[a] = fmax(hi[a], __shfl_xor(hi[a], d));
+        }
+    if (lane_id() != 0) return;
     bool periodic = boxL[0] > 0.0;
     double side = 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -629,6 +634,19 @@ __global__ __launch_bounds__(256) void k_item_write(const uint64_t* __restrict__
 
 // ---------------------------------------------------------------------------
 // Per-step gathers into sorted order.
+// Per-pair data of the other species of a pass, one 16-byte-aligned record
+// per sorted particle, so that a pair's reads are a few wide loads from one
+// base pointer.
+template <typename Real> struct alignas(16) GasRec {   // gas, read by the DM pass and the resolve
+    double Vx, Vy, Vz;            // velocity
+    Real vs, K, crit;             // sqrt(2 u / 3), K_j, P threshold
+    uint32_t perm;                // sorted position -> gas index
+};
+template <typename Real> struct alignas(16) DmRec {    // DM, read by the gas pass
+    double vx, vy, vz;            // velocity
+    Real m;                       // mass
+};
+
 struct GasGatherArgs {
     int64_t n;
     const uint32_t* perm;
@@ -636,7 +654,8 @@ struct GasGatherArgs {
     double m_chi, sig_kpc2_cn, alpha_n;
     int n_pow;
     double* Vx; double* Vy; double* Vz;
-    void* vs; void* inv2s2; void* ra; void* rb; void* rr; void* K; void* crit;
+    void* inv2s2; void* ra; void* rb; void* rr;             // owner factors (Real)
+    void* rec;                    // GasRec<Real>[n]
 };
 
 template <typename Real>
@@ -666,13 +685,15 @@ __global__ __launch_bounds__(256) void k_gather_gas(GasGatherArgs a)
     double mu = a.mu ? a.mu[o] : kMpG;
     Real vs, i2, ra, rb, rr, cr;
     gas_derived<Real>(a.u[o], mu, a.m_chi, a.alpha_n, a.n_pow, &vs, &i2, &ra, &rb, &rr, &cr);
-    reinterpret_cast<Real*>(a.vs)[k] = vs;
     reinterpret_cast<Real*>(a.inv2s2)[k] = i2;
     reinterpret_cast<Real*>(a.ra)[k] = ra;
     reinterpret_cast<Real*>(a.rb)[k] = rb;
     reinterpret_cast<Real*>(a.rr)[k] = rr;
-    reinterpret_cast<Real*>(a.crit)[k] = cr;
-    reinterpret_cast<Real*>(a.K)[k] = Real(a.mass[o] * kMsunG / mu * a.sig_kpc2_cn);
+    const Real K = Real(a.mass[o] * kMsunG / mu * a.sig_kpc2_cn);
+    GasRec<Real> r;
+    r.Vx = a.vel[3 * int64_t(o)]; r.Vy = a.vel[3 * int64_t(o) + 1]; r.Vz = a.vel[3 * int64_t(o) + 2];
+    r.vs = vs; r.K = K; r.crit = cr; r.perm = o;
+    reinterpret_cast<GasRec<Real>*>(a.rec)[k] = r;
 }
 
 struct DmGatherArgs {
@@ -681,7 +702,8 @@ struct DmGatherArgs {
     const double* vel; const double* mass; const double* dt;
     double dt_default;
     double* vx; double* vy; double* vz;
-    void* m; void* dtr;
+    void* dtr;
+    void* rec;                    // DmRec<Real>[n]
 };
 
 template <typename Real>
@@ -693,8 +715,11 @@ __global__ __launch_bounds__(256) void k_gather_dm(DmGatherArgs a)
     a.vx[k] = a.vel[3 * int64_t(o)];
     a.vy[k] = a.vel[3 * int64_t(o) + 1];
     a.vz[k] = a.vel[3 * int64_t(o) + 2];
-    reinterpret_cast<Real*>(a.m)[k] = Real(a.mass[o]);
     reinterpret_cast<Real*>(a.dtr)[k] = Real(a.dt ? a.dt[o] : a.dt_default);
+    DmRec<Real> r;
+    r.vx = a.vel[3 * int64_t(o)]; r.vy = a.vel[3 * int64_t(o) + 1]; r.vz = a.vel[3 * int64_t(o) + 2];
+    r.m = Real(a.mass[o]);
+    reinterpret_cast<DmRec<Real>*>(a.rec)[k] = r;
 }
 
 __global__ __launch_bounds__(256) void k_fill_out(int64_t n_gas, int64_t n_dm, double* dp, double* de, double* dv,
@@ -1144,8 +1169,7 @@ struct GasPassArgs {
     PassGeom g;
     const double* Vx; const double* Vy; const double* Vz;     // gas, sorted
     const void* inv2s2; const void* ra; const void* rb; const void* rr;
-    const double* dvx; const double* dvy; const double* dvz;  // DM velocities, sorted
-    const void* dm_m;
+    const void* drec;             // DmRec<Real>, sorted DM (velocity, mass)
     const float4* gtab;
     const void* gl_x; const void* gl_w; int gl_k; double inv_alpha;   // quadrature rates (Real)
     double gl_hw, gl_bmin;        // quadrature window
@@ -1229,7 +1253,6 @@ void k_pass_gas(
         const Real* ra = reinterpret_cast<const Real*>(a.ra);
         const Real* rb = reinterpret_cast<const Real*>(a.rb);
         const Real* rr = reinterpret_cast<const Real*>(a.rr);
-        const Real* dm_m = reinterpret_cast<const Real*>(a.dm_m);
         const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
         const int64_t t = G.it_tile[it];
         const uint64_t cb = G.it_cb[it], ce = G.it_ce[it];
@@ -1271,11 +1294,11 @@ void k_pass_gas(
                         const double hs = o_h[o] + qh;
                         if (d2 < hs * hs) {
                             npairs++;
-                            const Real d = Real(sqrt(d2));
+                            const Real d = sqrt_real(Real(d2));
                             const Real gg = EXACT_G ? overlap_g_exact<Real>(d, Real(qh), Real(o_h[o]))
                                                     : overlap_g_table<Real>(a.gtab, d, Real(qh), Real(o_h[o]));
-                            const Real wx = Real(a.dvx[q] - o_Vx[o]), wy = Real(a.dvy[q] - o_Vy[o]),
-                                       wz = Real(a.dvz[q] - o_Vz[o]);
+                            const DmRec<Real> r = reinterpret_cast<const DmRec<Real>*>(a.drec)[q];
+                            const Real wx = Real(r.vx - o_Vx[o]), wy = Real(r.vy - o_Vy[o]), wz = Real(r.vz - o_Vz[o]);
                             const Real w2 = wx * wx + wy * wy + wz * wz;
                             Real FA, FB, Ar, Br;
                             const Real i2 = o_i2[o];
@@ -1292,7 +1315,7 @@ void k_pass_gas(
                                 Ar = o_a[o] * FA;
                                 Br = o_b[o] * FB;
                             }
-                            const Real mg = dm_m[q] * gg;
+                            const Real mg = r.m * gg;
                             const Real mgA = mg * Ar;
                             c0 = mgA * wx; c1 = mgA * wy; c2 = mgA * wz;
                             c3 = mg * (w2 * Ar - o_r[o] * Br);
@@ -1303,7 +1326,7 @@ void k_pass_gas(
                     bool live = false;
                     int o = 0;
                     int64_t q = 0;
-                    float gg = 0.f, wx = 0.f, wy = 0.f, wz = 0.f, w2 = 0.f, i2 = 0.f, u = 0.f;
+                    float gg = 0.f, wx = 0.f, wy = 0.f, wz = 0.f, w2 = 0.f, i2 = 0.f, u = 0.f, mq = 0.f;
                     if (pp < H) {
                         int sl;
                         test_decode(S, pp, &o, &sl);
@@ -1315,10 +1338,12 @@ void k_pass_gas(
                         if (d2 < hs * hs) {
                             live = true;
                             npairs++;
-                            gg = overlap_g_table<float>(a.gtab, float(sqrt(d2)), float(qh), float(o_h[o]));
-                            wx = float(a.dvx[q] - o_Vx[o]);
-                            wy = float(a.dvy[q] - o_Vy[o]);
-                            wz = float(a.dvz[q] - o_Vz[o]);
+                            gg = overlap_g_table<float>(a.gtab, __fsqrt_rn(float(d2)), float(qh), float(o_h[o]));
+                            const DmRec<float> r = reinterpret_cast<const DmRec<float>*>(a.drec)[q];
+                            wx = float(r.vx - o_Vx[o]);
+                            wy = float(r.vy - o_Vy[o]);
+                            wz = float(r.vz - o_Vz[o]);
+                            mq = r.m;
                             w2 = wx * wx + wy * wy + wz * wz;
                             i2 = o_i2[o];
                             u = isinf(i2) ? 0.f : __fsqrt_rn(2.f * w2 * i2);
@@ -1360,7 +1385,7 @@ void k_pass_gas(
                             Ar = o_a[o] * FA;
                             Br = o_b[o] * FB;
                         }
-                        const float mg = dm_m[q] * gg;
+                        const float mg = mq * gg;
                         const float mgA = mg * Ar;
                         c0 = mgA * wx; c1 = mgA * wy; c2 = mgA * wz;
                         c3 = mg * (w2 * Ar - o_r[o] * Br);
@@ -1398,8 +1423,7 @@ struct DmPassArgs {
     const void* dtr;                                          // DM dt (Real), sorted
     const uint32_t* dm_perm;                                  // DM sorted pos -> index
     const double* Vx; const double* Vy; const double* Vz;     // gas, sorted
-    const void* vs; const void* K; const void* crit;          // gas (Real), sorted
-    const uint32_t* gas_perm;                                 // gas sorted pos -> index
+    const void* grec;                                         // GasRec<Real>, sorted gas
     const float4* gtab;
     uint32_t k0, k1, step, box;
     const uint32_t* step_off;     // nullable: device offset added to step (graph replays)
@@ -1421,7 +1445,7 @@ __device__ __forceinline__ Real pair_P(double d2, double dh, double gh, double v
                                        uint32_t step, uint32_t box, uint32_t k0, uint32_t k1, const float4* gtab,
                                        Real urel[3])
 {
-    Real d = Real(sqrt(d2));
+    Real d = sqrt_real(Real(d2));   // binary32 path: the root of the rounded d^2 (within one unit of float(sqrt(d2)))
     Real g = EXACT_G ? overlap_g_exact<Real>(d, Real(dh), Real(gh)) : overlap_g_table<Real>(gtab, d, Real(dh), Real(gh));
     U4 r = philox_block(i, j, step, kTagGasVel, box, k0, k1);
     Real z[3];
@@ -1505,9 +1529,6 @@ __global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a0, const DmPassAr
         const DmPassArgs& a = BATCH ? boxes[b] : a0;
         const PassGeom& G = a.g;
         const Real* dtr = reinterpret_cast<const Real*>(a.dtr);
-        const Real* vs = reinterpret_cast<const Real*>(a.vs);
-        const Real* Kp = reinterpret_cast<const Real*>(a.K);
-        const Real* cr = reinterpret_cast<const Real*>(a.crit);
         const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
         const uint32_t step = a.step + (a.step_off ? *a.step_off : 0u);
         const int64_t t = G.it_tile[it];
@@ -1554,12 +1575,13 @@ __global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a0, const DmPassAr
                     if (d2 < hs2) {
                         npairs++;
                         Real urel[3];
-                        const Real P = pair_P<Real, N, EXACT_G>(d2, o_h[o], qh, o_vx[o], o_vy[o], o_vz[o], a.Vx[q],
-                                                                a.Vy[q], a.Vz[q], vs[q], Kp[q], o_dt[o], o_id[o],
-                                                                a.gas_perm[q], step, a.box, a.k0, a.k1, a.gtab, urel);
+                        const GasRec<Real> r = reinterpret_cast<const GasRec<Real>*>(a.grec)[q];
+                        const Real P = pair_P<Real, N, EXACT_G>(d2, o_h[o], qh, o_vx[o], o_vy[o], o_vz[o], r.Vx, r.Vy,
+                                                                r.Vz, r.vs, r.K, o_dt[o], o_id[o], r.perm, step, a.box,
+                                                                a.k0, a.k1, a.gtab, urel);
                         cP = double(P);
                         cM = P;
-                        if (P >= cr[q]) ncrit++;
+                        if (P >= r.crit) ncrit++;
                     }
                 }
                 cP = seg_sum(cP, lane, seg_end);
@@ -1708,7 +1730,7 @@ struct ResolveArgs {
     PassGeom g;                   // owners = DM, others = gas sub-tiles (as in the DM pass)
     const uint64_t* cand_beg; const uint32_t* cand_cnt;   // each owner tile's candidate list
     const double* vx; const double* vy; const double* vz; const void* dtr; const uint32_t* dm_perm;
-    const double* Vx; const double* Vy; const double* Vz; const void* vs; const void* K; const uint32_t* gas_perm;
+    const void* grec;                                         // GasRec<Real>, sorted gas
     const double* gas_vel; const double* gas_u; const double* gas_mu;   // raw gas inputs (partner kick)
     double m_chi;
     const float4* gtab;
@@ -1751,8 +1773,6 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
     const int tid = threadIdx.x;
     const uint32_t step = a.step + (a.step_off ? *a.step_off : 0u);
     const Real* dtr = reinterpret_cast<const Real*>(a.dtr);
-    const Real* vs = reinterpret_cast<const Real*>(a.vs);
-    const Real* Kp = reinterpret_cast<const Real*>(a.K);
     const uint32_t nsc = *a.scount;
     uint32_t nnearD = 0;
     for (uint32_t e = blockIdx.x; e < nsc; e += gridDim.x) {
@@ -1824,10 +1844,11 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
                     const double d2 = pair_d2(mx, my, mz, px, py, pz, clean, G.L);
                     const double hs = mh + G.th[k];
                     if (d2 < hs * hs) {
-                        const uint32_t gid = a.gas_perm[k];
+                        const GasRec<Real> r = reinterpret_cast<const GasRec<Real>*>(a.grec)[k];
+                        const uint32_t gid = r.perm;
                         Real urel[3];
-                        const double P = double(pair_P<Real, N, EXACT_G>(d2, mh, G.th[k], mvx, mvy, mvz, a.Vx[k],
-                                                                         a.Vy[k], a.Vz[k], vs[k], Kp[k], mdt, oid, gid,
+                        const double P = double(pair_P<Real, N, EXACT_G>(d2, mh, G.th[k], mvx, mvy, mvz, r.Vx, r.Vy,
+                                                                         r.Vz, r.vs, r.K, mdt, oid, gid,
                                                                          step, a.box, a.k0, a.k1, a.gtab, urel));
                         fn(gid, P);
                     }
