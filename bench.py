@@ -29,11 +29,13 @@ HBM_PEAK_GBS = 8000.0
 # Vector ALU: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz lane-instructions per second.
 VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 # VALU instructions per visited pair in the built kernels (binary32 pair
-# math, n = 0, closed-form rates), counted from their gfx950 assembly: the
-# hit decode with the exact distance recheck, plus the pair body (DM pass:
-# overlap table, Philox4x32-10, Box-Muller, P_ij, running sums; gas pass:
-# overlap table, relative velocity, erf/exp rate terms, the four sums).
-PAIR_BODY_VALU = {"pass_dm": 90 + 333, "pass_gas": 89 + 120 + 49}
+# math, n = 0, closed-form rates), counted in their gfx950 assembly by
+# `python -m paper_2603_24688_amd.isa_count`: the vector instructions of one
+# round of 64 pairs (lane = pair) - hit decode, binary64 distance recheck,
+# pair body (DM pass: overlap table, Philox4x32-10, Box-Muller, P_ij; gas
+# pass: overlap table, relative velocity, erf/exp rate terms) and the
+# segmented sums over the round's lanes.
+PAIR_BODY_VALU = {"pass_dm": 396, "pass_gas": 355}
 
 
 def log(msg):
