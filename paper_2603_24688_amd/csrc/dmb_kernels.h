@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 #include "dmb_device.h"
 #include "dmb_mlp.h"
@@ -843,26 +844,68 @@ __device__ __forceinline__ bool item_next(uint32_t* queue_ctr, int64_t n_items, 
     return *it < n_items;
 }
 
-template <typename T>
-__device__ __forceinline__ T seg_sum(T v, int lane, int seg_end)
+// Lane moves of the data-parallel primitives (DPP), all within registers.
+// CTRL 0x111/0x112/0x114/0x118 = row_shr 1/2/4/8: lane i takes lane i - d of
+// its row of 16; 0x142 = row_bcast:15: every lane of row r takes lane 16r - 1;
+// 0x143 = row_bcast:31: every lane takes lane 31.  ROWS masks the rows that
+// receive; lanes without a source and rows outside ROWS read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
 {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        T t = __shfl_down(v, d);
-        if (lane + d <= seg_end) v += t;
-    }
-    return v;
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, ROWS, 0xF, true));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __uint_as_float(dpp_u32<CTRL, ROWS>(__float_as_uint(v)));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const uint64_t b = uint64_t(__double_as_longlong(v));
+    const uint64_t lo = dpp_u32<CTRL, ROWS>(uint32_t(b)), hi = dpp_u32<CTRL, ROWS>(uint32_t(b >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
 }
 
-template <typename T>
-__device__ __forceinline__ T seg_max(T v, int lane, int seg_end)
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dpp_take_add(T v, bool take)
 {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        T t = __shfl_down(v, d);
-        if (lane + d <= seg_end) v = v > t ? v : t;
-    }
-    return v;
+    const T t = dpp_move<CTRL, ROWS>(v);
+    return take ? v + t : v;
+}
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dpp_take_max(T v, bool take)
+{
+    const T t = dpp_move<CTRL, ROWS>(v);
+    return take && t > v ? t : v;
+}
+
+// Segmented inclusive scan upward over the wave: segments are runs of
+// consecutive lanes, `lo` the first lane of this lane's run.  f(ctrl, rows,
+// take) is called for six steps (four row shifts, then the two row
+// broadcasts); folding the moved copies in where `take` holds leaves every
+// lane with the combination of lanes [lo, lane] in a fixed order, so the
+// run's total sits in its last lane.
+template <typename F>
+__device__ __forceinline__ void seg_scan_up(int lane, int lo, F&& f)
+{
+    using std::integral_constant;
+    const int row0 = lane & ~15;
+    const int lr = max(lo, row0);   // first lane of the run within this lane's row
+    f(integral_constant<int, 0x111>(), integral_constant<int, 0xF>(), lane - 1 >= lr);
+    f(integral_constant<int, 0x112>(), integral_constant<int, 0xF>(), lane - 2 >= lr);
+    f(integral_constant<int, 0x114>(), integral_constant<int, 0xF>(), lane - 4 >= lr);
+    f(integral_constant<int, 0x118>(), integral_constant<int, 0xF>(), lane - 8 >= lr);
+    f(integral_constant<int, 0x142>(), integral_constant<int, 0xA>(), (lane & 16) != 0 && lo < row0);
+    f(integral_constant<int, 0x143>(), integral_constant<int, 0xC>(), lane >= 32 && lo <= 31);
+}
+
+// Bits [b, e) of a wave-uniform mask, tested for any set bit (0 <= b <= e <= 64).
+__device__ __forceinline__ bool any_bits(uint64_t m, int b, int e)
+{
+    const int n = e - b;
+    const uint64_t w = n >= 64 ? ~0ull : (1ull << n) - 1ull;
+    return n > 0 && ((m >> b) & w) != 0ull;
 }
 
 // Index of the r-th set bit (r < popcount(m)).
@@ -1140,14 +1183,15 @@ __device__ __forceinline__ int test_next(PairTest& T, TestLds& S, const PassGeom
 }
 
 // Hit `pos` of the group: owner lane o and slot s.
-__device__ __forceinline__ void test_decode(const TestLds& S, int pos, int* o_out, int* s_out)
+__device__ __forceinline__ void test_decode(const TestLds& S, int pos, int* o_out, int* s_out, int* first)
 {
     int lo = 0;
 #pragma unroll
     for (int step = 32; step >= 1; step >>= 1)
         if (S.offs[lo + step] <= pos) lo += step;
     *o_out = lo;
-    *s_out = select_bit(S.mask[lo], pos - S.offs[lo]);
+    *first = S.offs[lo];
+    *s_out = select_bit(S.mask[lo], pos - *first);
 }
 
 // ---------------------------------------------------------------------------
@@ -1282,12 +1326,12 @@ void k_pass_gas(
             for (int base = 0; base < H; base += 64) {
                 const int pp = base + lane;
                 Real c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-                int seg_end = -1;
+                int seg_lo = lane;
                 if constexpr (RM != kRatesMlp) {
                     if (pp < H) {
-                        int o, sl;
-                        test_decode(S, pp, &o, &sl);
-                        seg_end = min(S.offs[o + 1], base + 64) - 1 - base;
+                        int o, sl, first;
+                        test_decode(S, pp, &o, &sl, &first);
+                        seg_lo = max(first, base) - base;
                         const int64_t q = int64_t(S.pq[sl]);
                         const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
                         const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.pclean[sl] != 0, G.L);
@@ -1328,9 +1372,9 @@ void k_pass_gas(
                     int64_t q = 0;
                     float gg = 0.f, wx = 0.f, wy = 0.f, wz = 0.f, w2 = 0.f, i2 = 0.f, u = 0.f, mq = 0.f;
                     if (pp < H) {
-                        int sl;
-                        test_decode(S, pp, &o, &sl);
-                        seg_end = min(S.offs[o + 1], base + 64) - 1 - base;
+                        int sl, first;
+                        test_decode(S, pp, &o, &sl, &first);
+                        seg_lo = max(first, base) - base;
                         q = int64_t(S.pq[sl]);
                         const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
                         const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.pclean[sl] != 0, G.L);
@@ -1391,13 +1435,17 @@ void k_pass_gas(
                         c3 = mg * (w2 * Ar - o_r[o] * Br);
                     }
                 }
-                c0 = seg_sum(c0, lane, seg_end);
-                c1 = seg_sum(c1, lane, seg_end);
-                c2 = seg_sum(c2, lane, seg_end);
-                c3 = seg_sum(c3, lane, seg_end);
-                const int s0 = max(my_lo, base);
-                const bool has = s0 < my_hi && s0 < base + 64;
-                const int src = has ? s0 - base : 0;
+                seg_scan_up(lane, seg_lo, [&](auto ctl, auto rows, bool take) {
+                    constexpr int C = decltype(ctl)::value, R = decltype(rows)::value;
+                    c0 = dpp_take_add<C, R>(c0, take);
+                    c1 = dpp_take_add<C, R>(c1, take);
+                    c2 = dpp_take_add<C, R>(c2, take);
+                    c3 = dpp_take_add<C, R>(c3, take);
+                });
+                // this owner's hits in the round are lanes [s0, e0) - base; their sums sit in the last
+                const int s0 = max(my_lo, base), e0 = min(my_hi, base + 64);
+                const bool has = s0 < e0;
+                const int src = has ? e0 - 1 - base : 0;
                 const Real v0 = __shfl(c0, src), v1 = __shfl(c1, src), v2 = __shfl(c2, src), v3 = __shfl(c3, src);
                 if (has) { acc0 += double(v0); acc1 += double(v1); acc2 += double(v2); acc3 += double(v3); }
             }
@@ -1561,11 +1609,11 @@ __global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a0, const DmPassAr
                 double cP = 0.0;
                 Real cM = 0;
                 int cNB = 0;
-                int seg_end = -1;
+                int seg_lo = lane;
                 if (pp < H) {
-                    int o, sl;
-                    test_decode(S, pp, &o, &sl);
-                    seg_end = min(S.offs[o + 1], base + 64) - 1 - base;
+                    int o, sl, first;
+                    test_decode(S, pp, &o, &sl, &first);
+                    seg_lo = max(first, base) - base;
                     const int64_t q = int64_t(S.pq[sl]);
                     const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
                     const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.pclean[sl] != 0, G.L);
@@ -1584,16 +1632,23 @@ __global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a0, const DmPassAr
                         if (P >= r.crit) ncrit++;
                     }
                 }
-                cP = seg_sum(cP, lane, seg_end);
-                cM = seg_max(cM, lane, seg_end);
-                cNB = seg_max(cNB, lane, seg_end);
-                const int s0 = max(my_lo, base);
-                const bool has = s0 < my_hi && s0 < base + 64;
-                const int src = has ? s0 - base : 0;
+                seg_scan_up(lane, seg_lo, [&](auto ctl, auto rows, bool take) {
+                    constexpr int C = decltype(ctl)::value, R = decltype(rows)::value;
+                    cP = dpp_take_add<C, R>(cP, take);
+                    cM = dpp_take_max<C, R>(cM, take);
+                });
+                const uint64_t nbm = __ballot(cNB != 0);
+                // this owner's hits in the round are lanes [s0, e0) - base; their sums sit in the last
+                const int s0 = max(my_lo, base), e0 = min(my_hi, base + 64);
+                const bool has = s0 < e0;
+                const int src = has ? e0 - 1 - base : 0;
                 const double vP = __shfl(cP, src);
                 const Real vM = __shfl(cM, src);
-                const int vNB = __shfl(cNB, src);
-                if (has) { accP += vP; accM = accM > vM ? accM : vM; accNB |= vNB; }
+                if (has) {
+                    accP += vP;
+                    accM = accM > vM ? accM : vM;
+                    accNB |= int(any_bits(nbm, s0 - base, e0 - base));
+                }
             }
         }
         if (G.item_off[t + 1] - G.item_off[t] == 1u) {

@@ -7,7 +7,8 @@ VALU roofline uses).
 compiles the library's device code to assembly (hipcc -S, about a minute) and,
 for k_pass_dm<float, 0> and k_pass_gas<float, 0, exact rates>, finds the loop
 that evaluates one round of 64 pairs (lane = pair): the loop holding the
-segmented reductions over the round's lanes.  It sums the vector-ALU
+segmented scans over the round's lanes (the only row_bcast:31 moves of the
+kernel).  It sums the vector-ALU
 instructions of that loop's blocks at the loop's own depth: hit decode,
 binary64 distance recheck, pair body and reductions, once per round.  Each
 such wave instruction does one pair's share on every lane, so the count is
@@ -53,7 +54,7 @@ def _blocks(body):
         while j < len(body) and not re.match(r"^\.LBB", body[j]):
             t = body[j].strip()
             if t and not t.startswith(";") and not t.startswith("."):
-                ins.append(t.split()[0])
+                ins.append(t)
             j += 1
         own = re.search(r"Loop Header: Depth=(\d)", info)
         h = re.search(r"Header=(\S+)\s+Depth=(\d)", info)
@@ -75,11 +76,11 @@ def count(asm_path: str) -> dict:
         st = next(i for i, l in enumerate(lines) if l.startswith(prefix))
         en = next(i for i in range(st, len(lines)) if lines[i].startswith(".Lfunc_end"))
         blocks = _blocks(lines[st:en])
-        hot = max((b for b in blocks if b[1]), key=lambda b: sum(1 for x in b[3] if x.startswith("ds_bpermute")))
+        hot = next(b for b in blocks if b[1] and any("row_bcast:31" in x for x in b[3]))
         sel = [b for b in blocks if b[1] == hot[1] and b[2] == hot[2]]
         c = Counter()
         for b in sel:
-            c.update(x for x in b[3] if x.startswith("v_"))
+            c.update(x.split()[0] for x in b[3] if x.startswith("v_"))
         res[key] = {
             "valu_per_round": sum(c.values()),
             "transcendental": sum(v for k, v in c.items()
