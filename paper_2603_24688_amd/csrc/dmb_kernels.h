@@ -46,14 +46,67 @@ __device__ __forceinline__ void stage_sync()
 
 __device__ __forceinline__ int lane_id() { return int(threadIdx.x & 63); }
 
+// Lane moves of the data-parallel primitives (DPP), all within registers.
+// CTRL 0x111/0x112/0x114/0x118 = row_shr 1/2/4/8: lane i takes lane i - d of
+// its row of 16; 0x142 = row_bcast:15: every lane of row r takes lane 16r - 1;
+// 0x143 = row_bcast:31: every lane takes lane 31.  ROWS masks the rows that
+// receive; lanes without a source and rows outside ROWS read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
+{
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, ROWS, 0xF, true));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __uint_as_float(dpp_u32<CTRL, ROWS>(__float_as_uint(v)));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const uint64_t b = uint64_t(__double_as_longlong(v));
+    const uint64_t lo = dpp_u32<CTRL, ROWS>(uint32_t(b)), hi = dpp_u32<CTRL, ROWS>(uint32_t(b >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dpp_take_add(T v, bool take)
+{
+    const T t = dpp_move<CTRL, ROWS>(v);
+    return take ? v + t : v;
+}
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dpp_take_max(T v, bool take)
+{
+    const T t = dpp_move<CTRL, ROWS>(v);
+    return take && t > v ? t : v;
+}
+
+// Inclusive prefix sum over the wave's lanes (v >= 0), in registers: four
+// row shifts, then the row broadcasts carry row totals upward.
 __device__ __forceinline__ int wave_incl_scan(int v)
 {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int y = __shfl_up(v, d);
-        if (lane_id() >= d) v += y;
-    }
-    return v;
+    uint32_t u = uint32_t(v);
+    u += dpp_u32<0x111, 0xF>(u);
+    u += dpp_u32<0x112, 0xF>(u);
+    u += dpp_u32<0x114, 0xF>(u);
+    u += dpp_u32<0x118, 0xF>(u);
+    u += dpp_u32<0x142, 0xA>(u);
+    u += dpp_u32<0x143, 0xC>(u);
+    return int(u);
+}
+
+// Inclusive prefix maximum over the wave's lanes of values >= 0 (0 acts as
+// "nothing yet"), in registers.
+__device__ __forceinline__ uint32_t wave_incl_umax(uint32_t u)
+{
+    u = max(u, dpp_u32<0x111, 0xF>(u));
+    u = max(u, dpp_u32<0x112, 0xF>(u));
+    u = max(u, dpp_u32<0x114, 0xF>(u));
+    u = max(u, dpp_u32<0x118, 0xF>(u));
+    u = max(u, dpp_u32<0x142, 0xA>(u));
+    u = max(u, dpp_u32<0x143, 0xC>(u));
+    return u;
 }
 
 // ---------------------------------------------------------------------------
@@ -844,42 +897,6 @@ __device__ __forceinline__ bool item_next(uint32_t* queue_ctr, int64_t n_items, 
     return *it < n_items;
 }
 
-// Lane moves of the data-parallel primitives (DPP), all within registers.
-// CTRL 0x111/0x112/0x114/0x118 = row_shr 1/2/4/8: lane i takes lane i - d of
-// its row of 16; 0x142 = row_bcast:15: every lane of row r takes lane 16r - 1;
-// 0x143 = row_bcast:31: every lane takes lane 31.  ROWS masks the rows that
-// receive; lanes without a source and rows outside ROWS read 0.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
-{
-    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, ROWS, 0xF, true));
-}
-template <int CTRL, int ROWS>
-__device__ __forceinline__ float dpp_move(float v)
-{
-    return __uint_as_float(dpp_u32<CTRL, ROWS>(__float_as_uint(v)));
-}
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_move(double v)
-{
-    const uint64_t b = uint64_t(__double_as_longlong(v));
-    const uint64_t lo = dpp_u32<CTRL, ROWS>(uint32_t(b)), hi = dpp_u32<CTRL, ROWS>(uint32_t(b >> 32));
-    return __longlong_as_double((long long)((hi << 32) | lo));
-}
-
-template <int CTRL, int ROWS, typename T>
-__device__ __forceinline__ T dpp_take_add(T v, bool take)
-{
-    const T t = dpp_move<CTRL, ROWS>(v);
-    return take ? v + t : v;
-}
-template <int CTRL, int ROWS, typename T>
-__device__ __forceinline__ T dpp_take_max(T v, bool take)
-{
-    const T t = dpp_move<CTRL, ROWS>(v);
-    return take && t > v ? t : v;
-}
-
 // Segmented inclusive scan upward over the wave: segments are runs of
 // consecutive lanes, `lo` the first lane of this lane's run.  f(ctrl, rows,
 // take) is called for six steps (four row shifts, then the two row
@@ -946,16 +963,6 @@ struct PairTest {
     uint64_t actA, actB;          // chunk sub-tiles reached by some owner of lanes 0-31 / 32-63
     int total, Ps;                // slots of the chunk, start of the next group
 };
-
-__device__ __forceinline__ int wave_incl_max(int v)
-{
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int y = __shfl_up(v, d);
-        if (lane_id() >= d) v = v > y ? v : y;
-    }
-    return v;
-}
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -1094,11 +1101,11 @@ __device__ __forceinline__ int test_next(PairTest& T, TestLds& S, const PassGeom
     const int end = S.dincl[63 - __clzll(gm)];
     const int ns = end - T.Ps;
     const bool tileA = (T.actA & gm) != 0ull, tileB = (T.actB & gm) != 0ull;
-    S.sj[lane] = -1;
+    S.sj[lane] = 0;
     stage_sync<W>();
-    if (mem) S.sj[pre - T.Ps] = lane;
+    if (mem) S.sj[pre - T.Ps] = lane + 1;
     stage_sync<W>();
-    const int jm = wave_incl_max(S.sj[lane]);
+    const int jm = int(wave_incl_umax(uint32_t(S.sj[lane]))) - 1;
     // lane L loads slot s
     const int s = slot_of_lane(lane);
     const int j = __shfl(jm, s);
@@ -1182,16 +1189,30 @@ __device__ __forceinline__ int test_next(PairTest& T, TestLds& S, const PassGeom
     return H;
 }
 
-// Hit `pos` of the group: owner lane o and slot s.
-__device__ __forceinline__ void test_decode(const TestLds& S, int pos, int* o_out, int* s_out, int* first)
+// Hits of one round of a group: lane L takes hit base + L.  Every owner whose
+// hits [s0, e0) reach into the round marks the lane of its first one there
+// with (that lane + 1, the hit's rank among the owner's hits, owner); a
+// prefix maximum over the lanes hands each lane the latest mark at or below
+// it.  A wave's LDS operations complete in issue order, so the marks need no
+// barrier beyond the wave.
+__device__ __forceinline__ uint32_t round_marks(TestLds& S, int lane, int base, int s0, int e0, int my_lo)
 {
-    int lo = 0;
-#pragma unroll
-    for (int step = 32; step >= 1; step >>= 1)
-        if (S.offs[lo + step] <= pos) lo += step;
-    *o_out = lo;
-    *first = S.offs[lo];
-    *s_out = select_bit(S.mask[lo], pos - *first);
+    S.sj[lane] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (s0 < e0) S.sj[s0 - base] = int((uint32_t(s0 - base + 1) << 16) | (uint32_t(s0 - my_lo) << 8) | uint32_t(lane));
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    return wave_incl_umax(uint32_t(S.sj[lane]));
+}
+
+// Owner o, slot s and first lane `lo` of the owner's run for the lane's hit
+// (lanes that hold a hit of the round only).
+__device__ __forceinline__ void round_decode(const TestLds& S, int lane, uint32_t mark, int* o, int* s, int* lo)
+{
+    *lo = int(mark >> 16) - 1;
+    *o = int(mark & 255u);
+    *s = select_bit(S.mask[*o], int((mark >> 8) & 255u) + lane - *lo);
 }
 
 // ---------------------------------------------------------------------------
@@ -1325,13 +1346,15 @@ void k_pass_gas(
             const int my_lo = S.offs[lane], my_hi = S.offs[lane + 1];
             for (int base = 0; base < H; base += 64) {
                 const int pp = base + lane;
+                // this owner's hits in the round: [s0, e0)
+                const int s0 = max(my_lo, base), e0 = min(my_hi, base + 64);
+                const uint32_t mark = round_marks(S, lane, base, s0, e0, my_lo);
                 Real c0 = 0, c1 = 0, c2 = 0, c3 = 0;
                 int seg_lo = lane;
                 if constexpr (RM != kRatesMlp) {
                     if (pp < H) {
-                        int o, sl, first;
-                        test_decode(S, pp, &o, &sl, &first);
-                        seg_lo = max(first, base) - base;
+                        int o, sl;
+                        round_decode(S, lane, mark, &o, &sl, &seg_lo);
                         const int64_t q = int64_t(S.pq[sl]);
                         const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
                         const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.pclean[sl] != 0, G.L);
@@ -1372,9 +1395,8 @@ void k_pass_gas(
                     int64_t q = 0;
                     float gg = 0.f, wx = 0.f, wy = 0.f, wz = 0.f, w2 = 0.f, i2 = 0.f, u = 0.f, mq = 0.f;
                     if (pp < H) {
-                        int sl, first;
-                        test_decode(S, pp, &o, &sl, &first);
-                        seg_lo = max(first, base) - base;
+                        int sl;
+                        round_decode(S, lane, mark, &o, &sl, &seg_lo);
                         q = int64_t(S.pq[sl]);
                         const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
                         const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.pclean[sl] != 0, G.L);
@@ -1442,8 +1464,7 @@ void k_pass_gas(
                     c2 = dpp_take_add<C, R>(c2, take);
                     c3 = dpp_take_add<C, R>(c3, take);
                 });
-                // this owner's hits in the round are lanes [s0, e0) - base; their sums sit in the last
-                const int s0 = max(my_lo, base), e0 = min(my_hi, base + 64);
+                // the owner's sums of the round sit in the lane of its last hit
                 const bool has = s0 < e0;
                 const int src = has ? e0 - 1 - base : 0;
                 const Real v0 = __shfl(c0, src), v1 = __shfl(c1, src), v2 = __shfl(c2, src), v3 = __shfl(c3, src);
@@ -1606,14 +1627,16 @@ __global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a0, const DmPassAr
             const int my_lo = S.offs[lane], my_hi = S.offs[lane + 1];
             for (int base = 0; base < H; base += 64) {
                 const int pp = base + lane;
+                // this owner's hits in the round: [s0, e0)
+                const int s0 = max(my_lo, base), e0 = min(my_hi, base + 64);
+                const uint32_t mark = round_marks(S, lane, base, s0, e0, my_lo);
                 double cP = 0.0;
                 Real cM = 0;
                 int cNB = 0;
                 int seg_lo = lane;
                 if (pp < H) {
-                    int o, sl, first;
-                    test_decode(S, pp, &o, &sl, &first);
-                    seg_lo = max(first, base) - base;
+                    int o, sl;
+                    round_decode(S, lane, mark, &o, &sl, &seg_lo);
                     const int64_t q = int64_t(S.pq[sl]);
                     const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
                     const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.pclean[sl] != 0, G.L);
@@ -1638,8 +1661,7 @@ __global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a0, const DmPassAr
                     cM = dpp_take_max<C, R>(cM, take);
                 });
                 const uint64_t nbm = __ballot(cNB != 0);
-                // this owner's hits in the round are lanes [s0, e0) - base; their sums sit in the last
-                const int s0 = max(my_lo, base), e0 = min(my_hi, base + 64);
+                // the owner's sums of the round sit in the lane of its last hit
                 const bool has = s0 < e0;
                 const int src = has ? e0 - 1 - base : 0;
                 const double vP = __shfl(cP, src);

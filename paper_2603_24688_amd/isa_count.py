@@ -7,8 +7,8 @@ VALU roofline uses).
 compiles the library's device code to assembly (hipcc -S, about a minute) and,
 for k_pass_dm<float, 0> and k_pass_gas<float, 0, exact rates>, finds the loop
 that evaluates one round of 64 pairs (lane = pair): the loop holding the
-segmented scans over the round's lanes (the only row_bcast:31 moves of the
-kernel).  It sums the vector-ALU
+segmented scans over the round's lanes (the block with the most row_bcast:31
+moves of the kernel).  It sums the vector-ALU
 instructions of that loop's blocks at the loop's own depth: hit decode,
 binary64 distance recheck, pair body and reductions, once per round.  Each
 such wave instruction does one pair's share on every lane, so the count is
@@ -76,7 +76,7 @@ def count(asm_path: str) -> dict:
         st = next(i for i, l in enumerate(lines) if l.startswith(prefix))
         en = next(i for i in range(st, len(lines)) if lines[i].startswith(".Lfunc_end"))
         blocks = _blocks(lines[st:en])
-        hot = next(b for b in blocks if b[1] and any("row_bcast:31" in x for x in b[3]))
+        hot = max((b for b in blocks if b[1]), key=lambda b: sum("row_bcast:31" in x for x in b[3]))
         sel = [b for b in blocks if b[1] == hot[1] and b[2] == hot[2]]
         c = Counter()
         for b in sel:
