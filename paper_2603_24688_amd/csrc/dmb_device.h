@@ -165,8 +165,10 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
     asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        // one 32x32->64 multiply (v_mad_u64_u32) gives both halves
+        const uint64_t p0 = uint64_t(c.x) * 0xD2511F53u, p1 = uint64_t(c.z) * 0xCD9E8D57u;
+        const uint32_t lo0 = uint32_t(p0), hi0 = uint32_t(p0 >> 32);
+        const uint32_t lo1 = uint32_t(p1), hi1 = uint32_t(p1 >> 32);
         U4 n;
         n.x = hi1 ^ c.y ^ k0;
         n.y = lo1;
@@ -202,10 +204,16 @@ __device__ __forceinline__ void sincos_turns(float u, float* s, float* c)
 }
 __device__ __forceinline__ void sincos_turns(double u, double* s, double* c) { sincospi(2.0 * u, s, c); }
 
-__device__ __forceinline__ float log_real(float x) { return __logf(x); }
+// Binary32 uses the hardware units directly: log2 (within 1 ulp) times ln 2,
+// square root and reciprocal (1 ulp).  Their arguments on the binary32 path
+// are normal numbers or zero, so the library wrappers' rescaling of
+// subnormal arguments is not needed.
+__device__ __forceinline__ float log_real(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
 __device__ __forceinline__ double log_real(double x) { return log(x); }
-__device__ __forceinline__ float sqrt_real(float x) { return __fsqrt_rn(x); }
+__device__ __forceinline__ float sqrt_real(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_real(double x) { return sqrt(x); }
+__device__ __forceinline__ float rcp_real(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_real(double x) { return 1.0 / x; }
 
 // Three standard normals by Box-Muller from one Philox block.
 template <typename T>
@@ -269,7 +277,16 @@ __device__ __forceinline__ void rate_1f1(T x, T* FA, T* FB)
         *FB = fb;
         return;
     }
-    T t = sqrt_real(x), r = T(1) / x, it = T(1) / t;
+    T t, r, it;
+    if constexpr (sizeof(T) == 4) {
+        it = __builtin_amdgcn_rsqf(x);   // x >= 1 here
+        t = x * it;
+        r = it * it;
+    } else {
+        t = sqrt_real(x);
+        r = T(1) / x;
+        it = T(1) / t;
+    }
     T E = erf_real(t), ex = exp_neg(x);
     T spE = T(kSqrtPi) * E;
     if constexpr (N == 0) {
@@ -331,8 +348,8 @@ __device__ __forceinline__ void rate_quad(Real x, const Real* __restrict__ gx, c
             es = e0 * (Real(1) + k2 * (Real(1.0 / 6.0) + k2 * (Real(1.0 / 120.0) + k2 * (Real(1.0 / 5040.0) + k2 * Real(1.0 / 362880.0)))));
         } else {
             const Real g1 = exp_neg(Real(0.5) * (s - x) * (s - x)), g2 = exp_neg(Real(0.5) * (s + x) * (s + x));
-            const Real c = Real(0.5) * (g1 + g2), sh = Real(0.5) * (g1 - g2), ik = Real(1) / k;
-            jx = (c - sh * ik) * ik / x;
+            const Real c = Real(0.5) * (g1 + g2), sh = Real(0.5) * (g1 - g2), ik = rcp_real(k);
+            jx = (c - sh * ik) * ik * rcp_real(x);
             es = sh * ik;
         }
         const Real p4 = Pow<4 + N>::of(s);
@@ -349,8 +366,8 @@ template <int N, typename T>
 __device__ __forceinline__ T pow_np1(T v)
 {
     if constexpr (N == 0) return v;
-    else if constexpr (N == -2) return T(1) / v;
-    else if constexpr (N == -4) { T iv = T(1) / v; return iv * iv * iv; }
+    else if constexpr (N == -2) return rcp_real(v);
+    else if constexpr (N == -4) { T iv = rcp_real(v); return iv * iv * iv; }
     else if constexpr (N == 2) return v * v * v;
     else return T(0);
 }

@@ -1404,7 +1404,7 @@ void k_pass_gas(
                         if (d2 < hs * hs) {
                             live = true;
                             npairs++;
-                            gg = overlap_g_table<float>(a.gtab, __fsqrt_rn(float(d2)), float(qh), float(o_h[o]));
+                            gg = overlap_g_table<float>(a.gtab, sqrt_real(float(d2)), float(qh), float(o_h[o]));
                             const DmRec<float> r = reinterpret_cast<const DmRec<float>*>(a.drec)[q];
                             wx = float(r.vx - o_Vx[o]);
                             wy = float(r.vy - o_Vy[o]);
@@ -1412,7 +1412,7 @@ void k_pass_gas(
                             mq = r.m;
                             w2 = wx * wx + wy * wy + wz * wz;
                             i2 = o_i2[o];
-                            u = isinf(i2) ? 0.f : __fsqrt_rn(2.f * w2 * i2);
+                            u = isinf(i2) ? 0.f : sqrt_real(2.f * w2 * i2);
                         }
                     }
                     const bool net = live && !isinf(i2) && u <= kMlpUMax;
@@ -1436,7 +1436,7 @@ void k_pass_gas(
                     if (live) {
                         float Ar, Br;
                         if (isinf(i2)) {
-                            Ar = pow_np1<N>(__fsqrt_rn(w2));
+                            Ar = pow_np1<N>(sqrt_real(w2));
                             Br = Ar * w2;
                         } else {
                             float FA, FB;
@@ -2144,14 +2144,14 @@ __global__ __launch_bounds__(256) void k_rates_eval_mlp(MlpRatesArgs a)
     const float w2 = ok ? float(a.w[i] * a.w[i]) : 0.f;
     const bool cold = !(s > 0.0);
     const float i2 = cold ? INFINITY : float(1.0 / (2.0 * s * s));
-    const float u = cold ? 0.f : __fsqrt_rn(2.f * w2 * i2);
+    const float u = cold ? 0.f : sqrt_real(2.f * w2 * i2);
     const bool net = ok && !cold && u <= kMlpUMax;
     float yA = 0.f, yB = 0.f;
     mlp_forward64(a.mlp, mlp_input(u), a.nidx, &yA, &yB);
     if (!ok) return;
     float Ar, Br;
     if (cold) {
-        Ar = pow_np1<N>(__fsqrt_rn(w2));
+        Ar = pow_np1<N>(sqrt_real(w2));
         Br = Ar * w2;
     } else {
         const float ra = float(a.alpha_n / 3.0 * pow(s, double(N + 1))), rb = float(a.alpha_n * pow(s, double(N + 3)));
