@@ -96,6 +96,12 @@ __device__ __forceinline__ int wave_incl_scan(int v)
     return int(u);
 }
 
+// Value of lane j (wave-uniform j), read into a scalar register.
+__device__ __forceinline__ float lane_get(float v, int j)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+
 // Inclusive prefix maximum over the wave's lanes of values >= 0 (0 acts as
 // "nothing yet"), in registers.
 __device__ __forceinline__ uint32_t wave_incl_umax(uint32_t u)
@@ -942,15 +948,13 @@ __device__ __forceinline__ int select_bit(uint64_t m, int r)
 
 // Per-wave LDS of the test phase.
 struct TestLds {
-    float4 dlo[64];               // chunk sub-tiles: box lo (offsets from the owner-tile centre), max h
-    float4 dhi[64];               // box hi; w = 1 when every pair of the sub-tile is at its tile-level image
-    double dsh[64][3];            // periodic image shift of each chunk sub-tile
-    int dbase[64];                // first sorted index of each chunk sub-tile
+    uint32_t dsh[64];             // periodic image of each chunk sub-tile: shift / L per axis, a signed byte each
+    int dbase[64];                // first sorted index of each chunk sub-tile; bit 31: every pair of the
+                                  // sub-tile is at its tile-level image (clean)
     int dpre[64], dincl[64];      // exclusive / inclusive slot prefix over the reached sub-tiles
     int sj[64];                   // slot -> chunk sub-tile (prefix-max scratch)
     double px[64], py[64], pz[64], ph[64];   // slot particles: shifted position and h
-    uint32_t pq[64];              // slot -> sorted index of the other particle
-    int pclean[64];               // slot's sub-tile is clean
+    uint32_t pq[64];              // slot -> sorted index of the other particle; bit 31: the slot's sub-tile is clean
     uint64_t mask[64];            // per owner lane: hit mask over the group's slots
     int offs[65];                 // owner-major offsets of the group's hits
 };
@@ -1030,6 +1034,9 @@ __device__ __forceinline__ void test_chunk(PairTest& T, TestLds& S, const PassGe
     const int nch = int(min<uint64_t>(64, T.ce - T.c0));
     stage_sync<W>();    // the previous chunk's groups are done with the descriptors
     int cnt = 0;
+    // lane j holds chunk sub-tile j: box lo (offsets from the owner-tile centre) and max h,
+    // box hi and the clean flag; the owner loop below reads them lane by lane
+    float4 blo = make_float4(0.f, 0.f, 0.f, 0.f), bhi = make_float4(0.f, 0.f, 0.f, 0.f);
     if (lane < nch) {
         const uint32_t ot = G.cand[T.c0 + lane];
         const double* B = G.tbox + 6 * int64_t(ot);
@@ -1039,12 +1046,16 @@ __device__ __forceinline__ void test_chunk(PairTest& T, TestLds& S, const PassGe
         double sh[3];
         bool clean;
         tile_pair_shift(A, Bx, G.L, sh, &clean);
-        S.dlo[lane] = make_float4(float(Bx[0] + sh[0] - cen[0]), float(Bx[1] + sh[1] - cen[1]),
-                                  float(Bx[2] + sh[2] - cen[2]), float(G.thmax[ot]));
-        S.dhi[lane] = make_float4(float(Bx[3] + sh[0] - cen[0]), float(Bx[4] + sh[1] - cen[1]),
-                                  float(Bx[5] + sh[2] - cen[2]), clean ? 1.f : 0.f);
-        S.dsh[lane][0] = sh[0]; S.dsh[lane][1] = sh[1]; S.dsh[lane][2] = sh[2];
-        S.dbase[lane] = int(G.sub_start[ot]);
+        blo = make_float4(float(Bx[0] + sh[0] - cen[0]), float(Bx[1] + sh[1] - cen[1]), float(Bx[2] + sh[2] - cen[2]),
+                          float(G.thmax[ot]));
+        bhi = make_float4(float(Bx[3] + sh[0] - cen[0]), float(Bx[4] + sh[1] - cen[1]), float(Bx[5] + sh[2] - cen[2]),
+                          clean ? 1.f : 0.f);
+        uint32_t pk = 0u;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (G.L[a] > 0.0) pk |= (uint32_t(int(rint(sh[a] / G.L[a]))) & 255u) << (8 * a);
+        S.dsh[lane] = pk;
+        S.dbase[lane] = int(uint32_t(G.sub_start[ot]) | (clean ? 0x80000000u : 0u));
         cnt = int(G.sub_cnt[ot]);
     }
     T.c0 += uint64_t(nch);
@@ -1054,7 +1065,8 @@ __device__ __forceinline__ void test_chunk(PairTest& T, TestLds& S, const PassGe
     const float ap2 = fx * fx + fy * fy + fz * fz, ah2 = fh * fh;
     uint64_t actA = 0ull, actB = 0ull;
     for (int j = 0; j < nch; ++j) {
-        const float4 lo = S.dlo[j], hi = S.dhi[j];
+        const float4 lo = make_float4(lane_get(blo.x, j), lane_get(blo.y, j), lane_get(blo.z, j), lane_get(blo.w, j));
+        const float4 hi = make_float4(lane_get(bhi.x, j), lane_get(bhi.y, j), lane_get(bhi.z, j), lane_get(bhi.w, j));
         bool near = T.ov;
         if (hi.w != 0.f) {
             const float gx = fmaxf(0.f, fmaxf(lo.x - fx, fx - hi.x));
@@ -1113,13 +1125,15 @@ __device__ __forceinline__ int test_next(PairTest& T, TestLds& S, const PassGeom
     int cl = 1;
     float c[6] = {0.f, 0.f, 0.f, 0.f, 1.f, __builtin_inff()};
     if (sv) {
-        const int64_t q = int64_t(S.dbase[j]) + (s - (S.dpre[j] - T.Ps));
-        cl = S.dhi[j].w != 0.f;
-        const double X = G.tx[q] + S.dsh[j][0], Y = G.ty[q] + S.dsh[j][1], Z = G.tz[q] + S.dsh[j][2];
+        const uint32_t db = uint32_t(S.dbase[j]);
+        const int64_t q = int64_t(db & 0x7fffffffu) + (s - (S.dpre[j] - T.Ps));
+        cl = int(db >> 31);
+        const uint32_t pk = S.dsh[j];
+        const double X = G.tx[q] + double(int8_t(pk)) * G.L[0], Y = G.ty[q] + double(int8_t(pk >> 8)) * G.L[1],
+                     Z = G.tz[q] + double(int8_t(pk >> 16)) * G.L[2];
         const double Hh = G.th[q];
         S.px[s] = X; S.py[s] = Y; S.pz[s] = Z; S.ph[s] = Hh;
-        S.pq[s] = uint32_t(q);
-        S.pclean[s] = cl;
+        S.pq[s] = uint32_t(q) | (cl ? 0x80000000u : 0u);
         const float qx = float(X - cen[0]), qy = float(Y - cen[1]), qz = float(Z - cen[2]), qh = float(Hh);
         const float p2 = qx * qx + qy * qy + qz * qz, h2 = qh * qh;
         c[0] = -2.f * qx; c[1] = -2.f * qy; c[2] = -2.f * qz; c[3] = -2.f * qh;
@@ -1166,7 +1180,7 @@ __device__ __forceinline__ int test_next(PairTest& T, TestLds& S, const PassGeom
             const float4 q = make_float4(float(S.px[t] - cen[0]), float(S.py[t] - cen[1]), float(S.pz[t] - cen[2]),
                                          float(S.ph[t]));
             bool hit;
-            if (S.pclean[t]) {
+            if (S.pq[t] >> 31) {
                 const float p2 = q.x * q.x + q.y * q.y + q.z * q.z, h2 = q.w * q.w;
                 const float tb = (p2 - h2) - kTestSlack * (p2 + h2);
                 hit = fmaf(mx2, q.x, fmaf(my2, q.y, fmaf(mz2, q.z, fmaf(mh2, q.w, A2 + tb)))) < 0.f;
@@ -1261,8 +1275,10 @@ __device__ __forceinline__ void gas_write_out(const GasPassArgs& a, uint32_t o, 
     a.de[o] = sc * acc[3];
 }
 
+// Occupancy: the binary32 passes fit 128 VGPRs and < 10 KB of LDS per
+// one-wave block, so four waves share each SIMD (16 blocks per CU).
 template <typename Real, int N, bool EXACT_G, int RM, bool BATCH = false>
-__global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kRatesMlp ? 2 : (sizeof(Real) == 4 ? 3 : (RM == kRatesExact ? 1 : 2)))
+__global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kRatesMlp ? 2 : (sizeof(Real) == 4 ? 4 : (RM == kRatesExact ? 1 : 2)))
 void k_pass_gas(
     GasPassArgs a0, const GasPassArgs* __restrict__ boxes, const int64_t* __restrict__ box_items, int nbox)
 {
@@ -1355,9 +1371,10 @@ void k_pass_gas(
                     if (pp < H) {
                         int o, sl;
                         round_decode(S, lane, mark, &o, &sl, &seg_lo);
-                        const int64_t q = int64_t(S.pq[sl]);
+                        const uint32_t pqv = S.pq[sl];
+                        const int64_t q = int64_t(pqv & 0x7fffffffu);
                         const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
-                        const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.pclean[sl] != 0, G.L);
+                        const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, (pqv >> 31) != 0u, G.L);
                         const double hs = o_h[o] + qh;
                         if (d2 < hs * hs) {
                             npairs++;
@@ -1397,9 +1414,10 @@ void k_pass_gas(
                     if (pp < H) {
                         int sl;
                         round_decode(S, lane, mark, &o, &sl, &seg_lo);
-                        q = int64_t(S.pq[sl]);
+                        const uint32_t pqv = S.pq[sl];
+                        q = int64_t(pqv & 0x7fffffffu);
                         const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
-                        const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.pclean[sl] != 0, G.L);
+                        const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, (pqv >> 31) != 0u, G.L);
                         const double hs = o_h[o] + qh;
                         if (d2 < hs * hs) {
                             live = true;
@@ -1552,7 +1570,7 @@ __device__ __forceinline__ uint32_t dm_decide(uint32_t o, int64_t s, double P, f
 }
 
 template <typename Real, int N, bool EXACT_G, bool BATCH = false>
-__global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a0, const DmPassArgs* __restrict__ boxes,
+__global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPassArgs a0, const DmPassArgs* __restrict__ boxes,
                                                    const int64_t* __restrict__ box_items, int nbox)
 {
     __shared__ TestLds S;
@@ -1637,9 +1655,10 @@ __global__ __launch_bounds__(64, 3) void k_pass_dm(DmPassArgs a0, const DmPassAr
                 if (pp < H) {
                     int o, sl;
                     round_decode(S, lane, mark, &o, &sl, &seg_lo);
-                    const int64_t q = int64_t(S.pq[sl]);
+                    const uint32_t pqv = S.pq[sl];
+                    const int64_t q = int64_t(pqv & 0x7fffffffu);
                     const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
-                    const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, S.pclean[sl] != 0, G.L);
+                    const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, (pqv >> 31) != 0u, G.L);
                     const double hs = o_h[o] + qh;
                     const double hs2 = hs * hs;
                     if (fabs(d2 - hs2) <= 1e-6 * hs2) cNB = 1;
