@@ -84,6 +84,8 @@ struct dmb_ctx {
     DevBuf sort_table;
     DevBuf bbox_part;
     DevBuf counters_local;
+    DevBuf rb_dev;                         // build-stage scalars for the host (one copy per stage)
+    uint64_t* rb_host = nullptr;           // pinned
     int split = 64;
     int subtile_delta = 1;                 // (tunable) sub-tile cut: Morton level below (median - delta)
     int grid_pct = 100;                    // (tunable) persistent grid size, % of the resident maximum
@@ -1115,8 +1117,9 @@ dmb_status dmb_destroy(dmb_ctx* c)
     for (DevBuf* b : mlp) fr(*b);
     if (c->train_stream) hipStreamDestroy(c->train_stream);
     DevBuf* rest[] = {&c->gl64, &c->gl32, &c->gtab, &c->sort_table, &c->bbox_part, &c->counters_local,
-                      &c->bstep, &c->bgeom, &c->bitem};
+                      &c->bstep, &c->bgeom, &c->bitem, &c->rb_dev};
     for (DevBuf* b : rest) fr(*b);
+    if (c->rb_host) hipHostFree(c->rb_host);
     delete c;
     return DMB_OK;
 }
@@ -1186,6 +1189,28 @@ dmb_status dmb_build_cells(dmb_ctx* c, const dmb_particles* gas, const dmb_parti
 }  // extern "C"
 
 namespace {
+// Scalars to bring back to the host in one copy (see k_readback).
+struct Readback {
+    ReadbackArgs a{};
+    void u32(const void* p) { a.src[a.cnt] = p; a.n[a.cnt++] = -4; }
+    void u64(const void* p) { a.src[a.cnt] = p; a.n[a.cnt++] = -8; }
+    void dmax(const void* p, int64_t n) { a.src[a.cnt] = p; a.n[a.cnt++] = n; }
+};
+
+// Runs the gather, copies the values into pinned memory and waits for them.
+dmb_status readback(dmb_ctx* c, const Readback& r, uint64_t* out)
+{
+    if (r.a.cnt == 0) return DMB_OK;
+    ENSURE(c, c->rb_dev, kReadbackMax * sizeof(uint64_t));
+    if (!c->rb_host) HIPCHK(c, hipHostMalloc(reinterpret_cast<void**>(&c->rb_host), kReadbackMax * sizeof(uint64_t)));
+    hipLaunchKernelGGL(k_readback, dim3(1), dim3(256), 0, c->stream, r.a, c->rb_dev.as<uint64_t>());
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->rb_host, c->rb_dev.p, r.a.cnt * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::memcpy(out, c->rb_host, r.a.cnt * sizeof(uint64_t));
+    return DMB_OK;
+}
+
 // Cell structure of one box into c->X (arguments already checked).
 dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par)
 {
@@ -1199,18 +1224,20 @@ dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_part
     if ((s = build_species(c, c->X->gas, gas)) != DMB_OK) return s;
     if ((s = build_species(c, c->X->dm, dm)) != DMB_OK) return s;
     // read back owner and sub-tile counts
-    uint32_t nown[2] = {0, 0}, nsub[2] = {0, 0};
-    for (int sp = 0; sp < 2; ++sp) {
-        Species& S = sp == 0 ? c->X->gas : c->X->dm;
-        if (S.n == 0) continue;
-        HIPCHK(c, hipMemcpyAsync(&nown[sp], S.flag_off.as<uint32_t>() + S.n, 4, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipMemcpyAsync(&nsub[sp], S.sub_coff.as<uint32_t>() + S.nchunk, 4, hipMemcpyDeviceToHost, c->stream));
+    {
+        Readback r;
+        for (int sp = 0; sp < 2; ++sp) {
+            Species& S = sp == 0 ? c->X->gas : c->X->dm;
+            r.u32(S.n > 0 ? S.flag_off.as<uint32_t>() + S.n : nullptr);
+            r.u32(S.n > 0 ? S.sub_coff.as<uint32_t>() + S.nchunk : nullptr);
+        }
+        uint64_t v[4];
+        if ((s = readback(c, r, v)) != DMB_OK) return s;
+        c->X->gas.n_own = int64_t(v[0]);
+        c->X->gas.ntile = int64_t(v[1]);
+        c->X->dm.n_own = int64_t(v[2]);
+        c->X->dm.ntile = int64_t(v[3]);
     }
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->X->gas.n_own = nown[0];
-    c->X->dm.n_own = nown[1];
-    c->X->gas.ntile = nsub[0];
-    c->X->dm.ntile = nsub[1];
     if ((s = build_subtiles(c, c->X->gas)) != DMB_OK) return s;
     if ((s = build_subtiles(c, c->X->dm)) != DMB_OK) return s;
     if ((s = build_owner_tiles(c, c->X->gas)) != DMB_OK) return s;
@@ -1220,27 +1247,28 @@ dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_part
     uint64_t npairs[2] = {0, 0};
     uint32_t maxcnt[2] = {0, 0};
     double hmax[2] = {0, 0};
-    for (int k = 0; k < 2; ++k) {
-        Species& A = k == 0 ? c->X->gas : c->X->dm;
-        Species& B = k == 0 ? c->X->dm : c->X->gas;
-        Pairs& P = k == 0 ? c->X->gp : c->X->dp;
-        if (A.nown_tile == 0) continue;
-        HIPCHK(c, hipMemcpyAsync(&npairs[k], P.off.as<uint64_t>() + A.nown_tile, 8, hipMemcpyDeviceToHost, c->stream));
-        if (B.ntile > 0) HIPCHK(c, hipMemcpyAsync(&maxcnt[k], P.maxcnt.p, 4, hipMemcpyDeviceToHost, c->stream));
-    }
-    if (periodic) {
-        // largest h of each species from the super-tile maxima
+    {
+        Readback r;
+        for (int k = 0; k < 2; ++k) {
+            Species& A = k == 0 ? c->X->gas : c->X->dm;
+            Species& B = k == 0 ? c->X->dm : c->X->gas;
+            Pairs& P = k == 0 ? c->X->gp : c->X->dp;
+            r.u64(A.nown_tile > 0 ? P.off.as<uint64_t>() + A.nown_tile : nullptr);
+            r.u32(A.nown_tile > 0 && B.ntile > 0 ? P.maxcnt.p : nullptr);
+        }
+        // largest h of each species from the super-tile maxima (periodic boxes)
         for (int sp = 0; sp < 2; ++sp) {
             Species& S = sp == 0 ? c->X->gas : c->X->dm;
-            if (S.nsuper == 0) continue;
-            double* tmp = new double[S.nsuper];
-            HIPCHK(c, hipMemcpyAsync(tmp, S.shh.p, S.nsuper * 8, hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(c, hipStreamSynchronize(c->stream));
-            for (int64_t k = 0; k < S.nsuper; ++k) hmax[sp] = std::max(hmax[sp], tmp[k]);
-            delete[] tmp;
+            r.dmax(periodic && S.nsuper > 0 ? S.shh.p : nullptr, periodic ? S.nsuper : 0);
+        }
+        uint64_t v[6];
+        if ((s = readback(c, r, v)) != DMB_OK) return s;
+        for (int k = 0; k < 2; ++k) {
+            npairs[k] = v[2 * k];
+            maxcnt[k] = uint32_t(v[2 * k + 1]);
+            std::memcpy(&hmax[k], &v[4 + k], sizeof(double));
         }
     }
-    HIPCHK(c, hipStreamSynchronize(c->stream));
     if (periodic) {
         double Lmin = std::min(par->box[0], std::min(par->box[1], par->box[2]));
         if (hmax[0] + hmax[1] >= 0.5 * Lmin) {
@@ -1254,14 +1282,21 @@ dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_part
     if ((s = cand_subs(c, c->X->dm, c->X->gas, c->X->dp)) != DMB_OK) return s;
     uint64_t tot[2] = {0, 0};
     uint32_t nit[2] = {0, 0};
-    for (int k = 0; k < 2; ++k) {
-        Species& A = k == 0 ? c->X->gas : c->X->dm;
-        Pairs& P = k == 0 ? c->X->gp : c->X->dp;
-        if (A.nown_tile == 0) continue;
-        if (P.npairs > 0) HIPCHK(c, hipMemcpyAsync(&tot[k], P.soff.as<uint64_t>() + P.npairs, 8, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipMemcpyAsync(&nit[k], P.ioff.as<uint32_t>() + A.nown_tile, 4, hipMemcpyDeviceToHost, c->stream));
+    {
+        Readback r;
+        for (int k = 0; k < 2; ++k) {
+            Species& A = k == 0 ? c->X->gas : c->X->dm;
+            Pairs& P = k == 0 ? c->X->gp : c->X->dp;
+            r.u64(A.nown_tile > 0 && P.npairs > 0 ? P.soff.as<uint64_t>() + P.npairs : nullptr);
+            r.u32(A.nown_tile > 0 ? P.ioff.as<uint32_t>() + A.nown_tile : nullptr);
+        }
+        uint64_t v[4];
+        if ((s = readback(c, r, v)) != DMB_OK) return s;
+        for (int k = 0; k < 2; ++k) {
+            tot[k] = v[2 * k];
+            nit[k] = uint32_t(v[2 * k + 1]);
+        }
     }
-    HIPCHK(c, hipStreamSynchronize(c->stream));
     c->X->gp.total = int64_t(tot[0]); c->X->gp.nitems = nit[0];
     c->X->dp.total = int64_t(tot[1]); c->X->dp.nitems = nit[1];
     if ((s = cand_write(c, c->X->gas, c->X->dm, c->X->gp)) != DMB_OK) return s;

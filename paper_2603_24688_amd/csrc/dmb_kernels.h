@@ -148,6 +148,44 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const double* __restrict__
     }
 }
 
+// Scalars the host reads after a build stage, gathered into one buffer so
+// that one copy brings them back: a 4- or 8-byte value, or the maximum of n
+// binary64 values (h maxima).  A null source reads as 0.  One block.
+constexpr int kReadbackMax = 8;
+struct ReadbackArgs {
+    const void* src[kReadbackMax];
+    int64_t n[kReadbackMax];      // -4: uint32 value, -8: uint64 value, n >= 0: max of n doubles
+    int cnt;
+};
+
+__global__ __launch_bounds__(256) void k_readback(ReadbackArgs a, uint64_t* __restrict__ dst)
+{
+    __shared__ double red[256];
+    for (int i = 0; i < a.cnt; ++i) {
+        const int64_t n = a.n[i];
+        if (n < 0) {
+            if (threadIdx.x == 0) {
+                uint64_t v = 0;
+                if (a.src[i]) v = n == -8 ? *static_cast<const uint64_t*>(a.src[i]) : *static_cast<const uint32_t*>(a.src[i]);
+                dst[i] = v;
+            }
+            continue;
+        }
+        const double* x = static_cast<const double*>(a.src[i]);
+        double m = 0.0;
+        if (x)
+            for (int64_t k = threadIdx.x; k < n; k += 256) m = fmax(m, x[k]);
+        red[threadIdx.x] = m;
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if (int(threadIdx.x) < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) dst[i] = uint64_t(__double_as_longlong(red[0]));
+        __syncthreads();
+    }
+}
+
 // cube[0..2] = origin, cube[3] = 2^21 / side (quantisation scale).  One wave.
 __global__ __launch_bounds__(64) void k_bbox_final(const double* __restrict__ part, int nparts,
                                                    const double* __restrict__ boxL, double* __restrict__ cube)
