@@ -12,6 +12,8 @@
 #include <new>
 #include <vector>
 
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "../../include/dmb.h"
 #include "dmb_kernels.h"
 #include "dmb_sort.h"
@@ -81,7 +83,7 @@ struct dmb_ctx {
     std::vector<Cells*> boxes;             // batched boxes
     DevBuf bstep, bgeom, bitem;            // batched step: Philox step offset, per-box pass arguments, item offsets
     DevBuf scan_tmp[4];
-    DevBuf sort_table;
+    DevBuf sort_tmp;                       // radix-sort temporary storage
     DevBuf bbox_part;
     DevBuf counters_local;
     DevBuf rb_dev;                         // build-stage scalars for the host (one copy per stage)
@@ -246,22 +248,19 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
     // radix sort on the top bits that resolve ~2^6 particles per cell
     int need = std::min(63, std::max(24, 3 * ((bits_for(n) + 6 + 2) / 3)));
     int passes = (need + 7) / 8;
-    int nblk = int((n + kSortTile - 1) / kSortTile);
-    int64_t tsz = int64_t(256) * nblk;
-    ENSURE(c, c->sort_table, size_t(tsz + 1) * 4);
+    // stable LSD radix sort (rocPRIM onesweep) of the keys' bits [63 - 8 passes, 63)
+    const int lo_bit = std::max(0, 63 - 8 * passes);
     uint64_t *ka = S.keys.as<uint64_t>(), *kb = S.keys2.as<uint64_t>();
     uint32_t *va = S.vals.as<uint32_t>(), *vb = S.vals2.as<uint32_t>();
-    for (int ps = 0; ps < passes; ++ps) {
-        int shift = 63 - 8 * (passes - ps);
-        if (shift < 0) shift = 0;
-        hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(kSortBlock), 0, c->stream, ka, n, shift,
-                           c->sort_table.as<uint32_t>(), nblk);
-        dmb_status s = scan_excl(c, c->sort_table.as<uint32_t>(), c->sort_table.as<uint32_t>(), tsz);
-        if (s != DMB_OK) return s;
-        hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(kSortBlock), 0, c->stream, ka, va, kb, vb, n, shift,
-                           c->sort_table.as<const uint32_t>(), nblk);
-        std::swap(ka, kb);
-        std::swap(va, vb);
+    {
+        rocprim::double_buffer<uint64_t> kd(ka, kb);
+        rocprim::double_buffer<uint32_t> vd(va, vb);
+        size_t tmp = 0;
+        HIPCHK(c, rocprim::radix_sort_pairs(nullptr, tmp, kd, vd, size_t(n), unsigned(lo_bit), 63u, c->stream));
+        ENSURE(c, c->sort_tmp, tmp);
+        HIPCHK(c, rocprim::radix_sort_pairs(c->sort_tmp.p, tmp, kd, vd, size_t(n), unsigned(lo_bit), 63u, c->stream));
+        ka = kd.current();
+        va = vd.current();
     }
     S.sort_lo_bit = std::max(0, 63 - 8 * passes);
     // keep the sorted permutation in S.vals
@@ -1116,8 +1115,8 @@ dmb_status dmb_destroy(dmb_ctx* c)
                      &c->mlp_loss, &c->mlp_epoch, &c->mlp_shuf};
     for (DevBuf* b : mlp) fr(*b);
     if (c->train_stream) hipStreamDestroy(c->train_stream);
-    DevBuf* rest[] = {&c->gl64, &c->gl32, &c->gtab, &c->sort_table, &c->bbox_part, &c->counters_local,
-                      &c->bstep, &c->bgeom, &c->bitem, &c->rb_dev};
+    DevBuf* rest[] = {&c->gl64, &c->gl32, &c->gtab, &c->bbox_part, &c->counters_local,
+                      &c->bstep, &c->bgeom, &c->bitem, &c->rb_dev, &c->sort_tmp};
     for (DevBuf* b : rest) fr(*b);
     if (c->rb_host) hipHostFree(c->rb_host);
     delete c;
