@@ -39,6 +39,7 @@ struct Species {
     DevBuf tsup, ssup, msup;               // support boxes (union of [x - h, x + h]) of sub-, super-, mega-tiles
     DevBuf tq, sq, mq;                     // binary32 candidate-search nodes of sub-, super-, mega-tiles
     DevBuf cube;                           // Morton cube
+    DevBuf prec;                           // packed (x, y, z, h) in input order
     // per-step gathers (sorted order)
     DevBuf v0, v1, v2;                     // velocity components (double)
     DevBuf r0, r1, r2, r3, r4, r5, r6;     // Real-typed per-particle factors
@@ -242,9 +243,10 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
     hipLaunchKernelGGL(k_bbox_partial, dim3(nparts), dim3(256), 0, c->stream, p->pos, n, c->bbox_part.as<double>());
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, c->stream, c->bbox_part.as<const double>(), nparts,
                        c->X->boxL.as<const double>(), S.cube.as<double>());
-    hipLaunchKernelGGL(k_morton, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, p->pos, n,
+    ENSURE(c, S.prec, n * sizeof(double4));
+    hipLaunchKernelGGL(k_morton, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, p->pos, p->h, n,
                        S.cube.as<const double>(), c->X->boxL.as<const double>(), S.keys.as<uint64_t>(),
-                       S.vals.as<uint32_t>());
+                       S.vals.as<uint32_t>(), S.prec.as<double4>());
     // radix sort on the top bits that resolve ~2^6 particles per cell
     int need = std::min(63, std::max(24, 3 * ((bits_for(n) + 6 + 2) / 3)));
     int passes = (need + 7) / 8;
@@ -270,8 +272,8 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
     }
     S.perm = S.vals.as<const uint32_t>();
     ENSURE(c, S.sx, n * 8); ENSURE(c, S.sy, n * 8); ENSURE(c, S.sz, n * 8); ENSURE(c, S.sh, n * 8);
-    hipLaunchKernelGGL(k_gather_pos, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, S.perm, n, p->pos, p->h,
-                       c->X->boxL.as<const double>(), S.sx.as<double>(), S.sy.as<double>(), S.sz.as<double>(),
+    hipLaunchKernelGGL(k_gather_pos, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, S.perm, n,
+                       S.prec.as<const double4>(), S.sx.as<double>(), S.sy.as<double>(), S.sz.as<double>(),
                        S.sh.as<double>());
     // owners (active subset, Morton order)
     ENSURE(c, S.flag, (n + 1) * 4); ENSURE(c, S.flag_off, (n + 1) * 4); ENSURE(c, S.own, n * 4);
@@ -1033,7 +1035,7 @@ void free_cells(Cells& X)
                          &S->flag_off, &S->own, &S->tbox, &S->th, &S->sbox, &S->shh, &S->mbox, &S->mhh, &S->obox,
                          &S->oh, &S->cube, &S->v0, &S->v1, &S->v2, &S->r0, &S->r1, &S->r2, &S->r3, &S->r4, &S->r5,
                          &S->r6, &S->rec, &S->sub_ccnt, &S->sub_coff, &S->sub_start, &S->sub_cnt, &S->tsup, &S->ssup,
-                         &S->msup, &S->tq, &S->sq, &S->mq};
+                         &S->msup, &S->tq, &S->sq, &S->mq, &S->prec};
         for (DevBuf* b : all) fr(*b);
     }
     for (Pairs* P : {&X.gp, &X.dp}) {

@@ -225,45 +225,44 @@ __device__ __forceinline__ uint64_t spread21(uint64_t x)
     return x;
 }
 
-__global__ __launch_bounds__(256) void k_morton(const double* __restrict__ pos, int64_t n,
+// Morton key of each particle (input order), plus a packed copy of its
+// position (wrapped into [0, L) when periodic) and h, so that the gather into
+// Morton order reads one 32-byte record per particle.
+__global__ __launch_bounds__(256) void k_morton(const double* __restrict__ pos, const double* __restrict__ h, int64_t n,
                                                 const double* __restrict__ cube, const double* __restrict__ boxL,
-                                                uint64_t* __restrict__ keys, uint32_t* __restrict__ vals)
+                                                uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                double4* __restrict__ rec)
 {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     uint64_t q[3];
+    double p[3];
     for (int a = 0; a < 3; ++a) {
         double x = pos[3 * i + a];
         if (boxL[a] > 0.0) x -= boxL[a] * floor(x / boxL[a]);
+        p[a] = x;
         double f = (x - cube[a]) * cube[3];
         f = fmin(fmax(f, 0.0), 2097151.0);
         q[a] = uint64_t(f);
     }
     keys[i] = spread21(q[0]) | (spread21(q[1]) << 1) | (spread21(q[2]) << 2);
     vals[i] = uint32_t(i);
+    rec[i] = make_double4(p[0], p[1], p[2], h[i]);
 }
 
-// Sorted SoA copies of position and h (positions wrapped into [0, L) when
-// periodic so that tile boxes are compact).
+// Sorted SoA copies of position and h from the packed records.
 __global__ __launch_bounds__(256) void k_gather_pos(const uint32_t* __restrict__ perm, int64_t n,
-                                                    const double* __restrict__ pos, const double* __restrict__ h,
-                                                    const double* __restrict__ boxL, double* __restrict__ sx,
+                                                    const double4* __restrict__ rec, double* __restrict__ sx,
                                                     double* __restrict__ sy, double* __restrict__ sz,
                                                     double* __restrict__ sh)
 {
     int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    uint32_t o = perm[k];
-    double p[3];
-    for (int a = 0; a < 3; ++a) {
-        double x = pos[3 * int64_t(o) + a];
-        if (boxL[a] > 0.0) x -= boxL[a] * floor(x / boxL[a]);
-        p[a] = x;
-    }
-    sx[k] = p[0];
-    sy[k] = p[1];
-    sz[k] = p[2];
-    sh[k] = h[o];
+    const double4 r = rec[perm[k]];
+    sx[k] = r.x;
+    sy[k] = r.y;
+    sz[k] = r.z;
+    sh[k] = r.w;
 }
 
 __global__ __launch_bounds__(256) void k_active_flags(const uint32_t* __restrict__ perm, int64_t n,
