@@ -1078,16 +1078,22 @@ dmb_status dmb_create(dmb_ctx** out, int device, void* hip_stream)
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         c->num_cu = ncu;
-    size_t tb = size_t(kTabND + 1) * (kTabNE + 1) * sizeof(float4);
-    if (ensure(c, c->gtab, tb) != DMB_OK || ensure(c, c->X->boxL, 4 * sizeof(double)) != DMB_OK) {
+    size_t tb = size_t(kTabCells) * 4 * sizeof(float4);
+    const int64_t nnodes = int64_t(kTabND + 1) * (kTabNE + 1);
+    DevBuf nodes;
+    if (ensure(c, c->gtab, tb) != DMB_OK || ensure(c, c->X->boxL, 4 * sizeof(double)) != DMB_OK ||
+        ensure(c, nodes, size_t(nnodes) * 3 * sizeof(double)) != DMB_OK) {
         snprintf(g_create_err, sizeof(g_create_err), "%s", c->err);
+        if (nodes.p) (void)hipFree(nodes.p);
         dmb_destroy(c);
         return DMB_ENOMEM;
     }
-    hipLaunchKernelGGL(k_gtab_build, dim3(blocks_for(int64_t(kTabND + 1) * (kTabNE + 1), 256)), dim3(256), 0,
-                       c->stream, c->gtab.as<float4>());
+    hipLaunchKernelGGL(k_gtab_build, dim3(blocks_for(nnodes, 256)), dim3(256), 0, c->stream, nodes.as<double>());
+    hipLaunchKernelGGL(k_gtab_cells, dim3(blocks_for(kTabCells, 256)), dim3(256), 0, c->stream,
+                       nodes.as<const double>(), c->gtab.as<float4>());
     he = hipGetLastError();
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    (void)hipFree(nodes.p);
     if (he != hipSuccess) {
         snprintf(g_create_err, sizeof(g_create_err), "overlap table build: %s", hipGetErrorString(he));
         dmb_destroy(c);

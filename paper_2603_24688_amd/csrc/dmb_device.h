@@ -110,37 +110,38 @@ __device__ double overlap_H_exact(double delta, double eta)
 // ---------------------------------------------------------------------------
 // Overlap table for the FP32 path (Appendix D tabulates the overlap over the
 // distance ratio and the softening ratio).  Nodes delta_i = i*2/ND (i <= ND),
-// eta_j = j/NE (j <= NE); each node holds float4(H, dH/ddelta * ddelta,
-// dH/deta * deta, 0); lookup is cubic Hermite in both directions with the
-// eta-derivative interpolated linearly along delta.
+// eta_j = j/NE (j <= NE) carry H, dH/ddelta * ddelta and dH/deta * deta; the
+// interpolant is cubic Hermite along delta for H, linear along delta for the
+// eta-derivative, and cubic Hermite along eta.  Each cell stores that
+// interpolant as polynomial coefficients in the cell offsets (a, b) in [0,1]^2:
+//   H = P0(a) + P1(a) b + P2(a) b^2 + P3(a) b^3,
+// P0, P2, P3 cubic and P1 linear in a, as four float4 (P0, P2, P3, P1) = 64
+// bytes, so one lookup reads one aligned 64-byte segment.
 constexpr int kTabND = 512;
 constexpr int kTabNE = 128;
-
+constexpr int kTabCells = kTabND * kTabNE;
 
 template <typename T>
 __device__ __forceinline__ T overlap_g_table(const float4* __restrict__ tab, T d, T hi, T hj)
 {
-    // Nodes are stored in binary32; the interpolation runs in binary64 (same
-    // FMA rate as binary32 on gfx950 vector ALUs) so that the result carries
-    // only the node rounding (~1e-7 of the peak), not float arithmetic error.
+    // Coefficients are stored in binary32; the evaluation runs in binary64
+    // (same FMA rate as binary32 on gfx950 vector ALUs) so that the result
+    // carries only the coefficient rounding (~1e-7 of the peak).
     double hb = double(hi > hj ? hi : hj), hs = double(hi > hj ? hj : hi);
     // 1/hb: binary32 reciprocal and one Newton step in binary64 (relative
-    // error ~1e-14, far below the node rounding; no binary64 division)
+    // error ~1e-14, far below the coefficient rounding; no binary64 division)
     double ib = double(__builtin_amdgcn_rcpf(float(hb)));
     ib = ib * fma(-hb, ib, 2.0);
     double fd = double(d) * ib * (kTabND * 0.5), fe = hs * ib * double(kTabNE);
     int i = min(int(fd), kTabND - 1), j = min(int(fe), kTabNE - 1);
     double a = fd - double(i), b = fe - double(j);
-    float4 c00 = tab[j * (kTabND + 1) + i], c10 = tab[j * (kTabND + 1) + i + 1];
-    float4 c01 = tab[(j + 1) * (kTabND + 1) + i], c11 = tab[(j + 1) * (kTabND + 1) + i + 1];
-    double a2 = a * a, a3 = a2 * a;
-    double h0 = 2.0 * a3 - 3.0 * a2 + 1.0, h1 = a3 - 2.0 * a2 + a, h2 = 3.0 * a2 - 2.0 * a3, h3 = a3 - a2;
-    double r0 = h0 * double(c00.x) + h1 * double(c00.y) + h2 * double(c10.x) + h3 * double(c10.y);
-    double r1 = h0 * double(c01.x) + h1 * double(c01.y) + h2 * double(c11.x) + h3 * double(c11.y);
-    double e0 = double(c00.z) + a * double(c10.z - c00.z), e1 = double(c01.z) + a * double(c11.z - c01.z);
-    double b2 = b * b, b3 = b2 * b;
-    double H = (2.0 * b3 - 3.0 * b2 + 1.0) * r0 + (b3 - 2.0 * b2 + b) * e0 + (3.0 * b2 - 2.0 * b3) * r1 +
-               (b3 - b2) * e1;
+    const float4* c = tab + 4 * (int64_t(j) * kTabND + i);
+    const float4 q0 = c[0], q2 = c[1], q3 = c[2], q1 = c[3];
+    auto cubic = [a](float4 q) {
+        return fma(fma(fma(double(q.w), a, double(q.z)), a, double(q.y)), a, double(q.x));
+    };
+    const double p0 = cubic(q0), p2 = cubic(q2), p3 = cubic(q3), p1 = fma(double(q1.y), a, double(q1.x));
+    double H = fma(fma(fma(p3, b, p2), b, p1), b, p0);
     H = fmax(H, 0.0);
     return T(H * ib * ib * ib);
 }

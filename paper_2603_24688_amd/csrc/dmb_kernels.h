@@ -2107,7 +2107,9 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
 
 // ---------------------------------------------------------------------------
 // Overlap table (Appendix D), built on the device from the exact overlap.
-__global__ __launch_bounds__(256) void k_gtab_build(float4* __restrict__ tab)
+// Overlap-table nodes in binary64: (H, dH/ddelta * ddelta, dH/deta * deta)
+// per node, derivatives by central differences of the exact overlap.
+__global__ __launch_bounds__(256) void k_gtab_build(double* __restrict__ nodes)
 {
     int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int nx = kTabND + 1, ny = kTabNE + 1;
@@ -2124,7 +2126,44 @@ __global__ __launch_bounds__(256) void k_gtab_build(float4* __restrict__ tab)
     double dHd = delta == 0.0 ? 0.0 : (H(delta + st, eta) - H(fmax(delta - st, 0.0), eta)) / (delta + st - fmax(delta - st, 0.0));
     double el = fmax(eta - st, 0.0), eh = fmin(eta + st, 1.0);
     double dHe = (H(delta, eh) - H(delta, el)) / (eh - el);
-    tab[id] = make_float4(float(h0), float(dHd * dd), float(dHe * de), 0.f);
+    nodes[3 * id] = h0;
+    nodes[3 * id + 1] = dHd * dd;
+    nodes[3 * id + 2] = dHe * de;
+}
+
+// Cell coefficients of the table interpolant from the four corner nodes
+// (layout in the comment above overlap_g_table).
+__global__ __launch_bounds__(256) void k_gtab_cells(const double* __restrict__ nodes, float4* __restrict__ tab)
+{
+    int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (id >= int64_t(kTabCells)) return;
+    const int i = int(id % kTabND), j = int(id / kTabND);
+    auto node = [&](int ii, int jj, int k) { return nodes[3 * (int64_t(jj) * (kTabND + 1) + ii) + k]; };
+    // Hermite along delta on the two eta rows: r(a) = R[0] + R[1] a + R[2] a^2 + R[3] a^3
+    double R0[4], R1[4];
+    for (int row = 0; row < 2; ++row) {
+        const double v0 = node(i, j + row, 0), d0 = node(i, j + row, 1);
+        const double v1 = node(i + 1, j + row, 0), d1 = node(i + 1, j + row, 1);
+        double* R = row == 0 ? R0 : R1;
+        R[0] = v0;
+        R[1] = d0;
+        R[2] = 3.0 * (v1 - v0) - 2.0 * d0 - d1;
+        R[3] = 2.0 * (v0 - v1) + d0 + d1;
+    }
+    // eta-derivative, linear along delta
+    const double E0[2] = {node(i, j, 2), node(i + 1, j, 2) - node(i, j, 2)};
+    const double E1[2] = {node(i, j + 1, 2), node(i + 1, j + 1, 2) - node(i, j + 1, 2)};
+    // Hermite along eta: H = r0 + e0 b + (3 (r1 - r0) - 2 e0 - e1) b^2 + (2 (r0 - r1) + e0 + e1) b^3
+    double P2[4], P3[4];
+    for (int k = 0; k < 4; ++k) {
+        P2[k] = 3.0 * (R1[k] - R0[k]) - (k < 2 ? 2.0 * E0[k] + E1[k] : 0.0);
+        P3[k] = 2.0 * (R0[k] - R1[k]) + (k < 2 ? E0[k] + E1[k] : 0.0);
+    }
+    float4* c = tab + 4 * id;
+    c[0] = make_float4(float(R0[0]), float(R0[1]), float(R0[2]), float(R0[3]));
+    c[1] = make_float4(float(P2[0]), float(P2[1]), float(P2[2]), float(P2[3]));
+    c[2] = make_float4(float(P3[0]), float(P3[1]), float(P3[2]), float(P3[3]));
+    c[3] = make_float4(float(E0[0]), float(E0[1]), 0.f, 0.f);
 }
 
 template <typename Real>
