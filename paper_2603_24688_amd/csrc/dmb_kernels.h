@@ -1072,7 +1072,8 @@ __device__ __forceinline__ void test_chunk(PairTest& T, TestLds& S, const PassGe
     stage_sync<W>();    // the previous chunk's groups are done with the descriptors
     int cnt = 0;
     // lane j holds chunk sub-tile j: box lo (offsets from the owner-tile centre) and max h,
-    // box hi and the clean flag; the owner loop below reads them lane by lane
+    // box hi and the sub-tile's share of the reach slack, 4e-6 (Q2 + hmax^2), or -1 when the
+    // sub-tile is not clean; the owner loop below reads them lane by lane
     float4 blo = make_float4(0.f, 0.f, 0.f, 0.f), bhi = make_float4(0.f, 0.f, 0.f, 0.f);
     if (lane < nch) {
         const uint32_t ot = G.cand[T.c0 + lane];
@@ -1086,7 +1087,12 @@ __device__ __forceinline__ void test_chunk(PairTest& T, TestLds& S, const PassGe
         blo = make_float4(float(Bx[0] + sh[0] - cen[0]), float(Bx[1] + sh[1] - cen[1]), float(Bx[2] + sh[2] - cen[2]),
                           float(G.thmax[ot]));
         bhi = make_float4(float(Bx[3] + sh[0] - cen[0]), float(Bx[4] + sh[1] - cen[1]), float(Bx[5] + sh[2] - cen[2]),
-                          clean ? 1.f : 0.f);
+                          -1.f);
+        if (clean) {
+            const float Q2 = fmaxf(blo.x * blo.x, bhi.x * bhi.x) + fmaxf(blo.y * blo.y, bhi.y * bhi.y) +
+                             fmaxf(blo.z * blo.z, bhi.z * bhi.z);
+            bhi.w = 4e-6f * (Q2 + blo.w * blo.w);
+        }
         uint32_t pk = 0u;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -1099,21 +1105,19 @@ __device__ __forceinline__ void test_chunk(PairTest& T, TestLds& S, const PassGe
     stage_sync<W>();
     float fx = T.fx, fy = T.fy, fz = T.fz, fh = T.fh;     // opaque copies: not hoisted out of the item loop
     asm volatile("" : "+v"(fx), "+v"(fy), "+v"(fz), "+v"(fh));
-    const float ap2 = fx * fx + fy * fy + fz * fz, ah2 = fh * fh;
+    const float ao = 4e-6f * (fx * fx + fy * fy + fz * fz + fh * fh);   // the owner's share of the slack
     uint64_t actA = 0ull, actB = 0ull;
     for (int j = 0; j < nch; ++j) {
         const float4 lo = make_float4(lane_get(blo.x, j), lane_get(blo.y, j), lane_get(blo.z, j), lane_get(blo.w, j));
         const float4 hi = make_float4(lane_get(bhi.x, j), lane_get(bhi.y, j), lane_get(bhi.z, j), lane_get(bhi.w, j));
         bool near = T.ov;
-        if (hi.w != 0.f) {
+        if (hi.w >= 0.f) {
             const float gx = fmaxf(0.f, fmaxf(lo.x - fx, fx - hi.x));
             const float gy = fmaxf(0.f, fmaxf(lo.y - fy, fy - hi.y));
             const float gz = fmaxf(0.f, fmaxf(lo.z - fz, fz - hi.z));
             const float gap2 = fmaf(gx, gx, fmaf(gy, gy, gz * gz));
-            const float Q2 = fmaxf(lo.x * lo.x, hi.x * hi.x) + fmaxf(lo.y * lo.y, hi.y * hi.y) +
-                             fmaxf(lo.z * lo.z, hi.z * hi.z);
             const float hs = fh + lo.w;
-            const float reach2 = fmaf(hs, hs, 4e-6f * (ap2 + ah2 + Q2 + lo.w * lo.w)) * (1.f + 1e-5f);
+            const float reach2 = fmaf(hs, hs, ao + hi.w) * (1.f + 1e-5f);
             near = T.ov && gap2 < reach2;
         }
         const uint64_t om = __ballot(near);
