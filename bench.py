@@ -34,8 +34,9 @@ VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 # round of 64 pairs (lane = pair) - hit decode, binary64 distance recheck,
 # pair body (DM pass: overlap table, Philox4x32-10, Box-Muller, P_ij; gas
 # pass: overlap table, relative velocity, erf/exp rate terms) and the
-# segmented sums over the round's lanes.
-PAIR_BODY_VALU = {"pass_dm": 396, "pass_gas": 355}
+# segmented sums over the round's lanes (the periodic minimum-image blocks,
+# never taken in a non-periodic box, are not counted).
+PAIR_BODY_VALU = {"pass_dm": 352, "pass_gas": 348}
 
 
 def log(msg):
