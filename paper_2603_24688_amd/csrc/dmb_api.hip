@@ -89,7 +89,7 @@ struct dmb_ctx {
     DevBuf counters_local;
     DevBuf rb_dev;                         // build-stage scalars for the host (one copy per stage)
     uint64_t* rb_host = nullptr;           // pinned
-    int split = 64;
+    int split = 32;                        // candidate sub-tiles per work item (tunable)
     int subtile_delta = 1;                 // (tunable) sub-tile cut: Morton level below (median - delta)
     int grid_pct = 100;                    // (tunable) persistent grid size, % of the resident maximum
     int batch_n = 0;                       // boxes of the last batch build
