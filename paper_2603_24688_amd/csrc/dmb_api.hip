@@ -49,10 +49,11 @@ struct Species {
 
 struct Pairs {                             // candidate lists: owner tiles of A x sub-tiles of B
     // (owner tile, candidate super-tile) pairs: per-tile counts and offsets, the pairs, their sub-tile masks
-    DevBuf cnt, off, psup, ptile, mask, pcnt, soff;
+    DevBuf cnt, off, psup, ptile, mask, pcnt, soff, pw, woff;
     DevBuf pad, maxcnt;                    // count-pass copy of the first pad_cap super-tiles per tile; largest count
     // candidate sub-tiles: per-tile counts and starts, the lists, work items
-    DevBuf scnt, beg, cand, icnt, ioff, it_tile, it_cb, it_ce;
+    DevBuf scnt, beg, swt, cand, icnt, ioff, it_tile, it_cb, it_ce;
+    DevBuf it_key, it_key2, it_id, it_ord;  // item order (largest first): sort keys, item ids, order
     int pad_cap = 128;                     // grown from the largest count seen
     int64_t npairs = 0, total = 0, nitems = 0;
 };
@@ -85,6 +86,7 @@ struct dmb_ctx {
     DevBuf bstep, bgeom, bitem;            // batched step: Philox step offset, per-box pass arguments, item offsets
     DevBuf scan_tmp[4];
     DevBuf sort_tmp;                       // radix-sort temporary storage
+    DevBuf sort_table;                     // digit counts per block (one-pass counting sort)
     DevBuf bbox_part;
     DevBuf counters_local;
     DevBuf rb_dev;                         // build-stage scalars for the host (one copy per stage)
@@ -209,6 +211,24 @@ dmb_status scan_excl(dmb_ctx* c, const TI* in, TO* out, int64_t n, int level = 0
     return DMB_OK;
 }
 
+// One stable counting-sort pass over the 8-bit digit of the keys at `shift`.
+dmb_status digit_pass(dmb_ctx* c, const uint64_t* ka, const uint32_t* va, uint64_t* kb, uint32_t* vb, int64_t n,
+                      int shift)
+{
+    if (n <= 0) return DMB_OK;
+    const int nblk = int((n + kSortTile - 1) / kSortTile);
+    const int64_t tsz = int64_t(256) * nblk;
+    ENSURE(c, c->sort_table, size_t(tsz + 1) * 4);
+    hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(kSortBlock), 0, c->stream, ka, n, shift,
+                       c->sort_table.as<uint32_t>(), nblk);
+    dmb_status s = scan_excl(c, c->sort_table.as<uint32_t>(), c->sort_table.as<uint32_t>(), tsz);
+    if (s != DMB_OK) return s;
+    hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(kSortBlock), 0, c->stream, ka, va, kb, vb, n, shift,
+                       c->sort_table.as<const uint32_t>(), nblk);
+    HIPCHK(c, hipGetLastError());
+    return DMB_OK;
+}
+
 int bits_for(int64_t n)
 {
     int b = 1;
@@ -254,7 +274,15 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
     const int lo_bit = std::max(0, 63 - 8 * passes);
     uint64_t *ka = S.keys.as<uint64_t>(), *kb = S.keys2.as<uint64_t>();
     uint32_t *va = S.vals.as<uint32_t>(), *vb = S.vals2.as<uint32_t>();
-    {
+    if (n < (int64_t(1) << 21)) {
+        // small species: one counting-sort pass per 8-bit digit (fewer launches than the library sort)
+        for (int ps = 0; ps < passes; ++ps) {
+            dmb_status s = digit_pass(c, ka, va, kb, vb, n, lo_bit + 8 * ps);
+            if (s != DMB_OK) return s;
+            std::swap(ka, kb);
+            std::swap(va, vb);
+        }
+    } else {
         rocprim::double_buffer<uint64_t> kd(ka, kb);
         rocprim::double_buffer<uint32_t> vd(va, vb);
         size_t tmp = 0;
@@ -390,6 +418,7 @@ dmb_status cand_subs(dmb_ctx* c, Species& A, Species& B, Pairs& P)
     const int64_t np = P.npairs;
     ENSURE(c, P.psup, np * 4); ENSURE(c, P.ptile, np * 4);
     ENSURE(c, P.mask, np * 8); ENSURE(c, P.pcnt, (np + 1) * 4); ENSURE(c, P.soff, (np + 1) * 8);
+    ENSURE(c, P.pw, (np + 1) * 4); ENSURE(c, P.woff, (np + 1) * 8); ENSURE(c, P.swt, (nt + 1) * 4);
     CandArgs a = cand_args(c, A, B, P);
     hipLaunchKernelGGL(k_cand<true>, dim3(unsigned((nt + kXcd - 1) / kXcd * kXcd)), dim3(64), 0, c->stream, a);
     SubMaskArgs m;
@@ -398,15 +427,19 @@ dmb_status cand_subs(dmb_ctx* c, Species& A, Species& B, Pairs& P)
     m.obox = A.obox.as<const double>(); m.oh = A.oh.as<const double>();
     m.tq = B.tq.as<const float4>();
     for (int k = 0; k < 3; ++k) m.L[k] = c->X->built_L[k];
-    m.mask = P.mask.as<uint64_t>(); m.pcnt = P.pcnt.as<uint32_t>();
+    m.sub_cnt = B.sub_cnt.as<const uint32_t>();
+    m.mask = P.mask.as<uint64_t>(); m.pcnt = P.pcnt.as<uint32_t>(); m.pw = P.pw.as<uint32_t>();
     hipLaunchKernelGGL(k_sub_masks, dim3(unsigned((np + kSubPairs - 1) / kSubPairs)), dim3(64), 0, c->stream, m);
     HIPCHK(c, hipMemsetAsync(P.pcnt.as<uint32_t>() + np, 0, 4, c->stream));
+    HIPCHK(c, hipMemsetAsync(P.pw.as<uint32_t>() + np, 0, 4, c->stream));
     // candidate offsets in 64 bits (totals pass 2^32 at Milky-Way sizes)
     dmb_status s = scan_excl<uint32_t, uint64_t>(c, P.pcnt.as<const uint32_t>(), P.soff.as<uint64_t>(), np + 1);
     if (s != DMB_OK) return s;
+    s = scan_excl<uint32_t, uint64_t>(c, P.pw.as<const uint32_t>(), P.woff.as<uint64_t>(), np + 1);
+    if (s != DMB_OK) return s;
     hipLaunchKernelGGL(k_tile_subs, dim3(blocks_for(nt + 1, 256)), dim3(256), 0, c->stream, nt,
-                       P.off.as<const uint64_t>(), P.soff.as<const uint64_t>(), P.scnt.as<uint32_t>(),
-                       P.beg.as<uint64_t>());
+                       P.off.as<const uint64_t>(), P.soff.as<const uint64_t>(), P.woff.as<const uint64_t>(),
+                       P.scnt.as<uint32_t>(), P.beg.as<uint64_t>(), P.swt.as<uint32_t>());
     hipLaunchKernelGGL(k_item_count, dim3(blocks_for(nt + 1, 256)), dim3(256), 0, c->stream,
                        P.scnt.as<const uint32_t>(), nt, uint32_t(c->split), P.icnt.as<uint32_t>());
     s = scan_excl(c, P.icnt.as<const uint32_t>(), P.ioff.as<uint32_t>(), nt + 1);
@@ -427,9 +460,16 @@ dmb_status cand_write(dmb_ctx* c, Species& A, Species& B, Pairs& P)
     hipLaunchKernelGGL(k_expand, dim3(blocks_for(P.npairs, 256)), dim3(256), 0, c->stream, P.npairs,
                        P.psup.as<const uint32_t>(), P.mask.as<const uint64_t>(), P.soff.as<const uint64_t>(),
                        P.cand.as<uint32_t>());
-    hipLaunchKernelGGL(k_item_write, dim3(blocks_for(P.nitems, 256)), dim3(256), 0, c->stream, P.beg.as<const uint64_t>(),
-                       P.scnt.as<const uint32_t>(), P.ioff.as<const uint32_t>(), nt, P.nitems, uint32_t(c->split),
-                       P.it_tile.as<uint32_t>(), P.it_cb.as<uint64_t>(), P.it_ce.as<uint64_t>());
+    const int64_t ni = P.nitems;
+    ENSURE(c, P.it_key, std::max<int64_t>(ni, 1) * 8); ENSURE(c, P.it_key2, std::max<int64_t>(ni, 1) * 8);
+    ENSURE(c, P.it_id, std::max<int64_t>(ni, 1) * 4); ENSURE(c, P.it_ord, std::max<int64_t>(ni, 1) * 4);
+    hipLaunchKernelGGL(k_item_write, dim3(blocks_for(ni, 256)), dim3(256), 0, c->stream, P.beg.as<const uint64_t>(),
+                       P.scnt.as<const uint32_t>(), P.swt.as<const uint32_t>(), P.ioff.as<const uint32_t>(), nt, ni,
+                       P.it_tile.as<uint32_t>(), P.it_cb.as<uint64_t>(), P.it_ce.as<uint64_t>(),
+                       P.it_key.as<uint64_t>(), P.it_id.as<uint32_t>());
+    dmb_status s = digit_pass(c, P.it_key.as<const uint64_t>(), P.it_id.as<const uint32_t>(), P.it_key2.as<uint64_t>(),
+                              P.it_ord.as<uint32_t>(), ni, 0);
+    if (s != DMB_OK) return s;
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
 }
@@ -499,6 +539,7 @@ PassGeom geom(Cells& X, Species& A, Species& B, Pairs& P, uint64_t* counters)
     g.sub_start = B.sub_start.as<const uint32_t>(); g.sub_cnt = B.sub_cnt.as<const uint32_t>();
     g.cand = P.cand.as<const uint32_t>();
     g.item_off = P.ioff.as<const uint32_t>();
+    g.item_order = P.it_ord.as<const uint32_t>();
     g.it_tile = P.it_tile.as<const uint32_t>(); g.it_cb = P.it_cb.as<const uint64_t>();
     g.it_ce = P.it_ce.as<const uint64_t>(); g.n_items = P.nitems;
     g.queue_ctr = X.qctr.as<uint32_t>();
@@ -1041,7 +1082,8 @@ void free_cells(Cells& X)
     for (Pairs* P : {&X.gp, &X.dp}) {
         DevBuf* all[] = {&P->cnt, &P->off, &P->cand, &P->icnt, &P->ioff, &P->it_tile, &P->it_cb, &P->it_ce,
                          &P->pad, &P->maxcnt, &P->beg, &P->psup, &P->ptile, &P->mask, &P->pcnt, &P->soff,
-                         &P->scnt};
+                         &P->scnt, &P->pw, &P->woff, &P->swt, &P->it_key, &P->it_key2, &P->it_id,
+                         &P->it_ord};
         for (DevBuf* b : all) fr(*b);
     }
     DevBuf* rest[] = {&X.boxL, &X.part_gas, &X.part_p, &X.part_pm, &X.part_nb, &X.psum_own, &X.qctr, &X.slist};
@@ -1123,7 +1165,7 @@ dmb_status dmb_destroy(dmb_ctx* c)
                      &c->mlp_loss, &c->mlp_epoch, &c->mlp_shuf};
     for (DevBuf* b : mlp) fr(*b);
     if (c->train_stream) hipStreamDestroy(c->train_stream);
-    DevBuf* rest[] = {&c->gl64, &c->gl32, &c->gtab, &c->bbox_part, &c->counters_local,
+    DevBuf* rest[] = {&c->gl64, &c->gl32, &c->gtab, &c->sort_table, &c->bbox_part, &c->counters_local,
                       &c->bstep, &c->bgeom, &c->bitem, &c->rb_dev, &c->sort_tmp};
     for (DevBuf* b : rest) fr(*b);
     if (c->rb_host) hipHostFree(c->rb_host);

@@ -634,7 +634,8 @@ struct SubMaskArgs {
     const double* obox; const double* oh;          // owner tiles
     const float4* tq;                              // sub-tile nodes (write_node_q layout)
     double L[3];
-    uint64_t* mask; uint32_t* pcnt;                // per pair
+    const uint32_t* sub_cnt;                       // particles per sub-tile
+    uint64_t* mask; uint32_t* pcnt; uint32_t* pw;  // per pair: sub-tile mask, its count and its particles
 };
 
 constexpr int kSubPairs = 4;       // pairs per wave, their node loads in flight together
@@ -666,10 +667,13 @@ __global__ __launch_bounds__(64) void k_sub_masks(SubMaskArgs a)
         const bool hit = p0 + u < a.npairs && st[u] < a.ntile &&
                          node_near(alo, ahi, __double2float_ru(a.oh[t]), nq[u], Lf, dL);
         const uint64_t m = __ballot(hit);
+        const int sc = int(a.sub_cnt[st[u] < a.ntile ? st[u] : 0]);
+        const int w = wave_incl_scan(hit ? sc : 0);
         if (lane == 0 && p0 + u < a.npairs) {
             a.mask[p0 + u] = m;
             a.pcnt[p0 + u] = uint32_t(__popcll(m));
         }
+        if (lane == 63 && p0 + u < a.npairs) a.pw[p0 + u] = uint32_t(w);
     }
 }
 
@@ -686,11 +690,13 @@ __global__ __launch_bounds__(256) void k_expand(int64_t npairs, const uint32_t* 
     for (int k = 0; m; ++k, m &= m - 1) dst[k] = s0 + uint32_t(__ffsll((unsigned long long)m) - 1);
 }
 
-// Per owner tile: its candidate sub-tile count and where its list starts
-// (poff: pair offsets per tile, soff: sub-tile offsets per pair).
+// Per owner tile: its candidate sub-tile count, where its list starts and
+// the particles of its candidates (poff: pair offsets per tile, soff and
+// woff: sub-tile and particle offsets per pair).
 __global__ __launch_bounds__(256) void k_tile_subs(int64_t nt, const uint64_t* __restrict__ poff,
-                                                   const uint64_t* __restrict__ soff, uint32_t* __restrict__ scnt,
-                                                   uint64_t* __restrict__ sbeg)
+                                                   const uint64_t* __restrict__ soff, const uint64_t* __restrict__ woff,
+                                                   uint32_t* __restrict__ scnt, uint64_t* __restrict__ sbeg,
+                                                   uint32_t* __restrict__ swt)
 {
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t > nt) return;
@@ -698,9 +704,11 @@ __global__ __launch_bounds__(256) void k_tile_subs(int64_t nt, const uint64_t* _
     const uint64_t b = soff[poff[t]], e = soff[poff[t + 1]];
     sbeg[t] = b;
     scnt[t] = uint32_t(e - b);
+    swt[t] = uint32_t(min<uint64_t>(woff[poff[t + 1]] - woff[poff[t]], 0xFFFFFFFFull));
 }
 
-// Work items: candidate lists split into pieces of at most `split` sub-tiles.
+// Work items: each tile's candidate list cut into equal pieces of at most
+// `split` sub-tiles.
 __global__ __launch_bounds__(256) void k_item_count(const uint32_t* __restrict__ cnt, int64_t nt, uint32_t split,
                                                     uint32_t* __restrict__ icnt)
 {
@@ -710,11 +718,17 @@ __global__ __launch_bounds__(256) void k_item_count(const uint32_t* __restrict__
 }
 
 // Item it: its tile t (binary search over item_off), and the piece of t's
-// list (cnt[t] sub-tiles from beg[t]) it covers.
+// list (cnt[t] sub-tiles from beg[t]) it covers: piece k of n holds
+// candidates [k cnt / n, (k + 1) cnt / n).  Also a sort key that orders the
+// items by decreasing candidate particles (wt: per tile; the item takes its
+// share of the tile's), so that a pass starts the largest ones first and
+// ends on small ones.
 __global__ __launch_bounds__(256) void k_item_write(const uint64_t* __restrict__ beg, const uint32_t* __restrict__ cnt,
+                                                    const uint32_t* __restrict__ wt,
                                                     const uint32_t* __restrict__ item_off, int64_t nt, int64_t nitems,
-                                                    uint32_t split, uint32_t* __restrict__ it_tile,
-                                                    uint64_t* __restrict__ it_cb, uint64_t* __restrict__ it_ce)
+                                                    uint32_t* __restrict__ it_tile, uint64_t* __restrict__ it_cb,
+                                                    uint64_t* __restrict__ it_ce, uint64_t* __restrict__ it_key,
+                                                    uint32_t* __restrict__ it_id)
 {
     const int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (it >= nitems) return;
@@ -723,10 +737,15 @@ __global__ __launch_bounds__(256) void k_item_write(const uint64_t* __restrict__
         const int64_t mid = (lo + hi) >> 1;
         if (int64_t(item_off[mid]) <= it) lo = mid; else hi = mid;
     }
-    const uint64_t cb = beg[lo] + uint64_t(it - int64_t(item_off[lo])) * split, ce = beg[lo] + cnt[lo];
+    const uint64_t n = item_off[lo + 1] - item_off[lo], k = uint64_t(it - int64_t(item_off[lo])), c = cnt[lo];
+    const uint64_t cb = k * c / n, ce = (k + 1) * c / n;
     it_tile[it] = uint32_t(lo);
-    it_cb[it] = cb;
-    it_ce[it] = min(ce, cb + uint64_t(split));
+    it_cb[it] = beg[lo] + cb;
+    it_ce[it] = beg[lo] + ce;
+    // 8-bit key, 1/12 octave per step: 255 for an empty item, smaller for larger ones
+    const double w = double(wt[lo]) * double(ce - cb) / double(max<uint64_t>(c, 1));
+    it_key[it] = 255u - uint32_t(fmin(255.0, 12.0 * log2(w + 1.0)));
+    it_id[it] = uint32_t(it);
 }
 
 // ---------------------------------------------------------------------------
@@ -873,6 +892,7 @@ struct PassGeom {
     const uint32_t* cand;         // candidate other sub-tiles
     const uint32_t* it_tile; const uint64_t* it_cb; const uint64_t* it_ce;
     const uint32_t* item_off;     // [owner tiles + 1] item ranges per owner tile
+    const uint32_t* item_order;   // items in the order they are dealt (largest first)
     int64_t n_items;
     uint32_t* queue_ctr;          // [kXcd] work counters
     double L[3];
@@ -1376,6 +1396,7 @@ void k_pass_gas(
         const Real* rb = reinterpret_cast<const Real*>(a.rb);
         const Real* rr = reinterpret_cast<const Real*>(a.rr);
         const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
+        it = G.item_order[it];
         const int64_t t = G.it_tile[it];
         const uint64_t cb = G.it_cb[it], ce = G.it_ce[it];
         const int64_t slot = t * kTile + lane;
@@ -1659,6 +1680,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
         const Real* dtr = reinterpret_cast<const Real*>(a.dtr);
         const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
         const uint32_t step = a.step + (a.step_off ? *a.step_off : 0u);
+        it = G.item_order[it];
         const int64_t t = G.it_tile[it];
         const uint64_t cb = G.it_cb[it], ce = G.it_ce[it];
         const int64_t slot = t * kTile + lane;

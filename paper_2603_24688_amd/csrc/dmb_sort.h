@@ -1,5 +1,6 @@
-// dmb_sort.h -- device-wide exclusive scan (the Morton sort itself is
-// rocPRIM's radix sort).
+// dmb_sort.h -- device-wide exclusive scan and one-pass stable counting
+// sort by an 8-bit digit (64-bit keys, 32-bit payload): the Morton sort of
+// small species and the ordering of work items.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -58,6 +59,77 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(TO* __restrict__ out, c
     for (int k = 0; k < kScanItems; ++k) {
         int64_t i = base + int64_t(k) * kScanBlock;
         if (i < n) out[i] += add;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort, 8-bit digits.  Each block owns kSortTile
+// consecutive keys; per-block digit counts are scanned digit-major so the
+// scatter keeps the input order of equal digits.
+constexpr int kSortBlock = 256;
+constexpr int kSortRounds = 16;
+constexpr int kSortTile = kSortBlock * kSortRounds;  // 4096
+
+__global__ __launch_bounds__(kSortBlock) void k_sort_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                                                          uint32_t* __restrict__ table, int nblocks)
+{
+    __shared__ uint32_t hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = int64_t(blockIdx.x) * kSortTile;
+    for (int r = 0; r < kSortRounds; ++r) {
+        int64_t i = base + int64_t(r) * kSortBlock + threadIdx.x;
+        if (i < n) atomicAdd(&hist[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    table[int64_t(threadIdx.x) * nblocks + blockIdx.x] = hist[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const uint64_t* __restrict__ keys_in,
+                                                             const uint32_t* __restrict__ vals_in,
+                                                             uint64_t* __restrict__ keys_out,
+                                                             uint32_t* __restrict__ vals_out, int64_t n, int shift,
+                                                             const uint32_t* __restrict__ table, int nblocks)
+{
+    __shared__ uint32_t boff[256];
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[kSortBlock / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    boff[tid] = table[int64_t(tid) * nblocks + blockIdx.x];
+    run[tid] = 0;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t base = int64_t(blockIdx.x) * kSortTile;
+    for (int r = 0; r < kSortRounds; ++r) {
+#pragma unroll
+        for (int w = 0; w < kSortBlock / 64; ++w) wcnt[w][tid] = 0;
+        __syncthreads();
+        int64_t i = base + int64_t(r) * kSortBlock + tid;
+        bool valid = i < n;
+        uint64_t key = valid ? keys_in[i] : 0ull;
+        uint32_t val = valid ? vals_in[i] : 0u;
+        uint32_t d = uint32_t(key >> shift) & 255u;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t bal = __ballot(valid && ((d >> b) & 1u));
+            m &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        int rank = __popcll(m & lt);
+        if (valid && rank == 0) wcnt[wid][d] = uint32_t(__popcll(m));
+        __syncthreads();
+        if (valid) {
+            uint32_t pre = 0;
+            for (int w = 0; w < wid; ++w) pre += wcnt[w][d];
+            uint32_t pos = boff[d] + run[d] + pre + uint32_t(rank);
+            keys_out[pos] = key;
+            vals_out[pos] = val;
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+#pragma unroll
+        for (int w = 0; w < kSortBlock / 64; ++w) tot += wcnt[w][tid];
+        run[tid] += tot;
+        __syncthreads();
     }
 }
 
