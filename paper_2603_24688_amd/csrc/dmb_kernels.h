@@ -81,6 +81,32 @@ __device__ __forceinline__ T dpp_take_max(T v, bool take)
     const T t = dpp_move<CTRL, ROWS>(v);
     return take && t > v ? t : v;
 }
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dpp_take_min(T v, bool take)
+{
+    const T t = dpp_move<CTRL, ROWS>(v);
+    return take && t < v ? t : v;
+}
+
+// Segmented inclusive scan upward over the wave: segments are runs of
+// consecutive lanes, `lo` the first lane of this lane's run.  f(ctrl, rows,
+// take) is called for six steps (four row shifts, then the two row
+// broadcasts); folding the moved copies in where `take` holds leaves every
+// lane with the combination of lanes [lo, lane] in a fixed order, so the
+// run's total sits in its last lane.
+template <typename F>
+__device__ __forceinline__ void seg_scan_up(int lane, int lo, F&& f)
+{
+    using std::integral_constant;
+    const int row0 = lane & ~15;
+    const int lr = max(lo, row0);   // first lane of the run within this lane's row
+    f(integral_constant<int, 0x111>(), integral_constant<int, 0xF>(), lane - 1 >= lr);
+    f(integral_constant<int, 0x112>(), integral_constant<int, 0xF>(), lane - 2 >= lr);
+    f(integral_constant<int, 0x114>(), integral_constant<int, 0xF>(), lane - 4 >= lr);
+    f(integral_constant<int, 0x118>(), integral_constant<int, 0xF>(), lane - 8 >= lr);
+    f(integral_constant<int, 0x142>(), integral_constant<int, 0xA>(), (lane & 16) != 0 && lo < row0);
+    f(integral_constant<int, 0x143>(), integral_constant<int, 0xC>(), lane >= 32 && lo <= 31);
+}
 
 // Inclusive prefix sum over the wave's lanes (v >= 0), in registers: four
 // row shifts, then the row broadcasts carry row totals upward.
@@ -388,27 +414,6 @@ __global__ __launch_bounds__(64) void k_subtile_count(const uint64_t* __restrict
     if (lane_id() == 0) cnt[blockIdx.x] = uint32_t(__popcll(cm));
 }
 
-// Segmented reductions over runs of lanes: lane l ends with the min / max over
-// lanes [l, seg_end] (seg_end is shared by the lanes of a run).
-__device__ __forceinline__ double seg_min_d(double v, int lane, int seg_end)
-{
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double t = __shfl_down(v, d);
-        if (lane + d <= seg_end) v = fmin(v, t);
-    }
-    return v;
-}
-__device__ __forceinline__ double seg_max_d(double v, int lane, int seg_end)
-{
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double t = __shfl_down(v, d);
-        if (lane + d <= seg_end) v = fmax(v, t);
-    }
-    return v;
-}
-
 // Support box of one particle coordinate: [x - h, x + h] widened by a few
 // units in the last place, so that it holds the exact interval.
 __device__ __forceinline__ double sup_lo(double x, double h) { const double v = x - h; return v - 4e-16 * fabs(v); }
@@ -432,25 +437,39 @@ __global__ __launch_bounds__(64) void k_subtile_write(const uint64_t* __restrict
     const uint64_t cm = subtile_cuts(keys, n, lo_bit, cut_delta, c);
     const uint64_t above = lane == 63 ? 0ull : (cm >> (lane + 1));
     const int next = above ? lane + __ffsll((unsigned long long)above) : m;
-    const int seg_end = next - 1;
     const bool valid = lane < m;
+    // first lane of this lane's sub-tile (a run of lanes); lanes past the chunk end stand alone
+    const uint64_t upto = cm & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+    const int lo = valid && upto ? 63 - __clzll(upto) : lane;
     const int64_t kk = valid ? k : c * kTile;
     const double x3[3] = {sx[kk], sy[kk], sz[kk]};
     const double hh = sh[kk];
     double b[6], u[6];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        b[a] = seg_min_d(x3[a], lane, seg_end);
-        b[3 + a] = seg_max_d(x3[a], lane, seg_end);
-        u[a] = seg_min_d(sup_lo(x3[a], hh), lane, seg_end);
-        u[3 + a] = seg_max_d(sup_hi(x3[a], hh), lane, seg_end);
+        b[a] = x3[a];
+        b[3 + a] = x3[a];
+        u[a] = sup_lo(x3[a], hh);
+        u[3 + a] = sup_hi(x3[a], hh);
     }
-    const double hm = seg_max_d(hh, lane, seg_end);
-    if (valid && ((cm >> lane) & 1ull)) {
-        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    double hm = hh;
+    // segmented minima / maxima over each run, in registers; totals at the run's last lane
+    seg_scan_up(lane, lo, [&](auto ctl, auto rows, bool take) {
+        constexpr int C = decltype(ctl)::value, R = decltype(rows)::value;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            b[a] = dpp_take_min<C, R>(b[a], take);
+            b[3 + a] = dpp_take_max<C, R>(b[3 + a], take);
+            u[a] = dpp_take_min<C, R>(u[a], take);
+            u[3 + a] = dpp_take_max<C, R>(u[3 + a], take);
+        }
+        hm = dpp_take_max<C, R>(hm, take);
+    });
+    if (valid && lane == next - 1) {
+        const uint64_t lt = lo == 0 ? 0ull : (~0ull >> (64 - lo));
         const int64_t idx = int64_t(off[c]) + __popcll(cm & lt);
-        sub_start[idx] = uint32_t(k);
-        sub_cnt[idx] = uint32_t(next - lane);
+        sub_start[idx] = uint32_t(c * kTile + lo);
+        sub_cnt[idx] = uint32_t(next - lo);
 #pragma unroll
         for (int a = 0; a < 6; ++a) { box[6 * idx + a] = b[a]; sup[6 * idx + a] = u[a]; }
         hmax[idx] = hm;
@@ -648,6 +667,7 @@ __global__ __launch_bounds__(64) void k_sub_masks(SubMaskArgs a)
     const float dL = 1e-6f * fmaxf(Lf[0], fmaxf(Lf[1], Lf[2]));
     float4 nq[kSubPairs][4];
     int64_t st[kSubPairs], tl[kSubPairs];
+    int sc[kSubPairs];
 #pragma unroll
     for (int u = 0; u < kSubPairs; ++u) {     // loads first, all in flight
         const int64_t p = p0 + u < a.npairs ? p0 + u : 0;
@@ -656,6 +676,7 @@ __global__ __launch_bounds__(64) void k_sub_masks(SubMaskArgs a)
         const int64_t si = st[u] < a.ntile ? st[u] : 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) nq[u][k] = a.tq[4 * si + k];
+        sc[u] = int(a.sub_cnt[si]);
     }
 #pragma unroll
     for (int u = 0; u < kSubPairs; ++u) {
@@ -667,8 +688,7 @@ __global__ __launch_bounds__(64) void k_sub_masks(SubMaskArgs a)
         const bool hit = p0 + u < a.npairs && st[u] < a.ntile &&
                          node_near(alo, ahi, __double2float_ru(a.oh[t]), nq[u], Lf, dL);
         const uint64_t m = __ballot(hit);
-        const int sc = int(a.sub_cnt[st[u] < a.ntile ? st[u] : 0]);
-        const int w = wave_incl_scan(hit ? sc : 0);
+        const int w = wave_incl_scan(hit ? sc[u] : 0);
         if (lane == 0 && p0 + u < a.npairs) {
             a.mask[p0 + u] = m;
             a.pcnt[p0 + u] = uint32_t(__popcll(m));
@@ -960,25 +980,6 @@ __device__ __forceinline__ bool item_next(uint32_t* queue_ctr, int64_t n_items, 
     return *it < n_items;
 }
 
-// Segmented inclusive scan upward over the wave: segments are runs of
-// consecutive lanes, `lo` the first lane of this lane's run.  f(ctrl, rows,
-// take) is called for six steps (four row shifts, then the two row
-// broadcasts); folding the moved copies in where `take` holds leaves every
-// lane with the combination of lanes [lo, lane] in a fixed order, so the
-// run's total sits in its last lane.
-template <typename F>
-__device__ __forceinline__ void seg_scan_up(int lane, int lo, F&& f)
-{
-    using std::integral_constant;
-    const int row0 = lane & ~15;
-    const int lr = max(lo, row0);   // first lane of the run within this lane's row
-    f(integral_constant<int, 0x111>(), integral_constant<int, 0xF>(), lane - 1 >= lr);
-    f(integral_constant<int, 0x112>(), integral_constant<int, 0xF>(), lane - 2 >= lr);
-    f(integral_constant<int, 0x114>(), integral_constant<int, 0xF>(), lane - 4 >= lr);
-    f(integral_constant<int, 0x118>(), integral_constant<int, 0xF>(), lane - 8 >= lr);
-    f(integral_constant<int, 0x142>(), integral_constant<int, 0xA>(), (lane & 16) != 0 && lo < row0);
-    f(integral_constant<int, 0x143>(), integral_constant<int, 0xC>(), lane >= 32 && lo <= 31);
-}
 
 // Bits [b, e) of a wave-uniform mask, tested for any set bit (0 <= b <= e <= 64).
 __device__ __forceinline__ bool any_bits(uint64_t m, int b, int e)
