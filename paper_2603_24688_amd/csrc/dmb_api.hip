@@ -258,9 +258,13 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
     ENSURE(c, S.keys, n * 8); ENSURE(c, S.keys2, n * 8);
     ENSURE(c, S.vals, n * 4); ENSURE(c, S.vals2, n * 4);
     ENSURE(c, S.cube, 8 * sizeof(double));
-    const int nparts = 256;
-    ENSURE(c, c->bbox_part, nparts * 6 * sizeof(double));
-    hipLaunchKernelGGL(k_bbox_partial, dim3(nparts), dim3(256), 0, c->stream, p->pos, n, c->bbox_part.as<double>());
+    // bounding box (k_bbox_final takes [0, L) when L_x > 0, so the partial pass is skipped
+    // then); enough blocks to fill the chip
+    const bool periodic = c->X->built_L[0] > 0.0;
+    const int nparts = periodic ? 0 : int(std::min<int64_t>(2048, (n + 1023) / 1024));
+    ENSURE(c, c->bbox_part, std::max(nparts, 1) * 6 * sizeof(double));
+    if (nparts > 0)
+        hipLaunchKernelGGL(k_bbox_partial, dim3(nparts), dim3(256), 0, c->stream, p->pos, n, c->bbox_part.as<double>());
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, c->stream, c->bbox_part.as<const double>(), nparts,
                        c->X->boxL.as<const double>(), S.cube.as<double>());
     ENSURE(c, S.prec, n * sizeof(double4));

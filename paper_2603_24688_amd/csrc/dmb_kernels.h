@@ -320,12 +320,14 @@ __global__ __launch_bounds__(64) void k_tile_bounds(const uint32_t* __restrict__
     double x = v ? sx[p] : 1e300, y = v ? sy[p] : 1e300, z = v ? sz[p] : 1e300;
     double X = v ? sx[p] : -1e300, Y = v ? sy[p] : -1e300, Z = v ? sz[p] : -1e300;
     double hh = v ? sh[p] : 0.0;
-    for (int d = 32; d >= 1; d >>= 1) {
-        x = fmin(x, __shfl_xor(x, d)); y = fmin(y, __shfl_xor(y, d)); z = fmin(z, __shfl_xor(z, d));
-        X = fmax(X, __shfl_xor(X, d)); Y = fmax(Y, __shfl_xor(Y, d)); Z = fmax(Z, __shfl_xor(Z, d));
-        hh = fmax(hh, __shfl_xor(hh, d));
-    }
-    if (lane_id() == 0) {
+    // minima / maxima over the wave in registers; totals at lane 63
+    seg_scan_up(lane_id(), 0, [&](auto ctl, auto rows, bool take) {
+        constexpr int C = decltype(ctl)::value, R = decltype(rows)::value;
+        x = dpp_take_min<C, R>(x, take); y = dpp_take_min<C, R>(y, take); z = dpp_take_min<C, R>(z, take);
+        X = dpp_take_max<C, R>(X, take); Y = dpp_take_max<C, R>(Y, take); Z = dpp_take_max<C, R>(Z, take);
+        hh = dpp_take_max<C, R>(hh, take);
+    });
+    if (lane_id() == 63) {
         box[6 * t + 0] = x; box[6 * t + 1] = y; box[6 * t + 2] = z;
         box[6 * t + 3] = X; box[6 * t + 4] = Y; box[6 * t + 5] = Z;
         hmax[t] = hh;
@@ -360,16 +362,18 @@ __global__ __launch_bounds__(64) void k_super_bounds(int64_t ntile, const double
         u[3 + a] = v ? tsup[6 * t + 3 + a] : -1e300;
     }
     double hh = v ? th[t] : 0.0;
-    for (int d = 32; d >= 1; d >>= 1) {
+    seg_scan_up(lane_id(), 0, [&](auto ctl, auto rows, bool take) {
+        constexpr int C = decltype(ctl)::value, R = decltype(rows)::value;
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
-            b[a] = fmin(b[a], __shfl_xor(b[a], d));
-            b[3 + a] = fmax(b[3 + a], __shfl_xor(b[3 + a], d));
-            u[a] = fmin(u[a], __shfl_xor(u[a], d));
-            u[3 + a] = fmax(u[3 + a], __shfl_xor(u[3 + a], d));
+            b[a] = dpp_take_min<C, R>(b[a], take);
+            b[3 + a] = dpp_take_max<C, R>(b[3 + a], take);
+            u[a] = dpp_take_min<C, R>(u[a], take);
+            u[3 + a] = dpp_take_max<C, R>(u[3 + a], take);
         }
-        hh = fmax(hh, __shfl_xor(hh, d));
-    }
-    if (lane_id() == 0) {
+        hh = dpp_take_max<C, R>(hh, take);
+    });
+    if (lane_id() == 63) {
         for (int a = 0; a < 6; ++a) { box[6 * s + a] = b[a]; sup[6 * s + a] = u[a]; }
         hmax[s] = hh;
         write_node_q(q + 4 * s, b, hh, u);
