@@ -253,9 +253,15 @@ struct RateCoef {
     }
 };
 
+// Taylor terms for x < 1: binary64 keeps 22; binary32 keeps the fewest whose
+// tail (the series alternate) stays below 3e-8 of the value at x = 1.
 template <typename T> struct RealTraits;
-template <> struct RealTraits<float> { static constexpr int kTaylor = 12; };
-template <> struct RealTraits<double> { static constexpr int kTaylor = 22; };
+template <> struct RealTraits<float> {
+    template <int N> static constexpr int taylor() { return N == -4 ? 11 : (N == -2 ? 9 : 8); }
+};
+template <> struct RealTraits<double> {
+    template <int N> static constexpr int taylor() { return 22; }
+};
 
 __device__ __forceinline__ float erf_real(float x) { return erff(x); }
 __device__ __forceinline__ double erf_real(double x) { return erf(x); }
@@ -267,7 +273,7 @@ __device__ __forceinline__ void rate_1f1(T x, T* FA, T* FB)
 {
     constexpr RateCoef<N> C{};
     if (x < T(1)) {
-        constexpr int K = RealTraits<T>::kTaylor;
+        constexpr int K = RealTraits<T>::template taylor<N>();
         T fa = T(C.ca[K - 1]), fb = T(C.cb[K - 1]);
 #pragma unroll
         for (int k = K - 2; k >= 0; --k) {
