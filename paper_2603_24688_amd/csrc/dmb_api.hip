@@ -91,7 +91,8 @@ struct dmb_ctx {
     DevBuf counters_local;
     DevBuf rb_dev;                         // build-stage scalars for the host (one copy per stage)
     uint64_t* rb_host = nullptr;           // pinned
-    int split = 32;                        // candidate sub-tiles per work item (tunable)
+    int split = 32;                        // candidate sub-tiles per work item of the DM pass (tunable);
+                                           // the gas pass, whose partial sums cost more to combine, twice that
     int subtile_delta = 1;                 // (tunable) sub-tile cut: Morton level below (median - delta)
     int grid_pct = 100;                    // (tunable) persistent grid size, % of the resident maximum
     int batch_n = 0;                       // boxes of the last batch build
@@ -445,7 +446,8 @@ dmb_status cand_subs(dmb_ctx* c, Species& A, Species& B, Pairs& P)
                        P.off.as<const uint64_t>(), P.soff.as<const uint64_t>(), P.woff.as<const uint64_t>(),
                        P.scnt.as<uint32_t>(), P.beg.as<uint64_t>(), P.swt.as<uint32_t>());
     hipLaunchKernelGGL(k_item_count, dim3(blocks_for(nt + 1, 256)), dim3(256), 0, c->stream,
-                       P.scnt.as<const uint32_t>(), nt, uint32_t(c->split), P.icnt.as<uint32_t>());
+                       P.scnt.as<const uint32_t>(), nt, uint32_t(&P == &c->X->gp ? 2 * c->split : c->split),
+                       P.icnt.as<uint32_t>());
     s = scan_excl(c, P.icnt.as<const uint32_t>(), P.ioff.as<uint32_t>(), nt + 1);
     if (s != DMB_OK) return s;
     HIPCHK(c, hipGetLastError());
