@@ -593,13 +593,9 @@ dmb_status gather_and_fill(dmb_ctx* c, Cells& X, const dmb_particles* gas, const
         hipLaunchKernelGGL(k_gather_gas<Real>, dim3(blocks_for(G.n, 256)), dim3(256), 0, c->stream, ga);
     }
     if (D.n > 0) {
-        ENSURE(c, D.v0, D.n * 8); ENSURE(c, D.v1, D.n * 8); ENSURE(c, D.v2, D.n * 8);
-        ENSURE(c, D.r0, D.n * rs); ENSURE(c, D.r1, D.n * rs);
         DmGatherArgs da;
         da.n = D.n; da.perm = D.perm; da.vel = dm->vel; da.mass = dm->mass; da.dt = dm->dt;
         da.dt_default = par->dt;
-        da.vx = D.v0.as<double>(); da.vy = D.v1.as<double>(); da.vz = D.v2.as<double>();
-        da.dtr = D.r1.p;
         ENSURE(c, D.rec, D.n * (sizeof(Real) == 4 ? sizeof(DmRec<float>) : sizeof(DmRec<double>)));
         da.rec = D.rec.p;
         hipLaunchKernelGGL(k_gather_dm<Real>, dim3(blocks_for(D.n, 256)), dim3(256), 0, c->stream, da);
@@ -677,8 +673,7 @@ DmPassArgs dm_pass_args(dmb_ctx* c, Cells& X, const dmb_params* par, dmb_out* ou
     DmPassArgs a;
     a.g = geom(X, D, G, X.dp, counters);
     a.g.queue_ctr = X.qctr.as<uint32_t>() + kXcd;
-    a.vx = D.v0.as<const double>(); a.vy = D.v1.as<const double>(); a.vz = D.v2.as<const double>();
-    a.dtr = D.r1.p; a.dm_perm = D.perm;
+    a.drec = D.rec.p; a.dm_perm = D.perm;
     a.Vx = G.v0.as<const double>(); a.Vy = G.v1.as<const double>(); a.Vz = G.v2.as<const double>();
     a.grec = G.rec.p;
     a.gtab = c->gtab.as<const float4>();
@@ -712,7 +707,7 @@ void combine_dm_and_resolve(dmb_ctx* c, Cells& X, const DmPassArgs& a, const dmb
     ResolveArgs r;
     r.g = a.g;
     r.cand_beg = X.dp.beg.as<const uint64_t>(); r.cand_cnt = X.dp.scnt.as<const uint32_t>();
-    r.vx = a.vx; r.vy = a.vy; r.vz = a.vz; r.dtr = a.dtr; r.dm_perm = a.dm_perm;
+    r.drec = a.drec; r.dm_perm = a.dm_perm;
     r.grec = a.grec;
     r.gas_vel = gas->vel; r.gas_u = gas->u; r.gas_mu = gas->mu; r.m_chi = par->m_chi_g;
     r.gtab = a.gtab; r.k0 = a.k0; r.k1 = a.k1; r.step = a.step; r.box = a.box; r.step_off = a.step_off;
@@ -811,8 +806,6 @@ dmb_status batch_prepare(dmb_ctx* c, int nbox, const dmb_particles* gas, const d
             ENSURE(c, G.rec, G.n * (sizeof(Real) == 4 ? sizeof(GasRec<float>) : sizeof(GasRec<double>)));
         }
         if (D.n > 0) {
-            ENSURE(c, D.v0, D.n * 8); ENSURE(c, D.v1, D.n * 8); ENSURE(c, D.v2, D.n * 8);
-            ENSURE(c, D.r0, D.n * rs); ENSURE(c, D.r1, D.n * rs);
             ENSURE(c, D.rec, D.n * (sizeof(Real) == 4 ? sizeof(DmRec<float>) : sizeof(DmRec<double>)));
         }
         uint64_t* counters = out[b].counters;

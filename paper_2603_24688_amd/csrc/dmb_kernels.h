@@ -782,9 +782,10 @@ template <typename Real> struct alignas(16) GasRec {   // gas, read by the DM pa
     Real vs, K, crit;             // sqrt(2 u / 3), K_j, P threshold
     uint32_t perm;                // sorted position -> gas index
 };
-template <typename Real> struct alignas(16) DmRec {    // DM, read by the gas pass
+template <typename Real> struct alignas(16) DmRec {    // DM, read by the gas pass (other) and the DM pass (owner)
     double vx, vy, vz;            // velocity
     Real m;                       // mass
+    Real dt;                      // timestep
 };
 
 struct GasGatherArgs {
@@ -841,8 +842,6 @@ struct DmGatherArgs {
     const uint32_t* perm;
     const double* vel; const double* mass; const double* dt;
     double dt_default;
-    double* vx; double* vy; double* vz;
-    void* dtr;
     void* rec;                    // DmRec<Real>[n]
 };
 
@@ -852,13 +851,10 @@ __global__ __launch_bounds__(256) void k_gather_dm(DmGatherArgs a)
     int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= a.n) return;
     uint32_t o = a.perm[k];
-    a.vx[k] = a.vel[3 * int64_t(o)];
-    a.vy[k] = a.vel[3 * int64_t(o) + 1];
-    a.vz[k] = a.vel[3 * int64_t(o) + 2];
-    reinterpret_cast<Real*>(a.dtr)[k] = Real(a.dt ? a.dt[o] : a.dt_default);
     DmRec<Real> r;
     r.vx = a.vel[3 * int64_t(o)]; r.vy = a.vel[3 * int64_t(o) + 1]; r.vz = a.vel[3 * int64_t(o) + 2];
     r.m = Real(a.mass[o]);
+    r.dt = Real(a.dt ? a.dt[o] : a.dt_default);
     reinterpret_cast<DmRec<Real>*>(a.rec)[k] = r;
 }
 
@@ -1573,8 +1569,7 @@ void k_pass_gas(
 // DM (Monte Carlo) pass: owners = active DM, others = gas.
 struct DmPassArgs {
     PassGeom g;
-    const double* vx; const double* vy; const double* vz;    // DM velocities, sorted
-    const void* dtr;                                          // DM dt (Real), sorted
+    const void* drec;                                         // DmRec<Real>, sorted DM (velocity, mass, dt)
     const uint32_t* dm_perm;                                  // DM sorted pos -> index
     const double* Vx; const double* Vy; const double* Vz;     // gas, sorted
     const void* grec;                                         // GasRec<Real>, sorted gas
@@ -1682,7 +1677,6 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
         }
         const DmPassArgs& a = BATCH ? boxes[b] : a0;
         const PassGeom& G = a.g;
-        const Real* dtr = reinterpret_cast<const Real*>(a.dtr);
         const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
         const uint32_t step = a.step + (a.step_off ? *a.step_off : 0u);
         it = G.item_order[it];
@@ -1695,8 +1689,12 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
         const double mh = ov ? G.oh[sp] : 0.0;
         __syncthreads();
         o_x[lane] = mx; o_y[lane] = my; o_z[lane] = mz; o_h[lane] = mh;
-        o_vx[lane] = ov ? a.vx[sp] : 0.0; o_vy[lane] = ov ? a.vy[sp] : 0.0; o_vz[lane] = ov ? a.vz[sp] : 0.0;
-        o_dt[lane] = ov ? dtr[sp] : Real(0);
+        {
+            DmRec<Real> orc{0.0, 0.0, 0.0, Real(0), Real(0)};
+            if (ov) orc = reinterpret_cast<const DmRec<Real>*>(a.drec)[sp];
+            o_vx[lane] = orc.vx; o_vy[lane] = orc.vy; o_vz[lane] = orc.vz;
+            o_dt[lane] = orc.dt;
+        }
         o_id[lane] = ov ? a.dm_perm[sp] : 0u;
         double A[6];
         for (int k = 0; k < 6; ++k) A[k] = G.obox[6 * t + k];
@@ -1893,7 +1891,7 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine_dm(DmCombineArgs
 struct ResolveArgs {
     PassGeom g;                   // owners = DM, others = gas sub-tiles (as in the DM pass)
     const uint64_t* cand_beg; const uint32_t* cand_cnt;   // each owner tile's candidate list
-    const double* vx; const double* vy; const double* vz; const void* dtr; const uint32_t* dm_perm;
+    const void* drec; const uint32_t* dm_perm;
     const void* grec;                                         // GasRec<Real>, sorted gas
     const double* gas_vel; const double* gas_u; const double* gas_mu;   // raw gas inputs (partner kick)
     double m_chi;
@@ -1936,7 +1934,6 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
     const PassGeom& G = a.g;
     const int tid = threadIdx.x;
     const uint32_t step = a.step + (a.step_off ? *a.step_off : 0u);
-    const Real* dtr = reinterpret_cast<const Real*>(a.dtr);
     const uint32_t nsc = *a.scount;
     uint32_t nnearD = 0;
     for (uint32_t e = blockIdx.x; e < nsc; e += gridDim.x) {
@@ -1944,8 +1941,9 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
         const int64_t sp = G.own[s];
         const int64_t t = s / kTile;
         const double mx = G.ox[sp], my = G.oy[sp], mz = G.oz[sp], mh = G.oh[sp];
-        const double mvx = a.vx[sp], mvy = a.vy[sp], mvz = a.vz[sp];
-        const Real mdt = dtr[sp];
+        const DmRec<Real> orc = reinterpret_cast<const DmRec<Real>*>(a.drec)[sp];
+        const double mvx = orc.vx, mvy = orc.vy, mvz = orc.vz;
+        const Real mdt = orc.dt;
         const uint32_t oid = a.dm_perm[sp];
         U4 rd = philox_block(oid, 0xFFFFFFFFu, step, kTagDecision, a.box, a.k0, a.k1);
         const unsigned __int128 Ufix = (unsigned __int128)(2ull * (rd.x >> 8) + 1ull) << 39;
