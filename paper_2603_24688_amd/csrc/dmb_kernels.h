@@ -1714,7 +1714,9 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
                 // this owner's hits in the round: [s0, e0)
                 const int s0 = max(my_lo, base), e0 = min(my_hi, base + 64);
                 const uint32_t mark = round_marks(S, lane, base, s0, e0, my_lo);
-                double cP = 0.0;
+                // a round's per-owner sums of P_ij in the pair precision (binary32: at most 64 terms,
+                // a relative error below 6 units of 2^-24), accumulated over rounds in binary64
+                Real cP = 0;
                 Real cM = 0;
                 int cNB = 0;
                 int seg_lo = lane;
@@ -1735,7 +1737,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
                         const Real P = pair_P<Real, N, EXACT_G>(d2, o_h[o], qh, o_vx[o], o_vy[o], o_vz[o], r.Vx, r.Vy,
                                                                 r.Vz, r.vs, r.K, o_dt[o], o_id[o], r.perm, step, a.box,
                                                                 a.k0, a.k1, a.gtab, urel);
-                        cP = double(P);
+                        cP = P;
                         cM = P;
                         if (P >= r.crit) ncrit++;
                     }
@@ -1749,10 +1751,10 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
                 // the owner's sums of the round sit in the lane of its last hit
                 const bool has = s0 < e0;
                 const int src = has ? e0 - 1 - base : 0;
-                const double vP = __shfl(cP, src);
+                const Real vP = __shfl(cP, src);
                 const Real vM = __shfl(cM, src);
                 if (has) {
-                    accP += vP;
+                    accP += double(vP);
                     accM = accM > vM ? accM : vM;
                     accNB |= int(any_bits(nbm, s0 - base, e0 - base));
                 }
