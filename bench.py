@@ -36,7 +36,7 @@ VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 # pass: overlap table, relative velocity, erf/exp rate terms) and the
 # segmented sums over the round's lanes (the periodic minimum-image blocks,
 # never taken in a non-periodic box, are not counted).
-PAIR_BODY_VALU = {"pass_dm": 352, "pass_gas": 342}
+PAIR_BODY_VALU = {"pass_dm": 334, "pass_gas": 342}
 
 
 def log(msg):
