@@ -1917,7 +1917,7 @@ __device__ __forceinline__ void fixed_split(double P, unsigned long long* hi, un
     *lo = (unsigned long long)((pd - fl) * 4294967296.0);
 }
 
-constexpr int kResolveThreads = 256;  // four wavefronts per scattering DM
+constexpr int kResolveThreads = 1024; // sixteen wavefronts per scattering DM (the first 256 threads own the histogram bins)
 constexpr int kResolveList = 2048;    // candidate sub-tiles kept per scattering DM after the point test
 constexpr int kResolvePairs = 8192;   // pairs cached per scattering DM (LDS)
 
@@ -1932,7 +1932,9 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
     __shared__ uint32_t s_nrel, s_npairs, s_sel;
     __shared__ int s_near, s_found, s_lastnz;
     __shared__ unsigned __int128 s_cum[256], s_selb, s_sela;
-    static_assert(kResolveThreads == 256, "one thread per histogram bin");
+    __shared__ unsigned long long s_run[kResolveThreads];
+    static_assert(kResolveThreads >= 256 && kResolveThreads % 256 == 0, "thread t < 256 owns histogram bin t");
+    const bool bin_owner = threadIdx.x < 256;
     const PassGeom& G = a.g;
     const int tid = threadIdx.x;
     const uint32_t step = a.step + (a.step_off ? *a.step_off : 0u);
@@ -1977,21 +1979,21 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
             const uint32_t q0 = min(nl, uint32_t(tid) * per), q1 = min(nl, q0 + per);
             uint32_t run = 0;
             for (uint32_t q = q0; q < q1; ++q) run += s_pre[q];
-            hhi[tid] = run;
+            s_run[tid] = run;
             __syncthreads();
             for (int d = 1; d < kResolveThreads; d <<= 1) {
-                const unsigned long long y = tid >= d ? hhi[tid - d] : 0ull;
+                const unsigned long long y = tid >= d ? s_run[tid - d] : 0ull;
                 __syncthreads();
-                hhi[tid] += y;
+                s_run[tid] += y;
                 __syncthreads();
             }
-            uint32_t acc = uint32_t(hhi[tid]) - run;
+            uint32_t acc = uint32_t(s_run[tid]) - run;
             for (uint32_t q = q0; q < q1; ++q) {
                 const uint32_t v = s_pre[q];
                 s_pre[q] = acc;
                 acc += v;
             }
-            if (tid == kResolveThreads - 1) s_pre[nl] = uint32_t(hhi[tid]);
+            if (tid == kResolveThreads - 1) s_pre[nl] = uint32_t(s_run[tid]);
         }
         __syncthreads();
         // Pairs of this DM, enumerated over the flattened particles of the kept
@@ -2066,18 +2068,21 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
             // U_i, by an inclusive scan over the 256 bins (thread = bin)
             if (tid == 0) { s_found = 0; s_lastnz = -1; }
             __syncthreads();
-            const unsigned __int128 v = ((unsigned __int128)hhi[tid] << 32) + (unsigned __int128)hlo[tid];
-            s_cum[tid] = v;
-            if (v != 0) atomicMax(&s_lastnz, tid);
+            const int bt = tid & 255;
+            const unsigned __int128 v = ((unsigned __int128)hhi[bt] << 32) + (unsigned __int128)hlo[bt];
+            if (bin_owner) {
+                s_cum[tid] = v;
+                if (v != 0) atomicMax(&s_lastnz, tid);
+            }
             __syncthreads();
             for (int d = 1; d < 256; d <<= 1) {
-                const unsigned __int128 y = tid >= d ? s_cum[tid - d] : (unsigned __int128)0;
+                const unsigned __int128 y = bin_owner && tid >= d ? s_cum[tid - d] : (unsigned __int128)0;
                 __syncthreads();
-                s_cum[tid] += y;
+                if (bin_owner) s_cum[tid] += y;
                 __syncthreads();
             }
-            const unsigned __int128 incl = below + s_cum[tid], excl = incl - v;
-            if (excl <= Ufix && incl > Ufix) {      // unique: running sums increase, empty bins cannot pass
+            const unsigned __int128 incl = below + s_cum[bt], excl = incl - v;
+            if (bin_owner && excl <= Ufix && incl > Ufix) {      // unique: running sums increase, empty bins cannot pass
                 s_found = 1;
                 s_sel = uint32_t(tid);
                 s_selb = excl;
