@@ -1997,7 +1997,7 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
         }
         __syncthreads();
         // Pairs of this DM, enumerated over the flattened particles of the kept
-        // sub-tiles (four wavefronts in parallel).  Without a list (too many
+        // sub-tiles (all wavefronts of the block in parallel).  Without a list (too many
         // candidates) every candidate sub-tile is walked by one wavefront.
         auto for_pairs = [&](auto&& fn) {
             auto visit = [&](uint32_t ot, int kk) {
