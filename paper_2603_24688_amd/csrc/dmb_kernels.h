@@ -1167,17 +1167,18 @@ __device__ __forceinline__ int test_next(PairTest& T, TestLds& S, const PassGeom
         test_chunk<W>(T, S, G, A, cen);
     }
     stage_sync<W>();    // the previous group's decode is done with the slot table
-    // reached sub-tiles whose slots fall in [Ps, Ps + 64): a contiguous run
+    // reached sub-tiles whose slots overlap [Ps, Ps + 64): a contiguous run, the first of which
+    // may have begun in the previous group and the last may go on in the next (full groups)
     const bool act = ((T.actA | T.actB) >> lane) & 1ull;
     const int pre = S.dpre[lane], inc = S.dincl[lane];
-    const bool mem = act && pre >= T.Ps && inc <= T.Ps + 64;
+    const bool mem = act && inc > T.Ps && pre < T.Ps + 64;
     const uint64_t gm = __ballot(mem);
-    const int end = S.dincl[63 - __clzll(gm)];
+    const int end = min(S.dincl[63 - __clzll(gm)], T.Ps + 64);
     const int ns = end - T.Ps;
     const bool tileA = (T.actA & gm) != 0ull, tileB = (T.actB & gm) != 0ull;
     S.sj[lane] = 0;
     stage_sync<W>();
-    if (mem) S.sj[pre - T.Ps] = lane + 1;
+    if (mem) S.sj[max(pre - T.Ps, 0)] = lane + 1;
     stage_sync<W>();
     const int jm = int(wave_incl_umax(uint32_t(S.sj[lane]))) - 1;
     // lane L loads slot s
