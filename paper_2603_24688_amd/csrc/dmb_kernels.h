@@ -881,14 +881,14 @@ __global__ __launch_bounds__(256) void k_fill_out(int64_t n_gas, int64_t n_dm, d
 // Pair passes.  One wavefront per block owns a tile of 64 owners (lane =
 // owner) and walks its candidate sub-tiles of the other species in chunks of
 // up to 64.  Test phase: each owner is checked against every sub-tile box of
-// the chunk; the sub-tiles some owner reaches are packed into groups of at
-// most 64 particles ("slots"), and one group is tested against all 64 owners
-// at once as a dense binary32 product on the matrix cores (below), giving
-// one 64-bit hit mask over the slots per owner.  Evaluate phase: the group's
-// hits, ordered owner-major, are decoded 64 at a time (lane = pair); each
-// lane repeats the test exactly in binary64, evaluates the pair and the
-// owner's terms form a contiguous run of lanes, so a segmented suffix sum
-// over lanes (wavefront shuffles) leaves each run's total on its first lane,
+// the chunk; the particles ("slots") of the sub-tiles some owner reaches are
+// packed into groups of 64 (a sub-tile may straddle two groups), and one
+// group is tested against all 64 owners at once as a dense binary32 product
+// on the matrix cores (below), giving one 64-bit hit mask over the slots per
+// owner.  Evaluate phase: the group's hits, ordered owner-major, are decoded
+// 64 at a time (lane = pair); each lane repeats the test exactly in binary64
+// and evaluates the pair; an owner's terms form a contiguous run of lanes, so
+// a segmented scan in registers leaves each run's total on its last lane,
 // which the owner lane pulls.  No atomics touch physical quantities.
 constexpr float kTestMargin = 1.0f + 4e-6f;
 // Slack of the expanded binary32 test |a-b|^2 - (ha+hb)^2 = A + B - 2 (a.b + ha hb)
