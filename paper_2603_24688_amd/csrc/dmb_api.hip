@@ -193,18 +193,24 @@ struct Phase {
 inline unsigned blocks_for(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
 
 // Exclusive scan of n values (TI in, TO out and partial sums) into out (out
-// may equal in when the types agree).
+// may equal in when the types agree); inputs from n_in on (n_in <= n) read
+// as 0, so out[n_in] receives the total without touching in[n_in].
 template <typename TI = uint32_t, typename TO = uint32_t>
-dmb_status scan_excl(dmb_ctx* c, const TI* in, TO* out, int64_t n, int level = 0)
+dmb_status scan_excl(dmb_ctx* c, const TI* in, TO* out, int64_t n, int64_t n_in = -1, int level = 0)
 {
     if (n <= 0) return DMB_OK;
+    if (n_in < 0 || n_in > n) n_in = n;
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (level >= 4) return fail(c, DMB_EINVAL, "scan too large");
     ENSURE(c, c->scan_tmp[level], size_t(nb + 1) * sizeof(TO));
     TO* sums = c->scan_tmp[level].as<TO>();
-    hipLaunchKernelGGL((k_scan_block<TI, TO>), dim3(unsigned(nb)), dim3(kScanBlock), 0, c->stream, in, out, sums, n);
-    if (nb > 1) {
-        dmb_status s = scan_excl<TO, TO>(c, sums, sums, nb, level + 1);
+    hipLaunchKernelGGL((k_scan_block<TI, TO>), dim3(unsigned(nb)), dim3(kScanBlock), 0, c->stream, in, out, sums, n,
+                       n_in);
+    if (nb > 1 && nb <= kScanOwnMax) {
+        hipLaunchKernelGGL(k_scan_add_own<TO>, dim3(unsigned(nb)), dim3(kScanBlock), 0, c->stream, out,
+                           (const TO*)sums, n);
+    } else if (nb > 1) {
+        dmb_status s = scan_excl<TO, TO>(c, sums, sums, nb, nb, level + 1);
         if (s != DMB_OK) return s;
         hipLaunchKernelGGL(k_scan_add<TO>, dim3(unsigned(nb)), dim3(kScanBlock), 0, c->stream, out, sums, n);
     }
@@ -321,8 +327,7 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
     ENSURE(c, S.sub_ccnt, (S.nchunk + 1) * 4); ENSURE(c, S.sub_coff, (S.nchunk + 1) * 4);
     hipLaunchKernelGGL(k_subtile_count, dim3(unsigned(S.nchunk)), dim3(64), 0, c->stream,
                        S.keys.as<const uint64_t>(), n, S.sort_lo_bit, c->subtile_delta, S.sub_ccnt.as<uint32_t>());
-    HIPCHK(c, hipMemsetAsync(S.sub_ccnt.as<uint32_t>() + S.nchunk, 0, 4, c->stream));
-    s = scan_excl(c, S.sub_ccnt.as<const uint32_t>(), S.sub_coff.as<uint32_t>(), S.nchunk + 1);
+    s = scan_excl(c, S.sub_ccnt.as<const uint32_t>(), S.sub_coff.as<uint32_t>(), S.nchunk + 1, S.nchunk);
     if (s != DMB_OK) return s;
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
@@ -402,8 +407,7 @@ dmb_status cand_count(dmb_ctx* c, Species& A, Species& B, Pairs& P)
     CandArgs a = cand_args(c, A, B, P);
     const unsigned grid = unsigned((nt + kXcd - 1) / kXcd * kXcd);
     hipLaunchKernelGGL(k_cand<false>, dim3(grid), dim3(64), 0, c->stream, a);
-    HIPCHK(c, hipMemsetAsync(P.cnt.as<uint32_t>() + nt, 0, 4, c->stream));
-    dmb_status s = scan_excl<uint32_t, uint64_t>(c, P.cnt.as<const uint32_t>(), P.off.as<uint64_t>(), nt + 1);
+    dmb_status s = scan_excl<uint32_t, uint64_t>(c, P.cnt.as<const uint32_t>(), P.off.as<uint64_t>(), nt + 1, nt);
     if (s != DMB_OK) return s;
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
@@ -435,12 +439,11 @@ dmb_status cand_subs(dmb_ctx* c, Species& A, Species& B, Pairs& P)
     m.sub_cnt = B.sub_cnt.as<const uint32_t>();
     m.mask = P.mask.as<uint64_t>(); m.pcnt = P.pcnt.as<uint32_t>(); m.pw = P.pw.as<uint32_t>();
     hipLaunchKernelGGL(k_sub_masks, dim3(unsigned((np + kSubPairs - 1) / kSubPairs)), dim3(64), 0, c->stream, m);
-    HIPCHK(c, hipMemsetAsync(P.pcnt.as<uint32_t>() + np, 0, 4, c->stream));
-    HIPCHK(c, hipMemsetAsync(P.pw.as<uint32_t>() + np, 0, 4, c->stream));
     // candidate offsets in 64 bits (totals pass 2^32 at Milky-Way sizes)
-    dmb_status s = scan_excl<uint32_t, uint64_t>(c, P.pcnt.as<const uint32_t>(), P.soff.as<uint64_t>(), np + 1);
+    dmb_status s =
+        scan_excl<uint32_t, uint64_t>(c, P.pcnt.as<const uint32_t>(), P.soff.as<uint64_t>(), np + 1, np);
     if (s != DMB_OK) return s;
-    s = scan_excl<uint32_t, uint64_t>(c, P.pw.as<const uint32_t>(), P.woff.as<uint64_t>(), np + 1);
+    s = scan_excl<uint32_t, uint64_t>(c, P.pw.as<const uint32_t>(), P.woff.as<uint64_t>(), np + 1, np);
     if (s != DMB_OK) return s;
     hipLaunchKernelGGL(k_tile_subs, dim3(blocks_for(nt + 1, 256)), dim3(256), 0, c->stream, nt,
                        P.off.as<const uint64_t>(), P.soff.as<const uint64_t>(), P.woff.as<const uint64_t>(),

@@ -13,9 +13,10 @@ constexpr int kScanTile = kScanBlock * kScanItems;  // 1024
 
 // Block-local exclusive scan (inputs TI, sums and outputs TO: 64-bit outputs
 // for offsets that can pass 2^32); writes the block total to sums[blockIdx].
+// Inputs at or past n_in read as 0 (so that out[n_in] can hold the total).
 template <typename TI, typename TO>
 __global__ __launch_bounds__(kScanBlock) void k_scan_block(const TI* __restrict__ in, TO* __restrict__ out,
-                                                           TO* __restrict__ sums, int64_t n)
+                                                           TO* __restrict__ sums, int64_t n, int64_t n_in)
 {
     __shared__ TO wsum[kScanBlock / 64];
     int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
@@ -23,7 +24,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_block(const TI* __restrict_
     TO t = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        v[k] = (base + k < n) ? TO(in[base + k]) : TO(0);
+        v[k] = (base + k < n_in) ? TO(in[base + k]) : TO(0);
         t += v[k];
     }
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -47,6 +48,33 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_block(const TI* __restrict_
         TO tot = 0;
         for (int w = 0; w < kScanBlock / 64; ++w) tot += wsum[w];
         sums[blockIdx.x] = tot;
+    }
+}
+
+// Adds to block b's tile the totals of blocks 0 .. b-1, which the block sums
+// itself (for up to kScanOwnMax blocks), so the block totals need no scan of
+// their own.
+constexpr int64_t kScanOwnMax = 4096;
+
+template <typename TO>
+__global__ __launch_bounds__(kScanBlock) void k_scan_add_own(TO* __restrict__ out, const TO* __restrict__ sums,
+                                                             int64_t n)
+{
+    __shared__ TO part[kScanBlock / 64];
+    const int b = int(blockIdx.x);
+    if (b == 0) return;
+    TO acc = 0;
+    for (int k = int(threadIdx.x); k < b; k += kScanBlock) acc += sums[k];
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    TO add = 0;
+    for (int w = 0; w < kScanBlock / 64; ++w) add += part[w];
+    const int64_t base = int64_t(b) * kScanTile + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + int64_t(k) * kScanBlock;
+        if (i < n) out[i] += add;
     }
 }
 
