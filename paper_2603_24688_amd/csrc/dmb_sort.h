@@ -105,10 +105,15 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_hist(const uint64_t* __rest
     hist[threadIdx.x] = 0;
     __syncthreads();
     int64_t base = int64_t(blockIdx.x) * kSortTile;
-    for (int r = 0; r < kSortRounds; ++r) {
+    uint32_t dg[kSortRounds];
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {    // all loads in flight before the first count
         int64_t i = base + int64_t(r) * kSortBlock + threadIdx.x;
-        if (i < n) atomicAdd(&hist[(keys[i] >> shift) & 255u], 1u);
+        dg[r] = i < n ? uint32_t(keys[i] >> shift) & 255u : 256u;
     }
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r)
+        if (dg[r] < 256u) atomicAdd(&hist[dg[r]], 1u);
     __syncthreads();
     table[int64_t(threadIdx.x) * nblocks + blockIdx.x] = hist[threadIdx.x];
 }
@@ -127,14 +132,23 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const uint64_t* __r
     run[tid] = 0;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int64_t base = int64_t(blockIdx.x) * kSortTile;
+    uint64_t kr[kSortRounds];
+    uint32_t vr[kSortRounds];
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {    // the block's keys and values, all loads in flight at once
+        const int64_t i = base + int64_t(r) * kSortBlock + tid;
+        kr[r] = i < n ? keys_in[i] : 0ull;
+        vr[r] = i < n ? vals_in[i] : 0u;
+    }
+#pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
 #pragma unroll
         for (int w = 0; w < kSortBlock / 64; ++w) wcnt[w][tid] = 0;
         __syncthreads();
         int64_t i = base + int64_t(r) * kSortBlock + tid;
         bool valid = i < n;
-        uint64_t key = valid ? keys_in[i] : 0ull;
-        uint32_t val = valid ? vals_in[i] : 0u;
+        uint64_t key = kr[r];
+        uint32_t val = vr[r];
         uint32_t d = uint32_t(key >> shift) & 255u;
         uint64_t m = __ballot(valid);
 #pragma unroll
