@@ -310,10 +310,8 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
         std::swap(S.keys, S.keys2);
     }
     S.perm = S.vals.as<const uint32_t>();
+    // sorted position and h are gathered by k_subtile_write
     ENSURE(c, S.sx, n * 8); ENSURE(c, S.sy, n * 8); ENSURE(c, S.sz, n * 8); ENSURE(c, S.sh, n * 8);
-    hipLaunchKernelGGL(k_gather_pos, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, S.perm, n,
-                       S.prec.as<const double4>(), S.sx.as<double>(), S.sy.as<double>(), S.sz.as<double>(),
-                       S.sh.as<double>());
     // owners (active subset, Morton order)
     ENSURE(c, S.flag, (n + 1) * 4); ENSURE(c, S.flag_off, (n + 1) * 4); ENSURE(c, S.own, n * 4);
     hipLaunchKernelGGL(k_active_flags, dim3(blocks_for(n + 1, 256)), dim3(256), 0, c->stream, S.perm, n, p->active,
@@ -345,9 +343,9 @@ dmb_status build_subtiles(dmb_ctx* c, Species& S)
     hipLaunchKernelGGL(k_subtile_write, dim3(unsigned(S.nchunk)), dim3(64), 0, c->stream,
                        S.keys.as<const uint64_t>(), S.n, S.sort_lo_bit, c->subtile_delta,
                        S.sub_coff.as<const uint32_t>(), S.sub_start.as<uint32_t>(), S.sub_cnt.as<uint32_t>(),
-                       S.sx.as<const double>(), S.sy.as<const double>(), S.sz.as<const double>(),
-                       S.sh.as<const double>(), S.tbox.as<double>(), S.th.as<double>(), S.tsup.as<double>(),
-                       S.tq.as<float4>());
+                       S.perm, S.prec.as<const double4>(), S.sx.as<double>(), S.sy.as<double>(),
+                       S.sz.as<double>(), S.sh.as<double>(), S.tbox.as<double>(), S.th.as<double>(),
+                       S.tsup.as<double>(), S.tq.as<float4>());
     hipLaunchKernelGGL(k_super_bounds, dim3(unsigned(S.nsuper)), dim3(64), 0, c->stream, S.ntile,
                        S.tbox.as<const double>(), S.th.as<const double>(), S.tsup.as<const double>(),
                        S.sbox.as<double>(), S.shh.as<double>(), S.ssup.as<double>(), S.sq.as<float4>());

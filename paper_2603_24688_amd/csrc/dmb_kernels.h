@@ -253,7 +253,7 @@ __device__ __forceinline__ uint64_t spread21(uint64_t x)
 
 // Morton key of each particle (input order), plus a packed copy of its
 // position (wrapped into [0, L) when periodic) and h, so that the gather into
-// Morton order reads one 32-byte record per particle.
+// Morton order (in k_subtile_write) reads one 32-byte record per particle.
 __global__ __launch_bounds__(256) void k_morton(const double* __restrict__ pos, const double* __restrict__ h, int64_t n,
                                                 const double* __restrict__ cube, const double* __restrict__ boxL,
                                                 uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
@@ -274,21 +274,6 @@ __global__ __launch_bounds__(256) void k_morton(const double* __restrict__ pos, 
     keys[i] = spread21(q[0]) | (spread21(q[1]) << 1) | (spread21(q[2]) << 2);
     vals[i] = uint32_t(i);
     rec[i] = make_double4(p[0], p[1], p[2], h[i]);
-}
-
-// Sorted SoA copies of position and h from the packed records.
-__global__ __launch_bounds__(256) void k_gather_pos(const uint32_t* __restrict__ perm, int64_t n,
-                                                    const double4* __restrict__ rec, double* __restrict__ sx,
-                                                    double* __restrict__ sy, double* __restrict__ sz,
-                                                    double* __restrict__ sh)
-{
-    int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const double4 r = rec[perm[k]];
-    sx[k] = r.x;
-    sy[k] = r.y;
-    sz[k] = r.z;
-    sh[k] = r.w;
 }
 
 __global__ __launch_bounds__(256) void k_active_flags(const uint32_t* __restrict__ perm, int64_t n,
@@ -425,14 +410,17 @@ __device__ __forceinline__ double sup_hi(double x, double h) { const double v = 
 
 // Starts, counts and bounds of the sub-tiles of chunk c at off[c]...: box,
 // max h and support box (union of the particles' [x - h, x + h]), each a
-// segmented reduction over the sub-tile's run of lanes.
+// segmented reduction over the sub-tile's run of lanes.  Also writes the
+// chunk's sorted SoA position and h, gathered from the packed records.
 __global__ __launch_bounds__(64) void k_subtile_write(const uint64_t* __restrict__ keys, int64_t n, int lo_bit,
                                                       int cut_delta, const uint32_t* __restrict__ off,
                                                       uint32_t* __restrict__ sub_start, uint32_t* __restrict__ sub_cnt,
-                                                      const double* __restrict__ sx, const double* __restrict__ sy,
-                                                      const double* __restrict__ sz, const double* __restrict__ sh,
-                                                      double* __restrict__ box, double* __restrict__ hmax,
-                                                      double* __restrict__ sup, float4* __restrict__ q)
+                                                      const uint32_t* __restrict__ perm,
+                                                      const double4* __restrict__ rec, double* __restrict__ sx,
+                                                      double* __restrict__ sy, double* __restrict__ sz,
+                                                      double* __restrict__ sh, double* __restrict__ box,
+                                                      double* __restrict__ hmax, double* __restrict__ sup,
+                                                      float4* __restrict__ q)
 {
     const int lane = lane_id();
     const int64_t c = blockIdx.x;
@@ -446,8 +434,10 @@ __global__ __launch_bounds__(64) void k_subtile_write(const uint64_t* __restrict
     const uint64_t upto = cm & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
     const int lo = valid && upto ? 63 - __clzll(upto) : lane;
     const int64_t kk = valid ? k : c * kTile;
-    const double x3[3] = {sx[kk], sy[kk], sz[kk]};
-    const double hh = sh[kk];
+    const double4 r = rec[perm[kk]];
+    if (valid) { sx[k] = r.x; sy[k] = r.y; sz[k] = r.z; sh[k] = r.w; }
+    const double x3[3] = {r.x, r.y, r.z};
+    const double hh = r.w;
     double b[6], u[6];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
