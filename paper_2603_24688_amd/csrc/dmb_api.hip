@@ -51,10 +51,13 @@ struct Pairs {                             // candidate lists: owner tiles of A 
     // (owner tile, candidate super-tile) pairs: per-tile counts and offsets, the pairs, their sub-tile masks
     DevBuf cnt, off, psup, ptile, mask, pcnt, soff, pw, woff;
     DevBuf pad, maxcnt;                    // count-pass copy of the first pad_cap super-tiles per tile; largest count
+    // groups of 64 owner tiles: bounds (box, h, support, nodes), candidate counts and lists, a spare max
+    DevBuf gbox, gh, gsup, gq, gcnt, glist, gmax;
     // candidate sub-tiles: per-tile counts and starts, the lists, work items
     DevBuf scnt, beg, swt, cand, icnt, ioff, it_tile, it_cb, it_ce;
     DevBuf it_key, it_key2, it_id, it_ord;  // item order (largest first): sort keys, item ids, order
     int pad_cap = 128;                     // grown from the largest count seen
+    static constexpr int kGroupCap = 1024; // group list capacity (super-tiles); larger groups traverse
     int64_t npairs = 0, total = 0, nitems = 0;
 };
 
@@ -382,6 +385,7 @@ CandArgs cand_args(dmb_ctx* c, Species& A, Species& B, Pairs& P)
     a.cnt = P.cnt.as<uint32_t>(); a.off = P.off.as<const uint64_t>(); a.cand = P.cand.as<uint32_t>();
     a.pad = P.pad.as<uint32_t>(); a.pad_cap = P.pad_cap; a.maxcnt = P.maxcnt.as<uint32_t>();
     a.cand = P.psup.as<uint32_t>(); a.ptile = P.ptile.as<uint32_t>();
+    a.gcnt = P.gcnt.as<const uint32_t>(); a.glist = P.glist.as<const uint32_t>(); a.gcap = Pairs::kGroupCap;
     return a;
 }
 
@@ -402,6 +406,18 @@ dmb_status cand_count(dmb_ctx* c, Species& A, Species& B, Pairs& P)
     ENSURE(c, P.pad, std::max<int64_t>(1, nt * P.pad_cap) * 4);
     ENSURE(c, P.maxcnt, 4);
     HIPCHK(c, hipMemsetAsync(P.maxcnt.p, 0, 4, c->stream));
+    // group lists: a count pass over groups of 64 owner tiles, their lists kept in glist
+    const int64_t ng = (nt + kTile - 1) / kTile;
+    ENSURE(c, P.gbox, ng * 48); ENSURE(c, P.gh, ng * 8); ENSURE(c, P.gsup, ng * 48); ENSURE(c, P.gq, ng * 64);
+    ENSURE(c, P.gcnt, ng * 4); ENSURE(c, P.glist, ng * Pairs::kGroupCap * 4); ENSURE(c, P.gmax, 4);
+    hipLaunchKernelGGL(k_super_bounds, dim3(unsigned(ng)), dim3(64), 0, c->stream, nt, A.obox.as<const double>(),
+                       A.oh.as<const double>(), A.obox.as<const double>(), P.gbox.as<double>(), P.gh.as<double>(),
+                       P.gsup.as<double>(), P.gq.as<float4>());
+    CandArgs ga = cand_args(c, A, B, P);
+    ga.nown_tile = ng; ga.obox = P.gbox.as<const double>(); ga.oh = P.gh.as<const double>();
+    ga.cnt = P.gcnt.as<uint32_t>(); ga.pad = P.glist.as<uint32_t>(); ga.pad_cap = Pairs::kGroupCap;
+    ga.maxcnt = P.gmax.as<uint32_t>(); ga.gcnt = nullptr; ga.glist = nullptr;
+    hipLaunchKernelGGL(k_cand<false>, dim3(unsigned((ng + kXcd - 1) / kXcd * kXcd)), dim3(64), 0, c->stream, ga);
     CandArgs a = cand_args(c, A, B, P);
     const unsigned grid = unsigned((nt + kXcd - 1) / kXcd * kXcd);
     hipLaunchKernelGGL(k_cand<false>, dim3(grid), dim3(64), 0, c->stream, a);
@@ -1083,7 +1099,7 @@ void free_cells(Cells& X)
         DevBuf* all[] = {&P->cnt, &P->off, &P->cand, &P->icnt, &P->ioff, &P->it_tile, &P->it_cb, &P->it_ce,
                          &P->pad, &P->maxcnt, &P->beg, &P->psup, &P->ptile, &P->mask, &P->pcnt, &P->soff,
                          &P->scnt, &P->pw, &P->woff, &P->swt, &P->it_key, &P->it_key2, &P->it_id,
-                         &P->it_ord};
+                         &P->it_ord, &P->gbox, &P->gh, &P->gsup, &P->gq, &P->gcnt, &P->glist, &P->gmax};
         for (DevBuf* b : all) fr(*b);
     }
     DevBuf* rest[] = {&X.boxL, &X.part_gas, &X.part_p, &X.part_pm, &X.part_nb, &X.psum_own, &X.qctr, &X.slist};

@@ -543,6 +543,12 @@ __device__ __forceinline__ bool node_near(float4 alo, float4 ahi, float ah, cons
 // bits become each tile's candidate sub-tile list (ascending within a pair).
 // Splitting the levels keeps the per-tile work short: one owner tile whose
 // box spans much of the domain no longer holds up a whole launch.
+// Owner tiles come in groups of 64 consecutive tiles; a first count pass over
+// the groups (union box, max h) keeps each group's candidate list, and a
+// tile whose group list fits tests only that list's super-tiles.  The node
+// test only passes more easily as the owner box grows and h rises, so the
+// group list holds every candidate of its tiles, in the same ascending
+// order as the full traversal gives.
 struct CandArgs {
     int64_t nown_tile, ntile, nsuper, nmega;
     const double* obox; const double* oh;
@@ -555,6 +561,9 @@ struct CandArgs {
     int pad_cap;
     uint32_t* maxcnt;             // largest count (count pass)
     uint32_t* ptile;              // write mode: owner tile of each pair
+    const uint32_t* gcnt;         // per group of 64 owner tiles: candidate count (nullptr: no group lists)
+    const uint32_t* glist;        // [groups][gcap]: the group's candidates, valid when gcnt <= gcap
+    int gcap;
 };
 
 constexpr int kCandUnroll = 4;     // independent node tests in flight per lane
@@ -598,7 +607,35 @@ __global__ __launch_bounds__(64) void k_cand(CandArgs a)
     uint32_t count = 0;
     const uint64_t base = WRITE ? a.off[t] : 0ull;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    for (int64_t m0 = 0; m0 < a.nmega; m0 += 64) {
+    const uint32_t gn = a.gcnt ? a.gcnt[t / kTile] : ~0u;
+    if (gn <= uint32_t(a.gcap)) {
+        // the group's candidates, kCandUnroll rounds of 64 at a time
+        const uint32_t* gl = a.glist + (t / kTile) * int64_t(a.gcap);
+        for (uint32_t k0 = 0; k0 < gn; k0 += 64 * kCandUnroll) {
+            bool ok[kCandUnroll], hit[kCandUnroll];
+            int64_t sg[kCandUnroll];
+            float4 nq[kCandUnroll][4];
+#pragma unroll
+            for (int u = 0; u < kCandUnroll; ++u) {     // loads first, all in flight
+                const uint32_t k = k0 + uint32_t(u * 64 + lane);
+                ok[u] = k < gn;
+                sg[u] = ok[u] ? int64_t(gl[k]) : 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) nq[u][q] = a.sq[4 * sg[u] + q];
+            }
+#pragma unroll
+            for (int u = 0; u < kCandUnroll; ++u) hit[u] = ok[u] && node_near(alo, ahi, ah, nq[u], Lf, dL);
+#pragma unroll
+            for (int u = 0; u < kCandUnroll; ++u) {
+                const uint64_t b = __ballot(hit[u]);
+                const uint32_t k = count + uint32_t(__popcll(b & lt));
+                if (WRITE && hit[u]) { a.cand[base + k] = uint32_t(sg[u]); a.ptile[base + k] = uint32_t(t); }
+                if (!WRITE && hit[u] && k < uint32_t(a.pad_cap)) pad[k] = uint32_t(sg[u]);
+                count += uint32_t(__popcll(b));
+            }
+        }
+    }
+    for (int64_t m0 = 0; gn > uint32_t(a.gcap) && m0 < a.nmega; m0 += 64) {
         const int64_t mg = m0 + lane;
         const bool hm = mg < a.nmega && node_near(alo, ahi, ah, a.mq + 4 * mg, Lf, dL);
         uint64_t bm = __ballot(hm);
