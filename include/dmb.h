@@ -268,6 +268,18 @@ dmb_status dmb_profile_enable(dmb_ctx *ctx, int32_t on);
  * counts per phase (host arrays of DMB_NPHASES); reset != 0 clears them. */
 dmb_status dmb_profile_read(dmb_ctx *ctx, double *ms, int64_t *calls, int32_t reset);
 
+/* Candidate-search groups (a tuning control of the neighbour structure that
+ * dmb_build_cells forms for Sec. 2.4's pairs d_ij < h_i + h_j: which
+ * other-species super-tiles each owner tile of 64 owners may reach).
+ * Outputs never depend on it.  A first pass lists the candidates of each group of
+ * 64 consecutive owner tiles, keeping up to `cap` of them; each tile whose
+ * group list fits tests only that list, the others walk the full node
+ * hierarchy.  Both give the same candidate lists in the same order.
+ * cap = 0 turns the group pass off; default 1024.
+ * Applies to later dmb_build_cells / dmb_batch_build calls.  Errors:
+ * DMB_EINVAL for a null ctx or cap outside [0, 65536]. */
+dmb_status dmb_set_search_groups(dmb_ctx *ctx, int32_t cap);
+
 /* Structure of the last dmb_build_cells (host array of 10 int64):
  * [active gas, active DM, gas tiles, DM tiles, gas owner tiles, DM owner
  *  tiles, candidate (owner tile, sub-tile) pairs of the gas pass, of the DM

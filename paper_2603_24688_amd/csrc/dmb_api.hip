@@ -57,7 +57,6 @@ struct Pairs {                             // candidate lists: owner tiles of A 
     DevBuf scnt, beg, swt, cand, icnt, ioff, it_tile, it_cb, it_ce;
     DevBuf it_key, it_key2, it_id, it_ord;  // item order (largest first): sort keys, item ids, order
     int pad_cap = 128;                     // grown from the largest count seen
-    static constexpr int kGroupCap = 1024; // group list capacity (super-tiles); larger groups traverse
     int64_t npairs = 0, total = 0, nitems = 0;
 };
 
@@ -97,6 +96,7 @@ struct dmb_ctx {
     int split = 32;                        // candidate sub-tiles per work item of the DM pass (tunable);
                                            // the gas pass, whose partial sums cost more to combine, twice that
     int subtile_delta = 1;                 // (tunable) sub-tile cut: Morton level below (median - delta)
+    int group_cap = 1024;                  // candidate-search group list capacity (0: no group pass)
     int grid_pct = 100;                    // (tunable) persistent grid size, % of the resident maximum
     int batch_n = 0;                       // boxes of the last batch build
     DevBuf gl64, gl32;                     // Gauss-Legendre nodes [x | w] for the quadrature rates
@@ -385,7 +385,9 @@ CandArgs cand_args(dmb_ctx* c, Species& A, Species& B, Pairs& P)
     a.cnt = P.cnt.as<uint32_t>(); a.off = P.off.as<const uint64_t>(); a.cand = P.cand.as<uint32_t>();
     a.pad = P.pad.as<uint32_t>(); a.pad_cap = P.pad_cap; a.maxcnt = P.maxcnt.as<uint32_t>();
     a.cand = P.psup.as<uint32_t>(); a.ptile = P.ptile.as<uint32_t>();
-    a.gcnt = P.gcnt.as<const uint32_t>(); a.glist = P.glist.as<const uint32_t>(); a.gcap = Pairs::kGroupCap;
+    a.gcap = c->group_cap;
+    a.gcnt = c->group_cap > 0 ? P.gcnt.as<const uint32_t>() : nullptr;
+    a.glist = c->group_cap > 0 ? P.glist.as<const uint32_t>() : nullptr;
     return a;
 }
 
@@ -407,17 +409,20 @@ dmb_status cand_count(dmb_ctx* c, Species& A, Species& B, Pairs& P)
     ENSURE(c, P.maxcnt, 4);
     HIPCHK(c, hipMemsetAsync(P.maxcnt.p, 0, 4, c->stream));
     // group lists: a count pass over groups of 64 owner tiles, their lists kept in glist
-    const int64_t ng = (nt + kTile - 1) / kTile;
-    ENSURE(c, P.gbox, ng * 48); ENSURE(c, P.gh, ng * 8); ENSURE(c, P.gsup, ng * 48); ENSURE(c, P.gq, ng * 64);
-    ENSURE(c, P.gcnt, ng * 4); ENSURE(c, P.glist, ng * Pairs::kGroupCap * 4); ENSURE(c, P.gmax, 4);
-    hipLaunchKernelGGL(k_super_bounds, dim3(unsigned(ng)), dim3(64), 0, c->stream, nt, A.obox.as<const double>(),
-                       A.oh.as<const double>(), A.obox.as<const double>(), P.gbox.as<double>(), P.gh.as<double>(),
-                       P.gsup.as<double>(), P.gq.as<float4>());
-    CandArgs ga = cand_args(c, A, B, P);
-    ga.nown_tile = ng; ga.obox = P.gbox.as<const double>(); ga.oh = P.gh.as<const double>();
-    ga.cnt = P.gcnt.as<uint32_t>(); ga.pad = P.glist.as<uint32_t>(); ga.pad_cap = Pairs::kGroupCap;
-    ga.maxcnt = P.gmax.as<uint32_t>(); ga.gcnt = nullptr; ga.glist = nullptr;
-    hipLaunchKernelGGL(k_cand<false>, dim3(unsigned((ng + kXcd - 1) / kXcd * kXcd)), dim3(64), 0, c->stream, ga);
+    if (c->group_cap > 0) {
+        const int64_t ng = (nt + kTile - 1) / kTile;
+        ENSURE(c, P.gbox, ng * 48); ENSURE(c, P.gh, ng * 8); ENSURE(c, P.gsup, ng * 48); ENSURE(c, P.gq, ng * 64);
+        ENSURE(c, P.gcnt, ng * 4); ENSURE(c, P.glist, ng * c->group_cap * 4); ENSURE(c, P.gmax, 4);
+        hipLaunchKernelGGL(k_super_bounds, dim3(unsigned(ng)), dim3(64), 0, c->stream, nt,
+                           A.obox.as<const double>(), A.oh.as<const double>(), A.obox.as<const double>(),
+                           P.gbox.as<double>(), P.gh.as<double>(), P.gsup.as<double>(), P.gq.as<float4>());
+        CandArgs ga = cand_args(c, A, B, P);
+        ga.nown_tile = ng; ga.obox = P.gbox.as<const double>(); ga.oh = P.gh.as<const double>();
+        ga.cnt = P.gcnt.as<uint32_t>(); ga.pad = P.glist.as<uint32_t>(); ga.pad_cap = c->group_cap;
+        ga.maxcnt = P.gmax.as<uint32_t>(); ga.gcnt = nullptr; ga.glist = nullptr;
+        hipLaunchKernelGGL(k_cand<false>, dim3(unsigned((ng + kXcd - 1) / kXcd * kXcd)), dim3(64), 0, c->stream,
+                           ga);
+    }
     CandArgs a = cand_args(c, A, B, P);
     const unsigned grid = unsigned((nt + kXcd - 1) / kXcd * kXcd);
     hipLaunchKernelGGL(k_cand<false>, dim3(grid), dim3(64), 0, c->stream, a);
@@ -1204,6 +1209,14 @@ dmb_status dmb_build_stats(const dmb_ctx* c, int64_t* o)
     const int64_t v[10] = {c->X->gas.n_own, c->X->dm.n_own, c->X->gas.ntile, c->X->dm.ntile, c->X->gas.nown_tile, c->X->dm.nown_tile,
                            c->X->gp.total, c->X->dp.total, c->X->gp.nitems, c->X->dp.nitems};
     for (int k = 0; k < 10; ++k) o[k] = v[k];
+    return DMB_OK;
+}
+
+dmb_status dmb_set_search_groups(dmb_ctx* c, int32_t cap)
+{
+    if (!c) return DMB_EINVAL;
+    if (cap < 0 || cap > 65536) return fail(c, DMB_EINVAL, "dmb_set_search_groups: cap %d outside [0, 65536]", cap);
+    c->group_cap = cap;
     return DMB_OK;
 }
 

@@ -236,6 +236,33 @@ def test_determinism(ctx):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("name", ["galaxy", "box"])
+def test_search_groups_do_not_change_outputs(ctx, name):
+    """Candidate search with group lists (default capacity), with lists that overflow for most
+    groups (capacity 1: those tiles walk the node hierarchy) and with no group pass: the
+    candidate lists are the same in the same order, so every output is bit-identical."""
+    import paper_2603_24688_amd as dmb
+    if name == "galaxy":
+        cfg = workloads.galaxy(n_gas=20000, n_dm=80000, seed=(2, 21))
+    else:
+        cfg = workloads.box(n_gas=20000, n_dm=20000, seed=(14, 3), sigma0_cm2=1e-22)
+    runs = {}
+    try:
+        for cap in (1024, 1, 0):
+            _log(f"search groups {name} cap {cap}")
+            ctx.set_search_groups(cap)
+            runs[cap] = run_gpu(ctx, cfg, 1)
+    finally:
+        ctx.set_search_groups(1024)
+    for cap in (1, 0):
+        for k in ("dp_gas", "de_gas", "dv_dm", "partner", "p_sum", "p_max"):
+            assert np.array_equal(runs[1024][k], runs[cap][k]), (cap, k)
+        assert runs[1024]["counters"] == runs[cap]["counters"], cap
+    assert runs[1024]["counters"]["pairs_gas"] > 0
+    with pytest.raises(dmb.DmbError, match="EINVAL"):
+        ctx.set_search_groups(-1)
+
+
 def test_invalid_arguments(ctx):
     import torch
     import paper_2603_24688_amd as dmb
