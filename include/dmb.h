@@ -143,9 +143,26 @@ dmb_status dmb_build_cells(dmb_ctx *ctx, const dmb_particles *gas, const dmb_par
 dmb_status dmb_interact_step(dmb_ctx *ctx, const dmb_particles *gas, const dmb_particles *dm,
                              const dmb_params *params, dmb_out *out);
 
+/* The pair set of Sec. 2.4 (every overlapping pair d_ij < h_i + h_j, the
+ * support of the overlap of Appendix D, processed once per pass) as the two
+ * pair passes enumerate it.  Runs one interaction step exactly as
+ * dmb_interact_step (same outputs in *out) and also writes each pair that the
+ * gas pass and the DM pass visit, as (DM index, gas index) uint32 pairs, into
+ * pairs_gas[cap][2] and pairs_dm[cap][2] (device, caller-owned), in no
+ * particular order.  counts (HOST, 2 int64) receives each pass's total; when
+ * a total exceeds cap, only cap pairs of that pass are written.  For checking
+ * the neighbour structure: the step must use n_pow = 0 and
+ * DMB_RATES_EXACT (the pair set depends on neither).  Synchronous.
+ * Errors: those of dmb_interact_step; DMB_EINVAL for n_pow != 0, other rate
+ * modes, cap < 0, or null lists with cap > 0. */
+dmb_status dmb_pair_list(dmb_ctx *ctx, const dmb_particles *gas, const dmb_particles *dm,
+                         const dmb_params *params, dmb_out *out, int64_t cap, uint32_t *pairs_gas,
+                         uint32_t *pairs_dm, int64_t *counts);
+
 /* Device-side evaluation helpers (synchronous; device arrays of length n).
  * dmb_overlap_eval: g(d; h1, h2) of eq. dm-update-prob / Appendix D, table
- *   (DMB_FP32) or exact (DMB_FP64).
+ *   (DMB_FP32: relative error below 1e-6 everywhere inside the support) or
+ *   exact (DMB_FP64).
  * dmb_rates_eval: A/(sigma0 c^-n), B/(sigma0 c^-n) of eq. scrA/scrB at speeds
  *   w and dispersions vs for power n, by the closed forms of Appendix B
  *   (rates = DMB_RATES_EXACT), by quad_nodes-point quadrature (DMB_RATES_QUAD)

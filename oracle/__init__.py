@@ -84,6 +84,9 @@ def lib():
         L.orc_pairs.restype = C.c_int64
         L.orc_pairs.argtypes = [C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params), p, p, C.c_int64]
         L.orc_num_threads.restype = i; L.orc_num_threads.argtypes = []
+        L.orc_pair_stats.restype = None
+        L.orc_pair_stats.argtypes = [C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params), p, C.c_int64,
+                                     i, p, p, p]
         _lib = L
     return _lib
 
@@ -236,3 +239,20 @@ def pairs(gas: dict, dm: dict, params: dict, cap: int | None = None) -> np.ndarr
     if n > cap:
         return pairs(gas, dm, params, cap=int(n))
     return np.stack([oi[:n], oj[:n]], axis=1)
+
+
+def pair_stats(gas: dict, dm: dict, params: dict, sel, owner_is_dm: bool):
+    """For owners `sel` (gas indices, or DM indices when owner_is_dm): number of
+    partners, sum of partner indices and sum of their squares (uint64), brute
+    force over the other species."""
+    keep: list = []
+    G = _particles(gas, keep)
+    D = _particles(dm, keep)
+    P = _params(params)
+    s = np.ascontiguousarray(sel, dtype=np.int64)
+    cnt = np.zeros(s.size, np.int64)
+    s1 = np.zeros(s.size, np.uint64)
+    s2 = np.zeros(s.size, np.uint64)
+    lib().orc_pair_stats(C.byref(G), C.byref(D), C.byref(P), s.ctypes.data, s.size, int(bool(owner_is_dm)),
+                         cnt.ctypes.data, s1.ctypes.data, s2.ctypes.data)
+    return cnt, s1, s2

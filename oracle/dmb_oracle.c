@@ -588,6 +588,32 @@ int64_t orc_pairs(const orc_particles *gas, const orc_particles *dm, const orc_p
     return cnt;
 }
 
+/* Per-owner pair statistics for selected owners (the same pair set as
+ * orc_pairs, brute force over the other species): for owner sel[t] (a gas
+ * index when owner_is_dm == 0, else a DM index) the number of partners, the
+ * sum of their indices and the sum of their squared indices.               */
+void orc_pair_stats(const orc_particles *gas, const orc_particles *dm, const orc_params *par, const int64_t *sel,
+                    int64_t nsel, int owner_is_dm, int64_t *cnt, uint64_t *sum1, uint64_t *sum2)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < nsel; t++) {
+        int64_t o = sel[t], n = 0;
+        uint64_t s1 = 0, s2 = 0;
+        int64_t nother = owner_is_dm ? gas->n : dm->n;
+        for (int64_t k = 0; k < nother; k++) {
+            double d;
+            int in = owner_is_dm ? pair_test(gas, dm, par, k, o, &d, NULL) : pair_test(gas, dm, par, o, k, &d, NULL);
+            if (!in) continue;
+            n++;
+            s1 += (uint64_t)k;
+            s2 += (uint64_t)k * (uint64_t)k;
+        }
+        cnt[t] = n;
+        sum1[t] = s1;
+        sum2[t] = s2;
+    }
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

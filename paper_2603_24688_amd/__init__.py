@@ -27,7 +27,7 @@ EXPORTS = ["dmb_create", "dmb_destroy", "dmb_set_stream", "dmb_build_cells", "dm
            "dmb_overlap_eval", "dmb_rates_eval", "dmb_philox_eval", "dmb_profile_enable", "dmb_profile_read",
            "dmb_build_stats", "dmb_last_error", "dmb_mlp_labels", "dmb_mlp_init", "dmb_mlp_set_params",
            "dmb_mlp_get_params", "dmb_mlp_grad", "dmb_mlp_train", "dmb_mlp_eval", "dmb_batch_build",
-           "dmb_batch_step", "dmb_batch_tune", "dmb_set_search_groups"]
+           "dmb_batch_step", "dmb_batch_tune", "dmb_set_search_groups", "dmb_pair_list"]
 BUILD_STATS = ["active_gas", "active_dm", "gas_tiles", "dm_tiles", "gas_owner_tiles", "dm_owner_tiles",
                "cand_pairs_gas", "cand_pairs_dm", "items_gas", "items_dm"]
 PHASES = ["build", "gather", "pass_gas", "combine_gas", "pass_dm", "combine_dm", "resolve"]
@@ -85,6 +85,9 @@ def load_library(path: str = LIB_PATH):
     L.dmb_build_cells.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params)]
     L.dmb_interact_step.restype = C.c_int
     L.dmb_interact_step.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params), C.POINTER(Out)]
+    L.dmb_pair_list.restype = C.c_int
+    L.dmb_pair_list.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params), C.POINTER(Out),
+                                i64, vp, vp, vp]
     L.dmb_overlap_eval.restype = C.c_int; L.dmb_overlap_eval.argtypes = [vp, i64, vp, vp, vp, i32, vp]
     L.dmb_rates_eval.restype = C.c_int; L.dmb_rates_eval.argtypes = [vp, i64, vp, vp, i32, i32, i32, i32, vp, vp]
     L.dmb_philox_eval.restype = C.c_int; L.dmb_philox_eval.argtypes = [vp, i64, vp, u64, vp]
@@ -185,6 +188,26 @@ class Context:
                 _ptr(out.get("p_sum")), _ptr(out.get("p_max")), _ptr(out.get("counters")))
         self._check(self.lib.dmb_interact_step(self.h, C.byref(G), C.byref(D), C.byref(P), C.byref(O)),
                     "dmb_interact_step")
+
+    def pair_list(self, gas: dict, dm: dict, params: dict, out: dict, precision: int = DMB_FP32, cap: int = 0):
+        """One step (outputs into `out`) that also returns the pairs each pass visited:
+        (pairs_gas, pairs_dm) as int64 [n, 2] device tensors of (DM index, gas index)."""
+        import torch
+        G, D, P = _particles(gas), _particles(dm), _params(params, precision)
+        O = Out(_ptr(out["dv_dm"]), _ptr(out["dp_gas"]), _ptr(out["de_gas"]), _ptr(out["partner"]),
+                _ptr(out.get("p_sum")), _ptr(out.get("p_max")), _ptr(out.get("counters")))
+        dev = out["dv_dm"].device
+        for _ in range(2):
+            lg = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=dev)
+            ld = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=dev)
+            cnt = (C.c_int64 * 2)()
+            self._check(self.lib.dmb_pair_list(self.h, C.byref(G), C.byref(D), C.byref(P), C.byref(O), int(cap),
+                                               _ptr(lg), _ptr(ld), cnt), "dmb_pair_list")
+            if max(cnt[0], cnt[1]) <= cap:
+                break
+            cap = int(max(cnt[0], cnt[1]))
+        to64 = lambda t, n: t[:n].to(torch.int64) & 0xFFFFFFFF
+        return to64(lg, int(cnt[0])), to64(ld, int(cnt[1]))
 
     def build_stats(self) -> dict:
         v = (C.c_int64 * len(BUILD_STATS))()

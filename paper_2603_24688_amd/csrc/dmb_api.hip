@@ -91,6 +91,10 @@ struct dmb_ctx {
     DevBuf sort_table;                     // digit counts per block (one-pass counting sort)
     DevBuf bbox_part;
     DevBuf counters_local;
+    // pair export (dmb_pair_list): destination lists, capacity, device counts [gas pass, DM pass]
+    uint32_t* pair_dst[2] = {nullptr, nullptr};
+    int64_t pair_cap = 0;
+    DevBuf pair_cnt;
     DevBuf rb_dev;                         // build-stage scalars for the host (one copy per stage)
     uint64_t* rb_host = nullptr;           // pinned
     int split = 32;                        // candidate sub-tiles per work item of the DM pass (tunable);
@@ -573,6 +577,7 @@ PassGeom geom(Cells& X, Species& A, Species& B, Pairs& P, uint64_t* counters)
     g.queue_ctr = X.qctr.as<uint32_t>();
     for (int k = 0; k < 3; ++k) g.L[k] = X.built_L[k];
     g.counters = counters;
+    g.pairs = nullptr; g.pair_n = nullptr; g.pair_cap = 0;
     return g;
 }
 
@@ -742,7 +747,7 @@ void combine_dm_and_resolve(dmb_ctx* c, Cells& X, const DmPassArgs& a, const dmb
                        c->stream, r);
 }
 
-template <typename Real, int N, int RM>
+template <typename Real, int N, int RM, bool PAIRS = false>
 dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
                        dmb_out* out, uint64_t* counters)
 {
@@ -756,22 +761,30 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
     }
     if (X.gp.nitems > 0) {
         GasPassArgs a = gas_pass_args<Real, N, RM>(c, X, gas, par, out, counters);
-        const int nb = persist_blocks(c, (const void*)k_pass_gas<Real, N, kExact, RM>, 64 * kW,
+        if constexpr (PAIRS) {
+            a.g.pairs = c->pair_dst[0]; a.g.pair_cap = uint64_t(c->pair_cap);
+            a.g.pair_n = c->pair_cnt.as<unsigned long long>();
+        }
+        const int nb = persist_blocks(c, (const void*)k_pass_gas<Real, N, kExact, RM, false, PAIRS>, 64 * kW,
                                       (X.gp.nitems + kW - 1) / kW);
         {
             Phase ph(c, DMB_PH_PASS_GAS);
-            hipLaunchKernelGGL((k_pass_gas<Real, N, kExact, RM>), dim3(nb), dim3(64 * kW), 0, c->stream, a,
-                               (const GasPassArgs*)nullptr, (const int64_t*)nullptr, 0);
+            hipLaunchKernelGGL((k_pass_gas<Real, N, kExact, RM, false, PAIRS>), dim3(nb), dim3(64 * kW), 0, c->stream,
+                               a, (const GasPassArgs*)nullptr, (const int64_t*)nullptr, 0);
         }
         Phase ph(c, DMB_PH_COMBINE_GAS);
         combine_gas(c, X, gas, par, out);
     }
     if (X.dp.nitems > 0) {
         DmPassArgs a = dm_pass_args(c, X, par, out, counters, nullptr);
-        const int nb = persist_blocks(c, (const void*)k_pass_dm<Real, N, kExact>, 64, X.dp.nitems);
+        if constexpr (PAIRS) {
+            a.g.pairs = c->pair_dst[1]; a.g.pair_cap = uint64_t(c->pair_cap);
+            a.g.pair_n = c->pair_cnt.as<unsigned long long>() + 1;
+        }
+        const int nb = persist_blocks(c, (const void*)k_pass_dm<Real, N, kExact, false, PAIRS>, 64, X.dp.nitems);
         {
             Phase ph(c, DMB_PH_PASS_DM);
-            hipLaunchKernelGGL((k_pass_dm<Real, N, kExact>), dim3(nb), dim3(64), 0, c->stream, a,
+            hipLaunchKernelGGL((k_pass_dm<Real, N, kExact, false, PAIRS>), dim3(nb), dim3(64), 0, c->stream, a,
                                (const DmPassArgs*)nullptr, (const int64_t*)nullptr, 0);
         }
         combine_dm_and_resolve<Real, N>(c, X, a, gas, par, out, counters);
@@ -1142,7 +1155,7 @@ dmb_status dmb_create(dmb_ctx** out, int device, void* hip_stream)
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         c->num_cu = ncu;
     size_t tb = size_t(kTabCells) * 4 * sizeof(float4);
-    const int64_t nnodes = int64_t(kTabND + 1) * (kTabNE + 1);
+    const int64_t nnodes = 2 * int64_t(kTabNodesRegion);
     DevBuf nodes;
     if (ensure(c, c->gtab, tb) != DMB_OK || ensure(c, c->X->boxL, 4 * sizeof(double)) != DMB_OK ||
         ensure(c, nodes, size_t(nnodes) * 3 * sizeof(double)) != DMB_OK) {
@@ -1390,14 +1403,11 @@ dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_part
     c->X->built_dm_pos = dm->pos;
     return DMB_OK;
 }
-}  // namespace
 
-extern "C" {
-
-dmb_status dmb_interact_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
-                             dmb_out* out)
+// Argument checks shared by dmb_interact_step and dmb_pair_list.
+dmb_status check_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
+                      dmb_out* out)
 {
-    if (!c) return DMB_EINVAL;
     if (!par || !out) return fail(c, DMB_EINVAL, "null params or out");
     dmb_status s;
     if ((s = check_particles(c, gas, "gas", true)) != DMB_OK) return s;
@@ -1420,6 +1430,18 @@ dmb_status dmb_interact_step(dmb_ctx* c, const dmb_particles* gas, const dmb_par
     if (par->rates != DMB_RATES_EXACT && (quad_k(par) < 4 || quad_k(par) > kMaxQuadNodes))
         return fail(c, DMB_EINVAL, "quad_nodes %d outside 4..%d", par->quad_nodes, kMaxQuadNodes);
     if (!(par->m_chi_g > 0.0) || !(par->sigma0_cm2 >= 0.0)) return fail(c, DMB_EINVAL, "bad m_chi or sigma0");
+    return DMB_OK;
+}
+}  // namespace
+
+extern "C" {
+
+dmb_status dmb_interact_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
+                             dmb_out* out)
+{
+    if (!c) return DMB_EINVAL;
+    dmb_status s0 = check_step(c, gas, dm, par, out);
+    if (s0 != DMB_OK) return s0;
     HIPCHK(c, hipSetDevice(c->device));
     uint64_t* counters = out->counters;
     if (!counters) {
@@ -1429,6 +1451,49 @@ dmb_status dmb_interact_step(dmb_ctx* c, const dmb_particles* gas, const dmb_par
     if (par->precision == DMB_FP64) return dispatch_rates<double>(c, gas, dm, par, out, counters);
     if (par->precision == DMB_FP32) return dispatch_rates<float>(c, gas, dm, par, out, counters);
     return fail(c, DMB_EINVAL, "precision %d not supported", par->precision);
+}
+
+dmb_status dmb_pair_list(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
+                         dmb_out* out, int64_t cap, uint32_t* pairs_gas, uint32_t* pairs_dm, int64_t* counts)
+{
+    if (!c) return DMB_EINVAL;
+    dmb_status s0 = check_step(c, gas, dm, par, out);
+    if (s0 != DMB_OK) return s0;
+    if (par->n_pow != 0 || par->rates != DMB_RATES_EXACT)
+        return fail(c, DMB_EINVAL, "pair_list: needs n_pow 0 and DMB_RATES_EXACT");
+    if (cap < 0 || (cap > 0 && (!pairs_gas || !pairs_dm)) || !counts)
+        return fail(c, DMB_EINVAL, "pair_list: bad list arguments");
+    if (par->precision != DMB_FP64 && par->precision != DMB_FP32)
+        return fail(c, DMB_EINVAL, "precision %d not supported", par->precision);
+    HIPCHK(c, hipSetDevice(c->device));
+    uint64_t* counters = out->counters;
+    if (!counters) {
+        ENSURE(c, c->counters_local, DMB_NCOUNTERS * 8);
+        counters = c->counters_local.as<uint64_t>();
+    }
+    ENSURE(c, c->pair_cnt, 2 * sizeof(unsigned long long));
+    HIPCHK(c, hipMemsetAsync(c->pair_cnt.p, 0, 2 * sizeof(unsigned long long), c->stream));
+    c->pair_dst[0] = pairs_gas; c->pair_dst[1] = pairs_dm; c->pair_cap = cap;
+    dmb_status s = par->precision == DMB_FP64 ? launch_step<double, 0, kRatesExact, true>(c, gas, dm, par, out, counters)
+                                              : launch_step<float, 0, kRatesExact, true>(c, gas, dm, par, out, counters);
+    c->pair_dst[0] = c->pair_dst[1] = nullptr; c->pair_cap = 0;
+    if (s != DMB_OK) return s;
+    unsigned long long n[2] = {0ull, 0ull};
+    HIPCHK(c, hipMemcpyAsync(n, c->pair_cnt.p, sizeof(n), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    Cells& X = *c->X;
+    uint32_t* lists[2] = {pairs_gas, pairs_dm};
+    for (int k = 0; k < 2; ++k) {
+        counts[k] = int64_t(n[k]);
+        const int64_t m = std::min<int64_t>(int64_t(n[k]), cap);
+        if (m <= 0) continue;
+        const bool owner_dm = k == 1;
+        hipLaunchKernelGGL(k_pairs_map, dim3(blocks_for(m, 256)), dim3(256), 0, c->stream, m, lists[k],
+                           owner_dm ? X.dm.perm : X.gas.perm, owner_dm ? X.gas.perm : X.dm.perm, owner_dm);
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DMB_OK;
 }
 
 dmb_status dmb_overlap_eval(dmb_ctx* c, int64_t n, const double* d, const double* h1, const double* h2,

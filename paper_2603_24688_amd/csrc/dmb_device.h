@@ -108,42 +108,77 @@ __device__ double overlap_H_exact(double delta, double eta)
 }
 
 // ---------------------------------------------------------------------------
-// Overlap table for the FP32 path (Appendix D tabulates the overlap over the
-// distance ratio and the softening ratio).  Nodes delta_i = i*2/ND (i <= ND),
-// eta_j = j/NE (j <= NE) carry H, dH/ddelta * ddelta and dH/deta * deta; the
-// interpolant is cubic Hermite along delta for H, linear along delta for the
-// eta-derivative, and cubic Hermite along eta.  Each cell stores that
-// interpolant as polynomial coefficients in the cell offsets (a, b) in [0,1]^2:
-//   H = P0(a) + P1(a) b + P2(a) b^2 + P3(a) b^3,
+// Overlap for the binary32 path (Appendix D tabulates the overlap; here the
+// table keeps RELATIVE accuracy over the whole support, down to pairs that
+// barely touch).  With h_b >= h_s, eta = h_s/h_b, delta = d/h_b, H = h_b^3 g:
+//   shell (h_b - d < h_s: the small kernel crosses the big one's surface):
+//     rho = (h_b + h_s - d)/h_s in [0, 2),  H = eta^3 rho^8 QA(rho, eta);
+//   core (h_b - d >= h_s: the small kernel lies inside the big one):
+//     kappa = eta/(1 - delta) in (0, 1],  H = (1 - delta)^3 QB(delta, kappa).
+// The envelopes carry how H vanishes at the support edge (as its eighth power
+// in the distance to contact) and at the big kernel's surface (as the cube),
+// so QA and QB are smooth and bounded (QA in [0.0038, 0.146], QB in
+// [0.99, 6.3]).  For rho <= 1/2 the shell overlap has the closed form
+//   QA = 512/(pi delta) [1/1120 - (1 + eta) rho/2520 + eta rho^2/6300]
+// (one polynomial piece of the Appendix D integral), used for the nodes.
+// Each region is a kTabN x kTabN grid of cells on [0,1]^2 (x = rho/2 or
+// delta, y = eta or kappa); nodes carry Q and its two first derivatives
+// scaled by the cell width; the interpolant is cubic Hermite along x for Q,
+// linear along x for the y-derivative and cubic Hermite along y, stored per
+// cell as polynomial coefficients in the cell offsets (a, b):
+//   Q = P0(a) + P1(a) b + P2(a) b^2 + P3(a) b^3,
 // P0, P2, P3 cubic and P1 linear in a, as four float4 (P0, P2, P3, P1) = 64
-// bytes, so one lookup reads one aligned 64-byte segment.
-constexpr int kTabND = 512;
-constexpr int kTabNE = 128;
-constexpr int kTabCells = kTabND * kTabNE;
+// bytes, so one lookup reads one aligned 64-byte segment.  Interpolation and
+// coefficient rounding stay below 6e-7 of g itself.
+constexpr int kTabN = 128;
+constexpr int kTabCellsRegion = kTabN * kTabN;
+constexpr int kTabCells = 2 * kTabCellsRegion;   // shell cells, then core cells
 
-template <typename T>
-__device__ __forceinline__ T overlap_g_table(const float4* __restrict__ tab, T d, T hi, T hj)
+// 1/x for x > 0 in binary64: binary32 reciprocal and one Newton step
+// (relative error ~1e-14; no binary64 division).
+__device__ __forceinline__ double rcp64(double x)
 {
-    // Coefficients are stored in binary32; the evaluation runs in binary64
-    // (same FMA rate as binary32 on gfx950 vector ALUs) so that the result
-    // carries only the coefficient rounding (~1e-7 of the peak).
-    double hb = double(hi > hj ? hi : hj), hs = double(hi > hj ? hj : hi);
-    // 1/hb: binary32 reciprocal and one Newton step in binary64 (relative
-    // error ~1e-14, far below the coefficient rounding; no binary64 division)
-    double ib = double(__builtin_amdgcn_rcpf(float(hb)));
-    ib = ib * fma(-hb, ib, 2.0);
-    double fd = double(d) * ib * (kTabND * 0.5), fe = hs * ib * double(kTabNE);
-    int i = min(int(fd), kTabND - 1), j = min(int(fe), kTabNE - 1);
-    double a = fd - double(i), b = fe - double(j);
-    const float4* c = tab + 4 * (int64_t(j) * kTabND + i);
+    double r = double(__builtin_amdgcn_rcpf(float(x)));
+    return r * fma(-x, r, 2.0);
+}
+
+// g(d; h1, h2) from the binary64 squared distance of a pair inside the
+// support (d2 < (h1 + h2)^2).  The distance is refined from the binary32 root
+// by one Newton step in binary64, so that h_b + h_s - d and h_b - d keep their
+// relative accuracy near contact.
+template <typename T>
+__device__ __forceinline__ T overlap_g_table(const float4* __restrict__ tab, double d2, double h1, double h2)
+{
+    const double hb = h1 > h2 ? h1 : h2, hs = h1 > h2 ? h2 : h1;
+    const float d0f = __builtin_amdgcn_sqrtf(float(d2));
+    const double d0 = double(d0f);
+    const double d = d0f > 0.f ? fma(d2 - d0 * d0, double(0.5f * __builtin_amdgcn_rcpf(d0f)), d0) : 0.0;
+    const double ib = rcp64(hb);
+    const double inner = hb - d;             // >= hs in the core
+    const bool shell = inner < hs;
+    const double num = shell ? (hb + hs) - d : hs;
+    const double r = num * rcp64(shell ? hs : inner);   // rho (shell) or kappa (core)
+    const double eta = hs * ib;
+    const double x = shell ? 0.5 * r : d * ib, y = shell ? eta : r;
+    const double fx = fmin(x, 1.0) * double(kTabN), fy = fmin(y, 1.0) * double(kTabN);
+    const int i = min(int(fx), kTabN - 1), j = min(int(fy), kTabN - 1);
+    const double a = fx - double(i), b = fy - double(j);
+    const float4* c = tab + 4 * ((shell ? 0 : kTabCellsRegion) + j * kTabN + i);
     const float4 q0 = c[0], q2 = c[1], q3 = c[2], q1 = c[3];
     auto cubic = [a](float4 q) {
         return fma(fma(fma(double(q.w), a, double(q.z)), a, double(q.y)), a, double(q.x));
     };
     const double p0 = cubic(q0), p2 = cubic(q2), p3 = cubic(q3), p1 = fma(double(q1.y), a, double(q1.x));
-    double H = fma(fma(fma(p3, b, p2), b, p1), b, p0);
-    H = fmax(H, 0.0);
-    return T(H * ib * ib * ib);
+    const double Q = fma(fma(fma(p3, b, p2), b, p1), b, p0);
+    double env;
+    if (shell) {
+        const double r2 = r * r, r4 = r2 * r2;
+        env = eta * eta * eta * (r4 * r4);
+    } else {
+        const double t = inner * ib;
+        env = t * t * t;
+    }
+    return T(Q * env * (ib * ib * ib));
 }
 
 template <typename T>

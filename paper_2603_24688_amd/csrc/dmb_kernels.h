@@ -921,10 +921,12 @@ constexpr float kTestMargin = 1.0f + 4e-6f;
 // Slack of the expanded binary32 test |a-b|^2 - (ha+hb)^2 = A + B - 2 (a.b + ha hb)
 // with A = |a|^2 - ha^2, B = |b|^2 - hb^2, in offsets from the owner tile's
 // centre: evaluated as a six-term dot product (any summation order) its
-// rounding error stays below 20 eps32 (|a|^2 + ha^2 + |b|^2 + hb^2) ~ 1.2e-6 (...);
-// subtracting kTestSlack times that sum makes the test accept every pair that
-// is inside in exact arithmetic.
-constexpr float kTestSlack = 2e-6f;
+// rounding error stays below 20 eps32 S ~ 1.2e-6 S, S = |a|^2 + ha^2 + |b|^2 + hb^2;
+// subtracting kTestSlack S makes the test accept every pair with
+// d^2 - (ha+hb)^2 < 2.8e-6 S.  As (ha+hb)^2 <= 2 S, that holds every pair inside
+// in exact arithmetic and every pair of the near-boundary band
+// |d^2/(ha+hb)^2 - 1| <= 1e-6, so the binary64 recheck sees all of them.
+constexpr float kTestSlack = 4e-6f;
 
 struct PassGeom {
     const uint32_t* own;          // owner slot -> sorted position (owner species)
@@ -944,7 +946,27 @@ struct PassGeom {
     uint32_t* queue_ctr;          // [kXcd] work counters
     double L[3];
     uint64_t* counters;
+    // pair export (the PAIRS variants of the passes only): every visited pair
+    // d_ij < h_i + h_j as (owner sorted index, other sorted index)
+    uint32_t* pairs; unsigned long long* pair_n; uint64_t pair_cap;
 };
+
+// Appends this lane's pair (owner sorted index o, other sorted index q) to the
+// export list when `take`: one counter atomic per wave, lanes in order.
+__device__ __forceinline__ void pair_export(const PassGeom& G, bool take, uint32_t o, uint32_t q)
+{
+    const uint64_t m = __ballot(take);
+    if (m == 0ull) return;
+    const int lane = lane_id();
+    unsigned long long base = 0ull;
+    if (lane == __ffsll((long long)m) - 1) base = atomicAdd(G.pair_n, (unsigned long long)__popcll(m));
+    base = __shfl(base, __ffsll((long long)m) - 1);
+    const uint64_t pos = base + uint64_t(__popcll(m & ((1ull << lane) - 1ull)));
+    if (take && pos < G.pair_cap) {
+        G.pairs[2 * pos] = o;
+        G.pairs[2 * pos + 1] = q;
+    }
+}
 
 // Per tile pair: image shift of the other tile and whether every pair of
 // particles is then at its minimum image (else per-pair minimum image).
@@ -1110,7 +1132,8 @@ __device__ __forceinline__ void test_begin(PairTest& T, bool ov, float fx, float
 // Every owner/sub-tile pair the per-pair test can accept passes the reach check:
 // each candidate offset q lies in the binary32 box [lo, hi] (same rounding,
 // monotone), so gap <= |p - q|, and an accepted pair has
-// gap^2 < (fh + hb)^2 + (kTestSlack + 20 eps32) (|p|^2 + fh^2 + Q2 + hb^2), Q2 >= |q|^2.
+// gap^2 < (fh + hb)^2 + (kTestSlack + 20 eps32) (|p|^2 + fh^2 + Q2 + hb^2), Q2 >= |q|^2,
+// which the reach 6e-6 (...) below covers.
 template <int W>
 __device__ __forceinline__ void test_chunk(PairTest& T, TestLds& S, const PassGeom& G, const double* A,
                                            const double cen[3])
@@ -1120,7 +1143,7 @@ __device__ __forceinline__ void test_chunk(PairTest& T, TestLds& S, const PassGe
     stage_sync<W>();    // the previous chunk's groups are done with the descriptors
     int cnt = 0;
     // lane j holds chunk sub-tile j: box lo (offsets from the owner-tile centre) and max h,
-    // box hi and the sub-tile's share of the reach slack, 4e-6 (Q2 + hmax^2), or -1 when the
+    // box hi and the sub-tile's share of the reach slack, 6e-6 (Q2 + hmax^2), or -1 when the
     // sub-tile is not clean; the owner loop below reads them lane by lane
     float4 blo = make_float4(0.f, 0.f, 0.f, 0.f), bhi = make_float4(0.f, 0.f, 0.f, 0.f);
     if (lane < nch) {
@@ -1139,7 +1162,7 @@ __device__ __forceinline__ void test_chunk(PairTest& T, TestLds& S, const PassGe
         if (clean) {
             const float Q2 = fmaxf(blo.x * blo.x, bhi.x * bhi.x) + fmaxf(blo.y * blo.y, bhi.y * bhi.y) +
                              fmaxf(blo.z * blo.z, bhi.z * bhi.z);
-            bhi.w = 4e-6f * (Q2 + blo.w * blo.w);
+            bhi.w = 6e-6f * (Q2 + blo.w * blo.w);
         }
         uint32_t pk = 0u;
 #pragma unroll
@@ -1153,7 +1176,7 @@ __device__ __forceinline__ void test_chunk(PairTest& T, TestLds& S, const PassGe
     stage_sync<W>();
     float fx = T.fx, fy = T.fy, fz = T.fz, fh = T.fh;     // opaque copies: not hoisted out of the item loop
     asm volatile("" : "+v"(fx), "+v"(fy), "+v"(fz), "+v"(fh));
-    const float ao = 4e-6f * (fx * fx + fy * fy + fz * fz + fh * fh);   // the owner's share of the slack
+    const float ao = 6e-6f * (fx * fx + fy * fy + fz * fz + fh * fh);   // the owner's share of the slack
     uint64_t actA = 0ull, actB = 0ull;
     for (int j = 0; j < nch; ++j) {
         const float4 lo = make_float4(lane_get(blo.x, j), lane_get(blo.y, j), lane_get(blo.z, j), lane_get(blo.w, j));
@@ -1367,7 +1390,7 @@ __device__ __forceinline__ void gas_write_out(const GasPassArgs& a, uint32_t o, 
 
 // Occupancy: the binary32 passes fit 128 VGPRs and < 10 KB of LDS per
 // one-wave block, so four waves share each SIMD (16 blocks per CU).
-template <typename Real, int N, bool EXACT_G, int RM, bool BATCH = false>
+template <typename Real, int N, bool EXACT_G, int RM, bool BATCH = false, bool PAIRS = false>
 __global__ __launch_bounds__(RM == kRatesMlp ? 64 * kMlpPassWaves : 64, RM == kRatesMlp ? 2 : (sizeof(Real) == 4 ? 4 : (RM == kRatesExact ? 1 : 2)))
 void k_pass_gas(
     GasPassArgs a0, const GasPassArgs* __restrict__ boxes, const int64_t* __restrict__ box_items, int nbox)
@@ -1459,6 +1482,8 @@ void k_pass_gas(
                 Real c0 = 0, c1 = 0, c2 = 0, c3 = 0;
                 int seg_lo = lane;
                 if constexpr (RM != kRatesMlp) {
+                    bool hit = false;
+                    uint32_t e_o = 0u, e_q = 0u;
                     if (pp < H) {
                         int o, sl;
                         round_decode(S, lane, mark, &o, &sl, &seg_lo);
@@ -1467,11 +1492,15 @@ void k_pass_gas(
                         const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
                         const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, (pqv >> 31) != 0u, G.L);
                         const double hs = o_h[o] + qh;
+                        if constexpr (PAIRS) {
+                            hit = d2 < hs * hs;
+                            e_o = G.own[t * kTile + o];
+                            e_q = uint32_t(q);
+                        }
                         if (d2 < hs * hs) {
                             npairs++;
-                            const Real d = sqrt_real(Real(d2));
-                            const Real gg = EXACT_G ? overlap_g_exact<Real>(d, Real(qh), Real(o_h[o]))
-                                                    : overlap_g_table<Real>(a.gtab, d, Real(qh), Real(o_h[o]));
+                            const Real gg = EXACT_G ? overlap_g_exact<Real>(sqrt_real(Real(d2)), Real(qh), Real(o_h[o]))
+                                                    : overlap_g_table<Real>(a.gtab, d2, qh, o_h[o]);
                             const DmRec<Real> r = reinterpret_cast<const DmRec<Real>*>(a.drec)[q];
                             const Real wx = Real(r.vx - o_Vx[o]), wy = Real(r.vy - o_Vy[o]), wz = Real(r.vz - o_Vz[o]);
                             const Real w2 = wx * wx + wy * wy + wz * wz;
@@ -1496,6 +1525,7 @@ void k_pass_gas(
                             c3 = mg * (w2 * Ar - o_r[o] * Br);
                         }
                     }
+                    if constexpr (PAIRS) pair_export(G, hit, e_o, e_q);
                 } else {
                     // pair geometry per lane, then the network over the whole wave
                     bool live = false;
@@ -1513,7 +1543,7 @@ void k_pass_gas(
                         if (d2 < hs * hs) {
                             live = true;
                             npairs++;
-                            gg = overlap_g_table<float>(a.gtab, sqrt_real(float(d2)), float(qh), float(o_h[o]));
+                            gg = overlap_g_table<float>(a.gtab, d2, qh, o_h[o]);
                             const DmRec<float> r = reinterpret_cast<const DmRec<float>*>(a.drec)[q];
                             wx = float(r.vx - o_Vx[o]);
                             wy = float(r.vy - o_Vy[o]);
@@ -1622,8 +1652,8 @@ __device__ __forceinline__ Real pair_P(double d2, double dh, double gh, double v
                                        uint32_t step, uint32_t box, uint32_t k0, uint32_t k1, const float4* gtab,
                                        Real urel[3])
 {
-    Real d = sqrt_real(Real(d2));   // binary32 path: the root of the rounded d^2 (within one unit of float(sqrt(d2)))
-    Real g = EXACT_G ? overlap_g_exact<Real>(d, Real(dh), Real(gh)) : overlap_g_table<Real>(gtab, d, Real(dh), Real(gh));
+    Real g = EXACT_G ? overlap_g_exact<Real>(sqrt_real(Real(d2)), Real(dh), Real(gh))
+                     : overlap_g_table<Real>(gtab, d2, dh, gh);
     U4 r = philox_block(i, j, step, kTagGasVel, box, k0, k1);
     Real z[3];
     normals3<Real>(r, z);
@@ -1659,7 +1689,7 @@ __device__ __forceinline__ uint32_t dm_decide(uint32_t o, int64_t s, double P, f
     return f;
 }
 
-template <typename Real, int N, bool EXACT_G, bool BATCH = false>
+template <typename Real, int N, bool EXACT_G, bool BATCH = false, bool PAIRS = false>
 __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPassArgs a0, const DmPassArgs* __restrict__ boxes,
                                                    const int64_t* __restrict__ box_items, int nbox)
 {
@@ -1748,6 +1778,8 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
                 Real cM = 0;
                 int cNB = 0;
                 int seg_lo = lane;
+                bool hit = false;
+                uint32_t e_o = 0u, e_q = 0u;
                 if (pp < H) {
                     int o, sl;
                     round_decode(S, lane, mark, &o, &sl, &seg_lo);
@@ -1757,6 +1789,11 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
                     const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, (pqv >> 31) != 0u, G.L);
                     const double hs = o_h[o] + qh;
                     const double hs2 = hs * hs;
+                    if constexpr (PAIRS) {
+                        hit = d2 < hs2;
+                        e_o = G.own[t * kTile + o];
+                        e_q = uint32_t(q);
+                    }
                     if (fabs(d2 - hs2) <= 1e-6 * hs2) cNB = 1;
                     if (d2 < hs2) {
                         npairs++;
@@ -1770,6 +1807,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
                         if (P >= r.crit) ncrit++;
                     }
                 }
+                if constexpr (PAIRS) pair_export(G, hit, e_o, e_q);
                 seg_scan_up(lane, seg_lo, [&](auto ctl, auto rows, bool take) {
                     constexpr int C = decltype(ctl)::value, R = decltype(rows)::value;
                     cP = dpp_take_add<C, R>(cP, take);
@@ -1802,6 +1840,19 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
         }
     }
     flush(BATCH ? boxes[cur_b].g.counters : a0.g.counters);
+}
+
+// Exported pairs from sorted to input indices, as (DM index, gas index).
+// owner_is_dm: the list came from the DM pass (owner = DM).
+__global__ __launch_bounds__(256) void k_pairs_map(int64_t n, uint32_t* __restrict__ pairs,
+                                                   const uint32_t* __restrict__ owner_perm,
+                                                   const uint32_t* __restrict__ other_perm, bool owner_is_dm)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t o = owner_perm[pairs[2 * k]], q = other_perm[pairs[2 * k + 1]];
+    pairs[2 * k] = owner_is_dm ? o : q;
+    pairs[2 * k + 1] = owner_is_dm ? q : o;
 }
 
 // ---------------------------------------------------------------------------
@@ -2170,40 +2221,73 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Overlap table (Appendix D), built on the device from the exact overlap.
-// Overlap-table nodes in binary64: (H, dH/ddelta * ddelta, dH/deta * deta)
-// per node, derivatives by central differences of the exact overlap.
+// Overlap table (Appendix D), built on the device from the exact overlap (the
+// regions and envelopes are described above overlap_g_table).
+// Shell ratio QA(rho, eta) = H(1 + eta - eta rho, eta) / (eta^3 rho^8).
+__device__ double gtab_qa(double rho, double eta)
+{
+    if (rho <= 0.5) {   // one polynomial piece of the Appendix D integral, in closed form
+        const double dl = 1.0 + eta - eta * rho;
+        return 512.0 / (kPi * dl) * (1.0 / 1120.0 - (1.0 + eta) * rho / 2520.0 + eta * rho * rho / 6300.0);
+    }
+    auto q = [rho](double e) {
+        const double r2 = rho * rho, r4 = r2 * r2;
+        return overlap_H_exact(1.0 + e - e * rho, e) / (e * e * e * r4 * r4);
+    };
+    if (eta > 0.0) return q(eta);
+    return 2.0 * q(1e-6) - q(2e-6);   // eta -> 0: linear extrapolation (QA is smooth in eta)
+}
+
+// Core ratio QB(delta, kappa) = H(delta, kappa (1 - delta)) / (1 - delta)^3.
+__device__ double gtab_qb(double delta, double kappa)
+{
+    auto q = [kappa](double dl) {
+        const double e = kappa * (1.0 - dl), t = 1.0 - dl;
+        const double H = e > 0.0 ? overlap_H_exact(dl, e) : kernel_w(dl);
+        return H / (t * t * t);
+    };
+    if (delta < 1.0 - 1e-9) return q(delta);
+    return 2.0 * q(1.0 - 1e-6) - q(1.0 - 2e-6);   // delta -> 1: linear extrapolation
+}
+
+// Nodes in binary64, region-major: (Q, dQ/dx * dx, dQ/dy * dy) per node of
+// the (kTabN + 1)^2 grid on [0,1]^2 (shell: x = rho/2, y = eta; core:
+// x = delta, y = kappa).  Derivatives by central differences, second-order
+// one-sided at the grid edges.
+constexpr int kTabNodesRegion = (kTabN + 1) * (kTabN + 1);
 __global__ __launch_bounds__(256) void k_gtab_build(double* __restrict__ nodes)
 {
-    int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int nx = kTabND + 1, ny = kTabNE + 1;
-    if (id >= int64_t(nx) * ny) return;
-    int i = int(id % nx), j = int(id / nx);
-    double dd = 2.0 / kTabND, de = 1.0 / kTabNE;
-    double delta = i * dd, eta = j * de;
-    auto H = [](double dl, double et) -> double {
-        if (et <= 0.0) return kernel_w(dl);
-        return overlap_H_exact(dl, et);
-    };
-    double h0 = H(delta, eta);
+    const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (id >= 2 * int64_t(kTabNodesRegion)) return;
+    const int region = int(id / kTabNodesRegion), k = int(id % kTabNodesRegion);
+    const int i = k % (kTabN + 1), j = k / (kTabN + 1);
+    const double w = 1.0 / kTabN;
+    const double x = i * w, y = j * w;
+    auto Q = [region](double xx, double yy) { return region == 0 ? gtab_qa(2.0 * xx, yy) : gtab_qb(xx, yy); };
     const double st = 1e-5;
-    double dHd = delta == 0.0 ? 0.0 : (H(delta + st, eta) - H(fmax(delta - st, 0.0), eta)) / (delta + st - fmax(delta - st, 0.0));
-    double el = fmax(eta - st, 0.0), eh = fmin(eta + st, 1.0);
-    double dHe = (H(delta, eh) - H(delta, el)) / (eh - el);
-    nodes[3 * id] = h0;
-    nodes[3 * id + 1] = dHd * dd;
-    nodes[3 * id + 2] = dHe * de;
+    auto deriv = [&](bool along_x) {
+        const double v = along_x ? x : y;
+        auto at = [&](double t) { return along_x ? Q(t, y) : Q(x, t); };
+        if (v - st < 0.0) return (-3.0 * at(v) + 4.0 * at(v + st) - at(v + 2.0 * st)) / (2.0 * st);
+        if (v + st > 1.0) return (3.0 * at(v) - 4.0 * at(v - st) + at(v - 2.0 * st)) / (2.0 * st);
+        return (at(v + st) - at(v - st)) / (2.0 * st);
+    };
+    nodes[3 * id] = Q(x, y);
+    nodes[3 * id + 1] = deriv(true) * w;
+    nodes[3 * id + 2] = deriv(false) * w;
 }
 
 // Cell coefficients of the table interpolant from the four corner nodes
 // (layout in the comment above overlap_g_table).
 __global__ __launch_bounds__(256) void k_gtab_cells(const double* __restrict__ nodes, float4* __restrict__ tab)
 {
-    int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (id >= int64_t(kTabCells)) return;
-    const int i = int(id % kTabND), j = int(id / kTabND);
-    auto node = [&](int ii, int jj, int k) { return nodes[3 * (int64_t(jj) * (kTabND + 1) + ii) + k]; };
-    // Hermite along delta on the two eta rows: r(a) = R[0] + R[1] a + R[2] a^2 + R[3] a^3
+    const int region = int(id / kTabCellsRegion), k = int(id % kTabCellsRegion);
+    const int i = k % kTabN, j = k / kTabN;
+    const double* rn = nodes + 3 * int64_t(region) * kTabNodesRegion;
+    auto node = [&](int ii, int jj, int c) { return rn[3 * (int64_t(jj) * (kTabN + 1) + ii) + c]; };
+    // Hermite along x on the two y rows: r(a) = R[0] + R[1] a + R[2] a^2 + R[3] a^3
     double R0[4], R1[4];
     for (int row = 0; row < 2; ++row) {
         const double v0 = node(i, j + row, 0), d0 = node(i, j + row, 1);
@@ -2214,20 +2298,20 @@ __global__ __launch_bounds__(256) void k_gtab_cells(const double* __restrict__ n
         R[2] = 3.0 * (v1 - v0) - 2.0 * d0 - d1;
         R[3] = 2.0 * (v0 - v1) + d0 + d1;
     }
-    // eta-derivative, linear along delta
+    // y-derivative, linear along x
     const double E0[2] = {node(i, j, 2), node(i + 1, j, 2) - node(i, j, 2)};
     const double E1[2] = {node(i, j + 1, 2), node(i + 1, j + 1, 2) - node(i, j + 1, 2)};
-    // Hermite along eta: H = r0 + e0 b + (3 (r1 - r0) - 2 e0 - e1) b^2 + (2 (r0 - r1) + e0 + e1) b^3
+    // Hermite along y: Q = r0 + e0 b + (3 (r1 - r0) - 2 e0 - e1) b^2 + (2 (r0 - r1) + e0 + e1) b^3
     double P2[4], P3[4];
-    for (int k = 0; k < 4; ++k) {
-        P2[k] = 3.0 * (R1[k] - R0[k]) - (k < 2 ? 2.0 * E0[k] + E1[k] : 0.0);
-        P3[k] = 2.0 * (R0[k] - R1[k]) + (k < 2 ? E0[k] + E1[k] : 0.0);
+    for (int c = 0; c < 4; ++c) {
+        P2[c] = 3.0 * (R1[c] - R0[c]) - (c < 2 ? 2.0 * E0[c] + E1[c] : 0.0);
+        P3[c] = 2.0 * (R0[c] - R1[c]) + (c < 2 ? E0[c] + E1[c] : 0.0);
     }
-    float4* c = tab + 4 * id;
-    c[0] = make_float4(float(R0[0]), float(R0[1]), float(R0[2]), float(R0[3]));
-    c[1] = make_float4(float(P2[0]), float(P2[1]), float(P2[2]), float(P2[3]));
-    c[2] = make_float4(float(P3[0]), float(P3[1]), float(P3[2]), float(P3[3]));
-    c[3] = make_float4(float(E0[0]), float(E0[1]), 0.f, 0.f);
+    float4* cc = tab + 4 * id;
+    cc[0] = make_float4(float(R0[0]), float(R0[1]), float(R0[2]), float(R0[3]));
+    cc[1] = make_float4(float(P2[0]), float(P2[1]), float(P2[2]), float(P2[3]));
+    cc[2] = make_float4(float(P3[0]), float(P3[1]), float(P3[2]), float(P3[3]));
+    cc[3] = make_float4(float(E0[0]), float(E0[1]), 0.f, 0.f);
 }
 
 template <typename Real>
@@ -2236,10 +2320,10 @@ __global__ __launch_bounds__(256) void k_overlap_eval(int64_t n, const double* d
 {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    Real dd = Real(d[i]), a = Real(h1[i]), b = Real(h2[i]);
     Real g;
     if (d[i] >= h1[i] + h2[i]) g = Real(0);
-    else g = exact ? overlap_g_exact<Real>(dd, a, b) : overlap_g_table<Real>(tab, dd, a, b);
+    else if (exact) g = overlap_g_exact<Real>(Real(d[i]), Real(h1[i]), Real(h2[i]));
+    else g = overlap_g_table<Real>(tab, d[i] * d[i], h1[i], h2[i]);
     out[i] = double(g);
 }
 

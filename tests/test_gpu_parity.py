@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import workloads
-from parity_util import decision_report, kick_error, mean_field_error, mean_field_peak_error, run_gpu
+from parity_util import decision_report, kick_error, mean_field_error, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -53,24 +53,35 @@ def test_philox_bitexact(ctx, orc):
 
 
 def test_overlap_fp64_exact_and_fp32_table(ctx, orc):
+    """FP64: the exact overlap.  FP32: the table, relative to g itself over the
+    whole support, including pairs that barely touch (distance to contact down
+    to 1e-6 of h_i + h_j) and small softening ratios."""
     import torch
     r = np.random.default_rng(6)
-    n = 20000
+    n = 30000
     h1 = r.uniform(0.05, 2.0, n)
-    h2 = h1 * np.where(r.uniform(size=n) < 0.3, r.uniform(1e-3, 1.0, n), r.uniform(0.2, 5.0, n))
-    d = r.uniform(0, 1, n) * (h1 + h2)
+    h2 = h1 * np.where(r.uniform(size=n) < 0.3, 10 ** r.uniform(-5, 0, n), r.uniform(0.2, 5.0, n))
+    nu = np.where(r.uniform(size=n) < 0.5, 10 ** r.uniform(-6, 0, n), r.uniform(0, 1, n))
+    d = (1 - nu) * (h1 + h2)
     d[:5] = 0.0
     d[5:10] = 1e-9 * h1[5:10]
+    h2[10:15] = h1[10:15]
     ref = np.array([orc.overlap(a, b, c) for a, b, c in zip(d, h1, h2)])
+    assert np.all(ref > 0)
     T = [torch.from_numpy(x).cuda() for x in (d, h1, h2)]
     g64 = ctx.overlap_eval(*T, precision=0).cpu().numpy()
     g32 = ctx.overlap_eval(*T, precision=1).cpu().numpy()
-    peak = np.array([orc.overlap(0.0, a, b) for a, b in zip(h1, h2)])
-    e64 = np.max(np.abs(g64 - ref) / peak)
-    e32 = np.max(np.abs(g32 - ref) / peak)
-    _log(f"overlap: fp64 max err/peak {e64:.2e}, fp32 table max err/peak {e32:.2e}")
-    assert e64 < 1e-13
-    assert e32 < 4e-7   # binary32 inputs d, h: ~1 ulp of delta
+    e64 = np.max(np.abs(g64 / ref - 1))
+    e32 = np.abs(g32 / ref - 1)
+    k = int(np.argmax(e32))
+    _log(f"overlap: fp64 max rel err {e64:.2e}, fp32 table max rel err {e32.max():.2e} "
+         f"(p99 {np.quantile(e32, 0.99):.1e}; worst at 1 - d/(h1+h2) = {nu[k]:.1e}, h ratio "
+         f"{min(h1[k], h2[k]) / max(h1[k], h2[k]):.1e})")
+    assert e64 < 1e-12
+    assert e32.max() < 1e-6
+    # outside the support the overlap is zero in both paths
+    Tout = [torch.from_numpy(x).cuda() for x in ((h1 + h2) * 1.0000001, h1, h2)]
+    assert np.all(ctx.overlap_eval(*Tout, precision=1).cpu().numpy() == 0.0)
 
 
 @pytest.mark.parametrize("n_pow", [-4, -2, 0, 2])
@@ -111,38 +122,55 @@ def test_rates_quadrature(ctx, orc, n_pow):
 
 
 # --------------------------------------------------------------------------- full step
-def _check_step(ctx, orc, cfg, precision, label, dm_sel=None, gas_sel=None, ref=None, edge_only=False):
-    """edge_only: the configuration puts gas particles whose whole neighbour
-    set lies near the kernel-support edge; there the FP32 table path is held
-    to its peak-scaled accuracy (1e-6) instead of the per-sum norm."""
+def counter_check(gpu, ref, precision):
+    """All eight counters against the oracle.  Pair counts may differ only by
+    pairs of the near-boundary band (their binary64 d^2 is rounded in a
+    different order); scatters only if some DM is near a decision; in FP32 the
+    criterion and P_i >= 1 counts only for values within the binary32 rounding
+    of their thresholds."""
+    c, o = gpu["counters"], ref["counters"]
+    nb = o["near_boundary"]
+    assert abs(c["pairs_gas"] - o["pairs_gas"]) <= nb, (c, o)
+    assert abs(c["pairs_dm"] - o["pairs_dm"]) <= nb, (c, o)
+    assert c["near_boundary"] == o["near_boundary"], (c, o)
+    assert c["nonfinite"] == o["nonfinite"] == 0, (c, o)
+    assert c["scatters"] == o["scatters"] or o["near_decision"] > 0, (c, o)
+    if precision == 0:
+        for k in ("near_decision", "crit_viol", "p_ge_1"):
+            assert c[k] == o[k], (k, c, o)
+    else:
+        amb = int(np.sum(np.abs(ref["p_sum"] - 1.0) <= 2e-5))
+        assert abs(c["p_ge_1"] - o["p_ge_1"]) <= amb, (c, o)
+        assert abs(c["crit_viol"] - o["crit_viol"]) <= max(1, o["crit_viol"] // 500), (c, o)
+        assert abs(c["near_decision"] - o["near_decision"]) <= max(1, o["near_decision"] // 50), (c, o)
+
+
+def _check_step(ctx, orc, cfg, precision, label, dm_sel=None, gas_sel=None, ref=None):
     _log(f"[{label}] n_gas={len(cfg['gas']['mass'])} n_dm={len(cfg['dm']['mass'])} precision={precision}")
     if ref is None:
-        ref = orc.step(cfg["gas"], cfg["dm"], cfg["params"], gas_sel=gas_sel, dm_sel=dm_sel, peak_scale=True)
+        ref = orc.step(cfg["gas"], cfg["dm"], cfg["params"], gas_sel=gas_sel, dm_sel=dm_sel)
     gpu = run_gpu(ctx, cfg, precision)
     ep, ee = mean_field_error(gpu, ref, gas_sel)
-    epk = mean_field_peak_error(gpu, ref, gas_sel)
     dec = decision_report(gpu, ref, dm_sel)
     ke = kick_error(gpu, ref, dm_sel)
     sel = slice(None) if dm_sel is None else dm_sel
     ps = ref["p_sum"][sel]
     # probabilities below 1e-9 cannot decide anything (uniforms are >= 2^-25)
     pe = np.max(np.abs(gpu["p_sum"][sel] - ps) / np.maximum(ps, 1e-9), initial=0.0)
-    _log(f"[{label}] dp err {ep:.2e} dE err {ee:.2e} peak-scaled {epk:.2e} p_sum err {pe:.2e} kick err {ke:.2e} "
+    pm = ref["p_max"][sel]
+    pme = np.max(np.abs(gpu["p_max"][sel] - pm) / np.maximum(pm, 1e-9), initial=0.0)
+    _log(f"[{label}] dp err {ep:.2e} dE err {ee:.2e} p_sum err {pe:.2e} p_max err {pme:.2e} kick err {ke:.2e} "
          f"decisions {dec['compared']} (excluded {dec['excluded']}, scatters {dec['scatters']}) "
          f"mismatch {dec['mismatch']} counters gpu {gpu['counters']} oracle {ref['counters']}")
     tol = TOL[precision]
-    if edge_only and precision == 1:
-        assert epk <= 1e-6
-    else:
-        assert ep <= tol and ee <= tol
+    assert ep <= tol and ee <= tol
     assert dec["mismatch"] == 0, dec["mismatch_idx"][:10]
     assert ke <= (1e-12 if precision == 0 else 2e-5)
     assert pe <= (1e-12 if precision == 0 else 2e-5)
+    # P_max is reported in binary32 in both precisions (a diagnostic)
+    assert pme <= (1.2e-7 if precision == 0 else 2e-5)
     if dm_sel is None and gas_sel is None:
-        c = gpu["counters"]
-        assert c["pairs_dm"] == ref["counters"]["pairs_dm"]
-        assert abs(c["pairs_gas"] - ref["counters"]["pairs_gas"]) <= ref["counters"]["near_boundary"]
-        assert c["scatters"] == ref["counters"]["scatters"] or ref["counters"]["near_decision"] > 0
+        counter_check(gpu, ref, precision)
     return gpu, ref
 
 
@@ -215,7 +243,7 @@ def test_edge_sizes(ctx, orc, ng, nd):
         assert np.all(gpu["dp_gas"] == 0) and np.all(gpu["partner"] == -1)
         return
     for prec in (0, 1):
-        _check_step(ctx, orc, cfg, prec, f"edge-{ng}-{nd}", edge_only=True)
+        _check_step(ctx, orc, cfg, prec, f"edge-{ng}-{nd}")
 
 
 def test_degenerate_positions_and_cold_gas(ctx, orc):
@@ -225,7 +253,7 @@ def test_degenerate_positions_and_cold_gas(ctx, orc):
     cfg["dm"]["h"][:50] = cfg["gas"]["h"][:50]
     cfg["gas"]["u"][100:150] = 0.0
     for prec in (0, 1):
-        _check_step(ctx, orc, cfg, prec, "degenerate", edge_only=True)
+        _check_step(ctx, orc, cfg, prec, "degenerate")
 
 
 def test_determinism(ctx):
@@ -282,3 +310,89 @@ def test_invalid_arguments(ctx):
     with pytest.raises(dmb.DmbError, match="ERANGE"):
         ctx.build_cells(dmb.to_device(big), dmb.to_device(dict(cfg["dm"], h=np.full(200, 0.25))), par)
     torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------------------- neighbour sets
+def _pair_keys(p, n_gas):
+    return np.sort(p[:, 0].astype(np.int64) * n_gas + p[:, 1].astype(np.int64))
+
+
+def _near_band(cfg, keys, n_gas):
+    """|d^2/(h_i+h_j)^2 - 1| of the (DM, gas) pairs in `keys` (binary64, minimum image)."""
+    i, j = keys // n_gas, keys % n_gas
+    dx = cfg["dm"]["pos"][i] - cfg["gas"]["pos"][j]
+    box = cfg["params"].get("box")
+    if box:
+        L = np.asarray(box)
+        dx -= L * np.rint(dx / L)
+    hs = cfg["dm"]["h"][i] + cfg["gas"]["h"][j]
+    return np.abs(np.sum(dx * dx, axis=1) / (hs * hs) - 1.0)
+
+
+@pytest.mark.parametrize("name,precision", [("box", 1), ("box", 0), ("galaxy", 1), ("galaxy", 0)])
+def test_pair_sets(ctx, orc, name, precision):
+    """The pair set each pass visits (Sec. 2.4: every pair d_ij < h_i + h_j, once)
+    equals the oracle's brute-force set; a pair may differ only inside the
+    1e-6 near-boundary band."""
+    import paper_2603_24688_amd as dmb
+    if name == "box":
+        cfg = workloads.box(seed=(16, 1))
+    else:
+        cfg = workloads.galaxy(n_gas=4000, n_dm=16000, seed=(2, 13))
+    ng = len(cfg["gas"]["mass"])
+    ref = _pair_keys(orc.pairs(cfg["gas"], cfg["dm"], cfg["params"]), ng)
+    G, D = dmb.to_device(cfg["gas"]), dmb.to_device(cfg["dm"])
+    out = dmb.alloc_out(ng, len(cfg["dm"]["mass"]))
+    ctx.build_cells(G, D, cfg["params"], precision=precision)
+    pg, pd = ctx.pair_list(G, D, cfg["params"], out, precision=precision, cap=int(ref.size * 1.1) + 64)
+    for label, p in (("gas pass", pg), ("DM pass", pd)):
+        got = _pair_keys(p.cpu().numpy(), ng)
+        assert np.all(np.diff(got) > 0), f"{label}: a pair was visited twice"
+        only_gpu = np.setdiff1d(got, ref, assume_unique=True)
+        only_orc = np.setdiff1d(ref, got, assume_unique=True)
+        band = _near_band(cfg, np.concatenate([only_gpu, only_orc]), ng)
+        _log(f"[pairs {name} prec {precision}] {label}: {got.size} pairs, oracle {ref.size}, "
+             f"only GPU {only_gpu.size}, only oracle {only_orc.size}")
+        assert np.all(band <= 1e-6)
+    assert out["counters"].cpu().numpy()[0] == pg.shape[0] and out["counters"].cpu().numpy()[1] == pd.shape[0]
+
+
+def test_counters_at_thresholds(ctx, orc):
+    """A light DM particle (m_chi = m_p / 2) and a large cross section: many pairs
+    break the criterion of eq. prob_criterion, many DM reach P_i >= 1; every
+    counter and P_max against the oracle, in both precisions."""
+    cfg = workloads.box(n_gas=1500, n_dm=1400, seed=(17, 2), sigma0_cm2=2e-21, m_chi_over_mp=0.5)
+    for prec in (0, 1):
+        gpu, ref = _check_step(ctx, orc, cfg, prec, "thresholds")
+        o = ref["counters"]
+        assert o["crit_viol"] > 1000 and o["p_ge_1"] > 50 and o["scatters"] > 500, o
+
+
+def test_resolve_beyond_lds_caches(ctx, orc):
+    """Scattering DM whose pairs exceed the resolve's LDS caches (more than 8192
+    pairs and more than 2048 candidate sub-tiles): their partners are found by
+    recomputing pairs in every digit pass; partners and kicks bit-exact against
+    the oracle."""
+    cfg = workloads.galaxy(n_gas=150_000, n_dm=3000, seed=(2, 31))
+    r = np.random.default_rng(31)
+    big = np.arange(16)
+    cfg["dm"]["pos"][big] = r.normal(0.0, 1.5, (16, 3))
+    cfg["dm"]["h"][big] = 25.0
+    # per-DM timesteps that put P_i near 0.95 for the big DM (from the oracle's P_i at unit dt)
+    probe = dict(cfg["dm"], dt=np.ones(len(cfg["dm"]["mass"])))
+    pr = orc.step(cfg["gas"], probe, dict(cfg["params"], sigma0_cm2=1e-21), gas_sel=np.arange(1), dm_sel=big)
+    dt = np.full(len(cfg["dm"]["mass"]), cfg["params"]["dt"])
+    dt[big] = 0.95 / pr["p_sum"][big]
+    cfg["dm"]["dt"] = dt
+    cfg["params"]["sigma0_cm2"] = 1e-21
+    cnt, _, _ = orc.pair_stats(cfg["gas"], cfg["dm"], cfg["params"], big, True)
+    _log(f"[resolve caches] pairs of the big DM: min {cnt.min()} max {cnt.max()}")
+    assert cnt.min() > 8192
+    gsel = np.sort(r.choice(len(cfg["gas"]["mass"]), 400, replace=False))
+    for prec in (0, 1):
+        gpu, ref = _check_step(ctx, orc, cfg, prec, "resolve-caches", gas_sel=gsel)
+        sc = int(np.sum(ref["partner"][big] >= 0))
+        _log(f"[resolve caches] big DM scattering: {sc} of {big.size}")
+        assert sc >= 8
+        ok = ref["flags"][big] == 0
+        assert np.array_equal(gpu["partner"][big][ok], ref["partner"][big][ok])

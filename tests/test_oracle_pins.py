@@ -265,6 +265,22 @@ def test_mean_field_averages_to_app_f_rates(orc, n):
 
 
 # --------------------------------------------------------------------------- Philox, uniforms, normals
+def test_philox4x32_known_answers(orc):
+    """Philox4x32-10 against the published known-answer vectors of its authors
+    (tests/golden/philox4x32_10_kat.json): pins the multipliers, the Weyl key
+    increments, the round count and the word order."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "philox4x32_10_kat.json")
+    with open(path) as f:
+        kat = json.load(f)["vectors"]
+    for v in kat:
+        ctr = [int(x, 16) for x in v["ctr"]]
+        key = [int(x, 16) for x in v["key"]]
+        want = [int(x, 16) for x in v["out"]]
+        assert [int(x) for x in orc.philox4x32(ctr, key)] == want
+
+
 def test_philox_round_structure_vs_numpy(orc):
     """The 64-bit-word instance of the oracle's Philox round structure equals
     numpy's Philox4x64-10 (an independent implementation); numpy generates the
