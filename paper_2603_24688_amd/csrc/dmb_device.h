@@ -142,12 +142,12 @@ __device__ __forceinline__ double rcp64(double x)
     return r * fma(-x, r, 2.0);
 }
 
-// g(d; h1, h2) from the binary64 squared distance of a pair inside the
-// support (d2 < (h1 + h2)^2).  The distance is refined from the binary32 root
-// by one Newton step in binary64, so that h_b + h_s - d and h_b - d keep their
-// relative accuracy near contact.
-template <typename T>
-__device__ __forceinline__ T overlap_g_table(const float4* __restrict__ tab, double d2, double h1, double h2)
+// g(d; h1, h2) in binary64 from the binary64 squared distance of a pair
+// inside the support (d2 < (h1 + h2)^2).  The distance is refined from the
+// binary32 root by one Newton step in binary64, so that h_b + h_s - d and
+// h_b - d keep their relative accuracy near contact.  The value is returned in
+// binary64: near contact it falls far below the binary32 range.
+__device__ __forceinline__ double overlap_g_table(const float4* __restrict__ tab, double d2, double h1, double h2)
 {
     const double hb = h1 > h2 ? h1 : h2, hs = h1 > h2 ? h2 : h1;
     const float d0f = __builtin_amdgcn_sqrtf(float(d2));
@@ -178,7 +178,7 @@ __device__ __forceinline__ T overlap_g_table(const float4* __restrict__ tab, dou
         const double t = inner * ib;
         env = t * t * t;
     }
-    return T(Q * env * (ib * ib * ib));
+    return Q * env * (ib * ib * ib);
 }
 
 template <typename T>

@@ -1479,7 +1479,10 @@ void k_pass_gas(
                 // this owner's hits in the round: [s0, e0)
                 const int s0 = max(my_lo, base), e0 = min(my_hi, base + 64);
                 const uint32_t mark = round_marks(S, lane, base, s0, e0, my_lo);
-                Real c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+                // per-pair terms and their per-owner sums over the round in binary64 (the overlap
+                // near contact is far below the binary32 range; sums of terms that cancel keep
+                // their accuracy)
+                double c0 = 0, c1 = 0, c2 = 0, c3 = 0;
                 int seg_lo = lane;
                 if constexpr (RM != kRatesMlp) {
                     bool hit = false;
@@ -1499,8 +1502,8 @@ void k_pass_gas(
                         }
                         if (d2 < hs * hs) {
                             npairs++;
-                            const Real gg = EXACT_G ? overlap_g_exact<Real>(sqrt_real(Real(d2)), Real(qh), Real(o_h[o]))
-                                                    : overlap_g_table<Real>(a.gtab, d2, qh, o_h[o]);
+                            const double gg = EXACT_G ? double(overlap_g_exact<Real>(sqrt_real(Real(d2)), Real(qh), Real(o_h[o])))
+                                                      : overlap_g_table(a.gtab, d2, qh, o_h[o]);
                             const DmRec<Real> r = reinterpret_cast<const DmRec<Real>*>(a.drec)[q];
                             const Real wx = Real(r.vx - o_Vx[o]), wy = Real(r.vy - o_Vy[o]), wz = Real(r.vz - o_Vz[o]);
                             const Real w2 = wx * wx + wy * wy + wz * wz;
@@ -1519,10 +1522,10 @@ void k_pass_gas(
                                 Ar = o_a[o] * FA;
                                 Br = o_b[o] * FB;
                             }
-                            const Real mg = r.m * gg;
-                            const Real mgA = mg * Ar;
-                            c0 = mgA * wx; c1 = mgA * wy; c2 = mgA * wz;
-                            c3 = mg * (w2 * Ar - o_r[o] * Br);
+                            const double mg = double(r.m) * gg;
+                            const double mgA = mg * double(Ar);
+                            c0 = mgA * double(wx); c1 = mgA * double(wy); c2 = mgA * double(wz);
+                            c3 = mg * double(w2 * Ar - o_r[o] * Br);
                         }
                     }
                     if constexpr (PAIRS) pair_export(G, hit, e_o, e_q);
@@ -1531,7 +1534,8 @@ void k_pass_gas(
                     bool live = false;
                     int o = 0;
                     int64_t q = 0;
-                    float gg = 0.f, wx = 0.f, wy = 0.f, wz = 0.f, w2 = 0.f, i2 = 0.f, u = 0.f, mq = 0.f;
+                    double gg = 0.0;
+                    float wx = 0.f, wy = 0.f, wz = 0.f, w2 = 0.f, i2 = 0.f, u = 0.f, mq = 0.f;
                     if (pp < H) {
                         int sl;
                         round_decode(S, lane, mark, &o, &sl, &seg_lo);
@@ -1543,7 +1547,7 @@ void k_pass_gas(
                         if (d2 < hs * hs) {
                             live = true;
                             npairs++;
-                            gg = overlap_g_table<float>(a.gtab, d2, qh, o_h[o]);
+                            gg = overlap_g_table(a.gtab, d2, qh, o_h[o]);
                             const DmRec<float> r = reinterpret_cast<const DmRec<float>*>(a.drec)[q];
                             wx = float(r.vx - o_Vx[o]);
                             wy = float(r.vy - o_Vy[o]);
@@ -1590,10 +1594,10 @@ void k_pass_gas(
                             Ar = o_a[o] * FA;
                             Br = o_b[o] * FB;
                         }
-                        const float mg = mq * gg;
-                        const float mgA = mg * Ar;
-                        c0 = mgA * wx; c1 = mgA * wy; c2 = mgA * wz;
-                        c3 = mg * (w2 * Ar - o_r[o] * Br);
+                        const double mg = double(mq) * gg;
+                        const double mgA = mg * double(Ar);
+                        c0 = mgA * double(wx); c1 = mgA * double(wy); c2 = mgA * double(wz);
+                        c3 = mg * double(w2 * Ar - o_r[o] * Br);
                     }
                 }
                 seg_scan_up(lane, seg_lo, [&](auto ctl, auto rows, bool take) {
@@ -1606,8 +1610,8 @@ void k_pass_gas(
                 // the owner's sums of the round sit in the lane of its last hit
                 const bool has = s0 < e0;
                 const int src = has ? e0 - 1 - base : 0;
-                const Real v0 = __shfl(c0, src), v1 = __shfl(c1, src), v2 = __shfl(c2, src), v3 = __shfl(c3, src);
-                if (has) { acc0 += double(v0); acc1 += double(v1); acc2 += double(v2); acc3 += double(v3); }
+                const double v0 = __shfl(c0, src), v1 = __shfl(c1, src), v2 = __shfl(c2, src), v3 = __shfl(c3, src);
+                if (has) { acc0 += v0; acc1 += v1; acc2 += v2; acc3 += v3; }
             }
         }
         const double acc[4] = {acc0, acc1, acc2, acc3};
@@ -1653,7 +1657,7 @@ __device__ __forceinline__ Real pair_P(double d2, double dh, double gh, double v
                                        Real urel[3])
 {
     Real g = EXACT_G ? overlap_g_exact<Real>(sqrt_real(Real(d2)), Real(dh), Real(gh))
-                     : overlap_g_table<Real>(gtab, d2, dh, gh);
+                     : Real(overlap_g_table(gtab, d2, dh, gh));
     U4 r = philox_block(i, j, step, kTagGasVel, box, k0, k1);
     Real z[3];
     normals3<Real>(r, z);
@@ -2235,7 +2239,9 @@ __device__ double gtab_qa(double rho, double eta)
         return overlap_H_exact(1.0 + e - e * rho, e) / (e * e * e * r4 * r4);
     };
     if (eta > 0.0) return q(eta);
-    return 2.0 * q(1e-6) - q(2e-6);   // eta -> 0: linear extrapolation (QA is smooth in eta)
+    // eta -> 0: quadratic extrapolation from eta = 1e-3, 2e-3, 3e-3 (QA is smooth in eta; much
+    // closer to 0 the integration range shrinks to ~eta and rounding noise grows as 1/eta)
+    return 3.0 * q(1e-3) - 3.0 * q(2e-3) + q(3e-3);
 }
 
 // Core ratio QB(delta, kappa) = H(delta, kappa (1 - delta)) / (1 - delta)^3.
@@ -2247,13 +2253,14 @@ __device__ double gtab_qb(double delta, double kappa)
         return H / (t * t * t);
     };
     if (delta < 1.0 - 1e-9) return q(delta);
-    return 2.0 * q(1.0 - 1e-6) - q(1.0 - 2e-6);   // delta -> 1: linear extrapolation
+    return 3.0 * q(1.0 - 1e-3) - 3.0 * q(1.0 - 2e-3) + q(1.0 - 3e-3);   // delta -> 1: quadratic extrapolation
 }
 
 // Nodes in binary64, region-major: (Q, dQ/dx * dx, dQ/dy * dy) per node of
 // the (kTabN + 1)^2 grid on [0,1]^2 (shell: x = rho/2, y = eta; core:
-// x = delta, y = kappa).  Derivatives by central differences, second-order
-// one-sided at the grid edges.
+// x = delta, y = kappa).  Derivatives by fourth-order central differences,
+// third-order one-sided at the grid edges, with step 1e-3: a smaller step
+// would difference the rounding noise of the exact overlap at small eta.
 constexpr int kTabNodesRegion = (kTabN + 1) * (kTabN + 1);
 __global__ __launch_bounds__(256) void k_gtab_build(double* __restrict__ nodes)
 {
@@ -2264,13 +2271,15 @@ __global__ __launch_bounds__(256) void k_gtab_build(double* __restrict__ nodes)
     const double w = 1.0 / kTabN;
     const double x = i * w, y = j * w;
     auto Q = [region](double xx, double yy) { return region == 0 ? gtab_qa(2.0 * xx, yy) : gtab_qb(xx, yy); };
-    const double st = 1e-5;
+    const double st = 1e-3;
     auto deriv = [&](bool along_x) {
         const double v = along_x ? x : y;
         auto at = [&](double t) { return along_x ? Q(t, y) : Q(x, t); };
-        if (v - st < 0.0) return (-3.0 * at(v) + 4.0 * at(v + st) - at(v + 2.0 * st)) / (2.0 * st);
-        if (v + st > 1.0) return (3.0 * at(v) - 4.0 * at(v - st) + at(v - 2.0 * st)) / (2.0 * st);
-        return (at(v + st) - at(v - st)) / (2.0 * st);
+        if (v - 2.0 * st < 0.0)
+            return (-11.0 * at(v) + 18.0 * at(v + st) - 9.0 * at(v + 2.0 * st) + 2.0 * at(v + 3.0 * st)) / (6.0 * st);
+        if (v + 2.0 * st > 1.0)
+            return (11.0 * at(v) - 18.0 * at(v - st) + 9.0 * at(v - 2.0 * st) - 2.0 * at(v - 3.0 * st)) / (6.0 * st);
+        return (8.0 * (at(v + st) - at(v - st)) - (at(v + 2.0 * st) - at(v - 2.0 * st))) / (12.0 * st);
     };
     nodes[3 * id] = Q(x, y);
     nodes[3 * id + 1] = deriv(true) * w;
@@ -2320,11 +2329,11 @@ __global__ __launch_bounds__(256) void k_overlap_eval(int64_t n, const double* d
 {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    Real g;
-    if (d[i] >= h1[i] + h2[i]) g = Real(0);
-    else if (exact) g = overlap_g_exact<Real>(Real(d[i]), Real(h1[i]), Real(h2[i]));
-    else g = overlap_g_table<Real>(tab, d[i] * d[i], h1[i], h2[i]);
-    out[i] = double(g);
+    double g;
+    if (d[i] >= h1[i] + h2[i]) g = 0.0;
+    else if (exact) g = double(overlap_g_exact<Real>(Real(d[i]), Real(h1[i]), Real(h2[i])));
+    else g = overlap_g_table(tab, d[i] * d[i], h1[i], h2[i]);
+    out[i] = g;
 }
 
 template <typename Real, int N, int RM>

@@ -32,23 +32,9 @@ def mean_field_error(gpu, ref, gas_sel=None):
     return float(np.max(e1, initial=0.0)), float(np.max(e2, initial=0.0))
 
 
-def mean_field_peak_error(gpu, ref, gas_sel=None):
-    """|gpu - oracle| / (sum over pairs of |terms| with g replaced by its
-    zero-separation value): the scale at which a tabulated overlap is
-    accurate (absolute error of the table ~1e-7 of the pair's peak)."""
-    sel = slice(None) if gas_sel is None else gas_sel
-    pk = ref["pk_abs"][sel]
-    err = np.maximum(np.abs(gpu["dp_gas"][sel] - ref["dp_gas"][sel]).max(axis=1),
-                     np.abs(gpu["de_gas"][sel] - ref["de_gas"][sel]))
-    with np.errstate(invalid="ignore", divide="ignore"):
-        e = np.where(pk > 0, err / pk, err)
-    return float(np.max(e, initial=0.0))
-
-
 def mean_field_errors(gpu, ref, gas_sel=None):
-    """Per gas owner: (condition-aware error, peak-scaled error), each the
-    larger over the momentum components and the energy (see the two
-    functions above)."""
+    """Per gas owner: the condition-aware error of mean_field_error, the larger
+    over the momentum components and the energy."""
     sel = slice(None) if gas_sel is None else gas_sel
     dp_err = np.abs(gpu["dp_gas"][sel] - ref["dp_gas"][sel])                 # [n, 3]
     de_err = np.abs(gpu["de_gas"][sel] - ref["de_gas"][sel])
@@ -57,10 +43,7 @@ def mean_field_errors(gpu, ref, gas_sel=None):
     with np.errstate(invalid="ignore", divide="ignore"):
         cond = np.maximum(np.where(dp_scale > 0, dp_err / dp_scale, dp_err).max(axis=1),
                           np.where(de_scale > 0, de_err / de_scale, de_err))
-        worst = np.maximum(dp_err.max(axis=1), de_err)
-        pk = ref["pk_abs"][sel]
-        peak = np.where(pk > 0, worst / pk, worst)
-    return cond, peak
+    return cond
 
 
 def decision_report(gpu, ref, dm_sel=None):

@@ -83,7 +83,7 @@ def _sampled_check(ctx, cfg, label, n_gas_s=192, n_dm_s=192, precision=1, pair_s
     dsel = np.sort(r.choice(dpool, min(n_dm_s, dpool.size), replace=False))
     ref = oracle.step(cfg["gas"], cfg["dm"], cfg["params"], gas_sel=gsel, dm_sel=dsel)
     t2 = time.time()
-    cond, _ = mean_field_errors(gpu, ref, gsel)
+    cond = mean_field_errors(gpu, ref, gsel)
     dec = decision_report(gpu, ref, dsel)
     ke = kick_error(gpu, ref, dsel)
     c = gpu["counters"]

@@ -61,11 +61,11 @@ def test_overlap_fp64_exact_and_fp32_table(ctx, orc):
     n = 30000
     h1 = r.uniform(0.05, 2.0, n)
     h2 = h1 * np.where(r.uniform(size=n) < 0.3, 10 ** r.uniform(-5, 0, n), r.uniform(0.2, 5.0, n))
+    h2[10:15] = h1[10:15]
     nu = np.where(r.uniform(size=n) < 0.5, 10 ** r.uniform(-6, 0, n), r.uniform(0, 1, n))
     d = (1 - nu) * (h1 + h2)
     d[:5] = 0.0
     d[5:10] = 1e-9 * h1[5:10]
-    h2[10:15] = h1[10:15]
     ref = np.array([orc.overlap(a, b, c) for a, b, c in zip(d, h1, h2)])
     assert np.all(ref > 0)
     T = [torch.from_numpy(x).cuda() for x in (d, h1, h2)]
@@ -361,11 +361,11 @@ def test_counters_at_thresholds(ctx, orc):
     """A light DM particle (m_chi = m_p / 2) and a large cross section: many pairs
     break the criterion of eq. prob_criterion, many DM reach P_i >= 1; every
     counter and P_max against the oracle, in both precisions."""
-    cfg = workloads.box(n_gas=1500, n_dm=1400, seed=(17, 2), sigma0_cm2=2e-21, m_chi_over_mp=0.5)
+    cfg = workloads.box(n_gas=1500, n_dm=1400, seed=(17, 2), sigma0_cm2=1.5e-22, m_chi_over_mp=0.5)
     for prec in (0, 1):
         gpu, ref = _check_step(ctx, orc, cfg, prec, "thresholds")
         o = ref["counters"]
-        assert o["crit_viol"] > 1000 and o["p_ge_1"] > 50 and o["scatters"] > 500, o
+        assert o["crit_viol"] > 1000 and 50 < o["p_ge_1"] < 1400 and 500 < o["scatters"] < 1400, o
 
 
 def test_resolve_beyond_lds_caches(ctx, orc):
