@@ -28,15 +28,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Vector ALU: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz lane-instructions per second.
 VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
-# VALU instructions per visited pair in the built kernels (binary32 pair
-# math, n = 0, closed-form rates), counted in their gfx950 assembly by
-# `python -m paper_2603_24688_amd.isa_count`: the vector instructions of one
-# round of 64 pairs (lane = pair) - hit decode, binary64 distance recheck,
-# pair body (DM pass: overlap table, Philox4x32-10, Box-Muller, P_ij; gas
-# pass: overlap table, relative velocity, erf/exp rate terms) and the
-# segmented sums over the round's lanes (the periodic minimum-image blocks,
-# never taken in a non-periodic box, are not counted).
-PAIR_BODY_VALU = {"pass_dm": 334, "pass_gas": 342}
+# Algorithmic VALU lane-instructions per pair (the method's own work, not the
+# kernels' issue count): DM pass = distance and test 25 + overlap 25 +
+# Philox4x32-10 100 + Box-Muller 30 + P_ij and its sums 15; gas pass =
+# distance and test 25 + overlap 25 + closed-form rate terms 60 + binary64
+# accumulation 8.
+PAIR_ALGO_VALU = {"pass_dm": 195, "pass_gas": 118}
 
 
 def log(msg):
@@ -96,36 +93,42 @@ def train_network(ctx, dev, log_fn) -> dict:
             "train_s": round(t2 - t1, 3), "final_loss": float(losses[-1])}
 
 
-def cpu_baseline(cfg, seconds: float, seed: int = 0):
-    """The CPU oracle, as it stands, on a bounded random sample of owners of
-    the same workload (both passes, brute-force neighbours over the full other
-    species), scaled to pairs per second."""
+def cpu_baseline(cfg, seconds: float, pairs_per_step: int, seed: int = 0):
+    """The CPU oracle, as it stands, with its uniform-grid candidate search,
+    timed on a bounded random sample of the owners of the same workload and
+    scaled to a whole step: grid build + per-owner time x (all owners /
+    sampled owners).  Returns pairs per second of the extrapolated step."""
     import numpy as np
     import oracle
     oracle.lib()
     gas, dm, par = cfg["gas"], cfg["dm"], cfg["params"]
     r = np.random.default_rng(seed)
     ng, nd = len(gas["mass"]), len(dm["mass"])
-    k = 16
-    done_pairs, done_t, n_gs, n_ds = 0, 0.0, 0, 0
-    while done_t < seconds and (n_gs < ng or n_ds < nd):
+    none = np.zeros(0, dtype=np.int64)
+    t0 = time.perf_counter()
+    oracle.step(gas, dm, par, gas_sel=none, dm_sel=none, grid=True)    # the two grids, no owners
+    t_build = time.perf_counter() - t0
+    k = max(1, min(ng, 2000))
+    t_own = 0.0
+    while True:
         gs = np.sort(r.choice(ng, size=min(k, ng), replace=False))
-        ds = np.sort(r.choice(nd, size=min(4 * k, nd), replace=False))
+        ds = np.sort(r.choice(nd, size=min(k * max(1, nd // max(ng, 1)), nd), replace=False))
         t0 = time.perf_counter()
-        res = oracle.step(gas, dm, par, gas_sel=gs, dm_sel=ds)
+        res = oracle.step(gas, dm, par, gas_sel=gs, dm_sel=ds, grid=True)
         dt = time.perf_counter() - t0
-        done_pairs += res["counters"]["pairs_gas"] + res["counters"]["pairs_dm"]
-        done_t += dt
-        n_gs += len(gs)
-        n_ds += len(ds)
-        if dt < 0.25 * seconds:
-            k *= 2
-    # pairs processed by both passes count once per pass; the metric counts each pair once
-    rate = 0.5 * done_pairs / max(done_t, 1e-9)
-    return {"value": rate, "unit": "pair interactions/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{n_gs} random gas owners and {n_ds} random DM owners of the benchmark workload "
-                      f"(brute-force neighbours over all particles of the other species), {done_t:.1f} s of "
-                      f"oracle time, {done_pairs} pair evaluations over both passes"}
+        t_own = max(dt - t_build, 1e-9)
+        if dt >= 0.5 * seconds or (len(gs) == ng and len(ds) == nd):
+            break
+        k = int(min(ng, k * max(2.0, 0.6 * seconds / max(dt, 1e-3))))
+    frac = 0.5 * (len(gs) / max(ng, 1) + len(ds) / max(nd, 1))
+    t_full = t_build + t_own / frac
+    c = res["counters"]
+    return {"value": pairs_per_step / t_full, "unit": "pair interactions/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "neighbours": "uniform grids (the oracle's own candidate search)",
+            "sample": f"{len(gs)} random gas owners and {len(ds)} random DM owners of the benchmark workload "
+                      f"({c['pairs_gas']} + {c['pairs_dm']} pairs in {dt:.1f} s including the grid build of "
+                      f"{t_build:.1f} s); a whole step is estimated as the build plus the per-owner time scaled "
+                      f"to all owners: {t_full:.1f} s for {pairs_per_step} pairs"}
 
 
 def surrogate_compare(ctx, cfg, dev, steps: int, log_fn) -> dict:
@@ -228,9 +231,11 @@ def batch_sweep(dev, steps: int, log_fn) -> dict:
         ctx.close()
 
 
-def traffic_from_profile(kernel: str):
-    """HBM bytes per launch measured with rocprofv3 PMC runs, if they were
-    taken for the current kernel sources; else None."""
+def pmc_from_profile(kernel: str):
+    """Counters of one launch of `kernel` from the rocprofv3 PMC runs committed
+    under profiles/ (HBM bytes from FETCH_SIZE / WRITE_SIZE scaled by a plain
+    copy of known size, and SQ_INSTS_VALU), if they were taken for the current
+    kernel sources; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -338,17 +343,20 @@ def main():
     t_dom = per_kernel[dom] * 1e-3
     units = cnt["pairs_dm"] if dom == "pass_dm" else cnt["pairs_gas"]
     counted = precision == dmb.DMB_FP32 and args.n_pow == 0 and (dom == "pass_dm" or args.rates == "exact")
+    kname = "k_pass_dm" if dom == "pass_dm" else "k_pass_gas"
+    pmc = pmc_from_profile(kname)
     if counted:
-        achieved = units * PAIR_BODY_VALU[dom] / t_dom / 1e9
-        roof = {"bound": "alu", "kernel": "k_pass_dm" if dom == "pass_dm" else "k_pass_gas",
-                "achieved": achieved, "peak": VALU_PEAK_GOPS, "unit": "Gop/s (VALU lane-instructions)",
-                "frac": achieved / VALU_PEAK_GOPS, "traffic": traffic_from_profile(dom),
-                "kernel_ms": per_kernel[dom],
-                "ops_per_pair": PAIR_BODY_VALU[dom], "pairs_per_launch": units}
+        achieved = units * PAIR_ALGO_VALU[dom] / t_dom / 1e9
+        roof = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": VALU_PEAK_GOPS,
+                "unit": "Gop/s (VALU lane-instructions)", "frac": achieved / VALU_PEAK_GOPS,
+                "traffic": None if pmc is None else pmc.get("hbm_bytes"),
+                "kernel_ms": per_kernel[dom], "algorithmic_ops_per_pair": PAIR_ALGO_VALU[dom],
+                "pairs_per_launch": units,
+                "issued_valu_per_pair": None if pmc is None else pmc.get("valu_lane_instr") / units}
     else:
-        roof = {"bound": "alu", "kernel": dom, "achieved": None, "peak": VALU_PEAK_GOPS, "unit": "Gop/s",
+        roof = {"bound": "alu", "kernel": kname, "achieved": None, "peak": VALU_PEAK_GOPS, "unit": "Gop/s",
                 "frac": None, "traffic": None, "kernel_ms": per_kernel[dom],
-                "note": "instruction counts are taken for binary32 closed-form rates with n = 0"}
+                "note": "algorithmic counts are stated for binary32 closed-form rates with n = 0"}
     # algorithmic HBM bytes of the step: each particle read once (sorted copies),
     # outputs written once (see the design doc for the per-particle byte counts)
     bytes_step = desc["n_gas"] * (40 + 32) + desc["n_dm"] * (32 + 36)
@@ -373,7 +381,7 @@ def main():
         line["batch"] = batch_sweep(dev, 10, log)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
-        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, pairs)
     ctx.close()
     print(json.dumps(line), flush=True)
 

@@ -86,7 +86,10 @@ def lib():
         L.orc_num_threads.restype = i; L.orc_num_threads.argtypes = []
         L.orc_pair_stats.restype = None
         L.orc_pair_stats.argtypes = [C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params), p, C.c_int64,
-                                     i, p, p, p]
+                                     i, i, p, p, p]
+        L.orc_step_sel_grid.restype = i
+        L.orc_step_sel_grid.argtypes = [C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params),
+                                        C.POINTER(Out), p, C.c_int64, p, C.c_int64]
         _lib = L
     return _lib
 
@@ -191,12 +194,13 @@ def _params(p: dict) -> Params:
                   int(p.get("box_id", 0)), (C.c_double * 3)(*[float(b) for b in box]))
 
 
-def step(gas: dict, dm: dict, params: dict, gas_sel=None, dm_sel=None, peak_scale=False) -> dict:
+def step(gas: dict, dm: dict, params: dict, gas_sel=None, dm_sel=None, peak_scale=False, grid=False) -> dict:
     """Run the oracle step.  gas/dm: dicts of numpy arrays (pos, vel, mass, h,
     u, mu, active, dt); params: sigma0_cm2, n_pow, m_chi_g, dt, seed, step,
     box_id, box.  gas_sel / dm_sel: optional owner index subsets.  peak_scale
     also returns pk_abs: per gas, the sum of |terms| with each overlap
-    replaced by its value at zero separation."""
+    replaced by its value at zero separation.  grid: neighbour candidates from
+    uniform grids instead of every particle (bit-identical results)."""
     keep: list = []
     G = _particles(gas, keep)
     D = _particles(dm, keep)
@@ -216,7 +220,8 @@ def step(gas: dict, dm: dict, params: dict, gas_sel=None, dm_sel=None, peak_scal
     gs = None if gas_sel is None else np.ascontiguousarray(gas_sel, dtype=np.int64)
     ds = None if dm_sel is None else np.ascontiguousarray(dm_sel, dtype=np.int64)
     keep.extend(a for a in (gs, ds) if a is not None)
-    rc = lib().orc_step_sel(C.byref(G), C.byref(D), C.byref(P), C.byref(O),
+    fn = lib().orc_step_sel_grid if grid else lib().orc_step_sel
+    rc = fn(C.byref(G), C.byref(D), C.byref(P), C.byref(O),
                             None if gs is None else gs.ctypes.data, 0 if gs is None else len(gs),
                             None if ds is None else ds.ctypes.data, 0 if ds is None else len(ds))
     if rc != 0:
@@ -241,10 +246,10 @@ def pairs(gas: dict, dm: dict, params: dict, cap: int | None = None) -> np.ndarr
     return np.stack([oi[:n], oj[:n]], axis=1)
 
 
-def pair_stats(gas: dict, dm: dict, params: dict, sel, owner_is_dm: bool):
+def pair_stats(gas: dict, dm: dict, params: dict, sel, owner_is_dm: bool, grid: bool = False):
     """For owners `sel` (gas indices, or DM indices when owner_is_dm): number of
     partners, sum of partner indices and sum of their squares (uint64), brute
-    force over the other species."""
+    force over the other species (or over the uniform grids' candidates)."""
     keep: list = []
     G = _particles(gas, keep)
     D = _particles(dm, keep)
@@ -254,5 +259,5 @@ def pair_stats(gas: dict, dm: dict, params: dict, sel, owner_is_dm: bool):
     s1 = np.zeros(s.size, np.uint64)
     s2 = np.zeros(s.size, np.uint64)
     lib().orc_pair_stats(C.byref(G), C.byref(D), C.byref(P), s.ctypes.data, s.size, int(bool(owner_is_dm)),
-                         cnt.ctypes.data, s1.ctypes.data, s2.ctypes.data)
+                         int(bool(grid)), cnt.ctypes.data, s1.ctypes.data, s2.ctypes.data)
     return cnt, s1, s2

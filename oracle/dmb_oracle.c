@@ -8,8 +8,11 @@
  * leg of the benchmark do.  It shares no code, header, table or constant with
  * the HIP path.
  *
- * Everything is IEEE double.  Neighbours are found by brute force.  Each
- * function cites the passage of the paper it writes out.
+ * Everything is IEEE double.  Neighbours are found by brute force, or, for
+ * large inputs, among the candidates of a set of uniform grids (orc_grid_*):
+ * every candidate still passes the same pair test and sums run in the same
+ * ascending index order, so both give bit-identical results.  Each function
+ * cites the passage of the paper it writes out.
  *
  * Units: kpc, km/s, Msun; time in kpc/(km/s); sigma0 in cm^2; m_chi, mu in g;
  * gas specific internal energy u in (km/s)^2, 1-D velocity variance
@@ -17,6 +20,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -363,9 +367,10 @@ static double nsum_get(const orc_sum *a) { return a->s + a->c; }
  *   (3/(2 mu_j)) dT_j/dt = sum_i M_i/(m_chi+mu_j) g_ij [w^2 A - mu_j/(m_chi+mu_j) B],
  * w = v_i - V_j.  Output dp = M_j dt_j dV/dt and dE = M_j dt_j (3/(2mu)) dT/dt
  * (the internal-energy change; the bulk-kinetic part is V_j . dp).  Sums run
- * over DM in index order, compensated.                                      */
+ * over DM in index order, compensated.  cand: ascending DM candidates (NULL:
+ * every DM particle).                                                       */
 static void gas_one(const orc_particles *gas, const orc_particles *dm, const orc_params *par, int64_t j,
-                    orc_out *out, uint64_t *npairs)
+                    const int64_t *cand, int64_t ncand, orc_out *out, uint64_t *npairs)
 {
     orc_sum sp[3] = {{0, 0}, {0, 0}, {0, 0}}, se = {0, 0};
     double ap[3] = {0, 0, 0}, ae = 0, apk = 0;
@@ -376,7 +381,9 @@ static void gas_one(const orc_particles *gas, const orc_particles *dm, const orc
         double sig_kpc2 = par->sigma0_cm2 / (ORC_KPC_CM * ORC_KPC_CM);
         double cfac = sig_kpc2 * pow(ORC_C_KMS, -par->n_pow);
         double redm = mu / (par->m_chi_g + mu);
-        for (int64_t i = 0; i < dm->n; i++) {
+        int64_t nc = cand ? ncand : dm->n;
+        for (int64_t c = 0; c < nc; c++) {
+            int64_t i = cand ? cand[c] : c;
             double d;
             if (!pair_test(gas, dm, par, j, i, &d, NULL)) continue;
             np++;
@@ -448,9 +455,10 @@ static int cmp_pair(const void *x, const void *y)
  * exceeds U_i; the new direction is isotropic (tag-1 block of the chosen
  * pair, cos theta = 2u0-1, phi = 2 pi u1) and the kick follows eq. scatter_chi
  * with the same gas-velocity sample that set P_ij.  Criterion of eq.
- * prob_criterion is counted, not enforced.                                   */
+ * prob_criterion is counted, not enforced.  cand: ascending gas candidates
+ * (NULL: every gas particle); a near-boundary pair must be among them.      */
 static void dm_one(const orc_particles *gas, const orc_particles *dm, const orc_params *par, int64_t i,
-                   orc_out *out, uint64_t cnt[ORC_NCOUNTERS])
+                   const int64_t *cand, int64_t ncand, orc_out *out, uint64_t cnt[ORC_NCOUNTERS])
 {
     for (int k = 0; k < 3; k++) out->dv_dm[3 * i + k] = 0.0;
     out->partner[i] = -1;
@@ -462,7 +470,9 @@ static void dm_one(const orc_particles *gas, const orc_particles *dm, const orc_
     size_t cap = 64, np = 0;
     orc_pair *pairs = (orc_pair *)malloc(cap * sizeof(orc_pair));
     int near_b = 0;
-    for (int64_t j = 0; j < gas->n; j++) {
+    int64_t nc = cand ? ncand : gas->n;
+    for (int64_t c = 0; c < nc; c++) {
+        int64_t j = cand ? cand[c] : c;
         double d;
         int near;
         int in = pair_test(gas, dm, par, j, i, &d, &near);
@@ -529,40 +539,274 @@ static void dm_one(const orc_particles *gas, const orc_particles *dm, const orc_
     free(pairs);
 }
 
+/* ------------------------------------------------------------------------- */
+/* Candidate search on uniform grids (a filter only: the pair set is defined by
+ * pair_test).  The particles of one species are split into levels by kernel
+ * radius, level l holding h in [2^l h_min, 2^(l+1) h_min); each level is
+ * bucketed on a uniform grid whose cell side c_l >= 2^(l+1) h_min, as cell
+ * keys sorted with their particle indices.  A query point x with radius h_x
+ * receives every particle of every level whose cell lies within
+ * (h_x + c_l)(1 + 1e-5) of x per axis (each periodic image once), or the
+ * whole level when that box covers more cells than the level has particles.
+ * Candidates come back sorted by index.                                    */
+#define ORC_GRID_LEVELS 48
+typedef struct {
+    int64_t n;                /* particles in the level */
+    int64_t *idx;             /* particle indices, sorted by cell key */
+    uint64_t *key;            /* their cell keys */
+    int64_t nc[3];            /* cells per axis */
+    double cs[3];             /* cell sides */
+    double org[3];            /* grid origin */
+    double hmax;              /* largest h in the level */
+} orc_level;
+
+typedef struct {
+    int nlev;
+    orc_level lev[ORC_GRID_LEVELS];
+    double box[3];            /* periodic sides; 0 => open */
+} orc_grid;
+
+typedef struct { uint64_t k; int64_t i; } orc_kv;
+static int cmp_kv(const void *a, const void *b)
+{
+    uint64_t x = ((const orc_kv *)a)->k, y = ((const orc_kv *)b)->k;
+    if (x != y) return (x > y) - (x < y);
+    int64_t u = ((const orc_kv *)a)->i, v = ((const orc_kv *)b)->i;
+    return (u > v) - (u < v);
+}
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+static double wrap(double x, double L) { return L > 0.0 ? x - L * floor(x / L) : x; }
+
+static void grid_build(orc_grid *g, const orc_particles *p, const orc_params *par)
+{
+    memset(g, 0, sizeof(*g));
+    for (int k = 0; k < 3; k++) g->box[k] = par->box[k];
+    if (p->n == 0) return;
+    double hmin = INFINITY;
+    for (int64_t i = 0; i < p->n; i++) if (p->h[i] > 0.0 && p->h[i] < hmin) hmin = p->h[i];
+    if (!(hmin < INFINITY)) hmin = 1.0;
+    int *lv = (int *)malloc((size_t)p->n * sizeof(int));
+    int64_t cnt[ORC_GRID_LEVELS] = {0};
+    for (int64_t i = 0; i < p->n; i++) {
+        int l = p->h[i] > hmin ? (int)floor(log2(p->h[i] / hmin)) : 0;
+        if (l < 0) l = 0;
+        if (l >= ORC_GRID_LEVELS) l = ORC_GRID_LEVELS - 1;
+        lv[i] = l;
+        cnt[l]++;
+        if (l + 1 > g->nlev) g->nlev = l + 1;
+    }
+    for (int l = 0; l < g->nlev; l++) {
+        orc_level *L = &g->lev[l];
+        L->n = cnt[l];
+        if (L->n == 0) continue;
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        L->hmax = 0.0;
+        for (int64_t i = 0; i < p->n; i++) {
+            if (lv[i] != l) continue;
+            if (p->h[i] > L->hmax) L->hmax = p->h[i];
+            for (int k = 0; k < 3; k++) {
+                double x = wrap(p->pos[3 * i + k], g->box[k]);
+                if (x < lo[k]) lo[k] = x;
+                if (x > hi[k]) hi[k] = x;
+            }
+        }
+        double c = ldexp(hmin, l + 1);
+        if (L->hmax > c) c = L->hmax;
+        for (int k = 0; k < 3; k++) {
+            if (g->box[k] > 0.0) {
+                int64_t n = (int64_t)floor(g->box[k] / c);
+                L->nc[k] = n < 1 ? 1 : (n > 2097151 ? 2097151 : n);
+                L->cs[k] = g->box[k] / (double)L->nc[k];
+                L->org[k] = 0.0;
+            } else {
+                int64_t n = (int64_t)floor((hi[k] - lo[k]) / c) + 1;
+                L->nc[k] = n < 1 ? 1 : (n > 2097151 ? 2097151 : n);
+                L->cs[k] = c;
+                L->org[k] = lo[k];
+            }
+        }
+        orc_kv *kv = (orc_kv *)malloc((size_t)L->n * sizeof(orc_kv));
+        int64_t m = 0;
+        for (int64_t i = 0; i < p->n; i++) {
+            if (lv[i] != l) continue;
+            int64_t ci[3];
+            for (int k = 0; k < 3; k++) {
+                int64_t t = (int64_t)floor((wrap(p->pos[3 * i + k], g->box[k]) - L->org[k]) / L->cs[k]);
+                ci[k] = t < 0 ? 0 : (t >= L->nc[k] ? L->nc[k] - 1 : t);
+            }
+            kv[m].k = ((uint64_t)ci[0] * (uint64_t)L->nc[1] + (uint64_t)ci[1]) * (uint64_t)L->nc[2] + (uint64_t)ci[2];
+            kv[m].i = i;
+            m++;
+        }
+        qsort(kv, (size_t)L->n, sizeof(orc_kv), cmp_kv);
+        L->idx = (int64_t *)malloc((size_t)L->n * sizeof(int64_t));
+        L->key = (uint64_t *)malloc((size_t)L->n * sizeof(uint64_t));
+        for (int64_t t = 0; t < L->n; t++) { L->idx[t] = kv[t].i; L->key[t] = kv[t].k; }
+        free(kv);
+    }
+    free(lv);
+}
+
+static void grid_free(orc_grid *g)
+{
+    for (int l = 0; l < g->nlev; l++) { free(g->lev[l].idx); free(g->lev[l].key); }
+}
+
+typedef struct { int64_t *v; int64_t n, cap; } orc_list;
+static void list_push(orc_list *a, int64_t x)
+{
+    if (a->n == a->cap) {
+        a->cap = a->cap ? 2 * a->cap : 256;
+        a->v = (int64_t *)realloc(a->v, (size_t)a->cap * sizeof(int64_t));
+    }
+    a->v[a->n++] = x;
+}
+
+static int64_t lower_key(const uint64_t *key, int64_t n, uint64_t k)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) { int64_t mid = (lo + hi) / 2; if (key[mid] < k) lo = mid + 1; else hi = mid; }
+    return lo;
+}
+
+/* Cell range along one axis for [x - R, x + R]: cells lo..hi (hi - lo + 1 <=
+ * nc; with wrap, indices are taken modulo nc).                              */
+static void axis_range(const orc_level *L, int k, double x, double R, int periodic, int64_t *lo, int64_t *hi)
+{
+    double a = (x - R - L->org[k]) / L->cs[k], b = (x + R - L->org[k]) / L->cs[k];
+    int64_t i0 = (int64_t)floor(a), i1 = (int64_t)floor(b);
+    if (periodic) {
+        if (i1 - i0 + 1 >= L->nc[k]) { i0 = 0; i1 = L->nc[k] - 1; }
+    } else {
+        if (i0 < 0) i0 = 0;
+        if (i1 > L->nc[k] - 1) i1 = L->nc[k] - 1;
+    }
+    *lo = i0;
+    *hi = i1;
+}
+
+static int64_t wrapi(int64_t i, int64_t n) { int64_t r = i % n; return r < 0 ? r + n : r; }
+
+static void grid_query(const orc_grid *g, const double x[3], double hx, orc_list *out)
+{
+    out->n = 0;
+    for (int l = 0; l < g->nlev; l++) {
+        const orc_level *L = &g->lev[l];
+        if (L->n == 0) continue;
+        double R = (hx + L->hmax) * (1.0 + 1e-5) + 1e-12 * (fabs(x[0]) + fabs(x[1]) + fabs(x[2]) + 1.0);
+        int64_t lo[3], hi[3];
+        double xw[3];
+        double ncell = 1.0;
+        int empty = 0;
+        for (int k = 0; k < 3; k++) {
+            int per = g->box[k] > 0.0;
+            xw[k] = wrap(x[k], g->box[k]);
+            axis_range(L, k, xw[k], R, per, &lo[k], &hi[k]);
+            if (hi[k] < lo[k]) empty = 1;
+            ncell *= (double)(hi[k] - lo[k] + 1);
+        }
+        if (empty) continue;
+        if (ncell > (double)L->n) {          /* cheaper to take the whole level */
+            for (int64_t t = 0; t < L->n; t++) list_push(out, L->idx[t]);
+            continue;
+        }
+        for (int64_t ix = lo[0]; ix <= hi[0]; ix++)
+            for (int64_t iy = lo[1]; iy <= hi[1]; iy++) {
+                uint64_t base = ((uint64_t)wrapi(ix, L->nc[0]) * (uint64_t)L->nc[1] + (uint64_t)wrapi(iy, L->nc[1])) *
+                                (uint64_t)L->nc[2];
+                /* z run(s): contiguous keys, split where a periodic range wraps */
+                int64_t z0 = lo[2], z1 = hi[2];
+                int64_t runs[2][2];
+                int nr = 0;
+                if (wrapi(z0, L->nc[2]) <= wrapi(z1, L->nc[2]) && z1 - z0 + 1 < L->nc[2] + 1 &&
+                    wrapi(z0, L->nc[2]) + (z1 - z0) < L->nc[2]) {
+                    runs[0][0] = wrapi(z0, L->nc[2]); runs[0][1] = runs[0][0] + (z1 - z0); nr = 1;
+                } else {
+                    runs[0][0] = wrapi(z0, L->nc[2]); runs[0][1] = L->nc[2] - 1;
+                    runs[1][0] = 0; runs[1][1] = wrapi(z1, L->nc[2]); nr = 2;
+                }
+                for (int r = 0; r < nr; r++) {
+                    int64_t a = lower_key(L->key, L->n, base + (uint64_t)runs[r][0]);
+                    int64_t b = lower_key(L->key, L->n, base + (uint64_t)runs[r][1] + 1);
+                    for (int64_t t = a; t < b; t++) list_push(out, L->idx[t]);
+                }
+            }
+    }
+    qsort(out->v, (size_t)out->n, sizeof(int64_t), cmp_i64);
+}
+
 /* Full step for selected owners.  gas_sel/dm_sel list the owner indices to
  * evaluate (NULL => all).  Outputs of unselected owners are left untouched. */
-int orc_step_sel(const orc_particles *gas, const orc_particles *dm, const orc_params *par, orc_out *out,
-                 const int64_t *gas_sel, int64_t n_gas_sel, const int64_t *dm_sel, int64_t n_dm_sel)
+static int step_impl(const orc_particles *gas, const orc_particles *dm, const orc_params *par, orc_out *out,
+                     const int64_t *gas_sel, int64_t n_gas_sel, const int64_t *dm_sel, int64_t n_dm_sel, int use_grid)
 {
     if (!gas || !dm || !par || !out) return -1;
     memset(out->counters, 0, sizeof(out->counters));
     int64_t ng = gas_sel ? n_gas_sel : gas->n;
     int64_t nd = dm_sel ? n_dm_sel : dm->n;
+    orc_grid *gg = NULL, *gd = NULL;   /* grids over gas and over DM */
+    if (use_grid) {
+        gg = (orc_grid *)malloc(sizeof(orc_grid));
+        gd = (orc_grid *)malloc(sizeof(orc_grid));
+        grid_build(gg, gas, par);
+        grid_build(gd, dm, par);
+    }
     uint64_t pg = 0;
-#pragma omp parallel for schedule(dynamic, 16) reduction(+ : pg)
-    for (int64_t t = 0; t < ng; t++) {
-        int64_t j = gas_sel ? gas_sel[t] : t;
-        gas_one(gas, dm, par, j, out, &pg);
+#pragma omp parallel reduction(+ : pg)
+    {
+        orc_list cl = {NULL, 0, 0};
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t t = 0; t < ng; t++) {
+            int64_t j = gas_sel ? gas_sel[t] : t;
+            if (gd) grid_query(gd, gas->pos + 3 * j, gas->h[j], &cl);
+            gas_one(gas, dm, par, j, gd ? cl.v : NULL, cl.n, out, &pg);
+        }
+        free(cl.v);
     }
     out->counters[ORC_C_PAIRS_GAS] = pg;
     uint64_t c[ORC_NCOUNTERS];
     memset(c, 0, sizeof(c));
     uint64_t c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0, c7 = 0;
-#pragma omp parallel for schedule(dynamic, 16) reduction(+ : c1, c2, c3, c4, c5, c6, c7)
-    for (int64_t t = 0; t < nd; t++) {
-        int64_t i = dm_sel ? dm_sel[t] : t;
-        uint64_t cl[ORC_NCOUNTERS];
-        memset(cl, 0, sizeof(cl));
-        dm_one(gas, dm, par, i, out, cl);
-        c1 += cl[ORC_C_PAIRS_DM]; c2 += cl[ORC_C_SCATTERS]; c3 += cl[ORC_C_NEAR_BOUNDARY];
-        c4 += cl[ORC_C_NEAR_DECISION]; c5 += cl[ORC_C_CRIT_VIOL]; c6 += cl[ORC_C_P_GE_1];
-        c7 += cl[ORC_C_NONFINITE];
+#pragma omp parallel reduction(+ : c1, c2, c3, c4, c5, c6, c7)
+    {
+        orc_list ca = {NULL, 0, 0};
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t t = 0; t < nd; t++) {
+            int64_t i = dm_sel ? dm_sel[t] : t;
+            uint64_t cl[ORC_NCOUNTERS];
+            memset(cl, 0, sizeof(cl));
+            if (gg) grid_query(gg, dm->pos + 3 * i, dm->h[i], &ca);
+            dm_one(gas, dm, par, i, gg ? ca.v : NULL, ca.n, out, cl);
+            c1 += cl[ORC_C_PAIRS_DM]; c2 += cl[ORC_C_SCATTERS]; c3 += cl[ORC_C_NEAR_BOUNDARY];
+            c4 += cl[ORC_C_NEAR_DECISION]; c5 += cl[ORC_C_CRIT_VIOL]; c6 += cl[ORC_C_P_GE_1];
+            c7 += cl[ORC_C_NONFINITE];
+        }
+        free(ca.v);
     }
+    if (use_grid) { grid_free(gg); grid_free(gd); free(gg); free(gd); }
     out->counters[ORC_C_PAIRS_DM] = c1; out->counters[ORC_C_SCATTERS] = c2;
     out->counters[ORC_C_NEAR_BOUNDARY] = c3; out->counters[ORC_C_NEAR_DECISION] = c4;
     out->counters[ORC_C_CRIT_VIOL] = c5; out->counters[ORC_C_P_GE_1] = c6; out->counters[ORC_C_NONFINITE] = c7;
     (void)c;
     return 0;
+}
+
+int orc_step_sel(const orc_particles *gas, const orc_particles *dm, const orc_params *par, orc_out *out,
+                 const int64_t *gas_sel, int64_t n_gas_sel, const int64_t *dm_sel, int64_t n_dm_sel)
+{
+    return step_impl(gas, dm, par, out, gas_sel, n_gas_sel, dm_sel, n_dm_sel, 0);
+}
+
+/* The same step with candidates from the uniform grids (identical results). */
+int orc_step_sel_grid(const orc_particles *gas, const orc_particles *dm, const orc_params *par, orc_out *out,
+                      const int64_t *gas_sel, int64_t n_gas_sel, const int64_t *dm_sel, int64_t n_dm_sel)
+{
+    return step_impl(gas, dm, par, out, gas_sel, n_gas_sel, dm_sel, n_dm_sel, 1);
 }
 
 int orc_step(const orc_particles *gas, const orc_particles *dm, const orc_params *par, orc_out *out)
@@ -591,16 +835,28 @@ int64_t orc_pairs(const orc_particles *gas, const orc_particles *dm, const orc_p
 /* Per-owner pair statistics for selected owners (the same pair set as
  * orc_pairs, brute force over the other species): for owner sel[t] (a gas
  * index when owner_is_dm == 0, else a DM index) the number of partners, the
- * sum of their indices and the sum of their squared indices.               */
+ * sum of their indices and the sum of their squared indices; use_grid takes
+ * the candidates from the uniform grids (same sets).                        */
 void orc_pair_stats(const orc_particles *gas, const orc_particles *dm, const orc_params *par, const int64_t *sel,
-                    int64_t nsel, int owner_is_dm, int64_t *cnt, uint64_t *sum1, uint64_t *sum2)
+                    int64_t nsel, int owner_is_dm, int use_grid, int64_t *cnt, uint64_t *sum1, uint64_t *sum2)
 {
-#pragma omp parallel for schedule(dynamic, 4)
+    orc_grid *g = NULL;
+    if (use_grid) {
+        g = (orc_grid *)malloc(sizeof(orc_grid));
+        grid_build(g, owner_is_dm ? gas : dm, par);
+    }
+#pragma omp parallel
+    {
+    orc_list cl = {NULL, 0, 0};
+#pragma omp for schedule(dynamic, 4)
     for (int64_t t = 0; t < nsel; t++) {
         int64_t o = sel[t], n = 0;
         uint64_t s1 = 0, s2 = 0;
-        int64_t nother = owner_is_dm ? gas->n : dm->n;
-        for (int64_t k = 0; k < nother; k++) {
+        const orc_particles *own = owner_is_dm ? dm : gas;
+        if (g) grid_query(g, own->pos + 3 * o, own->h[o], &cl);
+        int64_t nother = g ? cl.n : (owner_is_dm ? gas->n : dm->n);
+        for (int64_t c = 0; c < nother; c++) {
+            int64_t k = g ? cl.v[c] : c;
             double d;
             int in = owner_is_dm ? pair_test(gas, dm, par, k, o, &d, NULL) : pair_test(gas, dm, par, o, k, &d, NULL);
             if (!in) continue;
@@ -612,6 +868,9 @@ void orc_pair_stats(const orc_particles *gas, const orc_particles *dm, const orc
         sum1[t] = s1;
         sum2[t] = s2;
     }
+    free(cl.v);
+    }
+    if (g) { grid_free(g); free(g); }
 }
 
 int orc_num_threads(void)
