@@ -159,6 +159,16 @@ dmb_status dmb_pair_list(dmb_ctx *ctx, const dmb_particles *gas, const dmb_parti
                          const dmb_params *params, dmb_out *out, int64_t cap, uint32_t *pairs_gas,
                          uint32_t *pairs_dm, int64_t *counts);
 
+/* The stable radix sort that orders particles along the Morton curve for the
+ * neighbour search (Sec. 2.4) and work items by size: sorts n (key, value)
+ * pairs by the key bits [lo_bit, lo_bit + 8 passes), ties kept in input
+ * order.  keys_in/vals_in, keys_out/vals_out: device arrays of n (the
+ * inputs are not modified; outputs must not alias them).  Synchronous.
+ * Errors: DMB_EINVAL (n < 0 or >= 2^31, null arrays, passes outside 1..8,
+ * bits outside the key), DMB_ENOMEM, DMB_EHIP. */
+dmb_status dmb_sort_pairs(dmb_ctx *ctx, int64_t n, const uint64_t *keys_in, const uint32_t *vals_in, int32_t lo_bit,
+                          int32_t passes, uint64_t *keys_out, uint32_t *vals_out);
+
 /* Device-side evaluation helpers (synchronous; device arrays of length n).
  * dmb_overlap_eval: g(d; h1, h2) of eq. dm-update-prob / Appendix D, table
  *   (DMB_FP32: relative error below 1e-6 everywhere inside the support) or

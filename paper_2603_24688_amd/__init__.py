@@ -27,7 +27,8 @@ EXPORTS = ["dmb_create", "dmb_destroy", "dmb_set_stream", "dmb_build_cells", "dm
            "dmb_overlap_eval", "dmb_rates_eval", "dmb_philox_eval", "dmb_profile_enable", "dmb_profile_read",
            "dmb_build_stats", "dmb_last_error", "dmb_mlp_labels", "dmb_mlp_init", "dmb_mlp_set_params",
            "dmb_mlp_get_params", "dmb_mlp_grad", "dmb_mlp_train", "dmb_mlp_eval", "dmb_batch_build",
-           "dmb_batch_step", "dmb_batch_tune", "dmb_set_search_groups", "dmb_pair_list"]
+           "dmb_batch_step", "dmb_batch_tune", "dmb_set_search_groups", "dmb_pair_list",
+           "dmb_sort_pairs"]
 BUILD_STATS = ["active_gas", "active_dm", "gas_tiles", "dm_tiles", "gas_owner_tiles", "dm_owner_tiles",
                "cand_pairs_gas", "cand_pairs_dm", "items_gas", "items_dm"]
 PHASES = ["build", "gather", "pass_gas", "combine_gas", "pass_dm", "combine_dm", "resolve"]
@@ -88,6 +89,7 @@ def load_library(path: str = LIB_PATH):
     L.dmb_pair_list.restype = C.c_int
     L.dmb_pair_list.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params), C.POINTER(Out),
                                 i64, vp, vp, vp]
+    L.dmb_sort_pairs.restype = C.c_int; L.dmb_sort_pairs.argtypes = [vp, i64, vp, vp, i32, i32, vp, vp]
     L.dmb_overlap_eval.restype = C.c_int; L.dmb_overlap_eval.argtypes = [vp, i64, vp, vp, vp, i32, vp]
     L.dmb_rates_eval.restype = C.c_int; L.dmb_rates_eval.argtypes = [vp, i64, vp, vp, i32, i32, i32, i32, vp, vp]
     L.dmb_philox_eval.restype = C.c_int; L.dmb_philox_eval.argtypes = [vp, i64, vp, u64, vp]
@@ -208,6 +210,15 @@ class Context:
             cap = int(max(cnt[0], cnt[1]))
         to64 = lambda t, n: t[:n].to(torch.int64) & 0xFFFFFFFF
         return to64(lg, int(cnt[0])), to64(ld, int(cnt[1]))
+
+    def sort_pairs(self, keys, vals, lo_bit: int, passes: int):
+        """Stable radix sort of (keys uint64-as-int64, vals int32) device tensors by key
+        bits [lo_bit, lo_bit + 8 passes); returns the sorted (keys, vals)."""
+        import torch
+        ko, vo = torch.empty_like(keys), torch.empty_like(vals)
+        self._check(self.lib.dmb_sort_pairs(self.h, keys.numel(), _ptr(keys), _ptr(vals), int(lo_bit), int(passes),
+                                            _ptr(ko), _ptr(vo)), "dmb_sort_pairs")
+        return ko, vo
 
     def build_stats(self) -> dict:
         v = (C.c_int64 * len(BUILD_STATS))()

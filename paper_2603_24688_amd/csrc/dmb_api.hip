@@ -12,8 +12,6 @@
 #include <new>
 #include <vector>
 
-#include <rocprim/device/device_radix_sort.hpp>
-
 #include "../../include/dmb.h"
 #include "dmb_kernels.h"
 #include "dmb_sort.h"
@@ -87,8 +85,9 @@ struct dmb_ctx {
     std::vector<Cells*> boxes;             // batched boxes
     DevBuf bstep, bgeom, bitem;            // batched step: Philox step offset, per-box pass arguments, item offsets
     DevBuf scan_tmp[4];
-    DevBuf sort_tmp;                       // radix-sort temporary storage
-    DevBuf sort_table;                     // digit counts per block (one-pass counting sort)
+    DevBuf os_hist;                        // radix sort: digit counts of every pass, then tile counters
+    DevBuf os_status;                      // radix sort: look-back words [passes][tiles][256]
+    DevBuf os_err;                         // radix sort: raised when a look-back wait gave up (sticky)
     DevBuf bbox_part;
     DevBuf counters_local;
     // pair export (dmb_pair_list): destination lists, capacity, device counts [gas pass, DM pass]
@@ -225,20 +224,39 @@ dmb_status scan_excl(dmb_ctx* c, const TI* in, TO* out, int64_t n, int64_t n_in 
     return DMB_OK;
 }
 
-// One stable counting-sort pass over the 8-bit digit of the keys at `shift`.
-dmb_status digit_pass(dmb_ctx* c, const uint64_t* ka, const uint32_t* va, uint64_t* kb, uint32_t* vb, int64_t n,
-                      int shift)
+// Stable LSD radix sort of n (key, value) pairs by the key bits
+// [lo_bit, lo_bit + 8 passes), ping-ponging between (ka, va) and (kb, vb);
+// on return *ka, *va point at the sorted arrays.  A raised look-back error
+// is reported by the next build's first read-back.
+__global__ __launch_bounds__(256) void k_os_clear(uint32_t* __restrict__ w, int n)
 {
-    if (n <= 0) return DMB_OK;
-    const int nblk = int((n + kSortTile - 1) / kSortTile);
-    const int64_t tsz = int64_t(256) * nblk;
-    ENSURE(c, c->sort_table, size_t(tsz + 1) * 4);
-    hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(kSortBlock), 0, c->stream, ka, n, shift,
-                       c->sort_table.as<uint32_t>(), nblk);
-    dmb_status s = scan_excl(c, c->sort_table.as<uint32_t>(), c->sort_table.as<uint32_t>(), tsz);
-    if (s != DMB_OK) return s;
-    hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(kSortBlock), 0, c->stream, ka, va, kb, vb, n, shift,
-                       c->sort_table.as<const uint32_t>(), nblk);
+    for (int i = int(threadIdx.x); i < n; i += 256) w[i] = 0u;
+}
+
+dmb_status radix_sort(dmb_ctx* c, uint64_t** ka, uint32_t** va, uint64_t** kb, uint32_t** vb, int64_t n, int lo_bit,
+                      int passes)
+{
+    if (n <= 0 || passes <= 0) return DMB_OK;
+    if (passes > kOsMaxPasses) return fail(c, DMB_EINVAL, "radix sort: %d passes", passes);
+    const int64_t ntile = (n + kOsTile - 1) / kOsTile;
+    const int nw = kOsMaxPasses * 256 + kOsMaxPasses;
+    ENSURE(c, c->os_hist, size_t(nw) * 4);
+    ENSURE(c, c->os_status, size_t(passes) * size_t(ntile) * 256 * 8);
+    OsArgs a;
+    a.n = n; a.passes = passes; a.lo_bit = lo_bit;
+    a.hist = c->os_hist.as<uint32_t>();
+    a.tile_ctr = a.hist + kOsMaxPasses * 256;
+    a.status = c->os_status.as<unsigned long long>();
+    a.err = c->os_err.as<uint32_t>();
+    a.ntile = ntile;
+    hipLaunchKernelGGL(k_os_clear, dim3(1), dim3(256), 0, c->stream, a.hist, nw);
+    const int hb = int(std::min<int64_t>(2048, std::max<int64_t>(ntile, (int64_t(passes) * ntile * 256 + 4095) / 4096)));
+    hipLaunchKernelGGL(k_os_hist, dim3(hb), dim3(kOsBlock), 0, c->stream, *ka, a);
+    for (int p = 0; p < passes; ++p) {
+        hipLaunchKernelGGL(k_os_pass, dim3(unsigned(ntile)), dim3(kOsBlock), 0, c->stream, *ka, *va, *kb, *vb, a, p);
+        std::swap(*ka, *kb);
+        std::swap(*va, *vb);
+    }
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
 }
@@ -288,27 +306,13 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
     // radix sort on the top bits that resolve ~2^6 particles per cell
     int need = std::min(63, std::max(24, 3 * ((bits_for(n) + 6 + 2) / 3)));
     int passes = (need + 7) / 8;
-    // stable LSD radix sort (rocPRIM onesweep) of the keys' bits [63 - 8 passes, 63)
+    // stable LSD radix sort of the keys' bits [63 - 8 passes, 63)
     const int lo_bit = std::max(0, 63 - 8 * passes);
     uint64_t *ka = S.keys.as<uint64_t>(), *kb = S.keys2.as<uint64_t>();
     uint32_t *va = S.vals.as<uint32_t>(), *vb = S.vals2.as<uint32_t>();
-    if (n < (int64_t(1) << 21)) {
-        // small species: one counting-sort pass per 8-bit digit (fewer launches than the library sort)
-        for (int ps = 0; ps < passes; ++ps) {
-            dmb_status s = digit_pass(c, ka, va, kb, vb, n, lo_bit + 8 * ps);
-            if (s != DMB_OK) return s;
-            std::swap(ka, kb);
-            std::swap(va, vb);
-        }
-    } else {
-        rocprim::double_buffer<uint64_t> kd(ka, kb);
-        rocprim::double_buffer<uint32_t> vd(va, vb);
-        size_t tmp = 0;
-        HIPCHK(c, rocprim::radix_sort_pairs(nullptr, tmp, kd, vd, size_t(n), unsigned(lo_bit), 63u, c->stream));
-        ENSURE(c, c->sort_tmp, tmp);
-        HIPCHK(c, rocprim::radix_sort_pairs(c->sort_tmp.p, tmp, kd, vd, size_t(n), unsigned(lo_bit), 63u, c->stream));
-        ka = kd.current();
-        va = vd.current();
+    {
+        dmb_status s0 = radix_sort(c, &ka, &va, &kb, &vb, n, lo_bit, passes);
+        if (s0 != DMB_OK) return s0;
     }
     S.sort_lo_bit = std::max(0, 63 - 8 * passes);
     // keep the sorted permutation in S.vals
@@ -499,8 +503,9 @@ dmb_status cand_write(dmb_ctx* c, Species& A, Species& B, Pairs& P)
                        P.scnt.as<const uint32_t>(), P.swt.as<const uint32_t>(), P.ioff.as<const uint32_t>(), nt, ni,
                        P.it_tile.as<uint32_t>(), P.it_cb.as<uint64_t>(), P.it_ce.as<uint64_t>(),
                        P.it_key.as<uint64_t>(), P.it_id.as<uint32_t>());
-    dmb_status s = digit_pass(c, P.it_key.as<const uint64_t>(), P.it_id.as<const uint32_t>(), P.it_key2.as<uint64_t>(),
-                              P.it_ord.as<uint32_t>(), ni, 0);
+    uint64_t *ka = P.it_key.as<uint64_t>(), *kb = P.it_key2.as<uint64_t>();
+    uint32_t *va = P.it_id.as<uint32_t>(), *vb = P.it_ord.as<uint32_t>();
+    dmb_status s = radix_sort(c, &ka, &va, &kb, &vb, ni, 0, 1);   // one pass: the order lands in it_ord
     if (s != DMB_OK) return s;
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
@@ -1158,12 +1163,14 @@ dmb_status dmb_create(dmb_ctx** out, int device, void* hip_stream)
     const int64_t nnodes = 2 * int64_t(kTabNodesRegion);
     DevBuf nodes;
     if (ensure(c, c->gtab, tb) != DMB_OK || ensure(c, c->X->boxL, 4 * sizeof(double)) != DMB_OK ||
+        ensure(c, c->os_err, sizeof(uint32_t)) != DMB_OK ||
         ensure(c, nodes, size_t(nnodes) * 3 * sizeof(double)) != DMB_OK) {
         snprintf(g_create_err, sizeof(g_create_err), "%s", c->err);
         if (nodes.p) (void)hipFree(nodes.p);
         dmb_destroy(c);
         return DMB_ENOMEM;
     }
+    hipLaunchKernelGGL(k_os_clear, dim3(1), dim3(256), 0, c->stream, c->os_err.as<uint32_t>(), 1);
     hipLaunchKernelGGL(k_gtab_build, dim3(blocks_for(nnodes, 256)), dim3(256), 0, c->stream, nodes.as<double>());
     hipLaunchKernelGGL(k_gtab_cells, dim3(blocks_for(kTabCells, 256)), dim3(256), 0, c->stream,
                        nodes.as<const double>(), c->gtab.as<float4>());
@@ -1199,8 +1206,8 @@ dmb_status dmb_destroy(dmb_ctx* c)
                      &c->mlp_loss, &c->mlp_epoch, &c->mlp_shuf};
     for (DevBuf* b : mlp) fr(*b);
     if (c->train_stream) hipStreamDestroy(c->train_stream);
-    DevBuf* rest[] = {&c->gl64, &c->gl32, &c->gtab, &c->sort_table, &c->bbox_part, &c->counters_local,
-                      &c->bstep, &c->bgeom, &c->bitem, &c->rb_dev, &c->sort_tmp};
+    DevBuf* rest[] = {&c->gl64, &c->gl32, &c->gtab, &c->os_hist, &c->os_status, &c->os_err, &c->bbox_part,
+                      &c->counters_local, &c->bstep, &c->bgeom, &c->bitem, &c->rb_dev};
     for (DevBuf* b : rest) fr(*b);
     if (c->rb_host) hipHostFree(c->rb_host);
     delete c;
@@ -1322,8 +1329,14 @@ dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_part
             r.u32(S.n > 0 ? S.flag_off.as<uint32_t>() + S.n : nullptr);
             r.u32(S.n > 0 ? S.sub_coff.as<uint32_t>() + S.nchunk : nullptr);
         }
-        uint64_t v[4];
+        r.u32(c->os_err.as<uint32_t>());
+        uint64_t v[5];
         if ((s = readback(c, r, v)) != DMB_OK) return s;
+        if (v[4] != 0) {
+            hipLaunchKernelGGL(k_os_clear, dim3(1), dim3(256), 0, c->stream, c->os_err.as<uint32_t>(), 1);
+            c->X->built_ngas = c->X->built_ndm = -1;
+            return fail(c, DMB_EHIP, "radix sort: a look-back wait gave up");
+        }
         c->X->gas.n_own = int64_t(v[0]);
         c->X->gas.ntile = int64_t(v[1]);
         c->X->dm.n_own = int64_t(v[2]);
@@ -1494,6 +1507,44 @@ dmb_status dmb_pair_list(dmb_ctx* c, const dmb_particles* gas, const dmb_particl
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return DMB_OK;
+}
+
+dmb_status dmb_sort_pairs(dmb_ctx* c, int64_t n, const uint64_t* keys_in, const uint32_t* vals_in, int32_t lo_bit,
+                          int32_t passes, uint64_t* keys_out, uint32_t* vals_out)
+{
+    if (!c) return DMB_EINVAL;
+    if (n < 0 || n >= (int64_t(1) << 31) || (n > 0 && (!keys_in || !vals_in || !keys_out || !vals_out)))
+        return fail(c, DMB_EINVAL, "sort_pairs: bad arrays");
+    if (passes < 1 || passes > kOsMaxPasses || lo_bit < 0 || lo_bit + 8 * passes > 64)
+        return fail(c, DMB_EINVAL, "sort_pairs: bits [%d, %d) outside the key", lo_bit, lo_bit + 8 * passes);
+    if (n == 0) return DMB_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    DevBuf kt, vt;
+    dmb_status s = DMB_OK;
+    if ((s = ensure(c, kt, size_t(n) * 8)) == DMB_OK && (s = ensure(c, vt, size_t(n) * 4)) == DMB_OK) {
+        // the passes ping-pong between the output arrays and temporaries: start where the
+        // last pass lands in the outputs
+        uint64_t* k0 = (passes & 1) ? kt.as<uint64_t>() : keys_out;
+        uint32_t* v0 = (passes & 1) ? vt.as<uint32_t>() : vals_out;
+        uint64_t* k1 = (passes & 1) ? keys_out : kt.as<uint64_t>();
+        uint32_t* v1 = (passes & 1) ? vals_out : vt.as<uint32_t>();
+        if (hipMemcpyAsync(k0, keys_in, size_t(n) * 8, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(v0, vals_in, size_t(n) * 4, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+            s = fail(c, DMB_EHIP, "sort_pairs: copy failed");
+        if (s == DMB_OK) s = radix_sort(c, &k0, &v0, &k1, &v1, n, lo_bit, passes);
+        uint32_t err = 0;
+        if (s == DMB_OK && (hipMemcpyAsync(&err, c->os_err.p, 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+                            hipStreamSynchronize(c->stream) != hipSuccess))
+            s = fail(c, DMB_EHIP, "sort_pairs: sync failed");
+        if (s == DMB_OK && err) {
+            hipLaunchKernelGGL(k_os_clear, dim3(1), dim3(256), 0, c->stream, c->os_err.as<uint32_t>(), 1);
+            s = fail(c, DMB_EHIP, "radix sort: a look-back wait gave up");
+        }
+    }
+    (void)hipStreamSynchronize(c->stream);
+    if (kt.p) (void)hipFree(kt.p);
+    if (vt.p) (void)hipFree(vt.p);
+    return s;
 }
 
 dmb_status dmb_overlap_eval(dmb_ctx* c, int64_t n, const double* d, const double* h1, const double* h2,

@@ -1,6 +1,6 @@
-// dmb_sort.h -- device-wide exclusive scan and one-pass stable counting
-// sort by an 8-bit digit (64-bit keys, 32-bit payload): the Morton sort of
-// small species and the ordering of work items.
+// dmb_sort.h -- device-wide exclusive scan and a stable LSD radix sort of
+// 64-bit keys with 32-bit payloads: the Morton sort of both species and the
+// ordering of work items.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -90,88 +90,175 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(TO* __restrict__ out, c
     }
 }
 
-// ---------------------------------------------------------------------------
-// Stable LSD radix sort, 8-bit digits.  Each block owns kSortTile
-// consecutive keys; per-block digit counts are scanned digit-major so the
-// scatter keeps the input order of equal digits.
-constexpr int kSortBlock = 256;
-constexpr int kSortRounds = 16;
-constexpr int kSortTile = kSortBlock * kSortRounds;  // 4096
 
-__global__ __launch_bounds__(kSortBlock) void k_sort_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
-                                                          uint32_t* __restrict__ table, int nblocks)
+// ---------------------------------------------------------------------------
+// Onesweep LSD radix sort (Adinets & Merrill, "Onesweep: A Faster Least
+// Significant Digit Radix Sort for GPUs", 2022): 8-bit digits of 64-bit keys
+// with 32-bit payloads, stable.  One kernel histograms every digit pass in a
+// single read of the keys (and clears the look-back state); then one kernel
+// per pass: each block takes the next tile of kOsTile keys from an atomic
+// counter, publishes its per-digit counts, finds the counts of all earlier
+// tiles by decoupled look-back, ranks its keys stably in LDS and writes them
+// out digit by digit (coalesced runs).  Tiles are numbered in the order
+// blocks start, so a look-back only ever waits on tiles whose blocks are
+// already running and publish their counts before they look back
+// themselves; the wait is still bounded (kOsSpinMax polls, then an error
+// flag is raised and the pass ends).
+constexpr int kOsBlock = 256;
+constexpr int kOsItems = 16;
+constexpr int kOsTile = kOsBlock * kOsItems;   // 4096 keys per tile
+constexpr int kOsMaxPasses = 8;
+constexpr uint64_t kOsAgg = 1ull << 62;        // status: this tile's own count is available
+constexpr uint64_t kOsInc = 2ull << 62;        // status: count of this and all earlier tiles
+constexpr uint64_t kOsCount = (1ull << 62) - 1;
+constexpr uint32_t kOsSpinMax = 1u << 24;
+
+struct OsArgs {
+    int64_t n;
+    int passes, lo_bit;                 // digit p covers key bits [lo_bit + 8p, lo_bit + 8p + 8)
+    uint32_t* hist;                     // [passes][256] global digit counts
+    unsigned long long* status;         // [passes][ntile][256] look-back words
+    uint32_t* tile_ctr;                 // [passes] tile counters
+    uint32_t* err;                      // raised if a look-back wait gave up
+    int64_t ntile;
+};
+
+// Global digit histograms of all passes; also clears the look-back state.
+__global__ __launch_bounds__(kOsBlock) void k_os_hist(const uint64_t* __restrict__ keys, OsArgs a)
 {
-    __shared__ uint32_t hist[256];
-    hist[threadIdx.x] = 0;
+    __shared__ uint32_t h[kOsMaxPasses][256];
+    for (int p = 0; p < a.passes; ++p) h[p][threadIdx.x] = 0u;
     __syncthreads();
-    int64_t base = int64_t(blockIdx.x) * kSortTile;
-    uint32_t dg[kSortRounds];
-#pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {    // all loads in flight before the first count
-        int64_t i = base + int64_t(r) * kSortBlock + threadIdx.x;
-        dg[r] = i < n ? uint32_t(keys[i] >> shift) & 255u : 256u;
+    const int64_t stride = int64_t(gridDim.x) * kOsBlock;
+    for (int64_t i = int64_t(blockIdx.x) * kOsBlock + threadIdx.x; i < a.n; i += stride) {
+        const uint64_t k = keys[i];
+        for (int p = 0; p < a.passes; ++p) atomicAdd(&h[p][uint32_t(k >> (a.lo_bit + 8 * p)) & 255u], 1u);
     }
-#pragma unroll
-    for (int r = 0; r < kSortRounds; ++r)
-        if (dg[r] < 256u) atomicAdd(&hist[dg[r]], 1u);
     __syncthreads();
-    table[int64_t(threadIdx.x) * nblocks + blockIdx.x] = hist[threadIdx.x];
+    for (int p = 0; p < a.passes; ++p)
+        if (h[p][threadIdx.x]) atomicAdd(&a.hist[p * 256 + threadIdx.x], h[p][threadIdx.x]);
+    const int64_t nst = int64_t(a.passes) * a.ntile * 256;
+    for (int64_t i = int64_t(blockIdx.x) * kOsBlock + threadIdx.x; i < nst; i += stride) a.status[i] = 0ull;
 }
 
-__global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const uint64_t* __restrict__ keys_in,
-                                                             const uint32_t* __restrict__ vals_in,
-                                                             uint64_t* __restrict__ keys_out,
-                                                             uint32_t* __restrict__ vals_out, int64_t n, int shift,
-                                                             const uint32_t* __restrict__ table, int nblocks)
+// Exclusive scan over the 256 threads of a block (one value each).
+__device__ __forceinline__ uint32_t os_block_excl(uint32_t v, uint32_t* ws)
 {
-    __shared__ uint32_t boff[256];
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wcnt[kSortBlock / 64][256];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    boff[tid] = table[int64_t(tid) * nblocks + blockIdx.x];
-    run[tid] = 0;
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int64_t base = int64_t(blockIdx.x) * kSortTile;
-    uint64_t kr[kSortRounds];
-    uint32_t vr[kSortRounds];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {    // the block's keys and values, all loads in flight at once
-        const int64_t i = base + int64_t(r) * kSortBlock + tid;
-        kr[r] = i < n ? keys_in[i] : 0ull;
-        vr[r] = i < n ? vals_in[i] : 0u;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) ws[w] = x;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int k = 0; k < w; ++k) off += ws[k];
+    __syncthreads();
+    return off + x - v;
+}
+
+__global__ __launch_bounds__(kOsBlock) void k_os_pass(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                      uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                      OsArgs a, int pass)
+{
+    __shared__ uint64_t sk[kOsTile];
+    __shared__ uint32_t sv[kOsTile];
+    __shared__ uint32_t hist[256], tstart[256], run[256], wcnt[kOsBlock / 64][256];
+    __shared__ uint64_t gbase[256];    // global position of this tile's first key of each digit
+    __shared__ uint32_t ws[kOsBlock / 64];
+    __shared__ uint32_t s_tile;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int shift = a.lo_bit + 8 * pass;
+    if (tid == 0) s_tile = atomicAdd(&a.tile_ctr[pass], 1u);
+    hist[tid] = 0u;
+    run[tid] = 0u;
+    __syncthreads();
+    const int64_t tile = int64_t(s_tile);
+    const int64_t base = tile * kOsTile;
+    uint64_t kr[kOsItems];
+    uint32_t vr[kOsItems];
+#pragma unroll
+    for (int r = 0; r < kOsItems; ++r) {
+        const int64_t i = base + int64_t(r) * kOsBlock + tid;
+        kr[r] = i < a.n ? kin[i] : 0ull;
+        vr[r] = i < a.n ? vin[i] : 0u;
     }
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
+    for (int r = 0; r < kOsItems; ++r)
+        if (base + int64_t(r) * kOsBlock + tid < a.n) atomicAdd(&hist[uint32_t(kr[r] >> shift) & 255u], 1u);
+    __syncthreads();
+    // publish this tile's counts, then look back for the counts of all earlier tiles
+    unsigned long long* st = a.status + (int64_t(pass) * a.ntile) * 256;
+    const uint32_t mine = hist[tid];
+    if (tile == 0) {
+        __hip_atomic_store(&st[tid], kOsInc | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        __hip_atomic_store(&st[tile * 256 + tid], kOsAgg | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    uint64_t excl = 0;
+    if (tile > 0) {
+        int64_t t = tile - 1;
+        uint32_t spins = 0;
+        for (;;) {
+            const uint64_t s = __hip_atomic_load(&st[t * 256 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (s & kOsInc) { excl += s & kOsCount; break; }
+            if (s & kOsAgg) { excl += s & kOsCount; --t; spins = 0; continue; }
+            if (++spins > kOsSpinMax) { atomicOr(a.err, 1u); break; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __hip_atomic_store(&st[tile * 256 + tid], kOsInc | (excl + mine), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // digit starts: global (digits below d over all keys + this digit in earlier tiles) and in the tile
+    const uint32_t g = a.hist[pass * 256 + tid];
+    const uint32_t gex = os_block_excl(g, ws);
+    const uint32_t tex = os_block_excl(mine, ws);
+    gbase[tid] = uint64_t(gex) + excl;
+    tstart[tid] = tex;
+    __syncthreads();
+    // stable ranks in the tile: round r, wave w holds keys r*256 + 64w + lane
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-        for (int w = 0; w < kSortBlock / 64; ++w) wcnt[w][tid] = 0;
+    for (int r = 0; r < kOsItems; ++r) {
+#pragma unroll
+        for (int w = 0; w < kOsBlock / 64; ++w) wcnt[w][tid] = 0u;
         __syncthreads();
-        int64_t i = base + int64_t(r) * kSortBlock + tid;
-        bool valid = i < n;
-        uint64_t key = kr[r];
-        uint32_t val = vr[r];
-        uint32_t d = uint32_t(key >> shift) & 255u;
+        const bool valid = base + int64_t(r) * kOsBlock + tid < a.n;
+        const uint32_t d = uint32_t(kr[r] >> shift) & 255u;
         uint64_t m = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            uint64_t bal = __ballot(valid && ((d >> b) & 1u));
+            const uint64_t bal = __ballot(valid && ((d >> b) & 1u));
             m &= ((d >> b) & 1u) ? bal : ~bal;
         }
-        int rank = __popcll(m & lt);
+        const int rank = __popcll(m & lt);
         if (valid && rank == 0) wcnt[wid][d] = uint32_t(__popcll(m));
         __syncthreads();
         if (valid) {
             uint32_t pre = 0;
             for (int w = 0; w < wid; ++w) pre += wcnt[w][d];
-            uint32_t pos = boff[d] + run[d] + pre + uint32_t(rank);
-            keys_out[pos] = key;
-            vals_out[pos] = val;
+            const uint32_t pos = tstart[d] + run[d] + pre + uint32_t(rank);
+            sk[pos] = kr[r];
+            sv[pos] = vr[r];
         }
         __syncthreads();
         uint32_t tot = 0;
 #pragma unroll
-        for (int w = 0; w < kSortBlock / 64; ++w) tot += wcnt[w][tid];
+        for (int w = 0; w < kOsBlock / 64; ++w) tot += wcnt[w][tid];
         run[tid] += tot;
         __syncthreads();
+    }
+    // write out in tile order: consecutive threads of one digit write consecutive positions
+    const int64_t cnt = a.n - base < kOsTile ? a.n - base : kOsTile;
+    for (int i = tid; i < int(cnt); i += kOsBlock) {
+        const uint64_t k = sk[i];
+        const uint32_t d = uint32_t(k >> shift) & 255u;
+        const uint64_t pos = gbase[d] + uint64_t(i - int(tstart[d]));
+        if (pos < uint64_t(a.n)) {
+            kout[pos] = k;
+            vout[pos] = sv[i];
+        }
     }
 }
 
