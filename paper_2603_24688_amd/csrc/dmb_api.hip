@@ -251,7 +251,7 @@ dmb_status radix_sort(dmb_ctx* c, uint64_t** ka, uint32_t** va, uint64_t** kb, u
     a.ntile = ntile;
     hipLaunchKernelGGL(k_os_clear, dim3(1), dim3(256), 0, c->stream, a.hist, nw);
     const int hb = int(std::min<int64_t>(2048, std::max<int64_t>(ntile, (int64_t(passes) * ntile * 256 + 4095) / 4096)));
-    hipLaunchKernelGGL(k_os_hist, dim3(hb), dim3(kOsBlock), 0, c->stream, *ka, a);
+    hipLaunchKernelGGL(k_os_hist, dim3(hb), dim3(kOsHistBlock), 0, c->stream, *ka, a);
     for (int p = 0; p < passes; ++p) {
         hipLaunchKernelGGL(k_os_pass, dim3(unsigned(ntile)), dim3(kOsBlock), 0, c->stream, *ka, *va, *kb, *vb, a, p);
         std::swap(*ka, *kb);

@@ -104,8 +104,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(TO* __restrict__ out, c
 // already running and publish their counts before they look back
 // themselves; the wait is still bounded (kOsSpinMax polls, then an error
 // flag is raised and the pass ends).
-constexpr int kOsBlock = 256;
-constexpr int kOsItems = 16;
+constexpr int kOsBlock = 512;
+constexpr int kOsItems = 8;
 constexpr int kOsTile = kOsBlock * kOsItems;   // 4096 keys per tile
 constexpr int kOsMaxPasses = 8;
 constexpr uint64_t kOsAgg = 1ull << 62;        // status: this tile's own count is available
@@ -124,13 +124,14 @@ struct OsArgs {
 };
 
 // Global digit histograms of all passes; also clears the look-back state.
-__global__ __launch_bounds__(kOsBlock) void k_os_hist(const uint64_t* __restrict__ keys, OsArgs a)
+constexpr int kOsHistBlock = 256;
+__global__ __launch_bounds__(kOsHistBlock) void k_os_hist(const uint64_t* __restrict__ keys, OsArgs a)
 {
     __shared__ uint32_t h[kOsMaxPasses][256];
     for (int p = 0; p < a.passes; ++p) h[p][threadIdx.x] = 0u;
     __syncthreads();
-    const int64_t stride = int64_t(gridDim.x) * kOsBlock;
-    for (int64_t i = int64_t(blockIdx.x) * kOsBlock + threadIdx.x; i < a.n; i += stride) {
+    const int64_t stride = int64_t(gridDim.x) * kOsHistBlock;
+    for (int64_t i = int64_t(blockIdx.x) * kOsHistBlock + threadIdx.x; i < a.n; i += stride) {
         const uint64_t k = keys[i];
         for (int p = 0; p < a.passes; ++p) atomicAdd(&h[p][uint32_t(k >> (a.lo_bit + 8 * p)) & 255u], 1u);
     }
@@ -138,10 +139,11 @@ __global__ __launch_bounds__(kOsBlock) void k_os_hist(const uint64_t* __restrict
     for (int p = 0; p < a.passes; ++p)
         if (h[p][threadIdx.x]) atomicAdd(&a.hist[p * 256 + threadIdx.x], h[p][threadIdx.x]);
     const int64_t nst = int64_t(a.passes) * a.ntile * 256;
-    for (int64_t i = int64_t(blockIdx.x) * kOsBlock + threadIdx.x; i < nst; i += stride) a.status[i] = 0ull;
+    for (int64_t i = int64_t(blockIdx.x) * kOsHistBlock + threadIdx.x; i < nst; i += stride) a.status[i] = 0ull;
 }
 
-// Exclusive scan over the 256 threads of a block (one value each).
+// Exclusive scan of one value per digit held by threads 0..255 of the block
+// (every thread of the block calls it; threads >= 256 pass 0 and get 0).
 __device__ __forceinline__ uint32_t os_block_excl(uint32_t v, uint32_t* ws)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -151,10 +153,10 @@ __device__ __forceinline__ uint32_t os_block_excl(uint32_t v, uint32_t* ws)
         const uint32_t y = __shfl_up(x, d);
         if (lane >= d) x += y;
     }
-    if (lane == 63) ws[w] = x;
+    if (lane == 63 && w < 4) ws[w] = x;
     __syncthreads();
     uint32_t off = 0;
-    for (int k = 0; k < w; ++k) off += ws[k];
+    for (int k = 0; k < w && k < 4; ++k) off += ws[k];
     __syncthreads();
     return off + x - v;
 }
@@ -163,42 +165,63 @@ __global__ __launch_bounds__(kOsBlock) void k_os_pass(const uint64_t* __restrict
                                                       uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                       OsArgs a, int pass)
 {
+    constexpr int kW = kOsBlock / 64;          // waves; wave w owns keys [w, w + 1) * kOsTile / kW of the tile
     __shared__ uint64_t sk[kOsTile];
     __shared__ uint32_t sv[kOsTile];
-    __shared__ uint32_t hist[256], tstart[256], run[256], wcnt[kOsBlock / 64][256];
+    __shared__ uint32_t hist[256], tstart[256], wcnt[kW][256];
     __shared__ uint64_t gbase[256];    // global position of this tile's first key of each digit
-    __shared__ uint32_t ws[kOsBlock / 64];
+    __shared__ uint32_t ws[4];
     __shared__ uint32_t s_tile;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int shift = a.lo_bit + 8 * pass;
+    const bool dig = tid < 256;                // threads 0..255 own one digit each
     if (tid == 0) s_tile = atomicAdd(&a.tile_ctr[pass], 1u);
-    hist[tid] = 0u;
-    run[tid] = 0u;
+    for (int k = tid; k < 256 * (kW + 1); k += kOsBlock) (k < 256 ? hist[k] : wcnt[k / 256 - 1][k % 256]) = 0u;
     __syncthreads();
     const int64_t tile = int64_t(s_tile);
     const int64_t base = tile * kOsTile;
+    const int64_t wbase = base + int64_t(wid) * (kOsTile / kW);
     uint64_t kr[kOsItems];
     uint32_t vr[kOsItems];
 #pragma unroll
-    for (int r = 0; r < kOsItems; ++r) {
-        const int64_t i = base + int64_t(r) * kOsBlock + tid;
+    for (int r = 0; r < kOsItems; ++r) {       // round r: 64 consecutive keys of the wave's chunk
+        const int64_t i = wbase + int64_t(r) * 64 + lane;
         kr[r] = i < a.n ? kin[i] : 0ull;
         vr[r] = i < a.n ? vin[i] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < kOsItems; ++r)
-        if (base + int64_t(r) * kOsBlock + tid < a.n) atomicAdd(&hist[uint32_t(kr[r] >> shift) & 255u], 1u);
+        if (wbase + int64_t(r) * 64 + lane < a.n) atomicAdd(&hist[uint32_t(kr[r] >> shift) & 255u], 1u);
     __syncthreads();
     // publish this tile's counts, then look back for the counts of all earlier tiles
     unsigned long long* st = a.status + (int64_t(pass) * a.ntile) * 256;
-    const uint32_t mine = hist[tid];
-    if (tile == 0) {
+    const uint32_t mine = dig ? hist[tid] : 0u;
+    if (dig && tile == 0) {
         __hip_atomic_store(&st[tid], kOsInc | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+    } else if (dig) {
         __hip_atomic_store(&st[tile * 256 + tid], kOsAgg | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    // stable ranks within the wave's chunk, wave-private counts (no block barrier per round)
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint32_t rk[kOsItems];
+#pragma unroll
+    for (int r = 0; r < kOsItems; ++r) {
+        const bool valid = wbase + int64_t(r) * 64 + lane < a.n;
+        const uint32_t d = uint32_t(kr[r] >> shift) & 255u;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bal = __ballot(valid && ((d >> b) & 1u));
+            m &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        const uint32_t before = valid ? wcnt[wid][d] : 0u;
+        rk[r] = before + uint32_t(__popcll(m & lt));
+        // the first lane of each digit group adds the group; a wave's LDS operations
+        // complete in issue order, so the next round reads the updated count
+        if (valid && (m & lt) == 0ull) wcnt[wid][d] = before + uint32_t(__popcll(m));
+    }
     uint64_t excl = 0;
-    if (tile > 0) {
+    if (dig && tile > 0) {
         int64_t t = tile - 1;
         uint32_t spins = 0;
         for (;;) {
@@ -210,45 +233,33 @@ __global__ __launch_bounds__(kOsBlock) void k_os_pass(const uint64_t* __restrict
         }
         __hip_atomic_store(&st[tile * 256 + tid], kOsInc | (excl + mine), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    // digit starts: global (digits below d over all keys + this digit in earlier tiles) and in the tile
-    const uint32_t g = a.hist[pass * 256 + tid];
+    // digit starts: global (digits below d over all keys + this digit in earlier tiles), in the tile,
+    // and per wave (earlier waves' keys of the digit)
+    const uint32_t g = dig ? a.hist[pass * 256 + tid] : 0u;
     const uint32_t gex = os_block_excl(g, ws);
     const uint32_t tex = os_block_excl(mine, ws);
-    gbase[tid] = uint64_t(gex) + excl;
-    tstart[tid] = tex;
+    if (dig) {
+        gbase[tid] = uint64_t(gex) + excl;
+        tstart[tid] = tex;
+        uint32_t acc = tex;
+#pragma unroll
+        for (int w = 0; w < kW; ++w) {
+            const uint32_t cw = wcnt[w][tid];
+            wcnt[w][tid] = acc;            // becomes the wave's first tile position of the digit
+            acc += cw;
+        }
+    }
     __syncthreads();
-    // stable ranks in the tile: round r, wave w holds keys r*256 + 64w + lane
-    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int r = 0; r < kOsItems; ++r) {
-#pragma unroll
-        for (int w = 0; w < kOsBlock / 64; ++w) wcnt[w][tid] = 0u;
-        __syncthreads();
-        const bool valid = base + int64_t(r) * kOsBlock + tid < a.n;
-        const uint32_t d = uint32_t(kr[r] >> shift) & 255u;
-        uint64_t m = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const uint64_t bal = __ballot(valid && ((d >> b) & 1u));
-            m &= ((d >> b) & 1u) ? bal : ~bal;
-        }
-        const int rank = __popcll(m & lt);
-        if (valid && rank == 0) wcnt[wid][d] = uint32_t(__popcll(m));
-        __syncthreads();
-        if (valid) {
-            uint32_t pre = 0;
-            for (int w = 0; w < wid; ++w) pre += wcnt[w][d];
-            const uint32_t pos = tstart[d] + run[d] + pre + uint32_t(rank);
+        if (wbase + int64_t(r) * 64 + lane < a.n) {
+            const uint32_t d = uint32_t(kr[r] >> shift) & 255u;
+            const uint32_t pos = wcnt[wid][d] + rk[r];
             sk[pos] = kr[r];
             sv[pos] = vr[r];
         }
-        __syncthreads();
-        uint32_t tot = 0;
-#pragma unroll
-        for (int w = 0; w < kOsBlock / 64; ++w) tot += wcnt[w][tid];
-        run[tid] += tot;
-        __syncthreads();
     }
+    __syncthreads();
     // write out in tile order: consecutive threads of one digit write consecutive positions
     const int64_t cnt = a.n - base < kOsTile ? a.n - base : kOsTile;
     for (int i = tid; i < int(cnt); i += kOsBlock) {
