@@ -143,6 +143,28 @@ dmb_status dmb_build_cells(dmb_ctx *ctx, const dmb_particles *gas, const dmb_par
 dmb_status dmb_interact_step(dmb_ctx *ctx, const dmb_particles *gas, const dmb_particles *dm,
                              const dmb_params *params, dmb_out *out);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): dmb_build_cells
+ * followed by dmb_interact_step in one call, with every scratch buffer of
+ * both carved from a static device array of DMB_STATIC_SCRATCH_MIB MiB
+ * instead of device allocations.  Each GPU the library runs on holds its own
+ * copy of the array until the process ends (looked up by dmb_create).
+ * The caller passes inputs and outputs as for dmb_interact_step, and the
+ * outputs are identical to theirs.  Limits: n_gas, n_dm <= DMB_STATIC_MAX_N;
+ * rates DMB_RATES_EXACT; phase timing off.  Every call on one GPU shares that
+ * GPU's array, so calls that overlap on one GPU (from any context or
+ * stream) race; the array keeps the last call's contents and every call
+ * rebuilds what it reads.  The structure of the last dmb_build_cells on ctx is
+ * left untouched.  Synchronises the stream (as dmb_build_cells does).
+ * Errors: those of dmb_build_cells / dmb_interact_step; DMB_ERANGE for sizes
+ * above the limit; DMB_EINVAL for other rate modes or with phase timing on;
+ * DMB_ENOMEM when the inputs need more scratch than the array holds (very
+ * dense neighbour structures). */
+#define DMB_STATIC_SCRATCH_MIB 256
+#define DMB_STATIC_MAX_N 262144
+dmb_status dmb_step_static(dmb_ctx *ctx, const dmb_particles *gas, const dmb_particles *dm,
+                           const dmb_params *params, dmb_out *out);
+
 /* The pair set of Sec. 2.4 (every overlapping pair d_ij < h_i + h_j, the
  * support of the overlap of Appendix D, processed once per pass) as the two
  * pair passes enumerate it.  Runs one interaction step exactly as

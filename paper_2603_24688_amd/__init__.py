@@ -28,7 +28,7 @@ EXPORTS = ["dmb_create", "dmb_destroy", "dmb_set_stream", "dmb_build_cells", "dm
            "dmb_build_stats", "dmb_last_error", "dmb_mlp_labels", "dmb_mlp_init", "dmb_mlp_set_params",
            "dmb_mlp_get_params", "dmb_mlp_grad", "dmb_mlp_train", "dmb_mlp_eval", "dmb_batch_build",
            "dmb_batch_step", "dmb_batch_tune", "dmb_set_search_groups", "dmb_pair_list",
-           "dmb_sort_pairs"]
+           "dmb_sort_pairs", "dmb_step_static"]
 BUILD_STATS = ["active_gas", "active_dm", "gas_tiles", "dm_tiles", "gas_owner_tiles", "dm_owner_tiles",
                "cand_pairs_gas", "cand_pairs_dm", "items_gas", "items_dm"]
 PHASES = ["build", "gather", "pass_gas", "combine_gas", "pass_dm", "combine_dm", "resolve"]
@@ -89,6 +89,8 @@ def load_library(path: str = LIB_PATH):
     L.dmb_pair_list.restype = C.c_int
     L.dmb_pair_list.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params), C.POINTER(Out),
                                 i64, vp, vp, vp]
+    L.dmb_step_static.restype = C.c_int
+    L.dmb_step_static.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params), C.POINTER(Out)]
     L.dmb_sort_pairs.restype = C.c_int; L.dmb_sort_pairs.argtypes = [vp, i64, vp, vp, i32, i32, vp, vp]
     L.dmb_overlap_eval.restype = C.c_int; L.dmb_overlap_eval.argtypes = [vp, i64, vp, vp, vp, i32, vp]
     L.dmb_rates_eval.restype = C.c_int; L.dmb_rates_eval.argtypes = [vp, i64, vp, vp, i32, i32, i32, i32, vp, vp]
@@ -219,6 +221,14 @@ class Context:
         self._check(self.lib.dmb_sort_pairs(self.h, keys.numel(), _ptr(keys), _ptr(vals), int(lo_bit), int(passes),
                                             _ptr(ko), _ptr(vo)), "dmb_sort_pairs")
         return ko, vo
+
+    def step_static(self, gas: dict, dm: dict, params: dict, out: dict, precision: int = DMB_FP32):
+        """build_cells + interact_step in one call that allocates no device memory (static scratch)."""
+        G, D, P = _particles(gas), _particles(dm), _params(params, precision)
+        O = Out(_ptr(out["dv_dm"]), _ptr(out["dp_gas"]), _ptr(out["de_gas"]), _ptr(out["partner"]),
+                _ptr(out.get("p_sum")), _ptr(out.get("p_max")), _ptr(out.get("counters")))
+        self._check(self.lib.dmb_step_static(self.h, C.byref(G), C.byref(D), C.byref(P), C.byref(O)),
+                    "dmb_step_static")
 
     def build_stats(self) -> dict:
         v = (C.c_int64 * len(BUILD_STATS))()

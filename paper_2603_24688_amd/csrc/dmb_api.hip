@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -58,6 +59,17 @@ struct Pairs {                             // candidate lists: owner tiles of A 
     int64_t npairs = 0, total = 0, nitems = 0;
 };
 
+// Grow-only scratch of one build + step (scans, radix sort, read-backs).
+struct Scratch {
+    DevBuf scan_tmp[4];
+    DevBuf os_hist;                        // radix sort: digit counts of every pass, then tile counters
+    DevBuf os_status;                      // radix sort: look-back words [passes][tiles][256]
+    DevBuf bbox_part;
+    DevBuf counters_local;
+    DevBuf pair_cnt;                       // pair export counts [gas pass, DM pass]
+    DevBuf rb_dev;                         // build-stage scalars for the host (one copy per stage)
+};
+
 // Cell structure and per-step buffers of one box (one periodic volume or
 // open region).  The context keeps one for dmb_build_cells / dmb_interact_step
 // and one per box of the batched calls.
@@ -84,17 +96,18 @@ struct dmb_ctx {
     Cells* X = &cells;                     // structure the internal build / step functions act on
     std::vector<Cells*> boxes;             // batched boxes
     DevBuf bstep, bgeom, bitem;            // batched step: Philox step offset, per-box pass arguments, item offsets
-    DevBuf scan_tmp[4];
-    DevBuf os_hist;                        // radix sort: digit counts of every pass, then tile counters
-    DevBuf os_status;                      // radix sort: look-back words [passes][tiles][256]
+    Scratch heap;                          // per-call scratch of the entry points that allocate
+    Scratch* S = &heap;                    // scratch set in use (dmb_step_static swaps in its own)
     DevBuf os_err;                         // radix sort: raised when a look-back wait gave up (sticky)
-    DevBuf bbox_part;
-    DevBuf counters_local;
-    // pair export (dmb_pair_list): destination lists, capacity, device counts [gas pass, DM pass]
+    // pair export (dmb_pair_list): destination lists, capacity
     uint32_t* pair_dst[2] = {nullptr, nullptr};
     int64_t pair_cap = 0;
-    DevBuf pair_cnt;
-    DevBuf rb_dev;                         // build-stage scalars for the host (one copy per stage)
+    // static scratch (dmb_step_static): this device's copy of the file-scope array, and the
+    // bump-carving state while a static call runs (arena != nullptr)
+    char* static_ptr = nullptr;
+    char* arena = nullptr;
+    size_t arena_cap = 0, arena_off = 0;
+    Cells static_cells;
     uint64_t* rb_host = nullptr;           // pinned
     int split = 32;                        // candidate sub-tiles per work item of the DM pass (tunable);
                                            // the gas pass, whose partial sums cost more to combine, twice that
@@ -143,6 +156,16 @@ dmb_status ensure(dmb_ctx* c, DevBuf& b, size_t bytes)
 {
     if (bytes == 0) bytes = 256;
     if (bytes <= b.cap) return DMB_OK;
+    if (c->arena) {   // a static call: carve from the static scratch, never allocate
+        const size_t off = (c->arena_off + 255) & ~size_t(255);
+        if (off > c->arena_cap || bytes > c->arena_cap - off)
+            return fail(c, DMB_ENOMEM, "static scratch of %zu bytes exhausted (%zu in use, %zu more requested)",
+                        c->arena_cap, off, bytes);
+        b.p = c->arena + off;
+        b.cap = bytes;
+        c->arena_off = off + bytes;
+        return DMB_OK;
+    }
     if (b.p) {
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return fail(c, DMB_EHIP, "sync before realloc: %s", hipGetErrorString(e));
@@ -208,8 +231,8 @@ dmb_status scan_excl(dmb_ctx* c, const TI* in, TO* out, int64_t n, int64_t n_in 
     if (n_in < 0 || n_in > n) n_in = n;
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (level >= 4) return fail(c, DMB_EINVAL, "scan too large");
-    ENSURE(c, c->scan_tmp[level], size_t(nb + 1) * sizeof(TO));
-    TO* sums = c->scan_tmp[level].as<TO>();
+    ENSURE(c, c->S->scan_tmp[level], size_t(nb + 1) * sizeof(TO));
+    TO* sums = c->S->scan_tmp[level].as<TO>();
     hipLaunchKernelGGL((k_scan_block<TI, TO>), dim3(unsigned(nb)), dim3(kScanBlock), 0, c->stream, in, out, sums, n,
                        n_in);
     if (nb > 1 && nb <= kScanOwnMax) {
@@ -240,13 +263,13 @@ dmb_status radix_sort(dmb_ctx* c, uint64_t** ka, uint32_t** va, uint64_t** kb, u
     if (passes > kOsMaxPasses) return fail(c, DMB_EINVAL, "radix sort: %d passes", passes);
     const int64_t ntile = (n + kOsTile - 1) / kOsTile;
     const int nw = kOsMaxPasses * 256 + kOsMaxPasses;
-    ENSURE(c, c->os_hist, size_t(nw) * 4);
-    ENSURE(c, c->os_status, size_t(passes) * size_t(ntile) * 256 * 8);
+    ENSURE(c, c->S->os_hist, size_t(nw) * 4);
+    ENSURE(c, c->S->os_status, size_t(passes) * size_t(ntile) * 256 * 8);
     OsArgs a;
     a.n = n; a.passes = passes; a.lo_bit = lo_bit;
-    a.hist = c->os_hist.as<uint32_t>();
+    a.hist = c->S->os_hist.as<uint32_t>();
     a.tile_ctr = a.hist + kOsMaxPasses * 256;
-    a.status = c->os_status.as<unsigned long long>();
+    a.status = c->S->os_status.as<unsigned long long>();
     a.err = c->os_err.as<uint32_t>();
     a.ntile = ntile;
     hipLaunchKernelGGL(k_os_clear, dim3(1), dim3(256), 0, c->stream, a.hist, nw);
@@ -294,10 +317,10 @@ dmb_status build_species(dmb_ctx* c, Species& S, const dmb_particles* p)
     // then); enough blocks to fill the chip
     const bool periodic = c->X->built_L[0] > 0.0;
     const int nparts = periodic ? 0 : int(std::min<int64_t>(2048, (n + 1023) / 1024));
-    ENSURE(c, c->bbox_part, std::max(nparts, 1) * 6 * sizeof(double));
+    ENSURE(c, c->S->bbox_part, std::max(nparts, 1) * 6 * sizeof(double));
     if (nparts > 0)
-        hipLaunchKernelGGL(k_bbox_partial, dim3(nparts), dim3(256), 0, c->stream, p->pos, n, c->bbox_part.as<double>());
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, c->stream, c->bbox_part.as<const double>(), nparts,
+        hipLaunchKernelGGL(k_bbox_partial, dim3(nparts), dim3(256), 0, c->stream, p->pos, n, c->S->bbox_part.as<double>());
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, c->stream, c->S->bbox_part.as<const double>(), nparts,
                        c->X->boxL.as<const double>(), S.cube.as<double>());
     ENSURE(c, S.prec, n * sizeof(double4));
     hipLaunchKernelGGL(k_morton, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, p->pos, p->h, n,
@@ -768,7 +791,7 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
         GasPassArgs a = gas_pass_args<Real, N, RM>(c, X, gas, par, out, counters);
         if constexpr (PAIRS) {
             a.g.pairs = c->pair_dst[0]; a.g.pair_cap = uint64_t(c->pair_cap);
-            a.g.pair_n = c->pair_cnt.as<unsigned long long>();
+            a.g.pair_n = c->S->pair_cnt.as<unsigned long long>();
         }
         const int nb = persist_blocks(c, (const void*)k_pass_gas<Real, N, kExact, RM, false, PAIRS>, 64 * kW,
                                       (X.gp.nitems + kW - 1) / kW);
@@ -784,7 +807,7 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
         DmPassArgs a = dm_pass_args(c, X, par, out, counters, nullptr);
         if constexpr (PAIRS) {
             a.g.pairs = c->pair_dst[1]; a.g.pair_cap = uint64_t(c->pair_cap);
-            a.g.pair_n = c->pair_cnt.as<unsigned long long>() + 1;
+            a.g.pair_n = c->S->pair_cnt.as<unsigned long long>() + 1;
         }
         const int nb = persist_blocks(c, (const void*)k_pass_dm<Real, N, kExact, false, PAIRS>, 64, X.dp.nitems);
         {
@@ -1136,8 +1159,36 @@ dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_part
 }
 
 // ===========================================================================
+// Static scratch of dmb_step_static: one copy of this array per GPU the
+// library is loaded on, held until the process ends.  Host code never uses
+// the array's name as an address: dmb_create looks up each device's copy once
+// (with that device current) and every later use goes through that pointer.
+constexpr size_t kStaticScratchBytes = size_t(DMB_STATIC_SCRATCH_MIB) << 20;
+constexpr int64_t kStaticMaxN = DMB_STATIC_MAX_N;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
 char g_create_err[256] = "no error";   // message of the last failed dmb_create (no context exists then)
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's address of `scratch` (the device must be current).
+hipError_t static_scratch_of(int device, void** ptr)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
 }
 
 extern "C" {
@@ -1159,6 +1210,21 @@ dmb_status dmb_create(dmb_ctx** out, int device, void* hip_stream)
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         c->num_cu = ncu;
+    void* sp = nullptr;
+    he = static_scratch_of(device, &sp);
+    if (he != hipSuccess) {
+        snprintf(g_create_err, sizeof(g_create_err), "static scratch of device %d: %s", device, hipGetErrorString(he));
+        delete c;
+        return DMB_EHIP;
+    }
+    c->static_ptr = static_cast<char*>(sp);
+    he = hipHostMalloc(reinterpret_cast<void**>(&c->rb_host), kReadbackMax * sizeof(uint64_t));
+    if (he != hipSuccess) {
+        c->rb_host = nullptr;
+        snprintf(g_create_err, sizeof(g_create_err), "pinned read-back buffer: %s", hipGetErrorString(he));
+        delete c;
+        return DMB_ENOMEM;
+    }
     size_t tb = size_t(kTabCells) * 4 * sizeof(float4);
     const int64_t nnodes = 2 * int64_t(kTabNodesRegion);
     DevBuf nodes;
@@ -1199,15 +1265,16 @@ dmb_status dmb_destroy(dmb_ctx* c)
     }
     c->boxes.clear();
     auto fr = [](DevBuf& b) { if (b.p) hipFree(b.p); b.p = nullptr; b.cap = 0; };
-    for (auto& b : c->scan_tmp) fr(b);
+    for (auto& b : c->heap.scan_tmp) fr(b);
     for (auto& p : c->pending) { c->ev_pool.push_back(p.a); c->ev_pool.push_back(p.b); }
     for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
     DevBuf* mlp[] = {&c->mlp_p, &c->mlp_m, &c->mlp_v, &c->mlp_blob, &c->mlp_part, &c->mlp_red, &c->mlp_ts,
                      &c->mlp_loss, &c->mlp_epoch, &c->mlp_shuf};
     for (DevBuf* b : mlp) fr(*b);
     if (c->train_stream) hipStreamDestroy(c->train_stream);
-    DevBuf* rest[] = {&c->gl64, &c->gl32, &c->gtab, &c->os_hist, &c->os_status, &c->os_err, &c->bbox_part,
-                      &c->counters_local, &c->bstep, &c->bgeom, &c->bitem, &c->rb_dev};
+    DevBuf* rest[] = {&c->gl64, &c->gl32, &c->gtab, &c->heap.os_hist, &c->heap.os_status, &c->os_err,
+                      &c->heap.bbox_part, &c->heap.counters_local, &c->heap.pair_cnt, &c->bstep, &c->bgeom,
+                      &c->bitem, &c->heap.rb_dev};
     for (DevBuf* b : rest) fr(*b);
     if (c->rb_host) hipHostFree(c->rb_host);
     delete c;
@@ -1299,11 +1366,11 @@ struct Readback {
 dmb_status readback(dmb_ctx* c, const Readback& r, uint64_t* out)
 {
     if (r.a.cnt == 0) return DMB_OK;
-    ENSURE(c, c->rb_dev, kReadbackMax * sizeof(uint64_t));
+    ENSURE(c, c->S->rb_dev, kReadbackMax * sizeof(uint64_t));
     if (!c->rb_host) HIPCHK(c, hipHostMalloc(reinterpret_cast<void**>(&c->rb_host), kReadbackMax * sizeof(uint64_t)));
-    hipLaunchKernelGGL(k_readback, dim3(1), dim3(256), 0, c->stream, r.a, c->rb_dev.as<uint64_t>());
+    hipLaunchKernelGGL(k_readback, dim3(1), dim3(256), 0, c->stream, r.a, c->S->rb_dev.as<uint64_t>());
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(c->rb_host, c->rb_dev.p, r.a.cnt * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->rb_host, c->S->rb_dev.p, r.a.cnt * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     std::memcpy(out, c->rb_host, r.a.cnt * sizeof(uint64_t));
     return DMB_OK;
@@ -1425,7 +1492,6 @@ dmb_status check_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles*
     dmb_status s;
     if ((s = check_particles(c, gas, "gas", true)) != DMB_OK) return s;
     if ((s = check_particles(c, dm, "dm", false)) != DMB_OK) return s;
-    c->X = &c->cells;
     if (gas->n != c->X->built_ngas || dm->n != c->X->built_ndm)
         return fail(c, DMB_ESTALE, "interact_step: sizes differ from the last build_cells");
     if (gas->n > 0 && (!gas->vel || !gas->mass || !gas->u))
@@ -1453,13 +1519,14 @@ dmb_status dmb_interact_step(dmb_ctx* c, const dmb_particles* gas, const dmb_par
                              dmb_out* out)
 {
     if (!c) return DMB_EINVAL;
+    c->X = &c->cells;
     dmb_status s0 = check_step(c, gas, dm, par, out);
     if (s0 != DMB_OK) return s0;
     HIPCHK(c, hipSetDevice(c->device));
     uint64_t* counters = out->counters;
     if (!counters) {
-        ENSURE(c, c->counters_local, DMB_NCOUNTERS * 8);
-        counters = c->counters_local.as<uint64_t>();
+        ENSURE(c, c->S->counters_local, DMB_NCOUNTERS * 8);
+        counters = c->S->counters_local.as<uint64_t>();
     }
     if (par->precision == DMB_FP64) return dispatch_rates<double>(c, gas, dm, par, out, counters);
     if (par->precision == DMB_FP32) return dispatch_rates<float>(c, gas, dm, par, out, counters);
@@ -1470,6 +1537,7 @@ dmb_status dmb_pair_list(dmb_ctx* c, const dmb_particles* gas, const dmb_particl
                          dmb_out* out, int64_t cap, uint32_t* pairs_gas, uint32_t* pairs_dm, int64_t* counts)
 {
     if (!c) return DMB_EINVAL;
+    c->X = &c->cells;
     dmb_status s0 = check_step(c, gas, dm, par, out);
     if (s0 != DMB_OK) return s0;
     if (par->n_pow != 0 || par->rates != DMB_RATES_EXACT)
@@ -1481,18 +1549,18 @@ dmb_status dmb_pair_list(dmb_ctx* c, const dmb_particles* gas, const dmb_particl
     HIPCHK(c, hipSetDevice(c->device));
     uint64_t* counters = out->counters;
     if (!counters) {
-        ENSURE(c, c->counters_local, DMB_NCOUNTERS * 8);
-        counters = c->counters_local.as<uint64_t>();
+        ENSURE(c, c->S->counters_local, DMB_NCOUNTERS * 8);
+        counters = c->S->counters_local.as<uint64_t>();
     }
-    ENSURE(c, c->pair_cnt, 2 * sizeof(unsigned long long));
-    HIPCHK(c, hipMemsetAsync(c->pair_cnt.p, 0, 2 * sizeof(unsigned long long), c->stream));
+    ENSURE(c, c->S->pair_cnt, 2 * sizeof(unsigned long long));
+    HIPCHK(c, hipMemsetAsync(c->S->pair_cnt.p, 0, 2 * sizeof(unsigned long long), c->stream));
     c->pair_dst[0] = pairs_gas; c->pair_dst[1] = pairs_dm; c->pair_cap = cap;
     dmb_status s = par->precision == DMB_FP64 ? launch_step<double, 0, kRatesExact, true>(c, gas, dm, par, out, counters)
                                               : launch_step<float, 0, kRatesExact, true>(c, gas, dm, par, out, counters);
     c->pair_dst[0] = c->pair_dst[1] = nullptr; c->pair_cap = 0;
     if (s != DMB_OK) return s;
     unsigned long long n[2] = {0ull, 0ull};
-    HIPCHK(c, hipMemcpyAsync(n, c->pair_cnt.p, sizeof(n), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(n, c->S->pair_cnt.p, sizeof(n), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     Cells& X = *c->X;
     uint32_t* lists[2] = {pairs_gas, pairs_dm};
@@ -1507,6 +1575,51 @@ dmb_status dmb_pair_list(dmb_ctx* c, const dmb_particles* gas, const dmb_particl
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return DMB_OK;
+}
+
+dmb_status dmb_step_static(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
+                           dmb_out* out)
+{
+    if (!c) return DMB_EINVAL;
+    if (!par || !out) return fail(c, DMB_EINVAL, "null params or out");
+    dmb_status s;
+    if ((s = check_particles(c, gas, "gas", true)) != DMB_OK) return s;
+    if ((s = check_particles(c, dm, "dm", false)) != DMB_OK) return s;
+    if (gas->n > kStaticMaxN || dm->n > kStaticMaxN)
+        return fail(c, DMB_ERANGE, "step_static: n_gas %lld, n_dm %lld above the static limit %lld per species",
+                    (long long)gas->n, (long long)dm->n, (long long)kStaticMaxN);
+    const bool periodic = par->box[0] > 0.0 || par->box[1] > 0.0 || par->box[2] > 0.0;
+    if (periodic && !(par->box[0] > 0.0 && par->box[1] > 0.0 && par->box[2] > 0.0))
+        return fail(c, DMB_EINVAL, "periodic box needs three positive sides");
+    if (par->rates != DMB_RATES_EXACT) return fail(c, DMB_EINVAL, "step_static: needs DMB_RATES_EXACT");
+    if (c->prof) return fail(c, DMB_EINVAL, "step_static: phase timing is on (it creates events)");
+    if (!c->static_ptr || !c->rb_host) return fail(c, DMB_EHIP, "step_static: no static scratch on this device");
+    HIPCHK(c, hipSetDevice(c->device));
+    // the static cell structure and scratch set, carved afresh from the static array
+    Scratch fresh;
+    c->static_cells = Cells{};
+    c->S = &fresh;
+    c->X = &c->static_cells;
+    c->arena = c->static_ptr;
+    c->arena_cap = kStaticScratchBytes;
+    c->arena_off = 0;
+    s = build_cells_impl(c, gas, dm, par);
+    if (s == DMB_OK) s = check_step(c, gas, dm, par, out);
+    if (s == DMB_OK) {
+        uint64_t* counters = out->counters;
+        if (!counters && (s = ensure(c, c->S->counters_local, DMB_NCOUNTERS * 8)) == DMB_OK)
+            counters = c->S->counters_local.as<uint64_t>();
+        if (s == DMB_OK) {
+            if (par->precision == DMB_FP64) s = dispatch_rates<double>(c, gas, dm, par, out, counters);
+            else if (par->precision == DMB_FP32) s = dispatch_rates<float>(c, gas, dm, par, out, counters);
+            else s = fail(c, DMB_EINVAL, "precision %d not supported", par->precision);
+        }
+    }
+    c->arena = nullptr;
+    c->arena_cap = c->arena_off = 0;
+    c->S = &c->heap;
+    c->X = &c->cells;
+    return s;
 }
 
 dmb_status dmb_sort_pairs(dmb_ctx* c, int64_t n, const uint64_t* keys_in, const uint32_t* vals_in, int32_t lo_bit,

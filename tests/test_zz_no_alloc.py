@@ -1,0 +1,75 @@
+"""The entry point that allocates nothing (dmb_step_static) against the
+allocating pair dmb_build_cells + dmb_interact_step, through the C ABI:
+several calls in a row on one context, each later call smaller than an
+earlier one (the static scratch keeps the last call's contents), in both
+precisions and for periodic and open volumes; every output bit-identical."""
+import numpy as np
+import pytest
+
+import workloads
+from parity_util import run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2603_24688_amd as dmb
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = dmb.Context(0)
+    yield c
+    c.close()
+
+
+def _static(ctx, cfg, precision):
+    import torch
+    import paper_2603_24688_amd as dmb
+    G, D = dmb.to_device(cfg["gas"]), dmb.to_device(cfg["dm"])
+    out = dmb.alloc_out(len(cfg["gas"]["mass"]), len(cfg["dm"]["mass"]))
+    for v in out.values():
+        v.fill_(7)     # stale values must be overwritten
+    ctx.step_static(G, D, cfg["params"], out, precision=precision)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items() if k != "counters"}
+    res["counters"] = dmb.counters_dict(out["counters"])
+    return res
+
+
+def test_static_step_equals_build_and_step(ctx):
+    cases = [
+        ("box 4096+4096", workloads.box(seed=(19, 1), sigma0_cm2=3e-22), 1),
+        ("box 2000+1500", workloads.box(n_gas=2000, n_dm=1500, seed=(19, 2), sigma0_cm2=3e-22), 1),
+        ("galaxy 20000+80000", workloads.galaxy(n_gas=20000, n_dm=80000, seed=(2, 19), sigma0_cm2=1e-20), 0),
+        ("box 1000+900", workloads.box(n_gas=1000, n_dm=900, seed=(19, 3), sigma0_cm2=3e-22), 0),
+    ]
+    for label, cfg, prec in cases:
+        ref = run_gpu(ctx, cfg, prec)
+        got = _static(ctx, cfg, prec)
+        print(f"[static {label} prec {prec}] pairs {got['counters']['pairs_gas']} scatters "
+              f"{got['counters']['scatters']}", flush=True)
+        for k in ("dp_gas", "de_gas", "dv_dm", "partner", "p_sum", "p_max"):
+            assert np.array_equal(ref[k], got[k]), (label, k)
+        assert ref["counters"] == got["counters"], label
+        assert got["counters"]["pairs_gas"] > 0 and got["counters"]["scatters"] > 0
+
+
+def test_static_step_limits(ctx):
+    import paper_2603_24688_amd as dmb
+    cfg = workloads.box(n_gas=300, n_dm=300, seed=(19, 4), h_mode="density", n_ngb=8)
+    quad = dict(cfg["params"], rates=dmb.DMB_RATES_QUAD)
+    G, D = dmb.to_device(cfg["gas"]), dmb.to_device(cfg["dm"])
+    out = dmb.alloc_out(300, 300)
+    with pytest.raises(dmb.DmbError, match="EINVAL"):
+        ctx.step_static(G, D, quad, out)
+    import torch
+    big = {"pos": torch.zeros((dmb_max() + 1, 3), dtype=torch.float64, device="cuda"),
+           "mass": torch.ones(dmb_max() + 1, dtype=torch.float64, device="cuda"),
+           "h": torch.ones(dmb_max() + 1, dtype=torch.float64, device="cuda")}
+    with pytest.raises(dmb.DmbError, match="ERANGE"):
+        ctx.step_static(G, big, cfg["params"], dmb.alloc_out(300, dmb_max() + 1))
+
+
+def dmb_max():
+    return 262144
