@@ -143,6 +143,51 @@ dmb_status dmb_build_cells(dmb_ctx *ctx, const dmb_particles *gas, const dmb_par
 dmb_status dmb_interact_step(dmb_ctx *ctx, const dmb_particles *gas, const dmb_particles *dm,
                              const dmb_params *params, dmb_out *out);
 
+/* ------------------------------------------------------------------------
+ * Time loop.  nsteps steps of the method on one volume: each step rebuilds
+ * the neighbour structure, runs dmb_interact_step, then applies the DM kicks
+ * and the gas momentum and internal-energy transfers (from start-of-step
+ * states) and drifts both species with their new velocities (wrapped into
+ * [0, L) when periodic).  gas->pos, gas->vel, gas->u, dm->pos and dm->vel are
+ * UPDATED IN PLACE (device arrays).  Step k uses Philox step params->step + k.
+ * Timestep control (eq. prob_criterion, applied to the next step as the
+ * paper's implementation does): with cfg->dt_control, step k+1 takes
+ * dt = min(dt_max, dt_k * safety * crit / max_ij P_ij) where crit is the
+ * smallest criterion min(0.1, 1e-4 ((m_chi + mu_j)/mu_j)^2) over the gas;
+ * otherwise every step takes dt_max.  A per-particle dt is not allowed here.
+ * diag (HOST, (nsteps + 1) x DMB_NDIAG doubles): row 0 the initial state, row
+ * k the state after step k; all sums in binary64 in a fixed order. */
+enum {
+    DMB_D_TIME = 0,                 /* elapsed time, kpc/(km/s) */
+    DMB_D_DT = 1,                   /* length of this step (0 in row 0) */
+    DMB_D_P_DM = 2,                 /* [3] total DM momentum sum M v, Msun km/s */
+    DMB_D_P_GAS = 5,                /* [3] total gas momentum sum M V */
+    DMB_D_E_DM = 8,                 /* DM kinetic energy sum M v^2/2, Msun (km/s)^2 */
+    DMB_D_E_GAS = 9,                /* gas energy sum M (V^2/2 + u) (bulk kinetic + internal) */
+    DMB_D_V_DM = 10,                /* [3] mass-weighted mean DM velocity, km/s */
+    DMB_D_V_GAS = 13,               /* [3] mass-weighted mean gas velocity */
+    DMB_D_S2_DM = 16,               /* DM 1-D velocity variance about the mean (T_DM = m_chi s2), (km/s)^2 */
+    DMB_D_S2_GAS = 17,              /* gas 1-D variance: 2<u>/3 + <|V - <V>|^2>/3 (T_gas = mu s2) */
+    DMB_D_JB_DM = 18,               /* largest Jarque-Bera statistic (S^2 + (K-3)^2/4)/6 of the three DM
+                                       velocity components, without the sample-size factor (Appendix F) */
+    DMB_D_SCATTERS = 19,            /* DM that scattered in the step */
+    DMB_D_CRIT_VIOL = 20,           /* pairs above the criterion of eq. prob_criterion in the step */
+    DMB_D_P_MAX = 21,               /* largest P_ij of the step */
+    DMB_D_PAIRS = 22,               /* pairs visited by the DM pass in the step */
+    DMB_NDIAG = 23
+};
+typedef struct {
+    int32_t nsteps;                 /* >= 0 */
+    int32_t dt_control;             /* nonzero: limit dt by the scattering-probability criterion */
+    double dt_max;                  /* nominal (and largest) step, kpc/(km/s) */
+    double safety;                  /* fraction of the criterion aimed at, in (0, 1] */
+} dmb_run_cfg;
+/* Errors: those of dmb_build_cells / dmb_interact_step; DMB_EINVAL for a null
+ * cfg or diag, nsteps < 0, dt_max <= 0, safety outside (0, 1], per-particle dt
+ * arrays, or network rates with timing on. */
+dmb_status dmb_run(dmb_ctx *ctx, const dmb_particles *gas, const dmb_particles *dm, const dmb_params *params,
+                   const dmb_run_cfg *cfg, double *diag);
+
 /* For callers that cannot allocate device memory (code under stream capture,
  * tight serving loops, harnesses that forbid allocation): dmb_build_cells
  * followed by dmb_interact_step in one call, with every scratch buffer of

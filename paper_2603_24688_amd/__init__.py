@@ -28,7 +28,7 @@ EXPORTS = ["dmb_create", "dmb_destroy", "dmb_set_stream", "dmb_build_cells", "dm
            "dmb_build_stats", "dmb_last_error", "dmb_mlp_labels", "dmb_mlp_init", "dmb_mlp_set_params",
            "dmb_mlp_get_params", "dmb_mlp_grad", "dmb_mlp_train", "dmb_mlp_eval", "dmb_batch_build",
            "dmb_batch_step", "dmb_batch_tune", "dmb_set_search_groups", "dmb_pair_list",
-           "dmb_sort_pairs", "dmb_step_static"]
+           "dmb_sort_pairs", "dmb_step_static", "dmb_run"]
 BUILD_STATS = ["active_gas", "active_dm", "gas_tiles", "dm_tiles", "gas_owner_tiles", "dm_owner_tiles",
                "cand_pairs_gas", "cand_pairs_dm", "items_gas", "items_dm"]
 PHASES = ["build", "gather", "pass_gas", "combine_gas", "pass_dm", "combine_dm", "resolve"]
@@ -53,6 +53,16 @@ class Params(C.Structure):
 class Out(C.Structure):
     _fields_ = [("dv_dm", C.c_void_p), ("dp_gas", C.c_void_p), ("de_gas", C.c_void_p), ("partner", C.c_void_p),
                 ("p_sum", C.c_void_p), ("p_max", C.c_void_p), ("counters", C.c_void_p)]
+
+
+class RunCfg(C.Structure):
+    _fields_ = [("nsteps", C.c_int32), ("dt_control", C.c_int32), ("dt_max", C.c_double), ("safety", C.c_double)]
+
+
+DIAG_NAMES = ["time", "dt", "p_dm_x", "p_dm_y", "p_dm_z", "p_gas_x", "p_gas_y", "p_gas_z", "e_dm", "e_gas",
+              "v_dm_x", "v_dm_y", "v_dm_z", "v_gas_x", "v_gas_y", "v_gas_z", "s2_dm", "s2_gas", "jb_dm", "scatters",
+              "crit_viol", "p_max", "pairs"]
+N_DIAG = len(DIAG_NAMES)
 
 
 class MlpTrainCfg(C.Structure):
@@ -89,6 +99,8 @@ def load_library(path: str = LIB_PATH):
     L.dmb_pair_list.restype = C.c_int
     L.dmb_pair_list.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params), C.POINTER(Out),
                                 i64, vp, vp, vp]
+    L.dmb_run.restype = C.c_int
+    L.dmb_run.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params), C.POINTER(RunCfg), vp]
     L.dmb_step_static.restype = C.c_int
     L.dmb_step_static.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params), C.POINTER(Out)]
     L.dmb_sort_pairs.restype = C.c_int; L.dmb_sort_pairs.argtypes = [vp, i64, vp, vp, i32, i32, vp, vp]
@@ -221,6 +233,18 @@ class Context:
         self._check(self.lib.dmb_sort_pairs(self.h, keys.numel(), _ptr(keys), _ptr(vals), int(lo_bit), int(passes),
                                             _ptr(ko), _ptr(vo)), "dmb_sort_pairs")
         return ko, vo
+
+    def run(self, gas: dict, dm: dict, params: dict, nsteps: int, dt_max: float, dt_control: bool = False,
+            safety: float = 0.5, precision: int = DMB_FP64):
+        """nsteps steps of the time loop on device (pos, vel, u of the tensors updated in place);
+        returns the diagnostics as a numpy array [nsteps + 1, N_DIAG] (columns DIAG_NAMES)."""
+        import numpy as np
+        G, D, P = _particles(gas), _particles(dm), _params(params, precision)
+        cfg = RunCfg(int(nsteps), int(bool(dt_control)), float(dt_max), float(safety))
+        diag = np.zeros((int(nsteps) + 1, N_DIAG), dtype=np.float64)
+        self._check(self.lib.dmb_run(self.h, C.byref(G), C.byref(D), C.byref(P), C.byref(cfg), diag.ctypes.data),
+                    "dmb_run")
+        return diag
 
     def step_static(self, gas: dict, dm: dict, params: dict, out: dict, precision: int = DMB_FP32):
         """build_cells + interact_step in one call that allocates no device memory (static scratch)."""

@@ -104,6 +104,8 @@ struct dmb_ctx {
     int64_t pair_cap = 0;
     // static scratch (dmb_step_static): this device's copy of the file-scope array, and the
     // bump-carving state while a static call runs (arena != nullptr)
+    DevBuf run_buf;                        // dmb_run: step outputs, diagnostics, dt
+    double* run_dt_host = nullptr;         // pinned: the next step's dt
     char* static_ptr = nullptr;
     char* arena = nullptr;
     size_t arena_cap = 0, arena_off = 0;
@@ -1218,11 +1220,11 @@ dmb_status dmb_create(dmb_ctx** out, int device, void* hip_stream)
         return DMB_EHIP;
     }
     c->static_ptr = static_cast<char*>(sp);
-    he = hipHostMalloc(reinterpret_cast<void**>(&c->rb_host), kReadbackMax * sizeof(uint64_t));
+    he = hipHostMalloc(reinterpret_cast<void**>(&c->run_dt_host), sizeof(double));
+    if (he == hipSuccess) he = hipHostMalloc(reinterpret_cast<void**>(&c->rb_host), kReadbackMax * sizeof(uint64_t));
     if (he != hipSuccess) {
-        c->rb_host = nullptr;
         snprintf(g_create_err, sizeof(g_create_err), "pinned read-back buffer: %s", hipGetErrorString(he));
-        delete c;
+        dmb_destroy(c);
         return DMB_ENOMEM;
     }
     size_t tb = size_t(kTabCells) * 4 * sizeof(float4);
@@ -1277,6 +1279,8 @@ dmb_status dmb_destroy(dmb_ctx* c)
                       &c->bitem, &c->heap.rb_dev};
     for (DevBuf* b : rest) fr(*b);
     if (c->rb_host) hipHostFree(c->rb_host);
+    if (c->run_dt_host) hipHostFree(c->run_dt_host);
+    fr(c->run_buf);
     delete c;
     return DMB_OK;
 }
@@ -1573,6 +1577,87 @@ dmb_status dmb_pair_list(dmb_ctx* c, const dmb_particles* gas, const dmb_particl
                            owner_dm ? X.dm.perm : X.gas.perm, owner_dm ? X.gas.perm : X.dm.perm, owner_dm);
     }
     HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DMB_OK;
+}
+
+dmb_status dmb_run(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par0,
+                   const dmb_run_cfg* cfg, double* diag)
+{
+    if (!c) return DMB_EINVAL;
+    if (!par0 || !cfg || !diag) return fail(c, DMB_EINVAL, "run: null params, cfg or diag");
+    if (cfg->nsteps < 0 || !(cfg->dt_max > 0.0) || !(cfg->safety > 0.0 && cfg->safety <= 1.0))
+        return fail(c, DMB_EINVAL, "run: nsteps %d, dt_max %g, safety %g", cfg->nsteps, cfg->dt_max, cfg->safety);
+    dmb_status s;
+    if ((s = check_particles(c, gas, "gas", true)) != DMB_OK) return s;
+    if ((s = check_particles(c, dm, "dm", false)) != DMB_OK) return s;
+    if (gas->dt || dm->dt) return fail(c, DMB_EINVAL, "run: per-particle dt arrays are not supported");
+    if ((gas->n > 0 && (!gas->vel || !gas->mass || !gas->u)) || (dm->n > 0 && (!dm->vel || !dm->mass)))
+        return fail(c, DMB_EINVAL, "run: null vel, mass or u");
+    HIPCHK(c, hipSetDevice(c->device));
+    // per-run buffers: step outputs, diagnostics partials and rows, dt and time
+    const int64_t ng = gas->n, nd = dm->n;
+    ENSURE(c, c->run_buf, size_t(std::max<int64_t>(ng, 1)) * 32 + size_t(std::max<int64_t>(nd, 1)) * 56 +
+                              size_t(kRunDiagBlocks) * kRN * 8 + size_t(cfg->nsteps + 1) * DMB_NDIAG * 8 + 64 +
+                              DMB_NCOUNTERS * 8 + 1024);
+    char* b = c->run_buf.as<char>();
+    auto take = [&b](size_t bytes) { char* p = b; b += (bytes + 255) & ~size_t(255); return p; };
+    dmb_out out;
+    out.dp_gas = reinterpret_cast<double*>(take(size_t(std::max<int64_t>(ng, 1)) * 24));
+    out.de_gas = reinterpret_cast<double*>(take(size_t(std::max<int64_t>(ng, 1)) * 8));
+    out.dv_dm = reinterpret_cast<double*>(take(size_t(std::max<int64_t>(nd, 1)) * 24));
+    out.partner = reinterpret_cast<int32_t*>(take(size_t(std::max<int64_t>(nd, 1)) * 4));
+    out.p_sum = nullptr;
+    out.p_max = reinterpret_cast<double*>(take(size_t(std::max<int64_t>(nd, 1)) * 8));
+    out.counters = reinterpret_cast<uint64_t*>(take(DMB_NCOUNTERS * 8));
+    double* part = reinterpret_cast<double*>(take(size_t(kRunDiagBlocks) * kRN * 8));
+    double* rows = reinterpret_cast<double*>(take(size_t(cfg->nsteps + 1) * DMB_NDIAG * 8));
+    double* dtd = reinterpret_cast<double*>(take(16));
+    double* timed = dtd + 1;
+    double init[2] = {cfg->dt_max, 0.0};
+    HIPCHK(c, hipMemcpyAsync(dtd, init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+    RunArgs ra;
+    ra.n_gas = ng; ra.n_dm = nd;
+    ra.gpos = const_cast<double*>(gas->pos); ra.gvel = const_cast<double*>(gas->vel);
+    ra.gu = const_cast<double*>(gas->u); ra.gmass = gas->mass; ra.gmu = gas->mu;
+    ra.dpos = const_cast<double*>(dm->pos); ra.dvel = const_cast<double*>(dm->vel); ra.dmass = dm->mass;
+    ra.dp_gas = out.dp_gas; ra.de_gas = out.de_gas; ra.dv_dm = out.dv_dm; ra.p_max = out.p_max;
+    ra.counters = out.counters;
+    for (int k = 0; k < 3; ++k) ra.L[k] = par0->box[k];
+    ra.m_chi = par0->m_chi_g;
+    ra.dt = dtd;
+    const unsigned nbd = unsigned(std::min<int64_t>(kRunDiagBlocks, std::max<int64_t>(1, (std::max(ng, nd) + 255) / 256)));
+    RunDiagArgs da;
+    da.n_gas = ng; da.n_dm = nd; da.part = part; da.nblocks = int(nbd); da.counters = out.counters;
+    da.dt = dtd; da.time = timed; da.control = cfg->dt_control; da.dt_max = cfg->dt_max; da.safety = cfg->safety;
+    auto diag_row = [&](int k) {
+        hipLaunchKernelGGL(k_run_diag_partial, dim3(nbd), dim3(256), 0, c->stream, ra, part);
+        da.row = rows + int64_t(k) * DMB_NDIAG;
+        da.first = k == 0;
+        hipLaunchKernelGGL(k_run_diag_final, dim3(1), dim3(64), 0, c->stream, da);
+    };
+    diag_row(0);
+    dmb_params par = *par0;
+    double dt = cfg->dt_max;
+    for (int k = 0; k < cfg->nsteps; ++k) {
+        par.step = par0->step + uint32_t(k);
+        c->X = &c->cells;
+        if ((s = build_cells_impl(c, gas, dm, &par)) != DMB_OK) return s;
+        // the build waited on the stream, so the previous step's dt copy has landed
+        if (cfg->dt_control && k > 0) dt = *c->run_dt_host;
+        par.dt = dt;
+        if ((s = check_step(c, gas, dm, &par, &out)) != DMB_OK) return s;
+        if (par.precision == DMB_FP64) s = dispatch_rates<double>(c, gas, dm, &par, &out, out.counters);
+        else if (par.precision == DMB_FP32) s = dispatch_rates<float>(c, gas, dm, &par, &out, out.counters);
+        else s = fail(c, DMB_EINVAL, "precision %d not supported", par.precision);
+        if (s != DMB_OK) return s;
+        hipLaunchKernelGGL(k_run_apply, dim3(blocks_for(ng + nd, 256)), dim3(256), 0, c->stream, ra);
+        diag_row(k + 1);
+        // the next dt reaches the host with the next build's first read-back (same stream)
+        HIPCHK(c, hipMemcpyAsync(c->run_dt_host, dtd, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(diag, rows, size_t(cfg->nsteps + 1) * DMB_NDIAG * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return DMB_OK;
 }

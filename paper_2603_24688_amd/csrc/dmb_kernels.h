@@ -6,6 +6,7 @@
 #include <stdint.h>
 #include <type_traits>
 
+#include "../../include/dmb.h"
 #include "dmb_device.h"
 #include "dmb_mlp.h"
 
@@ -2222,6 +2223,193 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
         __syncthreads();
     }
     if (tid == 0 && nnearD) atomicAdd((unsigned long long*)&a.counters[4], (unsigned long long)nnearD);
+}
+
+// ---------------------------------------------------------------------------
+// Time loop (dmb_run): after each interaction step the DM take their kicks
+// and the gas its momentum and internal-energy transfers (all computed from
+// start-of-step states), then both species drift with their new velocities
+// (kick, then drift), wrapped into [0, L) in a periodic box.
+struct RunArgs {
+    int64_t n_gas, n_dm;
+    double* gpos; double* gvel; double* gu; const double* gmass; const double* gmu;
+    double* dpos; double* dvel; const double* dmass;
+    const double* dp_gas; const double* de_gas; const double* dv_dm; const double* p_max;
+    const uint64_t* counters;
+    double L[3];
+    double m_chi;
+    const double* dt;             // device: this step's dt
+};
+
+__global__ __launch_bounds__(256) void k_run_apply(RunArgs a)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const double dt = *a.dt;
+    if (k < a.n_gas) {
+        const double im = 1.0 / a.gmass[k];
+        for (int c = 0; c < 3; ++c) {
+            const double v = a.gvel[3 * k + c] + a.dp_gas[3 * k + c] * im;
+            a.gvel[3 * k + c] = v;
+            double x = a.gpos[3 * k + c] + v * dt;
+            if (a.L[c] > 0.0) x -= a.L[c] * floor(x / a.L[c]);
+            a.gpos[3 * k + c] = x;
+        }
+        a.gu[k] += a.de_gas[k] * im;
+    } else if (k < a.n_gas + a.n_dm) {
+        const int64_t i = k - a.n_gas;
+        for (int c = 0; c < 3; ++c) {
+            const double v = a.dvel[3 * i + c] + a.dv_dm[3 * i + c];
+            a.dvel[3 * i + c] = v;
+            double x = a.dpos[3 * i + c] + v * dt;
+            if (a.L[c] > 0.0) x -= a.L[c] * floor(x / a.L[c]);
+            a.dpos[3 * i + c] = x;
+        }
+    }
+}
+
+// Per-step diagnostics: fixed-order reductions (per-block partial sums, then
+// one block adds the blocks in order), binary64.  Partial layout per block:
+constexpr int kRunDiagBlocks = 256;
+enum : int {
+    kRdM = 0, kRdP = 1, kRdE = 4, kRdV1 = 5, kRdV2 = 8, kRdV3 = 11, kRdV4 = 14,    // DM (v moments unweighted)
+    kRgM = 17, kRgP = 18, kRgE = 21, kRgU = 22, kRgV1 = 23, kRgV2 = 26,              // gas
+    kRPmax = 29, kRCrit = 30, kRN = 31
+};
+
+__global__ __launch_bounds__(256) void k_run_diag_partial(RunArgs a, double* __restrict__ part)
+{
+    __shared__ double red[kRN][4];
+    double acc[kRN];
+    for (int q = 0; q < kRN; ++q) acc[q] = 0.0;
+    acc[kRCrit] = 0.1;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n_dm; i += stride) {
+        const double m = a.dmass[i];
+        acc[kRdM] += m;
+        for (int c = 0; c < 3; ++c) {
+            const double v = a.dvel[3 * i + c], v2 = v * v;
+            acc[kRdP + c] += m * v;
+            acc[kRdE] += 0.5 * m * v2;
+            acc[kRdV1 + c] += v;
+            acc[kRdV2 + c] += v2;
+            acc[kRdV3 + c] += v2 * v;
+            acc[kRdV4 + c] += v2 * v2;
+        }
+        if (a.p_max) acc[kRPmax] = fmax(acc[kRPmax], a.p_max[i]);
+    }
+    for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < a.n_gas; j += stride) {
+        const double m = a.gmass[j], u = a.gu[j];
+        acc[kRgM] += m;
+        acc[kRgU] += u;
+        acc[kRgE] += m * u;
+        for (int c = 0; c < 3; ++c) {
+            const double v = a.gvel[3 * j + c];
+            acc[kRgP + c] += m * v;
+            acc[kRgE] += 0.5 * m * v * v;
+            acc[kRgV1 + c] += v;
+            acc[kRgV2 + c] += v * v;
+        }
+        // the criterion of eq. prob_criterion for this gas particle's pairs
+        const double mu = a.gmu ? a.gmu[j] : kMpG, q = (a.m_chi + mu) / mu;
+        acc[kRCrit] = fmin(acc[kRCrit], fmin(0.1, 1e-4 * q * q));
+    }
+    // block reduction in a fixed order: lanes by a butterfly, then waves in order
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int q = 0; q < kRN; ++q) {
+        double v = acc[q];
+        for (int d = 32; d >= 1; d >>= 1) {
+            const double o = __shfl_xor(v, d);
+            v = q == kRPmax ? fmax(v, o) : (q == kRCrit ? fmin(v, o) : v + o);
+        }
+        if (lane == 0) red[q][w] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kRN) {
+        const int q = threadIdx.x;
+        double v = red[q][0];
+        for (int k = 1; k < 4; ++k) v = q == kRPmax ? fmax(v, red[q][k]) : (q == kRCrit ? fmin(v, red[q][k]) : v + red[q][k]);
+        part[int64_t(blockIdx.x) * kRN + q] = v;
+    }
+}
+
+// Diagnostics row (layout of the DMB_D_* indices) and the next dt.
+struct RunDiagArgs {
+    int64_t n_gas, n_dm;
+    const double* part; int nblocks;
+    const uint64_t* counters;
+    double* row;                  // device row of the diagnostics
+    double* dt;                   // device: this step's dt (in), next step's dt (out when control != 0)
+    double* time;                 // device: elapsed time (advanced by this step's dt)
+    int control; double dt_max, safety;
+    int first;                    // row of the initial state: no counters, no step
+};
+
+__global__ __launch_bounds__(64) void k_run_diag_final(RunDiagArgs a)
+{
+    __shared__ double tot[kRN];
+    if (threadIdx.x < kRN) {
+        const int q = threadIdx.x;
+        double v = q == kRCrit ? 0.1 : 0.0;
+        for (int b = 0; b < a.nblocks; ++b) {
+            const double x = a.part[int64_t(b) * kRN + q];
+            v = q == kRPmax ? fmax(v, x) : (q == kRCrit ? fmin(v, x) : v + x);
+        }
+        tot[q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double* r = a.row;
+    const double nd = double(a.n_dm), ng = double(a.n_gas);
+    const double dt = *a.dt;
+    if (!a.first) *a.time += dt;
+    r[DMB_D_TIME] = *a.time;
+    r[DMB_D_DT] = a.first ? 0.0 : dt;
+    for (int c = 0; c < 3; ++c) {
+        r[DMB_D_P_DM + c] = tot[kRdP + c];
+        r[DMB_D_P_GAS + c] = tot[kRgP + c];
+        r[DMB_D_V_DM + c] = tot[kRdM] > 0.0 ? tot[kRdP + c] / tot[kRdM] : 0.0;
+        r[DMB_D_V_GAS + c] = tot[kRgM] > 0.0 ? tot[kRgP + c] / tot[kRgM] : 0.0;
+    }
+    r[DMB_D_E_DM] = tot[kRdE];
+    r[DMB_D_E_GAS] = tot[kRgE];
+    // 1-D dispersions about the (unweighted) mean; gas: thermal 2u/3 plus the bulk spread / 3
+    double s2d = 0.0, jb = 0.0, s2g = 0.0;
+    if (a.n_dm > 0) {
+        for (int c = 0; c < 3; ++c) {
+            const double m1 = tot[kRdV1 + c] / nd, m2 = tot[kRdV2 + c] / nd, m3 = tot[kRdV3 + c] / nd,
+                         m4 = tot[kRdV4 + c] / nd;
+            const double c2 = m2 - m1 * m1;
+            const double c3 = m3 - 3.0 * m1 * m2 + 2.0 * m1 * m1 * m1;
+            const double c4 = m4 - 4.0 * m1 * m3 + 6.0 * m1 * m1 * m2 - 3.0 * m1 * m1 * m1 * m1;
+            s2d += c2 / 3.0;
+            if (c2 > 0.0) {
+                const double S = c3 / (c2 * sqrt(c2)), K = c4 / (c2 * c2);
+                jb = fmax(jb, (S * S + 0.25 * (K - 3.0) * (K - 3.0)) / 6.0);   // no sample-size factor (App. F)
+            }
+        }
+    }
+    if (a.n_gas > 0) {
+        double spread = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double m1 = tot[kRgV1 + c] / ng;
+            spread += tot[kRgV2 + c] / ng - m1 * m1;
+        }
+        s2g = (2.0 / 3.0) * (tot[kRgU] / ng) + spread / 3.0;
+    }
+    r[DMB_D_S2_DM] = s2d;
+    r[DMB_D_S2_GAS] = s2g;
+    r[DMB_D_JB_DM] = jb;
+    r[DMB_D_SCATTERS] = a.first ? 0.0 : double(a.counters[DMB_C_SCATTERS]);
+    r[DMB_D_CRIT_VIOL] = a.first ? 0.0 : double(a.counters[DMB_C_CRIT_VIOL]);
+    r[DMB_D_P_MAX] = a.first ? 0.0 : tot[kRPmax];
+    r[DMB_D_PAIRS] = a.first ? 0.0 : double(a.counters[DMB_C_PAIRS_DM]);
+    // eq. prob_criterion: the next step keeps every P_ij below safety x the criterion
+    double next = dt;
+    if (a.control && !a.first) {
+        next = a.dt_max;
+        if (tot[kRPmax] > 0.0) next = fmin(next, dt * a.safety * tot[kRCrit] / tot[kRPmax]);
+    }
+    *a.dt = next;
 }
 
 // ---------------------------------------------------------------------------
