@@ -231,6 +231,86 @@ def batch_sweep(dev, steps: int, log_fn) -> dict:
         ctx.close()
 
 
+def milky_way_loop(dev, steps: int, warmup: int, log_fn, scale: float = 1.0) -> dict:
+    """Milky-Way-scale disk + halo (8M gas + 32M DM, h over 3 decades) advanced
+    `steps` steps of 0.1 Myr by the library's time loop with hierarchical
+    timesteps: each step draws an independent 10 % of each species as active
+    (Philox tag 3); binary32 pair math, binary64 totals.  Pairs counted are
+    those touching an active particle (gas pass + DM pass)."""
+    import torch
+    import paper_2603_24688_amd as dmb
+    import workloads
+    t0 = time.time()
+    cfg = workloads.milky_way(n_gas=int(8_000_000 * scale), n_dm=int(32_000_000 * scale))
+    for sp in ("gas", "dm"):
+        cfg[sp].pop("active", None)
+    ng, nd = len(cfg["gas"]["mass"]), len(cfg["dm"]["mass"])
+    log_fn(f"bench: milky way generated in {time.time() - t0:.1f} s: {ng} gas, {nd} DM")
+    par = dict(cfg["params"])
+    ctx = dmb.Context(0)
+    try:
+        G, D = dmb.to_device(cfg["gas"], dev), dmb.to_device(cfg["dm"], dev)
+        del cfg
+        if warmup > 0:
+            ctx.run(G, D, par, warmup, dt_max=par["dt"], precision=dmb.DMB_FP32, active_frac=0.1)
+        par["step"] = warmup
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        diag = ctx.run(G, D, par, steps, dt_max=par["dt"], precision=dmb.DMB_FP32, active_frac=0.1)
+        t2 = time.perf_counter()
+    finally:
+        ctx.close()
+    col = dmb.DIAG_NAMES.index
+    pairs = float(diag[1:, col("pairs")].sum() + diag[1:, col("pairs_gas")].sum())
+    ms = (t2 - t1) * 1e3 / max(steps, 1)
+    p0 = diag[0, col("p_dm_x")] + diag[0, col("p_gas_x")]
+    p1 = diag[-1, col("p_dm_x")] + diag[-1, col("p_gas_x")]
+    log_fn(f"bench: milky way loop: {steps} steps in {(t2 - t1):.2f} s, {pairs / max(steps, 1):.3e} active-touching "
+           f"pairs per step, {int(diag[1:, col('scatters')].sum())} scatters")
+    return {"workload": "Milky-Way-scale disk + NFW halo, 8M gas + 32M DM, h log-uniform over 3 decades (top-anchored "
+                        "at the 64-neighbour maximum), 10% of each species active per step, dt 0.1 Myr",
+            "n_gas": ng, "n_dm": nd, "steps": steps, "ms_per_step": ms, "s_for_steps": t2 - t1,
+            "active_pair_visits_per_step": pairs / max(steps, 1), "active_pair_visits_per_s": pairs / max(t2 - t1, 1e-12),
+            "pair_count": "gas-pass visits (active gas) + DM-pass visits (active DM); a pair with both ends active is evaluated by both passes and counts twice",
+            "scatters": int(diag[1:, col("scatters")].sum()), "pair_math": "binary32", "totals": "binary64",
+            "total_px_change_rel": float(abs(p1 - p0) / max(abs(diag[0, col("p_dm_x")]), 1e-300))}
+
+
+def box_time_loop(dev, steps: int, warmup: int, log_fn) -> dict:
+    """The periodic test box (4096 gas + 4096 DM, binary64) advanced `steps`
+    steps by the library's time loop (rebuild, interaction step, kicks and
+    transfers, drift, per-step diagnostics) in one dmb_run call, after
+    `warmup` untimed steps on a copy of the same state."""
+    import torch
+    import paper_2603_24688_amd as dmb
+    import workloads
+    cfg = workloads.box(seed=(1, 1))
+    par = dict(cfg["params"])
+    ctx = dmb.Context(0)
+    try:
+        if warmup > 0:
+            Gw, Dw = dmb.to_device(cfg["gas"], dev), dmb.to_device(cfg["dm"], dev)
+            ctx.run(Gw, Dw, par, warmup, dt_max=par["dt"], precision=dmb.DMB_FP64)
+            del Gw, Dw
+        G, D = dmb.to_device(cfg["gas"], dev), dmb.to_device(cfg["dm"], dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        diag = ctx.run(G, D, par, steps, dt_max=par["dt"], dt_control=False, precision=dmb.DMB_FP64)
+        t1 = time.perf_counter()
+    finally:
+        ctx.close()
+    col = dmb.DIAG_NAMES.index
+    pairs = float(diag[1:, col("pairs")].sum())
+    ms = (t1 - t0) * 1e3 / max(steps, 1)
+    log_fn(f"bench: box time loop: {steps} steps in {(t1 - t0) * 1e3:.2f} ms, {pairs / max(steps, 1):.0f} pairs per "
+           f"step, max JB {diag[:, col('jb_dm')].max():.4f}")
+    return {"workload": "periodic test box L = 1 kpc, 4096 gas + 4096 DM, Maxwellian gas T = 1e4 K, DM T = 1e5 K "
+                        "drifting at 50 km/s, m_chi = 2 m_p, sigma0 = 1e-24 cm^2, 32 neighbours, dt = 0.05 Myr",
+            "steps": steps, "ms_for_steps": (t1 - t0) * 1e3, "ms_per_step": ms, "pairs_per_step": pairs / max(steps, 1),
+            "pairs_per_s": pairs / max(t1 - t0, 1e-12), "precision": "binary64",
+            "scatters": int(diag[1:, col("scatters")].sum()), "max_jb": float(diag[:, col("jb_dm")].max())}
+
+
 def pmc_from_profile(kernel: str):
     """Counters of one launch of `kernel` from the rocprofv3 PMC runs committed
     under profiles/ (HBM bytes from FETCH_SIZE / WRITE_SIZE scaled by a plain
@@ -263,6 +343,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-box batched sweep")
+    ap.add_argument("--no-box", action="store_true", help="skip the 100-step time loop of the periodic test box")
+    ap.add_argument("--no-milky-way", action="store_true",
+                    help="skip the 200-step hierarchical-timestep run at Milky-Way scale")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the network-vs-quadrature comparison (sigma ~ v^n on the galaxy workload)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -277,6 +360,22 @@ def main():
     import paper_2603_24688_amd as dmb
 
     dev = torch.device("cuda:0")
+    if args.workload == "box":
+        b = box_time_loop(dev, args.steps, args.warmup, log)
+        line = {"metric": "DM-gas pair interactions/sec per step", "value": b["pairs_per_s"],
+                "unit": "pair interactions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                "ms_per_step": b["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f64", "data": "synthetic", "config": b}
+        print(json.dumps(line), flush=True)
+        return
+    if args.workload == "milky_way":
+        b = milky_way_loop(dev, args.steps, args.warmup, log, args.scale)
+        line = {"metric": "DM-gas pair interactions/sec per step (pairs touching an active particle)",
+                "value": b["active_pair_visits_per_s"], "unit": "pair interactions/s", "n_gpus": 1, "steps": args.steps,
+                "warmup": args.warmup, "ms_per_step": b["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": b}
+        print(json.dumps(line), flush=True)
+        return
     if args.workload == "batch":
         b = batch_sweep(dev, args.steps, log)
         line = {"metric": "DM-gas pair interactions/sec per step", "value": b["pairs_per_s"],
@@ -379,6 +478,10 @@ def main():
         line["surrogate"] = surrogate_compare(ctx, cfg, dev, 3, log)
     if default_run and not args.no_batch:
         line["batch"] = batch_sweep(dev, 10, log)
+    if default_run and not args.no_box:
+        line["box_time_loop"] = box_time_loop(dev, 100, 2, log)
+    if default_run and not args.no_milky_way:
+        line["milky_way_loop"] = milky_way_loop(dev, 200, 2, log)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, pairs)

@@ -173,18 +173,24 @@ enum {
     DMB_D_SCATTERS = 19,            /* DM that scattered in the step */
     DMB_D_CRIT_VIOL = 20,           /* pairs above the criterion of eq. prob_criterion in the step */
     DMB_D_P_MAX = 21,               /* largest P_ij of the step */
-    DMB_D_PAIRS = 22,               /* pairs visited by the DM pass in the step */
-    DMB_NDIAG = 23
+    DMB_D_PAIRS = 22,               /* pairs visited by the DM pass in the step (active DM) */
+    DMB_D_PAIRS_GAS = 23,           /* pairs visited by the gas pass in the step (active gas) */
+    DMB_NDIAG = 24
 };
 typedef struct {
     int32_t nsteps;                 /* >= 0 */
     int32_t dt_control;             /* nonzero: limit dt by the scattering-probability criterion */
     double dt_max;                  /* nominal (and largest) step, kpc/(km/s) */
     double safety;                  /* fraction of the criterion aimed at, in (0, 1] */
+    double active_frac;             /* 0: the particles' own active arrays every step; in (0, 1]: each step k
+                                       draws the active set of each species afresh (hierarchical timesteps):
+                                       particle i of species s (0 gas, 1 DM) is active iff the first word r0
+                                       of Philox4x32-10 (key = seed, counter = (i, s, step + k, 3 | box << 8))
+                                       gives ((r0 >> 8) + 1/2) 2^-24 < active_frac */
 } dmb_run_cfg;
 /* Errors: those of dmb_build_cells / dmb_interact_step; DMB_EINVAL for a null
- * cfg or diag, nsteps < 0, dt_max <= 0, safety outside (0, 1], per-particle dt
- * arrays, or network rates with timing on. */
+ * cfg or diag, nsteps < 0, dt_max <= 0, safety outside (0, 1], active_frac
+ * outside [0, 1], or per-particle dt arrays. */
 dmb_status dmb_run(dmb_ctx *ctx, const dmb_particles *gas, const dmb_particles *dm, const dmb_params *params,
                    const dmb_run_cfg *cfg, double *diag);
 

@@ -87,6 +87,8 @@ def lib():
         L.orc_pair_stats.restype = None
         L.orc_pair_stats.argtypes = [C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params), p, C.c_int64,
                                      i, i, p, p, p]
+        L.orc_active_flags.restype = None
+        L.orc_active_flags.argtypes = [C.c_int64, u32, u32, u64, u32, d, p]
         L.orc_step_sel_grid.restype = i
         L.orc_step_sel_grid.argtypes = [C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params),
                                         C.POINTER(Out), p, C.c_int64, p, C.c_int64]
@@ -261,3 +263,12 @@ def pair_stats(gas: dict, dm: dict, params: dict, sel, owner_is_dm: bool, grid: 
     lib().orc_pair_stats(C.byref(G), C.byref(D), C.byref(P), s.ctypes.data, s.size, int(bool(owner_is_dm)),
                          int(bool(grid)), cnt.ctypes.data, s1.ctypes.data, s2.ctypes.data)
     return cnt, s1, s2
+
+
+def active_flags(n: int, species: int, step: int, seed: int, box: int, frac: float) -> np.ndarray:
+    """Active flags (uint8) of one species (0 gas, 1 DM) at one step of a
+    hierarchical-timestep run: tag-3 uniform below frac."""
+    out = np.zeros(int(n), np.uint8)
+    lib().orc_active_flags(int(n), int(species), int(step) & 0xFFFFFFFF, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                           int(box), float(frac), out.ctypes.data)
+    return out

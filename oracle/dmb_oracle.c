@@ -832,6 +832,20 @@ int64_t orc_pairs(const orc_particles *gas, const orc_particles *dm, const orc_p
     return cnt;
 }
 
+/* Active sets of one step of a hierarchical-timestep run (reading of the
+ * Milky-Way-scale setup: an independent fraction of each species active per
+ * step): particle i of species s (0 gas, 1 DM) is active iff the first
+ * uniform of the block (i, s, step, tag 3) lies below frac.               */
+void orc_active_flags(int64_t n, uint32_t species, uint32_t step, uint64_t seed, uint32_t box, double frac,
+                      uint8_t *out)
+{
+    for (int64_t i = 0; i < n; i++) {
+        double u[4];
+        orc_block(seed, (uint32_t)i, species, step, 3u, box, u);
+        out[i] = u[0] < frac ? 1 : 0;
+    }
+}
+
 /* Per-owner pair statistics for selected owners (the same pair set as
  * orc_pairs, brute force over the other species): for owner sel[t] (a gas
  * index when owner_is_dm == 0, else a DM index) the number of partners, the

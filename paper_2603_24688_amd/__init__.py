@@ -56,12 +56,13 @@ class Out(C.Structure):
 
 
 class RunCfg(C.Structure):
-    _fields_ = [("nsteps", C.c_int32), ("dt_control", C.c_int32), ("dt_max", C.c_double), ("safety", C.c_double)]
+    _fields_ = [("nsteps", C.c_int32), ("dt_control", C.c_int32), ("dt_max", C.c_double), ("safety", C.c_double),
+                ("active_frac", C.c_double)]
 
 
 DIAG_NAMES = ["time", "dt", "p_dm_x", "p_dm_y", "p_dm_z", "p_gas_x", "p_gas_y", "p_gas_z", "e_dm", "e_gas",
               "v_dm_x", "v_dm_y", "v_dm_z", "v_gas_x", "v_gas_y", "v_gas_z", "s2_dm", "s2_gas", "jb_dm", "scatters",
-              "crit_viol", "p_max", "pairs"]
+              "crit_viol", "p_max", "pairs", "pairs_gas"]
 N_DIAG = len(DIAG_NAMES)
 
 
@@ -235,12 +236,12 @@ class Context:
         return ko, vo
 
     def run(self, gas: dict, dm: dict, params: dict, nsteps: int, dt_max: float, dt_control: bool = False,
-            safety: float = 0.5, precision: int = DMB_FP64):
+            safety: float = 0.5, precision: int = DMB_FP64, active_frac: float = 0.0):
         """nsteps steps of the time loop on device (pos, vel, u of the tensors updated in place);
         returns the diagnostics as a numpy array [nsteps + 1, N_DIAG] (columns DIAG_NAMES)."""
         import numpy as np
         G, D, P = _particles(gas), _particles(dm), _params(params, precision)
-        cfg = RunCfg(int(nsteps), int(bool(dt_control)), float(dt_max), float(safety))
+        cfg = RunCfg(int(nsteps), int(bool(dt_control)), float(dt_max), float(safety), float(active_frac))
         diag = np.zeros((int(nsteps) + 1, N_DIAG), dtype=np.float64)
         self._check(self.lib.dmb_run(self.h, C.byref(G), C.byref(D), C.byref(P), C.byref(cfg), diag.ctypes.data),
                     "dmb_run")

@@ -1586,8 +1586,10 @@ dmb_status dmb_run(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm
 {
     if (!c) return DMB_EINVAL;
     if (!par0 || !cfg || !diag) return fail(c, DMB_EINVAL, "run: null params, cfg or diag");
-    if (cfg->nsteps < 0 || !(cfg->dt_max > 0.0) || !(cfg->safety > 0.0 && cfg->safety <= 1.0))
-        return fail(c, DMB_EINVAL, "run: nsteps %d, dt_max %g, safety %g", cfg->nsteps, cfg->dt_max, cfg->safety);
+    if (cfg->nsteps < 0 || !(cfg->dt_max > 0.0) || !(cfg->safety > 0.0 && cfg->safety <= 1.0) ||
+        !(cfg->active_frac >= 0.0 && cfg->active_frac <= 1.0))
+        return fail(c, DMB_EINVAL, "run: nsteps %d, dt_max %g, safety %g, active_frac %g", cfg->nsteps, cfg->dt_max,
+                    cfg->safety, cfg->active_frac);
     dmb_status s;
     if ((s = check_particles(c, gas, "gas", true)) != DMB_OK) return s;
     if ((s = check_particles(c, dm, "dm", false)) != DMB_OK) return s;
@@ -1599,7 +1601,7 @@ dmb_status dmb_run(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm
     const int64_t ng = gas->n, nd = dm->n;
     ENSURE(c, c->run_buf, size_t(std::max<int64_t>(ng, 1)) * 32 + size_t(std::max<int64_t>(nd, 1)) * 56 +
                               size_t(kRunDiagBlocks) * kRN * 8 + size_t(cfg->nsteps + 1) * DMB_NDIAG * 8 + 64 +
-                              DMB_NCOUNTERS * 8 + 1024);
+                              DMB_NCOUNTERS * 8 + size_t(ng + nd) + 2048);
     char* b = c->run_buf.as<char>();
     auto take = [&b](size_t bytes) { char* p = b; b += (bytes + 255) & ~size_t(255); return p; };
     dmb_out out;
@@ -1614,6 +1616,14 @@ dmb_status dmb_run(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm
     double* rows = reinterpret_cast<double*>(take(size_t(cfg->nsteps + 1) * DMB_NDIAG * 8));
     double* dtd = reinterpret_cast<double*>(take(16));
     double* timed = dtd + 1;
+    uint8_t* gact = reinterpret_cast<uint8_t*>(take(size_t(std::max<int64_t>(ng, 1))));
+    uint8_t* dact = reinterpret_cast<uint8_t*>(take(size_t(std::max<int64_t>(nd, 1))));
+    // with drawn active sets the steps see the library's flag arrays
+    dmb_particles gs = *gas, ds = *dm;
+    if (cfg->active_frac > 0.0) {
+        gs.active = gact;
+        ds.active = dact;
+    }
     double init[2] = {cfg->dt_max, 0.0};
     HIPCHK(c, hipMemcpyAsync(dtd, init, sizeof(init), hipMemcpyHostToDevice, c->stream));
     RunArgs ra;
@@ -1641,14 +1651,18 @@ dmb_status dmb_run(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm
     double dt = cfg->dt_max;
     for (int k = 0; k < cfg->nsteps; ++k) {
         par.step = par0->step + uint32_t(k);
+        if (cfg->active_frac > 0.0)
+            hipLaunchKernelGGL(k_run_active, dim3(blocks_for(ng + nd, 256)), dim3(256), 0, c->stream, ng, nd, gact,
+                               dact, par.step, par.box_id, uint32_t(par.seed), uint32_t(par.seed >> 32),
+                               cfg->active_frac);
         c->X = &c->cells;
-        if ((s = build_cells_impl(c, gas, dm, &par)) != DMB_OK) return s;
+        if ((s = build_cells_impl(c, &gs, &ds, &par)) != DMB_OK) return s;
         // the build waited on the stream, so the previous step's dt copy has landed
         if (cfg->dt_control && k > 0) dt = *c->run_dt_host;
         par.dt = dt;
-        if ((s = check_step(c, gas, dm, &par, &out)) != DMB_OK) return s;
-        if (par.precision == DMB_FP64) s = dispatch_rates<double>(c, gas, dm, &par, &out, out.counters);
-        else if (par.precision == DMB_FP32) s = dispatch_rates<float>(c, gas, dm, &par, &out, out.counters);
+        if ((s = check_step(c, &gs, &ds, &par, &out)) != DMB_OK) return s;
+        if (par.precision == DMB_FP64) s = dispatch_rates<double>(c, &gs, &ds, &par, &out, out.counters);
+        else if (par.precision == DMB_FP32) s = dispatch_rates<float>(c, &gs, &ds, &par, &out, out.counters);
         else s = fail(c, DMB_EINVAL, "precision %d not supported", par.precision);
         if (s != DMB_OK) return s;
         hipLaunchKernelGGL(k_run_apply, dim3(blocks_for(ng + nd, 256)), dim3(256), 0, c->stream, ra);

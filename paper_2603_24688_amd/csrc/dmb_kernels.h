@@ -2267,6 +2267,23 @@ __global__ __launch_bounds__(256) void k_run_apply(RunArgs a)
     }
 }
 
+// Active sets of one step of a hierarchical-timestep run: particle i of
+// species s (0 gas, 1 DM) is active iff its tag-3 uniform is below frac.
+enum : uint32_t { kTagActive = 3u };
+__global__ __launch_bounds__(256) void k_run_active(int64_t n_gas, int64_t n_dm, uint8_t* __restrict__ gact,
+                                                    uint8_t* __restrict__ dact, uint32_t step, uint32_t box,
+                                                    uint32_t k0, uint32_t k1, double frac)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n_gas + n_dm) return;
+    const bool gas = k < n_gas;
+    const uint32_t i = uint32_t(gas ? k : k - n_gas);
+    const U4 r = philox_block(i, gas ? 0u : 1u, step, kTagActive, box, k0, k1);
+    const uint8_t a = u24<double>(r.x) < frac ? 1u : 0u;
+    if (gas) gact[i] = a;
+    else dact[i] = a;
+}
+
 // Per-step diagnostics: fixed-order reductions (per-block partial sums, then
 // one block adds the blocks in order), binary64.  Partial layout per block:
 constexpr int kRunDiagBlocks = 256;
@@ -2403,6 +2420,7 @@ __global__ __launch_bounds__(64) void k_run_diag_final(RunDiagArgs a)
     r[DMB_D_CRIT_VIOL] = a.first ? 0.0 : double(a.counters[DMB_C_CRIT_VIOL]);
     r[DMB_D_P_MAX] = a.first ? 0.0 : tot[kRPmax];
     r[DMB_D_PAIRS] = a.first ? 0.0 : double(a.counters[DMB_C_PAIRS_DM]);
+    r[DMB_D_PAIRS_GAS] = a.first ? 0.0 : double(a.counters[DMB_C_PAIRS_GAS]);
     // eq. prob_criterion: the next step keeps every P_ij below safety x the criterion
     double next = dt;
     if (a.control && !a.first) {

@@ -523,3 +523,20 @@ def test_grid_candidates_give_the_brute_force_step(orc, name):
         y = orc.pair_stats(cfg["gas"], cfg["dm"], cfg["params"], sel, owner_dm, grid=True)
         for u, v in zip(x, y):
             assert np.array_equal(u, v)
+
+
+def test_active_flags_fraction_and_independence(orc):
+    """Drawn active sets (hierarchical timesteps): each species' active fraction
+    is binomial about the requested value; species and steps are independent
+    (Philox counters differ in the species and step words)."""
+    n, f = 200_000, 0.1
+    a = orc.active_flags(n, 0, 5, 0x2603246880000001, 0, f)
+    b = orc.active_flags(n, 1, 5, 0x2603246880000001, 0, f)
+    c = orc.active_flags(n, 0, 6, 0x2603246880000001, 0, f)
+    sd = np.sqrt(f * (1 - f) / n)
+    for x in (a, b, c):
+        assert abs(x.mean() - f) < 5 * sd
+    # joint activity of two independent draws: f^2
+    for x, y in ((a, b), (a, c)):
+        assert abs((x & y).mean() - f * f) < 5 * np.sqrt(f * f * (1 - f * f) / n)
+    assert orc.active_flags(10, 0, 5, 1, 0, 0.0).sum() == 0 and orc.active_flags(10, 0, 5, 1, 0, 1.0).sum() == 10

@@ -196,14 +196,26 @@ def galaxy(n_gas=1_000_000, n_dm=4_000_000, n_ngb=64, seed=(2, 1), sigma0_cm2=1e
     return {"gas": gas, "dm": dm, "params": par}
 
 
-def spread_h_log(h: np.ndarray, decades: float = 3.0) -> np.ndarray:
-    """Rank-matched log-uniform kernel radii over `decades`, anchored at the
-    largest input radius: h_k = h_max 10^{-decades (1 - (k+1/2)/N)} by rank."""
+def spread_h_log(h: np.ndarray, decades: float = 3.0, h_top: float | None = None) -> np.ndarray:
+    """Rank-matched log-uniform kernel radii over `decades`, anchored at h_top
+    (default: the largest input radius): h_k = h_top 10^{-decades (1 - (k+1/2)/N)}
+    for the particle of rank k in h."""
     n = h.shape[0]
     order = np.argsort(h, kind="stable")
     out = np.empty_like(h)
-    out[order] = h.max() * 10.0 ** (-decades * (1.0 - (np.arange(n) + 0.5) / n))
+    top = h.max() if h_top is None else float(h_top)
+    out[order] = top * 10.0 ** (-decades * (1.0 - (np.arange(n) + 0.5) / n))
     return out
+
+
+def knn_max(pos: np.ndarray, h_rank: np.ndarray, k: int, n_cand: int = 50_000) -> float:
+    """Largest distance to the k-th nearest same-species neighbour, searched
+    among the n_cand particles with the largest h_rank (the sparsest ones)."""
+    from scipy.spatial import cKDTree
+    tree = cKDTree(pos, leafsize=32, balanced_tree=False, compact_nodes=False)
+    cand = np.argpartition(h_rank, -min(n_cand, len(h_rank)))[-min(n_cand, len(h_rank)):]
+    d, _ = tree.query(pos[cand], k=k + 1, workers=-1)
+    return float(d[:, -1].max())
 
 
 def sigma0_for_npow(n_pow: int, v_ref_kms: float = 200.0, sigma_ref_cm2: float = 1e-24) -> float:
@@ -275,12 +287,14 @@ def milky_way(n_gas=8_000_000, n_dm=32_000_000, seed=(3, 1), active_frac=0.1, st
               dt_myr=0.1, n_pow=0, sigma0_cm2=1e-24) -> dict:
     """Disk + halo with the galaxy profiles at Milky-Way particle counts, for
     one step of a hierarchical-timestep run: h spread log-uniformly over
-    `decades` decades per species (rank-matched to the density estimate,
-    top-anchored at its maximum) and an independent `active_frac` of each
-    species active (drawn per step)."""
+    `decades` decades per species, rank-matched to the profile-density h and
+    top-anchored at the largest 64-neighbour distance of the species (its kNN
+    maximum, found among the 50 000 sparsest particles), and an independent
+    `active_frac` of each species active (drawn per step)."""
     cfg = galaxy(n_gas=n_gas, n_dm=n_dm, n_ngb=64, seed=seed, sigma0_cm2=sigma0_cm2, n_pow=n_pow, dt_myr=dt_myr)
     for sp in ("gas", "dm"):
-        cfg[sp]["h"] = spread_h_log(cfg[sp]["h"], decades)
+        top = knn_max(cfg[sp]["pos"], cfg[sp]["h"], 64)
+        cfg[sp]["h"] = spread_h_log(cfg[sp]["h"], decades, top)
     r = rng(seed[0], seed[1], 100 + int(step))
     cfg["gas"]["active"] = (r.random(n_gas) < active_frac).astype(np.uint8)
     cfg["dm"]["active"] = (r.random(n_dm) < active_frac).astype(np.uint8)
