@@ -113,6 +113,9 @@ struct dmb_ctx {
     uint64_t* rb_host = nullptr;           // pinned
     int split = 32;                        // candidate sub-tiles per work item of the DM pass (tunable);
                                            // the gas pass, whose partial sums cost more to combine, twice that
+    int item_target_per_cu = 32;           // small problems: split candidate lists into about this many
+                                           // work items per compute unit (0: always `split`)
+    int item_share = 1;                    // boxes that share the chip in the build under way (batch)
     int subtile_delta = 1;                 // (tunable) sub-tile cut: Morton level below (median - delta)
     int group_cap = 1024;                  // candidate-search group list capacity (0: no group pass)
     int grid_pct = 100;                    // (tunable) persistent grid size, % of the resident maximum
@@ -502,6 +505,8 @@ dmb_status cand_subs(dmb_ctx* c, Species& A, Species& B, Pairs& P)
                        P.scnt.as<uint32_t>(), P.beg.as<uint64_t>(), P.swt.as<uint32_t>());
     hipLaunchKernelGGL(k_item_count, dim3(blocks_for(nt + 1, 256)), dim3(256), 0, c->stream,
                        P.scnt.as<const uint32_t>(), nt, uint32_t(&P == &c->X->gp ? 2 * c->split : c->split),
+                       P.soff.as<const uint64_t>() + np,
+                       uint32_t(int64_t(c->item_target_per_cu) * c->num_cu / std::max(1, c->item_share)),
                        P.icnt.as<uint32_t>());
     s = scan_excl(c, P.icnt.as<const uint32_t>(), P.ioff.as<uint32_t>(), nt + 1);
     if (s != DMB_OK) return s;
@@ -2092,6 +2097,8 @@ dmb_status batch_build_all(dmb_ctx* c, int32_t nbox, const dmb_particles* gas, c
 {
     CellsGuard guard{c};
     while (int(c->boxes.size()) < nbox) c->boxes.push_back(new Cells());
+    struct ShareGuard { dmb_ctx* c; ~ShareGuard() { c->item_share = 1; } } share{c};
+    c->item_share = nbox;
     for (int b = 0; b < nbox; ++b) {
         c->X = c->boxes[b];
         dmb_status s = build_cells_impl(c, gas + b, dm + b, par + b);

@@ -760,13 +760,22 @@ __global__ __launch_bounds__(256) void k_tile_subs(int64_t nt, const uint64_t* _
 }
 
 // Work items: each tile's candidate list cut into equal pieces of at most
-// `split` sub-tiles.
+// `split` sub-tiles.  A small problem (fewer than `target` x `split` candidate
+// sub-tiles in all, `total`) gets a smaller piece size, down to kItemMinSplit,
+// so that about `target` items keep every compute unit busy.
+constexpr uint32_t kItemMinSplit = 4;
 __global__ __launch_bounds__(256) void k_item_count(const uint32_t* __restrict__ cnt, int64_t nt, uint32_t split,
+                                                    const uint64_t* __restrict__ total, uint32_t target,
                                                     uint32_t* __restrict__ icnt)
 {
     int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t > nt) return;
-    icnt[t] = t < nt ? (cnt[t] + split - 1) / split : 0u;
+    uint32_t s = split;
+    if (target > 0 && split > kItemMinSplit) {
+        const uint64_t want = (*total + target - 1) / target;
+        s = uint32_t(max<uint64_t>(kItemMinSplit, min<uint64_t>(split, want)));
+    }
+    icnt[t] = t < nt ? (cnt[t] + s - 1) / s : 0u;
 }
 
 // Item it: its tile t (binary search over item_off), and the piece of t's
