@@ -91,22 +91,29 @@ __device__ __forceinline__ T dpp_take_min(T v, bool take)
 
 // Segmented inclusive scan upward over the wave: segments are runs of
 // consecutive lanes, `lo` the first lane of this lane's run.  f(ctrl, rows,
-// take) is called for six steps (four row shifts, then the two row
+// take) is called for up to six steps (four row shifts, then the two row
 // broadcasts); folding the moved copies in where `take` holds leaves every
 // lane with the combination of lanes [lo, lane] in a fixed order, so the
-// run's total sits in its last lane.
+// run's total sits in its last lane.  A step that no lane takes is skipped
+// (a wave-uniform branch): short runs cost only the first steps.
 template <typename F>
 __device__ __forceinline__ void seg_scan_up(int lane, int lo, F&& f)
 {
     using std::integral_constant;
     const int row0 = lane & ~15;
     const int lr = max(lo, row0);   // first lane of the run within this lane's row
-    f(integral_constant<int, 0x111>(), integral_constant<int, 0xF>(), lane - 1 >= lr);
-    f(integral_constant<int, 0x112>(), integral_constant<int, 0xF>(), lane - 2 >= lr);
-    f(integral_constant<int, 0x114>(), integral_constant<int, 0xF>(), lane - 4 >= lr);
-    f(integral_constant<int, 0x118>(), integral_constant<int, 0xF>(), lane - 8 >= lr);
-    f(integral_constant<int, 0x142>(), integral_constant<int, 0xA>(), (lane & 16) != 0 && lo < row0);
-    f(integral_constant<int, 0x143>(), integral_constant<int, 0xC>(), lane >= 32 && lo <= 31);
+    bool tk = lane - 1 >= lr;
+    if (__ballot(tk)) f(integral_constant<int, 0x111>(), integral_constant<int, 0xF>(), tk);
+    tk = lane - 2 >= lr;
+    if (__ballot(tk)) f(integral_constant<int, 0x112>(), integral_constant<int, 0xF>(), tk);
+    tk = lane - 4 >= lr;
+    if (__ballot(tk)) f(integral_constant<int, 0x114>(), integral_constant<int, 0xF>(), tk);
+    tk = lane - 8 >= lr;
+    if (__ballot(tk)) f(integral_constant<int, 0x118>(), integral_constant<int, 0xF>(), tk);
+    tk = (lane & 16) != 0 && lo < row0;
+    if (__ballot(tk)) f(integral_constant<int, 0x142>(), integral_constant<int, 0xA>(), tk);
+    tk = lane >= 32 && lo <= 31;
+    if (__ballot(tk)) f(integral_constant<int, 0x143>(), integral_constant<int, 0xC>(), tk);
 }
 
 // Inclusive prefix sum over the wave's lanes (v >= 0), in registers: four
@@ -1326,30 +1333,68 @@ __device__ __forceinline__ int test_next(PairTest& T, TestLds& S, const PassGeom
     return H;
 }
 
-// Hits of one round of a group: lane L takes hit base + L.  Every owner whose
-// hits [s0, e0) reach into the round marks the lane of its first one there
-// with (that lane + 1, the hit's rank among the owner's hits, owner); a
-// prefix maximum over the lanes hands each lane the latest mark at or below
-// it.  A wave's LDS operations complete in issue order, so the marks need no
-// barrier beyond the wave.
-__device__ __forceinline__ uint32_t round_marks(TestLds& S, int lane, int base, int s0, int e0, int my_lo)
+// Evaluation of a group's hits.  The hits are owner-major: owner o's are
+// ranks [offs[o], offs[o+1]) of the group, its slots the set bits of mask[o]
+// in increasing order.  With R = ceil(H / 64) rounds, lane l takes the
+// contiguous ranks [l R, min((l + 1) R, H)), one per round, and keeps a
+// running partial sum for the owner it is on.  When it takes an owner's last
+// hit of the group it adds the partial to the owner's row of the item sums
+// (in LDS) and moves to the next owner with hits; a lane whose range ends
+// inside an owner's hits leaves an open partial, and the open partials of
+// the lanes that share an owner are summed across lanes (segmented scan, lane
+// order) and added by the last of them.  Each owner's last hit lies in one
+// lane and one round, so the in-round adds touch distinct rows; every sum is
+// formed in a fixed order, independent of timing.
+struct HitWalk {
+    int o;                        // owner of the lane's next hit (64: none)
+    uint64_t rem;                 // slots of owner o not taken yet (the lane's next hit is the lowest)
+    int n;                        // hits of the lane's range
+    uint64_t own;                 // owners with hits in the group (wave-uniform)
+};
+
+// First owner with hits after owner o (64: none).
+__device__ __forceinline__ int next_owner(uint64_t own, int o)
 {
+    const uint64_t m = own & ~((2ull << o) - 1ull);   // o = 63: 2 << 63 wraps to 0, m = 0
+    return m ? int(__builtin_ctzll(m)) : 64;
+}
+
+// Lane ranges of a group with H > 0 hits in R rounds.  The owner of rank
+// l R is the owner with hits whose first rank is the largest one <= l R:
+// owner o marks lane ceil(offs[o] / R), the first lane whose range starts at
+// or after its first hit (the largest owner wins a shared lane), and a prefix
+// maximum over the lanes carries the marks upward.
+__device__ __forceinline__ void walk_begin(TestLds& S, int lane, int H, int R, HitWalk& w)
+{
+    const int k0 = lane * R;
+    w.n = max(0, min(R, H - k0));
+    const int lo = S.offs[lane], hi = S.offs[lane + 1];
+    w.own = __ballot(hi > lo);
     S.sj[lane] = 0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    if (s0 < e0) S.sj[s0 - base] = int((uint32_t(s0 - base + 1) << 16) | (uint32_t(s0 - my_lo) << 8) | uint32_t(lane));
+    if (hi > lo) {
+        const int l0 = (lo + R - 1) / R;
+        if (l0 < 64) atomicMax(&S.sj[l0], lane + 1);
+    }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    return wave_incl_umax(uint32_t(S.sj[lane]));
+    w.o = int(wave_incl_umax(uint32_t(S.sj[lane]))) - 1;
+    w.rem = 0ull;
+    if (w.n > 0) {
+        const uint64_t m = S.mask[w.o];
+        w.rem = m & (~0ull << select_bit(m, k0 - S.offs[w.o]));
+    }
 }
 
-// Owner o, slot s and first lane `lo` of the owner's run for the lane's hit
-// (lanes that hold a hit of the round only).
-__device__ __forceinline__ void round_decode(const TestLds& S, int lane, uint32_t mark, int* o, int* s, int* lo)
+// Runs of lanes with the same key (open partials: the owner; others a key of
+// their own): the first lane of this lane's run, and whether it is the last.
+__device__ __forceinline__ int run_first(int lane, int key, bool* last)
 {
-    *lo = int(mark >> 16) - 1;
-    *o = int(mark & 255u);
-    *s = select_bit(S.mask[*o], int((mark >> 8) & 255u) + lane - *lo);
+    const int kp = __shfl(key, max(lane - 1, 0)), kn = __shfl(key, min(lane + 1, 63));
+    *last = lane == 63 || kn != key;
+    const bool first = lane == 0 || kp != key;
+    return int(wave_incl_umax(first ? uint32_t(lane + 1) : 0u)) - 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1415,6 +1460,7 @@ void k_pass_gas(
     __shared__ Real s_gx[kMaxQuadNodes], s_gw[kMaxQuadNodes];
     __shared__ double o_x_[W][64], o_y_[W][64], o_z_[W][64], o_h_[W][64], o_Vx_[W][64], o_Vy_[W][64], o_Vz_[W][64];
     __shared__ Real o_i2_[W][64], o_a_[W][64], o_b_[W][64], o_r_[W][64];
+    __shared__ double osum_[W][64 * 4];
     __shared__ __align__(16) unsigned char s_mlp[RM == kRatesMlp ? kMlpInferBytes : 16];
     const int wv = W == 1 ? 0 : int(threadIdx.x) >> 6;
     TestLds& S = S_[wv];
@@ -1477,29 +1523,31 @@ void k_pass_gas(
         for (int k = 0; k < 6; ++k) A[k] = G.obox[6 * t + k];
         const double cen[3] = {0.5 * (A[0] + A[3]), 0.5 * (A[1] + A[4]), 0.5 * (A[2] + A[5])};
         const float fx = float(mx - cen[0]), fy = float(my - cen[1]), fz = float(mz - cen[2]), fh = float(mh);
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        // the item's per-owner sums (row = owner lane)
+        double* osum = osum_[wv] + 4 * lane;
+        osum[0] = 0.0; osum[1] = 0.0; osum[2] = 0.0; osum[3] = 0.0;
         PairTest T;
         test_begin(T, ov, fx, fy, fz, fh, cb, ce);
         for (;;) {
             const int H = test_next<W>(T, S, G, A, cen, Lf);
             if (H < 0) break;
-            const int my_lo = S.offs[lane], my_hi = S.offs[lane + 1];
-            for (int base = 0; base < H; base += 64) {
-                const int pp = base + lane;
-                // this owner's hits in the round: [s0, e0)
-                const int s0 = max(my_lo, base), e0 = min(my_hi, base + 64);
-                const uint32_t mark = round_marks(S, lane, base, s0, e0, my_lo);
-                // per-pair terms and their per-owner sums over the round in binary64 (the overlap
-                // near contact is far below the binary32 range; sums of terms that cancel keep
-                // their accuracy)
+            if (H == 0) continue;
+            const int R = (H + 63) >> 6;
+            HitWalk hw;
+            walk_begin(S, lane, H, R, hw);
+            // per-pair terms and the lane's partial sums in binary64 (the overlap near contact is
+            // far below the binary32 range; sums of terms that cancel keep their accuracy)
+            double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+            bool open = false;
+            for (int r = 0; r < R; ++r) {
+                const bool live = r < hw.n;
+                const int o = live ? hw.o : 0;
+                const int sl = live ? int(__builtin_ctzll(hw.rem)) : 0;
                 double c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-                int seg_lo = lane;
                 if constexpr (RM != kRatesMlp) {
                     bool hit = false;
                     uint32_t e_o = 0u, e_q = 0u;
-                    if (pp < H) {
-                        int o, sl;
-                        round_decode(S, lane, mark, &o, &sl, &seg_lo);
+                    if (live) {
                         const uint32_t pqv = S.pq[sl];
                         const int64_t q = int64_t(pqv & 0x7fffffffu);
                         const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
@@ -1541,21 +1589,18 @@ void k_pass_gas(
                     if constexpr (PAIRS) pair_export(G, hit, e_o, e_q);
                 } else {
                     // pair geometry per lane, then the network over the whole wave
-                    bool live = false;
-                    int o = 0;
+                    bool live2 = false;
                     int64_t q = 0;
                     double gg = 0.0;
                     float wx = 0.f, wy = 0.f, wz = 0.f, w2 = 0.f, i2 = 0.f, u = 0.f, mq = 0.f;
-                    if (pp < H) {
-                        int sl;
-                        round_decode(S, lane, mark, &o, &sl, &seg_lo);
+                    if (live) {
                         const uint32_t pqv = S.pq[sl];
                         q = int64_t(pqv & 0x7fffffffu);
                         const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
                         const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, (pqv >> 31) != 0u, G.L);
                         const double hs = o_h[o] + qh;
                         if (d2 < hs * hs) {
-                            live = true;
+                            live2 = true;
                             npairs++;
                             gg = overlap_g_table(a.gtab, d2, qh, o_h[o]);
                             const DmRec<float> r = reinterpret_cast<const DmRec<float>*>(a.drec)[q];
@@ -1568,7 +1613,7 @@ void k_pass_gas(
                             u = isinf(i2) ? 0.f : sqrt_real(2.f * w2 * i2);
                         }
                     }
-                    const bool net = live && !isinf(i2) && u <= kMlpUMax;
+                    const bool net = live2 && !isinf(i2) && u <= kMlpUMax;
                     float yA = 0.f, yB = 0.f;
                     if (__ballot(net) != 0ull) {
                         // an opaque zero offset keeps the weight reads inside the loop
@@ -1576,9 +1621,9 @@ void k_pass_gas(
                         int zoff = 0;
                         asm volatile("" : "+v"(zoff));
                         const MlpBlob* Wl = reinterpret_cast<const MlpBlob*>(s_mlp + zoff);
-                        // candidate pairs occupy lanes 0 .. H-base-1: evaluate only the
-                        // 16-column blocks that hold some
-                        const int nlive = min(H - base, 64);
+                        // the round's pairs occupy lanes 0 .. nlive-1 (the lanes whose range
+                        // reaches round r): evaluate only the 16-column blocks that hold some
+                        const int nlive = min((H - r + R - 1) / R, 64);
                         if (nlive > 32)
                             mlp_forward64<4, 4>(Wl, mlp_input(u), a0.mlp_nidx, &yA, &yB);
                         else if (nlive > 16)
@@ -1586,7 +1631,7 @@ void k_pass_gas(
                         else
                             mlp_forward64<1, 1>(Wl, mlp_input(u), a0.mlp_nidx, &yA, &yB);
                     }
-                    if (live) {
+                    if (live2) {
                         float Ar, Br;
                         if (isinf(i2)) {
                             Ar = pow_np1<N>(sqrt_real(w2));
@@ -1610,26 +1655,44 @@ void k_pass_gas(
                         c3 = mg * double(w2 * Ar - o_r[o] * Br);
                     }
                 }
-                seg_scan_up(lane, seg_lo, [&](auto ctl, auto rows, bool take) {
-                    constexpr int C = decltype(ctl)::value, R = decltype(rows)::value;
-                    c0 = dpp_take_add<C, R>(c0, take);
-                    c1 = dpp_take_add<C, R>(c1, take);
-                    c2 = dpp_take_add<C, R>(c2, take);
-                    c3 = dpp_take_add<C, R>(c3, take);
+                p0 += c0; p1 += c1; p2 += c2; p3 += c3;
+                if (live) hw.rem &= hw.rem - 1ull;
+                const bool done = live && hw.rem == 0ull;
+                if (live) open = !done;
+                if (__ballot(done) != 0ull && done) {
+                    // the owner's last hit of the group: its partial goes to the owner's row
+                    double* q = osum_[wv] + 4 * hw.o;
+                    q[0] += p0; q[1] += p1; q[2] += p2; q[3] += p3;
+                    p0 = 0.0; p1 = 0.0; p2 = 0.0; p3 = 0.0;
+                    hw.o = next_owner(hw.own, hw.o);
+                    hw.rem = hw.o < 64 ? S.mask[hw.o] : 0ull;
+                }
+            }
+            // open partials: lanes whose range ended inside an owner's hits
+            if (__ballot(open) != 0ull) {
+                bool last;
+                const int lo = run_first(lane, open ? hw.o : 64 + lane, &last);
+                seg_scan_up(lane, lo, [&](auto ctl, auto rows, bool take) {
+                    constexpr int C = decltype(ctl)::value, RW = decltype(rows)::value;
+                    p0 = dpp_take_add<C, RW>(p0, take);
+                    p1 = dpp_take_add<C, RW>(p1, take);
+                    p2 = dpp_take_add<C, RW>(p2, take);
+                    p3 = dpp_take_add<C, RW>(p3, take);
                 });
-                // the owner's sums of the round sit in the lane of its last hit
-                const bool has = s0 < e0;
-                const int src = has ? e0 - 1 - base : 0;
-                const double v0 = __shfl(c0, src), v1 = __shfl(c1, src), v2 = __shfl(c2, src), v3 = __shfl(c3, src);
-                if (has) { acc0 += v0; acc1 += v1; acc2 += v2; acc3 += v3; }
+                if (open && last) {
+                    double* q = osum_[wv] + 4 * hw.o;
+                    q[0] += p0; q[1] += p1; q[2] += p2; q[3] += p3;
+                }
             }
         }
-        const double acc[4] = {acc0, acc1, acc2, acc3};
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const double acc[4] = {osum[0], osum[1], osum[2], osum[3]};
         if (G.item_off[t + 1] - G.item_off[t] == 1u) {
             if (ov) gas_write_out(a, a.perm[sp], acc);
         } else {
             double* P = a.part + (it * kTile + lane) * 4;
-            P[0] = acc0; P[1] = acc1; P[2] = acc2; P[3] = acc3;
+            P[0] = acc[0]; P[1] = acc[1]; P[2] = acc[2]; P[3] = acc[3];
         }
     }
     for (int d = 32; d >= 1; d >>= 1) npairs += __shfl_xor(npairs, d);
@@ -1711,6 +1774,9 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
     __shared__ double o_x[64], o_y[64], o_z[64], o_h[64], o_vx[64], o_vy[64], o_vz[64];
     __shared__ Real o_dt[64];
     __shared__ uint32_t o_id[64];
+    __shared__ double osP[64];
+    __shared__ Real osM[64];
+    __shared__ int osNB[64];
     const int lane = lane_id();
     int64_t it;
     uint64_t npairs = 0, ncrit = 0, nnear = 0, nscat = 0, npge1 = 0, nnonf = 0, nneard = 0;
@@ -1772,31 +1838,30 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
         for (int k = 0; k < 6; ++k) A[k] = G.obox[6 * t + k];
         const double cen[3] = {0.5 * (A[0] + A[3]), 0.5 * (A[1] + A[4]), 0.5 * (A[2] + A[5])};
         const float fx = float(mx - cen[0]), fy = float(my - cen[1]), fz = float(mz - cen[2]), fh = float(mh);
-        double accP = 0.0;
-        Real accM = 0;
-        int accNB = 0;
+        // the item's per-owner sums (row = owner lane)
+        osP[lane] = 0.0; osM[lane] = Real(0); osNB[lane] = 0;
         PairTest T;
         test_begin(T, ov, fx, fy, fz, fh, cb, ce);
         for (;;) {
             const int H = test_next<1>(T, S, G, A, cen, Lf);
             if (H < 0) break;
-            const int my_lo = S.offs[lane], my_hi = S.offs[lane + 1];
-            for (int base = 0; base < H; base += 64) {
-                const int pp = base + lane;
-                // this owner's hits in the round: [s0, e0)
-                const int s0 = max(my_lo, base), e0 = min(my_hi, base + 64);
-                const uint32_t mark = round_marks(S, lane, base, s0, e0, my_lo);
-                // a round's per-owner sums of P_ij in the pair precision (binary32: at most 64 terms,
-                // a relative error below 6 units of 2^-24), accumulated over rounds in binary64
-                Real cP = 0;
-                Real cM = 0;
-                int cNB = 0;
-                int seg_lo = lane;
+            if (H == 0) continue;
+            const int R = (H + 63) >> 6;
+            HitWalk hw;
+            walk_begin(S, lane, H, R, hw);
+            // the lane's partial sum of P_ij in the pair precision (binary32: at most 64 terms, a
+            // relative error below 6 units of 2^-24), its maximum and near-boundary flag; the
+            // owner rows accumulate the partials in binary64
+            Real pP = 0, pM = 0;
+            int pNB = 0;
+            bool open = false;
+            for (int r = 0; r < R; ++r) {
+                const bool live = r < hw.n;
+                const int o = live ? hw.o : 0;
+                const int sl = live ? int(__builtin_ctzll(hw.rem)) : 0;
                 bool hit = false;
                 uint32_t e_o = 0u, e_q = 0u;
-                if (pp < H) {
-                    int o, sl;
-                    round_decode(S, lane, mark, &o, &sl, &seg_lo);
+                if (live) {
                     const uint32_t pqv = S.pq[sl];
                     const int64_t q = int64_t(pqv & 0x7fffffffu);
                     const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
@@ -1808,7 +1873,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
                         e_o = G.own[t * kTile + o];
                         e_q = uint32_t(q);
                     }
-                    if (fabs(d2 - hs2) <= 1e-6 * hs2) cNB = 1;
+                    if (fabs(d2 - hs2) <= 1e-6 * hs2) pNB = 1;
                     if (d2 < hs2) {
                         npairs++;
                         Real urel[3];
@@ -1816,30 +1881,47 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
                         const Real P = pair_P<Real, N, EXACT_G>(d2, o_h[o], qh, o_vx[o], o_vy[o], o_vz[o], r.Vx, r.Vy,
                                                                 r.Vz, r.vs, r.K, o_dt[o], o_id[o], r.perm, step, a.box,
                                                                 a.k0, a.k1, a.gtab, urel);
-                        cP = P;
-                        cM = P;
+                        pP += P;
+                        pM = pM > P ? pM : P;
                         if (P >= r.crit) ncrit++;
                     }
+                    hw.rem &= hw.rem - 1ull;
                 }
                 if constexpr (PAIRS) pair_export(G, hit, e_o, e_q);
-                seg_scan_up(lane, seg_lo, [&](auto ctl, auto rows, bool take) {
-                    constexpr int C = decltype(ctl)::value, R = decltype(rows)::value;
-                    cP = dpp_take_add<C, R>(cP, take);
-                    cM = dpp_take_max<C, R>(cM, take);
+                const bool done = live && hw.rem == 0ull;
+                if (live) open = !done;
+                if (__ballot(done) != 0ull && done) {
+                    // the owner's last hit of the group: its partial goes to the owner's row
+                    osP[hw.o] += double(pP);
+                    osM[hw.o] = osM[hw.o] > pM ? osM[hw.o] : pM;
+                    osNB[hw.o] |= pNB;
+                    pP = 0; pM = 0; pNB = 0;
+                    hw.o = next_owner(hw.own, hw.o);
+                    hw.rem = hw.o < 64 ? S.mask[hw.o] : 0ull;
+                }
+            }
+            // open partials: lanes whose range ended inside an owner's hits
+            if (__ballot(open) != 0ull) {
+                bool last;
+                const int lo = run_first(lane, open ? hw.o : 64 + lane, &last);
+                seg_scan_up(lane, lo, [&](auto ctl, auto rows, bool take) {
+                    constexpr int C = decltype(ctl)::value, RW = decltype(rows)::value;
+                    pP = dpp_take_add<C, RW>(pP, take);
+                    pM = dpp_take_max<C, RW>(pM, take);
+                    pNB |= int(dpp_u32<C, RW>(uint32_t(pNB))) & int(take);
                 });
-                const uint64_t nbm = __ballot(cNB != 0);
-                // the owner's sums of the round sit in the lane of its last hit
-                const bool has = s0 < e0;
-                const int src = has ? e0 - 1 - base : 0;
-                const Real vP = __shfl(cP, src);
-                const Real vM = __shfl(cM, src);
-                if (has) {
-                    accP += double(vP);
-                    accM = accM > vM ? accM : vM;
-                    accNB |= int(any_bits(nbm, s0 - base, e0 - base));
+                if (open && last) {
+                    osP[hw.o] += double(pP);
+                    osM[hw.o] = osM[hw.o] > pM ? osM[hw.o] : pM;
+                    osNB[hw.o] |= pNB;
                 }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const double accP = osP[lane];
+        const Real accM = osM[lane];
+        const int accNB = osNB[lane];
         if (G.item_off[t + 1] - G.item_off[t] == 1u) {
             if (ov) {
                 if (accNB) nnear++;
