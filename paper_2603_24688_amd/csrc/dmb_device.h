@@ -162,14 +162,14 @@ __device__ __forceinline__ double overlap_g_table(const float4* __restrict__ tab
     const double x = shell ? 0.5 * r : d * ib, y = shell ? eta : r;
     const double fx = fmin(x, 1.0) * double(kTabN), fy = fmin(y, 1.0) * double(kTabN);
     const int i = min(int(fx), kTabN - 1), j = min(int(fy), kTabN - 1);
-    const double a = fx - double(i), b = fy - double(j);
+    // the cell polynomial (smooth, positive, of order one) in binary32: its rounding stays
+    // below the table's own error; the envelope and the 1/h_b^3 scale stay in binary64
+    const float a = float(fx - double(i)), b = float(fy - double(j));
     const float4* c = tab + 4 * ((shell ? 0 : kTabCellsRegion) + j * kTabN + i);
     const float4 q0 = c[0], q2 = c[1], q3 = c[2], q1 = c[3];
-    auto cubic = [a](float4 q) {
-        return fma(fma(fma(double(q.w), a, double(q.z)), a, double(q.y)), a, double(q.x));
-    };
-    const double p0 = cubic(q0), p2 = cubic(q2), p3 = cubic(q3), p1 = fma(double(q1.y), a, double(q1.x));
-    const double Q = fma(fma(fma(p3, b, p2), b, p1), b, p0);
+    auto cubic = [a](float4 q) { return fmaf(fmaf(fmaf(q.w, a, q.z), a, q.y), a, q.x); };
+    const float p0 = cubic(q0), p2 = cubic(q2), p3 = cubic(q3), p1 = fmaf(q1.y, a, q1.x);
+    const double Q = double(fmaf(fmaf(fmaf(p3, b, p2), b, p1), b, p0));
     double env;
     if (shell) {
         const double r2 = r * r, r4 = r2 * r2;
@@ -299,6 +299,24 @@ template <> struct RealTraits<double> {
 };
 
 __device__ __forceinline__ float erf_real(float x) { return erff(x); }
+
+// erf(t) for t >= 1 in binary32, given e = e^{-t^2}: erf = 1 - e R(t) with
+// R(t) = e^{t^2} erfc(t), an entire function, as a degree-12 polynomial in
+// t - 2.75 (weighted least-squares fit for relative error on [1, 4.5]; Horner
+// in binary32 keeps R within 1.5e-7).  Past t = 4.5, e R < 2^-28 and R(4.5)
+// stands in.  Sharing e with the caller saves erf its own exponential.
+__device__ __forceinline__ float erf_ge1(float t, float e)
+{
+    constexpr float c[13] = {1.936620921e-01f, -6.323760748e-02f, 1.975860447e-02f, -5.934607703e-03f,
+                             1.719569904e-03f, -4.814862041e-04f, 1.311259839e-04f, -3.548420500e-05f,
+                             9.050128938e-06f, -1.834100885e-06f, 4.788607271e-07f, -2.315289720e-07f,
+                             5.124300273e-08f};
+    const float z = fminf(t, 4.5f) - 2.75f;
+    float R = c[12];
+#pragma unroll
+    for (int k = 11; k >= 0; --k) R = fmaf(R, z, c[k]);
+    return fmaf(-e, R, 1.0f);
+}
 __device__ __forceinline__ double erf_real(double x) { return erf(x); }
 __device__ __forceinline__ float exp_neg(float x) { return __expf(-x); }
 __device__ __forceinline__ double exp_neg(double x) { return exp(-x); }
@@ -329,7 +347,10 @@ __device__ __forceinline__ void rate_1f1(T x, T* FA, T* FB)
         r = T(1) / x;
         it = T(1) / t;
     }
-    T E = erf_real(t), ex = exp_neg(x);
+    const T ex = exp_neg(x);
+    T E;
+    if constexpr (sizeof(T) == 4) E = erf_ge1(t, ex);
+    else E = erf_real(t);
     T spE = T(kSqrtPi) * E;
     if constexpr (N == 0) {
         *FA = T(3.0 / 32.0) * (spE * (T(4) * x + T(4) - r) * it + T(2) * (T(2) + r) * ex);
