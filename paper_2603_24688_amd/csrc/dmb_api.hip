@@ -41,7 +41,7 @@ struct Species {
     DevBuf prec;                           // packed (x, y, z, h) in input order
     // per-step gathers (sorted order)
     DevBuf v0, v1, v2;                     // velocity components (double)
-    DevBuf r0, r1, r2, r3, r4, r5, r6;     // Real-typed per-particle factors
+    DevBuf orate;                          // gas: OwnRate<Real> of the active gas, owner-slot order
     DevBuf rec;                            // per-pair records of this species as the other one (GasRec / DmRec)
     const uint32_t* perm = nullptr;        // = vals after the sort
 };
@@ -642,14 +642,14 @@ dmb_status gather_and_fill(dmb_ctx* c, Cells& X, const dmb_particles* gas, const
     const int rs = int(sizeof(Real));
     if (G.n > 0) {
         ENSURE(c, G.v0, G.n * 8); ENSURE(c, G.v1, G.n * 8); ENSURE(c, G.v2, G.n * 8);
-        DevBuf* rb[7] = {&G.r0, &G.r1, &G.r2, &G.r3, &G.r4, &G.r5, &G.r6};
-        for (DevBuf* b : rb) ENSURE(c, *b, G.n * rs);
+        ENSURE(c, G.orate, std::max<int64_t>(G.n_own, 1) * rs * 4);
         GasGatherArgs ga;
         ga.n = G.n; ga.perm = G.perm; ga.vel = gas->vel; ga.mass = gas->mass; ga.u = gas->u; ga.mu = gas->mu;
         ga.m_chi = par->m_chi_g; ga.sig_kpc2_cn = sig_kpc2_cn_of(par); ga.alpha_n = alpha_n(par->n_pow);
         ga.n_pow = par->n_pow;
         ga.Vx = G.v0.as<double>(); ga.Vy = G.v1.as<double>(); ga.Vz = G.v2.as<double>();
-        ga.inv2s2 = G.r1.p; ga.ra = G.r2.p; ga.rb = G.r3.p; ga.rr = G.r4.p;
+        ga.flag = G.flag.as<const uint32_t>(); ga.flag_off = G.flag_off.as<const uint32_t>();
+        ga.orate = G.orate.p;
         ENSURE(c, G.rec, G.n * (sizeof(Real) == 4 ? sizeof(GasRec<float>) : sizeof(GasRec<double>)));
         ga.rec = G.rec.p;
         hipLaunchKernelGGL(k_gather_gas<Real>, dim3(blocks_for(G.n, 256)), dim3(256), 0, c->stream, ga);
@@ -688,7 +688,7 @@ GasPassArgs gas_pass_args(dmb_ctx* c, Cells& X, const dmb_particles* gas, const 
     GasPassArgs a;
     a.g = geom(X, G, D, X.gp, counters);
     a.Vx = G.v0.as<const double>(); a.Vy = G.v1.as<const double>(); a.Vz = G.v2.as<const double>();
-    a.inv2s2 = G.r1.p; a.ra = G.r2.p; a.rb = G.r3.p; a.rr = G.r4.p;
+    a.orate = G.orate.p;
     a.drec = D.rec.p;
     a.gtab = c->gtab.as<const float4>();
     const DevBuf& glb = sizeof(Real) == 8 ? c->gl64 : c->gl32;
@@ -871,8 +871,7 @@ dmb_status batch_prepare(dmb_ctx* c, int nbox, const dmb_particles* gas, const d
         Species& D = X.dm;
         if (G.n > 0) {
             ENSURE(c, G.v0, G.n * 8); ENSURE(c, G.v1, G.n * 8); ENSURE(c, G.v2, G.n * 8);
-            DevBuf* rb[7] = {&G.r0, &G.r1, &G.r2, &G.r3, &G.r4, &G.r5, &G.r6};
-            for (DevBuf* bb : rb) ENSURE(c, *bb, G.n * rs);
+            ENSURE(c, G.orate, std::max<int64_t>(G.n_own, 1) * rs * 4);
             ENSURE(c, G.rec, G.n * (sizeof(Real) == 4 ? sizeof(GasRec<float>) : sizeof(GasRec<double>)));
         }
         if (D.n > 0) {
@@ -1143,8 +1142,7 @@ void free_cells(Cells& X)
     for (Species* S : {&X.gas, &X.dm}) {
         DevBuf* all[] = {&S->keys, &S->keys2, &S->vals, &S->vals2, &S->sx, &S->sy, &S->sz, &S->sh, &S->flag,
                          &S->flag_off, &S->own, &S->tbox, &S->th, &S->sbox, &S->shh, &S->mbox, &S->mhh, &S->obox,
-                         &S->oh, &S->cube, &S->v0, &S->v1, &S->v2, &S->r0, &S->r1, &S->r2, &S->r3, &S->r4, &S->r5,
-                         &S->r6, &S->rec, &S->sub_ccnt, &S->sub_coff, &S->sub_start, &S->sub_cnt, &S->tsup, &S->ssup,
+                         &S->oh, &S->cube, &S->v0, &S->v1, &S->v2, &S->orate, &S->rec, &S->sub_ccnt, &S->sub_coff, &S->sub_start, &S->sub_cnt, &S->tsup, &S->ssup,
                          &S->msup, &S->tq, &S->sq, &S->mq, &S->prec};
         for (DevBuf* b : all) fr(*b);
     }

@@ -826,6 +826,11 @@ template <typename Real> struct alignas(16) GasRec {   // gas, read by the DM pa
     Real vs, K, crit;             // sqrt(2 u / 3), K_j, P threshold
     uint32_t perm;                // sorted position -> gas index
 };
+template <typename Real> struct alignas(16) OwnRate {  // active gas in owner-slot order, read by the gas pass
+    Real i2;                      // 1 / (2 vs^2) (infinite for cold gas)
+    Real a, b;                    // alpha_n/3 vs^{n+1}, alpha_n vs^{n+3}
+    Real r;                       // mu_j / (m_chi + mu_j)
+};
 template <typename Real> struct alignas(16) DmRec {    // DM, read by the gas pass (other) and the DM pass (owner)
     double vx, vy, vz;            // velocity
     Real m;                       // mass
@@ -839,7 +844,8 @@ struct GasGatherArgs {
     double m_chi, sig_kpc2_cn, alpha_n;
     int n_pow;
     double* Vx; double* Vy; double* Vz;
-    void* inv2s2; void* ra; void* rb; void* rr;             // owner factors (Real)
+    const uint32_t* flag; const uint32_t* flag_off;         // active flags and their exclusive scan (sorted order)
+    void* orate;                  // OwnRate<Real>[n_own], owner-slot order
     void* rec;                    // GasRec<Real>[n]
 };
 
@@ -870,10 +876,11 @@ __global__ __launch_bounds__(256) void k_gather_gas(GasGatherArgs a)
     double mu = a.mu ? a.mu[o] : kMpG;
     Real vs, i2, ra, rb, rr, cr;
     gas_derived<Real>(a.u[o], mu, a.m_chi, a.alpha_n, a.n_pow, &vs, &i2, &ra, &rb, &rr, &cr);
-    reinterpret_cast<Real*>(a.inv2s2)[k] = i2;
-    reinterpret_cast<Real*>(a.ra)[k] = ra;
-    reinterpret_cast<Real*>(a.rb)[k] = rb;
-    reinterpret_cast<Real*>(a.rr)[k] = rr;
+    if (a.flag[k]) {
+        OwnRate<Real> w;
+        w.i2 = i2; w.a = ra; w.b = rb; w.r = rr;
+        reinterpret_cast<OwnRate<Real>*>(a.orate)[a.flag_off[k]] = w;
+    }
     const Real K = Real(a.mass[o] * kMsunG / mu * a.sig_kpc2_cn);
     GasRec<Real> r;
     r.Vx = a.vel[3 * int64_t(o)]; r.Vy = a.vel[3 * int64_t(o) + 1]; r.Vz = a.vel[3 * int64_t(o) + 2];
@@ -1415,7 +1422,7 @@ __device__ __forceinline__ int box_of_item(const int64_t* __restrict__ box_items
 struct GasPassArgs {
     PassGeom g;
     const double* Vx; const double* Vy; const double* Vz;     // gas, sorted
-    const void* inv2s2; const void* ra; const void* rb; const void* rr;
+    const void* orate;            // OwnRate<Real>[n_own], owner-slot order
     const void* drec;             // DmRec<Real>, sorted DM (velocity, mass)
     const float4* gtab;
     const void* gl_x; const void* gl_w; int gl_k; double inv_alpha;   // quadrature rates (Real)
@@ -1459,14 +1466,12 @@ void k_pass_gas(
     __shared__ TestLds S_[W];
     __shared__ Real s_gx[kMaxQuadNodes], s_gw[kMaxQuadNodes];
     __shared__ double o_x_[W][64], o_y_[W][64], o_z_[W][64], o_h_[W][64], o_Vx_[W][64], o_Vy_[W][64], o_Vz_[W][64];
-    __shared__ Real o_i2_[W][64], o_a_[W][64], o_b_[W][64], o_r_[W][64];
     __shared__ double osum_[W][64 * 4];
     __shared__ __align__(16) unsigned char s_mlp[RM == kRatesMlp ? kMlpInferBytes : 16];
     const int wv = W == 1 ? 0 : int(threadIdx.x) >> 6;
     TestLds& S = S_[wv];
     double* o_x = o_x_[wv]; double* o_y = o_y_[wv]; double* o_z = o_z_[wv]; double* o_h = o_h_[wv];
     double* o_Vx = o_Vx_[wv]; double* o_Vy = o_Vy_[wv]; double* o_Vz = o_Vz_[wv];
-    Real* o_i2 = o_i2_[wv]; Real* o_a = o_a_[wv]; Real* o_b = o_b_[wv]; Real* o_r = o_r_[wv];
     const int lane = lane_id();
     if constexpr (RM == kRatesQuad || RM == kRatesMlp) {
         if (int(threadIdx.x) < a0.gl_k) {
@@ -1499,13 +1504,10 @@ void k_pass_gas(
         }
         const GasPassArgs& a = BATCH ? boxes[b] : a0;
         const PassGeom& G = a.g;
-        const Real* inv2s2 = reinterpret_cast<const Real*>(a.inv2s2);
-        const Real* ra = reinterpret_cast<const Real*>(a.ra);
-        const Real* rb = reinterpret_cast<const Real*>(a.rb);
-        const Real* rr = reinterpret_cast<const Real*>(a.rr);
         const float Lf[3] = {float(G.L[0]), float(G.L[1]), float(G.L[2])};
         it = G.item_order[it];
         const int64_t t = G.it_tile[it];
+        const OwnRate<Real>* orate = reinterpret_cast<const OwnRate<Real>*>(a.orate) + t * kTile;
         const uint64_t cb = G.it_cb[it], ce = G.it_ce[it];
         const int64_t slot = t * kTile + lane;
         const bool ov = slot < G.n_own;
@@ -1515,10 +1517,6 @@ void k_pass_gas(
         stage_sync<W>();
         o_x[lane] = mx; o_y[lane] = my; o_z[lane] = mz; o_h[lane] = mh;
         o_Vx[lane] = ov ? a.Vx[sp] : 0.0; o_Vy[lane] = ov ? a.Vy[sp] : 0.0; o_Vz[lane] = ov ? a.Vz[sp] : 0.0;
-        o_i2[lane] = ov ? inv2s2[sp] : Real(0);
-        o_a[lane] = ov ? ra[sp] : Real(0);
-        o_b[lane] = ov ? rb[sp] : Real(0);
-        o_r[lane] = ov ? rr[sp] : Real(0);
         double A[6];
         for (int k = 0; k < 6; ++k) A[k] = G.obox[6 * t + k];
         const double cen[3] = {0.5 * (A[0] + A[3]), 0.5 * (A[1] + A[4]), 0.5 * (A[2] + A[5])};
@@ -1563,10 +1561,11 @@ void k_pass_gas(
                             const double gg = EXACT_G ? double(overlap_g_exact<Real>(sqrt_real(Real(d2)), Real(qh), Real(o_h[o])))
                                                       : overlap_g_table(a.gtab, d2, qh, o_h[o]);
                             const DmRec<Real> r = reinterpret_cast<const DmRec<Real>*>(a.drec)[q];
+                            const OwnRate<Real> orr = orate[o];
                             const Real wx = Real(r.vx - o_Vx[o]), wy = Real(r.vy - o_Vy[o]), wz = Real(r.vz - o_Vz[o]);
                             const Real w2 = wx * wx + wy * wy + wz * wz;
                             Real FA, FB, Ar, Br;
-                            const Real i2 = o_i2[o];
+                            const Real i2 = orr.i2;
                             if (isinf(i2)) {  // cold gas: A = w^{n+1}, B = w^{n+3}
                                 const Real wn = sqrt_real(w2);
                                 Ar = pow_np1<N>(wn);
@@ -1577,13 +1576,13 @@ void k_pass_gas(
                                                        q_hw, q_bmin, &FA, &FB);
                                 else
                                     rate_1f1<N, Real>(w2 * i2, &FA, &FB);
-                                Ar = o_a[o] * FA;
-                                Br = o_b[o] * FB;
+                                Ar = orr.a * FA;
+                                Br = orr.b * FB;
                             }
                             const double mg = double(r.m) * gg;
                             const double mgA = mg * double(Ar);
                             c0 = mgA * double(wx); c1 = mgA * double(wy); c2 = mgA * double(wz);
-                            c3 = mg * double(w2 * Ar - o_r[o] * Br);
+                            c3 = mg * double(w2 * Ar - orr.r * Br);
                         }
                     }
                     if constexpr (PAIRS) pair_export(G, hit, e_o, e_q);
@@ -1593,6 +1592,7 @@ void k_pass_gas(
                     int64_t q = 0;
                     double gg = 0.0;
                     float wx = 0.f, wy = 0.f, wz = 0.f, w2 = 0.f, i2 = 0.f, u = 0.f, mq = 0.f;
+                    OwnRate<float> orr{0.f, 0.f, 0.f, 0.f};
                     if (live) {
                         const uint32_t pqv = S.pq[sl];
                         q = int64_t(pqv & 0x7fffffffu);
@@ -1609,7 +1609,8 @@ void k_pass_gas(
                             wz = float(r.vz - o_Vz[o]);
                             mq = r.m;
                             w2 = wx * wx + wy * wy + wz * wz;
-                            i2 = o_i2[o];
+                            orr = reinterpret_cast<const OwnRate<float>*>(orate)[o];
+                            i2 = orr.i2;
                             u = isinf(i2) ? 0.f : sqrt_real(2.f * w2 * i2);
                         }
                     }
@@ -1646,13 +1647,13 @@ void k_pass_gas(
                             } else {
                                 rate_quad<N, float>(u, s_gx, s_gw, a0.gl_k, inv_alpha, q_hw, q_bmin, &FA, &FB);
                             }
-                            Ar = o_a[o] * FA;
-                            Br = o_b[o] * FB;
+                            Ar = orr.a * FA;
+                            Br = orr.b * FB;
                         }
                         const double mg = double(mq) * gg;
                         const double mgA = mg * double(Ar);
                         c0 = mgA * double(wx); c1 = mgA * double(wy); c2 = mgA * double(wz);
-                        c3 = mg * double(w2 * Ar - o_r[o] * Br);
+                        c3 = mg * double(w2 * Ar - orr.r * Br);
                     }
                 }
                 p0 += c0; p1 += c1; p2 += c2; p3 += c3;
