@@ -170,14 +170,9 @@ __device__ __forceinline__ double overlap_g_table(const float4* __restrict__ tab
     auto cubic = [a](float4 q) { return fmaf(fmaf(fmaf(q.w, a, q.z), a, q.y), a, q.x); };
     const float p0 = cubic(q0), p2 = cubic(q2), p3 = cubic(q3), p1 = fmaf(q1.y, a, q1.x);
     const double Q = double(fmaf(fmaf(fmaf(p3, b, p2), b, p1), b, p0));
-    double env;
-    if (shell) {
-        const double r2 = r * r, r4 = r2 * r2;
-        env = eta * eta * eta * (r4 * r4);
-    } else {
-        const double t = inner * ib;
-        env = t * t * t;
-    }
+    // both envelopes and a select: one basic block, so the scheduler can overlap the cell loads
+    const double r2 = r * r, r4 = r2 * r2, tc = inner * ib;
+    const double env = shell ? eta * eta * eta * (r4 * r4) : tc * tc * tc;
     return Q * env * (ib * ib * ib);
 }
 

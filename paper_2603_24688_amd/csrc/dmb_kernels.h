@@ -1548,6 +1548,9 @@ void k_pass_gas(
                     if (live) {
                         const uint32_t pqv = S.pq[sl];
                         const int64_t q = int64_t(pqv & 0x7fffffffu);
+                        // the pair's records, issued before the distance work that hides their latency
+                        const DmRec<Real> r = reinterpret_cast<const DmRec<Real>*>(a.drec)[q];
+                        const OwnRate<Real> orr = orate[o];
                         const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
                         const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, (pqv >> 31) != 0u, G.L);
                         const double hs = o_h[o] + qh;
@@ -1560,8 +1563,6 @@ void k_pass_gas(
                             npairs++;
                             const double gg = EXACT_G ? double(overlap_g_exact<Real>(sqrt_real(Real(d2)), Real(qh), Real(o_h[o])))
                                                       : overlap_g_table(a.gtab, d2, qh, o_h[o]);
-                            const DmRec<Real> r = reinterpret_cast<const DmRec<Real>*>(a.drec)[q];
-                            const OwnRate<Real> orr = orate[o];
                             const Real wx = Real(r.vx - o_Vx[o]), wy = Real(r.vy - o_Vy[o]), wz = Real(r.vz - o_Vz[o]);
                             const Real w2 = wx * wx + wy * wy + wz * wz;
                             Real FA, FB, Ar, Br;
@@ -1730,9 +1731,9 @@ __device__ __forceinline__ Real pair_P(double d2, double dh, double gh, double v
                                        uint32_t step, uint32_t box, uint32_t k0, uint32_t k1, const float4* gtab,
                                        Real urel[3])
 {
+    U4 r = philox_block(i, j, step, kTagGasVel, box, k0, k1);
     Real g = EXACT_G ? overlap_g_exact<Real>(sqrt_real(Real(d2)), Real(dh), Real(gh))
                      : Real(overlap_g_table(gtab, d2, dh, gh));
-    U4 r = philox_block(i, j, step, kTagGasVel, box, k0, k1);
     Real z[3];
     normals3<Real>(r, z);
     urel[0] = Real(vx - Vx) - vs * z[0];
@@ -1865,6 +1866,8 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
                 if (live) {
                     const uint32_t pqv = S.pq[sl];
                     const int64_t q = int64_t(pqv & 0x7fffffffu);
+                    // the pair's gas record, issued before the distance work that hides its latency
+                    const GasRec<Real> r = reinterpret_cast<const GasRec<Real>*>(a.grec)[q];
                     const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
                     const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, (pqv >> 31) != 0u, G.L);
                     const double hs = o_h[o] + qh;
@@ -1878,7 +1881,6 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
                     if (d2 < hs2) {
                         npairs++;
                         Real urel[3];
-                        const GasRec<Real> r = reinterpret_cast<const GasRec<Real>*>(a.grec)[q];
                         const Real P = pair_P<Real, N, EXACT_G>(d2, o_h[o], qh, o_vx[o], o_vy[o], o_vz[o], r.Vx, r.Vy,
                                                                 r.Vz, r.vs, r.K, o_dt[o], o_id[o], r.perm, step, a.box,
                                                                 a.k0, a.k1, a.gtab, urel);
