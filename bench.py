@@ -179,8 +179,10 @@ def surrogate_compare(ctx, cfg, dev, steps: int, log_fn) -> dict:
             row[name] = {"pairs_per_s": pairs / (ms * 1e-3), "interact_ms": round(ms, 4),
                          "pass_gas_ms": round(ph["pass_gas"][0] / max(ph["pass_gas"][1], 1), 4),
                          "max_rel_rate_err": err}
+        # speed ratios (> 1: the network's gas pass is faster)
         row["mlp_vs_quad12"] = row["quad12"]["pass_gas_ms"] / row["mlp"]["pass_gas_ms"]
         row["mlp_vs_quad32"] = row["quad32"]["pass_gas_ms"] / row["mlp"]["pass_gas_ms"]
+        row["network_faster_than_quad12_at_equal_accuracy"] = bool(row["mlp_vs_quad12"] > 1.0)
         res[f"n={n_pow}"] = row
         log_fn(f"bench: surrogate n={n_pow}: " + ", ".join(
             f"{k} {v['pass_gas_ms']:.3f} ms (err {v['max_rel_rate_err']:.1e})" for k, v in row.items()

@@ -218,10 +218,14 @@ def test_mlp_step_small_galaxy(ctx, trained, n_pow):
     assert ke <= 2e-5
 
 
-def test_surrogate_gain(ctx, trained):
+def test_surrogate_cost_against_quadrature(ctx, trained):
     """Gas-pass time on a 250 000 gas + 1 000 000 DM galaxy with sigma ~ v^-2:
-    network rates vs quadrature at K = 32 (1e-10 level) and at K = 12 (the
-    smallest K at the 1e-3 level), and the closed forms for reference."""
+    network rates against quadrature at K = 32 (1e-10 level) and at K = 12
+    (the smallest K at the network's 1e-3 level), and the closed forms for
+    reference.  The network is cheaper than the K = 32 quadrature but not than
+    the K = 12 one that meets the same 1e-3 bar: at equal accuracy it brings
+    no speed gain here, which the log line records (network / K = 12 time
+    above 1).  Only the K = 32 ordering is asserted."""
     import torch
     import paper_2603_24688_amd as dmb
     ctx.mlp_set_params(trained["params"])
@@ -244,7 +248,7 @@ def test_surrogate_gain(ctx, trained):
         ctx.profile_enable(False)
         res[name] = ph["pass_gas"][0] / max(ph["pass_gas"][1], 1)
     pairs = dmb.counters_dict(out["counters"])["pairs_gas"]
-    _log("[gain] gas pass ms: " + ", ".join(f"{k} {v:.3f}" for k, v in res.items()) +
-         f"; pairs {pairs}; network vs quad32 x{res['quad32'] / res['mlp']:.2f}, vs quad12 "
-         f"x{res['quad12'] / res['mlp']:.2f}")
+    _log("[surrogate cost] gas pass ms: " + ", ".join(f"{k} {v:.3f}" for k, v in res.items()) +
+         f"; pairs {pairs}; network time / K=32 quadrature {res['mlp'] / res['quad32']:.2f}, "
+         f"/ K=12 quadrature {res['mlp'] / res['quad12']:.2f}")
     assert res["mlp"] < res["quad32"]
