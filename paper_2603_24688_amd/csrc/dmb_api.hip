@@ -98,6 +98,12 @@ struct dmb_ctx {
     DevBuf bstep, bgeom, bitem;            // batched step: Philox step offset, per-box pass arguments, item offsets
     Scratch heap;                          // per-call scratch of the entry points that allocate
     Scratch* S = &heap;                    // scratch set in use (dmb_step_static swaps in its own)
+    // the build runs the gas species' chain on a second stream beside the DM chain on the
+    // caller's stream (fork and join by events); that chain has a scratch set of its own
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    Scratch heap2;
+    Scratch* S2 = &heap2;
     DevBuf os_err;                         // radix sort: raised when a look-back wait gave up (sticky)
     // pair export (dmb_pair_list): destination lists, capacity
     uint32_t* pair_dst[2] = {nullptr, nullptr};
@@ -1223,6 +1229,14 @@ dmb_status dmb_create(dmb_ctx** out, int device, void* hip_stream)
         return DMB_EHIP;
     }
     c->static_ptr = static_cast<char*>(sp);
+    he = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (he != hipSuccess) {
+        snprintf(g_create_err, sizeof(g_create_err), "build side stream: %s", hipGetErrorString(he));
+        dmb_destroy(c);
+        return DMB_EHIP;
+    }
     he = hipHostMalloc(reinterpret_cast<void**>(&c->run_dt_host), sizeof(double));
     if (he == hipSuccess) he = hipHostMalloc(reinterpret_cast<void**>(&c->rb_host), kReadbackMax * sizeof(uint64_t));
     if (he != hipSuccess) {
@@ -1263,6 +1277,7 @@ dmb_status dmb_destroy(dmb_ctx* c)
     hipSetDevice(c->device);
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
+    if (c->side) hipStreamSynchronize(c->side);
     free_cells(c->cells);
     for (Cells* X : c->boxes) {
         free_cells(*X);
@@ -1271,6 +1286,13 @@ dmb_status dmb_destroy(dmb_ctx* c)
     c->boxes.clear();
     auto fr = [](DevBuf& b) { if (b.p) hipFree(b.p); b.p = nullptr; b.cap = 0; };
     for (auto& b : c->heap.scan_tmp) fr(b);
+    for (auto& b : c->heap2.scan_tmp) fr(b);
+    DevBuf* side_bufs[] = {&c->heap2.os_hist, &c->heap2.os_status, &c->heap2.bbox_part, &c->heap2.counters_local,
+                           &c->heap2.pair_cnt, &c->heap2.rb_dev};
+    for (DevBuf* b : side_bufs) fr(*b);
+    if (c->side) hipStreamDestroy(c->side);
+    if (c->ev_fork) hipEventDestroy(c->ev_fork);
+    if (c->ev_join) hipEventDestroy(c->ev_join);
     for (auto& p : c->pending) { c->ev_pool.push_back(p.a); c->ev_pool.push_back(p.b); }
     for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
     DevBuf* mlp[] = {&c->mlp_p, &c->mlp_m, &c->mlp_v, &c->mlp_blob, &c->mlp_part, &c->mlp_red, &c->mlp_ts,
@@ -1384,6 +1406,50 @@ dmb_status readback(dmb_ctx* c, const Readback& r, uint64_t* out)
 }
 
 // Cell structure of one box into c->X (arguments already checked).
+// Work enqueued inside an OnSide scope goes to the side stream with the side
+// scratch set; fork() makes the side stream wait for the caller's stream so
+// far, join() the caller's stream for the side stream.
+struct OnSide {
+    dmb_ctx* c;
+    hipStream_t st;
+    Scratch* sc;
+    explicit OnSide(dmb_ctx* c_) : c(c_), st(c_->stream), sc(c_->S) { c->stream = c->side; c->S = c->S2; }
+    ~OnSide() { c->stream = st; c->S = sc; }
+};
+
+dmb_status fork(dmb_ctx* c)
+{
+    HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    return DMB_OK;
+}
+
+dmb_status join(dmb_ctx* c)
+{
+    HIPCHK(c, hipEventRecord(c->ev_join, c->side));
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    return DMB_OK;
+}
+
+// Runs a(gas side) on the side stream and b (DM side) on the caller's stream;
+// both are enqueued before either status is checked, and the join comes first.
+template <typename FA, typename FB>
+dmb_status both(dmb_ctx* c, FA&& a, FB&& b)
+{
+    dmb_status s = fork(c);
+    if (s != DMB_OK) return s;
+    dmb_status sa;
+    {
+        OnSide on(c);
+        sa = a();
+    }
+    dmb_status sb = b();
+    dmb_status sj = join(c);
+    if (sa != DMB_OK) return sa;
+    if (sb != DMB_OK) return sb;
+    return sj;
+}
+
 dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par)
 {
     dmb_status s;
@@ -1393,8 +1459,9 @@ dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_part
     for (int k = 0; k < 3; ++k) c->X->built_L[k] = periodic ? par->box[k] : 0.0;
     double Lh[4] = {c->X->built_L[0], c->X->built_L[1], c->X->built_L[2], 0.0};
     HIPCHK(c, hipMemcpyAsync(c->X->boxL.p, Lh, sizeof(Lh), hipMemcpyHostToDevice, c->stream));
-    if ((s = build_species(c, c->X->gas, gas)) != DMB_OK) return s;
-    if ((s = build_species(c, c->X->dm, dm)) != DMB_OK) return s;
+    Cells& X = *c->X;
+    s = both(c, [&] { return build_species(c, X.gas, gas); }, [&] { return build_species(c, X.dm, dm); });
+    if (s != DMB_OK) return s;
     // read back owner and sub-tile counts
     {
         Readback r;
@@ -1416,12 +1483,19 @@ dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_part
         c->X->dm.n_own = int64_t(v[2]);
         c->X->dm.ntile = int64_t(v[3]);
     }
-    if ((s = build_subtiles(c, c->X->gas)) != DMB_OK) return s;
-    if ((s = build_subtiles(c, c->X->dm)) != DMB_OK) return s;
-    if ((s = build_owner_tiles(c, c->X->gas)) != DMB_OK) return s;
-    if ((s = build_owner_tiles(c, c->X->dm)) != DMB_OK) return s;
-    if ((s = cand_count(c, c->X->gas, c->X->dm, c->X->gp)) != DMB_OK) return s;
-    if ((s = cand_count(c, c->X->dm, c->X->gas, c->X->dp)) != DMB_OK) return s;
+    s = both(
+        c,
+        [&] {
+            dmb_status t = build_subtiles(c, X.gas);
+            return t == DMB_OK ? build_owner_tiles(c, X.gas) : t;
+        },
+        [&] {
+            dmb_status t = build_subtiles(c, X.dm);
+            return t == DMB_OK ? build_owner_tiles(c, X.dm) : t;
+        });
+    if (s != DMB_OK) return s;
+    s = both(c, [&] { return cand_count(c, X.gas, X.dm, X.gp); }, [&] { return cand_count(c, X.dm, X.gas, X.dp); });
+    if (s != DMB_OK) return s;
     uint64_t npairs[2] = {0, 0};
     uint32_t maxcnt[2] = {0, 0};
     double hmax[2] = {0, 0};
@@ -1456,8 +1530,8 @@ dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_part
     }
     c->X->gp.npairs = int64_t(npairs[0]);
     c->X->dp.npairs = int64_t(npairs[1]);
-    if ((s = cand_subs(c, c->X->gas, c->X->dm, c->X->gp)) != DMB_OK) return s;
-    if ((s = cand_subs(c, c->X->dm, c->X->gas, c->X->dp)) != DMB_OK) return s;
+    s = both(c, [&] { return cand_subs(c, X.gas, X.dm, X.gp); }, [&] { return cand_subs(c, X.dm, X.gas, X.dp); });
+    if (s != DMB_OK) return s;
     uint64_t tot[2] = {0, 0};
     uint32_t nit[2] = {0, 0};
     {
@@ -1477,8 +1551,8 @@ dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_part
     }
     c->X->gp.total = int64_t(tot[0]); c->X->gp.nitems = nit[0];
     c->X->dp.total = int64_t(tot[1]); c->X->dp.nitems = nit[1];
-    if ((s = cand_write(c, c->X->gas, c->X->dm, c->X->gp)) != DMB_OK) return s;
-    if ((s = cand_write(c, c->X->dm, c->X->gas, c->X->dp)) != DMB_OK) return s;
+    s = both(c, [&] { return cand_write(c, X.gas, X.dm, X.gp); }, [&] { return cand_write(c, X.dm, X.gas, X.dp); });
+    if (s != DMB_OK) return s;
     // later builds keep every candidate of (almost) every tile in the count pass
     for (int k = 0; k < 2; ++k) {
         Pairs& P = k == 0 ? c->X->gp : c->X->dp;
@@ -1698,9 +1772,10 @@ dmb_status dmb_step_static(dmb_ctx* c, const dmb_particles* gas, const dmb_parti
     if (!c->static_ptr || !c->rb_host) return fail(c, DMB_EHIP, "step_static: no static scratch on this device");
     HIPCHK(c, hipSetDevice(c->device));
     // the static cell structure and scratch set, carved afresh from the static array
-    Scratch fresh;
+    Scratch fresh, fresh2;
     c->static_cells = Cells{};
     c->S = &fresh;
+    c->S2 = &fresh2;
     c->X = &c->static_cells;
     c->arena = c->static_ptr;
     c->arena_cap = kStaticScratchBytes;
@@ -1720,6 +1795,7 @@ dmb_status dmb_step_static(dmb_ctx* c, const dmb_particles* gas, const dmb_parti
     c->arena = nullptr;
     c->arena_cap = c->arena_off = 0;
     c->S = &c->heap;
+    c->S2 = &c->heap2;
     c->X = &c->cells;
     return s;
 }
