@@ -34,6 +34,11 @@ VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 # distance and test 25 + overlap 25 + closed-form rate terms 60 + binary64
 # accumulation 8.
 PAIR_ALGO_VALU = {"pass_dm": 195, "pass_gas": 118}
+# Algorithmic HBM bytes per particle of build_cells: position and h read
+# (32), Morton key and index written (12), four 8-bit radix passes over key
+# and index (4 x 24), sorted position and h written (32), less the reuse of the
+# key pass by the sub-tile cut: about 150 bytes.
+BUILD_ALGO_BYTES_PER_PARTICLE = 150
 
 
 def log(msg):
@@ -129,6 +134,18 @@ def cpu_baseline(cfg, seconds: float, pairs_per_step: int, seed: int = 0):
                       f"({c['pairs_gas']} + {c['pairs_dm']} pairs in {dt:.1f} s including the grid build of "
                       f"{t_build:.1f} s); a whole step is estimated as the build plus the per-owner time scaled "
                       f"to all owners: {t_full:.1f} s for {pairs_per_step} pairs"}
+
+
+def build_roofline(n_particles: int, build_ms) -> dict:
+    """build_cells against HBM: algorithmic bytes per step over the measured
+    build time (event-timed, both species, all stages)."""
+    if not build_ms:
+        return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None}
+    b = n_particles * BUILD_ALGO_BYTES_PER_PARTICLE
+    achieved = b / (build_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "build_ms": build_ms,
+            "algorithmic_bytes": b, "bytes_per_particle": BUILD_ALGO_BYTES_PER_PARTICLE}
 
 
 def surrogate_compare(ctx, cfg, dev, steps: int, log_fn) -> dict:
@@ -471,6 +488,7 @@ def main():
         "interact_only_pairs_per_s": pairs / (sum(v for k, v in per_kernel.items() if k != "build") * 1e-3),
         "hbm_algorithmic_GBps": bytes_step / (ms_step * 1e-3) / 1e9,
         "roofline": roof,
+        "build_roofline": build_roofline(desc["n_gas"] + desc["n_dm"], per_kernel.get("build")),
         "build_stats": bst,
         "hit_fraction": {"gas": pairs / max(1, bst["cand_pairs_gas"] * 4096),
                          "dm": pairs / max(1, bst["cand_pairs_dm"] * 4096)},
