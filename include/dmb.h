@@ -85,7 +85,7 @@ typedef struct {
 } dmb_particles;
 
 typedef struct {
-    double sigma0_cm2;      /* sigma(v) = sigma0 (v/c)^n, isotropic (Sec. 2.4) */
+    double sigma0_cm2;      /* total cross section sigma(v) = sigma0 (v/c)^n (Sec. 2.4) */
     int32_t n_pow;          /* n in {-4, -2, 0, 2} */
     double m_chi_g;         /* DM particle mass m_chi, g */
     double dt;              /* default timestep, kpc/(km/s) */
@@ -97,6 +97,12 @@ typedef struct {
     int32_t rates;          /* dmb_rates */
     int32_t quad_nodes;     /* K for DMB_RATES_QUAD (and the DMB_RATES_MLP fallback), 4..64; 0 => 32.
                                K >= 24 integrates over w/vs +- 8.5, smaller K over +- 5.5 */
+    double aniso_g;         /* angular shape of dsigma/dOmega = sigma(v) p(Omega) (Sec. 2.2-2.3): the
+                               Henyey-Greenstein law in the scattering angle theta of the relative
+                               velocity, mean cos theta = g, |g| < 1; 0 => isotropic.  The DM Monte
+                               Carlo uses sigma and draws theta from p; the gas mean field uses the
+                               momentum-transfer cross section sigma-bar = (1 - g) sigma (eq. scrA,
+                               scrB).  Errors: DMB_EINVAL unless |g| < 1. */
 } dmb_params;
 
 typedef struct {

@@ -308,6 +308,8 @@ typedef struct {
     uint32_t step;
     uint32_t box_id;
     double box[3];            /* periodic side lengths; 0 => open */
+    double aniso_g;           /* dsigma/dOmega = sigma(v) p(Omega): Henyey-Greenstein p with mean
+                                 cos theta = g (0: isotropic); sigma-bar = (1 - g) sigma */
 } orc_params;
 
 enum { ORC_C_PAIRS_GAS = 0, ORC_C_PAIRS_DM, ORC_C_SCATTERS, ORC_C_NEAR_BOUNDARY, ORC_C_NEAR_DECISION,
@@ -378,7 +380,9 @@ static void gas_one(const orc_particles *gas, const orc_particles *dm, const orc
     int gas_act = gas->active ? gas->active[j] : 1;
     if (gas_act) {
         double mu = gas_mu(gas, j), vs = gas_vs(gas, j);
-        double sig_kpc2 = par->sigma0_cm2 / (ORC_KPC_CM * ORC_KPC_CM);
+        /* the mean field takes the momentum-transfer cross section (eq. scrA, scrB):
+         * sigma-bar = int dOmega dsigma/dOmega (1 - cos theta) = (1 - g) sigma */
+        double sig_kpc2 = par->sigma0_cm2 / (ORC_KPC_CM * ORC_KPC_CM) * (1.0 - par->aniso_g);
         double cfac = sig_kpc2 * pow(ORC_C_KMS, -par->n_pow);
         double redm = mu / (par->m_chi_g + mu);
         int64_t nc = cand ? ncand : dm->n;
@@ -442,6 +446,32 @@ static double pair_P(const orc_particles *gas, const orc_particles *dm, const or
 }
 
 typedef struct { int64_t j; double P; double urel[3]; } orc_pair;
+
+/* Henyey-Greenstein scattering angle (Sec. 2.2-2.3 with p(Omega) of mean
+ * cos theta = g): the density of c = cos theta is (1 - g^2) / (2 (1 + g^2 -
+ * 2 g c)^{3/2}) on [-1, 1]; its CDF F(c) = (1 - g^2) / (2g) [(1 + g^2 -
+ * 2 g c)^{-1/2} - 1/(1 + g)] set equal to u and solved for c.  Written as a
+ * ratio of polynomials in t = 2u - 1 (no division by g), so g -> 0 gives t.
+ * sin theta from 1 - c^2 in factored form, 4 (1 - g^2)^2 u (1 - u)
+ * (1 - g + g u) (1 + g u) / (1 + g t)^4, accurate where c is near +-1.     */
+static void hg_inverse_cdf(double g, double u, double *ct, double *st)
+{
+    double t = 2.0 * u - 1.0, den = 1.0 + g * t;
+    double c = (2.0 * t + g * (t * t + 3.0) + 2.0 * g * g * t + g * g * g * (t * t - 1.0)) / (2.0 * den * den);
+    *ct = fmax(-1.0, fmin(1.0, c));
+    double p = u * (1.0 - u) * (1.0 - g + g * u) * (1.0 + g * u);
+    *st = 2.0 * (1.0 - g * g) * sqrt(fmax(0.0, p)) / (den * den);
+}
+
+/* Unit vectors e1, e2 perpendicular to the unit vector n and to each other
+ * (Duff et al., Building an orthonormal basis, revisited, JCGT 2017). */
+static void basis_around(const double n[3], double e1[3], double e2[3])
+{
+    double sg = n[2] >= 0.0 ? 1.0 : -1.0;
+    double a = -1.0 / (sg + n[2]), b = n[0] * n[1] * a;
+    e1[0] = 1.0 + sg * n[0] * n[0] * a; e1[1] = sg * b; e1[2] = -sg * n[0];
+    e2[0] = b; e2[1] = sg + n[1] * n[1] * a; e2[2] = -n[1];
+}
 
 static int cmp_pair(const void *x, const void *y)
 {
@@ -528,9 +558,20 @@ static void dm_one(const orc_particles *gas, const orc_particles *dm, const orc_
         if (vrel > 0.0) {
             double ua[4];
             orc_block(par->seed, (uint32_t)i, (uint32_t)jstar, par->step, 1u, par->box_id, ua);
-            double ct = 2.0 * ua[0] - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
             double ph = 2.0 * ORC_PI * ua[1];
-            double nn[3] = {st * cos(ph), st * sin(ph), ct};
+            double nn[3];
+            if (par->aniso_g == 0.0) {
+                /* isotropic: the new direction itself, cos theta about the z axis */
+                double ct = 2.0 * ua[0] - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
+                nn[0] = st * cos(ph); nn[1] = st * sin(ph); nn[2] = ct;
+            } else {
+                /* scattering angle theta about the incoming relative velocity, from p(Omega) */
+                double uh[3] = {ur[0] / vrel, ur[1] / vrel, ur[2] / vrel}, e1[3], e2[3];
+                double ct, st;
+                hg_inverse_cdf(par->aniso_g, ua[0], &ct, &st);
+                basis_around(uh, e1, e2);
+                for (int k = 0; k < 3; k++) nn[k] = ct * uh[k] + st * (cos(ph) * e1[k] + sin(ph) * e2[k]);
+            }
             double mu = gas_mu(gas, jstar);
             double fr = mu / (par->m_chi_g + mu);
             for (int k = 0; k < 3; k++) out->dv_dm[3 * i + k] = fr * vrel * (nn[k] - ur[k] / vrel);

@@ -717,7 +717,9 @@ GasPassArgs gas_pass_args(dmb_ctx* c, Cells& X, const dmb_particles* gas, const 
     }
     a.part = X.part_gas.as<double>();
     a.perm = G.perm; a.mass = gas->mass; a.mu = gas->mu; a.dt = gas->dt; a.dt_default = par->dt;
-    a.m_chi = par->m_chi_g; a.sig_kpc2_cn = sig_kpc2_cn_of(par); a.dp = out->dp_gas; a.de = out->de_gas;
+    // the gas rates take the momentum-transfer cross section sigma-bar = (1 - g) sigma
+    a.m_chi = par->m_chi_g; a.sig_kpc2_cn = sig_kpc2_cn_of(par) * (1.0 - par->aniso_g);
+    a.dp = out->dp_gas; a.de = out->de_gas;
     return a;
 }
 
@@ -728,7 +730,7 @@ void combine_gas(dmb_ctx* c, Cells& X, const dmb_particles* gas, const dmb_param
     cb.n_own = G.n_own; cb.own = G.own.as<const uint32_t>(); cb.perm = G.perm;
     cb.item_off = X.gp.ioff.as<const uint32_t>(); cb.part = X.part_gas.as<const double>();
     cb.mass = gas->mass; cb.mu = gas->mu; cb.dt = gas->dt; cb.dt_default = par->dt; cb.m_chi = par->m_chi_g;
-    cb.sig_kpc2_cn = sig_kpc2_cn_of(par); cb.dp = out->dp_gas; cb.de = out->de_gas;
+    cb.sig_kpc2_cn = sig_kpc2_cn_of(par) * (1.0 - par->aniso_g); cb.dp = out->dp_gas; cb.de = out->de_gas;
     hipLaunchKernelGGL(k_combine_gas, dim3(unsigned((G.n_own + kTile - 1) / kTile)), dim3(64 * kCombineWaves), 0,
                        c->stream, cb);
 }
@@ -779,6 +781,7 @@ void combine_dm_and_resolve(dmb_ctx* c, Cells& X, const DmPassArgs& a, const dmb
     r.grec = a.grec;
     r.gas_vel = gas->vel; r.gas_u = gas->u; r.gas_mu = gas->mu; r.m_chi = par->m_chi_g;
     r.gtab = a.gtab; r.k0 = a.k0; r.k1 = a.k1; r.step = a.step; r.box = a.box; r.step_off = a.step_off;
+    r.aniso_g = par->aniso_g;
     r.n_gas_bits = bits_for(std::max<int64_t>(G.n, 2));
     r.n_gas = uint32_t(G.n);
     r.scount = a.scount; r.slist = X.slist.as<const uint32_t>();
@@ -1590,6 +1593,7 @@ dmb_status check_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles*
     if (par->rates != DMB_RATES_EXACT && (quad_k(par) < 4 || quad_k(par) > kMaxQuadNodes))
         return fail(c, DMB_EINVAL, "quad_nodes %d outside 4..%d", par->quad_nodes, kMaxQuadNodes);
     if (!(par->m_chi_g > 0.0) || !(par->sigma0_cm2 >= 0.0)) return fail(c, DMB_EINVAL, "bad m_chi or sigma0");
+    if (!(std::fabs(par->aniso_g) < 1.0)) return fail(c, DMB_EINVAL, "aniso_g %g outside (-1, 1)", par->aniso_g);
     return DMB_OK;
 }
 }  // namespace
@@ -2207,6 +2211,7 @@ dmb_status batch_step_checked(dmb_ctx* c, int32_t nbox, const dmb_particles* gas
             quad_k(&p) != quad_k(&p0))
             return fail(c, DMB_EINVAL, "box %d: n_pow, precision, rates and quad_nodes must agree across boxes", b);
         if (!(p.m_chi_g > 0.0) || !(p.sigma0_cm2 >= 0.0)) return fail(c, DMB_EINVAL, "box %d: bad m_chi or sigma0", b);
+        if (!(std::fabs(p.aniso_g) < 1.0)) return fail(c, DMB_EINVAL, "box %d: aniso_g %g outside (-1, 1)", b, p.aniso_g);
         const Cells& X = *c->boxes[b];
         if (gas[b].n != X.built_ngas || dm[b].n != X.built_ndm)
             return fail(c, DMB_ESTALE, "box %d: sizes differ from the last batch build", b);

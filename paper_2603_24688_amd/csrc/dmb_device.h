@@ -261,6 +261,37 @@ __device__ __forceinline__ void normals3(U4 r, T z[3])
 }
 
 // ---------------------------------------------------------------------------
+// Anisotropic scattering (Sec. 2.2-2.3: dsigma/dOmega = sigma(v) p(Omega)).
+// cos theta of the Henyey-Greenstein law p(c) = (1 - g^2) / (2 (1 + g^2 - 2 g c)^{3/2})
+// (mean g) from a uniform u by its inverse CDF, and sin theta.  With t = 2u - 1
+// the inverse c = (1 + g^2 - s^2) / (2g), s = (1 - g^2) / (1 - g + 2 g u),
+// expands to (2t + g (t^2 + 3) + 2 g^2 t + g^3 (t^2 - 1)) / (2 (1 + g t)^2), free
+// of the cancellation at small g (g = 0 gives t); and 1 - c^2 factors into
+// 4 (1 - g^2)^2 u (1 - u) (1 - g + g u) (1 + g u) / (1 + g t)^4, so sin theta
+// keeps its relative accuracy where c is within rounding of +-1.
+template <typename T>
+__device__ __forceinline__ void hg_angle(T g, T u, T* ct, T* st)
+{
+    const T t = T(2) * u - T(1), d = T(1) + g * t;
+    const T c = (T(2) * t + g * (t * t + T(3)) + T(2) * g * g * t + g * g * g * (t * t - T(1))) / (T(2) * d * d);
+    *ct = c < T(-1) ? T(-1) : (c > T(1) ? T(1) : c);
+    const T p = u * (T(1) - u) * (T(1) - g + g * u) * (T(1) + g * u);
+    *st = T(2) * (T(1) - g * g) * sqrt_real(p > T(0) ? p : T(0)) / (d * d);
+}
+
+// Orthonormal e1, e2 with (e1, e2, n) right-handed for a unit n (the
+// branch-free construction of Duff et al., J. Comput. Graph. Tech. 6(1), 2017).
+template <typename T>
+__device__ __forceinline__ void orthonormal_frame(const T n[3], T e1[3], T e2[3])
+{
+    const T sg = n[2] >= T(0) ? T(1) : T(-1);
+    const T a = T(-1) / (sg + n[2]);
+    const T b = n[0] * n[1] * a;
+    e1[0] = T(1) + sg * n[0] * n[0] * a; e1[1] = sg * b; e1[2] = -sg * n[0];
+    e2[0] = b; e2[1] = sg + n[1] * n[1] * a; e2[2] = -n[1];
+}
+
+// ---------------------------------------------------------------------------
 // Rate functions (Appendix B): for sigma-bar = sigma0 (v/c)^n,
 //   A = alpha_n/3 vs^{n+1} 1F1(-(n+1)/2, 5/2, -x),
 //   B = alpha_n   vs^{n+3} 1F1(-(n+3)/2, 3/2, -x),  x = w^2/(2 vs^2).

@@ -2075,6 +2075,7 @@ struct ResolveArgs {
     const void* grec;                                         // GasRec<Real>, sorted gas
     const double* gas_vel; const double* gas_u; const double* gas_mu;   // raw gas inputs (partner kick)
     double m_chi;
+    double aniso_g;               // Henyey-Greenstein asymmetry of the scattering angle (0: isotropic)
     const float4* gtab;
     uint32_t k0, k1, step, box;
     const uint32_t* step_off;     // nullable: device offset added to step
@@ -2299,15 +2300,28 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
             double dvx = 0.0, dvy = 0.0, dvz = 0.0;
             if (vrel > Real(0)) {
                 U4 r2 = philox_block(oid, j, step, kTagDir, a.box, a.k0, a.k1);
-                Real ct = Real(2) * u24<Real>(r2.x) - Real(1);
-                Real st = sqrt_real(fmax(Real(0), Real(1) - ct * ct));
                 Real sp_, cp_;
                 sincos_turns(u24<Real>(r2.y), &sp_, &cp_);
                 Real iv = Real(1) / vrel;
                 Real f = rr * vrel;
-                dvx = double(f * (st * cp_ - ux * iv));
-                dvy = double(f * (st * sp_ - uy * iv));
-                dvz = double(f * (ct - uz * iv));
+                Real n[3];
+                if (a.aniso_g == 0.0) {
+                    // isotropic: the new direction directly, cos theta about the z axis
+                    const Real ct = Real(2) * u24<Real>(r2.x) - Real(1);
+                    const Real st = sqrt_real(fmax(Real(0), Real(1) - ct * ct));
+                    n[0] = st * cp_; n[1] = st * sp_; n[2] = ct;
+                } else {
+                    // cos theta from p(Omega), about the incoming relative velocity
+                    const Real uh[3] = {ux * iv, uy * iv, uz * iv};
+                    Real ct, st;
+                    hg_angle(Real(a.aniso_g), u24<Real>(r2.x), &ct, &st);
+                    Real e1[3], e2[3];
+                    orthonormal_frame(uh, e1, e2);
+                    for (int k = 0; k < 3; ++k) n[k] = ct * uh[k] + st * (cp_ * e1[k] + sp_ * e2[k]);
+                }
+                dvx = double(f * (n[0] - ux * iv));
+                dvy = double(f * (n[1] - uy * iv));
+                dvz = double(f * (n[2] - uz * iv));
             }
             a.dv[3 * int64_t(oid)] = dvx;
             a.dv[3 * int64_t(oid) + 1] = dvy;

@@ -189,6 +189,19 @@ def test_box_high_sigma(ctx, orc, precision):
     assert ref["counters"]["scatters"] > 200
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("g", [0.6, -0.4])
+def test_box_anisotropic_scattering(ctx, orc, precision, g):
+    """Sec. 2.2-2.3, dsigma/dOmega = sigma(v) p(Omega) with the Henyey-Greenstein
+    p of mean cos theta = g: the Monte Carlo draws with sigma and turns the
+    relative velocity by an angle from p about its incoming direction, the
+    mean field uses sigma-bar = (1 - g) sigma.  Many scatters per step."""
+    cfg = workloads.box(n_gas=1500, n_dm=1300, seed=(18, 3), sigma0_cm2=3e-22)
+    cfg["params"]["aniso_g"] = g
+    gpu, ref = _check_step(ctx, orc, cfg, precision, f"box-aniso g={g}")
+    assert ref["counters"]["scatters"] > 200
+
+
 @pytest.mark.parametrize("n_pow", [-4, -2, 2])
 def test_box_velocity_dependent(ctx, orc, n_pow):
     cfg = workloads.box(n_gas=1200, n_dm=1000, seed=(4, n_pow + 10), n_pow=n_pow,
@@ -305,6 +318,9 @@ def test_invalid_arguments(ctx):
     bad = dict(par, n_pow=1)
     with pytest.raises(dmb.DmbError, match="EINVAL"):
         ctx.interact_step(G, D, bad, out)
+    for g in (1.0, -1.0, float("nan")):
+        with pytest.raises(dmb.DmbError, match="EINVAL"):
+            ctx.interact_step(G, D, dict(par, aniso_g=g), out)
     big = dict(cfg["gas"])
     big["h"] = np.full(200, 0.3)
     with pytest.raises(dmb.DmbError, match="ERANGE"):

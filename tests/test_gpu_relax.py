@@ -12,6 +12,8 @@ relaxation of Appendix F (oracle/relax.py).
   stays close to Maxwell-Boltzmann (max JB <~ 0.01, the paper's criterion)
   the gas tracks the relaxation; in every case total momentum is conserved
   within the scatter noise and the two species approach each other.
+- Anisotropic scattering: the box relaxes with the momentum-transfer cross
+  section sigma-bar = (1 - g) sigma, not with sigma (Sec. 2.3).
 - Timestep control (eq. prob_criterion): with a step far too long for the
   criterion, the controlled run lowers dt after the first step and keeps the
   criterion afterwards; the uncontrolled run breaks it every step.
@@ -57,9 +59,10 @@ def run_box(ctx, cfg, nsteps=100, control=True, safety=0.5):
     return diag, G, D
 
 
-def ode_for(cfg, diag):
+def ode_for(cfg, diag, sigma_bar=None):
     """The relaxation from the run's initial state, at the run's times:
-    columns (V_X, V_B, s_X^2, s_B^2) along x."""
+    columns (V_X, V_B, s_X^2, s_B^2) along x.  The relaxation rates carry the
+    momentum-transfer cross section, sigma-bar = (1 - g) sigma (Sec. 2.3)."""
     from oracle import relax
     L = cfg["params"]["box"][0]
     rho_b = cfg["gas"]["mass"].sum() / L ** 3
@@ -67,7 +70,9 @@ def ode_for(cfg, diag):
     st0 = [diag[0, _col("v_dm_x")], diag[0, _col("v_gas_x")], diag[0, _col("s2_dm")], diag[0, _col("s2_gas")]]
     t = diag[:, _col("time")]
     par = cfg["params"]
-    _, y = relax.evolve(st0, t[-1], rho_b, rho_x, par["sigma0_cm2"], par["n_pow"], par["m_chi_g"], MU, t_eval=t)
+    if sigma_bar is None:
+        sigma_bar = par["sigma0_cm2"] * (1.0 - par.get("aniso_g", 0.0))
+    _, y = relax.evolve(st0, t[-1], rho_b, rho_x, sigma_bar, par["n_pow"], par["m_chi_g"], MU, t_eval=t)
     return y
 
 
@@ -162,6 +167,28 @@ def test_table3_variants(ctx, name):
             assert eVB <= 0.05
         if abs(dT0) > 20 * mx * noise_s2:
             assert eSB <= 0.05
+
+
+@pytest.mark.parametrize("g", [0.6, -0.5])
+def test_anisotropic_box_relaxes_with_sigma_bar(ctx, g):
+    """Anisotropic scattering (Henyey-Greenstein p(Omega), mean cos theta = g):
+    the DM scatter with the total cross section and the gas takes the
+    momentum-transfer one, and the box relaxes as the Appendix F system with
+    sigma-bar = (1 - g) sigma does; the same system on sigma is rejected."""
+    cfg = workloads.box(seed=(1, 1))
+    cfg["params"]["aniso_g"] = g
+    diag, _, _ = run_box(ctx, cfg)
+    sim = sim_state(diag)
+    res = {}
+    for name, sb in (("sigma-bar", None), ("sigma", cfg["params"]["sigma0_cm2"])):
+        ode = ode_for(cfg, diag, sb)
+        chVB, chSB = abs(ode[-1, 1] - ode[0, 1]), abs(ode[-1, 3] - ode[0, 3])
+        res[name] = (np.max(np.abs(sim[:, 1] - ode[:, 1])) / chVB, np.max(np.abs(sim[:, 3] - ode[:, 3])) / chSB)
+    _log(f"[aniso g={g}] scatters {int(diag[:, _col('scatters')].sum())}, max JB {diag[:, _col('jb_dm')].max():.4f}; "
+         f"gas against the relaxation on sigma-bar: V_B err {res['sigma-bar'][0]:.3f}, s_B^2 err "
+         f"{res['sigma-bar'][1]:.3f} of change; on sigma: {res['sigma'][0]:.3f}, {res['sigma'][1]:.3f}")
+    assert max(res["sigma-bar"]) <= 0.03
+    assert max(res["sigma"]) >= 0.2
 
 
 def test_timestep_control(ctx):

@@ -415,13 +415,18 @@ def test_categorical_draw_frequencies(orc):
     assert chi2.sf(stat, 5) > 1e-4
 
 
-@pytest.mark.parametrize("n_pow,sigma0", [(0, 6e-23), (-2, 6e-23 * (299792.458 / 60) ** -2)])
-def test_mc_matches_mean_field_in_expectation(orc, n_pow, sigma0):
+@pytest.mark.parametrize("n_pow,sigma0,g", [(0, 6e-23, 0.0), (-2, 6e-23 * (299792.458 / 60) ** -2, 0.0),
+                                            (0, 6e-23, 0.6), (0, 6e-23, -0.5)])
+def test_mc_matches_mean_field_in_expectation(orc, n_pow, sigma0, g):
     """Appendix C: per pair, M_i E[dv_i] + dp_j = 0 and E[dE_i] + dE_j + V_j.dp_j
     = 0.  The Monte Carlo mean over many Philox steps agrees with the
-    deterministic mean field within 4 standard errors."""
+    deterministic mean field within 4 standard errors.  With anisotropic
+    scattering (g != 0) the Monte Carlo draws with the total cross section
+    and angles from p(Omega), the mean field uses sigma-bar = (1 - g) sigma
+    (Sec. 2.3); the mean field built on sigma instead is rejected."""
     gas, dm, par = _pair_system(sigma0, seed=2)
     par["n_pow"] = n_pow
+    par["aniso_g"] = g
     S = 20000
     dvs = np.zeros((S, 3))
     dEs = np.zeros(S)
@@ -440,6 +445,39 @@ def test_mc_matches_mean_field_in_expectation(orc, n_pow, sigma0):
     assert np.all(np.abs(m + dp) < 4 * se + 1e-12 * np.abs(dp).max())
     assert abs(dEs.mean() + dE) < 4 * dEs.std() / math.sqrt(S)
     assert res["counters"]["scatters"] in (0, 1)
+    if g != 0.0:
+        # the test has the power to see a mean field on the total cross section
+        iso = orc.step(gas, dm, dict(par, aniso_g=0.0))["dp_gas"][0]
+        assert np.abs(m + iso).max() > 8 * se.max()
+
+
+@pytest.mark.parametrize("g", [0.7, -0.4, 0.05])
+def test_anisotropic_scattering_angles(orc, g):
+    """Sec. 2.2-2.3, dsigma/dOmega = sigma p(Omega) with the Henyey-Greenstein
+    p of mean cos theta = g: every scatter turns the relative velocity by an
+    angle whose cosine follows the law's CDF (Kolmogorov-Smirnov) with mean g,
+    and keeps its magnitude (eq. scatter_chi).  Cold gas, so the incoming
+    relative velocity is known; a cross section that makes every step scatter."""
+    from scipy.stats import kstest
+    gas, dm, par = _pair_system(1e-15, seed=3)
+    gas["u"] = np.zeros(1)
+    par["aniso_g"] = g
+    mu = workloads.M_P
+    fr = mu / (par["m_chi_g"] + mu)
+    u_in = dm["vel"][0] - gas["vel"][0]
+    v = np.linalg.norm(u_in)
+    cos = []
+    for s in range(3000):
+        par["step"] = s
+        res = orc.step(gas, dm, par)
+        assert res["partner"][0] == 0
+        u_out = u_in + res["dv_dm"][0] / fr          # dv = fr (|u| n - u)
+        assert abs(np.linalg.norm(u_out) / v - 1) < 1e-12
+        cos.append(u_out @ u_in / (v * v))
+    cos = np.array(cos)
+    cdf = lambda c: (1 - g * g) / (2 * g) * (1 / np.sqrt(1 + g * g - 2 * g * c) - 1 / (1 + g))
+    assert kstest(cos, cdf).pvalue > 1e-3
+    assert abs(cos.mean() - g) < 4 * cos.std() / np.sqrt(len(cos))
 
 
 def test_step_outputs_structure(orc):
