@@ -44,7 +44,7 @@ class Particles(C.Structure):
 class Params(C.Structure):
     _fields_ = [("sigma0_cm2", C.c_double), ("n_pow", C.c_int), ("m_chi_g", C.c_double),
                 ("dt", C.c_double), ("seed", C.c_uint64), ("step", C.c_uint32), ("box_id", C.c_uint32),
-                ("box", C.c_double * 3), ("aniso_g", C.c_double)]
+                ("box", C.c_double * 3), ("aniso_g", C.c_double), ("gas_closure", C.c_int)]
 
 
 class Out(C.Structure):
@@ -194,7 +194,7 @@ def _params(p: dict) -> Params:
     return Params(float(p["sigma0_cm2"]), int(p.get("n_pow", 0)), float(p["m_chi_g"]), float(p["dt"]),
                   int(p["seed"]) & 0xFFFFFFFFFFFFFFFF, int(p.get("step", 0)) & 0xFFFFFFFF,
                   int(p.get("box_id", 0)), (C.c_double * 3)(*[float(b) for b in box]),
-                  float(p.get("aniso_g", 0.0)))
+                  float(p.get("aniso_g", 0.0)), 1 if p.get("rates") == 3 else 0)
 
 
 def step(gas: dict, dm: dict, params: dict, gas_sel=None, dm_sel=None, peak_scale=False, grid=False) -> dict:

@@ -310,6 +310,7 @@ typedef struct {
     double box[3];            /* periodic side lengths; 0 => open */
     double aniso_g;           /* dsigma/dOmega = sigma(v) p(Omega): Henyey-Greenstein p with mean
                                  cos theta = g (0: isotropic); sigma-bar = (1 - g) sigma */
+    int gas_closure;          /* 1: each gas takes the per-gas Maxwellian closure of its DM neighbours */
 } orc_params;
 
 enum { ORC_C_PAIRS_GAS = 0, ORC_C_PAIRS_DM, ORC_C_SCATTERS, ORC_C_NEAR_BOUNDARY, ORC_C_NEAR_DECISION,
@@ -371,9 +372,16 @@ static double nsum_get(const orc_sum *a) { return a->s + a->c; }
  * (the internal-energy change; the bulk-kinetic part is V_j . dp).  Sums run
  * over DM in index order, compensated.  cand: ascending DM candidates (NULL:
  * every DM particle).                                                       */
+static uint64_t gas_closure_one(const orc_particles *gas, const orc_particles *dm, const orc_params *par,
+                                int64_t j, const int64_t *cand, int64_t ncand, orc_out *out);
+
 static void gas_one(const orc_particles *gas, const orc_particles *dm, const orc_params *par, int64_t j,
                     const int64_t *cand, int64_t ncand, orc_out *out, uint64_t *npairs)
 {
+    if (par->gas_closure) {
+        *npairs += gas_closure_one(gas, dm, par, j, cand, ncand, out);
+        return;
+    }
     orc_sum sp[3] = {{0, 0}, {0, 0}, {0, 0}}, se = {0, 0};
     double ap[3] = {0, 0, 0}, ae = 0, apk = 0;
     uint64_t np = 0;
@@ -418,6 +426,81 @@ static void gas_one(const orc_particles *gas, const orc_particles *dm, const orc
     if (out->de_abs) out->de_abs[j] = sc * ae;
     if (out->pk_abs) out->pk_abs[j] = sc * apk;
     *npairs += np;
+}
+
+/* Per-gas Maxwellian closure (Appendix F applied per gas particle): the DM
+ * around gas j are taken as one Maxwellian population with the kernel-weighted
+ * density rho_j = sum_i M_i g_ij, drift W_j = sum_i M_i g_ij w_ij / rho_j and
+ * 1-D dispersion s_X^2 = (sum_i M_i g_ij |w_ij|^2 / rho_j - |W_j|^2) / 3, with
+ * w_ij = v_i - V_j over the pairs d_ij < h_i + h_j.  The two-population rates
+ * at the combined dispersion vth^2 = varsigma_j^2 + s_X^2 then give
+ *   dp_j = M_j dt S_j rho_j A(W_j; vth) W_j,
+ *   dE_j = M_j dt S_j rho_j [B (m_X s_X^2 - mu varsigma_j^2)/(m_X + mu)
+ *                            + A varsigma_j^2 |W_j|^2] / vth^2,
+ * S_j = sigma-bar_0 c^-n / (m_X + mu), the Maxwellian average of the per-pair
+ * terms of eq. gas-dVdt / gas-dTdt.  Sums are compensated, in DM-index order.
+ * dp_abs / de_abs are condition scales: for dp, f A sum_i M_i g_ij |w_ij,k| /
+ * rho (the magnitudes of the summed momentum terms, as for the per-pair mean
+ * field); for dE, the magnitudes of its three terms times max(1, <|w|^2> /
+ * vth^2), the factor by which the cancellation in s_X^2 = (<|w|^2> - |W|^2)/3
+ * magnifies a relative change of the moments (<.> the kernel-weighted mean). */
+static uint64_t gas_closure_one(const orc_particles *gas, const orc_particles *dm, const orc_params *par,
+                                int64_t j, const int64_t *cand, int64_t ncand, orc_out *out)
+{
+    orc_sum sr = {0, 0}, sw[3] = {{0, 0}, {0, 0}, {0, 0}}, s2 = {0, 0};
+    double swa[3] = {0, 0, 0};
+    int gas_act = gas->active ? gas->active[j] : 1;
+    uint64_t np = 0;
+    for (int k = 0; k < 3; k++) { out->dp_gas[3 * j + k] = 0.0; if (out->dp_abs) out->dp_abs[3 * j + k] = 0.0; }
+    out->de_gas[j] = 0.0;
+    if (out->de_abs) out->de_abs[j] = 0.0;
+    if (out->pk_abs) out->pk_abs[j] = 0.0;
+    if (!gas_act) return 0;
+    double sc = gas->mass[j] * p_dt(gas, par, j);
+    int64_t nc = cand ? ncand : dm->n;
+    for (int64_t c = 0; c < nc; c++) {
+        int64_t i = cand ? cand[c] : c;
+        double d;
+        if (!pair_test(gas, dm, par, j, i, &d, NULL)) continue;
+        np++;
+        double mg = dm->mass[i] * orc_overlap(d, dm->h[i], gas->h[j]), w2 = 0.0;
+        for (int k = 0; k < 3; k++) {
+            double w = dm->vel[3 * i + k] - gas->vel[3 * j + k];
+            nsum_add(&sw[k], mg * w);
+            swa[k] += fabs(mg * w);
+            w2 += w * w;
+        }
+        nsum_add(&sr, mg);
+        nsum_add(&s2, mg * w2);
+    }
+    double rho = nsum_get(&sr);
+    if (!(rho > 0.0)) return np;
+    double W[3], W2 = 0.0;
+    for (int k = 0; k < 3; k++) { W[k] = nsum_get(&sw[k]) / rho; W2 += W[k] * W[k]; }
+    double mw2 = nsum_get(&s2) / rho, sx2 = fmax(0.0, (mw2 - W2) / 3.0);
+    double mu = gas_mu(gas, j), vs = gas_vs(gas, j), vth2 = vs * vs + sx2;
+    if (!(vth2 > 0.0) && !(W2 > 0.0)) return np;
+    double A, B;
+    orc_rates(par->n_pow, sqrt(W2), sqrt(vth2), &A, &B);
+    double cfac = par->sigma0_cm2 / (ORC_KPC_CM * ORC_KPC_CM) * (1.0 - par->aniso_g) * pow(ORC_C_KMS, -par->n_pow);
+    double f = sc * rho * ORC_MSUN_G / (par->m_chi_g + mu) * cfac;
+    for (int k = 0; k < 3; k++) {
+        out->dp_gas[3 * j + k] = f * A * W[k];
+        if (out->dp_abs) out->dp_abs[3 * j + k] = fabs(f * A) * swa[k] / rho;
+    }
+    if (!(vth2 > 0.0)) {
+        /* both populations cold: the limit of either order is the per-pair form
+         * W^2 A - mu/(m_X + mu) B at A = |W|^{n+1}, B = |W|^{n+3}            */
+        double e1 = A * W2, e2 = B * mu / (par->m_chi_g + mu);
+        out->de_gas[j] = f * (e1 - e2);
+        if (out->de_abs) out->de_abs[j] = fabs(f) * (fabs(e1) + fabs(e2));
+        return np;
+    }
+    double e1 = B * par->m_chi_g * sx2 / (par->m_chi_g + mu), e2 = B * mu * vs * vs / (par->m_chi_g + mu);
+    double e3 = A * vs * vs * W2;
+    out->de_gas[j] = f * (e1 - e2 + e3) / vth2;
+    if (out->de_abs) out->de_abs[j] = fabs(f) * (fabs(e1) + fabs(e2) + fabs(e3)) / vth2 * fmax(1.0, mw2 / vth2);
+    return np;
 }
 
 /* Relative velocity v_i - v^B_ij with v^B_ij = V_j + varsigma_j z, z from the
