@@ -207,6 +207,50 @@ def surrogate_compare(ctx, cfg, dev, steps: int, log_fn) -> dict:
     return res
 
 
+def closure_compare(ctx, cfg, dev, steps: int, log_fn) -> dict:
+    """Per-gas Maxwellian closure (rates mode 3) against the per-pair mean field
+    on the galaxy workload in binary32: gas-pass time of each and how far the
+    closure's dp and dE lie from the per-pair sums (the DM around a gas
+    particle is not one Maxwellian, so they differ by more than rounding)."""
+    import numpy as np
+    import torch
+    import paper_2603_24688_amd as dmb
+    G = dmb.to_device(cfg["gas"], dev)
+    D = dmb.to_device(cfg["dm"], dev)
+    out = dmb.alloc_out(len(cfg["gas"]["mass"]), len(cfg["dm"]["mass"]), dev)
+    par = dict(cfg["params"])
+    ctx.build_cells(G, D, par, precision=dmb.DMB_FP32)
+    res, got = {}, {}
+    for name, rates in (("pair", dmb.DMB_RATES_EXACT), ("closure", dmb.DMB_RATES_CLOSURE)):
+        par["rates"] = rates
+        ctx.interact_step(G, D, par, out, precision=dmb.DMB_FP32)
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        ctx.profile_read(reset=True)
+        ta = time.perf_counter()
+        for _ in range(steps):
+            ctx.interact_step(G, D, par, out, precision=dmb.DMB_FP32)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        ph = ctx.profile_read(reset=True)
+        ctx.profile_enable(False)
+        got[name] = (out["dp_gas"].cpu().numpy(), out["de_gas"].cpu().numpy())
+        res[name] = {"interact_ms": round((tb - ta) * 1e3 / steps, 4),
+                     "pass_gas_ms": round(ph["pass_gas"][0] / max(ph["pass_gas"][1], 1), 4),
+                     "combine_gas_ms": round(ph["combine_gas"][0] / max(ph["combine_gas"][1], 1), 4)}
+    (p0, e0), (p1, e1) = got["pair"], got["closure"]
+    live = np.abs(e0) > 0
+    dpr = np.linalg.norm(p1 - p0, axis=1)[live] / np.maximum(np.linalg.norm(p0, axis=1)[live], 1e-300)
+    der = np.abs(e1 - e0)[live] / np.abs(e0)[live]
+    res["gas_pass_speedup"] = res["pair"]["pass_gas_ms"] / res["closure"]["pass_gas_ms"]
+    res["dp_rel_diff_median"] = float(np.median(dpr)) if dpr.size else None
+    res["de_rel_diff_median"] = float(np.median(der)) if der.size else None
+    log_fn(f"bench: closure: gas pass {res['closure']['pass_gas_ms']:.3f} ms vs per-pair "
+           f"{res['pair']['pass_gas_ms']:.3f} ms; median |ddp|/|dp| {res['dp_rel_diff_median']:.2e}, "
+           f"|ddE|/|dE| {res['de_rel_diff_median']:.2e}")
+    return res
+
+
 def batch_sweep(dev, steps: int, log_fn) -> dict:
     """Parameter sweep of 64 periodic boxes of uneven size (10^4 .. 5 10^5
     particles per species, sigma0 1e-28 .. 1e-24 cm^2, m_chi/m_p in
@@ -353,8 +397,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="galaxy", choices=["galaxy", "box", "milky_way", "batch"])
-    ap.add_argument("--rates", default="exact", choices=["exact", "quad", "mlp"],
-                    help="rate integrals: closed forms, quadrature (--quad-nodes) or the trained network")
+    ap.add_argument("--rates", default="exact", choices=["exact", "quad", "mlp", "closure"],
+                    help="rate integrals: closed forms, quadrature (--quad-nodes), the trained network "
+                         "or the per-gas Maxwellian closure")
     ap.add_argument("--quad-nodes", type=int, default=12)
     ap.add_argument("--n-pow", type=int, default=0, choices=[-4, -2, 0, 2])
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the workload's particle counts")
@@ -365,6 +410,8 @@ def main():
     ap.add_argument("--no-box", action="store_true", help="skip the 100-step time loop of the periodic test box")
     ap.add_argument("--no-milky-way", action="store_true",
                     help="skip the 200-step hierarchical-timestep run at Milky-Way scale")
+    ap.add_argument("--no-closure", action="store_true",
+                    help="skip the per-gas closure vs per-pair mean-field comparison")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the network-vs-quadrature comparison (sigma ~ v^n on the galaxy workload)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -412,7 +459,8 @@ def main():
     out = dmb.alloc_out(desc["n_gas"], desc["n_dm"], dev)
     ctx = dmb.Context(0)
     par = dict(cfg["params"])
-    rates = {"exact": dmb.DMB_RATES_EXACT, "quad": dmb.DMB_RATES_QUAD, "mlp": dmb.DMB_RATES_MLP}[args.rates]
+    rates = {"exact": dmb.DMB_RATES_EXACT, "quad": dmb.DMB_RATES_QUAD, "mlp": dmb.DMB_RATES_MLP,
+             "closure": dmb.DMB_RATES_CLOSURE}[args.rates]
     par["rates"], par["quad_nodes"] = rates, args.quad_nodes
     desc["rates"] = args.rates if args.rates != "quad" else f"quad{args.quad_nodes}"
     if args.rates == "mlp":
@@ -494,6 +542,8 @@ def main():
                          "dm": pairs / max(1, bst["cand_pairs_dm"] * 4096)},
     }
     default_run = args.workload == "galaxy" and args.rates == "exact" and args.n_pow == 0
+    if default_run and not args.no_closure:
+        line["closure"] = closure_compare(ctx, cfg, dev, 3, log)
     if default_run and not args.no_surrogate:
         line["surrogate"] = surrogate_compare(ctx, cfg, dev, 3, log)
     if default_run and not args.no_batch:

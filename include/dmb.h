@@ -53,8 +53,14 @@ typedef enum { DMB_FP64 = 0, DMB_FP32 = 1 } dmb_precision;
 typedef enum {
     DMB_RATES_EXACT = 0,  /* closed forms of the 1F1 expressions of Appendix B (integer n) */
     DMB_RATES_QUAD = 1,   /* K-node Gauss-Legendre quadrature of the radial form of eq. scrA/scrB */
-    DMB_RATES_MLP = 2     /* learned closure (dmb_mlp_*), binary32 only; K-node quadrature where the
+    DMB_RATES_MLP = 2,    /* learned closure (dmb_mlp_*), binary32 only; K-node quadrature where the
                              similarity variable u = w/varsigma exceeds the trained range (u > 1000) */
+    DMB_RATES_CLOSURE = 3 /* per-gas Maxwellian closure (the Appendix F rates applied per gas particle):
+                             the gas pass sums the kernel-weighted DM density, drift and dispersion
+                             around each gas particle (binary64 sums in either precision) and the
+                             closed-form rates are evaluated once per gas particle at the combined
+                             dispersion.  Exact for Maxwellian DM; the DM Monte Carlo is unchanged.
+                             Not for dmb_rates_eval. */
 } dmb_rates;
 
 enum {

@@ -15,7 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libdmb.so")
 
 DMB_FP64, DMB_FP32 = 0, 1
-DMB_RATES_EXACT, DMB_RATES_QUAD, DMB_RATES_MLP = 0, 1, 2
+DMB_RATES_EXACT, DMB_RATES_QUAD, DMB_RATES_MLP, DMB_RATES_CLOSURE = 0, 1, 2, 3
 MLP_PARAMS = 8834
 COUNTER_NAMES = ["pairs_gas", "pairs_dm", "scatters", "near_boundary", "near_decision",
                  "crit_viol", "p_ge_1", "nonfinite"]

@@ -639,7 +639,7 @@ double sig_kpc2_cn_of(const dmb_params* par)
 // Per-step gathers into Morton order and the clearing of outputs, counters
 // and the box's queue counters (qctr: [0, 8) gas queue, [8, 16) DM queue,
 // [16] scatter count).
-template <typename Real>
+template <typename Real, int RM>
 dmb_status gather_and_fill(dmb_ctx* c, Cells& X, const dmb_particles* gas, const dmb_particles* dm,
                            const dmb_params* par, dmb_out* out, uint64_t* counters)
 {
@@ -673,7 +673,7 @@ dmb_status gather_and_fill(dmb_ctx* c, Cells& X, const dmb_particles* gas, const
     hipLaunchKernelGGL(k_fill_out, dim3(blocks_for(nfill, 256)), dim3(256), 0, c->stream, G.n, D.n, out->dp_gas,
                        out->de_gas, out->dv_dm, out->partner, out->p_sum, out->p_max, counters,
                        X.qctr.as<uint32_t>(), 2 * kXcd + 4);
-    if (X.gp.nitems > 0) ENSURE(c, X.part_gas, size_t(X.gp.nitems) * kTile * 4 * 8);
+    if (X.gp.nitems > 0) ENSURE(c, X.part_gas, size_t(X.gp.nitems) * kTile * gas_sums<RM>() * 8);
     if (X.dp.nitems > 0) {
         ENSURE(c, X.part_p, size_t(X.dp.nitems) * kTile * 8);
         ENSURE(c, X.part_pm, size_t(X.dp.nitems) * kTile * 4);
@@ -716,23 +716,25 @@ GasPassArgs gas_pass_args(dmb_ctx* c, Cells& X, const dmb_particles* gas, const 
         a.mlp_kB = float(1.0 / al);
     }
     a.part = X.part_gas.as<double>();
-    a.perm = G.perm; a.mass = gas->mass; a.mu = gas->mu; a.dt = gas->dt; a.dt_default = par->dt;
+    a.perm = G.perm; a.mass = gas->mass; a.mu = gas->mu; a.dt = gas->dt; a.u = gas->u; a.dt_default = par->dt;
     // the gas rates take the momentum-transfer cross section sigma-bar = (1 - g) sigma
     a.m_chi = par->m_chi_g; a.sig_kpc2_cn = sig_kpc2_cn_of(par) * (1.0 - par->aniso_g);
+    a.alpha_n = alpha_n(par->n_pow);
     a.dp = out->dp_gas; a.de = out->de_gas;
     return a;
 }
 
+template <int N, int RM>
 void combine_gas(dmb_ctx* c, Cells& X, const dmb_particles* gas, const dmb_params* par, dmb_out* out)
 {
     Species& G = X.gas;
     GasCombineArgs cb;
     cb.n_own = G.n_own; cb.own = G.own.as<const uint32_t>(); cb.perm = G.perm;
     cb.item_off = X.gp.ioff.as<const uint32_t>(); cb.part = X.part_gas.as<const double>();
-    cb.mass = gas->mass; cb.mu = gas->mu; cb.dt = gas->dt; cb.dt_default = par->dt; cb.m_chi = par->m_chi_g;
-    cb.sig_kpc2_cn = sig_kpc2_cn_of(par) * (1.0 - par->aniso_g); cb.dp = out->dp_gas; cb.de = out->de_gas;
-    hipLaunchKernelGGL(k_combine_gas, dim3(unsigned((G.n_own + kTile - 1) / kTile)), dim3(64 * kCombineWaves), 0,
-                       c->stream, cb);
+    cb.out = GasOutArgs{gas->mass, gas->mu, gas->dt, gas->u, par->dt, par->m_chi_g,
+                        sig_kpc2_cn_of(par) * (1.0 - par->aniso_g), alpha_n(par->n_pow), out->dp_gas, out->de_gas};
+    hipLaunchKernelGGL((k_combine_gas<N, RM>), dim3(unsigned((G.n_own + kTile - 1) / kTile)),
+                       dim3(64 * kCombineWaves), 0, c->stream, cb);
 }
 
 DmPassArgs dm_pass_args(dmb_ctx* c, Cells& X, const dmb_params* par, dmb_out* out, uint64_t* counters,
@@ -800,7 +802,7 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
     Cells& X = *c->X;
     {
         Phase ph(c, DMB_PH_GATHER);
-        dmb_status s = gather_and_fill<Real>(c, X, gas, dm, par, out, counters);
+        dmb_status s = gather_and_fill<Real, RM>(c, X, gas, dm, par, out, counters);
         if (s != DMB_OK) return s;
     }
     if (X.gp.nitems > 0) {
@@ -817,7 +819,7 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
                                a, (const GasPassArgs*)nullptr, (const int64_t*)nullptr, 0);
         }
         Phase ph(c, DMB_PH_COMBINE_GAS);
-        combine_gas(c, X, gas, par, out);
+        combine_gas<N, RM>(c, X, gas, par, out);
     }
     if (X.dp.nitems > 0) {
         DmPassArgs a = dm_pass_args(c, X, par, out, counters, nullptr);
@@ -866,7 +868,7 @@ dmb_status batch_prepare(dmb_ctx* c, int nbox, const dmb_particles* gas, const d
     for (int b = 0; b < nbox; ++b) {
         Cells& X = *c->boxes[b];
         // buffers the step writes (sized here so that enqueueing allocates nothing)
-        if (X.gp.nitems > 0) ENSURE(c, X.part_gas, size_t(X.gp.nitems) * kTile * 4 * 8);
+        if (X.gp.nitems > 0) ENSURE(c, X.part_gas, size_t(X.gp.nitems) * kTile * gas_sums<RM>() * 8);
         if (X.dp.nitems > 0) {
             ENSURE(c, X.part_p, size_t(X.dp.nitems) * kTile * 8);
             ENSURE(c, X.part_pm, size_t(X.dp.nitems) * kTile * 4);
@@ -923,7 +925,7 @@ dmb_status batch_enqueue(dmb_ctx* c, const dmb_particles* gas, const dmb_particl
     const int64_t* gitems = c->bitem.as<const int64_t>();
     const int64_t* ditems = gitems + nbox + 1;
     for (int b = 0; b < nbox; ++b) {
-        dmb_status s = gather_and_fill<Real>(c, *c->boxes[b], gas + b, dm + b, par + b, out + b, out[b].counters);
+        dmb_status s = gather_and_fill<Real, RM>(c, *c->boxes[b], gas + b, dm + b, par + b, out + b, out[b].counters);
         if (s != DMB_OK) return s;
     }
     hipLaunchKernelGGL(k_fill_out, dim3(1), dim3(256), 0, c->stream, int64_t(0), int64_t(0), (double*)nullptr,
@@ -940,7 +942,7 @@ dmb_status batch_enqueue(dmb_ctx* c, const dmb_particles* gas, const dmb_particl
         }
         Phase ph(c, DMB_PH_COMBINE_GAS);
         for (int b = 0; b < nbox; ++b)
-            if (c->boxes[b]->gp.nitems > 0) combine_gas(c, *c->boxes[b], gas + b, par + b, out + b);
+            if (c->boxes[b]->gp.nitems > 0) combine_gas<N, RM>(c, *c->boxes[b], gas + b, par + b, out + b);
     }
     if (P.dm_items > 0) {
         DmPassArgs a0 = P.da[0];
@@ -1047,6 +1049,7 @@ dmb_status dispatch_rates(dmb_ctx* c, const dmb_particles* gas, const dmb_partic
             return fail(c, DMB_EINVAL, "network rates need DMB_FP32");
         }
     }
+    if (par->rates == DMB_RATES_CLOSURE) return dispatch_n<Real, kRatesClosure>(c, gas, dm, par, out, counters);
     return dispatch_n<Real, kRatesExact>(c, gas, dm, par, out, counters);
 }
 
@@ -1081,6 +1084,8 @@ dmb_status batch_dispatch_rates(dmb_ctx* c, int nbox, const dmb_particles* gas, 
             return fail(c, DMB_EINVAL, "network rates need DMB_FP32");
         }
     }
+    if (par->rates == DMB_RATES_CLOSURE)
+        return batch_dispatch_n<Real, kRatesClosure>(c, nbox, gas, dm, par, out, nsteps, graph);
     return batch_dispatch_n<Real, kRatesExact>(c, nbox, gas, dm, par, out, nsteps, graph);
 }
 
@@ -1584,13 +1589,15 @@ dmb_status check_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles*
     if ((gas->n > 0 && (!out->dp_gas || !out->de_gas)) || (dm->n > 0 && (!out->dv_dm || !out->partner)))
         return fail(c, DMB_EINVAL, "null output array");
     if (!n_supported(par->n_pow)) return fail(c, DMB_EINVAL, "n_pow %d not supported", par->n_pow);
-    if (par->rates != DMB_RATES_EXACT && par->rates != DMB_RATES_QUAD && par->rates != DMB_RATES_MLP)
+    if (par->rates != DMB_RATES_EXACT && par->rates != DMB_RATES_QUAD && par->rates != DMB_RATES_MLP &&
+        par->rates != DMB_RATES_CLOSURE)
         return fail(c, DMB_EINVAL, "rates mode %d not supported", par->rates);
     if (par->rates == DMB_RATES_MLP && !c->mlp_ready)
         return fail(c, DMB_EINVAL, "network rates requested but no weights are loaded (dmb_mlp_init/set_params/train)");
     if (par->rates == DMB_RATES_MLP && par->precision != DMB_FP32)
         return fail(c, DMB_EINVAL, "network rates need DMB_FP32");
-    if (par->rates != DMB_RATES_EXACT && (quad_k(par) < 4 || quad_k(par) > kMaxQuadNodes))
+    if ((par->rates == DMB_RATES_QUAD || par->rates == DMB_RATES_MLP) &&
+        (quad_k(par) < 4 || quad_k(par) > kMaxQuadNodes))
         return fail(c, DMB_EINVAL, "quad_nodes %d outside 4..%d", par->quad_nodes, kMaxQuadNodes);
     if (!(par->m_chi_g > 0.0) || !(par->sigma0_cm2 >= 0.0)) return fail(c, DMB_EINVAL, "bad m_chi or sigma0");
     if (!(std::fabs(par->aniso_g) < 1.0)) return fail(c, DMB_EINVAL, "aniso_g %g outside (-1, 1)", par->aniso_g);
@@ -2199,11 +2206,12 @@ dmb_status batch_step_checked(dmb_ctx* c, int32_t nbox, const dmb_particles* gas
     if (nsteps < 1) return fail(c, DMB_EINVAL, "nsteps < 1");
     const dmb_params& p0 = par[0];
     if (!n_supported(p0.n_pow)) return fail(c, DMB_EINVAL, "n_pow %d not supported", p0.n_pow);
-    if (p0.rates != DMB_RATES_EXACT && p0.rates != DMB_RATES_QUAD && p0.rates != DMB_RATES_MLP)
+    if (p0.rates != DMB_RATES_EXACT && p0.rates != DMB_RATES_QUAD && p0.rates != DMB_RATES_MLP &&
+        p0.rates != DMB_RATES_CLOSURE)
         return fail(c, DMB_EINVAL, "rates mode %d not supported", p0.rates);
     if (p0.rates == DMB_RATES_MLP && (!c->mlp_ready || p0.precision != DMB_FP32))
         return fail(c, DMB_EINVAL, "network rates need loaded weights and DMB_FP32");
-    if (p0.rates != DMB_RATES_EXACT && (quad_k(&p0) < 4 || quad_k(&p0) > kMaxQuadNodes))
+    if ((p0.rates == DMB_RATES_QUAD || p0.rates == DMB_RATES_MLP) && (quad_k(&p0) < 4 || quad_k(&p0) > kMaxQuadNodes))
         return fail(c, DMB_EINVAL, "quad_nodes %d outside 4..%d", p0.quad_nodes, kMaxQuadNodes);
     for (int b = 0; b < nbox; ++b) {
         const dmb_params& p = par[b];

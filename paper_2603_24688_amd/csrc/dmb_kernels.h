@@ -18,7 +18,7 @@ constexpr double kMsunG = 1.988409870698051e33;
 constexpr double kKpcCm = 3.0856775814913673e21;
 constexpr double kCKms = 299792.458;
 constexpr double kMpG = 1.67262192369e-24;
-enum { kRatesExact = 0, kRatesQuad = 1, kRatesMlp = 2 };
+enum { kRatesExact = 0, kRatesQuad = 1, kRatesMlp = 2, kRatesClosure = 3 };
 constexpr int kMaxQuadNodes = 64;
 constexpr int kMlpPassWaves = 4;     // independent waves per block of the network gas pass
 
@@ -1431,23 +1431,88 @@ struct GasPassArgs {
     int mlp_nidx;                 // one-hot slot of n
     float mlp_c0A, mlp_c1A, mlp_c0B, mlp_c1B;   // base-function constants
     float mlp_kA, mlp_kB;                       // 3/alpha_n, 1/alpha_n
-    double* part;                 // [n_items][64][4]
+    double* part;                 // [n_items][64][gas_sums<RM>()]
     // direct output for owner tiles with a single work item
     const uint32_t* perm;         // gas sorted pos -> index
     const double* mass; const double* mu; const double* dt;
-    double dt_default, m_chi, sig_kpc2_cn;
+    const double* u;              // gas internal energy (closure: varsigma^2 = 2u/3)
+    double dt_default, m_chi, sig_kpc2_cn, alpha_n;
     double* dp; double* de;
 };
 
-__device__ __forceinline__ void gas_write_out(const GasPassArgs& a, uint32_t o, const double acc[4])
+// Sums the gas pass keeps per owner: the per-pair mean field sums
+// (sum M g A w, sum M g (w^2 A - r B)); the closure keeps the DM moments
+// (sum M g w, sum M g |w|^2, sum M g).
+template <int RM> constexpr int gas_sums() { return RM == kRatesClosure ? 5 : 4; }
+
+// Per-gas Maxwellian closure (Appendix F rates applied per gas particle): the
+// DM around the gas particle form one Maxwellian population of kernel-weighted
+// density rho = sum M g, drift W = sum M g w / rho and 1-D dispersion
+// s_X^2 = (sum M g |w|^2 / rho - |W|^2) / 3.  The two-population rates at
+// vth^2 = varsigma^2 + s_X^2 give, per unit of M_j dt sigma-bar_0 c^-n / (m_X + mu),
+//   momentum rho A(|W|; vth) W,
+//   energy   rho [B (m_X s_X^2 - mu varsigma^2) / (m_X + mu) + A varsigma^2 |W|^2] / vth^2,
+// the Maxwellian average of the per-pair terms of eq. gas-dVdt / gas-dTdt.
+// With both populations cold (vth = 0) the energy takes its limit, the
+// per-pair form |W|^2 A - mu / (m_X + mu) B at A = |W|^{n+1}, B = |W|^{n+3}.
+template <int N>
+__device__ __forceinline__ void closure_transfer(const double s[5], double vs2, double mu, double m_chi,
+                                                 double alpha_n, double v[4])
 {
-    double mu = a.mu ? a.mu[o] : kMpG;
-    double dtj = a.dt ? a.dt[o] : a.dt_default;
-    double sc = a.mass[o] * dtj * kMsunG / (a.m_chi + mu) * a.sig_kpc2_cn;
-    a.dp[3 * int64_t(o)] = sc * acc[0];
-    a.dp[3 * int64_t(o) + 1] = sc * acc[1];
-    a.dp[3 * int64_t(o) + 2] = sc * acc[2];
-    a.de[o] = sc * acc[3];
+    v[0] = 0.0; v[1] = 0.0; v[2] = 0.0; v[3] = 0.0;
+    const double rho = s[4];
+    if (!(rho > 0.0)) return;
+    const double Wx = s[0] / rho, Wy = s[1] / rho, Wz = s[2] / rho;
+    const double W2 = Wx * Wx + Wy * Wy + Wz * Wz;
+    const double sx2 = fmax(0.0, (s[3] / rho - W2) / 3.0);
+    const double vth2 = vs2 + sx2;
+    if (!(vth2 > 0.0) && !(W2 > 0.0)) return;
+    double A, E;
+    if (vth2 > 0.0) {
+        double FA, FB;
+        rate_1f1<N, double>(W2 / (2.0 * vth2), &FA, &FB);
+        const double vth = sqrt(vth2);
+        A = alpha_n / 3.0 * pow(vth, double(N + 1)) * FA;
+        const double B = alpha_n * pow(vth, double(N + 3)) * FB;
+        E = (B * (m_chi * sx2 - mu * vs2) / (m_chi + mu) + A * vs2 * W2) / vth2;
+    } else {
+        A = pow_np1<N>(sqrt(W2));
+        E = A * W2 * (1.0 - mu / (m_chi + mu));
+    }
+    v[0] = rho * A * Wx; v[1] = rho * A * Wy; v[2] = rho * A * Wz;
+    v[3] = rho * E;
+}
+
+// Output of gas o from its summed terms: dp = M_j dt S x (momentum sums),
+// dE = M_j dt S x (energy sum), S = sigma-bar_0 c^-n / (m_X + mu_j).
+struct GasOutArgs {
+    const double* mass; const double* mu; const double* dt; const double* u;
+    double dt_default, m_chi, sig_kpc2_cn, alpha_n;
+    double* dp; double* de;
+};
+template <int N, int RM>
+__device__ __forceinline__ void gas_store(const GasOutArgs& a, uint32_t o, const double* acc)
+{
+    const double mu = a.mu ? a.mu[o] : kMpG;
+    const double dtj = a.dt ? a.dt[o] : a.dt_default;
+    const double sc = a.mass[o] * dtj * kMsunG / (a.m_chi + mu) * a.sig_kpc2_cn;
+    double v[4];
+    if constexpr (RM == kRatesClosure) {
+        closure_transfer<N>(acc, 2.0 * a.u[o] / 3.0, mu, a.m_chi, a.alpha_n, v);
+    } else {
+        for (int k = 0; k < 4; ++k) v[k] = acc[k];
+    }
+    a.dp[3 * int64_t(o)] = sc * v[0];
+    a.dp[3 * int64_t(o) + 1] = sc * v[1];
+    a.dp[3 * int64_t(o) + 2] = sc * v[2];
+    a.de[o] = sc * v[3];
+}
+
+template <int N, int RM>
+__device__ __forceinline__ void gas_write_out(const GasPassArgs& a, uint32_t o, const double* acc)
+{
+    const GasOutArgs w{a.mass, a.mu, a.dt, a.u, a.dt_default, a.m_chi, a.sig_kpc2_cn, a.alpha_n, a.dp, a.de};
+    gas_store<N, RM>(w, o, acc);
 }
 
 // Occupancy: the binary32 passes fit 128 VGPRs and < 10 KB of LDS per
@@ -1466,7 +1531,8 @@ void k_pass_gas(
     __shared__ TestLds S_[W];
     __shared__ Real s_gx[kMaxQuadNodes], s_gw[kMaxQuadNodes];
     __shared__ double o_x_[W][64], o_y_[W][64], o_z_[W][64], o_h_[W][64], o_Vx_[W][64], o_Vy_[W][64], o_Vz_[W][64];
-    __shared__ double osum_[W][64 * 4];
+    constexpr int NS = gas_sums<RM>();
+    __shared__ double osum_[W][64 * NS];
     __shared__ __align__(16) unsigned char s_mlp[RM == kRatesMlp ? kMlpInferBytes : 16];
     const int wv = W == 1 ? 0 : int(threadIdx.x) >> 6;
     TestLds& S = S_[wv];
@@ -1522,8 +1588,8 @@ void k_pass_gas(
         const double cen[3] = {0.5 * (A[0] + A[3]), 0.5 * (A[1] + A[4]), 0.5 * (A[2] + A[5])};
         const float fx = float(mx - cen[0]), fy = float(my - cen[1]), fz = float(mz - cen[2]), fh = float(mh);
         // the item's per-owner sums (row = owner lane)
-        double* osum = osum_[wv] + 4 * lane;
-        osum[0] = 0.0; osum[1] = 0.0; osum[2] = 0.0; osum[3] = 0.0;
+        double* osum = osum_[wv] + NS * lane;
+        for (int k = 0; k < NS; ++k) osum[k] = 0.0;
         PairTest T;
         test_begin(T, ov, fx, fy, fz, fh, cb, ce);
         for (;;) {
@@ -1535,14 +1601,42 @@ void k_pass_gas(
             walk_begin(S, lane, H, R, hw);
             // per-pair terms and the lane's partial sums in binary64 (the overlap near contact is
             // far below the binary32 range; sums of terms that cancel keep their accuracy)
-            double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+            double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
             bool open = false;
             for (int r = 0; r < R; ++r) {
                 const bool live = r < hw.n;
                 const int o = live ? hw.o : 0;
                 const int sl = live ? int(__builtin_ctzll(hw.rem)) : 0;
-                double c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-                if constexpr (RM != kRatesMlp) {
+                double c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0;
+                if constexpr (RM == kRatesClosure) {
+                    // the closure's DM moments: kernel-weighted mass, momentum and |w|^2
+                    bool hit = false;
+                    uint32_t e_o = 0u, e_q = 0u;
+                    if (live) {
+                        const uint32_t pqv = S.pq[sl];
+                        const int64_t q = int64_t(pqv & 0x7fffffffu);
+                        const DmRec<Real> r = reinterpret_cast<const DmRec<Real>*>(a.drec)[q];
+                        const double qx = S.px[sl], qy = S.py[sl], qz = S.pz[sl], qh = S.ph[sl];
+                        const double d2 = pair_d2(o_x[o], o_y[o], o_z[o], qx, qy, qz, (pqv >> 31) != 0u, G.L);
+                        const double hs = o_h[o] + qh;
+                        if constexpr (PAIRS) {
+                            hit = d2 < hs * hs;
+                            e_o = G.own[t * kTile + o];
+                            e_q = uint32_t(q);
+                        }
+                        if (d2 < hs * hs) {
+                            npairs++;
+                            const double gg = EXACT_G ? double(overlap_g_exact<Real>(sqrt_real(Real(d2)), Real(qh), Real(o_h[o])))
+                                                      : overlap_g_table(a.gtab, d2, qh, o_h[o]);
+                            const double wx = r.vx - o_Vx[o], wy = r.vy - o_Vy[o], wz = r.vz - o_Vz[o];
+                            const double mg = double(r.m) * gg;
+                            c0 = mg * wx; c1 = mg * wy; c2 = mg * wz;
+                            c3 = mg * (wx * wx + wy * wy + wz * wz);
+                            c4 = mg;
+                        }
+                    }
+                    if constexpr (PAIRS) pair_export(G, hit, e_o, e_q);
+                } else if constexpr (RM != kRatesMlp) {
                     bool hit = false;
                     uint32_t e_o = 0u, e_q = 0u;
                     if (live) {
@@ -1658,14 +1752,16 @@ void k_pass_gas(
                     }
                 }
                 p0 += c0; p1 += c1; p2 += c2; p3 += c3;
+                if constexpr (NS == 5) p4 += c4;
                 if (live) hw.rem &= hw.rem - 1ull;
                 const bool done = live && hw.rem == 0ull;
                 if (live) open = !done;
                 if (__ballot(done) != 0ull && done) {
                     // the owner's last hit of the group: its partial goes to the owner's row
-                    double* q = osum_[wv] + 4 * hw.o;
+                    double* q = osum_[wv] + NS * hw.o;
                     q[0] += p0; q[1] += p1; q[2] += p2; q[3] += p3;
-                    p0 = 0.0; p1 = 0.0; p2 = 0.0; p3 = 0.0;
+                    if constexpr (NS == 5) q[4] += p4;
+                    p0 = 0.0; p1 = 0.0; p2 = 0.0; p3 = 0.0; p4 = 0.0;
                     hw.o = next_owner(hw.own, hw.o);
                     hw.rem = hw.o < 64 ? S.mask[hw.o] : 0ull;
                 }
@@ -1680,21 +1776,24 @@ void k_pass_gas(
                     p1 = dpp_take_add<C, RW>(p1, take);
                     p2 = dpp_take_add<C, RW>(p2, take);
                     p3 = dpp_take_add<C, RW>(p3, take);
+                    if constexpr (NS == 5) p4 = dpp_take_add<C, RW>(p4, take);
                 });
                 if (open && last) {
-                    double* q = osum_[wv] + 4 * hw.o;
+                    double* q = osum_[wv] + NS * hw.o;
                     q[0] += p0; q[1] += p1; q[2] += p2; q[3] += p3;
+                    if constexpr (NS == 5) q[4] += p4;
                 }
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        const double acc[4] = {osum[0], osum[1], osum[2], osum[3]};
+        double acc[NS];
+        for (int k = 0; k < NS; ++k) acc[k] = osum[k];
         if (G.item_off[t + 1] - G.item_off[t] == 1u) {
-            if (ov) gas_write_out(a, a.perm[sp], acc);
+            if (ov) gas_write_out<N, RM>(a, a.perm[sp], acc);
         } else {
-            double* P = a.part + (it * kTile + lane) * 4;
-            P[0] = acc[0]; P[1] = acc[1]; P[2] = acc[2]; P[3] = acc[3];
+            double* P = a.part + (it * kTile + lane) * NS;
+            for (int k = 0; k < NS; ++k) P[k] = acc[k];
         }
     }
     for (int d = 32; d >= 1; d >>= 1) npairs += __shfl_xor(npairs, d);
@@ -1962,10 +2061,8 @@ struct GasCombineArgs {
     int64_t n_own;
     const uint32_t* own; const uint32_t* perm;
     const uint32_t* item_off;     // [nown_tile + 1]
-    const double* part;
-    const double* mass; const double* mu; const double* dt;
-    double dt_default, m_chi, sig_kpc2_cn;
-    double* dp; double* de;
+    const double* part;           // [n_items][64][gas_sums<RM>()]
+    GasOutArgs out;
 };
 
 // One block per owner tile with several items; wave w sums the tile's items
@@ -1973,33 +2070,29 @@ struct GasCombineArgs {
 // wave order, so the result does not depend on scheduling.
 constexpr int kCombineWaves = 8;
 
+template <int N, int RM>
 __global__ __launch_bounds__(64 * kCombineWaves) void k_combine_gas(GasCombineArgs a)
 {
-    __shared__ double s_acc[kCombineWaves][64][4];
+    constexpr int NS = gas_sums<RM>();
+    __shared__ double s_acc[kCombineWaves][64][NS];
     const int64_t t = blockIdx.x;
     const uint32_t i0 = a.item_off[t], i1 = a.item_off[t + 1];
     if (i1 - i0 <= 1u) return;
     const int w = int(threadIdx.x) >> 6, l = lane_id();
-    double acc[4] = {0, 0, 0, 0};
+    double acc[NS];
+    for (int c = 0; c < NS; ++c) acc[c] = 0.0;
 #pragma unroll 4
     for (uint32_t it = i0 + uint32_t(w); it < i1; it += kCombineWaves) {
-        const double* P = a.part + (int64_t(it) * kTile + l) * 4;
-        for (int c = 0; c < 4; ++c) acc[c] += P[c];
+        const double* P = a.part + (int64_t(it) * kTile + l) * NS;
+        for (int c = 0; c < NS; ++c) acc[c] += P[c];
     }
-    for (int c = 0; c < 4; ++c) s_acc[w][l][c] = acc[c];
+    for (int c = 0; c < NS; ++c) s_acc[w][l][c] = acc[c];
     __syncthreads();
     const int64_t s = t * kTile + l;
     if (w != 0 || s >= a.n_own) return;
     for (int v = 1; v < kCombineWaves; ++v)
-        for (int c = 0; c < 4; ++c) acc[c] += s_acc[v][l][c];
-    uint32_t o = a.perm[a.own[s]];
-    double mu = a.mu ? a.mu[o] : kMpG;
-    double dtj = a.dt ? a.dt[o] : a.dt_default;
-    double sc = a.mass[o] * dtj * kMsunG / (a.m_chi + mu) * a.sig_kpc2_cn;
-    a.dp[3 * int64_t(o)] = sc * acc[0];
-    a.dp[3 * int64_t(o) + 1] = sc * acc[1];
-    a.dp[3 * int64_t(o) + 2] = sc * acc[2];
-    a.de[o] = sc * acc[3];
+        for (int c = 0; c < NS; ++c) acc[c] += s_acc[v][l][c];
+    gas_store<N, RM>(a.out, a.perm[a.own[s]], acc);
 }
 
 struct DmCombineArgs {

@@ -43,11 +43,11 @@ def boxes():
     return workloads.batch(n_box=6, n_min=1200, n_max=6000, seed=(5, 2))
 
 
-def _to_dev(bx):
+def _to_dev(bx, rates=0):
     import paper_2603_24688_amd as dmb
     G = [dmb.to_device(b["gas"]) for b in bx]
     D = [dmb.to_device(b["dm"]) for b in bx]
-    P = [dict(b["params"]) for b in bx]
+    P = [dict(b["params"], rates=rates) for b in bx]
     O = [dmb.alloc_out(len(b["gas"]["mass"]), len(b["dm"]["mass"])) for b in bx]
     return G, D, P, O
 
@@ -68,27 +68,28 @@ def _same(a, b):
     return None
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_batch_equals_single_boxes(ctx, boxes, precision):
+# rates 3: the per-gas Maxwellian closure
+@pytest.mark.parametrize("precision,rates", [(0, 0), (1, 0), (0, 3), (1, 3)])
+def test_batch_equals_single_boxes(ctx, boxes, precision, rates):
     import torch
-    G, D, P, O = _to_dev(boxes)
+    G, D, P, O = _to_dev(boxes, rates)
     ctx.batch_build(G, D, P, precision=precision)
     ctx.batch_step(G, D, P, O, precision=precision)
     torch.cuda.synchronize()
     for b, bx in enumerate(boxes):
-        single = run_gpu(ctx, bx, precision)
+        single = run_gpu(ctx, dict(bx, params=P[b]), precision)
         got = _host(O[b])
         bad = _same(got, single)
-        _log(f"[batch p={precision}] box {b}: n={len(bx['gas']['mass'])} pairs {got['counters']['pairs_gas']} "
+        _log(f"[batch p={precision} rates={rates}] box {b}: n={len(bx['gas']['mass'])} pairs {got['counters']['pairs_gas']} "
              f"scatters {got['counters']['scatters']} {'identical' if bad is None else 'differs in ' + bad}")
         assert bad is None
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_batch_oracle_parity(ctx, boxes, precision):
+@pytest.mark.parametrize("precision,rates", [(0, 0), (1, 0), (1, 3)])
+def test_batch_oracle_parity(ctx, boxes, precision, rates):
     import oracle
     import torch
-    G, D, P, O = _to_dev(boxes)
+    G, D, P, O = _to_dev(boxes, rates)
     ctx.batch_build(G, D, P, precision=precision)
     ctx.batch_step(G, D, P, O, precision=precision)
     torch.cuda.synchronize()
@@ -97,12 +98,12 @@ def test_batch_oracle_parity(ctx, boxes, precision):
         ng, nd = len(bx["gas"]["mass"]), len(bx["dm"]["mass"])
         gsel = np.sort(np.random.default_rng(b).choice(ng, min(ng, 600), replace=False))
         dsel = np.sort(np.random.default_rng(b + 10).choice(nd, min(nd, 600), replace=False))
-        ref = oracle.step(bx["gas"], bx["dm"], bx["params"], gas_sel=gsel, dm_sel=dsel)
+        ref = oracle.step(bx["gas"], bx["dm"], P[b], gas_sel=gsel, dm_sel=dsel)
         got = _host(O[b])
         ep, ee = mean_field_error(got, ref, gsel)
         dec = decision_report(got, ref, dsel)
         ke = kick_error(got, ref, dsel)
-        _log(f"[batch oracle p={precision}] box {b}: dp {ep:.2e} dE {ee:.2e} decisions {dec['compared']} "
+        _log(f"[batch oracle p={precision} rates={rates}] box {b}: dp {ep:.2e} dE {ee:.2e} decisions {dec['compared']} "
              f"mismatch {dec['mismatch']} kick {ke:.2e}")
         assert ep <= TOL[precision] and ee <= TOL[precision]
         assert dec["mismatch"] == 0

@@ -222,6 +222,30 @@ def test_box_quadrature_rates(ctx, orc, precision, K):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("n_pow", [0, -2, 2, -4])
+def test_box_gas_closure(ctx, orc, precision, n_pow):
+    """DMB_RATES_CLOSURE (the Appendix F rates applied per gas particle): the
+    gas pass sums the kernel-weighted DM density, drift and |w|^2 around each
+    gas particle and evaluates the rates once at the combined dispersion; the
+    DM Monte Carlo is unchanged.  Against the oracle's closure, with many
+    owner tiles split over several work items (so the combine kernel runs)."""
+    import paper_2603_24688_amd as dmb
+    cfg = workloads.box(n_gas=1500, n_dm=2600, seed=(31, n_pow + 10), n_pow=n_pow,
+                        sigma0_cm2=workloads.sigma0_for_npow(n_pow, 30.0, 3e-23))
+    cfg["params"]["rates"] = dmb.DMB_RATES_CLOSURE
+    _check_step(ctx, orc, cfg, precision, f"box-closure n={n_pow}")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_galaxy_gas_closure(ctx, orc, precision):
+    """The closure on the galaxy profiles (open boundaries, h over ~2 decades)."""
+    import paper_2603_24688_amd as dmb
+    cfg = workloads.galaxy(n_gas=2500, n_dm=10000, seed=(2, 12))
+    cfg["params"]["rates"] = dmb.DMB_RATES_CLOSURE
+    _check_step(ctx, orc, cfg, precision, "galaxy-closure")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_small_galaxy(ctx, orc, precision):
     """Open boundaries, heterogeneous h over ~2 decades (galaxy profiles, 1/400 scale)."""
     cfg = workloads.galaxy(n_gas=2500, n_dm=10000, seed=(2, 9))
@@ -321,6 +345,8 @@ def test_invalid_arguments(ctx):
     for g in (1.0, -1.0, float("nan")):
         with pytest.raises(dmb.DmbError, match="EINVAL"):
             ctx.interact_step(G, D, dict(par, aniso_g=g), out)
+    with pytest.raises(dmb.DmbError, match="EINVAL"):
+        ctx.interact_step(G, D, dict(par, rates=4), out)
     big = dict(cfg["gas"])
     big["h"] = np.full(200, 0.3)
     with pytest.raises(dmb.DmbError, match="ERANGE"):
