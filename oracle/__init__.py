@@ -44,7 +44,7 @@ class Particles(C.Structure):
 class Params(C.Structure):
     _fields_ = [("sigma0_cm2", C.c_double), ("n_pow", C.c_int), ("m_chi_g", C.c_double),
                 ("dt", C.c_double), ("seed", C.c_uint64), ("step", C.c_uint32), ("box_id", C.c_uint32),
-                ("box", C.c_double * 3), ("aniso_g", C.c_double), ("gas_closure", C.c_int)]
+                ("box", C.c_double * 3), ("aniso_g", C.c_double), ("gas_closure", C.c_int), ("dm_rb", C.c_int)]
 
 
 class Out(C.Structure):
@@ -76,6 +76,8 @@ def lib():
         L.orc_philox4x64_10.restype = None; L.orc_philox4x64_10.argtypes = [p, p, p]
         L.orc_u24.restype = d; L.orc_u24.argtypes = [u32]
         L.orc_normals3.restype = None; L.orc_normals3.argtypes = [p, p]
+        L.orc_rb_radius.restype = d; L.orc_rb_radius.argtypes = [i, d, d]
+        L.orc_rb_urel.restype = None; L.orc_rb_urel.argtypes = [i, p, d, p, p]
         L.orc_step.restype = i
         L.orc_step.argtypes = [C.POINTER(Particles), C.POINTER(Particles), C.POINTER(Params), C.POINTER(Out)]
         L.orc_step_sel.restype = i
@@ -126,6 +128,20 @@ def hyp1f1_negx_v(a: float, b: float, x) -> np.ndarray:
 
 def alpha_n(n: int) -> float:
     return lib().orc_alpha_n(int(n))
+
+
+def rb_radius(m: int, a: float, u0: float) -> float:
+    """|u|/varsigma of the tilted law |u|^m N(u; w, varsigma^2 I) at uniform u0, a = |w|/varsigma."""
+    return lib().orc_rb_radius(int(m), float(a), float(u0))
+
+
+def rb_urel(n: int, w_, vs: float, u) -> np.ndarray:
+    """Tilted relative velocity (Rao-Blackwellised partner draw) for w, varsigma and uniforms u[0..2]."""
+    w_ = np.ascontiguousarray(w_, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_rb_urel(int(n), w_.ctypes.data, float(vs), u.ctypes.data, out.ctypes.data)
+    return out
 
 
 def rates(n: int, w_: float, vs: float) -> tuple[float, float]:
@@ -194,7 +210,8 @@ def _params(p: dict) -> Params:
     return Params(float(p["sigma0_cm2"]), int(p.get("n_pow", 0)), float(p["m_chi_g"]), float(p["dt"]),
                   int(p["seed"]) & 0xFFFFFFFFFFFFFFFF, int(p.get("step", 0)) & 0xFFFFFFFF,
                   int(p.get("box_id", 0)), (C.c_double * 3)(*[float(b) for b in box]),
-                  float(p.get("aniso_g", 0.0)), 1 if p.get("rates") == 3 else 0)
+                  float(p.get("aniso_g", 0.0)), 1 if p.get("rates") == 3 else 0,
+                  1 if p.get("dm_sampling") == 1 else 0)
 
 
 def step(gas: dict, dm: dict, params: dict, gas_sel=None, dm_sel=None, peak_scale=False, grid=False) -> dict:

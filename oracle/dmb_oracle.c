@@ -266,7 +266,8 @@ double orc_u24(uint32_t r) { return ((double)(r >> 8) + 0.5) * (1.0 / 16777216.0
 /* Stream layout: key = (seed lo32, seed hi32); counter = (dm index, gas index,
  * step, tag | box << 8).  Tag 0: gas-velocity sample of pair (i,j); tag 1:
  * scattering direction of pair (i,j); tag 2: per-DM decision uniform (gas
- * index 0xFFFFFFFF).                                                         */
+ * index 0xFFFFFFFF); tag 5: tilted relative velocity of the chosen pair
+ * (Rao-Blackwellised sampling only).                                         */
 static void orc_block(uint64_t seed, uint32_t i, uint32_t j, uint32_t step, uint32_t tag, uint32_t box,
                       double u[4])
 {
@@ -311,6 +312,7 @@ typedef struct {
     double aniso_g;           /* dsigma/dOmega = sigma(v) p(Omega): Henyey-Greenstein p with mean
                                  cos theta = g (0: isotropic); sigma-bar = (1 - g) sigma */
     int gas_closure;          /* 1: each gas takes the per-gas Maxwellian closure of its DM neighbours */
+    int dm_rb;                /* 1: Rao-Blackwellised DM sampling (expected P_ij, tilted partner draw) */
 } orc_params;
 
 enum { ORC_C_PAIRS_GAS = 0, ORC_C_PAIRS_DM, ORC_C_SCATTERS, ORC_C_NEAR_BOUNDARY, ORC_C_NEAR_DECISION,
@@ -515,11 +517,152 @@ static void pair_urel(const orc_particles *gas, const orc_particles *dm, const o
     for (int k = 0; k < 3; k++) urel[k] = dm->vel[3 * i + k] - (gas->vel[3 * j + k] + vs * z[k]);
 }
 
+/* ------------------------------------------------------------------------- */
+/* Rao-Blackwellised DM sampling (a variant of Sec. 2.2 that is exact in law;
+ * not the paper's scheme).  Pair (i,j) takes the expectation of its
+ * scattering probability over the Maxwellian gas-velocity sample,
+ *   Pbar_ij = (M_j/mu_j) g_ij sigma0 c^-n dt_i E|w - varsigma_j z|^{n+1},
+ * w = v_i - V_j, z ~ N(0, I).  For u ~ N(w, varsigma^2 I), E|u|^{n+3} is the
+ * Bhat integral of power n (eq. scrB without sigma0 c^-n), so E|u|^{n+1} is
+ * Bhat of power n - 2 (finite for n > -4).  A DM that scatters with partner
+ * j draws its relative velocity from the tilted law
+ *   p(u) ~ |u|^{n+1} N(u; w, varsigma^2 I),
+ * the law of u given a scatter with j in the per-pair scheme; so partner and
+ * u have the per-pair scheme's joint distribution whenever P_i <= 1.  The
+ * draw is by inversion from the tag-5 block (u0, u1, u2) of the pair: in
+ * units of varsigma, r = |u| has density proportional to
+ *   r^{n+2} e^{-(r-a)^2/2} (1 - e^{-2 r a}) / (2a),  a = |w|/varsigma
+ * (r^{n+3} e^{-r^2/2} at a = 0), inverted at u0 (lower CDF for u0 <= 1/2,
+ * upper tail otherwise); given r, c = cos(u, w) has density ~ e^{r a c} on
+ * [-1, 1], inverted at u1 (1 - c = -ln(1 - u1 (1 - e^{-2ra})) / (ra)); the
+ * azimuth is 2 pi u2 in the frame basis_around(w/|w|) (the z axis if w = 0).
+ * Cold gas (varsigma = 0) gives u = w.  The radial CDF is integrated here by
+ * adaptive 20-point Gauss-Legendre (nodes from Newton on P_20; halves
+ * until two levels agree to 4e-15, at most 8 levels deep) and inverted by
+ * bisection to the last bit.                                           */
+static void basis_around(const double n[3], double e1[3], double e2[3]);
+static double rb_gl_x[20], rb_gl_w[20];
+static int rb_gl_ready = 0;
+
+static void rb_gl_init(void)
+{
+    if (__atomic_load_n(&rb_gl_ready, __ATOMIC_ACQUIRE)) return;
+#pragma omp critical(orc_rb_gl)
+    {
+    if (!rb_gl_ready) {
+    const int K = 20;
+    for (int i = 0; i < K; i++) {
+        double x = cos(ORC_PI * (i + 0.75) / (K + 0.5)), dp = 1.0;
+        for (int it = 0; it < 200; it++) {
+            double pm = 1.0, pk = x;
+            for (int k = 2; k <= K; k++) { double pn = ((2 * k - 1) * x * pk - (k - 1) * pm) / k; pm = pk; pk = pn; }
+            dp = K * (pm - x * pk) / (1.0 - x * x);
+            double dx = pk / dp;
+            x -= dx;
+            if (fabs(dx) <= 1e-17) break;
+        }
+        double pm = 1.0, pk = x;
+        for (int k = 2; k <= K; k++) { double pn = ((2 * k - 1) * x * pk - (k - 1) * pm) / k; pm = pk; pk = pn; }
+        dp = K * (pm - x * pk) / (1.0 - x * x);
+        rb_gl_x[i] = x;
+        rb_gl_w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+    __atomic_store_n(&rb_gl_ready, 1, __ATOMIC_RELEASE);
+    }
+    }
+}
+
+/* radial density of the tilted law (unnormalised), m = n + 1 */
+static double rb_radial(int m, double a, double r)
+{
+    if (!(r > 0.0)) return 0.0;
+    double sh = a > 0.0 ? -expm1(-2.0 * r * a) / (2.0 * a) : r;
+    return pow(r, m + 1) * exp(-0.5 * (r - a) * (r - a)) * sh;
+}
+
+static double rb_gl(int m, double a, double lo, double hi)
+{
+    double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo), s = 0.0;
+    for (int k = 0; k < 20; k++) s += rb_gl_w[k] * rb_radial(m, a, c + h * rb_gl_x[k]);
+    return s * h;
+}
+
+static double rb_adapt(int m, double a, double lo, double hi, double whole, int depth)
+{
+    double mid = 0.5 * (lo + hi);
+    double l = rb_gl(m, a, lo, mid), r = rb_gl(m, a, mid, hi);
+    /* below width 24/2^8 the 20-point rule is exact to rounding for this integrand (unit scale) */
+    if (depth >= 8 || fabs(l + r - whole) <= 4e-15 * fabs(l + r)) return l + r;
+    return rb_adapt(m, a, lo, mid, l, depth + 1) + rb_adapt(m, a, mid, hi, r, depth + 1);
+}
+
+static double rb_int(int m, double a, double lo, double hi)
+{
+    if (!(hi > lo)) return 0.0;
+    return rb_adapt(m, a, lo, hi, rb_gl(m, a, lo, hi), 0);
+}
+
+/* r = |u| / varsigma of the tilted law at uniform u0; support [max(0, a - 12), a + 12] */
+double orc_rb_radius(int m, double a, double u0)
+{
+    rb_gl_init();
+    double lo = fmax(0.0, a - 12.0), hi = a + 12.0;
+    double Z = rb_int(m, a, lo, hi);
+    double bl = lo, bh = hi;
+    if (u0 <= 0.5) {
+        double T = u0 * Z;
+        for (int it = 0; it < 200; it++) {
+            double mid = 0.5 * (bl + bh);
+            if (!(mid > bl && mid < bh)) break;
+            if (rb_int(m, a, lo, mid) < T) bl = mid; else bh = mid;
+        }
+    } else {
+        double T = (1.0 - u0) * Z;
+        for (int it = 0; it < 200; it++) {
+            double mid = 0.5 * (bl + bh);
+            if (!(mid > bl && mid < bh)) break;
+            if (rb_int(m, a, mid, hi) > T) bl = mid; else bh = mid;
+        }
+    }
+    return 0.5 * (bl + bh);
+}
+
+/* the tilted relative velocity for w (km/s), varsigma vs, power n, uniforms u[0..2] */
+void orc_rb_urel(int n, const double w[3], double vs, const double u[3], double urel[3])
+{
+    double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    if (!(vs > 0.0)) { for (int k = 0; k < 3; k++) urel[k] = w[k]; return; }
+    double a = wn / vs;
+    double r = orc_rb_radius(n + 1, a, u[0]);
+    double kap = r * a;
+    double omc = kap > 0.0 ? -log1p(u[1] * expm1(-2.0 * kap)) / kap : 2.0 * u[1];  /* 1 - cos */
+    double c = 1.0 - omc, s = sqrt(fmax(0.0, omc * (2.0 - omc)));
+    double e[3] = {0.0, 0.0, 1.0}, e1[3], e2[3];
+    if (wn > 0.0) for (int k = 0; k < 3; k++) e[k] = w[k] / wn;
+    basis_around(e, e1, e2);
+    double ph = 2.0 * ORC_PI * u[2];
+    for (int k = 0; k < 3; k++) urel[k] = vs * r * (c * e[k] + s * (cos(ph) * e1[k] + sin(ph) * e2[k]));
+}
+
 /* Scattering probability P_ij = (M_j/mu_j) g_ij sigma(v_rel) v_rel dt_i
- * (eq. dm-update-prob), sigma = sigma0 (v/c)^n.                              */
+ * (eq. dm-update-prob), sigma = sigma0 (v/c)^n.  Rao-Blackwellised: the
+ * expectation over the gas-velocity sample (urel is then set by dm_one).    */
 static double pair_P(const orc_particles *gas, const orc_particles *dm, const orc_params *par, int64_t j,
                      int64_t i, double d, double urel[3])
 {
+    if (par->dm_rb) {
+        double w2 = 0.0, A, Bm;
+        for (int k = 0; k < 3; k++) {
+            double w = dm->vel[3 * i + k] - gas->vel[3 * j + k];
+            w2 += w * w;
+            urel[k] = 0.0;
+        }
+        orc_rates(par->n_pow - 2, sqrt(w2), gas_vs(gas, j), &A, &Bm);
+        double g = orc_overlap(d, dm->h[i], gas->h[j]);
+        double ncount = gas->mass[j] * ORC_MSUN_G / gas_mu(gas, j);
+        double sig = par->sigma0_cm2 / (ORC_KPC_CM * ORC_KPC_CM) * pow(ORC_C_KMS, -par->n_pow);
+        return ncount * g * sig * Bm * p_dt(dm, par, i);
+    }
     pair_urel(gas, dm, par, j, i, urel);
     double vrel = sqrt(urel[0] * urel[0] + urel[1] * urel[1] + urel[2] * urel[2]);
     double g = orc_overlap(d, dm->h[i], gas->h[j]);
@@ -637,6 +780,12 @@ static void dm_one(const orc_particles *gas, const orc_particles *dm, const orc_
         cnt[ORC_C_SCATTERS]++;
         out->partner[i] = (int32_t)jstar;
         double *ur = pairs[kstar].urel;
+        if (par->dm_rb) {
+            double ut[4], w[3];
+            orc_block(par->seed, (uint32_t)i, (uint32_t)jstar, par->step, 5u, par->box_id, ut);
+            for (int k = 0; k < 3; k++) w[k] = dm->vel[3 * i + k] - gas->vel[3 * jstar + k];
+            orc_rb_urel(par->n_pow, w, gas_vs(gas, jstar), ut, ur);
+        }
         double vrel = sqrt(ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2]);
         if (vrel > 0.0) {
             double ua[4];

@@ -642,3 +642,122 @@ def test_gas_closure_single_velocity_reduces_to_pair_sum(orc, n_pow, T):
     assert pair["counters"]["pairs_gas"] == clos["counters"]["pairs_gas"] == N
     np.testing.assert_allclose(clos["dp_gas"][0], pair["dp_gas"][0], rtol=1e-11)
     np.testing.assert_allclose(clos["de_gas"][0], pair["de_gas"][0], rtol=1e-11)
+
+
+# --------------------------------------------------------------------------- Rao-Blackwellised DM sampling
+@pytest.mark.parametrize("n_pow", [-2, 0, 2])
+def test_rb_expected_probability_is_the_mean_of_P(orc, n_pow):
+    """Pbar_ij uses E|w - varsigma z|^{n+1} = Bhat of power n - 2.  Checked
+    against a 4M-sample numpy average, against the textbook means of the
+    noncentral chi distribution with 3 degrees of freedom (E 1/|u| =
+    erf(a/sqrt2)/(a vs), E|u| = vs [sqrt(2/pi) e^{-a^2/2} + (a + 1/a)
+    erf(a/sqrt2)]), and at the step level: the Rao-Blackwellised P_i equals
+    the mean over Philox steps of the per-pair P_i (5 standard errors)."""
+    from scipy.special import erf
+    r = np.random.default_rng(7)
+    z = r.normal(size=(4_000_000, 3))
+    for w, vs in ((3.0, 2.0), (0.4, 1.5), (12.0, 1.0)):
+        v = np.linalg.norm(np.array([w, 0.0, 0.0]) - vs * z, axis=1) ** (n_pow + 1)
+        got = orc.rates(n_pow - 2, w, vs)[1]
+        assert abs(got - v.mean()) < 5 * v.std() / math.sqrt(len(v)), (w, vs, got, v.mean())
+        a = w / vs
+        if n_pow == -2:
+            assert got == pytest.approx(erf(a / math.sqrt(2)) / (a * vs), rel=1e-13)
+        if n_pow == 0:
+            ref = vs * (math.sqrt(2 / math.pi) * math.exp(-a * a / 2) + (a + 1 / a) * erf(a / math.sqrt(2)))
+            assert got == pytest.approx(ref, rel=1e-13)
+    gas, dm, par = _pair_system(3e-23, n_gas=4, seed=3)
+    par["n_pow"] = n_pow
+    par["sigma0_cm2"] = workloads.sigma0_for_npow(n_pow, 60.0, 3e-23)
+    rb = orc.step(gas, dm, dict(par, dm_sampling=1))["p_sum"][0]
+    S = 3000
+    ps = np.empty(S)
+    for s in range(S):
+        par["step"] = s
+        ps[s] = orc.step(gas, dm, par)["p_sum"][0]
+    assert abs(ps.mean() - rb) < 5 * ps.std() / math.sqrt(S), (ps.mean(), rb)
+
+
+def _tilted_radial_cdf(m, a, r):
+    """CDF of |u| for the law |u|^m N(u; a e_x, I), from the 3-D definition:
+    the density on the sphere |u| = t is t^{m+2} times the angular integral of
+    the Gaussian, both integrated numerically."""
+    from scipy import integrate
+
+    def shell(t):
+        ang = integrate.quad(lambda c: math.exp(-0.5 * (t * t + a * a - 2 * t * a * c)), -1.0, 1.0,
+                             epsabs=0, epsrel=1e-13)[0]
+        return t ** (m + 2) * ang
+    lo, hi = max(0.0, a - 12.0), a + 12.0
+    Z = integrate.quad(shell, lo, hi, epsabs=0, epsrel=1e-12, limit=200)[0]
+    return integrate.quad(shell, lo, min(max(r, lo), hi), epsabs=0, epsrel=1e-12, limit=200)[0] / Z
+
+
+@pytest.mark.parametrize("m", [-1, 1, 3])
+def test_rb_radius_inverts_the_tilted_radial_law(orc, m):
+    """The tilted radius at uniform u has CDF value u under the radial law
+    built numerically from the 3-D density |u|^m N(u; w, I)."""
+    for a in (0.0, 0.05, 1.3, 7.0):
+        for u in (1e-3, 0.2, 0.5, 0.8, 0.999):
+            r = orc.rb_radius(m, a, u)
+            F = _tilted_radial_cdf(m, a, r)
+            assert abs(F - u) < 1e-9 * max(min(u, 1 - u), 1e-3), (m, a, u, r, F)
+
+
+@pytest.mark.parametrize("n_pow", [-2, 0, 2])
+def test_rb_urel_follows_the_tilted_law(orc, n_pow):
+    """Moments of the tilted draw (orc_rb_urel with independent uniforms)
+    against importance-weighted moments of plain Gaussian samples (weights
+    |u|^{n+1}): mean vector, E|u|^2 and E u_k^2, within 5 standard errors."""
+    r = np.random.default_rng(11 + n_pow)
+    w, vs = np.array([30.0, -20.0, 10.0]), 25.0
+    N = 6000
+    U = r.uniform(size=(N, 3))
+    S = np.array([orc.rb_urel(n_pow, w, vs, U[k]) for k in range(N)])
+    z = r.normal(size=(4_000_000, 3))
+    u = w - vs * z
+    wt = np.linalg.norm(u, axis=1) ** (n_pow + 1)
+    wt /= wt.sum()
+    for f in (lambda x: x[:, 0], lambda x: x[:, 1], lambda x: x[:, 2], lambda x: (x * x).sum(1),
+              lambda x: x[:, 0] ** 2, lambda x: x[:, 2] ** 2):
+        ref = (wt * f(u)).sum()
+        got = f(S)
+        assert abs(got.mean() - ref) < 5 * got.std() / math.sqrt(N), (got.mean(), ref)
+    # cold gas: u = w exactly
+    assert np.array_equal(orc.rb_urel(n_pow, w, 0.0, U[0]), w)
+
+
+@pytest.mark.parametrize("n_pow", [0, -2])
+def test_rb_scheme_is_exact_in_law(orc, n_pow):
+    """With P_i <= 1 the Rao-Blackwellised scheme gives the per-pair scheme's
+    joint law of (partner, kick): over many Philox steps the partner
+    frequencies agree (chi-square on the two-sample table) and so do the
+    mean kick vector and mean |dv|^2 per partner (5 standard errors)."""
+    from scipy.stats import chi2_contingency
+    gas, dm, par = _pair_system(3e-23, n_gas=3, seed=5)
+    par["n_pow"] = n_pow
+    par["sigma0_cm2"] = workloads.sigma0_for_npow(n_pow, 60.0, 2.5e-22)
+    S = 8000
+    res = {}
+    for mode in (0, 1):
+        parts = np.empty(S, np.int64)
+        dv = np.empty((S, 3))
+        pmax = 0.0
+        for s in range(S):
+            out = orc.step(gas, dm, dict(par, step=s, dm_sampling=mode))
+            parts[s] = out["partner"][0]
+            dv[s] = out["dv_dm"][0]
+            pmax = max(pmax, out["p_sum"][0])
+        assert pmax < 1.0
+        res[mode] = (parts, dv)
+    (p0, d0), (p1, d1) = res[0], res[1]
+    tab = np.array([[np.sum(p == j) for j in (-1, 0, 1, 2)] for p in (p0, p1)])
+    assert tab[:, 1:].sum() > 0.2 * S
+    assert chi2_contingency(tab)[1] > 1e-4, tab
+    for j in (0, 1, 2):
+        a, b = d0[p0 == j], d1[p1 == j]
+        if min(len(a), len(b)) < 200:
+            continue
+        for fa, fb in ((a, b), ((a * a).sum(1, keepdims=True), (b * b).sum(1, keepdims=True))):
+            se = np.sqrt(fa.var(0) / len(fa) + fb.var(0) / len(fb))
+            assert np.all(np.abs(fa.mean(0) - fb.mean(0)) < 5 * se), (j, fa.mean(0), fb.mean(0), se)
