@@ -251,6 +251,43 @@ def closure_compare(ctx, cfg, dev, steps: int, log_fn) -> dict:
     return res
 
 
+def rb_compare(ctx, cfg, dev, steps: int, log_fn) -> dict:
+    """Rao-Blackwellised DM sampling against the paper's per-pair sampling on
+    the galaxy workload in binary32: DM-pass, combine and resolve times, and
+    the pairs per second of the whole interaction step for each."""
+    import torch
+    import paper_2603_24688_amd as dmb
+    G = dmb.to_device(cfg["gas"], dev)
+    D = dmb.to_device(cfg["dm"], dev)
+    out = dmb.alloc_out(len(cfg["gas"]["mass"]), len(cfg["dm"]["mass"]), dev)
+    par = dict(cfg["params"])
+    ctx.build_cells(G, D, par, precision=dmb.DMB_FP32)
+    res = {}
+    for name, mode in (("per_pair", dmb.DMB_SAMPLE_PAIR), ("rao_blackwell", dmb.DMB_SAMPLE_RB)):
+        par["dm_sampling"] = mode
+        ctx.interact_step(G, D, par, out, precision=dmb.DMB_FP32)
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        ctx.profile_read(reset=True)
+        ta = time.perf_counter()
+        for _ in range(steps):
+            ctx.interact_step(G, D, par, out, precision=dmb.DMB_FP32)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        ph = ctx.profile_read(reset=True)
+        ctx.profile_enable(False)
+        cnt = dmb.counters_dict(out["counters"])
+        ms = (tb - ta) * 1e3 / steps
+        res[name] = {"interact_ms": round(ms, 4), "pairs_per_s": cnt["pairs_dm"] / (ms * 1e-3),
+                     "scatters": cnt["scatters"],
+                     **{f"{k}_ms": round(ph[k][0] / max(ph[k][1], 1), 4) for k in ("pass_dm", "combine_dm", "resolve")}}
+    res["dm_pass_speedup"] = res["per_pair"]["pass_dm_ms"] / res["rao_blackwell"]["pass_dm_ms"]
+    log_fn(f"bench: rao-blackwell: DM pass {res['rao_blackwell']['pass_dm_ms']:.3f} ms vs per-pair "
+           f"{res['per_pair']['pass_dm_ms']:.3f} ms; resolve {res['rao_blackwell']['resolve_ms']:.3f} vs "
+           f"{res['per_pair']['resolve_ms']:.3f} ms")
+    return res
+
+
 def batch_sweep(dev, steps: int, log_fn) -> dict:
     """Parameter sweep of 64 periodic boxes of uneven size (10^4 .. 5 10^5
     particles per species, sigma0 1e-28 .. 1e-24 cm^2, m_chi/m_p in
@@ -410,6 +447,8 @@ def main():
     ap.add_argument("--no-box", action="store_true", help="skip the 100-step time loop of the periodic test box")
     ap.add_argument("--no-milky-way", action="store_true",
                     help="skip the 200-step hierarchical-timestep run at Milky-Way scale")
+    ap.add_argument("--no-rb", action="store_true",
+                    help="skip the Rao-Blackwellised vs per-pair DM sampling comparison")
     ap.add_argument("--no-closure", action="store_true",
                     help="skip the per-gas closure vs per-pair mean-field comparison")
     ap.add_argument("--no-surrogate", action="store_true",
@@ -542,6 +581,8 @@ def main():
                          "dm": pairs / max(1, bst["cand_pairs_dm"] * 4096)},
     }
     default_run = args.workload == "galaxy" and args.rates == "exact" and args.n_pow == 0
+    if default_run and not args.no_rb:
+        line["rao_blackwell"] = rb_compare(ctx, cfg, dev, 3, log)
     if default_run and not args.no_closure:
         line["closure"] = closure_compare(ctx, cfg, dev, 3, log)
     if default_run and not args.no_surrogate:

@@ -63,6 +63,18 @@ typedef enum {
                              Not for dmb_rates_eval. */
 } dmb_rates;
 
+/* DM Monte Carlo sampling (Sec. 2.2 and an exact-in-law variant). */
+typedef enum {
+    DMB_SAMPLE_PAIR = 0,  /* the paper's scheme: one Maxwellian gas-velocity sample v_B per pair (Philox
+                             tag 0), P_ij = K_j g_ij sigma(|v_i - v_B|) |v_i - v_B| dt_i */
+    DMB_SAMPLE_RB = 1     /* Rao-Blackwellised: P_ij replaced by its expectation over v_B (the B rate
+                             integral of power n - 2), and only a DM that scatters draws the relative
+                             velocity of its chosen pair, from the |u|^{n+1}-tilted Maxwellian (Philox
+                             tag 5, by inversion).  The same joint law of partner and kick as
+                             DMB_SAMPLE_PAIR while P_i <= 1, with no per-pair random numbers.
+                             n_pow > -4 only (the expectation diverges at n = -4): DMB_EINVAL. */
+} dmb_dm_sampling;
+
 enum {
     DMB_C_PAIRS_GAS = 0,  /* pairs visited by the gas (mean-field) pass */
     DMB_C_PAIRS_DM,       /* pairs visited by the DM (Monte Carlo) pass */
@@ -109,6 +121,7 @@ typedef struct {
                                Carlo uses sigma and draws theta from p; the gas mean field uses the
                                momentum-transfer cross section sigma-bar = (1 - g) sigma (eq. scrA,
                                scrB).  Errors: DMB_EINVAL unless |g| < 1. */
+    int32_t dm_sampling;    /* dmb_dm_sampling: how the DM Monte Carlo handles the gas-velocity sample */
 } dmb_params;
 
 typedef struct {
@@ -236,10 +249,10 @@ dmb_status dmb_step_static(dmb_ctx *ctx, const dmb_particles *gas, const dmb_par
  * pairs_gas[cap][2] and pairs_dm[cap][2] (device, caller-owned), in no
  * particular order.  counts (HOST, 2 int64) receives each pass's total; when
  * a total exceeds cap, only cap pairs of that pass are written.  For checking
- * the neighbour structure: the step must use n_pow = 0 and
- * DMB_RATES_EXACT (the pair set depends on neither).  Synchronous.
+ * the neighbour structure: the step must use n_pow = 0, DMB_RATES_EXACT
+ * and DMB_SAMPLE_PAIR (the pair set depends on none of them).  Synchronous.
  * Errors: those of dmb_interact_step; DMB_EINVAL for n_pow != 0, other rate
- * modes, cap < 0, or null lists with cap > 0. */
+ * or sampling modes, cap < 0, or null lists with cap > 0. */
 dmb_status dmb_pair_list(dmb_ctx *ctx, const dmb_particles *gas, const dmb_particles *dm,
                          const dmb_params *params, dmb_out *out, int64_t cap, uint32_t *pairs_gas,
                          uint32_t *pairs_dm, int64_t *counts);

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(PKG, "libdmb.so")
 
 DMB_FP64, DMB_FP32 = 0, 1
 DMB_RATES_EXACT, DMB_RATES_QUAD, DMB_RATES_MLP, DMB_RATES_CLOSURE = 0, 1, 2, 3
+DMB_SAMPLE_PAIR, DMB_SAMPLE_RB = 0, 1
 MLP_PARAMS = 8834
 COUNTER_NAMES = ["pairs_gas", "pairs_dm", "scatters", "near_boundary", "near_decision",
                  "crit_viol", "p_ge_1", "nonfinite"]
@@ -47,7 +48,8 @@ class Particles(C.Structure):
 class Params(C.Structure):
     _fields_ = [("sigma0_cm2", C.c_double), ("n_pow", C.c_int32), ("m_chi_g", C.c_double), ("dt", C.c_double),
                 ("seed", C.c_uint64), ("step", C.c_uint32), ("box_id", C.c_uint32), ("box", C.c_double * 3),
-                ("precision", C.c_int32), ("rates", C.c_int32), ("quad_nodes", C.c_int32), ("aniso_g", C.c_double)]
+                ("precision", C.c_int32), ("rates", C.c_int32), ("quad_nodes", C.c_int32), ("aniso_g", C.c_double),
+                ("dm_sampling", C.c_int32)]
 
 
 class Out(C.Structure):
@@ -156,7 +158,7 @@ def _params(p: dict, precision: int) -> Params:
     return Params(float(p["sigma0_cm2"]), int(p.get("n_pow", 0)), float(p["m_chi_g"]), float(p["dt"]),
                   int(p["seed"]) & 0xFFFFFFFFFFFFFFFF, int(p.get("step", 0)) & 0xFFFFFFFF, int(p.get("box_id", 0)),
                   (C.c_double * 3)(*[float(b) for b in box]), int(precision), int(p.get("rates", DMB_RATES_EXACT)),
-                  int(p.get("quad_nodes", 0)), float(p.get("aniso_g", 0.0)))
+                  int(p.get("quad_nodes", 0)), float(p.get("aniso_g", 0.0)), int(p.get("dm_sampling", 0)))
 
 
 class Context:

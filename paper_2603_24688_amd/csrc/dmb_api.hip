@@ -92,6 +92,7 @@ struct dmb_ctx {
     hipStream_t stream = nullptr;
     int num_cu = 256;
     DevBuf gtab;
+    DevBuf tilt_gl;                        // 16-point Gauss-Legendre rule of the Rao-Blackwellised draw
     Cells cells;                           // single-box structure
     Cells* X = &cells;                     // structure the internal build / step functions act on
     std::vector<Cells*> boxes;             // batched boxes
@@ -653,6 +654,8 @@ dmb_status gather_and_fill(dmb_ctx* c, Cells& X, const dmb_particles* gas, const
         ga.n = G.n; ga.perm = G.perm; ga.vel = gas->vel; ga.mass = gas->mass; ga.u = gas->u; ga.mu = gas->mu;
         ga.m_chi = par->m_chi_g; ga.sig_kpc2_cn = sig_kpc2_cn_of(par); ga.alpha_n = alpha_n(par->n_pow);
         ga.n_pow = par->n_pow;
+        ga.rb = par->dm_sampling == DMB_SAMPLE_RB;
+        ga.alpha_rb = ga.rb ? alpha_n(par->n_pow - 2) : 0.0;
         ga.Vx = G.v0.as<double>(); ga.Vy = G.v1.as<double>(); ga.Vz = G.v2.as<double>();
         ga.flag = G.flag.as<const uint32_t>(); ga.flag_off = G.flag_off.as<const uint32_t>();
         ga.orate = G.orate.p;
@@ -757,7 +760,7 @@ DmPassArgs dm_pass_args(dmb_ctx* c, Cells& X, const dmb_params* par, dmb_out* ou
     return a;
 }
 
-template <typename Real, int N>
+template <typename Real, int N, bool RB>
 void combine_dm_and_resolve(dmb_ctx* c, Cells& X, const DmPassArgs& a, const dmb_particles* gas,
                             const dmb_params* par, dmb_out* out, uint64_t* counters)
 {
@@ -784,13 +787,37 @@ void combine_dm_and_resolve(dmb_ctx* c, Cells& X, const DmPassArgs& a, const dmb
     r.gas_vel = gas->vel; r.gas_u = gas->u; r.gas_mu = gas->mu; r.m_chi = par->m_chi_g;
     r.gtab = a.gtab; r.k0 = a.k0; r.k1 = a.k1; r.step = a.step; r.box = a.box; r.step_off = a.step_off;
     r.aniso_g = par->aniso_g;
+    r.tilt_gl = c->tilt_gl.as<const double>();
     r.n_gas_bits = bits_for(std::max<int64_t>(G.n, 2));
     r.n_gas = uint32_t(G.n);
     r.scount = a.scount; r.slist = X.slist.as<const uint32_t>();
     r.dv = out->dv_dm; r.partner = out->partner; r.counters = counters;
     Phase ph(c, DMB_PH_RESOLVE);
-    hipLaunchKernelGGL((k_resolve<Real, N, kExact>), dim3(std::max(8, c->num_cu * 2)), dim3(kResolveThreads), 0,
+    hipLaunchKernelGGL((k_resolve<Real, N, kExact, RB>), dim3(std::max(8, c->num_cu * 2)), dim3(kResolveThreads), 0,
                        c->stream, r);
+    if constexpr (RB)
+        hipLaunchKernelGGL((k_rb_kick<Real, N>), dim3(std::max(8, c->num_cu * 4)), dim3(64), 0, c->stream, r);
+}
+
+// The DM side of one step: the pair pass, the combine and decision, the resolve.
+// RB: Rao-Blackwellised sampling (expected P_ij, tilted partner draw).
+template <typename Real, int N, bool RB, bool PAIRS>
+void dm_side(dmb_ctx* c, Cells& X, const dmb_particles* gas, const dmb_params* par, dmb_out* out,
+             uint64_t* counters)
+{
+    constexpr bool kExact = sizeof(Real) == 8;
+    DmPassArgs a = dm_pass_args(c, X, par, out, counters, nullptr);
+    if constexpr (PAIRS) {
+        a.g.pairs = c->pair_dst[1]; a.g.pair_cap = uint64_t(c->pair_cap);
+        a.g.pair_n = c->S->pair_cnt.as<unsigned long long>() + 1;
+    }
+    const int nb = persist_blocks(c, (const void*)k_pass_dm<Real, N, kExact, false, PAIRS, RB>, 64, X.dp.nitems);
+    {
+        Phase ph(c, DMB_PH_PASS_DM);
+        hipLaunchKernelGGL((k_pass_dm<Real, N, kExact, false, PAIRS, RB>), dim3(nb), dim3(64), 0, c->stream, a,
+                           (const DmPassArgs*)nullptr, (const int64_t*)nullptr, 0);
+    }
+    combine_dm_and_resolve<Real, N, RB>(c, X, a, gas, par, out, counters);
 }
 
 template <typename Real, int N, int RM, bool PAIRS = false>
@@ -822,18 +849,14 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
         combine_gas<N, RM>(c, X, gas, par, out);
     }
     if (X.dp.nitems > 0) {
-        DmPassArgs a = dm_pass_args(c, X, par, out, counters, nullptr);
-        if constexpr (PAIRS) {
-            a.g.pairs = c->pair_dst[1]; a.g.pair_cap = uint64_t(c->pair_cap);
-            a.g.pair_n = c->S->pair_cnt.as<unsigned long long>() + 1;
+        bool done = false;
+        if constexpr (N > -4 && !PAIRS) {
+            if (par->dm_sampling == DMB_SAMPLE_RB) {
+                dm_side<Real, N, true, false>(c, X, gas, par, out, counters);
+                done = true;
+            }
         }
-        const int nb = persist_blocks(c, (const void*)k_pass_dm<Real, N, kExact, false, PAIRS>, 64, X.dp.nitems);
-        {
-            Phase ph(c, DMB_PH_PASS_DM);
-            hipLaunchKernelGGL((k_pass_dm<Real, N, kExact, false, PAIRS>), dim3(nb), dim3(64), 0, c->stream, a,
-                               (const DmPassArgs*)nullptr, (const int64_t*)nullptr, 0);
-        }
-        combine_dm_and_resolve<Real, N>(c, X, a, gas, par, out, counters);
+        if (!done) dm_side<Real, N, false, PAIRS>(c, X, gas, par, out, counters);
     }
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
@@ -850,6 +873,7 @@ struct BatchPlan {
     std::vector<GasPassArgs> ga;
     std::vector<DmPassArgs> da;
     int nb_gas = 0, nb_dm = 0;
+    bool rb = false;                       // Rao-Blackwellised DM sampling
 };
 
 template <typename Real, int N, int RM>
@@ -909,8 +933,33 @@ dmb_status batch_prepare(dmb_ctx* c, int nbox, const dmb_particles* gas, const d
     HIPCHK(c, hipStreamSynchronize(c->stream));
     P.nb_gas = persist_blocks(c, (const void*)k_pass_gas<Real, N, kExact, RM, true>, 64 * kW,
                               (P.gas_items + kW - 1) / kW);
-    P.nb_dm = persist_blocks(c, (const void*)k_pass_dm<Real, N, kExact, true>, 64, P.dm_items);
+    P.rb = false;
+    if constexpr (N > -4) P.rb = par[0].dm_sampling == DMB_SAMPLE_RB;
+    const void* dm_kernel = (const void*)k_pass_dm<Real, N, kExact, true>;
+    if constexpr (N > -4)
+        if (P.rb) dm_kernel = (const void*)k_pass_dm<Real, N, kExact, true, false, true>;
+    P.nb_dm = persist_blocks(c, dm_kernel, 64, P.dm_items);
     return DMB_OK;
+}
+
+// The DM side of a batched step: one pass over all boxes' items, then the
+// per-box combines and resolves.
+template <typename Real, int N, bool RB>
+void batch_dm_side(dmb_ctx* c, const dmb_particles* gas, const dmb_params* par, dmb_out* out, const BatchPlan& P,
+                   const DmPassArgs* ddev, const int64_t* ditems)
+{
+    constexpr bool kExact = sizeof(Real) == 8;
+    DmPassArgs a0 = P.da[0];
+    a0.g.queue_ctr = c->bstep.as<uint32_t>() + kXcd;
+    a0.g.n_items = P.dm_items;
+    {
+        Phase ph(c, DMB_PH_PASS_DM);
+        hipLaunchKernelGGL((k_pass_dm<Real, N, kExact, true, false, RB>), dim3(P.nb_dm), dim3(64), 0, c->stream, a0,
+                           ddev, ditems, P.nbox);
+    }
+    for (int b = 0; b < P.nbox; ++b)
+        if (c->boxes[b]->dp.nitems > 0)
+            combine_dm_and_resolve<Real, N, RB>(c, *c->boxes[b], P.da[b], gas + b, par + b, out + b, out[b].counters);
 }
 
 template <typename Real, int N, int RM>
@@ -945,17 +994,14 @@ dmb_status batch_enqueue(dmb_ctx* c, const dmb_particles* gas, const dmb_particl
             if (c->boxes[b]->gp.nitems > 0) combine_gas<N, RM>(c, *c->boxes[b], gas + b, par + b, out + b);
     }
     if (P.dm_items > 0) {
-        DmPassArgs a0 = P.da[0];
-        a0.g.queue_ctr = c->bstep.as<uint32_t>() + kXcd;
-        a0.g.n_items = P.dm_items;
-        {
-            Phase ph(c, DMB_PH_PASS_DM);
-            hipLaunchKernelGGL((k_pass_dm<Real, N, kExact, true>), dim3(P.nb_dm), dim3(64), 0, c->stream, a0, ddev,
-                               ditems, nbox);
+        bool done = false;
+        if constexpr (N > -4) {
+            if (P.rb) {
+                batch_dm_side<Real, N, true>(c, gas, par, out, P, ddev, ditems);
+                done = true;
+            }
         }
-        for (int b = 0; b < nbox; ++b)
-            if (c->boxes[b]->dp.nitems > 0)
-                combine_dm_and_resolve<Real, N>(c, *c->boxes[b], P.da[b], gas + b, par + b, out + b, out[b].counters);
+        if (!done) batch_dm_side<Real, N, false>(c, gas, par, out, P, ddev, ditems);
     }
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
@@ -1256,12 +1302,21 @@ dmb_status dmb_create(dmb_ctx** out, int device, void* hip_stream)
     const int64_t nnodes = 2 * int64_t(kTabNodesRegion);
     DevBuf nodes;
     if (ensure(c, c->gtab, tb) != DMB_OK || ensure(c, c->X->boxL, 4 * sizeof(double)) != DMB_OK ||
-        ensure(c, c->os_err, sizeof(uint32_t)) != DMB_OK ||
+        ensure(c, c->os_err, sizeof(uint32_t)) != DMB_OK || ensure(c, c->tilt_gl, 32 * sizeof(double)) != DMB_OK ||
         ensure(c, nodes, size_t(nnodes) * 3 * sizeof(double)) != DMB_OK) {
         snprintf(g_create_err, sizeof(g_create_err), "%s", c->err);
         if (nodes.p) (void)hipFree(nodes.p);
         dmb_destroy(c);
         return DMB_ENOMEM;
+    }
+    double tilt_rule[32];
+    gauss_legendre(16, tilt_rule, tilt_rule + 16);
+    he = hipMemcpyAsync(c->tilt_gl.p, tilt_rule, sizeof(tilt_rule), hipMemcpyHostToDevice, c->stream);
+    if (he != hipSuccess) {
+        snprintf(g_create_err, sizeof(g_create_err), "node upload: %s", hipGetErrorString(he));
+        (void)hipFree(nodes.p);
+        dmb_destroy(c);
+        return DMB_EHIP;
     }
     hipLaunchKernelGGL(k_os_clear, dim3(1), dim3(256), 0, c->stream, c->os_err.as<uint32_t>(), 1);
     hipLaunchKernelGGL(k_gtab_build, dim3(blocks_for(nnodes, 256)), dim3(256), 0, c->stream, nodes.as<double>());
@@ -1307,7 +1362,7 @@ dmb_status dmb_destroy(dmb_ctx* c)
                      &c->mlp_loss, &c->mlp_epoch, &c->mlp_shuf};
     for (DevBuf* b : mlp) fr(*b);
     if (c->train_stream) hipStreamDestroy(c->train_stream);
-    DevBuf* rest[] = {&c->gl64, &c->gl32, &c->gtab, &c->heap.os_hist, &c->heap.os_status, &c->os_err,
+    DevBuf* rest[] = {&c->gl64, &c->gl32, &c->gtab, &c->tilt_gl, &c->heap.os_hist, &c->heap.os_status, &c->os_err,
                       &c->heap.bbox_part, &c->heap.counters_local, &c->heap.pair_cnt, &c->bstep, &c->bgeom,
                       &c->bitem, &c->heap.rb_dev};
     for (DevBuf* b : rest) fr(*b);
@@ -1601,6 +1656,10 @@ dmb_status check_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles*
         return fail(c, DMB_EINVAL, "quad_nodes %d outside 4..%d", par->quad_nodes, kMaxQuadNodes);
     if (!(par->m_chi_g > 0.0) || !(par->sigma0_cm2 >= 0.0)) return fail(c, DMB_EINVAL, "bad m_chi or sigma0");
     if (!(std::fabs(par->aniso_g) < 1.0)) return fail(c, DMB_EINVAL, "aniso_g %g outside (-1, 1)", par->aniso_g);
+    if (par->dm_sampling != DMB_SAMPLE_PAIR && par->dm_sampling != DMB_SAMPLE_RB)
+        return fail(c, DMB_EINVAL, "dm_sampling %d not supported", par->dm_sampling);
+    if (par->dm_sampling == DMB_SAMPLE_RB && par->n_pow <= -4)
+        return fail(c, DMB_EINVAL, "Rao-Blackwellised sampling needs n_pow > -4 (the expectation diverges)");
     return DMB_OK;
 }
 }  // namespace
@@ -1632,8 +1691,8 @@ dmb_status dmb_pair_list(dmb_ctx* c, const dmb_particles* gas, const dmb_particl
     c->X = &c->cells;
     dmb_status s0 = check_step(c, gas, dm, par, out);
     if (s0 != DMB_OK) return s0;
-    if (par->n_pow != 0 || par->rates != DMB_RATES_EXACT)
-        return fail(c, DMB_EINVAL, "pair_list: needs n_pow 0 and DMB_RATES_EXACT");
+    if (par->n_pow != 0 || par->rates != DMB_RATES_EXACT || par->dm_sampling != DMB_SAMPLE_PAIR)
+        return fail(c, DMB_EINVAL, "pair_list: needs n_pow 0, DMB_RATES_EXACT and DMB_SAMPLE_PAIR");
     if (cap < 0 || (cap > 0 && (!pairs_gas || !pairs_dm)) || !counts)
         return fail(c, DMB_EINVAL, "pair_list: bad list arguments");
     if (par->precision != DMB_FP64 && par->precision != DMB_FP32)
@@ -2211,13 +2270,18 @@ dmb_status batch_step_checked(dmb_ctx* c, int32_t nbox, const dmb_particles* gas
         return fail(c, DMB_EINVAL, "rates mode %d not supported", p0.rates);
     if (p0.rates == DMB_RATES_MLP && (!c->mlp_ready || p0.precision != DMB_FP32))
         return fail(c, DMB_EINVAL, "network rates need loaded weights and DMB_FP32");
+    if (p0.dm_sampling != DMB_SAMPLE_PAIR && p0.dm_sampling != DMB_SAMPLE_RB)
+        return fail(c, DMB_EINVAL, "dm_sampling %d not supported", p0.dm_sampling);
+    if (p0.dm_sampling == DMB_SAMPLE_RB && p0.n_pow <= -4)
+        return fail(c, DMB_EINVAL, "Rao-Blackwellised sampling needs n_pow > -4 (the expectation diverges)");
     if ((p0.rates == DMB_RATES_QUAD || p0.rates == DMB_RATES_MLP) && (quad_k(&p0) < 4 || quad_k(&p0) > kMaxQuadNodes))
         return fail(c, DMB_EINVAL, "quad_nodes %d outside 4..%d", p0.quad_nodes, kMaxQuadNodes);
     for (int b = 0; b < nbox; ++b) {
         const dmb_params& p = par[b];
         if (p.n_pow != p0.n_pow || p.precision != p0.precision || p.rates != p0.rates ||
-            quad_k(&p) != quad_k(&p0))
-            return fail(c, DMB_EINVAL, "box %d: n_pow, precision, rates and quad_nodes must agree across boxes", b);
+            quad_k(&p) != quad_k(&p0) || p.dm_sampling != p0.dm_sampling)
+            return fail(c, DMB_EINVAL,
+                        "box %d: n_pow, precision, rates, quad_nodes and dm_sampling must agree across boxes", b);
         if (!(p.m_chi_g > 0.0) || !(p.sigma0_cm2 >= 0.0)) return fail(c, DMB_EINVAL, "box %d: bad m_chi or sigma0", b);
         if (!(std::fabs(p.aniso_g) < 1.0)) return fail(c, DMB_EINVAL, "box %d: aniso_g %g outside (-1, 1)", b, p.aniso_g);
         const Cells& X = *c->boxes[b];

@@ -218,7 +218,7 @@ __device__ __forceinline__ T u24(uint32_t r) { return (T(r >> 8) + T(0.5)) * T(1
 
 // Stream layout shared with every consumer of the random numbers:
 // counter = (dm index, gas index, step, tag | box << 8), key = seed.
-enum : uint32_t { kTagGasVel = 0u, kTagDir = 1u, kTagDecision = 2u };
+enum : uint32_t { kTagGasVel = 0u, kTagDir = 1u, kTagDecision = 2u, kTagTilt = 5u };
 
 __device__ __forceinline__ U4 philox_block(uint32_t i, uint32_t j, uint32_t step, uint32_t tag, uint32_t box,
                                            uint32_t k0, uint32_t k1)

@@ -843,6 +843,8 @@ struct GasGatherArgs {
     const double* vel; const double* mass; const double* u; const double* mu;
     double m_chi, sig_kpc2_cn, alpha_n;
     int n_pow;
+    int rb;                       // Rao-Blackwellised DM sampling: the record carries 1/(2 vs^2) and K alpha_{n-2} vs^{n+1}
+    double alpha_rb;              // alpha_{n-2}
     double* Vx; double* Vy; double* Vz;
     const uint32_t* flag; const uint32_t* flag_off;         // active flags and their exclusive scan (sorted order)
     void* orate;                  // OwnRate<Real>[n_own], owner-slot order
@@ -881,10 +883,15 @@ __global__ __launch_bounds__(256) void k_gather_gas(GasGatherArgs a)
         w.i2 = i2; w.a = ra; w.b = rb; w.r = rr;
         reinterpret_cast<OwnRate<Real>*>(a.orate)[a.flag_off[k]] = w;
     }
-    const Real K = Real(a.mass[o] * kMsunG / mu * a.sig_kpc2_cn);
+    const double Kd = a.mass[o] * kMsunG / mu * a.sig_kpc2_cn;
     GasRec<Real> r;
     r.Vx = a.vel[3 * int64_t(o)]; r.Vy = a.vel[3 * int64_t(o) + 1]; r.Vz = a.vel[3 * int64_t(o) + 2];
-    r.vs = vs; r.K = K; r.crit = cr; r.perm = o;
+    r.vs = vs; r.K = Real(Kd); r.crit = cr; r.perm = o;
+    if (a.rb) {
+        const double s = sqrt(2.0 * a.u[o] / 3.0);
+        r.vs = i2;
+        if (s > 0.0) r.K = Real(Kd * a.alpha_rb * pow(s, double(a.n_pow + 1)));
+    }
     reinterpret_cast<GasRec<Real>*>(a.rec)[k] = r;
 }
 
@@ -1842,6 +1849,34 @@ __device__ __forceinline__ Real pair_P(double d2, double dh, double gh, double v
     return K * g * pow_np1<N>(vrel) * dt;
 }
 
+// Rao-Blackwellised P_ij (an exact-in-law variant of the per-pair draw):
+// the expectation of P_ij over the Maxwellian gas-velocity sample,
+// K_j g dt_i E|w - vs z|^{n+1}, w = v_i - V_j.  E|u|^{n+1} for
+// u ~ N(w, vs^2 I) is the B rate integral of power n - 2,
+// alpha_{n-2} vs^{n+1} 1F1(-(n+1)/2, 3/2, -w^2/(2 vs^2)); the gas record
+// carries i2 = 1/(2 vs^2) (infinite for cold gas, where E = |w|^{n+1}) and
+// Kb = K_j alpha_{n-2} vs^{n+1}.  Shared by the DM pass and the resolve.
+template <typename Real, int N, bool EXACT_G>
+__device__ __forceinline__ Real pair_Pbar(double d2, double dh, double gh, double vx, double vy, double vz,
+                                          double Vx, double Vy, double Vz, Real i2, Real Kb, Real dt,
+                                          const float4* gtab)
+{
+    static_assert(N > -4, "the expectation diverges for n = -4");
+    const Real g = EXACT_G ? overlap_g_exact<Real>(sqrt_real(Real(d2)), Real(dh), Real(gh))
+                           : Real(overlap_g_table(gtab, d2, dh, gh));
+    const Real wx = Real(vx - Vx), wy = Real(vy - Vy), wz = Real(vz - Vz);
+    const Real w2 = wx * wx + wy * wy + wz * wz;
+    Real E;
+    if (isinf(i2)) {
+        E = pow_np1<N>(sqrt_real(w2));
+    } else {
+        Real FA, FB;
+        rate_1f1<N - 2, Real>(w2 * i2, &FA, &FB);
+        E = FB;
+    }
+    return Kb * g * E * dt;
+}
+
 // Decision of eq. dm-update-vels for one DM owner: U_i (tag 2) against P_i;
 // scattering DM go to the resolve list.  Returns flags (scatter, P>=1,
 // non-finite, near-decision) as bits 0..3.
@@ -1867,7 +1902,7 @@ __device__ __forceinline__ uint32_t dm_decide(uint32_t o, int64_t s, double P, f
     return f;
 }
 
-template <typename Real, int N, bool EXACT_G, bool BATCH = false, bool PAIRS = false>
+template <typename Real, int N, bool EXACT_G, bool BATCH = false, bool PAIRS = false, bool RB = false>
 __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPassArgs a0, const DmPassArgs* __restrict__ boxes,
                                                    const int64_t* __restrict__ box_items, int nbox)
 {
@@ -1979,10 +2014,16 @@ __global__ __launch_bounds__(64, sizeof(Real) == 4 ? 4 : 3) void k_pass_dm(DmPas
                     if (fabs(d2 - hs2) <= 1e-6 * hs2) pNB = 1;
                     if (d2 < hs2) {
                         npairs++;
-                        Real urel[3];
-                        const Real P = pair_P<Real, N, EXACT_G>(d2, o_h[o], qh, o_vx[o], o_vy[o], o_vz[o], r.Vx, r.Vy,
-                                                                r.Vz, r.vs, r.K, o_dt[o], o_id[o], r.perm, step, a.box,
-                                                                a.k0, a.k1, a.gtab, urel);
+                        Real P;
+                        if constexpr (RB) {
+                            P = pair_Pbar<Real, N, EXACT_G>(d2, o_h[o], qh, o_vx[o], o_vy[o], o_vz[o], r.Vx, r.Vy, r.Vz,
+                                                            r.vs, r.K, o_dt[o], a.gtab);
+                        } else {
+                            Real urel[3];
+                            P = pair_P<Real, N, EXACT_G>(d2, o_h[o], qh, o_vx[o], o_vy[o], o_vz[o], r.Vx, r.Vy, r.Vz,
+                                                         r.vs, r.K, o_dt[o], o_id[o], r.perm, step, a.box, a.k0, a.k1,
+                                                         a.gtab, urel);
+                        }
                         pP += P;
                         pM = pM > P ? pM : P;
                         if (P >= r.crit) ncrit++;
@@ -2169,6 +2210,7 @@ struct ResolveArgs {
     const double* gas_vel; const double* gas_u; const double* gas_mu;   // raw gas inputs (partner kick)
     double m_chi;
     double aniso_g;               // Henyey-Greenstein asymmetry of the scattering angle (0: isotropic)
+    const double* tilt_gl;        // Rao-Blackwellised draw: 16-point Gauss-Legendre nodes [16] and weights [16]
     const float4* gtab;
     uint32_t k0, k1, step, box;
     const uint32_t* step_off;     // nullable: device offset added to step
@@ -2189,14 +2231,140 @@ __device__ __forceinline__ void fixed_split(double P, unsigned long long* hi, un
     *lo = (unsigned long long)((pd - fl) * 4294967296.0);
 }
 
+// Rao-Blackwellised partner draw: the relative velocity of the chosen pair
+// from the tilted law |u|^M N(u; w, vs^2 I), M = n + 1, by inversion of
+// three uniforms (tag 5).  In units of vs, r = |u| has density proportional
+// to r^{M+1} e^{-(r-a)^2/2} (1 - e^{-2ra})/(2a), a = |w|/vs (r^{M+2}
+// e^{-r^2/2} at a = 0), which is the 3-D density integrated over directions;
+// given r, c = cos(u, w) has density ~ e^{rac} on [-1, 1].  The radial CDF
+// is integrated on 24 unit cells from max(0, a - 12) (16-point
+// Gauss-Legendre per cell, one lane per cell); the cell that holds u0 is
+// found counting from below for u0 <= 1/2 and from above otherwise (so the
+// tails keep their relative accuracy), and the radius inside it by Newton
+// steps held in a bisection bracket, each partial integral spread over 16
+// lanes (one node each, butterfly sum).  Every lane of the wavefront follows
+// the same iterates.  Binary64 in both precisions.
+constexpr int kTiltCells = 24;
+
+template <int M>
+__device__ __forceinline__ double tilt_density(double a, double r)
+{
+    if (!(r > 0.0)) return 0.0;
+    const double sh = a > 0.0 ? -expm1(-2.0 * r * a) / (2.0 * a) : r;
+    double p = 1.0;
+#pragma unroll
+    for (int k = 0; k < M + 1; ++k) p *= r;
+    return p * exp(-0.5 * (r - a) * (r - a)) * sh;
+}
+
+template <int M>
+__device__ double tilt_cell(double a, double x0, double x1, const double* gl)
+{
+    const double c = 0.5 * (x0 + x1), h = 0.5 * (x1 - x0);
+    double s = 0.0;
+    for (int k = 0; k < 16; ++k) s += gl[16 + k] * tilt_density<M>(a, c + h * gl[k]);
+    return s * h;
+}
+
+// all 64 lanes of one wavefront call and all return the radius; gl in LDS
+template <int M>
+__device__ double tilted_radius(double a, double u0, const double* gl, double* s_cell, int lane)
+{
+    const double lo = fmax(0.0, a - 0.5 * kTiltCells);
+    if (lane < kTiltCells) s_cell[lane] = tilt_cell<M>(a, lo + lane, lo + lane + 1.0, gl);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int kn = lane & 15;
+    const double xk = gl[kn], wk = gl[16 + kn];
+    double Z = 0.0;
+    for (int k = 0; k < kTiltCells; ++k) Z += s_cell[k];
+    const bool upper = u0 > 0.5;
+    double T = (upper ? 1.0 - u0 : u0) * Z, cum = 0.0;
+    int cl = upper ? kTiltCells - 1 : 0;
+    if (!upper) {
+        while (cl < kTiltCells - 1 && cum + s_cell[cl] < T) cum += s_cell[cl++];
+    } else {
+        while (cl > 0 && cum + s_cell[cl] < T) cum += s_cell[cl--];
+    }
+    T -= cum;
+    const double x0 = lo + cl, x1 = x0 + 1.0;
+    double bl = x0, bh = x1;
+    const double fr = s_cell[cl] > 0.0 ? fmin(fmax(T / s_cell[cl], 0.0), 1.0) : 0.5;
+    double r = upper ? x1 - fr : x0 + fr;
+    for (int it = 0; it < 64; ++it) {
+        // lower: F(r) = int_x0^r - T (increasing); upper: F(r) = T - int_r^x1 (increasing)
+        const double xa = upper ? r : x0, xb = upper ? x1 : r;
+        const double c = 0.5 * (xa + xb), h = 0.5 * (xb - xa);
+        double I = wk * tilt_density<M>(a, c + h * xk);
+        I += __shfl_xor(I, 8);
+        I += __shfl_xor(I, 4);
+        I += __shfl_xor(I, 2);
+        I += __shfl_xor(I, 1);
+        I *= h;
+        const double F = upper ? T - I : I - T;
+        if (F < 0.0) bl = r; else bh = r;
+        const double g = tilt_density<M>(a, r);
+        double rn = g > 0.0 ? r - F / g : 0.5 * (bl + bh);
+        if (!(rn > bl && rn < bh)) rn = 0.5 * (bl + bh);
+        const bool done = fabs(rn - r) <= 4e-15 * rn || !(bh - bl > 4e-15 * bh);
+        r = rn;
+        if (done) break;
+    }
+    return r;
+}
+
+// The elastic kick of eq. scatter_chi for DM oid scattering off gas j with
+// relative velocity u = v_i - v_B: |u| is kept and its direction redrawn
+// (tag 1 of the pair: isotropic, or the Henyey-Greenstein angle about u), the
+// DM taking mu_j/(m_chi + mu_j) of the change.  Writes dv and the partner.
+template <typename Real>
+__device__ void scatter_kick(const ResolveArgs& a, uint32_t oid, uint32_t j, uint32_t step, Real ux, Real uy,
+                             Real uz)
+{
+    const double muj = a.gas_mu ? a.gas_mu[j] : kMpG;
+    const Real rr = Real(muj / (a.m_chi + muj));
+    const Real vrel = sqrt_real(ux * ux + uy * uy + uz * uz);
+    double dvx = 0.0, dvy = 0.0, dvz = 0.0;
+    if (vrel > Real(0)) {
+        U4 r2 = philox_block(oid, j, step, kTagDir, a.box, a.k0, a.k1);
+        Real sp_, cp_;
+        sincos_turns(u24<Real>(r2.y), &sp_, &cp_);
+        Real iv = Real(1) / vrel;
+        Real f = rr * vrel;
+        Real n[3];
+        if (a.aniso_g == 0.0) {
+            // isotropic: the new direction directly, cos theta about the z axis
+            const Real ct = Real(2) * u24<Real>(r2.x) - Real(1);
+            const Real st = sqrt_real(fmax(Real(0), Real(1) - ct * ct));
+            n[0] = st * cp_; n[1] = st * sp_; n[2] = ct;
+        } else {
+            // cos theta from p(Omega), about the incoming relative velocity
+            const Real uh[3] = {ux * iv, uy * iv, uz * iv};
+            Real ct, st;
+            hg_angle(Real(a.aniso_g), u24<Real>(r2.x), &ct, &st);
+            Real e1[3], e2[3];
+            orthonormal_frame(uh, e1, e2);
+            for (int k = 0; k < 3; ++k) n[k] = ct * uh[k] + st * (cp_ * e1[k] + sp_ * e2[k]);
+        }
+        dvx = double(f * (n[0] - ux * iv));
+        dvy = double(f * (n[1] - uy * iv));
+        dvz = double(f * (n[2] - uz * iv));
+    }
+    a.dv[3 * int64_t(oid)] = dvx;
+    a.dv[3 * int64_t(oid) + 1] = dvy;
+    a.dv[3 * int64_t(oid) + 2] = dvz;
+    a.partner[oid] = int32_t(j);
+}
+
 constexpr int kResolveThreads = 1024; // sixteen wavefronts per scattering DM (the first 256 threads own the histogram bins)
 constexpr int kResolveList = 2048;    // candidate sub-tiles kept per scattering DM after the point test
 constexpr int kResolvePairs = 8192;   // pairs cached per scattering DM (LDS)
 
-template <typename Real, int N, bool EXACT_G>
+template <typename Real, int N, bool EXACT_G, bool RB = false>
 __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
 {
     __shared__ unsigned long long hhi[256], hlo[256];
+
     __shared__ uint32_t s_list[kResolveList];
     __shared__ uint32_t s_pre[kResolveList + 1];
     __shared__ uint32_t s_gid[kResolvePairs];
@@ -2212,6 +2380,7 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
     const uint32_t step = a.step + (a.step_off ? *a.step_off : 0u);
     const uint32_t nsc = *a.scount;
     uint32_t nnearD = 0;
+
     for (uint32_t e = blockIdx.x; e < nsc; e += gridDim.x) {
         const int64_t s = a.slist[e];
         const int64_t sp = G.own[s];
@@ -2284,10 +2453,16 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
                     if (d2 < hs * hs) {
                         const GasRec<Real> r = reinterpret_cast<const GasRec<Real>*>(a.grec)[k];
                         const uint32_t gid = r.perm;
-                        Real urel[3];
-                        const double P = double(pair_P<Real, N, EXACT_G>(d2, mh, G.th[k], mvx, mvy, mvz, r.Vx, r.Vy,
-                                                                         r.Vz, r.vs, r.K, mdt, oid, gid,
-                                                                         step, a.box, a.k0, a.k1, a.gtab, urel));
+                        double P;
+                        if constexpr (RB) {
+                            P = double(pair_Pbar<Real, N, EXACT_G>(d2, mh, G.th[k], mvx, mvy, mvz, r.Vx, r.Vy, r.Vz,
+                                                                   r.vs, r.K, mdt, a.gtab));
+                        } else {
+                            Real urel[3];
+                            P = double(pair_P<Real, N, EXACT_G>(d2, mh, G.th[k], mvx, mvy, mvz, r.Vx, r.Vy, r.Vz, r.vs,
+                                                                r.K, mdt, oid, gid, step, a.box, a.k0, a.k1, a.gtab,
+                                                                urel));
+                        }
                         fn(gid, P);
                     }
                 }
@@ -2380,50 +2555,68 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
         if (tid == 0) {
             const uint32_t j = prefix < a.n_gas ? prefix : a.n_gas - 1u;
             nnearD += uint32_t(s_near);
-            const double muj = a.gas_mu ? a.gas_mu[j] : kMpG;
-            Real vsj, i2, ra, rb, rr, cr;
-            gas_derived<Real>(a.gas_u[j], muj, a.m_chi, 1.0, 0, &vsj, &i2, &ra, &rb, &rr, &cr);
-            U4 r = philox_block(oid, j, step, kTagGasVel, a.box, a.k0, a.k1);
-            Real z[3];
-            normals3<Real>(r, z);
-            Real ux = Real(mvx - a.gas_vel[3 * int64_t(j)]) - vsj * z[0];
-            Real uy = Real(mvy - a.gas_vel[3 * int64_t(j) + 1]) - vsj * z[1];
-            Real uz = Real(mvz - a.gas_vel[3 * int64_t(j) + 2]) - vsj * z[2];
-            Real vrel = sqrt_real(ux * ux + uy * uy + uz * uz);
-            double dvx = 0.0, dvy = 0.0, dvz = 0.0;
-            if (vrel > Real(0)) {
-                U4 r2 = philox_block(oid, j, step, kTagDir, a.box, a.k0, a.k1);
-                Real sp_, cp_;
-                sincos_turns(u24<Real>(r2.y), &sp_, &cp_);
-                Real iv = Real(1) / vrel;
-                Real f = rr * vrel;
-                Real n[3];
-                if (a.aniso_g == 0.0) {
-                    // isotropic: the new direction directly, cos theta about the z axis
-                    const Real ct = Real(2) * u24<Real>(r2.x) - Real(1);
-                    const Real st = sqrt_real(fmax(Real(0), Real(1) - ct * ct));
-                    n[0] = st * cp_; n[1] = st * sp_; n[2] = ct;
-                } else {
-                    // cos theta from p(Omega), about the incoming relative velocity
-                    const Real uh[3] = {ux * iv, uy * iv, uz * iv};
-                    Real ct, st;
-                    hg_angle(Real(a.aniso_g), u24<Real>(r2.x), &ct, &st);
-                    Real e1[3], e2[3];
-                    orthonormal_frame(uh, e1, e2);
-                    for (int k = 0; k < 3; ++k) n[k] = ct * uh[k] + st * (cp_ * e1[k] + sp_ * e2[k]);
-                }
-                dvx = double(f * (n[0] - ux * iv));
-                dvy = double(f * (n[1] - uy * iv));
-                dvz = double(f * (n[2] - uz * iv));
+            if constexpr (RB) {
+                a.partner[oid] = int32_t(j);   // the kick follows in k_rb_kick
+            } else {
+                const double vs = sqrt(2.0 * a.gas_u[j] / 3.0);
+                U4 r = philox_block(oid, j, step, kTagGasVel, a.box, a.k0, a.k1);
+                Real z[3];
+                normals3<Real>(r, z);
+                const Real vsj = Real(vs);
+                const Real ux = Real(mvx - a.gas_vel[3 * int64_t(j)]) - vsj * z[0];
+                const Real uy = Real(mvy - a.gas_vel[3 * int64_t(j) + 1]) - vsj * z[1];
+                const Real uz = Real(mvz - a.gas_vel[3 * int64_t(j) + 2]) - vsj * z[2];
+                scatter_kick<Real>(a, oid, j, step, ux, uy, uz);
             }
-            a.dv[3 * int64_t(oid)] = dvx;
-            a.dv[3 * int64_t(oid) + 1] = dvy;
-            a.dv[3 * int64_t(oid) + 2] = dvz;
-            a.partner[oid] = int32_t(j);
         }
         __syncthreads();
     }
     if (tid == 0 && nnearD) atomicAdd((unsigned long long*)&a.counters[4], (unsigned long long)nnearD);
+}
+
+// Kicks of the Rao-Blackwellised scheme, after k_resolve has chosen the
+// partners: one wavefront per scattering DM draws the relative velocity of
+// its pair from the tilted law (tag 5: radius, cosine to w, azimuth),
+// u = vs r (c e + s (cos phi e1 + sin phi e2)), e = w/|w| (the z axis if
+// w = 0; cold gas: u = w), and applies the kick.
+template <typename Real, int N>
+__global__ __launch_bounds__(64) void k_rb_kick(ResolveArgs a)
+{
+    __shared__ double s_cell[kTiltCells];
+    __shared__ double s_gl[32];
+    const int lane = int(threadIdx.x);
+    if (lane < 32) s_gl[lane] = a.tilt_gl[lane];
+    __syncthreads();
+    const uint32_t step = a.step + (a.step_off ? *a.step_off : 0u);
+    const uint32_t nsc = *a.scount;
+    for (uint32_t e = blockIdx.x; e < nsc; e += gridDim.x) {
+        const int64_t sp = a.g.own[a.slist[e]];
+        const DmRec<Real> orc = reinterpret_cast<const DmRec<Real>*>(a.drec)[sp];
+        const uint32_t oid = a.dm_perm[sp];
+        const uint32_t j = uint32_t(a.partner[oid]);
+        const double wx = orc.vx - a.gas_vel[3 * int64_t(j)], wy = orc.vy - a.gas_vel[3 * int64_t(j) + 1];
+        const double wz = orc.vz - a.gas_vel[3 * int64_t(j) + 2];
+        const double vsd = sqrt(2.0 * a.gas_u[j] / 3.0);
+        const double wn = sqrt(wx * wx + wy * wy + wz * wz);
+        double ud[3] = {wx, wy, wz};
+        if (vsd > 0.0) {
+            const U4 rt = philox_block(oid, j, step, kTagTilt, a.box, a.k0, a.k1);
+            const double trad = tilted_radius<N + 1>(wn / vsd, u24<double>(rt.x), s_gl, s_cell, lane);
+            const double kap = trad * wn / vsd;
+            const double u1 = u24<double>(rt.y), u2 = u24<double>(rt.z);
+            const double omc = kap > 0.0 ? -log1p(u1 * expm1(-2.0 * kap)) / kap : 2.0 * u1;
+            const double cc = 1.0 - omc, ss = sqrt(fmax(0.0, omc * (2.0 - omc)));
+            double ev[3] = {0.0, 0.0, 1.0}, e1[3], e2[3];
+            if (wn > 0.0) { ev[0] = wx / wn; ev[1] = wy / wn; ev[2] = wz / wn; }
+            orthonormal_frame(ev, e1, e2);
+            double sp2, cp2;
+            sincos_turns(u2, &sp2, &cp2);
+            for (int k = 0; k < 3; ++k) ud[k] = vsd * trad * (cc * ev[k] + ss * (cp2 * e1[k] + sp2 * e2[k]));
+        }
+        if (lane == 0) scatter_kick<Real>(a, oid, j, step, Real(ud[0]), Real(ud[1]), Real(ud[2]));
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
 }
 
 // ---------------------------------------------------------------------------

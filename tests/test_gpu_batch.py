@@ -43,11 +43,11 @@ def boxes():
     return workloads.batch(n_box=6, n_min=1200, n_max=6000, seed=(5, 2))
 
 
-def _to_dev(bx, rates=0):
+def _to_dev(bx, rates=0, sampling=0):
     import paper_2603_24688_amd as dmb
     G = [dmb.to_device(b["gas"]) for b in bx]
     D = [dmb.to_device(b["dm"]) for b in bx]
-    P = [dict(b["params"], rates=rates) for b in bx]
+    P = [dict(b["params"], rates=rates, dm_sampling=sampling) for b in bx]
     O = [dmb.alloc_out(len(b["gas"]["mass"]), len(b["dm"]["mass"])) for b in bx]
     return G, D, P, O
 
@@ -68,11 +68,12 @@ def _same(a, b):
     return None
 
 
-# rates 3: the per-gas Maxwellian closure
-@pytest.mark.parametrize("precision,rates", [(0, 0), (1, 0), (0, 3), (1, 3)])
-def test_batch_equals_single_boxes(ctx, boxes, precision, rates):
+# rates 3: the per-gas Maxwellian closure; sampling 1: Rao-Blackwellised DM sampling
+@pytest.mark.parametrize("precision,rates,sampling", [(0, 0, 0), (1, 0, 0), (0, 3, 0), (1, 3, 0), (0, 0, 1),
+                                                      (1, 0, 1)])
+def test_batch_equals_single_boxes(ctx, boxes, precision, rates, sampling):
     import torch
-    G, D, P, O = _to_dev(boxes, rates)
+    G, D, P, O = _to_dev(boxes, rates, sampling)
     ctx.batch_build(G, D, P, precision=precision)
     ctx.batch_step(G, D, P, O, precision=precision)
     torch.cuda.synchronize()
@@ -80,16 +81,16 @@ def test_batch_equals_single_boxes(ctx, boxes, precision, rates):
         single = run_gpu(ctx, dict(bx, params=P[b]), precision)
         got = _host(O[b])
         bad = _same(got, single)
-        _log(f"[batch p={precision} rates={rates}] box {b}: n={len(bx['gas']['mass'])} pairs {got['counters']['pairs_gas']} "
+        _log(f"[batch p={precision} rates={rates} sampling={sampling}] box {b}: n={len(bx['gas']['mass'])} pairs {got['counters']['pairs_gas']} "
              f"scatters {got['counters']['scatters']} {'identical' if bad is None else 'differs in ' + bad}")
         assert bad is None
 
 
-@pytest.mark.parametrize("precision,rates", [(0, 0), (1, 0), (1, 3)])
-def test_batch_oracle_parity(ctx, boxes, precision, rates):
+@pytest.mark.parametrize("precision,rates,sampling", [(0, 0, 0), (1, 0, 0), (1, 3, 0), (1, 0, 1)])
+def test_batch_oracle_parity(ctx, boxes, precision, rates, sampling):
     import oracle
     import torch
-    G, D, P, O = _to_dev(boxes, rates)
+    G, D, P, O = _to_dev(boxes, rates, sampling)
     ctx.batch_build(G, D, P, precision=precision)
     ctx.batch_step(G, D, P, O, precision=precision)
     torch.cuda.synchronize()
@@ -103,7 +104,7 @@ def test_batch_oracle_parity(ctx, boxes, precision, rates):
         ep, ee = mean_field_error(got, ref, gsel)
         dec = decision_report(got, ref, dsel)
         ke = kick_error(got, ref, dsel)
-        _log(f"[batch oracle p={precision} rates={rates}] box {b}: dp {ep:.2e} dE {ee:.2e} decisions {dec['compared']} "
+        _log(f"[batch oracle p={precision} rates={rates} sampling={sampling}] box {b}: dp {ep:.2e} dE {ee:.2e} decisions {dec['compared']} "
              f"mismatch {dec['mismatch']} kick {ke:.2e}")
         assert ep <= TOL[precision] and ee <= TOL[precision]
         assert dec["mismatch"] == 0

@@ -237,6 +237,35 @@ def test_box_gas_closure(ctx, orc, precision, n_pow):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("n_pow", [0, -2, 2])
+def test_box_rao_blackwell_sampling(ctx, orc, precision, n_pow):
+    """DMB_SAMPLE_RB: each pair's P_ij is its expectation over the gas-velocity
+    sample (closed form) and a scattering DM draws its relative velocity from
+    the tilted law by inversion (Philox tag 5).  Sums of P, decisions and
+    partners against the oracle at the usual bars; kicks of the tilted draw
+    to 1e-12 (binary64) / 2e-5 (binary32).  Many scatters per step."""
+    import paper_2603_24688_amd as dmb
+    cfg = workloads.box(n_gas=1500, n_dm=1300, seed=(33, n_pow + 10), n_pow=n_pow,
+                        sigma0_cm2=workloads.sigma0_for_npow(n_pow, 30.0, 3e-22))
+    cfg["params"]["dm_sampling"] = dmb.DMB_SAMPLE_RB
+    gpu, ref = _check_step(ctx, orc, cfg, precision, f"box-rb n={n_pow}")
+    assert ref["counters"]["scatters"] > 100
+
+
+def test_rao_blackwell_cold_gas_and_galaxy(ctx, orc):
+    """Rao-Blackwellised sampling with cold gas (u = 0: the draw is w itself)
+    on a quarter of the gas, and on the small galaxy (binary32)."""
+    import paper_2603_24688_amd as dmb
+    cfg = workloads.box(n_gas=1200, n_dm=1100, seed=(34, 1), sigma0_cm2=3e-22)
+    cfg["gas"]["u"][::4] = 0.0
+    cfg["params"]["dm_sampling"] = dmb.DMB_SAMPLE_RB
+    _check_step(ctx, orc, cfg, 0, "box-rb cold")
+    g = workloads.galaxy(n_gas=2500, n_dm=10000, seed=(2, 13))
+    g["params"]["dm_sampling"] = dmb.DMB_SAMPLE_RB
+    _check_step(ctx, orc, g, 1, "galaxy-rb")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_galaxy_gas_closure(ctx, orc, precision):
     """The closure on the galaxy profiles (open boundaries, h over ~2 decades)."""
     import paper_2603_24688_amd as dmb
@@ -347,6 +376,9 @@ def test_invalid_arguments(ctx):
             ctx.interact_step(G, D, dict(par, aniso_g=g), out)
     with pytest.raises(dmb.DmbError, match="EINVAL"):
         ctx.interact_step(G, D, dict(par, rates=4), out)
+    for bad_s in (dict(par, dm_sampling=2), dict(par, dm_sampling=1, n_pow=-4)):
+        with pytest.raises(dmb.DmbError, match="EINVAL"):
+            ctx.interact_step(G, D, bad_s, out)
     big = dict(cfg["gas"])
     big["h"] = np.full(200, 0.3)
     with pytest.raises(dmb.DmbError, match="ERANGE"):
