@@ -176,6 +176,41 @@ __device__ __forceinline__ double overlap_g_table(const float4* __restrict__ tab
     return Q * env * (ib * ib * ib);
 }
 
+// The same lookup returning binary32, for the binary32 DM pass, whose P_ij
+// are binary32: the distance and the two differences that vanish at contact
+// (h_b + h_s - d, h_b - d) are still formed in binary64, everything after
+// them in binary32 (rounding below 4e-7 of g).  Overlaps under the binary32
+// range (pairs within ~1e-5 h_s of contact) flush to zero, as the binary32
+// P_ij built from them would.  The gas pass keeps the binary64 envelope: its
+// terms are binary64, and an owner whose every neighbour is that close to
+// contact keeps its relative accuracy.
+__device__ __forceinline__ float overlap_g_table32(const float4* __restrict__ tab, double d2, double h1, double h2)
+{
+    const double hbd = h1 > h2 ? h1 : h2, hsd = h1 > h2 ? h2 : h1;
+    const float d0f = __builtin_amdgcn_sqrtf(float(d2));
+    const double d0 = double(d0f);
+    const double d = d0f > 0.f ? fma(d2 - d0 * d0, double(0.5f * __builtin_amdgcn_rcpf(d0f)), d0) : 0.0;
+    const double innerd = hbd - d;
+    const bool shell = innerd < hsd;
+    const float num = float(shell ? (hbd + hsd) - d : hsd);
+    const float hb = float(hbd), hs = float(hsd), inner = float(innerd);
+    const float ib = __builtin_amdgcn_rcpf(hb);
+    const float r = num * __builtin_amdgcn_rcpf(shell ? hs : inner);   // rho (shell) or kappa (core)
+    const float eta = hs * ib;
+    const float x = shell ? 0.5f * r : float(d) * ib, y = shell ? eta : r;
+    const float fx = fminf(x, 1.f) * float(kTabN), fy = fminf(y, 1.f) * float(kTabN);
+    const int i = min(int(fx), kTabN - 1), j = min(int(fy), kTabN - 1);
+    const float a = fx - float(i), b = fy - float(j);
+    const float4* c = tab + 4 * ((shell ? 0 : kTabCellsRegion) + j * kTabN + i);
+    const float4 q0 = c[0], q2 = c[1], q3 = c[2], q1 = c[3];
+    auto cubic = [a](float4 q) { return fmaf(fmaf(fmaf(q.w, a, q.z), a, q.y), a, q.x); };
+    const float p0 = cubic(q0), p2 = cubic(q2), p3 = cubic(q3), p1 = fmaf(q1.y, a, q1.x);
+    const float Q = fmaf(fmaf(fmaf(p3, b, p2), b, p1), b, p0);
+    const float r2 = r * r, r4 = r2 * r2, tc = inner * ib;
+    const float env = shell ? eta * eta * eta * (r4 * r4) : tc * tc * tc;
+    return Q * env * (ib * ib * ib);
+}
+
 template <typename T>
 __device__ __forceinline__ T overlap_g_exact(T d, T hi, T hj)
 {
@@ -189,6 +224,14 @@ __device__ __forceinline__ T overlap_g_exact(T d, T hi, T hj)
 // constants between rounds.
 struct U4 { uint32_t x, y, z, w; };
 
+// a ^ b ^ k with k wave-uniform, as one three-input XOR (the compiler splits it in two)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    asm("v_xor3_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
 __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
 {
     // the key schedule is rebuilt per call (scalar adds): hoisted, its 20 words
@@ -201,9 +244,9 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
         const uint32_t lo0 = uint32_t(p0), hi0 = uint32_t(p0 >> 32);
         const uint32_t lo1 = uint32_t(p1), hi1 = uint32_t(p1 >> 32);
         U4 n;
-        n.x = hi1 ^ c.y ^ k0;
+        n.x = xor3(hi1, c.y, k0);
         n.y = lo1;
-        n.z = hi0 ^ c.w ^ k1;
+        n.z = xor3(hi0, c.w, k1);
         n.w = lo0;
         c = n;
         k0 += 0x9E3779B9u;

@@ -1839,7 +1839,7 @@ __device__ __forceinline__ Real pair_P(double d2, double dh, double gh, double v
 {
     U4 r = philox_block(i, j, step, kTagGasVel, box, k0, k1);
     Real g = EXACT_G ? overlap_g_exact<Real>(sqrt_real(Real(d2)), Real(dh), Real(gh))
-                     : Real(overlap_g_table(gtab, d2, dh, gh));
+                     : Real(overlap_g_table32(gtab, d2, dh, gh));
     Real z[3];
     normals3<Real>(r, z);
     urel[0] = Real(vx - Vx) - vs * z[0];
@@ -1863,7 +1863,7 @@ __device__ __forceinline__ Real pair_Pbar(double d2, double dh, double gh, doubl
 {
     static_assert(N > -4, "the expectation diverges for n = -4");
     const Real g = EXACT_G ? overlap_g_exact<Real>(sqrt_real(Real(d2)), Real(dh), Real(gh))
-                           : Real(overlap_g_table(gtab, d2, dh, gh));
+                           : Real(overlap_g_table32(gtab, d2, dh, gh));
     const Real wx = Real(vx - Vx), wy = Real(vy - Vy), wz = Real(vz - Vz);
     const Real w2 = wx * wx + wy * wy + wz * wz;
     Real E;
