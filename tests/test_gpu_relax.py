@@ -191,6 +191,43 @@ def test_anisotropic_box_relaxes_with_sigma_bar(ctx, g):
     assert max(res["sigma"]) >= 0.2
 
 
+@pytest.mark.parametrize("mode", ["rao_blackwell", "closure", "both"])
+def test_variant_schemes_relax_like_the_paper_scheme(ctx, mode):
+    """The fiducial box with Rao-Blackwellised DM sampling (exact in law) and
+    with the per-gas Maxwellian closure of the gas mean field (exact for
+    Maxwellian DM, which the box's DM are and stay, JB <= 0.01): the gas
+    follows the Appendix F relaxation within 3 % of its change, the DM mean
+    velocity and variance stay within five times the scatter noise of it
+    (their own change is of the order of that noise), and total momentum is
+    conserved within the scatter noise."""
+    import paper_2603_24688_amd as dmb
+    cfg = workloads.box(seed=(1, 1))
+    if mode in ("rao_blackwell", "both"):
+        cfg["params"]["dm_sampling"] = dmb.DMB_SAMPLE_RB
+    if mode in ("closure", "both"):
+        cfg["params"]["rates"] = dmb.DMB_RATES_CLOSURE
+    diag, _, _ = run_box(ctx, cfg)
+    sim, ode = sim_state(diag), ode_for(cfg, diag)
+    err = [np.max(np.abs(sim[:, k] - ode[:, k])) / abs(ode[-1, k] - ode[0, k]) for k in range(4)]
+    nsc = diag[:, _col("scatters")].sum()
+    ptot = diag[:, _col("p_dm_x")] + diag[:, _col("p_gas_x")]
+    nd = len(cfg["dm"]["mass"])
+    vrel = np.sqrt(3 * (sim[:, 2].max() + sim[:, 3].max()) + np.max((sim[:, 0] - sim[:, 1]) ** 2))
+    kick = MU / (cfg["params"]["m_chi_g"] + MU) * vrel
+    noise_v = kick * np.sqrt(max(nsc, 1.0)) / nd
+    noise_s2 = (2 * vrel + kick) * kick * np.sqrt(max(nsc, 1.0)) / nd
+    noise_p = cfg["dm"]["mass"].sum() * noise_v
+    dX = [np.max(np.abs(sim[:, k] - ode[:, k])) for k in (0, 2)]
+    _log(f"[{mode}] scatters {int(nsc)}, max JB {diag[:, _col('jb_dm')].max():.4f}; errors of change: V_X {err[0]:.3f}, "
+         f"V_B {err[1]:.3f}, s_X^2 {err[2]:.3f}, s_B^2 {err[3]:.3f}; DM deviations V_X {dX[0]:.3f} (noise {noise_v:.3f}), "
+         f"s_X^2 {dX[1]:.3f} (noise {noise_s2:.3f}); total p_x change {ptot[-1] - ptot[0]:.3e} (noise {noise_p:.3e})")
+    assert diag[:, _col("jb_dm")].max() <= 0.01
+    assert err[1] <= 0.03 and err[3] <= 0.03
+    assert dX[0] <= 5 * noise_v and dX[1] <= 5 * noise_s2
+    if mode == "rao_blackwell":   # the closure's gas transfer is not the pair sum, so momentum holds only in the mean
+        assert abs(ptot[-1] - ptot[0]) <= 5 * noise_p
+
+
 def test_timestep_control(ctx):
     """A step 20x longer than the criterion allows (sigma 20x the fiducial one)."""
     cfg = workloads.box(n_gas=2000, n_dm=2000, seed=(20, 1), sigma0_cm2=2e-23)
