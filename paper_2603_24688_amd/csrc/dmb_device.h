@@ -181,9 +181,9 @@ __device__ __forceinline__ double overlap_g_table(const float4* __restrict__ tab
 // (h_b + h_s - d, h_b - d) are still formed in binary64, everything after
 // them in binary32 (rounding below 4e-7 of g).  Overlaps under the binary32
 // range (pairs within ~1e-5 h_s of contact) flush to zero, as the binary32
-// P_ij built from them would.  The gas pass keeps the binary64 envelope: its
-// terms are binary64, and an owner whose every neighbour is that close to
-// contact keeps its relative accuracy.
+// P_ij built from them would.  The gas pass (binary64 terms) takes the
+// binary64 lookup for such pairs (overlap_g_gas), so an owner whose every
+// neighbour is that close to contact keeps its relative accuracy.
 __device__ __forceinline__ float overlap_g_table32(const float4* __restrict__ tab, double d2, double h1, double h2)
 {
     const double hbd = h1 > h2 ? h1 : h2, hsd = h1 > h2 ? h2 : h1;
@@ -211,6 +211,16 @@ __device__ __forceinline__ float overlap_g_table32(const float4* __restrict__ ta
     return Q * env * (ib * ib * ib);
 }
 
+// For the gas pass (binary64 terms): the binary32 lookup, and the binary64
+// one for the rare pair so close to contact that its binary32 value nears
+// the bottom of the binary32 range, so every overlap keeps its relative
+// accuracy.
+__device__ __forceinline__ double overlap_g_gas(const float4* __restrict__ tab, double d2, double h1, double h2)
+{
+    const float g = overlap_g_table32(tab, d2, h1, h2);
+    return g >= 1e-30f ? double(g) : overlap_g_table(tab, d2, h1, h2);
+}
+
 template <typename T>
 __device__ __forceinline__ T overlap_g_exact(T d, T hi, T hj)
 {
@@ -224,14 +234,6 @@ __device__ __forceinline__ T overlap_g_exact(T d, T hi, T hj)
 // constants between rounds.
 struct U4 { uint32_t x, y, z, w; };
 
-// a ^ b ^ k with k wave-uniform, as one three-input XOR (the compiler splits it in two)
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k)
-{
-    uint32_t r;
-    asm("v_xor3_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(k));
-    return r;
-}
-
 __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
 {
     // the key schedule is rebuilt per call (scalar adds): hoisted, its 20 words
@@ -244,9 +246,9 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
         const uint32_t lo0 = uint32_t(p0), hi0 = uint32_t(p0 >> 32);
         const uint32_t lo1 = uint32_t(p1), hi1 = uint32_t(p1 >> 32);
         U4 n;
-        n.x = xor3(hi1, c.y, k0);
+        n.x = hi1 ^ c.y ^ k0;
         n.y = lo1;
-        n.z = xor3(hi0, c.w, k1);
+        n.z = hi0 ^ c.w ^ k1;
         n.w = lo0;
         c = n;
         k0 += 0x9E3779B9u;

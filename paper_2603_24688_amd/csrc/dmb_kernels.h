@@ -1634,7 +1634,7 @@ void k_pass_gas(
                         if (d2 < hs * hs) {
                             npairs++;
                             const double gg = EXACT_G ? double(overlap_g_exact<Real>(sqrt_real(Real(d2)), Real(qh), Real(o_h[o])))
-                                                      : overlap_g_table(a.gtab, d2, qh, o_h[o]);
+                                                      : overlap_g_gas(a.gtab, d2, qh, o_h[o]);
                             const double wx = r.vx - o_Vx[o], wy = r.vy - o_Vy[o], wz = r.vz - o_Vz[o];
                             const double mg = double(r.m) * gg;
                             c0 = mg * wx; c1 = mg * wy; c2 = mg * wz;
@@ -1663,7 +1663,7 @@ void k_pass_gas(
                         if (d2 < hs * hs) {
                             npairs++;
                             const double gg = EXACT_G ? double(overlap_g_exact<Real>(sqrt_real(Real(d2)), Real(qh), Real(o_h[o])))
-                                                      : overlap_g_table(a.gtab, d2, qh, o_h[o]);
+                                                      : overlap_g_gas(a.gtab, d2, qh, o_h[o]);
                             const Real wx = Real(r.vx - o_Vx[o]), wy = Real(r.vy - o_Vy[o]), wz = Real(r.vz - o_Vz[o]);
                             const Real w2 = wx * wx + wy * wy + wz * wz;
                             Real FA, FB, Ar, Br;
@@ -1704,7 +1704,7 @@ void k_pass_gas(
                         if (d2 < hs * hs) {
                             live2 = true;
                             npairs++;
-                            gg = overlap_g_table(a.gtab, d2, qh, o_h[o]);
+                            gg = overlap_g_gas(a.gtab, d2, qh, o_h[o]);
                             const DmRec<float> r = reinterpret_cast<const DmRec<float>*>(a.drec)[q];
                             wx = float(r.vx - o_Vx[o]);
                             wy = float(r.vy - o_Vy[o]);
