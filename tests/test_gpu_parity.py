@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import workloads
-from parity_util import decision_report, kick_error, mean_field_error, run_gpu
+from parity_util import decision_report, kick_error, mean_field_error, mean_field_errors, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -82,6 +82,43 @@ def test_overlap_fp64_exact_and_fp32_table(ctx, orc):
     # outside the support the overlap is zero in both paths
     Tout = [torch.from_numpy(x).cuda() for x in ((h1 + h2) * 1.0000001, h1, h2)]
     assert np.all(ctx.overlap_eval(*Tout, precision=1).cpu().numpy() == 0.0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pass_pairs_near_contact(ctx, orc, precision):
+    """Every gas particle has exactly one DM partner, at nu = 1 - d/(h_i + h_j)
+    from 1e-7 to 1e-2 (overlaps down to ~1e-50 of the centre value): the gas
+    pass keeps each owner's transfer to the relative bar (binary32 lookups that
+    fall below 1e-30 are repeated in binary64); the DM pass's P_i meet the
+    same bar down to 1e-9, below which no uniform (>= 2^-25) can pick them.
+    The bar per owner is the path's tolerance plus the conditioning of g in d
+    there: g ~ nu^8, and d, formed from three rounded differences, their
+    squares, a sum and a root, carries up to ~4 units of rounding (1.1e-16
+    each) on either side, so 8 x 8 x 1.1e-16 / nu of g is no implementation's
+    error."""
+    r = np.random.default_rng(21)
+    n = 400
+    grid = np.stack(np.meshgrid(*(np.arange(8.0),) * 3, indexing="ij"), -1).reshape(-1, 3)[:n] + 0.5
+    hg = r.uniform(0.05, 0.2, n)
+    hd = hg * np.where(r.uniform(size=n) < 0.3, 10 ** r.uniform(-3, 0, n), r.uniform(0.3, 2.0, n))
+    nu = 10 ** r.uniform(-7, -2, n)
+    u = r.normal(size=(n, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    gas = {"pos": grid, "vel": r.normal(0, 20, (n, 3)), "mass": np.full(n, 1e6), "h": hg,
+           "u": np.full(n, workloads.u_from_T(1e4)), "mu": np.full(n, workloads.M_P)}
+    dm = {"pos": grid + u * ((hg + hd) * (1 - nu))[:, None], "vel": r.normal(0, 80, (n, 3)),
+          "mass": np.full(n, 1e6), "h": hd}
+    cfg = {"gas": gas, "dm": dm, "params": workloads.params(sigma0_cm2=1e-22, dt_myr=0.05)}
+    ref = orc.step(gas, dm, cfg["params"])
+    gpu = run_gpu(ctx, cfg, precision)
+    assert ref["counters"]["pairs_gas"] >= n and np.abs(ref["de_gas"]).min() < 1e-40 * np.abs(ref["de_gas"]).max()
+    bar = TOL[precision] + 64 * 1.1e-16 / nu
+    eg = mean_field_errors(gpu, ref)
+    ep = np.abs(gpu["p_sum"] - ref["p_sum"]) / np.maximum(ref["p_sum"], 1e-9)
+    _log(f"[near-contact p={precision}] worst owner error / bar: gas {np.max(eg / bar):.2f}, DM {np.max(ep / bar):.2f}; "
+         f"smallest nu {nu.min():.1e}, smallest |dE| {np.abs(ref['de_gas']).min():.1e}")
+    assert np.all(eg <= bar) and np.all(ep <= 2 * bar)
+    counter_check(gpu, ref, precision)
 
 
 @pytest.mark.parametrize("n_pow", [-4, -2, 0, 2])
