@@ -637,12 +637,62 @@ double sig_kpc2_cn_of(const dmb_params* par)
     return par->sigma0_cm2 / (kKpcCm * kKpcCm) * std::pow(kCKms, -double(par->n_pow));
 }
 
+// Work enqueued inside an OnSide scope goes to the side stream with the side
+// scratch set; fork() makes the side stream wait for the caller's stream so
+// far, join() the caller's stream for the side stream.
+struct OnSide {
+    dmb_ctx* c;
+    hipStream_t st;
+    Scratch* sc;
+    bool on;
+    explicit OnSide(dmb_ctx* c_, bool on_ = true) : c(c_), st(c_->stream), sc(c_->S), on(on_)
+    {
+        if (on) { c->stream = c->side; c->S = c->S2; }
+    }
+    ~OnSide() { c->stream = st; c->S = sc; }
+};
+
+dmb_status fork(dmb_ctx* c)
+{
+    HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    return DMB_OK;
+}
+
+dmb_status join(dmb_ctx* c)
+{
+    HIPCHK(c, hipEventRecord(c->ev_join, c->side));
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    return DMB_OK;
+}
+
+// Runs a(gas side) on the side stream and b (DM side) on the caller's stream;
+// both are enqueued before either status is checked, and the join comes first.
+template <typename FA, typename FB>
+dmb_status both(dmb_ctx* c, FA&& a, FB&& b)
+{
+    dmb_status s = fork(c);
+    if (s != DMB_OK) return s;
+    dmb_status sa;
+    {
+        OnSide on(c);
+        sa = a();
+    }
+    dmb_status sb = b();
+    dmb_status sj = join(c);
+    if (sa != DMB_OK) return sa;
+    if (sb != DMB_OK) return sb;
+    return sj;
+}
+
 // Per-step gathers into Morton order and the clearing of outputs, counters
 // and the box's queue counters (qctr: [0, 8) gas queue, [8, 16) DM queue,
-// [16] scatter count).
+// [16] scatter count).  Buffers are sized first; with `overlap` the gas
+// gather runs on the side stream beside the DM gather (both are bound by
+// the latency of their indexed reads).
 template <typename Real, int RM>
 dmb_status gather_and_fill(dmb_ctx* c, Cells& X, const dmb_particles* gas, const dmb_particles* dm,
-                           const dmb_params* par, dmb_out* out, uint64_t* counters)
+                           const dmb_params* par, dmb_out* out, uint64_t* counters, bool overlap = false)
 {
     Species& G = X.gas;
     Species& D = X.dm;
@@ -650,6 +700,19 @@ dmb_status gather_and_fill(dmb_ctx* c, Cells& X, const dmb_particles* gas, const
     if (G.n > 0) {
         ENSURE(c, G.v0, G.n * 8); ENSURE(c, G.v1, G.n * 8); ENSURE(c, G.v2, G.n * 8);
         ENSURE(c, G.orate, std::max<int64_t>(G.n_own, 1) * rs * 4);
+        ENSURE(c, G.rec, G.n * (sizeof(Real) == 4 ? sizeof(GasRec<float>) : sizeof(GasRec<double>)));
+    }
+    if (D.n > 0) ENSURE(c, D.rec, D.n * (sizeof(Real) == 4 ? sizeof(DmRec<float>) : sizeof(DmRec<double>)));
+    ENSURE(c, X.qctr, (2 * kXcd + 4) * 4);
+    if (X.gp.nitems > 0) ENSURE(c, X.part_gas, size_t(X.gp.nitems) * kTile * gas_sums<RM>() * 8);
+    if (X.dp.nitems > 0) {
+        ENSURE(c, X.part_p, size_t(X.dp.nitems) * kTile * 8);
+        ENSURE(c, X.part_pm, size_t(X.dp.nitems) * kTile * 4);
+        ENSURE(c, X.part_nb, size_t(X.dp.nitems) * kTile);
+        ENSURE(c, X.psum_own, size_t(D.n_own) * 8);
+        ENSURE(c, X.slist, size_t(D.n_own) * 4);
+    }
+    auto gas_gather = [&] {
         GasGatherArgs ga;
         ga.n = G.n; ga.perm = G.perm; ga.vel = gas->vel; ga.mass = gas->mass; ga.u = gas->u; ga.mu = gas->mu;
         ga.m_chi = par->m_chi_g; ga.sig_kpc2_cn = sig_kpc2_cn_of(par); ga.alpha_n = alpha_n(par->n_pow);
@@ -659,30 +722,32 @@ dmb_status gather_and_fill(dmb_ctx* c, Cells& X, const dmb_particles* gas, const
         ga.Vx = G.v0.as<double>(); ga.Vy = G.v1.as<double>(); ga.Vz = G.v2.as<double>();
         ga.flag = G.flag.as<const uint32_t>(); ga.flag_off = G.flag_off.as<const uint32_t>();
         ga.orate = G.orate.p;
-        ENSURE(c, G.rec, G.n * (sizeof(Real) == 4 ? sizeof(GasRec<float>) : sizeof(GasRec<double>)));
         ga.rec = G.rec.p;
         hipLaunchKernelGGL(k_gather_gas<Real>, dim3(blocks_for(G.n, 256)), dim3(256), 0, c->stream, ga);
+    };
+    const bool side = overlap && G.n > 0 && D.n > 0;
+    if (side) {
+        dmb_status s = fork(c);
+        if (s != DMB_OK) return s;
+        OnSide on(c);
+        gas_gather();
+    } else if (G.n > 0) {
+        gas_gather();
     }
     if (D.n > 0) {
         DmGatherArgs da;
         da.n = D.n; da.perm = D.perm; da.vel = dm->vel; da.mass = dm->mass; da.dt = dm->dt;
         da.dt_default = par->dt;
-        ENSURE(c, D.rec, D.n * (sizeof(Real) == 4 ? sizeof(DmRec<float>) : sizeof(DmRec<double>)));
         da.rec = D.rec.p;
         hipLaunchKernelGGL(k_gather_dm<Real>, dim3(blocks_for(D.n, 256)), dim3(256), 0, c->stream, da);
     }
-    ENSURE(c, X.qctr, (2 * kXcd + 4) * 4);
     int64_t nfill = std::max<int64_t>(std::max<int64_t>(G.n, D.n), 2 * kXcd + 4);
     hipLaunchKernelGGL(k_fill_out, dim3(blocks_for(nfill, 256)), dim3(256), 0, c->stream, G.n, D.n, out->dp_gas,
                        out->de_gas, out->dv_dm, out->partner, out->p_sum, out->p_max, counters,
                        X.qctr.as<uint32_t>(), 2 * kXcd + 4);
-    if (X.gp.nitems > 0) ENSURE(c, X.part_gas, size_t(X.gp.nitems) * kTile * gas_sums<RM>() * 8);
-    if (X.dp.nitems > 0) {
-        ENSURE(c, X.part_p, size_t(X.dp.nitems) * kTile * 8);
-        ENSURE(c, X.part_pm, size_t(X.dp.nitems) * kTile * 4);
-        ENSURE(c, X.part_nb, size_t(X.dp.nitems) * kTile);
-        ENSURE(c, X.psum_own, size_t(D.n_own) * 8);
-        ENSURE(c, X.slist, size_t(D.n_own) * 4);
+    if (side) {
+        dmb_status s = join(c);
+        if (s != DMB_OK) return s;
     }
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
@@ -799,11 +864,10 @@ void combine_dm_and_resolve(dmb_ctx* c, Cells& X, const DmPassArgs& a, const dmb
         hipLaunchKernelGGL((k_rb_kick<Real, N>), dim3(std::max(8, c->num_cu * 4)), dim3(64), 0, c->stream, r);
 }
 
-// The DM side of one step: the pair pass, the combine and decision, the resolve.
-// RB: Rao-Blackwellised sampling (expected P_ij, tilted partner draw).
+// The DM pair pass of one step (RB: Rao-Blackwellised sampling, expected
+// P_ij); returns its arguments for the combine and resolve.
 template <typename Real, int N, bool RB, bool PAIRS>
-void dm_side(dmb_ctx* c, Cells& X, const dmb_particles* gas, const dmb_params* par, dmb_out* out,
-             uint64_t* counters)
+DmPassArgs dm_pass(dmb_ctx* c, Cells& X, const dmb_params* par, dmb_out* out, uint64_t* counters)
 {
     constexpr bool kExact = sizeof(Real) == 8;
     DmPassArgs a = dm_pass_args(c, X, par, out, counters, nullptr);
@@ -812,14 +876,17 @@ void dm_side(dmb_ctx* c, Cells& X, const dmb_particles* gas, const dmb_params* p
         a.g.pair_n = c->S->pair_cnt.as<unsigned long long>() + 1;
     }
     const int nb = persist_blocks(c, (const void*)k_pass_dm<Real, N, kExact, false, PAIRS, RB>, 64, X.dp.nitems);
-    {
-        Phase ph(c, DMB_PH_PASS_DM);
-        hipLaunchKernelGGL((k_pass_dm<Real, N, kExact, false, PAIRS, RB>), dim3(nb), dim3(64), 0, c->stream, a,
-                           (const DmPassArgs*)nullptr, (const int64_t*)nullptr, 0);
-    }
-    combine_dm_and_resolve<Real, N, RB>(c, X, a, gas, par, out, counters);
+    Phase ph(c, DMB_PH_PASS_DM);
+    hipLaunchKernelGGL((k_pass_dm<Real, N, kExact, false, PAIRS, RB>), dim3(nb), dim3(64), 0, c->stream, a,
+                       (const DmPassArgs*)nullptr, (const int64_t*)nullptr, 0);
+    return a;
 }
 
+// One interaction step of one box: gathers, then the DM pass, then the gas
+// pass on the caller's stream while the DM combine, decisions and resolve run
+// on the side stream (disjoint outputs and counters; they take the CUs the
+// gas pass's persistent blocks leave as its queue drains), then the gas
+// combine.
 template <typename Real, int N, int RM, bool PAIRS = false>
 dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
                        dmb_out* out, uint64_t* counters)
@@ -829,8 +896,27 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
     Cells& X = *c->X;
     {
         Phase ph(c, DMB_PH_GATHER);
-        dmb_status s = gather_and_fill<Real, RM>(c, X, gas, dm, par, out, counters);
+        dmb_status s = gather_and_fill<Real, RM>(c, X, gas, dm, par, out, counters, true);
         if (s != DMB_OK) return s;
+    }
+    bool rb = false;
+    if constexpr (N > -4 && !PAIRS) rb = par->dm_sampling == DMB_SAMPLE_RB;
+    const bool side = X.gp.nitems > 0 && X.dp.nitems > 0;
+    if (X.dp.nitems > 0) {
+        DmPassArgs a;
+        if constexpr (N > -4 && !PAIRS) {
+            if (rb) a = dm_pass<Real, N, true, false>(c, X, par, out, counters);
+        }
+        if (!rb) a = dm_pass<Real, N, false, PAIRS>(c, X, par, out, counters);
+        if (side) {
+            dmb_status s = fork(c);
+            if (s != DMB_OK) return s;
+        }
+        OnSide on(c, side);
+        if constexpr (N > -4 && !PAIRS) {
+            if (rb) combine_dm_and_resolve<Real, N, true>(c, X, a, gas, par, out, counters);
+        }
+        if (!rb) combine_dm_and_resolve<Real, N, false>(c, X, a, gas, par, out, counters);
     }
     if (X.gp.nitems > 0) {
         GasPassArgs a = gas_pass_args<Real, N, RM>(c, X, gas, par, out, counters);
@@ -848,15 +934,9 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
         Phase ph(c, DMB_PH_COMBINE_GAS);
         combine_gas<N, RM>(c, X, gas, par, out);
     }
-    if (X.dp.nitems > 0) {
-        bool done = false;
-        if constexpr (N > -4 && !PAIRS) {
-            if (par->dm_sampling == DMB_SAMPLE_RB) {
-                dm_side<Real, N, true, false>(c, X, gas, par, out, counters);
-                done = true;
-            }
-        }
-        if (!done) dm_side<Real, N, false, PAIRS>(c, X, gas, par, out, counters);
+    if (side) {
+        dmb_status s = join(c);
+        if (s != DMB_OK) return s;
     }
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
@@ -1469,50 +1549,6 @@ dmb_status readback(dmb_ctx* c, const Readback& r, uint64_t* out)
 }
 
 // Cell structure of one box into c->X (arguments already checked).
-// Work enqueued inside an OnSide scope goes to the side stream with the side
-// scratch set; fork() makes the side stream wait for the caller's stream so
-// far, join() the caller's stream for the side stream.
-struct OnSide {
-    dmb_ctx* c;
-    hipStream_t st;
-    Scratch* sc;
-    explicit OnSide(dmb_ctx* c_) : c(c_), st(c_->stream), sc(c_->S) { c->stream = c->side; c->S = c->S2; }
-    ~OnSide() { c->stream = st; c->S = sc; }
-};
-
-dmb_status fork(dmb_ctx* c)
-{
-    HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
-    HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
-    return DMB_OK;
-}
-
-dmb_status join(dmb_ctx* c)
-{
-    HIPCHK(c, hipEventRecord(c->ev_join, c->side));
-    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
-    return DMB_OK;
-}
-
-// Runs a(gas side) on the side stream and b (DM side) on the caller's stream;
-// both are enqueued before either status is checked, and the join comes first.
-template <typename FA, typename FB>
-dmb_status both(dmb_ctx* c, FA&& a, FB&& b)
-{
-    dmb_status s = fork(c);
-    if (s != DMB_OK) return s;
-    dmb_status sa;
-    {
-        OnSide on(c);
-        sa = a();
-    }
-    dmb_status sb = b();
-    dmb_status sj = join(c);
-    if (sa != DMB_OK) return sa;
-    if (sb != DMB_OK) return sb;
-    return sj;
-}
-
 dmb_status build_cells_impl(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par)
 {
     dmb_status s;
