@@ -2,7 +2,8 @@
 allocating pair dmb_build_cells + dmb_interact_step, through the C ABI:
 several calls in a row on one context, each later call smaller than an
 earlier one (the static scratch keeps the last call's contents), in both
-precisions and for periodic and open volumes; every output bit-identical."""
+precisions, for periodic and open volumes and with Rao-Blackwellised DM
+sampling; every output bit-identical."""
 import numpy as np
 import pytest
 
@@ -43,7 +44,9 @@ def test_static_step_equals_build_and_step(ctx):
         ("box 2000+1500", workloads.box(n_gas=2000, n_dm=1500, seed=(19, 2), sigma0_cm2=3e-22), 1),
         ("galaxy 20000+80000", workloads.galaxy(n_gas=20000, n_dm=80000, seed=(2, 19), sigma0_cm2=1e-20), 0),
         ("box 1000+900", workloads.box(n_gas=1000, n_dm=900, seed=(19, 3), sigma0_cm2=3e-22), 0),
+        ("box 1500+1200 Rao-Blackwellised", workloads.box(n_gas=1500, n_dm=1200, seed=(19, 5), sigma0_cm2=3e-22), 1),
     ]
+    cases[-1][1]["params"]["dm_sampling"] = 1
     for label, cfg, prec in cases:
         ref = run_gpu(ctx, cfg, prec)
         got = _static(ctx, cfg, prec)
