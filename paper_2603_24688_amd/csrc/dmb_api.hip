@@ -902,27 +902,17 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
     bool rb = false;
     if constexpr (N > -4 && !PAIRS) rb = par->dm_sampling == DMB_SAMPLE_RB;
     const bool side = X.gp.nitems > 0 && X.dp.nitems > 0;
-    if (X.dp.nitems > 0) {
-        DmPassArgs a;
-        if constexpr (N > -4 && !PAIRS) {
-            if (rb) a = dm_pass<Real, N, true, false>(c, X, par, out, counters);
-        }
-        if (!rb) a = dm_pass<Real, N, false, PAIRS>(c, X, par, out, counters);
-        if (side) {
-            dmb_status s = fork(c);
-            if (s != DMB_OK) return s;
-        }
-        OnSide on(c, side);
-        if constexpr (N > -4 && !PAIRS) {
-            if (rb) combine_dm_and_resolve<Real, N, true>(c, X, a, gas, par, out, counters);
-        }
-        if (!rb) combine_dm_and_resolve<Real, N, false>(c, X, a, gas, par, out, counters);
+    Scratch* const S0 = c->S;     // the pair-export counts live in the caller's scratch set
+    if (side) {
+        dmb_status s = fork(c);
+        if (s != DMB_OK) return s;
     }
     if (X.gp.nitems > 0) {
+        OnSide on(c, side);
         GasPassArgs a = gas_pass_args<Real, N, RM>(c, X, gas, par, out, counters);
         if constexpr (PAIRS) {
             a.g.pairs = c->pair_dst[0]; a.g.pair_cap = uint64_t(c->pair_cap);
-            a.g.pair_n = c->S->pair_cnt.as<unsigned long long>();
+            a.g.pair_n = S0->pair_cnt.as<unsigned long long>();
         }
         const int nb = persist_blocks(c, (const void*)k_pass_gas<Real, N, kExact, RM, false, PAIRS>, 64 * kW,
                                       (X.gp.nitems + kW - 1) / kW);
@@ -933,6 +923,17 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
         }
         Phase ph(c, DMB_PH_COMBINE_GAS);
         combine_gas<N, RM>(c, X, gas, par, out);
+    }
+    if (X.dp.nitems > 0) {
+        DmPassArgs a;
+        if constexpr (N > -4 && !PAIRS) {
+            if (rb) a = dm_pass<Real, N, true, false>(c, X, par, out, counters);
+        }
+        if (!rb) a = dm_pass<Real, N, false, PAIRS>(c, X, par, out, counters);
+        if constexpr (N > -4 && !PAIRS) {
+            if (rb) combine_dm_and_resolve<Real, N, true>(c, X, a, gas, par, out, counters);
+        }
+        if (!rb) combine_dm_and_resolve<Real, N, false>(c, X, a, gas, par, out, counters);
     }
     if (side) {
         dmb_status s = join(c);
