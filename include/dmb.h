@@ -405,6 +405,15 @@ dmb_status dmb_profile_read(dmb_ctx *ctx, double *ms, int64_t *calls, int32_t re
  * DMB_EINVAL for a null ctx or cap outside [0, 65536]. */
 dmb_status dmb_set_search_groups(dmb_ctx *ctx, int32_t cap);
 
+/* Pass overlap (a scheduling control of dmb_interact_step; outputs never
+ * depend on it).  on = 1 (default): the gas pass and its combine run on an
+ * internal stream while the DM pass, its decisions and the resolve run on the
+ * context's stream, so both persistent passes share the GPU.  on = 0: one
+ * after the other on the context's stream, so that phase timing
+ * (dmb_profile_read) gives each pass's own time.  The batched step always runs
+ * its passes in sequence.  Errors: DMB_EINVAL for a null ctx. */
+dmb_status dmb_set_pass_overlap(dmb_ctx *ctx, int32_t on);
+
 /* Structure of the last dmb_build_cells (host array of 10 int64):
  * [active gas, active DM, gas tiles, DM tiles, gas owner tiles, DM owner
  *  tiles, candidate (owner tile, sub-tile) pairs of the gas pass, of the DM

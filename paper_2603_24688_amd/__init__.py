@@ -28,7 +28,7 @@ EXPORTS = ["dmb_create", "dmb_destroy", "dmb_set_stream", "dmb_build_cells", "dm
            "dmb_overlap_eval", "dmb_rates_eval", "dmb_philox_eval", "dmb_profile_enable", "dmb_profile_read",
            "dmb_build_stats", "dmb_last_error", "dmb_mlp_labels", "dmb_mlp_init", "dmb_mlp_set_params",
            "dmb_mlp_get_params", "dmb_mlp_grad", "dmb_mlp_train", "dmb_mlp_eval", "dmb_batch_build",
-           "dmb_batch_step", "dmb_batch_tune", "dmb_set_search_groups", "dmb_pair_list",
+           "dmb_batch_step", "dmb_batch_tune", "dmb_set_search_groups", "dmb_set_pass_overlap", "dmb_pair_list",
            "dmb_sort_pairs", "dmb_step_static", "dmb_run"]
 BUILD_STATS = ["active_gas", "active_dm", "gas_tiles", "dm_tiles", "gas_owner_tiles", "dm_owner_tiles",
                "cand_pairs_gas", "cand_pairs_dm", "items_gas", "items_dm"]
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH):
     L.dmb_philox_eval.restype = C.c_int; L.dmb_philox_eval.argtypes = [vp, i64, vp, u64, vp]
     L.dmb_profile_enable.restype = C.c_int; L.dmb_profile_enable.argtypes = [vp, i32]
     L.dmb_set_search_groups.restype = C.c_int; L.dmb_set_search_groups.argtypes = [vp, i32]
+    L.dmb_set_pass_overlap.restype = C.c_int; L.dmb_set_pass_overlap.argtypes = [vp, i32]
     L.dmb_profile_read.restype = C.c_int; L.dmb_profile_read.argtypes = [vp, vp, vp, i32]
     L.dmb_build_stats.restype = C.c_int; L.dmb_build_stats.argtypes = [vp, vp]
     L.dmb_last_error.restype = C.c_char_p; L.dmb_last_error.argtypes = [vp]
@@ -266,6 +267,10 @@ class Context:
     def set_search_groups(self, cap: int):
         """Candidate-search group list capacity (0: no group pass); outputs do not depend on it."""
         self._check(self.lib.dmb_set_search_groups(self.h, int(cap)), "dmb_set_search_groups")
+
+    def set_pass_overlap(self, on: bool = True):
+        """Gas and DM passes on two streams (True, default) or in sequence (for per-pass timing)."""
+        self._check(self.lib.dmb_set_pass_overlap(self.h, int(bool(on))), "dmb_set_pass_overlap")
 
     def profile_enable(self, on: bool = True):
         self._check(self.lib.dmb_profile_enable(self.h, int(bool(on))), "dmb_profile_enable")

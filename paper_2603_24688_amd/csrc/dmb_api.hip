@@ -118,6 +118,7 @@ struct dmb_ctx {
     size_t arena_cap = 0, arena_off = 0;
     Cells static_cells;
     uint64_t* rb_host = nullptr;           // pinned
+    bool pass_overlap = true;              // the two pair passes on two streams (dmb_set_pass_overlap)
     int split = 32;                        // candidate sub-tiles per work item of the DM pass (tunable);
                                            // the gas pass, whose partial sums cost more to combine, twice that
     int item_target_per_cu = 32;           // small problems: split candidate lists into about this many
@@ -901,7 +902,7 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
     }
     bool rb = false;
     if constexpr (N > -4 && !PAIRS) rb = par->dm_sampling == DMB_SAMPLE_RB;
-    const bool side = X.gp.nitems > 0 && X.dp.nitems > 0;
+    const bool side = c->pass_overlap && X.gp.nitems > 0 && X.dp.nitems > 0;
     Scratch* const S0 = c->S;     // the pair-export counts live in the caller's scratch set
     if (side) {
         dmb_status s = fork(c);
@@ -1469,6 +1470,13 @@ dmb_status dmb_build_stats(const dmb_ctx* c, int64_t* o)
     const int64_t v[10] = {c->X->gas.n_own, c->X->dm.n_own, c->X->gas.ntile, c->X->dm.ntile, c->X->gas.nown_tile, c->X->dm.nown_tile,
                            c->X->gp.total, c->X->dp.total, c->X->gp.nitems, c->X->dp.nitems};
     for (int k = 0; k < 10; ++k) o[k] = v[k];
+    return DMB_OK;
+}
+
+dmb_status dmb_set_pass_overlap(dmb_ctx* c, int32_t on)
+{
+    if (!c) return DMB_EINVAL;
+    c->pass_overlap = on != 0;
     return DMB_OK;
 }
 

@@ -235,6 +235,7 @@ def test_surrogate_cost_against_quadrature(ctx, trained):
     out = dmb.alloc_out(len(cfg["gas"]["mass"]), len(cfg["dm"]["mass"]))
     par = dict(cfg["params"])
     ctx.build_cells(G, D, par, precision=1)
+    ctx.set_pass_overlap(False)     # each pass's own time
     res = {}
     for name, rates, K in [("exact", 0, 0), ("quad32", 1, 32), ("quad12", 1, 12), ("mlp", 2, 32)]:
         par["rates"], par["quad_nodes"] = rates, K
@@ -247,6 +248,7 @@ def test_surrogate_cost_against_quadrature(ctx, trained):
         ph = ctx.profile_read(reset=True)
         ctx.profile_enable(False)
         res[name] = ph["pass_gas"][0] / max(ph["pass_gas"][1], 1)
+    ctx.set_pass_overlap(True)
     pairs = dmb.counters_dict(out["counters"])["pairs_gas"]
     _log("[surrogate cost] gas pass ms: " + ", ".join(f"{k} {v:.3f}" for k, v in res.items()) +
          f"; pairs {pairs}; network time / K=32 quadrature {res['mlp'] / res['quad32']:.2f}, "

@@ -367,6 +367,27 @@ def test_determinism(ctx):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("rates,sampling", [(0, 0), (3, 1)])
+def test_pass_overlap_does_not_change_outputs(ctx, rates, sampling):
+    """The two pair passes on two streams or in sequence (dmb_set_pass_overlap):
+    every output bit-identical, on a small galaxy in binary32."""
+    cfg = workloads.galaxy(n_gas=4000, n_dm=16000, seed=(2, 14), sigma0_cm2=1e-20)
+    cfg["params"]["rates"] = rates
+    cfg["params"]["dm_sampling"] = sampling
+    ctx.set_pass_overlap(False)
+    try:
+        seq = run_gpu(ctx, cfg, 1)
+    finally:
+        ctx.set_pass_overlap(True)
+    par = run_gpu(ctx, cfg, 1)
+    _log(f"[overlap] rates {rates} sampling {sampling}: pairs {par['counters']['pairs_gas']}, "
+         f"scatters {par['counters']['scatters']}")
+    assert par["counters"]["scatters"] > 0
+    for k in ("dp_gas", "de_gas", "dv_dm", "partner", "p_sum", "p_max"):
+        assert np.array_equal(seq[k], par[k]), k
+    assert seq["counters"] == par["counters"]
+
+
 @pytest.mark.parametrize("name", ["galaxy", "box"])
 def test_search_groups_do_not_change_outputs(ctx, name):
     """Candidate search with group lists (default capacity), with lists that overflow for most
