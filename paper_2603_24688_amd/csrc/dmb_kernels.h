@@ -1204,14 +1204,20 @@ __device__ __forceinline__ void test_chunk(PairTest& T, TestLds& S, const PassGe
         cnt = int(G.sub_cnt[ot]);
     }
     T.c0 += uint64_t(nch);
+    // the boxes go through LDS (the slot table, free until the chunk's first group is staged):
+    // every lane then reads box j with two broadcast loads instead of eight lane reads
+    float4* s_blo = reinterpret_cast<float4*>(S.px);
+    float4* s_bhi = reinterpret_cast<float4*>(S.pz);
+    s_blo[lane] = blo;
+    s_bhi[lane] = bhi;
     stage_sync<W>();
     float fx = T.fx, fy = T.fy, fz = T.fz, fh = T.fh;     // opaque copies: not hoisted out of the item loop
     asm volatile("" : "+v"(fx), "+v"(fy), "+v"(fz), "+v"(fh));
     const float ao = 6e-6f * (fx * fx + fy * fy + fz * fz + fh * fh);   // the owner's share of the slack
     uint64_t actA = 0ull, actB = 0ull;
     for (int j = 0; j < nch; ++j) {
-        const float4 lo = make_float4(lane_get(blo.x, j), lane_get(blo.y, j), lane_get(blo.z, j), lane_get(blo.w, j));
-        const float4 hi = make_float4(lane_get(bhi.x, j), lane_get(bhi.y, j), lane_get(bhi.z, j), lane_get(bhi.w, j));
+        const float4 lo = s_blo[j];
+        const float4 hi = s_bhi[j];
         bool near = T.ov;
         if (hi.w >= 0.f) {
             const float gx = fmaxf(0.f, fmaxf(lo.x - fx, fx - hi.x));
