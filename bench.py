@@ -562,7 +562,13 @@ def main():
     pairs = max(cnt["pairs_gas"], cnt["pairs_dm"])
     value = pairs / (ms_step * 1e-3)
     per_kernel = {k: v[0] / max(v[1], 1) for k, v in ph.items()}
-    dom = "pass_dm" if per_kernel["pass_dm"] >= per_kernel["pass_gas"] else "pass_gas"
+    # the dominant pass: the one with the most algorithmic work per step (the DM pass for the
+    # closed-form rates); with other rate modes the gas pass's work grows, so take the longer span
+    if args.rates == "exact" and precision == dmb.DMB_FP32:
+        dom = ("pass_dm" if PAIR_ALGO_VALU["pass_dm"] * cnt["pairs_dm"] >= PAIR_ALGO_VALU["pass_gas"] * cnt["pairs_gas"]
+               else "pass_gas")
+    else:
+        dom = "pass_dm" if per_kernel["pass_dm"] >= per_kernel["pass_gas"] else "pass_gas"
     t_dom = per_kernel[dom] * 1e-3
     units = cnt["pairs_dm"] if dom == "pass_dm" else cnt["pairs_gas"]
     counted = (precision == dmb.DMB_FP32 and args.n_pow == 0 and args.dm_sampling == "pair"
@@ -576,8 +582,9 @@ def main():
                 "traffic": None if pmc is None else pmc.get("hbm_bytes"),
                 "kernel_ms": per_kernel[dom], "algorithmic_ops_per_pair": PAIR_ALGO_VALU[dom],
                 "pairs_per_launch": units,
-                "kernel_ms_note": "span of the pass in the timed steps (the other pass runs beside it on a second "
-                                  "stream; at the default work-item size the DM pass's span equals its own time)",
+                "kernel_ms_note": "span of the pass in the timed steps; the other pass runs beside it on a "
+                                  "second stream (the DM pass, enqueued first, takes the time it takes alone: "
+                                  "compare rao_blackwell.per_pair.pass_dm_ms)",
                 "issued_valu_per_pair": None if pmc is None else pmc.get("valu_lane_instr") / units}
     else:
         roof = {"bound": "alu", "kernel": kname, "achieved": None, "peak": VALU_PEAK_GOPS, "unit": "Gop/s",

@@ -883,11 +883,12 @@ DmPassArgs dm_pass(dmb_ctx* c, Cells& X, const dmb_params* par, dmb_out* out, ui
     return a;
 }
 
-// One interaction step of one box: gathers, then the DM pass, then the gas
-// pass on the caller's stream while the DM combine, decisions and resolve run
-// on the side stream (disjoint outputs and counters; they take the CUs the
-// gas pass's persistent blocks leave as its queue drains), then the gas
-// combine.
+// One interaction step of one box: gathers, then the DM pass, its combine,
+// decisions and resolve on the caller's stream, and the gas pass and its
+// combine on the side stream at the same time (disjoint outputs, queue words
+// and counters); both persistent passes share the GPU and drain their own
+// queues.  With pass overlap off, all of it runs in sequence on the caller's
+// stream.
 template <typename Real, int N, int RM, bool PAIRS = false>
 dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles* dm, const dmb_params* par,
                        dmb_out* out, uint64_t* counters)
@@ -905,8 +906,16 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
     const bool side = c->pass_overlap && X.gp.nitems > 0 && X.dp.nitems > 0;
     Scratch* const S0 = c->S;     // the pair-export counts live in the caller's scratch set
     if (side) {
-        dmb_status s = fork(c);
+        dmb_status s = fork(c);     // the side stream waits for the gathers only
         if (s != DMB_OK) return s;
+    }
+    // the DM pass is enqueued first, so its blocks are dispatched first
+    DmPassArgs da;
+    if (X.dp.nitems > 0) {
+        if constexpr (N > -4 && !PAIRS) {
+            if (rb) da = dm_pass<Real, N, true, false>(c, X, par, out, counters);
+        }
+        if (!rb) da = dm_pass<Real, N, false, PAIRS>(c, X, par, out, counters);
     }
     if (X.gp.nitems > 0) {
         OnSide on(c, side);
@@ -926,15 +935,10 @@ dmb_status launch_step(dmb_ctx* c, const dmb_particles* gas, const dmb_particles
         combine_gas<N, RM>(c, X, gas, par, out);
     }
     if (X.dp.nitems > 0) {
-        DmPassArgs a;
         if constexpr (N > -4 && !PAIRS) {
-            if (rb) a = dm_pass<Real, N, true, false>(c, X, par, out, counters);
+            if (rb) combine_dm_and_resolve<Real, N, true>(c, X, da, gas, par, out, counters);
         }
-        if (!rb) a = dm_pass<Real, N, false, PAIRS>(c, X, par, out, counters);
-        if constexpr (N > -4 && !PAIRS) {
-            if (rb) combine_dm_and_resolve<Real, N, true>(c, X, a, gas, par, out, counters);
-        }
-        if (!rb) combine_dm_and_resolve<Real, N, false>(c, X, a, gas, par, out, counters);
+        if (!rb) combine_dm_and_resolve<Real, N, false>(c, X, da, gas, par, out, counters);
     }
     if (side) {
         dmb_status s = join(c);
