@@ -1133,19 +1133,28 @@ __device__ __forceinline__ uint32_t mfma_signs(const float a[3], const float b[3
     return m;
 }
 
+// The two 32-lane halves exchanged in one instruction (v_permlane32_swap):
+// lo = (x of lanes 0-31, y of lanes 0-31 moved to lanes 32-63),
+// hi = (x of lanes 32-63 moved to lanes 0-31, y of lanes 32-63).
+__device__ __forceinline__ void halves_swap(uint32_t x, uint32_t y, uint32_t* lo, uint32_t* hi)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+    *lo = r[0];
+    *hi = r[1];
+}
+
 // Operands of the product for K components (2 step + half) of two 32-lane
-// halves: `own` is this lane's component set, the other half's arrives from
-// the partner lane L^32.  out[t][step] = operand for tile t.
+// halves: lanes 0-31 supply their own components 2 step, lanes 32-63 their own
+// 2 step + 1, each half also receiving the other half's.  out[t][step] =
+// operand for tile t.
 __device__ __forceinline__ void half_operands(const float c[6], float out[2][3])
 {
-    const bool h = lane_id() >= 32;
 #pragma unroll
     for (int step = 0; step < 3; ++step) {
-        const float mine = h ? c[2 * step + 1] : c[2 * step];
-        const float send = h ? c[2 * step] : c[2 * step + 1];
-        const float recv = __shfl_xor(send, 32);
-        out[0][step] = h ? recv : mine;
-        out[1][step] = h ? mine : recv;
+        uint32_t lo, hi;
+        halves_swap(__float_as_uint(c[2 * step]), __float_as_uint(c[2 * step + 1]), &lo, &hi);
+        out[0][step] = __uint_as_float(lo);
+        out[1][step] = __uint_as_float(hi);
     }
 }
 
@@ -1314,10 +1323,8 @@ __device__ __forceinline__ int test_next(PairTest& T, TestLds& S, const PassGeom
         // w_t: owner 32 t + L%32 against slots 16 (L/32) + r (low half) and
         // 32 + 16 (L/32) + r (high half); owner L keeps w_{L/32}, the partner
         // supplies the other 32 slots
-        const bool h = lane >= 32;
-        const uint32_t mine = h ? w1 : w0, send = h ? w0 : w1;
-        const uint32_t recv = uint32_t(__shfl_xor(int(send), 32));
-        const uint32_t lo16 = h ? recv : mine, hi16 = h ? mine : recv;
+        uint32_t lo16, hi16;
+        halves_swap(w0, w1, &lo16, &hi16);
         const uint32_t mlo = (lo16 & 0xffffu) | (hi16 << 16), mhi = (lo16 >> 16) | (hi16 & 0xffff0000u);
         m = (uint64_t(mhi) << 32) | mlo;
     } else {
