@@ -127,3 +127,14 @@ def test_milky_way_full_size_sampled(ctx):
     _log(f"[milky way] generated in {time.time() - t0:.1f} s")
     _sampled_check(ctx, cfg, "milky way 8M+32M, 10% active, h over 3 decades", n_gas_s=96, n_dm_s=96,
                    pair_sets=True)
+
+
+def test_galaxy_full_size_closure_and_rao_blackwell(ctx):
+    """The galaxy at full size with the per-gas Maxwellian closure on the gas
+    side and Rao-Blackwellised sampling on the DM side (each variant touches
+    one side only), on sampled owners against the oracle's same modes."""
+    import paper_2603_24688_amd as dmb
+    cfg = workloads.galaxy(n_gas=1_000_000, n_dm=4_000_000, seed=(2, 1))
+    cfg["params"]["rates"] = dmb.DMB_RATES_CLOSURE
+    cfg["params"]["dm_sampling"] = dmb.DMB_SAMPLE_RB
+    _sampled_check(ctx, cfg, "galaxy 1M+4M closure + Rao-Blackwellised")
