@@ -45,62 +45,71 @@ __device__ __forceinline__ double psi_piece(int br, double a, double b, double b
     return 0.0;
 }
 
-__device__ __forceinline__ int psi_branch(double q) { return q <= 0.5 ? 0 : (q <= 1.0 ? 1 : 2); }
-
+// psi(b) - psi(a) for 0 <= a <= b (bma = b - a, formed by the caller without
+// cancellation): the part of [a, b] on each polynomial branch ([0, 1/2],
+// (1/2, 1]; psi is flat past 1), each by its factored difference.  Both
+// branch terms are formed without data-dependent control flow, so the
+// quadrature nodes of one piece evaluate side by side.
 __device__ __forceinline__ double psi_range(double a, double b, double bma)
 {
-    int ba = psi_branch(a), bb = psi_branch(b);
-    if (ba == bb) return psi_piece(ba, a, b, bma);
-    double acc = 0.0, lo = a;
-    for (int br = ba; br < bb; ++br) {
-        double edge = br == 0 ? 0.5 : 1.0;
-        acc += psi_piece(br, lo, edge, edge - lo);
-        lo = edge;
-    }
-    return acc + psi_piece(bb, lo, b, b - lo);
+    const bool a0 = a <= 0.5, a1 = a <= 1.0, b0 = b <= 0.5, b1 = b <= 1.0;
+    // branch 0 holds [a, min(b, 1/2)] when a <= 1/2
+    const double hi0 = b0 ? b : 0.5;
+    const double p0 = psi_piece(0, a, hi0, b0 ? bma : 0.5 - a);
+    // branch 1 holds [max(a, 1/2), min(b, 1)] when a <= 1 and b > 1/2
+    const double lo1 = a0 ? 0.5 : a, hi1 = b1 ? b : 1.0;
+    const double p1 = psi_piece(1, lo1, hi1, (!a0 && b1) ? bma : hi1 - lo1);
+    return (a0 ? p0 : 0.0) + ((a1 && !b0) ? p1 : 0.0);
 }
 
 // Overlap H(delta, eta) = h_b^3 g for the cubic spline (Appendix D):
 //   H = (2 pi / eta^3) int_0^1 ds s^2 w(s) F(s),
-//   F(s) = eta^2/(delta s) [psi((s+delta)/eta) - psi(|s-delta|/eta)],
-// exact up to rounding with 6-point Gauss-Legendre on each polynomial piece.
+//   F(s) = eta^2/(delta s) [psi((s+delta)/eta) - psi(|s-delta|/eta)].
+// Between consecutive breakpoints (where s, |s - delta|/eta or (s + delta)/eta
+// crosses a branch edge of w or psi) the integrand s w(s) (eta^2/delta)
+// [psi(b) - psi(a)] is one polynomial of degree 9 in s (8 for delta = 0), so
+// 5-point Gauss-Legendre on each piece is exact up to rounding.
 __device__ double overlap_H_exact(double delta, double eta)
 {
     if (delta >= 1.0 + eta) return 0.0;
-    const double gx[3] = {0.2386191860831969086, 0.6612093864662645137, 0.9324695142031520278};
-    const double gw[3] = {0.4679139345726910473, 0.3607615730481386076, 0.1713244923791703450};
-    double bp[10];
-    int nb = 0;
-    bp[nb++] = 0.0;
-    bp[nb++] = 1.0;
-    const double cand[8] = {0.5, delta, delta - 0.5 * eta, delta + 0.5 * eta, delta - eta, delta + eta,
-                            0.5 * eta - delta, eta - delta};
-    for (int k = 0; k < 8; ++k)
-        if (cand[k] > 0.0 && cand[k] < 1.0) bp[nb++] = cand[k];
-    for (int i = 1; i < nb; ++i) {  // insertion sort, nb <= 10
-        double v = bp[i];
-        int j = i - 1;
-        while (j >= 0 && bp[j] > v) { bp[j + 1] = bp[j]; --j; }
-        bp[j + 1] = v;
+    // 5-point Gauss-Legendre: nodes 0, +-gx[1], +-gx[2] with weights gw[0..2]
+    const double gx[3] = {0.0, 0.5384693101056830910, 0.9061798459386639928};
+    const double gw[3] = {0.5688888888888888889, 0.4786286704993664680, 0.2369268850561890875};
+    // breakpoints of the integrand inside (0, 1), clamped to [0, 1] (those outside give
+    // empty pieces), sorted by Batcher's odd-even merge network in registers
+    double bp[10] = {0.0, 0.5, delta, delta - 0.5 * eta, delta + 0.5 * eta, delta - eta, delta + eta,
+                     0.5 * eta - delta, eta - delta, 1.0};
+#pragma unroll
+    for (int k = 1; k < 9; ++k) bp[k] = fmin(fmax(bp[k], 0.0), 1.0);
+    constexpr int kNet[19][2] = {{1, 2}, {3, 4}, {5, 6}, {7, 8}, {1, 3}, {2, 4}, {5, 7}, {6, 8}, {2, 3}, {6, 7},
+                                 {1, 5}, {2, 6}, {3, 7}, {4, 8}, {3, 5}, {4, 6}, {2, 3}, {4, 5}, {6, 7}};
+#pragma unroll
+    for (int k = 0; k < 19; ++k) {
+        const double x = bp[kNet[k][0]], y = bp[kNet[k][1]];
+        bp[kNet[k][0]] = fmin(x, y);
+        bp[kNet[k][1]] = fmax(x, y);
     }
+    // s^2 w(s) F(s) = s w(s) (eta^2/delta) [psi(b) - psi(a)]: one factor s cancels, and the
+    // two quotients are formed once per pair, so the nodes take no division
+    const double ie = 1.0 / eta, c_ed = delta > 0.0 ? eta * eta / delta : 0.0;
     double acc = 0.0;
-    for (int k = 0; k + 1 < nb; ++k) {
-        double lo = bp[k], hi = bp[k + 1];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double lo = bp[k], hi = bp[k + 1];
         if (!(hi > lo)) continue;
         double half = 0.5 * (hi - lo), mid = 0.5 * (hi + lo), piece = 0.0;
-        for (int q = 0; q < 6; ++q) {
-            double s = mid + half * (q < 3 ? -gx[2 - q] : gx[q - 3]);
-            double wq = q < 3 ? gw[2 - q] : gw[q - 3];
-            double ws = kernel_w(s);
-            double F;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const double s = mid + half * (q < 2 ? -gx[2 - q] : gx[q - 2]);
+            const double wq = q < 2 ? gw[2 - q] : gw[q - 2];
+            double sF;
             if (delta == 0.0) {
-                F = 2.0 * kernel_w(s / eta);
+                sF = 2.0 * s * kernel_w(s * ie);
             } else {
-                double a = fabs(s - delta) / eta, b = (s + delta) / eta;
-                double bma = 2.0 * fmin(s, delta) / eta;
-                F = eta * eta / (delta * s) * psi_range(a, b, bma);
+                const double a = fabs(s - delta) * ie, b = (s + delta) * ie, bma = 2.0 * fmin(s, delta) * ie;
+                sF = c_ed * psi_range(a, b, bma);
             }
-            piece += wq * s * s * ws * F;
+            piece += wq * s * kernel_w(s) * sF;
         }
         acc += half * piece;
     }
