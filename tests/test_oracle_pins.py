@@ -113,6 +113,49 @@ def test_overlap_limits_and_support(orc):
     assert orc.overlap(1e-5, 1.0, 0.6) == pytest.approx(orc.overlap(0.0, 1.0, 0.6), rel=1e-9)
 
 
+def _H_shell_closed(delta, eta):
+    """h_b^3 g within h_s/2 of contact, rho = (1 + eta - delta)/eta <= 1/2: only
+    the outer branch 2(1 - q)^3 of both kernels takes part, and the Appendix D
+    integral is one polynomial piece with the closed form
+    eta^3 rho^8 512/(pi delta) [1/1120 - (1 + eta) rho/2520 + eta rho^2/6300]."""
+    import mpmath as mp
+    rho = (1 + eta - delta) / eta
+    return eta ** 3 * rho ** 8 * 512 / (mp.pi * delta) * (mp.mpf(1) / 1120 - (1 + eta) * rho / 2520
+                                                         + eta * rho ** 2 / 6300)
+
+
+def test_overlap_near_contact_closed_form_and_conditioning(orc):
+    """Near contact the overlap goes as rho^8 and, for small eta, its integrand
+    sits on a window of width ~eta: a quadrature in s carries a relative
+    rounding error of order eps (1/nu + 1/eta), nu = 1 - d/(h_b + h_s).  At
+    rho = 0.2 ... 0.45 the oracle equals the closed form to 1e-13 (2e-14/eta for
+    small eta); nearer contact (nu down to 1e-7) its error, against the closed
+    form at 50 digits for the same rounded delta and eta, stays below
+    4 eps (1/nu + 1/eta)."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    for hb, hs, rho in [(1.0, 0.5, 0.3), (1.0, 1.0, 0.2), (1.3, 0.7, 0.45), (1.0, 0.01, 0.4)]:
+        d = hb + hs - rho * hs
+        ref = float(_H_shell_closed(mp.mpf(d / hb), mp.mpf(hs / hb)))
+        assert orc.overlap(d, hb, hs) * hb ** 3 == pytest.approx(ref, rel=1e-13 + 2e-14 * hb / hs)
+    r = np.random.default_rng(11)
+    eps, worst, n = 1.11e-16, 0.0, 0
+    for _ in range(200):
+        hb = r.uniform(0.1, 2.0)
+        eta = 10 ** r.uniform(-4, 0)
+        hs = eta * hb
+        d = (1 - 10 ** r.uniform(-7, -2)) * (hb + hs)
+        delta, et = d / hb, hs / hb
+        if (1 + et - delta) / et > 0.5:
+            continue
+        ref = float(_H_shell_closed(mp.mpf(delta), mp.mpf(et)))
+        nu = 1 - d / (hb + hs)
+        worst = max(worst, abs(orc.overlap(d, hb, hs) * hb ** 3 / ref - 1) / (eps * (1 / nu + 1 / et)))
+        n += 1
+    assert n > 100
+    assert worst < 4.0
+
+
 # --------------------------------------------------------------------------- 1F1 and the rates
 AB_PAIRS = [(-0.5 * (n + 1), 2.5) for n in (-4, -2, 0, 2)] + [(-0.5 * (n + 3), 1.5) for n in (-4, -2, 0, 2)]
 
