@@ -98,6 +98,24 @@ def train_network(ctx, dev, log_fn) -> dict:
             "train_s": round(t2 - t1, 3), "final_loss": float(losses[-1])}
 
 
+def host_cpu() -> dict:
+    """The host CPU model and the logical cores the process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 0
+    return {"model": model, "logical_cores_usable": usable}
+
+
 def cpu_baseline(cfg, seconds: float, pairs_per_step: int, seed: int = 0):
     """The CPU oracle, as it stands, with its uniform-grid candidate search,
     timed on a bounded random sample of the owners of the same workload and
@@ -129,7 +147,7 @@ def cpu_baseline(cfg, seconds: float, pairs_per_step: int, seed: int = 0):
     t_full = t_build + t_own / frac
     c = res["counters"]
     return {"value": pairs_per_step / t_full, "unit": "pair interactions/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "neighbours": "uniform grids (the oracle's own candidate search)",
+            "cpu": host_cpu(), "kind": "oracle", "neighbours": "uniform grids (the oracle's own candidate search)",
             "sample": f"{len(gs)} random gas owners and {len(ds)} random DM owners of the benchmark workload "
                       f"({c['pairs_gas']} + {c['pairs_dm']} pairs in {dt:.1f} s including the grid build of "
                       f"{t_build:.1f} s); a whole step is estimated as the build plus the per-owner time scaled "
