@@ -97,6 +97,33 @@ def test_overlap_fp64_exact_and_fp32_table(ctx, orc):
     assert np.all(ctx.overlap_eval(*Tout, precision=1).cpu().numpy() == 0.0)
 
 
+def test_overlap_fp64_coincident_breakpoints(ctx, orc):
+    """The exact overlap's pieces (Appendix D) end where s, |s - delta|/eta or
+    (s + delta)/eta cross a branch edge; pick (delta, eta) where several of
+    those breakpoints coincide with each other or with 0, 1/2 and 1 (equal
+    kernels, delta = 1/2, delta = eta/2, delta = eta, delta = 1 - eta, ...),
+    so that the device's sorted breakpoint list holds duplicates and empty
+    pieces.  Binary64 parity with the oracle at 1e-12 (these cases are far
+    from contact and from small eta)."""
+    import torch
+    cases = []
+    for eta in (1.0, 0.5, 0.25, 0.75, 0.4):
+        for delta in (0.0, 0.5, 0.25 * eta, 0.5 * eta, eta, 1.0 - eta, 1.0 - 0.5 * eta, 1.5 * eta, 1.0,
+                      0.5 + 0.5 * eta, 0.5 - 0.5 * eta, 0.5 + eta):
+            if 0.0 <= delta < 1.0 + eta - 0.05:
+                cases.append((delta, eta))
+    hb = np.array([0.3 + 0.1 * (k % 7) for k in range(len(cases))])
+    d = np.array([c[0] for c in cases]) * hb
+    hs = np.array([c[1] for c in cases]) * hb
+    ref = np.array([orc.overlap(a, b, c) for a, b, c in zip(d, hb, hs)])
+    T = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (d, hb, hs)]
+    g64 = ctx.overlap_eval(*T, precision=0).cpu().numpy()
+    err = np.abs(g64 / ref - 1)
+    _log(f"overlap at coincident breakpoints: {len(cases)} cases, fp64 max rel err {err.max():.2e}")
+    assert np.all(ref > 0)
+    assert err.max() < 1e-12
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_pass_pairs_near_contact(ctx, orc, precision):
     """Every gas particle has exactly one DM partner, at nu = 1 - d/(h_i + h_j)
