@@ -2591,7 +2591,7 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
 // partners: one wavefront per scattering DM draws the relative velocity of
 // its pair from the tilted law (tag 5: radius, cosine to w, azimuth),
 // u = vs r (c e + s (cos phi e1 + sin phi e2)), e = w/|w| (the z axis if
-// w = 0; cold gas: u = w), and applies the kick.
+// w = 0; cold gas: u = w), and applies the kick, all in binary64.
 template <typename Real, int N>
 __global__ __launch_bounds__(64) void k_rb_kick(ResolveArgs a)
 {
@@ -2626,7 +2626,9 @@ __global__ __launch_bounds__(64) void k_rb_kick(ResolveArgs a)
             sincos_turns(u2, &sp2, &cp2);
             for (int k = 0; k < 3; ++k) ud[k] = vsd * trad * (cc * ev[k] + ss * (cp2 * e1[k] + sp2 * e2[k]));
         }
-        if (lane == 0) scatter_kick<Real>(a, oid, j, step, Real(ud[0]), Real(ud[1]), Real(ud[2]));
+        // the kick in binary64 in either precision: the drawn u already is, and for a forward
+        // Henyey-Greenstein angle n' - u/|u| is a difference of nearly equal unit vectors
+        if (lane == 0) scatter_kick<double>(a, oid, j, step, ud[0], ud[1], ud[2]);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }

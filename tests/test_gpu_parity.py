@@ -329,6 +329,33 @@ def test_box_rao_blackwell_sampling(ctx, orc, precision, n_pow):
     assert ref["counters"]["scatters"] > 100
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("mode", ["rb+aniso", "closure+aniso", "rb+quad"])
+def test_box_combined_modes(ctx, orc, precision, mode):
+    """The options combine: Rao-Blackwellised sampling with the
+    Henyey-Greenstein angle about the tilted relative velocity (g = 0.5), the
+    per-gas closure with sigma-bar = (1 - g) sigma on the gas side (g = -0.3,
+    n = -2), and Rao-Blackwellised sampling beside quadrature gas rates
+    (n = -2).  Against the oracle at the usual bars."""
+    import paper_2603_24688_amd as dmb
+    n_pow = 0 if mode == "rb+aniso" else -2
+    cfg = workloads.box(n_gas=1500, n_dm=1300, seed=(41, len(mode)), n_pow=n_pow,
+                        sigma0_cm2=workloads.sigma0_for_npow(n_pow, 30.0, 3e-22))
+    par = cfg["params"]
+    if mode == "rb+aniso":
+        par["dm_sampling"] = dmb.DMB_SAMPLE_RB
+        par["aniso_g"] = 0.5
+    elif mode == "closure+aniso":
+        par["rates"] = dmb.DMB_RATES_CLOSURE
+        par["aniso_g"] = -0.3
+    else:
+        par["dm_sampling"] = dmb.DMB_SAMPLE_RB
+        par["rates"] = dmb.DMB_RATES_QUAD
+        par["quad_nodes"] = 48 if precision == 0 else 32
+    gpu, ref = _check_step(ctx, orc, cfg, precision, f"box-{mode}")
+    assert ref["counters"]["scatters"] > 100
+
+
 def test_rao_blackwell_cold_gas_and_galaxy(ctx, orc):
     """Rao-Blackwellised sampling with cold gas (u = 0: the draw is w itself)
     on a quarter of the gas, and on the small galaxy (binary32)."""
