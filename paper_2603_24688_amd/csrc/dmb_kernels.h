@@ -2571,15 +2571,16 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(ResolveArgs a)
             if constexpr (RB) {
                 a.partner[oid] = int32_t(j);   // the kick follows in k_rb_kick
             } else {
+                // the partner's gas-velocity sample from the same uniforms as its P_ij (tag 0),
+                // and the kick, in binary64 in either precision: one thread per scattering DM
                 const double vs = sqrt(2.0 * a.gas_u[j] / 3.0);
                 U4 r = philox_block(oid, j, step, kTagGasVel, a.box, a.k0, a.k1);
-                Real z[3];
-                normals3<Real>(r, z);
-                const Real vsj = Real(vs);
-                const Real ux = Real(mvx - a.gas_vel[3 * int64_t(j)]) - vsj * z[0];
-                const Real uy = Real(mvy - a.gas_vel[3 * int64_t(j) + 1]) - vsj * z[1];
-                const Real uz = Real(mvz - a.gas_vel[3 * int64_t(j) + 2]) - vsj * z[2];
-                scatter_kick<Real>(a, oid, j, step, ux, uy, uz);
+                double z[3];
+                normals3<double>(r, z);
+                const double ux = (mvx - a.gas_vel[3 * int64_t(j)]) - vs * z[0];
+                const double uy = (mvy - a.gas_vel[3 * int64_t(j) + 1]) - vs * z[1];
+                const double uz = (mvz - a.gas_vel[3 * int64_t(j) + 2]) - vs * z[2];
+                scatter_kick<double>(a, oid, j, step, ux, uy, uz);
             }
         }
         __syncthreads();

@@ -329,31 +329,65 @@ def test_box_rao_blackwell_sampling(ctx, orc, precision, n_pow):
     assert ref["counters"]["scatters"] > 100
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("mode", ["rb+aniso", "closure+aniso", "rb+quad"])
-def test_box_combined_modes(ctx, orc, precision, mode):
-    """The options combine: Rao-Blackwellised sampling with the
-    Henyey-Greenstein angle about the tilted relative velocity (g = 0.5), the
-    per-gas closure with sigma-bar = (1 - g) sigma on the gas side (g = -0.3,
-    n = -2), and Rao-Blackwellised sampling beside quadrature gas rates
-    (n = -2).  Against the oracle at the usual bars."""
+COMBOS = {   # mode: (n_pow, dm_sampling RB?, rates, aniso_g)
+    "rb+aniso": (0, True, "exact", 0.5),
+    "closure+aniso": (-2, False, "closure", -0.3),
+    "rb+quad": (-2, True, "quad", 0.0),
+    "rb+closure": (0, True, "closure", 0.0),
+    "aniso n=-4": (-4, False, "exact", 0.3),
+    "rb+aniso n=2": (2, True, "exact", -0.5),
+}
+
+
+def _combo_params(par, mode, precision):
     import paper_2603_24688_amd as dmb
-    n_pow = 0 if mode == "rb+aniso" else -2
-    cfg = workloads.box(n_gas=1500, n_dm=1300, seed=(41, len(mode)), n_pow=n_pow,
-                        sigma0_cm2=workloads.sigma0_for_npow(n_pow, 30.0, 3e-22))
-    par = cfg["params"]
-    if mode == "rb+aniso":
+    n_pow, rb, rates, g = COMBOS[mode]
+    if rb:
         par["dm_sampling"] = dmb.DMB_SAMPLE_RB
-        par["aniso_g"] = 0.5
-    elif mode == "closure+aniso":
+    if rates == "closure":
         par["rates"] = dmb.DMB_RATES_CLOSURE
-        par["aniso_g"] = -0.3
-    else:
-        par["dm_sampling"] = dmb.DMB_SAMPLE_RB
+    elif rates == "quad":
         par["rates"] = dmb.DMB_RATES_QUAD
         par["quad_nodes"] = 48 if precision == 0 else 32
+    par["aniso_g"] = g
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("mode", list(COMBOS))
+def test_box_combined_modes(ctx, orc, precision, mode):
+    """The options combine: Rao-Blackwellised sampling with the
+    Henyey-Greenstein angle about the tilted relative velocity, the per-gas
+    closure with sigma-bar = (1 - g) sigma on the gas side, either sampling
+    beside quadrature or closure gas rates, and anisotropic scattering with a
+    velocity-dependent cross section.  Against the oracle at the usual bars."""
+    n_pow = COMBOS[mode][0]
+    cfg = workloads.box(n_gas=1500, n_dm=1300, seed=(41, len(mode)), n_pow=n_pow,
+                        sigma0_cm2=workloads.sigma0_for_npow(n_pow, 30.0, 3e-22))
+    _combo_params(cfg["params"], mode, precision)
     gpu, ref = _check_step(ctx, orc, cfg, precision, f"box-{mode}")
     assert ref["counters"]["scatters"] > 100
+
+
+@pytest.mark.parametrize("mode", ["rb+aniso", "closure+aniso", "rb+closure"])
+def test_active_subsets_with_options(ctx, orc, mode):
+    """Active subsets and per-particle dt (hierarchical steps) under the
+    non-default options: inactive DM take no kick and inactive gas no
+    transfer; the active ones match the oracle."""
+    n_pow = COMBOS[mode][0]
+    cfg = workloads.box(n_gas=2000, n_dm=1800, seed=(43, len(mode)), n_pow=n_pow,
+                        sigma0_cm2=workloads.sigma0_for_npow(n_pow, 30.0, 1e-22))
+    r = np.random.default_rng(len(mode))
+    cfg["gas"]["active"] = (r.uniform(size=2000) < 0.3).astype(np.uint8)
+    cfg["dm"]["active"] = (r.uniform(size=1800) < 0.2).astype(np.uint8)
+    cfg["dm"]["dt"] = cfg["params"]["dt"] * r.uniform(0.5, 2.0, 1800)
+    cfg["gas"]["dt"] = cfg["params"]["dt"] * r.uniform(0.5, 2.0, 2000)
+    for prec in (0, 1):
+        par = dict(cfg["params"])
+        _combo_params(par, mode, prec)
+        gpu, ref = _check_step(ctx, orc, dict(cfg, params=par), prec, f"active {mode}")
+        inactive = cfg["dm"]["active"] == 0
+        assert np.all(gpu["partner"][inactive] == -1) and np.all(gpu["dv_dm"][inactive] == 0)
+        assert np.all(gpu["dp_gas"][cfg["gas"]["active"] == 0] == 0)
 
 
 def test_rao_blackwell_cold_gas_and_galaxy(ctx, orc):
