@@ -43,11 +43,13 @@ def boxes():
     return workloads.batch(n_box=6, n_min=1200, n_max=6000, seed=(5, 2))
 
 
-def _to_dev(bx, rates=0, sampling=0):
+def _to_dev(bx, rates=0, sampling=0, aniso=False):
     import paper_2603_24688_amd as dmb
     G = [dmb.to_device(b["gas"]) for b in bx]
     D = [dmb.to_device(b["dm"]) for b in bx]
-    P = [dict(b["params"], rates=rates, dm_sampling=sampling) for b in bx]
+    # anisotropic scattering: a different Henyey-Greenstein g per box
+    P = [dict(b["params"], rates=rates, dm_sampling=sampling, aniso_g=(0.4 * (-1) ** k if aniso else 0.0))
+         for k, b in enumerate(bx)]
     O = [dmb.alloc_out(len(b["gas"]["mass"]), len(b["dm"]["mass"])) for b in bx]
     return G, D, P, O
 
@@ -68,12 +70,14 @@ def _same(a, b):
     return None
 
 
-# rates 3: the per-gas Maxwellian closure; sampling 1: Rao-Blackwellised DM sampling
-@pytest.mark.parametrize("precision,rates,sampling", [(0, 0, 0), (1, 0, 0), (0, 3, 0), (1, 3, 0), (0, 0, 1),
-                                                      (1, 0, 1)])
-def test_batch_equals_single_boxes(ctx, boxes, precision, rates, sampling):
+# rates 3: the per-gas Maxwellian closure; sampling 1: Rao-Blackwellised DM sampling;
+# aniso: a Henyey-Greenstein g of +-0.4 per box
+@pytest.mark.parametrize("precision,rates,sampling,aniso", [(0, 0, 0, False), (1, 0, 0, False), (0, 3, 0, False),
+                                                            (1, 3, 0, False), (0, 0, 1, False), (1, 0, 1, False),
+                                                            (1, 0, 0, True), (1, 3, 1, True)])
+def test_batch_equals_single_boxes(ctx, boxes, precision, rates, sampling, aniso):
     import torch
-    G, D, P, O = _to_dev(boxes, rates, sampling)
+    G, D, P, O = _to_dev(boxes, rates, sampling, aniso)
     ctx.batch_build(G, D, P, precision=precision)
     ctx.batch_step(G, D, P, O, precision=precision)
     torch.cuda.synchronize()
@@ -81,16 +85,17 @@ def test_batch_equals_single_boxes(ctx, boxes, precision, rates, sampling):
         single = run_gpu(ctx, dict(bx, params=P[b]), precision)
         got = _host(O[b])
         bad = _same(got, single)
-        _log(f"[batch p={precision} rates={rates} sampling={sampling}] box {b}: n={len(bx['gas']['mass'])} pairs {got['counters']['pairs_gas']} "
+        _log(f"[batch p={precision} rates={rates} sampling={sampling} aniso={aniso}] box {b}: n={len(bx['gas']['mass'])} pairs {got['counters']['pairs_gas']} "
              f"scatters {got['counters']['scatters']} {'identical' if bad is None else 'differs in ' + bad}")
         assert bad is None
 
 
-@pytest.mark.parametrize("precision,rates,sampling", [(0, 0, 0), (1, 0, 0), (1, 3, 0), (1, 0, 1)])
-def test_batch_oracle_parity(ctx, boxes, precision, rates, sampling):
+@pytest.mark.parametrize("precision,rates,sampling,aniso", [(0, 0, 0, False), (1, 0, 0, False), (1, 3, 0, False),
+                                                            (1, 0, 1, False), (0, 3, 1, True)])
+def test_batch_oracle_parity(ctx, boxes, precision, rates, sampling, aniso):
     import oracle
     import torch
-    G, D, P, O = _to_dev(boxes, rates, sampling)
+    G, D, P, O = _to_dev(boxes, rates, sampling, aniso)
     ctx.batch_build(G, D, P, precision=precision)
     ctx.batch_step(G, D, P, O, precision=precision)
     torch.cuda.synchronize()
@@ -104,7 +109,7 @@ def test_batch_oracle_parity(ctx, boxes, precision, rates, sampling):
         ep, ee = mean_field_error(got, ref, gsel)
         dec = decision_report(got, ref, dsel)
         ke = kick_error(got, ref, dsel)
-        _log(f"[batch oracle p={precision} rates={rates} sampling={sampling}] box {b}: dp {ep:.2e} dE {ee:.2e} decisions {dec['compared']} "
+        _log(f"[batch oracle p={precision} rates={rates} sampling={sampling} aniso={aniso}] box {b}: dp {ep:.2e} dE {ee:.2e} decisions {dec['compared']} "
              f"mismatch {dec['mismatch']} kick {ke:.2e}")
         assert ep <= TOL[precision] and ee <= TOL[precision]
         assert dec["mismatch"] == 0
