@@ -419,6 +419,18 @@ def test_small_galaxy(ctx, orc, precision):
     _check_step(ctx, orc, cfg, precision, "galaxy-small")
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("mode", ["rb+aniso", "closure+aniso"])
+def test_small_galaxy_options(ctx, orc, precision, mode):
+    """Open boundaries and h over ~2 decades with sigma0 = 1e-20 cm^2 (a few
+    hundred scatters, some P_i >= 1): the option combinations against the
+    oracle, kicks included."""
+    cfg = workloads.galaxy(n_gas=2500, n_dm=10000, seed=(2, 9), sigma0_cm2=1e-20)
+    _combo_params(cfg["params"], mode, precision)
+    gpu, ref = _check_step(ctx, orc, cfg, precision, f"galaxy-small {mode}")
+    assert ref["counters"]["scatters"] > 100
+
+
 def test_active_subsets_and_per_particle_dt(ctx, orc):
     cfg = workloads.box(n_gas=2000, n_dm=1800, seed=(8, 1), sigma0_cm2=1e-22)
     r = np.random.default_rng(1)
