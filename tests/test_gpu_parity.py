@@ -613,12 +613,16 @@ def test_counters_at_thresholds(ctx, orc):
         assert o["crit_viol"] > 1000 and 50 < o["p_ge_1"] < 1400 and 500 < o["scatters"] < 1400, o
 
 
-def test_resolve_beyond_lds_caches(ctx, orc):
+@pytest.mark.parametrize("mode", [None, "rb+aniso"])
+def test_resolve_beyond_lds_caches(ctx, orc, mode):
     """Scattering DM whose pairs exceed the resolve's LDS caches (more than 8192
     pairs and more than 2048 candidate sub-tiles): their partners are found by
     recomputing pairs in every digit pass; partners and kicks bit-exact against
-    the oracle."""
+    the oracle (per-pair sampling, and Rao-Blackwellised sampling with a
+    Henyey-Greenstein angle)."""
     cfg = workloads.galaxy(n_gas=150_000, n_dm=3000, seed=(2, 31))
+    if mode is not None:
+        _combo_params(cfg["params"], mode, 0)
     r = np.random.default_rng(31)
     big = np.arange(16)
     cfg["dm"]["pos"][big] = r.normal(0.0, 1.5, (16, 3))
