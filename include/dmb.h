@@ -162,8 +162,12 @@ dmb_status dmb_build_cells(dmb_ctx *ctx, const dmb_particles *gas, const dmb_par
  * Maxwellian gas-velocity sample per pair (Philox tag 0); one uniform U_i
  * (tag 2) decides a scatter if U_i < sum_j P_ij; the partner is the first gas
  * index (ascending) whose running sum exceeds U_i; the new relative-velocity
- * direction is isotropic (tag 1) and dv_dm follows eq. scatter_chi.
+ * direction is isotropic (tag 1, or Henyey-Greenstein about the incoming
+ * direction when aniso_g != 0) and dv_dm follows eq. scatter_chi.
  * Overlap g: exact (piecewise Gauss-Legendre) in DMB_FP64, table in DMB_FP32.
+ * DMB_FP32 forms the pair terms in binary32 and sums them in binary64; the
+ * kick of a scattering DM (its pair's sample and dv_dm) is binary64 in
+ * either precision.
  * Errors: DMB_EINVAL, DMB_ESTALE. */
 dmb_status dmb_interact_step(dmb_ctx *ctx, const dmb_particles *gas, const dmb_particles *dm,
                              const dmb_params *params, dmb_out *out);
