@@ -1017,8 +1017,13 @@ __device__ __forceinline__ void tile_pair_shift(const double* A, const double* B
     *clean = ok;
 }
 
-__device__ __forceinline__ double min_image(double d, double L) { return L > 0.0 ? d - L * rint(d / L) : d; }
-__device__ __forceinline__ float min_image_f(float d, float L) { return L > 0.f ? d - L * rintf(d / L) : d; }
+// Minimum image along one axis.  The image index is rounded from d times 1/L
+// (the reciprocal is loop-invariant, so no division per pair); it can differ
+// from rounding d/L only where d/L lies within a few units in the last place
+// of a half-integer, i.e. for separations near L/2, which no pair reaches
+// (h_i + h_j < L/2 is required), so every pair keeps its distance bit for bit.
+__device__ __forceinline__ double min_image(double d, double L) { return L > 0.0 ? d - L * rint(d * (1.0 / L)) : d; }
+__device__ __forceinline__ float min_image_f(float d, float L) { return L > 0.f ? d - L * rintf(d * (1.f / L)) : d; }
 
 // d^2 of owner (a) and other (b, already shifted); explicit evaluation order
 // shared by every pass and by the resolve.
