@@ -613,6 +613,22 @@ def test_counters_at_thresholds(ctx, orc):
         assert o["crit_viol"] > 1000 and 50 < o["p_ge_1"] < 1400 and 500 < o["scatters"] < 1400, o
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("m_chi_over_mp,n_pow,sig30", [(0.01, 0, 1e-23), (100.0, 0, 1e-22), (0.01, -4, 1e-19),
+                                                       (100.0, 2, 1e-22)])
+def test_extreme_mass_ratios(ctx, orc, precision, m_chi_over_mp, n_pow, sig30):
+    """DM far lighter (10 MeV-like) or far heavier than a proton: the mass
+    factors mu/(m_chi + mu) of the kick and the energy transfer go to 1 or 0,
+    and the criterion's (m_chi + mu)/mu to 1 or 1e2; with sigma ~ v^-4 and
+    v^2 (sigma at 30 km/s chosen for some hundreds of scatters).  Against the
+    oracle at the usual bars."""
+    cfg = workloads.box(n_gas=1200, n_dm=1100, seed=(47, int(m_chi_over_mp) + n_pow + 10), n_pow=n_pow,
+                        m_chi_over_mp=m_chi_over_mp,
+                        sigma0_cm2=workloads.sigma0_for_npow(n_pow, 30.0, sig30))
+    gpu, ref = _check_step(ctx, orc, cfg, precision, f"mass ratio {m_chi_over_mp} n={n_pow}")
+    assert ref["counters"]["scatters"] > 20
+
+
 @pytest.mark.parametrize("mode", [None, "rb+aniso"])
 def test_resolve_beyond_lds_caches(ctx, orc, mode):
     """Scattering DM whose pairs exceed the resolve's LDS caches (more than 8192
