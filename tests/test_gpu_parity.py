@@ -614,6 +614,27 @@ def test_counters_at_thresholds(ctx, orc):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("mode", [None, "closure+aniso", "rb+aniso"])
+def test_per_particle_mean_molecular_weight(ctx, orc, precision, mode):
+    """Gas of mixed composition: mu_j per particle between 0.59 m_p (ionised)
+    and 1.3 m_p (neutral with helium), with gas masses and energies varied
+    too.  mu enters K_j (M_j/mu_j), the mass factors mu/(m_chi + mu) of the
+    kick and heat transfer, varsigma^2 = 2u/3 through T and the criterion.
+    Against the oracle at the usual bars, per-pair and with options."""
+    cfg = workloads.box(n_gas=1500, n_dm=1300, seed=(53, 1 + (0 if mode is None else len(mode))),
+                        sigma0_cm2=5e-23)
+    r = np.random.default_rng(53)
+    ng = len(cfg["gas"]["mass"])
+    cfg["gas"]["mu"] = cfg["gas"]["mu"] * r.uniform(0.59, 1.3, ng)
+    cfg["gas"]["mass"] = cfg["gas"]["mass"] * r.uniform(0.5, 2.0, ng)
+    cfg["gas"]["u"] = cfg["gas"]["u"] * r.uniform(0.3, 3.0, ng)
+    if mode is not None:
+        _combo_params(cfg["params"], mode, precision)
+    gpu, ref = _check_step(ctx, orc, cfg, precision, f"mixed mu {mode}")
+    assert ref["counters"]["scatters"] > 100
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("m_chi_over_mp,n_pow,sig30", [(0.01, 0, 1e-23), (100.0, 0, 1e-22), (0.01, -4, 1e-19),
                                                        (100.0, 2, 1e-22)])
 def test_extreme_mass_ratios(ctx, orc, precision, m_chi_over_mp, n_pow, sig30):
