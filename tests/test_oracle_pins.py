@@ -770,15 +770,17 @@ def test_rb_urel_follows_the_tilted_law(orc, n_pow):
     assert np.array_equal(orc.rb_urel(n_pow, w, 0.0, U[0]), w)
 
 
-@pytest.mark.parametrize("n_pow", [0, -2])
-def test_rb_scheme_is_exact_in_law(orc, n_pow):
+@pytest.mark.parametrize("n_pow,g", [(0, 0.0), (-2, 0.0), (0, 0.5)])
+def test_rb_scheme_is_exact_in_law(orc, n_pow, g):
     """With P_i <= 1 the Rao-Blackwellised scheme gives the per-pair scheme's
     joint law of (partner, kick): over many Philox steps the partner
     frequencies agree (chi-square on the two-sample table) and so do the
-    mean kick vector and mean |dv|^2 per partner (5 standard errors)."""
+    mean kick vector and mean |dv|^2 per partner (5 standard errors); also
+    with a Henyey-Greenstein angle (g = 0.5) about the relative velocity."""
     from scipy.stats import chi2_contingency
     gas, dm, par = _pair_system(3e-23, n_gas=3, seed=5)
     par["n_pow"] = n_pow
+    par["aniso_g"] = g
     par["sigma0_cm2"] = workloads.sigma0_for_npow(n_pow, 60.0, 2.5e-22)
     S = 8000
     res = {}
