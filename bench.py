@@ -273,6 +273,33 @@ def closure_compare(ctx, cfg, dev, steps: int, log_fn) -> dict:
     return res
 
 
+def galaxy_binary64(ctx, cfg, dev, steps: int, log_fn) -> dict:
+    """The same galaxy step in binary64 throughout (exact overlap, binary64
+    rates and draws): build + interaction step per step, passes overlapped as
+    in the headline."""
+    import torch
+    import paper_2603_24688_amd as dmb
+    G = dmb.to_device(cfg["gas"], dev)
+    D = dmb.to_device(cfg["dm"], dev)
+    out = dmb.alloc_out(len(cfg["gas"]["mass"]), len(cfg["dm"]["mass"]), dev)
+    par = dict(cfg["params"])
+    ctx.build_cells(G, D, par, precision=dmb.DMB_FP64)
+    ctx.interact_step(G, D, par, out, precision=dmb.DMB_FP64)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for s in range(steps):
+        par["step"] = s
+        ctx.build_cells(G, D, par, precision=dmb.DMB_FP64)
+        ctx.interact_step(G, D, par, out, precision=dmb.DMB_FP64)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    cnt = dmb.counters_dict(out["counters"])
+    ms = (tb - ta) * 1e3 / steps
+    log_fn(f"bench: galaxy in binary64: {ms:.2f} ms per step, {cnt['pairs_dm']} pairs")
+    return {"ms_per_step": round(ms, 4), "pairs_per_step": cnt["pairs_dm"], "pairs_per_s": cnt["pairs_dm"] / (ms * 1e-3),
+            "pair_math": "binary64", "overlap": "exact (piecewise Gauss-Legendre)", "steps": steps}
+
+
 def rb_compare(ctx, cfg, dev, steps: int, log_fn) -> dict:
     """Rao-Blackwellised DM sampling against the paper's per-pair sampling on
     the galaxy workload in binary32: DM-pass and resolve times (passes in
@@ -481,6 +508,7 @@ def main():
     ap.add_argument("--no-box", action="store_true", help="skip the 100-step time loop of the periodic test box")
     ap.add_argument("--no-milky-way", action="store_true",
                     help="skip the 200-step hierarchical-timestep run at Milky-Way scale")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the binary64 run of the galaxy step")
     ap.add_argument("--no-rb", action="store_true",
                     help="skip the Rao-Blackwellised vs per-pair DM sampling comparison")
     ap.add_argument("--no-closure", action="store_true",
@@ -629,6 +657,8 @@ def main():
                          "dm": pairs / max(1, bst["cand_pairs_dm"] * 4096)},
     }
     default_run = args.workload == "galaxy" and args.rates == "exact" and args.n_pow == 0 and args.dm_sampling == "pair"
+    if default_run and not args.no_fp64:
+        line["galaxy_binary64"] = galaxy_binary64(ctx, cfg, dev, 5, log)
     if default_run and not args.no_rb:
         line["rao_blackwell"] = rb_compare(ctx, cfg, dev, 3, log)
     if default_run and not args.no_closure:
