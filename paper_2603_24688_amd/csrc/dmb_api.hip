@@ -1066,7 +1066,25 @@ dmb_status batch_enqueue(dmb_ctx* c, const dmb_particles* gas, const dmb_particl
     hipLaunchKernelGGL(k_fill_out, dim3(1), dim3(256), 0, c->stream, int64_t(0), int64_t(0), (double*)nullptr,
                        (double*)nullptr, (double*)nullptr, (int32_t*)nullptr, (double*)nullptr, (double*)nullptr,
                        (uint64_t*)nullptr, c->bstep.as<uint32_t>(), 2 * kXcd);
+    // as in the single-box step, the DM side (enqueued first) and the gas side run on two
+    // streams, forked after the gathers and joined at the end (also inside a captured graph)
+    const bool side = c->pass_overlap && P.gas_items > 0 && P.dm_items > 0;
+    if (side) {
+        dmb_status s = fork(c);
+        if (s != DMB_OK) return s;
+    }
+    if (P.dm_items > 0) {
+        bool done = false;
+        if constexpr (N > -4) {
+            if (P.rb) {
+                batch_dm_side<Real, N, true>(c, gas, par, out, P, ddev, ditems);
+                done = true;
+            }
+        }
+        if (!done) batch_dm_side<Real, N, false>(c, gas, par, out, P, ddev, ditems);
+    }
     if (P.gas_items > 0) {
+        OnSide on(c, side);
         GasPassArgs a0 = P.ga[0];
         a0.g.queue_ctr = c->bstep.as<uint32_t>();
         a0.g.n_items = P.gas_items;
@@ -1079,15 +1097,9 @@ dmb_status batch_enqueue(dmb_ctx* c, const dmb_particles* gas, const dmb_particl
         for (int b = 0; b < nbox; ++b)
             if (c->boxes[b]->gp.nitems > 0) combine_gas<N, RM>(c, *c->boxes[b], gas + b, par + b, out + b);
     }
-    if (P.dm_items > 0) {
-        bool done = false;
-        if constexpr (N > -4) {
-            if (P.rb) {
-                batch_dm_side<Real, N, true>(c, gas, par, out, P, ddev, ditems);
-                done = true;
-            }
-        }
-        if (!done) batch_dm_side<Real, N, false>(c, gas, par, out, P, ddev, ditems);
+    if (side) {
+        dmb_status s = join(c);
+        if (s != DMB_OK) return s;
     }
     HIPCHK(c, hipGetLastError());
     return DMB_OK;
