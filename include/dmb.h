@@ -414,8 +414,9 @@ dmb_status dmb_set_search_groups(dmb_ctx *ctx, int32_t cap);
  * internal stream while the DM pass, its decisions and the resolve run on the
  * context's stream, so both persistent passes share the GPU.  on = 0: one
  * after the other on the context's stream, so that phase timing
- * (dmb_profile_read) gives each pass's own time.  The batched step always runs
- * its passes in sequence.  Errors: DMB_EINVAL for a null ctx. */
+ * (dmb_profile_read) gives each pass's own time.  The batched step follows the
+ * same setting (its two streams are forked and joined inside the captured
+ * graph when it replays).  Errors: DMB_EINVAL for a null ctx. */
 dmb_status dmb_set_pass_overlap(dmb_ctx *ctx, int32_t on);
 
 /* Structure of the last dmb_build_cells (host array of 10 int64):
